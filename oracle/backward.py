@@ -1,0 +1,139 @@
+"""Exact gradients through composite -> divergence -> Poisson, FP64 (test oracle).
+
+Sec. 1.1 of GDGS writes the particle-parameter gradients of a squared-error
+loss as the loss residual times the derivative of the kernel sum (Eq. 5-7).
+For this pipeline the loss is l = 1/2 sum_c sum_interior (u - u_target)^2 on
+the recovered image u and the parameters are the rasteriser inputs: image
+mean mu[2][K], conic (a, b, c)[3][K], opacity alpha[K] and gradient values
+v[6][K].  The chain is:
+
+* Poisson (Eq. 21) with a zero ring: u_int = -A^{-1} rho_int with
+  A = -L_int symmetric, so dl/drho = lam where L_int lam = (u - u_target)
+  (the same Poisson problem with a different right-hand side; A's symmetry
+  is the variational form of Sec. 3.2.4, Eq. 26);
+* divergence: dl/dgrad = D^T lam (``poisson.div_adjoint``);
+* compositing (Eq. 11 / Eq. 20): with w_k = a_k T_{k-1} and
+  S_k = sum_{j>k} v_j w_j,  d out / d v_k = w_k and
+  d out / d a_k = v_k T_{k-1} - S_k / (1 - a_k);
+  a_k = alpha_k G_k, G_k = exp(-E_k), E_k = a dx^2 + 2 b dx dy + c dy^2,
+  d = p - mu.
+
+``finite_difference`` gives central differences of the same loss for the
+self-check of these formulas.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg
+
+from . import composite, poisson
+from .constants import E_CUT
+from .project import project_2d
+
+
+class _Solver:
+    """Zero-ring Poisson solver with the LU factors kept (tiny grids) or the
+    DST-I path (larger grids)."""
+
+    def __init__(self, H: int, W: int):
+        self.H, self.W = H, W
+        n, m = H - 2, W - 2
+        self.lu = scipy.linalg.lu_factor(poisson.system_matrix(n, m)) if n * m <= 4096 else None
+
+    def __call__(self, rho: np.ndarray) -> np.ndarray:
+        if self.lu is None:
+            return poisson.solve_dst(rho, None)
+        C = rho.shape[0]
+        n, m = self.H - 2, self.W - 2
+        u = np.zeros(rho.shape)
+        b = poisson.rhs(rho, None)
+        for c in range(C):
+            u[c, 1:-1, 1:-1] = scipy.linalg.lu_solve(self.lu, b[c].ravel()).reshape(n, m)
+        return u
+
+
+def forward(params: dict, H: int, W: int, target: np.ndarray, solver=None):
+    """Loss and intermediates for rasteriser-level params (FP64 copies)."""
+    proj = project_2d(params["mean2d"], params["conic"], params["depth"], W, H)
+    grad = composite.render_grad(proj, params["opacity"], params["value"], H, W)
+    rho = poisson.divergence(grad)
+    solver = solver or _Solver(H, W)
+    u = solver(rho)
+    e = np.zeros(u.shape)
+    e[:, 1:-1, 1:-1] = u[:, 1:-1, 1:-1] - np.asarray(target, dtype=np.float64)[:, 1:-1, 1:-1]
+    loss = 0.5 * float((e * e).sum())
+    return dict(loss=loss, grad=grad, rho=rho, u=u, e=e, proj=proj)
+
+
+def gradients(params: dict, H: int, W: int, target: np.ndarray):
+    """Loss and exact dl/d(mean2d, conic, opacity, value) (FP64)."""
+    solver = _Solver(H, W)
+    fw = forward(params, H, W, target, solver)
+    lam = solver(fw["e"])             # L_int lam = e, zero ring
+    dgrad = poisson.div_adjoint(lam)
+    proj = fw["proj"]
+    K = np.asarray(params["opacity"]).shape[0]
+    alpha = np.asarray(params["opacity"], dtype=np.float64)
+    value = np.asarray(params["value"], dtype=np.float64)
+    conic = proj["conic"]
+    dmean = np.zeros((2, K))
+    dconic = np.zeros((3, K))
+    dalpha = np.zeros(K)
+    dvalue = np.zeros((6, K))
+    for i in range(H):
+        for j in range(W):
+            idx, G, dx, dy = composite.pixel_terms(i, j, proj, alpha, use_box=False)
+            if idx.size == 0:
+                continue
+            delta = dgrad[:, i, j]
+            a = alpha[idx] * G
+            T_prev = np.concatenate([[1.0], np.cumprod(1.0 - a)[:-1]])
+            w = a * T_prev
+            v = value[:, idx]
+            contrib = v * w[None, :]
+            S = np.cumsum(contrib[:, ::-1], axis=1)[:, ::-1] - contrib   # sum over j > k
+            dvalue[:, idx] += delta[:, None] * w[None, :]
+            dl_da = (delta[:, None] * (v * T_prev[None, :] - S / (1.0 - a)[None, :])).sum(axis=0)
+            dalpha[idx] += dl_da * G
+            dl_dE = -dl_da * alpha[idx] * G
+            ca, cb, cc = conic[0][idx], conic[1][idx], conic[2][idx]
+            dmean[0, idx] += dl_dE * (-2.0 * (ca * dx + cb * dy))
+            dmean[1, idx] += dl_dE * (-2.0 * (cb * dx + cc * dy))
+            dconic[0, idx] += dl_dE * dx * dx
+            dconic[1, idx] += dl_dE * 2.0 * dx * dy
+            dconic[2, idx] += dl_dE * dy * dy
+    return dict(loss=fw["loss"], mean2d=dmean, conic=dconic, opacity=dalpha, value=dvalue,
+                lam=lam, dgrad=dgrad, u=fw["u"], grad=fw["grad"])
+
+
+def support_signature(params: dict, H: int, W: int) -> int:
+    """Number of (pixel, splat) pairs inside the support cut-off; a finite
+    difference whose two sides differ in this count crossed the cut-off."""
+    mx, my = (np.asarray(params["mean2d"], dtype=np.float64)[r][None, :] for r in range(2))
+    a, b, c = (np.asarray(params["conic"], dtype=np.float64)[r][None, :] for r in range(3))
+    py, px = np.meshgrid(np.arange(H) + 0.5, np.arange(W) + 0.5, indexing="ij")
+    dx = px.reshape(-1, 1) - mx
+    dy = py.reshape(-1, 1) - my
+    E = a * dx * dx + 2.0 * b * dx * dy + c * dy * dy
+    return int(((E <= E_CUT) & (a * c - b * b > 0)).sum())
+
+
+def finite_difference(params: dict, H: int, W: int, target: np.ndarray, name: str,
+                      index: tuple, rel_step: float = 1e-6):
+    """Central difference of the loss in one parameter entry.  Returns
+    (derivative, crossed) where crossed says the support set changed."""
+    solver = _Solver(H, W)
+    base = {k: np.array(v, dtype=np.float64) for k, v in params.items()}
+    x0 = base[name][index]
+    h = rel_step * max(1.0, abs(x0))
+    plus = {k: v.copy() for k, v in base.items()}
+    minus = {k: v.copy() for k, v in base.items()}
+    plus[name][index] = x0 + h
+    minus[name][index] = x0 - h
+    lp = forward(plus, H, W, target, solver)["loss"]
+    lm = forward(minus, H, W, target, solver)["loss"]
+    crossed = support_signature(plus, H, W) != support_signature(minus, H, W)
+    return (lp - lm) / (2.0 * h), crossed
+
+
+__all__ = ["forward", "gradients", "finite_difference", "support_signature", "E_CUT"]

@@ -1,0 +1,20 @@
+"""End-to-end oracle of the three steps of the method (Sec. 2.2 and Algorithm 1):
+project the splats (Eq. 19), composite the projected gradient field front to
+back (Eq. 20), and recover the image by solving the 2D Poisson equation
+(Eq. 21) on the divergence of the composited gradients (Sec. 1.5 and Eq. 14)."""
+from __future__ import annotations
+
+import numpy as np
+
+from . import composite, poisson
+from .project import project
+
+
+def render(scene, cam, boundary=None) -> dict:
+    """Full-image FP64 render.  Returns proj, grad[6][H][W], rho[3][H][W] and
+    u[3][H][W] (ring = boundary's ring, or zero)."""
+    proj = project(scene, cam)
+    grad = composite.render_grad(proj, scene.opacity, scene.value, cam.H, cam.W)
+    rho = poisson.divergence(grad)
+    u = poisson.solve(rho, boundary)
+    return dict(proj=proj, grad=grad, rho=rho, u=u)

@@ -1,0 +1,42 @@
+"""Pins of the oracle's analytic gradients by FP64 central finite differences."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import backward as obk
+from oracle import poisson as P
+
+
+@pytest.fixture(scope="module")
+def instance():
+    H = W = 32
+    params = wl.raster_scene(200, W, H, seed=2, ls=(-1.5, 0.3), fx=W)
+    params = {k: v.astype(np.float64) for k, v in params.items()}
+    target = wl.reference_image(H, W, seed=1) - 0.5
+    g = obk.gradients(params, H, W, target)
+    return H, W, params, target, g
+
+
+def test_loss_gradient_matches_finite_differences(instance):
+    H, W, params, target, g = instance
+    rng = np.random.default_rng(0)
+    checked = 0
+    for name, rows in [("mean2d", 2), ("conic", 3), ("opacity", None), ("value", 6)]:
+        for _ in range(8):
+            k = int(rng.integers(0, 200))
+            idx = (k,) if rows is None else (int(rng.integers(0, rows)), k)
+            an = g[name][idx]
+            fd, crossed = obk.finite_difference(params, H, W, target, name, idx)
+            if crossed:
+                continue
+            scale = np.abs(g[name]).max()
+            assert abs(fd - an) <= 1e-6 * scale + 1e-6 * abs(an), (name, idx, fd, an)
+            checked += 1
+    assert checked >= 28
+
+
+def test_adjoint_solve_identity(instance):
+    # lam solves L lam = e with a zero ring, i.e. lam = -A^{-1} e
+    H, W, params, target, g = instance
+    fw = obk.forward(params, H, W, target)
+    assert np.abs(P.laplacian(g["lam"])[:, 1:-1, 1:-1] - fw["e"][:, 1:-1, 1:-1]).max() < 1e-12
