@@ -1,0 +1,247 @@
+/*
+ * gdgs.h -- C ABI of the gradient-domain Gaussian splatting render + Poisson
+ * hot path (GDGS, arXiv 2405.05446) for AMD Instinct MI355X (gfx950).
+ *
+ * The method (Sec. 2.2 and Algorithm 1 of the paper): splats carrying image
+ * gradients are projected to the image plane (Eq. 19), composited front to back
+ * into a gradient image (Eq. 20), and the image is recovered by solving the 2D
+ * Poisson equation on the divergence of that gradient image (Eq. 21).
+ *
+ * Conventions (the paper leaves them open):
+ *   - camera: OpenCV axes, x_c = R x + t, pinhole (fx x/z + cx, fy y/z + cy);
+ *     pixel (i, j) has centre (j + 0.5, i + 0.5);
+ *   - a splat's Gaussian is exp(-d^T Sigma2D^{-1} d) (no factor 1/2, Eq. 9),
+ *     taken as exactly 0 where the exponent exceeds ln(1e5);
+ *   - splats with camera depth <= 0.2, a zero quaternion or a singular 2D
+ *     covariance are culled;
+ *   - six gradient channels, index 2*c + d: colour c, d = 0 derivative along
+ *     image columns (x), d = 1 along image rows (y);
+ *   - gradients are forward differences, the divergence is the backward
+ *     difference, the Laplacian the 5-point stencil with unit spacing;
+ *   - the Poisson problem is solved on the (H-2) x (W-2) interior pixels with
+ *     Dirichlet values on the one-pixel outer ring.
+ *
+ * Memory and ownership:
+ *   - every array argument is a DEVICE pointer to caller-owned memory, FP32
+ *     (or u32 / i64 where stated), planar structure-of-arrays layout, 4-byte
+ *     aligned; "[a][b]" is row-major with b fastest;
+ *   - the library never allocates device memory: scratch comes from a
+ *     caller-provided workspace of the size the *_workspace_size calls report;
+ *   - host structs (camera, parameters) are read during the call only.
+ *
+ * Streams: every call enqueues work on `stream` (a hipStream_t; NULL = the
+ * default stream) and returns without waiting, unless stated otherwise.
+ *
+ * Errors: calls return a gdgs_status.  Argument checks happen on the host
+ * before anything is enqueued; gdgs_last_error() then describes the failure
+ * (thread-local).  Conditions found on the device (pair-capacity overflow,
+ * non-convergence) are reported in a device-side gdgs_stats the caller reads
+ * after synchronising the stream; they are not call failures.
+ */
+#ifndef GDGS_H
+#define GDGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gdgs_status {
+    GDGS_OK = 0,
+    GDGS_ERR_INVALID_ARGUMENT = 1, /* bad size, null or misaligned pointer, bad parameter */
+    GDGS_ERR_CAPACITY = 2,         /* pair list larger than the caller's capacity */
+    GDGS_ERR_WORKSPACE = 3,        /* workspace missing or smaller than required */
+    GDGS_ERR_BUDGET = 4,           /* serving: request does not fit the memory budget */
+    GDGS_ERR_HIP = 5,              /* a HIP runtime call failed */
+    GDGS_ERR_UNSUPPORTED = 6,      /* valid request this build does not handle */
+    GDGS_ERR_NOT_READY = 7         /* serving: nothing finished yet */
+} gdgs_status;
+
+/* Splat scene, K splats (Sec. 1.2: Sigma = R S S^T R^T).  Device pointers. */
+typedef struct gdgs_scene {
+    const float* mean;      /* [3][K] world position */
+    const float* log_scale; /* [3][K] log of the per-axis scale (S = diag(exp)) */
+    const float* quat;      /* [4][K] rotation quaternion (w, x, y, z), normalised by the kernel */
+    const float* opacity;   /* [K] alpha in (0, 1) */
+    const float* value;     /* [6][K] gradient values carried by each splat */
+    int64_t K;
+} gdgs_scene;
+
+/* Pinhole camera (host struct). R is row-major world-to-camera rotation. */
+typedef struct gdgs_camera {
+    int32_t W, H;           /* image size in pixels, each >= 3 */
+    double fx, fy, cx, cy;  /* focal lengths (> 0) and principal point, pixels */
+    double R[9];
+    double t[3];
+} gdgs_camera;
+
+/* Projected splats (Eq. 19), [.][K] device arrays written by gdgs_project or
+ * gdgs_project_2d.  The mean is stored relative to the pixel origin of the
+ * splat's tile rectangle, (16 * tx0, 16 * ty0), which keeps FP32 offsets small
+ * at any image size. */
+typedef struct gdgs_proj {
+    float* mean2d;    /* [2][K] image-plane mean minus (16 tx0, 16 ty0) */
+    float* conic;     /* [3][K] (a, b, c) of Sigma2D^{-1}: E = a dx^2 + 2 b dx dy + c dy^2 */
+    float* depth;     /* [K] camera-space depth (the compositing order key) */
+    uint32_t* rect;   /* [2][K] tile rectangle: rect[0] = tx0 | tx1 << 16, rect[1] = ty0 | ty1 << 16 (half-open) */
+    uint32_t* count;  /* [K] number of tiles in the rectangle, 0 if culled or off-screen */
+} gdgs_proj;
+
+/* Tile bins: the (tile, splat) pairs sorted by (tile, FP32 depth, splat
+ * index) and each tile's range.  Device arrays, caller-owned. */
+typedef struct gdgs_bins {
+    int64_t capacity;     /* length of tile_of_pair / rank_of_pair */
+    uint32_t* tile_of_pair; /* [capacity] sorted tile id (ty * ceil(W/16) + tx) */
+    uint32_t* rank_of_pair; /* [capacity] depth rank s of each sorted pair; splat = order[s] */
+    uint32_t* order;      /* [K] splat index of depth rank s (stable: ties by index; culled last) */
+    uint32_t* ranges;     /* [2][T] start and end (half-open) of each tile, T = ceil(W/16) ceil(H/16) */
+    int64_t* num_pairs;   /* [1] total pairs P; pairs beyond capacity are dropped */
+} gdgs_bins;
+
+/* Multigrid parameters (host struct) for the Poisson solve (Eq. 21). */
+typedef struct gdgs_mg_params {
+    int32_t levels;        /* grids including the finest, >= 1; 0 = as many as the size allows, at most 8 */
+    int32_t pre_sweeps;    /* red-black Gauss-Seidel sweeps before restriction, 1..2 */
+    int32_t post_sweeps;   /* sweeps after prolongation, 1..2 */
+    int32_t max_cycles;    /* V-cycle limit, 1..64 */
+    int32_t coarse_sweeps; /* SOR sweeps on the coarsest grid; 0 = automatic */
+    int32_t reserved;
+    double tol;            /* stop when the normwise backward error <= tol */
+} gdgs_mg_params;
+
+/* Device-side statistics written by the solve and the render.  The solve
+ * stops a channel once eta = ||b - A w||_inf / (8 ||w||_inf + ||b||_inf) <= tol
+ * (A = minus the interior 5-point Laplacian, w the interior unknowns). */
+typedef struct gdgs_stats {
+    int32_t cycles[3];     /* V-cycles run per colour channel */
+    int32_t converged;     /* 1 if every channel met tol */
+    double eta[3];         /* final normwise backward error per channel */
+    double rel_res[3];     /* final ||b - A w||_2 / ||b||_2 per channel */
+    double b_norm[3];      /* ||b||_2 per channel */
+    int64_t num_pairs;     /* render: (tile, splat) pairs needed */
+    int32_t overflow;      /* render: 1 if num_pairs exceeded the pair capacity */
+    int32_t reserved;
+} gdgs_stats;
+
+/* ------------------------------------------------------------------ */
+/* Status and errors.                                                  */
+const char* gdgs_status_string(gdgs_status s);
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char* gdgs_last_error(void);
+/* Version string of the library build. */
+const char* gdgs_version(void);
+
+/* ------------------------------------------------------------------ */
+/* Workspace sizes (bytes, host-only calls, nothing is enqueued).      */
+gdgs_status gdgs_bin_sort_workspace_size(int64_t K, int32_t W, int32_t H, int64_t pair_capacity,
+                                         size_t* bytes);
+gdgs_status gdgs_raster_workspace_size(int64_t K, size_t* bytes);
+gdgs_status gdgs_poisson_workspace_size(int32_t W, int32_t H, const gdgs_mg_params* mg,
+                                        size_t* bytes);
+/* Everything gdgs_render needs, including its projected splats and bins. */
+gdgs_status gdgs_workspace_size(int64_t K, int32_t W, int32_t H, int64_t pair_capacity,
+                                const gdgs_mg_params* mg, size_t* bytes);
+
+/* ------------------------------------------------------------------ */
+/* Step 1, projection (Sec. 1.2 Eq. 10; Sec. 2.2 "Projection", Eq. 19).
+ * Per splat: q -> R, Sigma = R diag(exp(2 l)) R^T, x_c = cam.R x + cam.t,
+ * J = d(pinhole)/d(x_c) at the mean, Sigma2D = J cam.R Sigma cam.R^T J^T,
+ * conic = Sigma2D^{-1}, depth = z_c, and the tile rectangle of the support
+ * box {columns j : |j + 0.5 - mu_x| <= sqrt(ln(1e5) Sigma2D_xx)} (rows alike),
+ * clamped to the image.  Arithmetic in FP64, results stored in FP32.
+ * K = 0 is allowed (nothing is enqueued). */
+gdgs_status gdgs_project(const gdgs_scene* scene, const gdgs_camera* cam, const gdgs_proj* out,
+                         void* stream);
+
+/* Step 1 for splats already in image space (used by the differentiable
+ * path): mean2d[2][K] absolute image coordinates, conic[3][K] and depth[K]
+ * given; fills out->mean2d (tile-relative), out->conic (copied), out->depth
+ * (copied), out->rect and out->count exactly as gdgs_project does. */
+gdgs_status gdgs_project_2d(const float* mean2d, const float* conic, const float* depth,
+                            int64_t K, int32_t W, int32_t H, const gdgs_proj* out, void* stream);
+
+/* ------------------------------------------------------------------ */
+/* Step 2, tile binning and ordering (the front-to-back order of Eq. 11 /
+ * Eq. 20, "sorted from the view direction").  Stable radix sort of the splats
+ * by FP32 depth (culled last), one (tile, rank) pair per tile of each splat's
+ * rectangle, stable radix sort of the pairs by tile, tile ranges.  The pair
+ * order equals a lexicographic sort by (tile, FP32 depth bits, splat index).
+ * Writes bins->num_pairs = P on the device; only the first min(P, capacity)
+ * pairs are kept and later steps use those (check P after the stream syncs).
+ * Workspace: gdgs_bin_sort_workspace_size(K, W, H, bins->capacity). */
+gdgs_status gdgs_bin_sort(const gdgs_proj* proj, int64_t K, int32_t W, int32_t H,
+                          const gdgs_bins* bins, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------ */
+/* Step 3, gradient compositing (Eq. 11 applied to the projected field,
+ * Eq. 20): for every pixel p and channel m,
+ *   grad[m][p] = sum_k value[m][k] a_k T_{k-1},  a_k = opacity[k] G_k(p),
+ *   T_0 = 1, T_k = T_{k-1} (1 - a_k),
+ * over the tile's pairs in bin order.  A pixel stops accumulating once its
+ * T falls below 1e-7 (the dropped weight is below 1e-7).  Output grad[6][H][W]
+ * is fully written.  Workspace: gdgs_raster_workspace_size(K). */
+gdgs_status gdgs_raster_grad(const gdgs_proj* proj, const float* opacity, const float* value,
+                             int64_t K, const gdgs_bins* bins, int32_t W, int32_t H, float* grad,
+                             void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------ */
+/* Step 4, Poisson reconstruction (Sec. 2.1 Eq. 13-16; Sec. 2.2 Eq. 21) with
+ * Dirichlet data.  rho = backward-difference divergence of grad[6][H][W] on
+ * interior pixels, then multigrid V-cycles (red-black Gauss-Seidel smoothing,
+ * full-weighting restriction, bilinear prolongation, SOR on the coarsest
+ * grid) for L u = rho on the interior, u = boundary on the ring.
+ * boundary[3][H][W] (only its ring is read) may be NULL for a zero ring.
+ * Output u[3][H][W] is fully written (ring = boundary ring).  stats_dev
+ * (device pointer, may be NULL) receives cycles, eta, rel_res.
+ * Workspace: gdgs_poisson_workspace_size(W, H, mg). */
+gdgs_status gdgs_poisson_solve(const float* grad, const float* boundary, int32_t W, int32_t H,
+                               const gdgs_mg_params* mg, float* u, gdgs_stats* stats_dev,
+                               void* ws, size_t ws_bytes, void* stream);
+
+/* Same solve with the right-hand side rho[3][H][W] given directly (interior
+ * read): used for the adjoint solve of the backward pass and for Laplacian
+ * splats. */
+gdgs_status gdgs_poisson_solve_rhs(const float* rho, const float* boundary, int32_t W, int32_t H,
+                                   const gdgs_mg_params* mg, float* u, gdgs_stats* stats_dev,
+                                   void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------ */
+/* Steps 1-4 on one stream with no host synchronisation: project, bin and
+ * sort, composite, solve.  u[3][H][W] is the recovered image.  If sync_stats
+ * is non-zero the call waits for the stream and returns GDGS_ERR_CAPACITY when
+ * the pairs exceeded pair_capacity (stats hold the needed count).
+ * Workspace: gdgs_workspace_size(scene->K, W, H, pair_capacity, mg). */
+gdgs_status gdgs_render(const gdgs_scene* scene, const gdgs_camera* cam, const float* boundary,
+                        const gdgs_mg_params* mg, int64_t pair_capacity, float* u,
+                        gdgs_stats* stats_dev, int sync_stats, void* ws, size_t ws_bytes,
+                        void* stream);
+
+/* ------------------------------------------------------------------ */
+/* Backward pass (gradients of a loss on u through the Poisson solve and the
+ * compositing; the particle-parameter gradients of Sec. 1.1, Eq. 5-7). */
+
+/* Transpose of the divergence: dgrad[6][H][W] from lam[3][H][W] (interior
+ * read, taken as 0 elsewhere): dgx = lam[i][j] - lam[i][j+1],
+ * dgy = lam[i][j] - lam[i+1][j]. */
+gdgs_status gdgs_div_adjoint(const float* lam, int32_t W, int32_t H, float* dgrad, void* stream);
+
+/* Reverse compositing.  Given the forward inputs, the forward output grad
+ * and dL/dgrad, writes dL/d(mean2d)[2][K], dL/d(conic)[3][K],
+ * dL/d(opacity)[K], dL/d(value)[6][K] (fully written; zero for splats that
+ * touch no pixel).  Per-pixel transmittance is recomputed, not stored.
+ * The per-splat sums are deterministic (no atomics).
+ * Workspace: gdgs_raster_backward_workspace_size(K, bins->capacity). */
+gdgs_status gdgs_raster_backward_workspace_size(int64_t K, int64_t pair_capacity, size_t* bytes);
+gdgs_status gdgs_raster_grad_backward(const gdgs_proj* proj, const float* opacity,
+                                      const float* value, int64_t K, const gdgs_bins* bins,
+                                      int32_t W, int32_t H, const float* grad, const float* dgrad,
+                                      float* dmean2d, float* dconic, float* dopacity,
+                                      float* dvalue, void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GDGS_H */

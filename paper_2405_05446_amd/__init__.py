@@ -1,0 +1,13 @@
+"""MI355X (gfx950) implementation of the gradient-domain Gaussian splatting
+render + Poisson reconstruction path of GDGS (arXiv 2405.05446).
+
+The compute lives in libgdgs.so (hand-written HIP kernels behind the C ABI of
+include/gdgs.h); this package marshals torch device tensors into it.
+"""
+from ._lib import GdgsError, load  # noqa: F401
+from .api import (  # noqa: F401
+    DeviceScene, Renderer, alloc_bins, alloc_proj, camera_struct, gdgs_bin_sort,
+    gdgs_div_adjoint, gdgs_poisson_solve, gdgs_poisson_solve_rhs, gdgs_project,
+    gdgs_project_2d, gdgs_raster_grad, gdgs_raster_grad_backward, gdgs_render, mg_params,
+    new_stats, read_stats, render_workspace_size, workspace,
+)

@@ -1,0 +1,304 @@
+"""Python entry points with the C ABI's names (include/gdgs.h), taking torch
+device tensors.  Each function validates shapes, allocates outputs and
+workspaces with torch, and calls the library; no arithmetic of the method
+happens here.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+F32 = torch.float32
+U32 = torch.int32          # u32 arrays are held in int32 tensors (same bytes)
+STATS_BYTES = ctypes.sizeof(L.Stats)
+
+
+def _dev(device=None) -> torch.device:
+    return torch.device(device if device is not None else "cuda")
+
+
+def _need(t: torch.Tensor, shape, dtype, name: str):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise ValueError(f"{name}: expected contiguous {dtype} {tuple(shape)}, got "
+                         f"{t.dtype} {tuple(t.shape)}")
+
+
+def workspace(nbytes: int, device=None) -> torch.Tensor:
+    """A 256-byte aligned uint8 device buffer of at least nbytes."""
+    buf = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=_dev(device))
+    off = (-buf.data_ptr()) % 256
+    return buf[off:off + int(nbytes)]
+
+
+def camera_struct(cam) -> L.Camera:
+    c = L.Camera()
+    c.W, c.H = int(cam.W), int(cam.H)
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    R = np.asarray(cam.R, dtype=np.float64).reshape(9)
+    t = np.asarray(cam.t, dtype=np.float64).reshape(3)
+    c.R = (ctypes.c_double * 9)(*R.tolist())
+    c.t = (ctypes.c_double * 3)(*t.tolist())
+    return c
+
+
+def mg_params(levels: int = 0, pre: int = 2, post: int = 2, max_cycles: int = 20,
+              tol: float = 1e-6, coarse_sweeps: int = 0) -> L.MgParams:
+    return L.MgParams(levels, pre, post, max_cycles, coarse_sweeps, 0, float(tol))
+
+
+@dataclass
+class DeviceScene:
+    mean: torch.Tensor       # [3][K]
+    log_scale: torch.Tensor  # [3][K]
+    quat: torch.Tensor       # [4][K]
+    opacity: torch.Tensor    # [K]
+    value: torch.Tensor      # [6][K]
+
+    @property
+    def K(self) -> int:
+        return int(self.opacity.shape[0])
+
+    @staticmethod
+    def from_host(scene, device=None) -> "DeviceScene":
+        d = _dev(device)
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(d)
+        return DeviceScene(t(scene.mean), t(scene.log_scale), t(scene.quat), t(scene.opacity),
+                           t(scene.value))
+
+    def struct(self) -> L.Scene:
+        K = self.K
+        _need(self.mean, (3, K), F32, "mean")
+        _need(self.log_scale, (3, K), F32, "log_scale")
+        _need(self.quat, (4, K), F32, "quat")
+        _need(self.opacity, (K,), F32, "opacity")
+        _need(self.value, (6, K), F32, "value")
+        return L.Scene(L.ptr(self.mean), L.ptr(self.log_scale), L.ptr(self.quat),
+                       L.ptr(self.opacity), L.ptr(self.value), K)
+
+
+def alloc_proj(K: int, device=None) -> dict:
+    d = _dev(device)
+    k = max(K, 1)
+    return dict(mean2d=torch.empty((2, k), dtype=F32, device=d)[:, :K],
+                conic=torch.empty((3, k), dtype=F32, device=d)[:, :K],
+                depth=torch.empty(k, dtype=F32, device=d)[:K],
+                rect=torch.empty((2, k), dtype=U32, device=d)[:, :K],
+                count=torch.empty(k, dtype=U32, device=d)[:K])
+
+
+def _proj_struct(p: dict) -> L.Proj:
+    return L.Proj(L.ptr(p["mean2d"]), L.ptr(p["conic"]), L.ptr(p["depth"]), L.ptr(p["rect"]),
+                  L.ptr(p["count"]))
+
+
+def alloc_bins(K: int, W: int, H: int, capacity: int, device=None) -> dict:
+    d = _dev(device)
+    T = ((W + 15) // 16) * ((H + 15) // 16)
+    return dict(capacity=int(capacity),
+                tile_of_pair=torch.empty(capacity, dtype=U32, device=d),
+                rank_of_pair=torch.empty(capacity, dtype=U32, device=d),
+                order=torch.empty(max(K, 1), dtype=U32, device=d),
+                ranges=torch.empty((2, T), dtype=U32, device=d),
+                num_pairs=torch.zeros(1, dtype=torch.int64, device=d))
+
+
+def _bins_struct(b: dict) -> L.Bins:
+    return L.Bins(b["capacity"], L.ptr(b["tile_of_pair"]), L.ptr(b["rank_of_pair"]),
+                  L.ptr(b["order"]), L.ptr(b["ranges"]), L.ptr(b["num_pairs"]))
+
+
+def read_stats(stats: torch.Tensor) -> dict:
+    raw = bytes(stats.cpu().numpy().tobytes())
+    s = L.Stats.from_buffer_copy(raw)
+    return dict(cycles=list(s.cycles), converged=bool(s.converged), eta=list(s.eta),
+                rel_res=list(s.rel_res), b_norm=list(s.b_norm), num_pairs=int(s.num_pairs),
+                overflow=bool(s.overflow))
+
+
+def new_stats(device=None) -> torch.Tensor:
+    return torch.zeros(STATS_BYTES, dtype=torch.uint8, device=_dev(device))
+
+
+def _size(fn, *args) -> int:
+    n = ctypes.c_size_t(0)
+    L.check(fn(*args, ctypes.byref(n)))
+    return int(n.value)
+
+
+# ---------------------------------------------------------------- steps
+def gdgs_project(scene: DeviceScene, cam, proj: dict | None = None, stream=None) -> dict:
+    lib = L.load()
+    proj = proj if proj is not None else alloc_proj(scene.K, scene.opacity.device)
+    c = camera_struct(cam)
+    L.check(lib.gdgs_project(ctypes.byref(scene.struct()), ctypes.byref(c),
+                             ctypes.byref(_proj_struct(proj)), L.stream_handle(stream)))
+    return proj
+
+
+def gdgs_project_2d(mean2d: torch.Tensor, conic: torch.Tensor, depth: torch.Tensor, W: int, H: int,
+                    proj: dict | None = None, stream=None) -> dict:
+    lib = L.load()
+    K = int(depth.shape[0])
+    _need(mean2d, (2, K), F32, "mean2d")
+    _need(conic, (3, K), F32, "conic")
+    _need(depth, (K,), F32, "depth")
+    proj = proj if proj is not None else alloc_proj(K, depth.device)
+    L.check(lib.gdgs_project_2d(L.ptr(mean2d), L.ptr(conic), L.ptr(depth), K, W, H,
+                                ctypes.byref(_proj_struct(proj)), L.stream_handle(stream)))
+    return proj
+
+
+def gdgs_bin_sort(proj: dict, K: int, W: int, H: int, capacity: int, bins: dict | None = None,
+                  ws: torch.Tensor | None = None, stream=None) -> dict:
+    lib = L.load()
+    dev = proj["depth"].device
+    bins = bins if bins is not None else alloc_bins(K, W, H, capacity, dev)
+    need = _size(lib.gdgs_bin_sort_workspace_size, K, W, H, bins["capacity"])
+    ws = ws if ws is not None else workspace(need, dev)
+    L.check(lib.gdgs_bin_sort(ctypes.byref(_proj_struct(proj)), K, W, H,
+                              ctypes.byref(_bins_struct(bins)), L.ptr(ws), ws.numel(),
+                              L.stream_handle(stream)))
+    return bins
+
+
+def gdgs_raster_grad(proj: dict, opacity: torch.Tensor, value: torch.Tensor, K: int, bins: dict,
+                     W: int, H: int, grad: torch.Tensor | None = None,
+                     ws: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    lib = L.load()
+    dev = bins["ranges"].device
+    _need(opacity, (K,), F32, "opacity")
+    _need(value, (6, K), F32, "value")
+    grad = grad if grad is not None else torch.empty((6, H, W), dtype=F32, device=dev)
+    _need(grad, (6, H, W), F32, "grad")
+    need = _size(lib.gdgs_raster_workspace_size, K)
+    ws = ws if ws is not None else workspace(need, dev)
+    L.check(lib.gdgs_raster_grad(ctypes.byref(_proj_struct(proj)), L.ptr(opacity), L.ptr(value),
+                                 K, ctypes.byref(_bins_struct(bins)), W, H, L.ptr(grad),
+                                 L.ptr(ws), ws.numel(), L.stream_handle(stream)))
+    return grad
+
+
+def _poisson(fn_name: str, src: torch.Tensor, src_ch: int, boundary, W, H, mg, u, stats, ws,
+             stream):
+    lib = L.load()
+    dev = src.device
+    _need(src, (src_ch, H, W), F32, "grad" if src_ch == 6 else "rho")
+    if boundary is not None:
+        _need(boundary, (3, H, W), F32, "boundary")
+    mg = mg if mg is not None else mg_params()
+    u = u if u is not None else torch.empty((3, H, W), dtype=F32, device=dev)
+    _need(u, (3, H, W), F32, "u")
+    stats = stats if stats is not None else new_stats(dev)
+    need = _size(lib.gdgs_poisson_workspace_size, W, H, ctypes.byref(mg))
+    ws = ws if ws is not None else workspace(need, dev)
+    fn = getattr(lib, fn_name)
+    L.check(fn(L.ptr(src), L.ptr(boundary), W, H, ctypes.byref(mg), L.ptr(u), L.ptr(stats),
+               L.ptr(ws), ws.numel(), L.stream_handle(stream)))
+    return u, stats
+
+
+def gdgs_poisson_solve(grad: torch.Tensor, boundary: torch.Tensor | None, W: int, H: int,
+                       mg: L.MgParams | None = None, u=None, stats=None, ws=None, stream=None):
+    return _poisson("gdgs_poisson_solve", grad, 6, boundary, W, H, mg, u, stats, ws, stream)
+
+
+def gdgs_poisson_solve_rhs(rho: torch.Tensor, boundary: torch.Tensor | None, W: int, H: int,
+                           mg: L.MgParams | None = None, u=None, stats=None, ws=None,
+                           stream=None):
+    return _poisson("gdgs_poisson_solve_rhs", rho, 3, boundary, W, H, mg, u, stats, ws, stream)
+
+
+def render_workspace_size(K: int, W: int, H: int, capacity: int, mg=None) -> int:
+    lib = L.load()
+    mg = mg if mg is not None else mg_params()
+    return _size(lib.gdgs_workspace_size, K, W, H, capacity, ctypes.byref(mg))
+
+
+def gdgs_render(scene: DeviceScene, cam, boundary: torch.Tensor | None, mg=None,
+                capacity: int | None = None, u=None, stats=None, ws=None, sync_stats=False,
+                stream=None):
+    lib = L.load()
+    dev = scene.opacity.device
+    W, H = int(cam.W), int(cam.H)
+    mg = mg if mg is not None else mg_params()
+    capacity = int(capacity if capacity is not None else max(1 << 16, 16 * scene.K))
+    if boundary is not None:
+        _need(boundary, (3, H, W), F32, "boundary")
+    u = u if u is not None else torch.empty((3, H, W), dtype=F32, device=dev)
+    _need(u, (3, H, W), F32, "u")
+    stats = stats if stats is not None else new_stats(dev)
+    if ws is None:
+        ws = workspace(render_workspace_size(scene.K, W, H, capacity, mg), dev)
+    c = camera_struct(cam)
+    L.check(lib.gdgs_render(ctypes.byref(scene.struct()), ctypes.byref(c), L.ptr(boundary),
+                            ctypes.byref(mg), capacity, L.ptr(u), L.ptr(stats),
+                            1 if sync_stats else 0, L.ptr(ws), ws.numel(),
+                            L.stream_handle(stream)))
+    return u, stats
+
+
+def gdgs_div_adjoint(lam: torch.Tensor, W: int, H: int, dgrad=None, stream=None) -> torch.Tensor:
+    lib = L.load()
+    _need(lam, (3, H, W), F32, "lam")
+    dgrad = dgrad if dgrad is not None else torch.empty((6, H, W), dtype=F32, device=lam.device)
+    _need(dgrad, (6, H, W), F32, "dgrad")
+    L.check(lib.gdgs_div_adjoint(L.ptr(lam), W, H, L.ptr(dgrad), L.stream_handle(stream)))
+    return dgrad
+
+
+def gdgs_raster_grad_backward(proj: dict, opacity: torch.Tensor, value: torch.Tensor, K: int,
+                              bins: dict, W: int, H: int, grad: torch.Tensor,
+                              dgrad: torch.Tensor, ws=None, stream=None) -> dict:
+    lib = L.load()
+    dev = grad.device
+    _need(grad, (6, H, W), F32, "grad")
+    _need(dgrad, (6, H, W), F32, "dgrad")
+    out = dict(mean2d=torch.empty((2, K), dtype=F32, device=dev),
+               conic=torch.empty((3, K), dtype=F32, device=dev),
+               opacity=torch.empty(K, dtype=F32, device=dev),
+               value=torch.empty((6, K), dtype=F32, device=dev))
+    need = _size(lib.gdgs_raster_backward_workspace_size, K, bins["capacity"])
+    ws = ws if ws is not None else workspace(need, dev)
+    L.check(lib.gdgs_raster_grad_backward(
+        ctypes.byref(_proj_struct(proj)), L.ptr(opacity), L.ptr(value), K,
+        ctypes.byref(_bins_struct(bins)), W, H, L.ptr(grad), L.ptr(dgrad), L.ptr(out["mean2d"]),
+        L.ptr(out["conic"]), L.ptr(out["opacity"]), L.ptr(out["value"]), L.ptr(ws), ws.numel(),
+        L.stream_handle(stream)))
+    return out
+
+
+class Renderer:
+    """Keeps a device scene and a workspace for repeated renders (the render
+    call itself allocates nothing).  On a pair-capacity overflow the render is
+    repeated once with a capacity large enough for the reported count."""
+
+    def __init__(self, scene: DeviceScene, W: int, H: int, mg=None, capacity: int | None = None):
+        self.scene, self.W, self.H = scene, int(W), int(H)
+        self.mg = mg if mg is not None else mg_params()
+        self.dev = scene.opacity.device
+        self.stats = new_stats(self.dev)
+        self.u = torch.empty((3, self.H, self.W), dtype=F32, device=self.dev)
+        self._set_capacity(capacity if capacity is not None else max(1 << 16, 16 * scene.K))
+
+    def _set_capacity(self, cap: int):
+        self.capacity = int(cap)
+        self.ws = workspace(render_workspace_size(self.scene.K, self.W, self.H, self.capacity,
+                                                  self.mg), self.dev)
+
+    def render(self, cam, boundary=None, check: bool = True, stream=None) -> torch.Tensor:
+        gdgs_render(self.scene, cam, boundary, self.mg, self.capacity, self.u, self.stats,
+                    self.ws, sync_stats=False, stream=stream)
+        if check:
+            st = read_stats(self.stats)
+            if st["overflow"]:
+                self._set_capacity(int(st["num_pairs"] * 1.25) + 1024)
+                gdgs_render(self.scene, cam, boundary, self.mg, self.capacity, self.u,
+                            self.stats, self.ws, sync_stats=True, stream=stream)
+        return self.u

@@ -1,0 +1,390 @@
+// extern "C" entry points of libgdgs (declared in include/gdgs.h): argument
+// validation on the host, workspace carving, and enqueueing of the HIP
+// kernels of the individual steps on the caller's stream.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "internal.hpp"
+
+namespace gdgs {
+
+namespace {
+thread_local char g_err[512] = "";
+}
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+void clear_error() { g_err[0] = '\0'; }
+
+namespace {
+
+bool aligned4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
+
+#define REQUIRE(cond, ...)                   \
+    do {                                     \
+        if (!(cond)) {                       \
+            set_error(__VA_ARGS__);          \
+            return GDGS_ERR_INVALID_ARGUMENT; \
+        }                                    \
+    } while (0)
+
+#define REQUIRE_PTR(p)                                                          \
+    REQUIRE((p) != nullptr && aligned4(p), "%s is null or not 4-byte aligned", #p)
+
+gdgs_status check_size(int32_t W, int32_t H) {
+    REQUIRE(W >= 3 && H >= 3, "image size %dx%d: both sides must be >= 3", W, H);
+    REQUIRE((int64_t)tiles_x(W) < 65536 && (int64_t)tiles_y(H) < 65536,
+            "image size %dx%d too large for 16-bit tile indices", W, H);
+    return GDGS_OK;
+}
+
+gdgs_status check_proj(const gdgs_proj* p) {
+    REQUIRE(p != nullptr, "proj is null");
+    REQUIRE_PTR(p->mean2d);
+    REQUIRE_PTR(p->conic);
+    REQUIRE_PTR(p->depth);
+    REQUIRE_PTR(p->rect);
+    REQUIRE_PTR(p->count);
+    return GDGS_OK;
+}
+
+gdgs_status check_bins(const gdgs_bins* b, int64_t K) {
+    REQUIRE(b != nullptr, "bins is null");
+    REQUIRE(b->capacity >= 1 && b->capacity < (int64_t)0xFFFFFFFFll,
+            "pair capacity %lld must be in [1, 2^32 - 1)", (long long)b->capacity);
+    REQUIRE_PTR(b->tile_of_pair);
+    REQUIRE_PTR(b->rank_of_pair);
+    REQUIRE_PTR(b->ranges);
+    REQUIRE(b->num_pairs != nullptr && (reinterpret_cast<uintptr_t>(b->num_pairs) & 7u) == 0,
+            "bins.num_pairs is null or not 8-byte aligned");
+    if (K > 0) REQUIRE_PTR(b->order);
+    return GDGS_OK;
+}
+
+gdgs_status check_ws(void* ws, size_t have, size_t need) {
+    if (need > have || (need > 0 && ws == nullptr)) {
+        set_error("workspace of %zu bytes is smaller than the %zu bytes required", have, need);
+        return GDGS_ERR_WORKSPACE;
+    }
+    if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) {
+        set_error("workspace must be 256-byte aligned");
+        return GDGS_ERR_WORKSPACE;
+    }
+    return GDGS_OK;
+}
+
+#define TRY(expr)                          \
+    do {                                   \
+        gdgs_status s_ = (expr);           \
+        if (s_ != GDGS_OK) return s_;      \
+    } while (0)
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Everything gdgs_render carves out of its workspace.
+struct RenderWs {
+    gdgs_proj proj;
+    gdgs_bins bins;
+    float* grad;
+    void* bin_ws;
+    void* raster_ws;
+    void* poisson_ws;
+};
+
+size_t render_layout(int64_t K, int W, int H, int64_t cap, const MgPlan& plan, void* ws,
+                     RenderWs* out) {
+    Carver c(ws);
+    RenderWs r{};
+    const int64_t Kp = K > 0 ? K : 1;
+    r.proj.mean2d = c.take<float>(2 * Kp);
+    r.proj.conic = c.take<float>(3 * Kp);
+    r.proj.depth = c.take<float>(Kp);
+    r.proj.rect = c.take<uint32_t>(2 * Kp);
+    r.proj.count = c.take<uint32_t>(Kp);
+    r.bins.capacity = cap;
+    r.bins.tile_of_pair = c.take<uint32_t>(cap);
+    r.bins.rank_of_pair = c.take<uint32_t>(cap);
+    r.bins.order = c.take<uint32_t>(Kp);
+    r.bins.ranges = c.take<uint32_t>(2 * (size_t)tiles_x(W) * tiles_y(H));
+    r.bins.num_pairs = c.take<int64_t>(1);
+    r.grad = c.take<float>((size_t)6 * W * H);
+    r.bin_ws = c.take<char>(bin_ws_layout(K, cap, nullptr, nullptr));
+    r.raster_ws = c.take<char>(raster_ws_bytes(K));
+    r.poisson_ws = c.take<char>(poisson_ws_bytes(plan, W, H));
+    if (out) *out = r;
+    return c.off + 256;
+}
+
+__global__ void k_render_stats(const int64_t* num_pairs, int64_t cap, gdgs_stats* stats) {
+    if (threadIdx.x == 0) {
+        const int64_t p = *num_pairs;
+        stats->num_pairs = p;
+        stats->overflow = p > cap ? 1 : 0;
+    }
+}
+
+}  // namespace
+}  // namespace gdgs
+
+using namespace gdgs;
+
+extern "C" {
+
+const char* gdgs_status_string(gdgs_status s) {
+    switch (s) {
+        case GDGS_OK: return "ok";
+        case GDGS_ERR_INVALID_ARGUMENT: return "invalid argument";
+        case GDGS_ERR_CAPACITY: return "pair capacity exceeded";
+        case GDGS_ERR_WORKSPACE: return "workspace too small";
+        case GDGS_ERR_BUDGET: return "memory budget exceeded";
+        case GDGS_ERR_HIP: return "HIP runtime error";
+        case GDGS_ERR_UNSUPPORTED: return "unsupported";
+        case GDGS_ERR_NOT_READY: return "not ready";
+    }
+    return "unknown status";
+}
+
+const char* gdgs_last_error(void) { return g_err; }
+
+const char* gdgs_version(void) { return "gdgs 0.1 gfx950"; }
+
+gdgs_status gdgs_bin_sort_workspace_size(int64_t K, int32_t W, int32_t H, int64_t pair_capacity,
+                                         size_t* bytes) {
+    clear_error();
+    REQUIRE(bytes != nullptr, "bytes is null");
+    REQUIRE(K >= 0 && K < (int64_t)0xFFFFFFFFll, "K = %lld out of range", (long long)K);
+    TRY(check_size(W, H));
+    REQUIRE(pair_capacity >= 1 && pair_capacity < (int64_t)0xFFFFFFFFll,
+            "pair capacity %lld out of range", (long long)pair_capacity);
+    *bytes = bin_ws_layout(K, pair_capacity, nullptr, nullptr);
+    return GDGS_OK;
+}
+
+gdgs_status gdgs_raster_workspace_size(int64_t K, size_t* bytes) {
+    clear_error();
+    REQUIRE(bytes != nullptr, "bytes is null");
+    REQUIRE(K >= 0 && K < (int64_t)0xFFFFFFFFll, "K = %lld out of range", (long long)K);
+    *bytes = raster_ws_bytes(K);
+    return GDGS_OK;
+}
+
+gdgs_status gdgs_poisson_workspace_size(int32_t W, int32_t H, const gdgs_mg_params* mg,
+                                        size_t* bytes) {
+    clear_error();
+    REQUIRE(bytes != nullptr, "bytes is null");
+    TRY(check_size(W, H));
+    MgPlan plan;
+    TRY(mg_plan(W, H, mg, &plan));
+    *bytes = poisson_ws_bytes(plan, W, H);
+    return GDGS_OK;
+}
+
+gdgs_status gdgs_workspace_size(int64_t K, int32_t W, int32_t H, int64_t pair_capacity,
+                                const gdgs_mg_params* mg, size_t* bytes) {
+    clear_error();
+    REQUIRE(bytes != nullptr, "bytes is null");
+    REQUIRE(K >= 0 && K < (int64_t)0xFFFFFFFFll, "K = %lld out of range", (long long)K);
+    TRY(check_size(W, H));
+    REQUIRE(pair_capacity >= 1 && pair_capacity < (int64_t)0xFFFFFFFFll,
+            "pair capacity %lld out of range", (long long)pair_capacity);
+    MgPlan plan;
+    TRY(mg_plan(W, H, mg, &plan));
+    *bytes = render_layout(K, W, H, pair_capacity, plan, nullptr, nullptr);
+    return GDGS_OK;
+}
+
+gdgs_status gdgs_raster_backward_workspace_size(int64_t K, int64_t pair_capacity, size_t* bytes) {
+    clear_error();
+    REQUIRE(bytes != nullptr, "bytes is null");
+    REQUIRE(K >= 0 && K < (int64_t)0xFFFFFFFFll, "K = %lld out of range", (long long)K);
+    REQUIRE(pair_capacity >= 1 && pair_capacity < (int64_t)0xFFFFFFFFll,
+            "pair capacity %lld out of range", (long long)pair_capacity);
+    *bytes = raster_bwd_ws_bytes(K, pair_capacity);
+    return GDGS_OK;
+}
+
+gdgs_status gdgs_project(const gdgs_scene* scene, const gdgs_camera* cam, const gdgs_proj* out,
+                         void* stream) {
+    clear_error();
+    REQUIRE(scene != nullptr && cam != nullptr, "scene or camera is null");
+    REQUIRE(scene->K >= 0 && scene->K < (int64_t)0xFFFFFFFFll, "K = %lld out of range",
+            (long long)scene->K);
+    TRY(check_size(cam->W, cam->H));
+    REQUIRE(cam->fx > 0 && cam->fy > 0, "focal lengths must be positive (fx %g, fy %g)", cam->fx,
+            cam->fy);
+    if (scene->K == 0) return GDGS_OK;
+    REQUIRE_PTR(scene->mean);
+    REQUIRE_PTR(scene->log_scale);
+    REQUIRE_PTR(scene->quat);
+    TRY(check_proj(out));
+    return launch_project(*scene, *cam, *out, as_stream(stream));
+}
+
+gdgs_status gdgs_project_2d(const float* mean2d, const float* conic, const float* depth,
+                            int64_t K, int32_t W, int32_t H, const gdgs_proj* out, void* stream) {
+    clear_error();
+    REQUIRE(K >= 0 && K < (int64_t)0xFFFFFFFFll, "K = %lld out of range", (long long)K);
+    TRY(check_size(W, H));
+    if (K == 0) return GDGS_OK;
+    REQUIRE_PTR(mean2d);
+    REQUIRE_PTR(conic);
+    REQUIRE_PTR(depth);
+    TRY(check_proj(out));
+    return launch_project_2d(mean2d, conic, depth, K, W, H, *out, as_stream(stream));
+}
+
+gdgs_status gdgs_bin_sort(const gdgs_proj* proj, int64_t K, int32_t W, int32_t H,
+                          const gdgs_bins* bins, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    REQUIRE(K >= 0 && K < (int64_t)0xFFFFFFFFll, "K = %lld out of range", (long long)K);
+    TRY(check_size(W, H));
+    if (K > 0) TRY(check_proj(proj));
+    TRY(check_bins(bins, K));
+    TRY(check_ws(ws, ws_bytes, bin_ws_layout(K, bins->capacity, nullptr, nullptr)));
+    BinWs b;
+    bin_ws_layout(K, bins->capacity, ws, &b);
+    gdgs_proj p = K > 0 ? *proj : gdgs_proj{};
+    return launch_bin_sort(p, K, W, H, *bins, b, as_stream(stream));
+}
+
+gdgs_status gdgs_raster_grad(const gdgs_proj* proj, const float* opacity, const float* value,
+                             int64_t K, const gdgs_bins* bins, int32_t W, int32_t H, float* grad,
+                             void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    REQUIRE(K >= 0 && K < (int64_t)0xFFFFFFFFll, "K = %lld out of range", (long long)K);
+    TRY(check_size(W, H));
+    REQUIRE_PTR(grad);
+    if (K > 0) {
+        TRY(check_proj(proj));
+        REQUIRE_PTR(opacity);
+        REQUIRE_PTR(value);
+    }
+    TRY(check_bins(bins, K));
+    TRY(check_ws(ws, ws_bytes, raster_ws_bytes(K)));
+    gdgs_proj p = K > 0 ? *proj : gdgs_proj{};
+    return launch_raster(p, opacity, value, K, *bins, W, H, grad, ws, as_stream(stream));
+}
+
+static gdgs_status poisson_common(const float* grad, const float* rho, const float* boundary,
+                                  int32_t W, int32_t H, const gdgs_mg_params* mg, float* u,
+                                  gdgs_stats* stats_dev, void* ws, size_t ws_bytes,
+                                  void* stream) {
+    TRY(check_size(W, H));
+    REQUIRE_PTR(u);
+    if (boundary) REQUIRE_PTR(boundary);
+    if (stats_dev) REQUIRE((reinterpret_cast<uintptr_t>(stats_dev) & 7u) == 0,
+                           "stats_dev not 8-byte aligned");
+    MgPlan plan;
+    TRY(mg_plan(W, H, mg, &plan));
+    TRY(check_ws(ws, ws_bytes, poisson_ws_bytes(plan, W, H)));
+    return launch_poisson(grad, rho, boundary, W, H, plan, u, stats_dev, ws, as_stream(stream));
+}
+
+gdgs_status gdgs_poisson_solve(const float* grad, const float* boundary, int32_t W, int32_t H,
+                               const gdgs_mg_params* mg, float* u, gdgs_stats* stats_dev,
+                               void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    REQUIRE_PTR(grad);
+    return poisson_common(grad, nullptr, boundary, W, H, mg, u, stats_dev, ws, ws_bytes, stream);
+}
+
+gdgs_status gdgs_poisson_solve_rhs(const float* rho, const float* boundary, int32_t W, int32_t H,
+                                   const gdgs_mg_params* mg, float* u, gdgs_stats* stats_dev,
+                                   void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    REQUIRE_PTR(rho);
+    return poisson_common(nullptr, rho, boundary, W, H, mg, u, stats_dev, ws, ws_bytes, stream);
+}
+
+gdgs_status gdgs_render(const gdgs_scene* scene, const gdgs_camera* cam, const float* boundary,
+                        const gdgs_mg_params* mg, int64_t pair_capacity, float* u,
+                        gdgs_stats* stats_dev, int sync_stats, void* ws, size_t ws_bytes,
+                        void* stream) {
+    clear_error();
+    REQUIRE(scene != nullptr && cam != nullptr, "scene or camera is null");
+    const int64_t K = scene->K;
+    REQUIRE(K >= 0 && K < (int64_t)0xFFFFFFFFll, "K = %lld out of range", (long long)K);
+    TRY(check_size(cam->W, cam->H));
+    REQUIRE(cam->fx > 0 && cam->fy > 0, "focal lengths must be positive");
+    REQUIRE(pair_capacity >= 1 && pair_capacity < (int64_t)0xFFFFFFFFll,
+            "pair capacity %lld out of range", (long long)pair_capacity);
+    REQUIRE_PTR(u);
+    REQUIRE(stats_dev != nullptr && (reinterpret_cast<uintptr_t>(stats_dev) & 7u) == 0,
+            "stats_dev is null or not 8-byte aligned");
+    if (boundary) REQUIRE_PTR(boundary);
+    if (K > 0) {
+        REQUIRE_PTR(scene->mean);
+        REQUIRE_PTR(scene->log_scale);
+        REQUIRE_PTR(scene->quat);
+        REQUIRE_PTR(scene->opacity);
+        REQUIRE_PTR(scene->value);
+    }
+    const int W = cam->W, H = cam->H;
+    MgPlan plan;
+    TRY(mg_plan(W, H, mg, &plan));
+    TRY(check_ws(ws, ws_bytes, render_layout(K, W, H, pair_capacity, plan, nullptr, nullptr)));
+    RenderWs r;
+    render_layout(K, W, H, pair_capacity, plan, ws, &r);
+    hipStream_t st = as_stream(stream);
+    if (K > 0) TRY(launch_project(*scene, *cam, r.proj, st));
+    BinWs b;
+    bin_ws_layout(K, pair_capacity, r.bin_ws, &b);
+    TRY(launch_bin_sort(r.proj, K, W, H, r.bins, b, st));
+    TRY(launch_raster(r.proj, scene->opacity, scene->value, K, r.bins, W, H, r.grad, r.raster_ws,
+                      st));
+    TRY(launch_poisson(r.grad, nullptr, boundary, W, H, plan, u, stats_dev, r.poisson_ws, st));
+    hipLaunchKernelGGL(k_render_stats, dim3(1), dim3(64), 0, st, r.bins.num_pairs, pair_capacity,
+                       stats_dev);
+    GDGS_LAUNCH_CHECK();
+    if (sync_stats) {
+        GDGS_HIP_TRY(hipStreamSynchronize(st));
+        gdgs_stats h;
+        GDGS_HIP_TRY(hipMemcpy(&h, stats_dev, sizeof(h), hipMemcpyDeviceToHost));
+        if (h.overflow) {
+            set_error("render needed %lld pairs, capacity is %lld", (long long)h.num_pairs,
+                      (long long)pair_capacity);
+            return GDGS_ERR_CAPACITY;
+        }
+    }
+    return GDGS_OK;
+}
+
+gdgs_status gdgs_div_adjoint(const float* lam, int32_t W, int32_t H, float* dgrad, void* stream) {
+    clear_error();
+    TRY(check_size(W, H));
+    REQUIRE_PTR(lam);
+    REQUIRE_PTR(dgrad);
+    return launch_div_adjoint(lam, W, H, dgrad, as_stream(stream));
+}
+
+gdgs_status gdgs_raster_grad_backward(const gdgs_proj* proj, const float* opacity,
+                                      const float* value, int64_t K, const gdgs_bins* bins,
+                                      int32_t W, int32_t H, const float* grad, const float* dgrad,
+                                      float* dmean2d, float* dconic, float* dopacity,
+                                      float* dvalue, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    REQUIRE(K >= 0 && K < (int64_t)0xFFFFFFFFll, "K = %lld out of range", (long long)K);
+    TRY(check_size(W, H));
+    if (K == 0) return GDGS_OK;
+    TRY(check_proj(proj));
+    TRY(check_bins(bins, K));
+    REQUIRE_PTR(opacity);
+    REQUIRE_PTR(value);
+    REQUIRE_PTR(grad);
+    REQUIRE_PTR(dgrad);
+    REQUIRE_PTR(dmean2d);
+    REQUIRE_PTR(dconic);
+    REQUIRE_PTR(dopacity);
+    REQUIRE_PTR(dvalue);
+    TRY(check_ws(ws, ws_bytes, raster_bwd_ws_bytes(K, bins->capacity)));
+    return launch_raster_backward(*proj, opacity, value, K, *bins, W, H, grad, dgrad, dmean2d,
+                                  dconic, dopacity, dvalue, ws, as_stream(stream));
+}
+
+}  // extern "C"

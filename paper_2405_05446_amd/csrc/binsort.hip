@@ -1,0 +1,463 @@
+// Tile binning and compositing order (the front-to-back order of the alpha
+// blend, GDGS Sec. 1.2 Eq. 11, "sorted from the view direction").
+//
+// 1. key each splat by the bits of its FP32 depth (culled splats last) and
+//    stable-radix-sort the splat indices: order[s] = splat of depth rank s;
+// 2. exclusive scan of the tile counts in rank order, then one (tile, s) pair
+//    per tile of each splat's rectangle, written in rank order;
+// 3. stable radix sort of the pairs by tile id, then each tile's range.
+// Because step 2 emits pairs in depth-rank order and step 3 is stable, the
+// final order equals a lexicographic sort by (tile, depth bits, splat index).
+//
+// The radix sort is a reduce-then-scan LSD sort with 8-bit digits on a fixed
+// grid (the element count may live on the device): per pass an upsweep digit
+// histogram per block, a scan of every digit's row of block counts, and a
+// downsweep that ranks each 2048-key tile in LDS with wave64 ballots (lanes
+// holding equal digits are matched bit by bit; a lane's rank is the popcount
+// of lower matched lanes), stages the tile in LDS in sorted order and writes
+// coalesced runs.
+#include "internal.hpp"
+
+namespace gdgs {
+namespace {
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 8;
+constexpr int kSortTile = kSortThreads * kSortItems;  // keys per block iteration
+constexpr int kWaves = kSortThreads / 64;
+constexpr int kRadix = 256;
+constexpr int kMaxGrid = 1024;
+
+__device__ __forceinline__ int64_t clamp_n(const int64_t* n_dev, int64_t n_host, int64_t cap) {
+    int64_t n = n_dev ? *n_dev : n_host;
+    if (n > cap) n = cap;
+    if (n < 0) n = 0;
+    return n;
+}
+
+// Contiguous key range of block b: chunks are whole multiples of kSortTile.
+__device__ __forceinline__ void block_range(int64_t n, int G, int b, int64_t* lo, int64_t* hi) {
+    int64_t chunk = (n + G - 1) / G;
+    chunk = (chunk + kSortTile - 1) / kSortTile * kSortTile;
+    int64_t l = (int64_t)b * chunk;
+    if (l > n) l = n;
+    int64_t h = l + chunk;
+    if (h > n) h = n;
+    *lo = l;
+    *hi = h;
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const int lane = __lane_id();
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Mask of the valid lanes of this wave whose digit equals this lane's digit.
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid, int bits) {
+    uint64_t m = __ballot(valid);
+    for (int b = 0; b < bits; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bb = __ballot(bit);
+        m &= bit ? bb : ~bb;
+    }
+    return m;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    const int lane = __lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+// Exclusive scan of one value per thread over a 256-thread block.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* s_tmp, uint32_t* total) {
+    const int lane = __lane_id(), w = threadIdx.x >> 6;
+    const uint32_t inc = wave_incl_scan(x);
+    if (lane == 63) s_tmp[w] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) {
+        const uint32_t v = s_tmp[i];
+        off += (i < w) ? v : 0u;
+        tot += v;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - x;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(
+    const uint32_t* __restrict__ keys, const int64_t* n_dev, int64_t n_host, int64_t cap,
+    int shift, int bits, uint32_t* __restrict__ hist) {
+    __shared__ uint32_t s_h[kRadix];
+    const int G = gridDim.x, b = blockIdx.x, t = threadIdx.x;
+    s_h[t] = 0;
+    __syncthreads();
+    int64_t lo, hi;
+    block_range(clamp_n(n_dev, n_host, cap), G, b, &lo, &hi);
+    const uint32_t mask = (1u << bits) - 1u;
+    const uint64_t lt = lanemask_lt();
+    for (int64_t base = lo; base < hi; base += kSortTile) {
+        uint32_t d[kSortItems];
+#pragma unroll
+        for (int r = 0; r < kSortItems; ++r) {
+            const int64_t i = base + r * kSortThreads + t;
+            d[r] = i < hi ? (keys[i] >> shift) & mask : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < kSortItems; ++r) {
+            const bool valid = base + r * kSortThreads + t < hi;
+            const uint64_t peers = match_digit(d[r], valid, bits);
+            if (valid && (peers & lt) == 0) atomicAdd(&s_h[d[r]], (uint32_t)__popcll(peers));
+        }
+    }
+    __syncthreads();
+    hist[(size_t)t * G + b] = s_h[t];
+}
+
+// Block d: exclusive scan of digit d's block counts (in place) and its total.
+__global__ __launch_bounds__(256) void k_radix_scan(uint32_t* __restrict__ hist, int G,
+                                                    uint32_t* __restrict__ digit_tot) {
+    __shared__ uint32_t s_tmp[kWaves];
+    constexpr int IT = kMaxGrid / 256;
+    const int d = blockIdx.x, t = threadIdx.x;
+    uint32_t* row = hist + (size_t)d * G;
+    uint32_t v[IT], sum = 0;
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+        const int idx = t * IT + i;
+        v[i] = idx < G ? row[idx] : 0u;
+        sum += v[i];
+    }
+    uint32_t tot;
+    uint32_t off = block_excl_scan(sum, s_tmp, &tot);
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+        const int idx = t * IT + i;
+        if (idx < G) row[idx] = off;
+        off += v[i];
+    }
+    if (t == 0) digit_tot[d] = tot;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const int64_t* n_dev,
+    int64_t n_host, int64_t cap, int shift, int bits, const uint32_t* __restrict__ hist,
+    const uint32_t* __restrict__ digit_tot) {
+    __shared__ uint32_t s_base[kRadix];
+    __shared__ uint32_t s_wcnt[kWaves][kRadix];
+    __shared__ uint32_t s_tstart[kRadix];
+    __shared__ uint32_t s_key[kSortTile];
+    __shared__ uint32_t s_val[kSortTile];
+    __shared__ uint32_t s_tmp[kWaves];
+    const int G = gridDim.x, b = blockIdx.x, t = threadIdx.x, lane = __lane_id(), w = t >> 6;
+    const uint32_t mask = (1u << bits) - 1u;
+    const uint64_t lt = lanemask_lt();
+    {
+        uint32_t all;
+        const uint32_t start = block_excl_scan(digit_tot[t], s_tmp, &all);
+        s_base[t] = start + hist[(size_t)t * G + b];
+    }
+    int64_t lo, hi;
+    block_range(clamp_n(n_dev, n_host, cap), G, b, &lo, &hi);
+    for (int64_t tlo = lo; tlo < hi; tlo += kSortTile) {
+        for (int i = t; i < kWaves * kRadix; i += kSortThreads) (&s_wcnt[0][0])[i] = 0u;
+        __syncthreads();
+        uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
+        const int64_t wbase = tlo + (int64_t)w * 64 * kSortItems;
+#pragma unroll
+        for (int r = 0; r < kSortItems; ++r) {
+            const int64_t i = wbase + r * 64 + lane;
+            const bool valid = i < hi;
+            key[r] = valid ? kin[i] : 0u;
+            val[r] = valid ? vin[i] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < kSortItems; ++r) {
+            const bool valid = wbase + r * 64 + lane < hi;
+            const uint32_t d = (key[r] >> shift) & mask;
+            const uint64_t peers = match_digit(d, valid, bits);
+            const uint32_t prev = s_wcnt[w][d];
+            const uint32_t rr = (uint32_t)__popcll(peers & lt);
+            if (valid && rr == 0) s_wcnt[w][d] = prev + (uint32_t)__popcll(peers);
+            rank[r] = prev + rr;
+        }
+        __syncthreads();
+        uint32_t tot_t;
+        {
+            const uint32_t c0 = s_wcnt[0][t], c1 = s_wcnt[1][t], c2 = s_wcnt[2][t],
+                           c3 = s_wcnt[3][t];
+            tot_t = c0 + c1 + c2 + c3;
+            s_wcnt[0][t] = 0u;
+            s_wcnt[1][t] = c0;
+            s_wcnt[2][t] = c0 + c1;
+            s_wcnt[3][t] = c0 + c1 + c2;
+            uint32_t all;
+            s_tstart[t] = block_excl_scan(tot_t, s_tmp, &all);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kSortItems; ++r) {
+            if (wbase + r * 64 + lane < hi) {
+                const uint32_t d = (key[r] >> shift) & mask;
+                const uint32_t pos = s_tstart[d] + s_wcnt[w][d] + rank[r];
+                s_key[pos] = key[r];
+                s_val[pos] = val[r];
+            }
+        }
+        __syncthreads();
+        const int ntile = (int)min((int64_t)kSortTile, hi - tlo);
+        for (int p = t; p < ntile; p += kSortThreads) {
+            const uint32_t k = s_key[p];
+            const uint32_t d = (k >> shift) & mask;
+            const uint32_t g = s_base[d] + ((uint32_t)p - s_tstart[d]);
+            kout[g] = k;
+            vout[g] = s_val[p];
+        }
+        __syncthreads();
+        s_base[t] += tot_t;
+    }
+}
+
+// ---------------------------------------------------------------- binning
+__global__ void k_depth_keys(const float* __restrict__ depth, const uint32_t* __restrict__ count,
+                             int64_t K, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    keys[k] = count[k] ? __float_as_uint(depth[k]) : 0xFFFFFFFFu;
+    vals[k] = (uint32_t)k;
+}
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__global__ __launch_bounds__(kScanThreads) void k_count_reduce(const uint32_t* __restrict__ order,
+                                                               const uint32_t* __restrict__ count,
+                                                               int64_t K,
+                                                               unsigned long long* __restrict__ bsum) {
+    __shared__ uint32_t s_tmp[kWaves];
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)t * kScanItems;
+    uint32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t s = base + i;
+        if (s < K) {
+            const uint32_t k = order[s];
+            if (k < (uint64_t)K) sum += count[k];
+        }
+    }
+    uint32_t tot;
+    block_excl_scan(sum, s_tmp, &tot);
+    if (t == 0) bsum[blockIdx.x] = tot;
+}
+
+// One block: exclusive scan of nb block sums in place; writes the total.
+__global__ __launch_bounds__(1024) void k_scan_bsums(unsigned long long* __restrict__ bsum,
+                                                     int64_t nb, int64_t* __restrict__ total) {
+    __shared__ unsigned long long s_w[16];
+    __shared__ unsigned long long s_carry;
+    const int t = threadIdx.x, lane = __lane_id(), w = t >> 6;
+    if (t == 0) s_carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < nb; base += 1024) {
+        const int64_t i = base + t;
+        const unsigned long long x = i < nb ? bsum[i] : 0ull;
+        unsigned long long inc = x;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const unsigned long long y = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += y;
+        }
+        if (lane == 63) s_w[w] = inc;
+        __syncthreads();
+        unsigned long long off = s_carry, tot = 0;
+        for (int j = 0; j < 16; ++j) {
+            off += (j < w) ? s_w[j] : 0ull;
+            tot += s_w[j];
+        }
+        if (i < nb) bsum[i] = off + inc - x;
+        __syncthreads();
+        if (t == 0) s_carry += tot;
+        __syncthreads();
+    }
+    if (t == 0) *total = (int64_t)s_carry;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_emit_pairs(
+    const uint32_t* __restrict__ order, const uint32_t* __restrict__ count,
+    const uint32_t* __restrict__ rect, int64_t K, const unsigned long long* __restrict__ bsum,
+    int64_t cap, int nx, uint32_t* __restrict__ tile_out, uint32_t* __restrict__ rank_out) {
+    __shared__ uint32_t s_tmp[kWaves];
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)t * kScanItems;
+    uint32_t c[kScanItems], ks[kScanItems], sum = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t s = base + i;
+        ks[i] = s < K ? order[s] : 0u;
+        c[i] = (s < K && ks[i] < (uint64_t)K) ? count[ks[i]] : 0u;
+        sum += c[i];
+    }
+    uint32_t tot;
+    const uint32_t excl = block_excl_scan(sum, s_tmp, &tot);
+    int64_t off = (int64_t)bsum[blockIdx.x] + excl;
+#pragma unroll 1
+    for (int i = 0; i < kScanItems; ++i) {
+        if (c[i] == 0) continue;
+        const uint32_t k = ks[i];
+        const uint32_t r0 = rect[k], r1 = rect[K + k];
+        const int tx0 = r0 & 0xFFFF, tx1 = r0 >> 16, ty0 = r1 & 0xFFFF, ty1 = r1 >> 16;
+        const uint32_t s = (uint32_t)(base + i);
+        for (int ty = ty0; ty < ty1; ++ty) {
+            for (int tx = tx0; tx < tx1; ++tx) {
+                if (off < cap) {
+                    tile_out[off] = (uint32_t)(ty * nx + tx);
+                    rank_out[off] = s;
+                }
+                ++off;
+            }
+        }
+    }
+}
+
+__global__ void k_tile_ranges(const uint32_t* __restrict__ tiles, const int64_t* n_dev, int64_t cap,
+                              uint32_t* __restrict__ ranges, int T) {
+    const int64_t n = clamp_n(n_dev, 0, cap);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t tl = tiles[i];
+        if (tl >= (uint32_t)T) continue;
+        if (i == 0 || tiles[i - 1] != tl) ranges[tl] = (uint32_t)i;
+        if (i == n - 1 || tiles[i + 1] != tl) ranges[T + tl] = (uint32_t)(i + 1);
+    }
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, size_t n, uint32_t v) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+int bitlen(uint64_t x) {
+    int b = 0;
+    while (x) {
+        ++b;
+        x >>= 1;
+    }
+    return b;
+}
+
+// One full LSD sort of (key, val) pairs over `bits` key bits.  X_0 = (k0, v0);
+// pass p writes X_{p+1}, alternating between (k0, v0) and (k1, v1); the last
+// pass writes (kfin, vfin).
+gdgs_status radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uint32_t* kfin,
+                       uint32_t* vfin, const int64_t* n_dev, int64_t n_host, int64_t cap,
+                       int key_bits, uint32_t* hist, uint32_t* digit_tot, hipStream_t st) {
+    const int G = sort_grid(cap);
+    const int passes = (key_bits + 7) / 8;
+    uint32_t* kb[2] = {k0, k1};
+    uint32_t* vb[2] = {v0, v1};
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
+        const int bits = key_bits - shift < 8 ? key_bits - shift : 8;
+        const uint32_t* kin = kb[p & 1];
+        const uint32_t* vin = vb[p & 1];
+        uint32_t* kout = (p == passes - 1) ? kfin : kb[(p + 1) & 1];
+        uint32_t* vout = (p == passes - 1) ? vfin : vb[(p + 1) & 1];
+        hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(kSortThreads), 0, st, kin, n_dev, n_host,
+                           cap, shift, bits, hist);
+        hipLaunchKernelGGL(k_radix_scan, dim3(kRadix), dim3(256), 0, st, hist, G, digit_tot);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(G), dim3(kSortThreads), 0, st, kin, vin, kout,
+                           vout, n_dev, n_host, cap, shift, bits, hist, digit_tot);
+    }
+    GDGS_LAUNCH_CHECK();
+    return GDGS_OK;
+}
+
+}  // namespace
+
+int sort_grid(int64_t cap) {
+    int64_t g = (cap + kSortTile - 1) / kSortTile;
+    if (g < 1) g = 1;
+    if (g > kMaxGrid) g = kMaxGrid;
+    return (int)g;
+}
+
+size_t bin_ws_layout(int64_t K, int64_t cap, void* ws, BinWs* out) {
+    Carver c(ws);
+    BinWs b;
+    const int64_t Kp = K > 0 ? K : 1;
+    const int64_t cp = cap > 0 ? cap : 1;
+    for (int i = 0; i < 2; ++i) {
+        b.dkey[i] = c.take<uint32_t>(Kp);
+        b.dval[i] = c.take<uint32_t>(Kp);
+        b.pkey[i] = c.take<uint32_t>(cp);
+        b.pval[i] = c.take<uint32_t>(cp);
+    }
+    const int G = sort_grid(Kp > cp ? Kp : cp);
+    b.hist = c.take<uint32_t>((size_t)kRadix * G);
+    b.digit_tot = c.take<uint32_t>(kRadix);
+    b.bsum = c.take<uint32_t>(2 * ((Kp + kScanTile - 1) / kScanTile + 1));
+    if (out) *out = b;
+    return c.off + 256;
+}
+
+gdgs_status launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st) {
+    if (n == 0) return GDGS_OK;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+    GDGS_LAUNCH_CHECK();
+    return GDGS_OK;
+}
+
+gdgs_status launch_bin_sort(const gdgs_proj& proj, int64_t K, int W, int H, const gdgs_bins& bins,
+                            const BinWs& ws, hipStream_t st) {
+    const int nx = tiles_x(W), T = nx * tiles_y(H);
+    gdgs_status s = launch_fill_u32(bins.ranges, 2 * (size_t)T, 0u, st);
+    if (s != GDGS_OK) return s;
+    if (K == 0) {
+        // no splats: zero pairs
+        hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(1024), 0, st,
+                           reinterpret_cast<unsigned long long*>(ws.bsum), (int64_t)0,
+                           bins.num_pairs);
+        GDGS_LAUNCH_CHECK();
+        return GDGS_OK;
+    }
+    // 1. depth order of the splats
+    hipLaunchKernelGGL(k_depth_keys, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, st,
+                       proj.depth, proj.count, K, ws.dkey[0], ws.dval[0]);
+    s = radix_sort(ws.dkey[0], ws.dval[0], ws.dkey[1], ws.dval[1],
+                   ws.dkey[0], bins.order, nullptr, K, K, 32, ws.hist,
+                   ws.digit_tot, st);
+    if (s != GDGS_OK) return s;
+    // 2. scan of tile counts in rank order, pair emission
+    const int64_t nb = (K + kScanTile - 1) / kScanTile;
+    unsigned long long* bsum = reinterpret_cast<unsigned long long*>(ws.bsum);
+    hipLaunchKernelGGL(k_count_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, st, bins.order,
+                       proj.count, K, bsum);
+    hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(1024), 0, st, bsum, nb, bins.num_pairs);
+    hipLaunchKernelGGL(k_emit_pairs, dim3((unsigned)nb), dim3(kScanThreads), 0, st, bins.order,
+                       proj.count, proj.rect, K, bsum, bins.capacity, nx, ws.pkey[0], ws.pval[0]);
+    GDGS_LAUNCH_CHECK();
+    // 3. stable sort of the pairs by tile, then the ranges
+    const int tbits = bitlen((uint64_t)(T > 1 ? T - 1 : 1));
+    s = radix_sort(ws.pkey[0], ws.pval[0], ws.pkey[1], ws.pval[1], bins.tile_of_pair,
+                   bins.rank_of_pair, bins.num_pairs, 0, bins.capacity, tbits, ws.hist,
+                   ws.digit_tot, st);
+    if (s != GDGS_OK) return s;
+    hipLaunchKernelGGL(k_tile_ranges, dim3(2048), dim3(256), 0, st, bins.tile_of_pair,
+                       bins.num_pairs, bins.capacity, bins.ranges, T);
+    GDGS_LAUNCH_CHECK();
+    return GDGS_OK;
+}
+
+}  // namespace gdgs

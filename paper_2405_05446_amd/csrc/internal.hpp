@@ -1,0 +1,134 @@
+// Internal declarations shared by the HIP translation units of libgdgs.
+// Not part of the public C ABI (include/gdgs.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/gdgs.h"
+
+namespace gdgs {
+
+// Support cut-off of a splat: G = exp(-E) only where E <= ln(1e5).
+constexpr double kEcutD = 11.512925464970229;
+constexpr float kEcut = 11.512925464970229f;
+// Splats at camera depth <= kZnear are culled.
+constexpr double kZnear = 0.2;
+// Screen tile edge (pixels) used to bin the compositing work.
+constexpr int kTile = 16;
+// A pixel stops accumulating once its transmittance is below this.
+constexpr float kTmin = 1e-7f;
+// Multigrid: at most this many grids, each channel's coarse grids that fit
+// together in kLdsBudget bytes of LDS are solved inside one workgroup.
+constexpr int kMaxLevels = 8;
+constexpr int kLdsBudget = 120 * 1024;
+
+// ---------------------------------------------------------------- errors
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define GDGS_HIP_TRY(expr)                                                        \
+    do {                                                                          \
+        hipError_t e_ = (expr);                                                   \
+        if (e_ != hipSuccess) {                                                   \
+            ::gdgs::set_error("%s failed: %s", #expr, hipGetErrorString(e_));      \
+            return GDGS_ERR_HIP;                                                  \
+        }                                                                         \
+    } while (0)
+
+#define GDGS_LAUNCH_CHECK()                                                       \
+    do {                                                                          \
+        hipError_t e_ = hipGetLastError();                                        \
+        if (e_ != hipSuccess) {                                                   \
+            ::gdgs::set_error("kernel launch failed at %s:%d: %s", __FILE__,       \
+                              __LINE__, hipGetErrorString(e_));                   \
+            return GDGS_ERR_HIP;                                                  \
+        }                                                                         \
+    } while (0)
+
+// ---------------------------------------------------------------- workspace
+// Bump allocator over a caller-provided workspace; every carve is 256-byte
+// aligned.  With base == nullptr it only measures.
+struct Carver {
+    char* base;
+    size_t off = 0;
+    explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+    template <typename T>
+    T* take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+inline int tiles_x(int W) { return (W + kTile - 1) / kTile; }
+inline int tiles_y(int H) { return (H + kTile - 1) / kTile; }
+
+// ---------------------------------------------------------------- sort
+// Sizes of the radix-sort launch for n (or a device-side n up to cap) keys.
+int sort_grid(int64_t cap);
+
+// Workspace of the binning step.
+struct BinWs {
+    uint32_t* dkey[2];   // depth-sort ping-pong keys [K]
+    uint32_t* dval[2];   // depth-sort ping-pong values [K]
+    uint32_t* pkey[2];   // pair ping-pong keys [cap]
+    uint32_t* pval[2];   // pair ping-pong values [cap]
+    uint32_t* hist;      // [256][G]
+    uint32_t* digit_tot; // [256]
+    uint32_t* bsum;      // [nb] block sums of tile counts
+};
+size_t bin_ws_layout(int64_t K, int64_t cap, void* ws, BinWs* out);
+
+gdgs_status launch_bin_sort(const gdgs_proj& proj, int64_t K, int W, int H, const gdgs_bins& bins,
+                            const BinWs& ws, hipStream_t st);
+
+// ---------------------------------------------------------------- project
+gdgs_status launch_project(const gdgs_scene& s, const gdgs_camera& cam, const gdgs_proj& out,
+                           hipStream_t st);
+gdgs_status launch_project_2d(const float* mean2d, const float* conic, const float* depth,
+                              int64_t K, int W, int H, const gdgs_proj& out, hipStream_t st);
+
+// ---------------------------------------------------------------- raster
+// 64-byte per-splat record in depth-rank order: (mx, my, ox, oy),
+// (a, 2b, c, alpha), (v0..v3), (v4, v5, 0, 0).
+size_t raster_ws_bytes(int64_t K);
+gdgs_status launch_raster(const gdgs_proj& proj, const float* opacity, const float* value,
+                          int64_t K, const gdgs_bins& bins, int W, int H, float* grad,
+                          void* ws, hipStream_t st);
+size_t raster_bwd_ws_bytes(int64_t K, int64_t cap);
+gdgs_status launch_raster_backward(const gdgs_proj& proj, const float* opacity,
+                                   const float* value, int64_t K, const gdgs_bins& bins, int W,
+                                   int H, const float* grad, const float* dgrad, float* dmean2d,
+                                   float* dconic, float* dopacity, float* dvalue, void* ws,
+                                   hipStream_t st);
+
+// ---------------------------------------------------------------- poisson
+struct MgPlan {
+    int levels = 0;       // grids including the finest
+    int lc = 0;           // first grid handled inside one workgroup
+    int n[kMaxLevels];    // interior rows per level
+    int m[kMaxLevels];    // interior columns per level
+    int pitch[kMaxLevels];
+    size_t lds_bytes = 0; // dynamic LDS of the in-workgroup V-cycle
+    int pre = 2, post = 2, max_cycles = 20, coarse_sweeps = 0;
+    float omega = 1.0f;   // SOR factor on the coarsest grid
+    double tol = 1e-6;
+};
+gdgs_status mg_plan(int W, int H, const gdgs_mg_params* mg, MgPlan* plan);
+size_t poisson_ws_bytes(const MgPlan& plan, int W, int H);
+// grad != nullptr: divergence of grad; else rho is the right-hand side.
+gdgs_status launch_poisson(const float* grad, const float* rho, const float* boundary, int W,
+                           int H, const MgPlan& plan, float* u, gdgs_stats* stats, void* ws,
+                           hipStream_t st);
+gdgs_status launch_div_adjoint(const float* lam, int W, int H, float* dgrad, hipStream_t st);
+
+// Fill a u32 array with a value (graph-capture friendly, no memset nodes).
+gdgs_status launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st);
+
+}  // namespace gdgs

@@ -1,0 +1,728 @@
+// Poisson reconstruction of the image from the composited gradients (GDGS
+// Sec. 2.1, Eq. 13-16, and Sec. 2.2 "Poisson Equation", Eq. 21; the paper names
+// multigrid as a linear-complexity solver).  Discretisation: backward-
+// difference divergence of forward-difference gradients, 5-point Laplacian with
+// unit spacing, unknowns on the interior pixels, Dirichlet values on the ring.
+//
+// Multigrid: vertex-centred grids, coarse point I <-> fine point 2I, n_c =
+// floor(n/2) interior points per axis (for even n the coarse boundary sits one
+// fine cell beyond the fine one).  V(pre, post) cycles: red-black Gauss-Seidel
+// (pre: red then black, post: black then red), full-weighting restriction of
+// the residual (coarse right-hand side = 4 x full weighting, the unit-spacing
+// scaling of a grid twice as coarse), bilinear prolongation, SOR on the
+// coarsest grid.
+//
+// Kernels:
+//  * fine grids: one 64x32 tile per workgroup, loaded once with a halo of
+//    2*sweeps+2 into LDS; all sweeps run in LDS (temporal blocking: the valid
+//    region shrinks by one cell per half-sweep), so a pre-smoothing pass reads
+//    u and f once and writes u and the coarse right-hand side once; the
+//    post-smoothing pass adds the prolongated correction, smooths and on the
+//    finest grid also produces the residual norms for the stopping test;
+//  * the coarse grids that fit in LDS together are run as a whole V-cycle by
+//    a single workgroup per channel (no launches per coarse level);
+//  * a finalize kernel evaluates eta = ||r||_inf / (8 ||w||_inf + ||b||_inf)
+//    per channel and raises a device flag; every later kernel of a finished
+//    channel returns immediately, so no host synchronisation is needed.
+#include "internal.hpp"
+
+namespace gdgs {
+namespace {
+
+constexpr int kTX = 64;
+constexpr int kTY = 32;
+constexpr int kDivTX = 64;
+constexpr int kDivTY = 4;
+constexpr int kLdsThreads = 1024;
+
+struct LevelDev {
+    float* u;        // [3][n+2][pitch]
+    const float* f;  // right-hand side, same layout
+    float* fw;       // writable alias of f (coarse levels)
+    int n, m, pitch;
+    long long cs;    // channel stride (floats)
+};
+
+struct LdsPlan {
+    int lc, L;
+    int n[kMaxLevels], m[kMaxLevels];
+    int off[kMaxLevels];   // float offset of u_l in LDS; f_l follows u_l
+    int pre, post, csweeps;
+    float omega;
+    LevelDev top;          // global arrays of level lc
+};
+
+__device__ __forceinline__ double wave_max_d(double x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x = fmax(x, __shfl_xor(x, d, 64));
+    return x;
+}
+__device__ __forceinline__ double wave_sum_d(double x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+    return x;
+}
+
+// Block-wide (max, max, sum) of three doubles; result valid in thread 0.
+__device__ void block_reduce3(double& a, double& b, double& s, double* sh /*[3*nwaves]*/) {
+    const int lane = __lane_id(), w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    a = wave_max_d(a);
+    b = wave_max_d(b);
+    s = wave_sum_d(s);
+    if (lane == 0) {
+        sh[3 * w] = a;
+        sh[3 * w + 1] = b;
+        sh[3 * w + 2] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < nw; ++i) {
+            a = fmax(a, sh[3 * i]);
+            b = fmax(b, sh[3 * i + 1]);
+            s += sh[3 * i + 2];
+        }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------- setup
+// rho (from the gradients or given), the level-0 right-hand side f0, the
+// initial u0 (ring = boundary, interior 0), and per-block max|b|, sum b^2
+// with b = -rho + ring neighbours.
+__global__ __launch_bounds__(kDivTX* kDivTY) void k_div_init(
+    const float* __restrict__ grad, const float* __restrict__ rho_in,
+    const float* __restrict__ boundary, int H, int W, float* __restrict__ f0,
+    float* __restrict__ u0, double* __restrict__ bpart) {
+    __shared__ double sh[3 * 4];
+    const int c = blockIdx.z;
+    const int j = blockIdx.x * kDivTX + (threadIdx.x % kDivTX);
+    const int i = blockIdx.y * kDivTY + (threadIdx.x / kDivTX);
+    const size_t HW = (size_t)H * W;
+    double bmax = 0.0, bdum = 0.0, bss = 0.0;
+    if (i < H && j < W) {
+        const size_t o = (size_t)c * HW + (size_t)i * W + j;
+        const bool ring = (i == 0) || (i == H - 1) || (j == 0) || (j == W - 1);
+        if (ring) {
+            u0[o] = boundary ? boundary[o] : 0.f;
+            if (f0) f0[o] = 0.f;
+        } else {
+            float rho;
+            if (grad) {
+                const float* gx = grad + (size_t)(2 * c) * HW;
+                const float* gy = grad + (size_t)(2 * c + 1) * HW;
+                const size_t p = (size_t)i * W + j;
+                rho = (gx[p] - gx[p - 1]) + (gy[p] - gy[p - W]);
+            } else {
+                rho = rho_in[o];
+            }
+            if (f0) f0[o] = rho;
+            u0[o] = 0.f;
+            double b = -(double)rho;
+            if (boundary) {
+                const float* g = boundary + (size_t)c * HW;
+                if (i == 1) b += g[(size_t)j];
+                if (i == H - 2) b += g[(size_t)(H - 1) * W + j];
+                if (j == 1) b += g[(size_t)i * W];
+                if (j == W - 2) b += g[(size_t)i * W + W - 1];
+            }
+            bmax = fabs(b);
+            bss = b * b;
+        }
+    }
+    block_reduce3(bmax, bdum, bss, sh);
+    if (threadIdx.x == 0) {
+        const int nblk = gridDim.x * gridDim.y;
+        const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+        bpart[((size_t)c * nblk + blk) * 2] = bmax;
+        bpart[((size_t)c * nblk + blk) * 2 + 1] = bss;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_setup_finalize(const double* __restrict__ bpart, int nblk,
+                                                        double* __restrict__ bnorm,
+                                                        int* __restrict__ done,
+                                                        gdgs_stats* __restrict__ stats) {
+    __shared__ double sh[3 * 4];
+    for (int c = 0; c < 3; ++c) {
+        double mx = 0.0, dum = 0.0, ss = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+            mx = fmax(mx, bpart[((size_t)c * nblk + b) * 2]);
+            ss += bpart[((size_t)c * nblk + b) * 2 + 1];
+        }
+        block_reduce3(mx, dum, ss, sh);
+        if (threadIdx.x == 0) {
+            bnorm[2 * c] = mx;
+            bnorm[2 * c + 1] = sqrt(ss);
+            const int d = (mx == 0.0);
+            done[c] = d;
+            stats->cycles[c] = 0;
+            stats->eta[c] = d ? 0.0 : 1.0;
+            stats->rel_res[c] = d ? 0.0 : 1.0;
+            stats->b_norm[c] = sqrt(ss);
+        }
+    }
+    if (threadIdx.x == 0) stats->converged = done[0] && done[1] && done[2];
+}
+
+// ---------------------------------------------------------------- smoothing
+// Red-black Gauss-Seidel half-sweeps on an LDS region RX x RY whose cell (0,0)
+// is grid point (gi0, gj0); only interior grid points (1..n, 1..m) change.
+template <int RX, int RY>
+__device__ __forceinline__ void smooth_region(float* __restrict__ su, const float* __restrict__ sf,
+                                              int gi0, int gj0, int n, int m, int color0,
+                                              int sweeps) {
+    constexpr int HX = (RX - 1) / 2;
+    for (int s = 0; s < sweeps; ++s) {
+        for (int h = 0; h < 2; ++h) {
+            const int color = color0 ^ h;
+            for (int idx = threadIdx.x; idx < (RY - 2) * HX; idx += blockDim.x) {
+                const int r = 1 + idx / HX;
+                const int k = idx - (r - 1) * HX;
+                const int gi = gi0 + r;
+                const int q = 1 + 2 * k + ((color + gi + gj0 + 1) & 1);
+                const int gj = gj0 + q;
+                if (q <= RX - 2 && gi >= 1 && gi <= n && gj >= 1 && gj <= m) {
+                    const int o = r * RX + q;
+                    su[o] = 0.25f * (su[o - RX] + su[o + RX] + su[o - 1] + su[o + 1] - sf[o]);
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <int RX, int RY>
+__device__ __forceinline__ void load_region(float* su, float* sf, const LevelDev& L, int c, int gi0,
+                                            int gj0, bool zero_guess) {
+    const int N = L.n + 2, M = L.m + 2;
+    const float* u = L.u + (size_t)c * L.cs;
+    const float* f = L.f + (size_t)c * L.cs;
+    for (int idx = threadIdx.x; idx < RY * RX; idx += blockDim.x) {
+        const int r = idx / RX, q = idx - r * RX;
+        const int gi = gi0 + r, gj = gj0 + q;
+        const bool in = (unsigned)gi < (unsigned)N && (unsigned)gj < (unsigned)M;
+        const size_t o = (size_t)gi * L.pitch + gj;
+        su[idx] = (in && !zero_guess) ? u[o] : 0.f;
+        sf[idx] = in ? f[o] : 0.f;
+    }
+}
+
+// Pre-smoothing + residual + restriction to the next grid.
+template <int NU>
+__global__ __launch_bounds__(256) void k_mg_pre(LevelDev L, LevelDev C, int zero_guess,
+                                                const int* __restrict__ done) {
+    constexpr int HALO = 2 * NU + 2;
+    constexpr int RX = kTX + 2 * HALO, RY = kTY + 2 * HALO;
+    __shared__ float su[RY * RX];
+    __shared__ float sf[RY * RX];
+    const int c = blockIdx.z;
+    if (done[c]) return;
+    const int gi0 = blockIdx.y * kTY - HALO, gj0 = blockIdx.x * kTX - HALO;
+    load_region<RX, RY>(su, sf, L, c, gi0, gj0, zero_guess != 0);
+    __syncthreads();
+    smooth_region<RX, RY>(su, sf, gi0, gj0, L.n, L.m, 0, NU);
+    const int N = L.n + 2, M = L.m + 2;
+    float* u = L.u + (size_t)c * L.cs;
+    for (int idx = threadIdx.x; idx < kTY * kTX; idx += blockDim.x) {
+        const int r = HALO + idx / kTX, q = HALO + idx % kTX;
+        const int gi = gi0 + r, gj = gj0 + q;
+        if (gi < N && gj < M) u[(size_t)gi * L.pitch + gj] = su[r * RX + q];
+    }
+    // residual on rows/cols [HALO-1, HALO+T-1], zero off the interior
+    constexpr int ZR = kTY + 1, ZC = kTX + 1;
+    for (int idx = threadIdx.x; idx < ZR * ZC; idx += blockDim.x) {
+        const int r = HALO - 1 + idx / ZC, q = HALO - 1 + idx % ZC;
+        const int gi = gi0 + r, gj = gj0 + q;
+        const int o = r * RX + q;
+        float rv = 0.f;
+        if (gi >= 1 && gi <= L.n && gj >= 1 && gj <= L.m)
+            rv = sf[o] - (su[o - RX] + su[o + RX] + su[o - 1] + su[o + 1] - 4.f * su[o]);
+        sf[o] = rv;
+    }
+    __syncthreads();
+    const int I0 = blockIdx.y * (kTY / 2), J0 = blockIdx.x * (kTX / 2);
+    float* fc = C.fw + (size_t)c * C.cs;
+    for (int idx = threadIdx.x; idx < (kTY / 2) * (kTX / 2); idx += blockDim.x) {
+        const int I = I0 + idx / (kTX / 2), J = J0 + idx % (kTX / 2);
+        if (I >= 1 && I <= C.n && J >= 1 && J <= C.m) {
+            const int o = (2 * I - gi0) * RX + (2 * J - gj0);
+            const float v = 4.f * sf[o] + 2.f * (sf[o - 1] + sf[o + 1] + sf[o - RX] + sf[o + RX]) +
+                            (sf[o - RX - 1] + sf[o - RX + 1] + sf[o + RX - 1] + sf[o + RX + 1]);
+            fc[(size_t)I * C.pitch + J] = 0.25f * v;
+        }
+    }
+}
+
+// Prolongation + correction + post-smoothing (+ residual norms on the finest grid).
+template <int NU, bool NORM>
+__global__ __launch_bounds__(256) void k_mg_post(LevelDev L, LevelDev C,
+                                                 const int* __restrict__ done,
+                                                 double* __restrict__ part) {
+    constexpr int HALO = 2 * NU + 2;
+    constexpr int RX = kTX + 2 * HALO, RY = kTY + 2 * HALO;
+    __shared__ float su[RY * RX];
+    __shared__ float sf[RY * RX];
+    __shared__ double sh[3 * 4];
+    const int c = blockIdx.z;
+    if (done[c]) return;
+    const int gi0 = blockIdx.y * kTY - HALO, gj0 = blockIdx.x * kTX - HALO;
+    load_region<RX, RY>(su, sf, L, c, gi0, gj0, false);
+    __syncthreads();
+    const float* e = C.u + (size_t)c * C.cs;
+    for (int idx = threadIdx.x; idx < RY * RX; idx += blockDim.x) {
+        const int r = idx / RX, q = idx - r * RX;
+        const int gi = gi0 + r, gj = gj0 + q;
+        if (gi >= 1 && gi <= L.n && gj >= 1 && gj <= L.m) {
+            const int oi = gi & 1, oj = gj & 1;
+            const float* p = e + (size_t)(gi >> 1) * C.pitch + (gj >> 1);
+            float v = p[0];
+            if (oi) v += p[C.pitch];
+            if (oj) v += p[1];
+            if (oi & oj) v += p[C.pitch + 1];
+            su[idx] += (oi ? 0.5f : 1.f) * (oj ? 0.5f : 1.f) * v;
+        }
+    }
+    __syncthreads();
+    smooth_region<RX, RY>(su, sf, gi0, gj0, L.n, L.m, 1, NU);
+    float* u = L.u + (size_t)c * L.cs;
+    double rmax = 0.0, umax = 0.0, rss = 0.0;
+    for (int idx = threadIdx.x; idx < kTY * kTX; idx += blockDim.x) {
+        const int r = HALO + idx / kTX, q = HALO + idx % kTX;
+        const int gi = gi0 + r, gj = gj0 + q;
+        if (gi >= 1 && gi <= L.n && gj >= 1 && gj <= L.m) {
+            const int o = r * RX + q;
+            const float uv = su[o];
+            u[(size_t)gi * L.pitch + gj] = uv;
+            if (NORM) {
+                const double rv = (double)sf[o] - ((double)su[o - RX] + (double)su[o + RX] +
+                                                   (double)su[o - 1] + (double)su[o + 1] -
+                                                   4.0 * (double)uv);
+                rmax = fmax(rmax, fabs(rv));
+                umax = fmax(umax, fabs((double)uv));
+                rss += rv * rv;
+            }
+        }
+    }
+    if (NORM) {
+        block_reduce3(rmax, umax, rss, sh);
+        if (threadIdx.x == 0) {
+            const int nblk = gridDim.x * gridDim.y;
+            const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+            double* p = part + ((size_t)c * nblk + blk) * 3;
+            p[0] = rmax;
+            p[1] = umax;
+            p[2] = rss;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- coarse V-cycle in LDS
+__device__ __forceinline__ void lds_gs(float* U, const float* F, int n, int m, int color0,
+                                       int sweeps, float omega) {
+    const int M = m + 2;
+    const int hx = (m + 1) / 2 + 1;
+    for (int s = 0; s < sweeps; ++s) {
+        for (int h = 0; h < 2; ++h) {
+            const int color = color0 ^ h;
+            for (int idx = threadIdx.x; idx < n * hx; idx += blockDim.x) {
+                const int i = 1 + idx / hx;
+                const int k = idx - (i - 1) * hx;
+                const int j = 1 + 2 * k + ((color + i + 1) & 1);
+                if (j <= m) {
+                    const int o = i * M + j;
+                    const float gs = 0.25f * (U[o - M] + U[o + M] + U[o - 1] + U[o + 1] - F[o]);
+                    U[o] = omega == 1.f ? gs : U[o] + omega * (gs - U[o]);
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__device__ __forceinline__ float lds_res(const float* U, const float* F, int n, int m, int i,
+                                         int j) {
+    if (i < 1 || i > n || j < 1 || j > m) return 0.f;
+    const int M = m + 2, o = i * M + j;
+    return F[o] - (U[o - M] + U[o + M] + U[o - 1] + U[o + 1] - 4.f * U[o]);
+}
+
+__global__ __launch_bounds__(kLdsThreads) void k_mg_lds(LdsPlan P, const int* __restrict__ done,
+                                                        double* __restrict__ part) {
+    extern __shared__ float lds[];
+    __shared__ double sh[3 * (kLdsThreads / 64)];
+    const int c = blockIdx.x;
+    if (done[c]) return;
+    const int lc = P.lc, L = P.L;
+    // load the top level
+    {
+        const int n = P.n[lc], m = P.m[lc], M = m + 2;
+        float* U = lds + P.off[lc];
+        float* F = U + (n + 2) * M;
+        const float* gu = P.top.u + (size_t)c * P.top.cs;
+        const float* gf = P.top.f + (size_t)c * P.top.cs;
+        for (int idx = threadIdx.x; idx < (n + 2) * M; idx += blockDim.x) {
+            const int i = idx / M, j = idx - i * M;
+            const size_t o = (size_t)i * P.top.pitch + j;
+            U[idx] = (lc == 0) ? gu[o] : 0.f;
+            F[idx] = (i >= 1 && i <= n && j >= 1 && j <= m) ? gf[o] : 0.f;
+        }
+        __syncthreads();
+    }
+    for (int l = lc; l < L - 1; ++l) {
+        const int n = P.n[l], m = P.m[l], M = m + 2;
+        float* U = lds + P.off[l];
+        float* F = U + (n + 2) * M;
+        lds_gs(U, F, n, m, 0, P.pre, 1.f);
+        const int nc = P.n[l + 1], mc = P.m[l + 1], Mc = mc + 2;
+        float* Uc = lds + P.off[l + 1];
+        float* Fc = Uc + (nc + 2) * Mc;
+        for (int idx = threadIdx.x; idx < (nc + 2) * Mc; idx += blockDim.x) {
+            const int I = idx / Mc, J = idx - I * Mc;
+            Uc[idx] = 0.f;
+            float v = 0.f;
+            if (I >= 1 && I <= nc && J >= 1 && J <= mc) {
+                const int i = 2 * I, j = 2 * J;
+                v = 4.f * lds_res(U, F, n, m, i, j) +
+                    2.f * (lds_res(U, F, n, m, i - 1, j) + lds_res(U, F, n, m, i + 1, j) +
+                           lds_res(U, F, n, m, i, j - 1) + lds_res(U, F, n, m, i, j + 1)) +
+                    (lds_res(U, F, n, m, i - 1, j - 1) + lds_res(U, F, n, m, i - 1, j + 1) +
+                     lds_res(U, F, n, m, i + 1, j - 1) + lds_res(U, F, n, m, i + 1, j + 1));
+                v *= 0.25f;
+            }
+            Fc[idx] = v;
+        }
+        __syncthreads();
+    }
+    {
+        const int n = P.n[L - 1], m = P.m[L - 1];
+        float* U = lds + P.off[L - 1];
+        float* F = U + (n + 2) * (m + 2);
+        lds_gs(U, F, n, m, 0, P.csweeps, P.omega);
+    }
+    for (int l = L - 2; l >= lc; --l) {
+        const int n = P.n[l], m = P.m[l], M = m + 2;
+        float* U = lds + P.off[l];
+        float* F = U + (n + 2) * M;
+        const int Mc = P.m[l + 1] + 2;
+        const float* Uc = lds + P.off[l + 1];
+        for (int idx = threadIdx.x; idx < (n + 2) * M; idx += blockDim.x) {
+            const int i = idx / M, j = idx - i * M;
+            if (i >= 1 && i <= n && j >= 1 && j <= m) {
+                const int oi = i & 1, oj = j & 1;
+                const float* p = Uc + (i >> 1) * Mc + (j >> 1);
+                float v = p[0];
+                if (oi) v += p[Mc];
+                if (oj) v += p[1];
+                if (oi & oj) v += p[Mc + 1];
+                U[idx] += (oi ? 0.5f : 1.f) * (oj ? 0.5f : 1.f) * v;
+            }
+        }
+        __syncthreads();
+        lds_gs(U, F, n, m, 1, P.post, 1.f);
+    }
+    // write back the top level (its ring too: zero for coarse grids, the
+    // unchanged Dirichlet data for the finest)
+    {
+        const int n = P.n[lc], m = P.m[lc], M = m + 2;
+        const float* U = lds + P.off[lc];
+        const float* F = U + (n + 2) * M;
+        float* gu = P.top.u + (size_t)c * P.top.cs;
+        double rmax = 0.0, umax = 0.0, rss = 0.0;
+        for (int idx = threadIdx.x; idx < (n + 2) * M; idx += blockDim.x) {
+            const int i = idx / M, j = idx - i * M;
+            gu[(size_t)i * P.top.pitch + j] = U[idx];
+            if (lc == 0 && i >= 1 && i <= n && j >= 1 && j <= m) {
+                const double rv = (double)F[idx] - ((double)U[idx - M] + (double)U[idx + M] +
+                                                    (double)U[idx - 1] + (double)U[idx + 1] -
+                                                    4.0 * (double)U[idx]);
+                rmax = fmax(rmax, fabs(rv));
+                umax = fmax(umax, fabs((double)U[idx]));
+                rss += rv * rv;
+            }
+        }
+        if (lc == 0) {
+            block_reduce3(rmax, umax, rss, sh);
+            if (threadIdx.x == 0) {
+                part[(size_t)c * 3] = rmax;
+                part[(size_t)c * 3 + 1] = umax;
+                part[(size_t)c * 3 + 2] = rss;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cycle_finalize(const double* __restrict__ part, int nblk,
+                                                        const double* __restrict__ bnorm,
+                                                        int* __restrict__ done,
+                                                        gdgs_stats* __restrict__ stats, int cycle,
+                                                        double tol) {
+    __shared__ double sh[3 * 4];
+    for (int c = 0; c < 3; ++c) {
+        if (done[c]) continue;  // uniform: finished before this cycle
+        double rmax = 0.0, umax = 0.0, rss = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+            const double* p = part + ((size_t)c * nblk + b) * 3;
+            rmax = fmax(rmax, p[0]);
+            umax = fmax(umax, p[1]);
+            rss += p[2];
+        }
+        block_reduce3(rmax, umax, rss, sh);
+        if (threadIdx.x == 0) {
+            const double eta = rmax / (8.0 * umax + bnorm[2 * c]);
+            const double b2 = bnorm[2 * c + 1];
+            stats->eta[c] = eta;
+            stats->rel_res[c] = b2 > 0.0 ? sqrt(rss) / b2 : 0.0;
+            stats->cycles[c] = cycle + 1;
+            if (eta <= tol) done[c] = 1;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) stats->converged = done[0] && done[1] && done[2];
+}
+
+// ---------------------------------------------------------------- divergence adjoint
+__global__ void k_div_adjoint(const float* __restrict__ lam, int H, int W,
+                              float* __restrict__ dgrad) {
+    const int j = blockIdx.x * kDivTX + (threadIdx.x % kDivTX);
+    const int i = blockIdx.y * kDivTY + (threadIdx.x / kDivTX);
+    const int c = blockIdx.z;
+    if (i >= H || j >= W) return;
+    const size_t HW = (size_t)H * W;
+    const float* L = lam + (size_t)c * HW;
+    auto li = [&](int a, int b) -> float {
+        return (a >= 1 && a <= H - 2 && b >= 1 && b <= W - 2) ? L[(size_t)a * W + b] : 0.f;
+    };
+    const float l0 = li(i, j);
+    dgrad[(size_t)(2 * c) * HW + (size_t)i * W + j] = l0 - li(i, j + 1);
+    dgrad[(size_t)(2 * c + 1) * HW + (size_t)i * W + j] = l0 - li(i + 1, j);
+}
+
+int lds_budget() {
+    static int cached = -1;
+    if (cached < 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+                hipSuccess || v <= 0)
+            v = 64 * 1024;
+        (void)hipGetLastError();
+        v -= 2048;  // static LDS of the kernel
+        cached = v < kLdsBudget ? v : kLdsBudget;
+    }
+    return cached;
+}
+
+template <int NU>
+gdgs_status launch_pre(const LevelDev& L, const LevelDev& C, bool zero, const int* done,
+                       hipStream_t st) {
+    dim3 grid((L.m + 2 + kTX - 1) / kTX, (L.n + 2 + kTY - 1) / kTY, 3);
+    hipLaunchKernelGGL(k_mg_pre<NU>, grid, dim3(256), 0, st, L, C, zero ? 1 : 0, done);
+    return GDGS_OK;
+}
+
+template <int NU>
+gdgs_status launch_post(const LevelDev& L, const LevelDev& C, bool norm, const int* done,
+                        double* part, hipStream_t st) {
+    dim3 grid((L.m + 2 + kTX - 1) / kTX, (L.n + 2 + kTY - 1) / kTY, 3);
+    if (norm)
+        hipLaunchKernelGGL((k_mg_post<NU, true>), grid, dim3(256), 0, st, L, C, done, part);
+    else
+        hipLaunchKernelGGL((k_mg_post<NU, false>), grid, dim3(256), 0, st, L, C, done, part);
+    return GDGS_OK;
+}
+
+int pitch_of(int cols) { return (cols + 31) / 32 * 32; }
+
+}  // namespace
+
+gdgs_status mg_plan(int W, int H, const gdgs_mg_params* mg, MgPlan* plan) {
+    MgPlan p;
+    gdgs_mg_params d{0, 2, 2, 20, 0, 0, 1e-6};
+    const gdgs_mg_params& q = mg ? *mg : d;
+    if (q.levels < 0 || q.levels > kMaxLevels || q.pre_sweeps < 1 || q.pre_sweeps > 2 ||
+        q.post_sweeps < 1 || q.post_sweeps > 2 || q.max_cycles < 1 || q.max_cycles > 64 ||
+        q.coarse_sweeps < 0 || q.coarse_sweeps > 4096 || !(q.tol >= 0.0)) {
+        set_error("invalid multigrid parameters (levels %d, sweeps %d/%d, cycles %d, tol %g)",
+                  q.levels, q.pre_sweeps, q.post_sweeps, q.max_cycles, q.tol);
+        return GDGS_ERR_INVALID_ARGUMENT;
+    }
+    p.pre = q.pre_sweeps;
+    p.post = q.post_sweeps;
+    p.max_cycles = q.max_cycles;
+    p.tol = q.tol;
+    p.n[0] = H - 2;
+    p.m[0] = W - 2;
+    p.pitch[0] = W;
+    int L = 1;
+    const int want = q.levels == 0 ? kMaxLevels : q.levels;
+    while (L < want && p.n[L - 1] / 2 >= 1 && p.m[L - 1] / 2 >= 1) {
+        p.n[L] = p.n[L - 1] / 2;
+        p.m[L] = p.m[L - 1] / 2;
+        p.pitch[L] = pitch_of(p.m[L] + 2);
+        ++L;
+    }
+    p.levels = L;
+    // coarse grids that fit in one workgroup's LDS
+    const size_t budget = (size_t)lds_budget();
+    size_t bytes = 0;
+    int lc = L;
+    while (lc > 0) {
+        const size_t b = 2 * sizeof(float) * (size_t)(p.n[lc - 1] + 2) * (p.m[lc - 1] + 2);
+        if (bytes + b > budget) break;
+        bytes += b;
+        --lc;
+    }
+    if (lc == L) {
+        set_error("coarsest grid %dx%d does not fit in LDS; use more multigrid levels",
+                  p.n[L - 1], p.m[L - 1]);
+        return GDGS_ERR_UNSUPPORTED;
+    }
+    p.lc = lc;
+    p.lds_bytes = bytes;
+    const int nc = p.n[L - 1], mcc = p.m[L - 1];
+    const double rj = 0.5 * (cos(M_PI / (nc + 1)) + cos(M_PI / (mcc + 1)));
+    p.omega = (float)(2.0 / (1.0 + sqrt(1.0 - rj * rj)));
+    if (q.coarse_sweeps > 0) {
+        p.coarse_sweeps = q.coarse_sweeps;
+    } else {
+        // enough SOR sweeps for a 1e-6 error reduction, (omega - 1)^k <= 1e-6
+        const double rho = p.omega - 1.0;
+        int k = rho > 0.0 ? (int)ceil(log(1e-6) / log(rho)) : 4;
+        if (k < 4) k = 4;
+        if (k > 4096) k = 4096;
+        p.coarse_sweeps = k;
+    }
+    *plan = p;
+    return GDGS_OK;
+}
+
+namespace {
+struct PoissonWs {
+    float* f0;
+    float* u[kMaxLevels];
+    float* f[kMaxLevels];
+    double* part;
+    double* bpart;
+    double* bnorm;
+    int* done;
+    gdgs_stats* stats;
+};
+
+int norm_blocks(const MgPlan& p) {
+    if (p.lc == 0) return 1;
+    return ((p.m[0] + 2 + kTX - 1) / kTX) * ((p.n[0] + 2 + kTY - 1) / kTY);
+}
+
+int div_blocks(int W, int H) { return ((W + kDivTX - 1) / kDivTX) * ((H + kDivTY - 1) / kDivTY); }
+
+size_t poisson_layout(const MgPlan& p, int W, int H, void* ws, PoissonWs* out) {
+    Carver c(ws);
+    PoissonWs w{};
+    w.f0 = c.take<float>((size_t)3 * H * W);
+    for (int l = 1; l < p.levels; ++l) {
+        const size_t cells = (size_t)(p.n[l] + 2) * p.pitch[l];
+        w.u[l] = c.take<float>(3 * cells);
+        w.f[l] = c.take<float>(3 * cells);
+    }
+    w.part = c.take<double>((size_t)3 * 3 * norm_blocks(p));
+    w.bpart = c.take<double>((size_t)3 * 2 * div_blocks(W, H));
+    w.bnorm = c.take<double>(6);
+    w.done = c.take<int>(4);
+    w.stats = c.take<gdgs_stats>(1);
+    if (out) *out = w;
+    return c.off + 256;
+}
+}  // namespace
+
+size_t poisson_ws_bytes(const MgPlan& plan, int W, int H) {
+    return poisson_layout(plan, W, H, nullptr, nullptr);
+}
+
+gdgs_status launch_poisson(const float* grad, const float* rho, const float* boundary, int W,
+                           int H, const MgPlan& p, float* u, gdgs_stats* stats, void* ws,
+                           hipStream_t st) {
+    PoissonWs w;
+    poisson_layout(p, W, H, ws, &w);
+    gdgs_stats* sd = stats ? stats : w.stats;
+    const long long cs0 = (long long)H * W;
+    LevelDev lev[kMaxLevels];
+    lev[0].u = u;
+    lev[0].f = grad ? w.f0 : rho;
+    lev[0].fw = nullptr;
+    lev[0].n = p.n[0];
+    lev[0].m = p.m[0];
+    lev[0].pitch = W;
+    lev[0].cs = cs0;
+    for (int l = 1; l < p.levels; ++l) {
+        lev[l].u = w.u[l];
+        lev[l].f = w.f[l];
+        lev[l].fw = w.f[l];
+        lev[l].n = p.n[l];
+        lev[l].m = p.m[l];
+        lev[l].pitch = p.pitch[l];
+        lev[l].cs = (long long)(p.n[l] + 2) * p.pitch[l];
+    }
+    const int nblk_div = div_blocks(W, H);
+    hipLaunchKernelGGL(k_div_init,
+                       dim3((W + kDivTX - 1) / kDivTX, (H + kDivTY - 1) / kDivTY, 3),
+                       dim3(kDivTX * kDivTY), 0, st, grad, grad ? nullptr : rho, boundary, H, W,
+                       grad ? w.f0 : nullptr, u, w.bpart);
+    hipLaunchKernelGGL(k_setup_finalize, dim3(1), dim3(256), 0, st, w.bpart, nblk_div, w.bnorm,
+                       w.done, sd);
+    GDGS_LAUNCH_CHECK();
+
+    LdsPlan lp;
+    lp.lc = p.lc;
+    lp.L = p.levels;
+    int off = 0;
+    for (int l = 0; l < p.levels; ++l) {
+        lp.n[l] = p.n[l];
+        lp.m[l] = p.m[l];
+        lp.off[l] = 0;
+        if (l >= p.lc) {
+            lp.off[l] = off;
+            off += 2 * (p.n[l] + 2) * (p.m[l] + 2);
+        }
+    }
+    lp.pre = p.pre;
+    lp.post = p.post;
+    lp.csweeps = p.coarse_sweeps;
+    lp.omega = p.omega;
+    lp.top = lev[p.lc];
+    if (p.lds_bytes > 64 * 1024) {
+        GDGS_HIP_TRY(hipFuncSetAttribute((const void*)k_mg_lds,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)p.lds_bytes));
+    }
+    const int nblk = norm_blocks(p);
+    for (int cyc = 0; cyc < p.max_cycles; ++cyc) {
+        for (int l = 0; l < p.lc; ++l) {
+            if (p.pre == 1)
+                launch_pre<1>(lev[l], lev[l + 1], l > 0, w.done, st);
+            else
+                launch_pre<2>(lev[l], lev[l + 1], l > 0, w.done, st);
+        }
+        hipLaunchKernelGGL(k_mg_lds, dim3(3), dim3(kLdsThreads), p.lds_bytes, st, lp, w.done,
+                           w.part);
+        for (int l = p.lc - 1; l >= 0; --l) {
+            if (p.post == 1)
+                launch_post<1>(lev[l], lev[l + 1], l == 0, w.done, w.part, st);
+            else
+                launch_post<2>(lev[l], lev[l + 1], l == 0, w.done, w.part, st);
+        }
+        hipLaunchKernelGGL(k_cycle_finalize, dim3(1), dim3(256), 0, st, w.part, nblk, w.bnorm,
+                           w.done, sd, cyc, p.tol);
+        GDGS_LAUNCH_CHECK();
+    }
+    return GDGS_OK;
+}
+
+gdgs_status launch_div_adjoint(const float* lam, int W, int H, float* dgrad, hipStream_t st) {
+    hipLaunchKernelGGL(k_div_adjoint,
+                       dim3((W + kDivTX - 1) / kDivTX, (H + kDivTY - 1) / kDivTY, 3),
+                       dim3(kDivTX * kDivTY), 0, st, lam, H, W, dgrad);
+    GDGS_LAUNCH_CHECK();
+    return GDGS_OK;
+}
+
+}  // namespace gdgs

@@ -1,0 +1,339 @@
+// Front-to-back compositing of the projected gradient field (GDGS Sec. 1.2,
+// Eq. 11, applied to the projected field in Sec. 2.2 "Projection", Eq. 20) and
+// its reverse-mode derivative.
+//
+// Forward: one workgroup per 16x16 screen tile, one thread per pixel.  The
+// tile's pairs (already in front-to-back order) are consumed in batches of
+// 256: every thread fetches one 64-byte splat record into LDS, then all
+// threads walk the batch reading the records as LDS broadcasts.  A pixel stops
+// accumulating once its transmittance is below 1e-7; the tile stops when all
+// its pixels have.  Splat means are stored relative to the pixel origin of
+// the splat's tile rectangle, so d = p - mu is computed from small numbers.
+//
+// Backward: same traversal; each pixel recomputes a_k and T_{k-1} exactly as
+// the forward did, so its running prefix sum of v w equals the forward's and
+// the suffix S_k = out - prefix_k needs no division by transmittance.  For
+// every (pixel, splat) the 12 partial derivatives are summed over the
+// workgroup (wave shuffles + LDS) into one record per pair; a second kernel
+// sums each splat's pair records in a fixed order (tile order of its
+// rectangle; position found by binary search in the tile's depth-ranked
+// range), so the result is deterministic.
+#include "internal.hpp"
+
+namespace gdgs {
+namespace {
+
+constexpr int kBatch = 256;
+
+__global__ void k_inv_order(const uint32_t* __restrict__ order, int64_t K,
+                            uint32_t* __restrict__ inv) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < K) {
+        const uint32_t k = order[s];
+        if (k < (uint64_t)K) inv[k] = (uint32_t)s;
+    }
+}
+
+// Record of splat k at its depth rank inv[k].
+__global__ __launch_bounds__(256) void k_gather_records(
+    const uint32_t* __restrict__ inv, gdgs_proj proj, const float* __restrict__ opacity,
+    const float* __restrict__ value, int64_t K, float4* __restrict__ rec) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    if (proj.count[k] == 0) return;
+    const uint32_t s = inv[k];
+    if (s >= (uint64_t)K) return;
+    const uint32_t r0 = proj.rect[k], r1 = proj.rect[K + k];
+    float4* r = rec + 4 * (size_t)s;
+    r[0] = make_float4(proj.mean2d[k], proj.mean2d[K + k], (float)(kTile * (int)(r0 & 0xFFFF)),
+                       (float)(kTile * (int)(r1 & 0xFFFF)));
+    r[1] = make_float4(proj.conic[k], 2.f * proj.conic[K + k], proj.conic[2 * K + k], opacity[k]);
+    r[2] = make_float4(value[k], value[K + k], value[2 * K + k], value[3 * K + k]);
+    r[3] = make_float4(value[4 * K + k], value[5 * K + k], 0.f, 0.f);
+}
+
+__global__ __launch_bounds__(256) void k_raster_fwd(const float4* __restrict__ rec,
+                                                    const uint32_t* __restrict__ rank_of_pair,
+                                                    const uint32_t* __restrict__ ranges, int T,
+                                                    int nx, int W, int H, int64_t K,
+                                                    float* __restrict__ grad) {
+    __shared__ float4 s_r0[kBatch], s_r1[kBatch], s_r2[kBatch], s_r3[kBatch];
+    const int tile = blockIdx.x;
+    const int tx = tile % nx, ty = tile / nx;
+    const int t = threadIdx.x;
+    const int px = tx * kTile + (t & 15), py = ty * kTile + (t >> 4);
+    const bool inside = px < W && py < H;
+    const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+    const uint32_t start = ranges[tile], end = ranges[T + tile];
+    float Tr = inside ? 1.f : 0.f;
+    float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f, acc4 = 0.f, acc5 = 0.f;
+    for (uint32_t b0 = start; b0 < end; b0 += kBatch) {
+        const int n = (int)min((uint32_t)kBatch, end - b0);
+        __syncthreads();
+        if (t < n) {
+            const uint32_t s = rank_of_pair[b0 + t];
+            if (s < (uint64_t)K) {
+                const float4* r = rec + 4 * (size_t)s;
+                s_r0[t] = r[0];
+                s_r1[t] = r[1];
+                s_r2[t] = r[2];
+                s_r3[t] = r[3];
+            } else {  // never produced by the binning; contributes nothing
+                s_r0[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+                s_r1[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+                s_r2[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+                s_r3[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        }
+        __syncthreads();
+        for (int j = 0; j < n; ++j) {
+            const float4 r0 = s_r0[j], r1 = s_r1[j];
+            const float dx = (fpx - r0.z) - r0.x;
+            const float dy = (fpy - r0.w) - r0.y;
+            const float E = dx * (r1.x * dx + r1.y * dy) + r1.z * dy * dy;
+            if (E <= kEcut && Tr >= kTmin) {
+                const float4 r2 = s_r2[j], r3 = s_r3[j];
+                const float al = r1.w * __expf(-E);
+                const float w = al * Tr;
+                acc0 += r2.x * w;
+                acc1 += r2.y * w;
+                acc2 += r2.z * w;
+                acc3 += r2.w * w;
+                acc4 += r3.x * w;
+                acc5 += r3.y * w;
+                Tr = Tr - al * Tr;
+            }
+        }
+        if (__syncthreads_count(Tr >= kTmin) == 0) break;
+    }
+    if (inside) {
+        const size_t HW = (size_t)H * W, p = (size_t)py * W + px;
+        grad[p] = acc0;
+        grad[HW + p] = acc1;
+        grad[2 * HW + p] = acc2;
+        grad[3 * HW + p] = acc3;
+        grad[4 * HW + p] = acc4;
+        grad[5 * HW + p] = acc5;
+    }
+}
+
+__device__ __forceinline__ float wave_sum(float x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+    return x;
+}
+
+// Partials per pair: (dmx, dmy, da, db, dc, dalpha, dv0..dv5).
+constexpr int kNP = 12;
+constexpr int kBatchB = 128;
+
+__global__ __launch_bounds__(256) void k_raster_bwd(const float4* __restrict__ rec,
+                                                    const uint32_t* __restrict__ rank_of_pair,
+                                                    const uint32_t* __restrict__ ranges, int T,
+                                                    int nx, int W, int H, int64_t K,
+                                                    const float* __restrict__ grad,
+                                                    const float* __restrict__ dgrad,
+                                                    float* __restrict__ part, int64_t cap) {
+    __shared__ float4 s_r0[kBatchB], s_r1[kBatchB], s_r2[kBatchB], s_r3[kBatchB];
+    __shared__ float s_p[4][kNP][kBatchB];
+    const int tile = blockIdx.x;
+    const int tx = tile % nx, ty = tile / nx;
+    const int t = threadIdx.x, lane = __lane_id(), wv = t >> 6;
+    const int px = tx * kTile + (t & 15), py = ty * kTile + (t >> 4);
+    const bool inside = px < W && py < H;
+    const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+    const size_t HW = (size_t)H * W, pp = (size_t)py * W + px;
+    float out[6], del[6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+        out[m] = inside ? grad[m * HW + pp] : 0.f;
+        del[m] = inside ? dgrad[m * HW + pp] : 0.f;
+    }
+    const uint32_t start = ranges[tile], end = ranges[T + tile];
+    float Tr = inside ? 1.f : 0.f;
+    float pre0 = 0.f, pre1 = 0.f, pre2 = 0.f, pre3 = 0.f, pre4 = 0.f, pre5 = 0.f;
+    for (uint32_t b0 = start; b0 < end; b0 += kBatchB) {
+        const int n = (int)min((uint32_t)kBatchB, end - b0);
+        __syncthreads();
+        if (t < n) {
+            const uint32_t s = rank_of_pair[b0 + t];
+            if (s < (uint64_t)K) {
+                const float4* r = rec + 4 * (size_t)s;
+                s_r0[t] = r[0];
+                s_r1[t] = r[1];
+                s_r2[t] = r[2];
+                s_r3[t] = r[3];
+            } else {  // never produced by the binning; contributes nothing
+                s_r0[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+                s_r1[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+                s_r2[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+                s_r3[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        }
+        __syncthreads();
+        for (int j = 0; j < n; ++j) {
+            const float4 r0 = s_r0[j], r1 = s_r1[j];
+            const float dx = (fpx - r0.z) - r0.x;
+            const float dy = (fpy - r0.w) - r0.y;
+            const float E = dx * (r1.x * dx + r1.y * dy) + r1.z * dy * dy;
+            const bool on = E <= kEcut && Tr >= kTmin;
+            float g[kNP];
+#pragma unroll
+            for (int q = 0; q < kNP; ++q) g[q] = 0.f;
+            if (on) {
+                const float4 r2 = s_r2[j], r3 = s_r3[j];
+                const float G = __expf(-E);
+                const float al = r1.w * G;
+                const float w = al * Tr;
+                const float v[6] = {r2.x, r2.y, r2.z, r2.w, r3.x, r3.y};
+                pre0 += v[0] * w;
+                pre1 += v[1] * w;
+                pre2 += v[2] * w;
+                pre3 += v[3] * w;
+                pre4 += v[4] * w;
+                pre5 += v[5] * w;
+                const float pre[6] = {pre0, pre1, pre2, pre3, pre4, pre5};
+                const float inv1m = 1.f / (1.f - al);
+                float dla = 0.f;
+#pragma unroll
+                for (int m = 0; m < 6; ++m) {
+                    dla += del[m] * (v[m] * Tr - (out[m] - pre[m]) * inv1m);
+                    g[6 + m] = del[m] * w;
+                }
+                g[5] = dla * G;
+                const float dE = -dla * r1.w * G;
+                g[0] = -dE * (2.f * r1.x * dx + r1.y * dy);
+                g[1] = -dE * (r1.y * dx + 2.f * r1.z * dy);
+                g[2] = dE * dx * dx;
+                g[3] = dE * 2.f * dx * dy;
+                g[4] = dE * dy * dy;
+                Tr = Tr - al * Tr;
+            }
+            if (__ballot(on) != 0ull) {
+#pragma unroll
+                for (int q = 0; q < kNP; ++q) g[q] = wave_sum(g[q]);
+            }
+            if (lane == 0) {
+#pragma unroll
+                for (int q = 0; q < kNP; ++q) s_p[wv][q][j] = g[q];
+            }
+        }
+        __syncthreads();
+        for (int idx = t; idx < n * kNP; idx += 256) {
+            const int j = idx / kNP, q = idx - j * kNP;
+            const float v = s_p[0][q][j] + s_p[1][q][j] + s_p[2][q][j] + s_p[3][q][j];
+            if (b0 + j < cap) part[(size_t)(b0 + j) * kNP + q] = v;
+        }
+        if (__syncthreads_count(Tr >= kTmin) == 0) {
+            // remaining pairs of this tile contribute nothing
+            for (uint32_t i = b0 + n + t; i < end; i += 256)
+                for (int q = 0; q < kNP; ++q) part[(size_t)i * kNP + q] = 0.f;
+            break;
+        }
+    }
+}
+
+// Per splat: sum its pair records over the tiles of its rectangle.
+__global__ __launch_bounds__(256) void k_seg_reduce(
+    gdgs_proj proj, const uint32_t* __restrict__ inv, const uint32_t* __restrict__ rank_of_pair,
+    const uint32_t* __restrict__ ranges, int T, int nx, int64_t K, const float* __restrict__ part,
+    float* __restrict__ dmean2d, float* __restrict__ dconic, float* __restrict__ dopacity,
+    float* __restrict__ dvalue) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    float acc[kNP];
+#pragma unroll
+    for (int q = 0; q < kNP; ++q) acc[q] = 0.f;
+    if (proj.count[k] != 0) {
+        const uint32_t s = inv[k];
+        const uint32_t r0 = proj.rect[k], r1 = proj.rect[K + k];
+        const int tx0 = r0 & 0xFFFF, tx1 = r0 >> 16, ty0 = r1 & 0xFFFF, ty1 = r1 >> 16;
+        for (int ty = ty0; ty < ty1; ++ty) {
+            for (int tx = tx0; tx < tx1; ++tx) {
+                const int tl = ty * nx + tx;
+                uint32_t lo = ranges[tl], hi = ranges[T + tl];
+                while (lo < hi) {
+                    const uint32_t mid = lo + ((hi - lo) >> 1);
+                    if (rank_of_pair[mid] < s)
+                        lo = mid + 1;
+                    else
+                        hi = mid;
+                }
+                if (lo < ranges[T + tl] && rank_of_pair[lo] == s) {
+                    const float* p = part + (size_t)lo * kNP;
+#pragma unroll
+                    for (int q = 0; q < kNP; ++q) acc[q] += p[q];
+                }
+            }
+        }
+    }
+    dmean2d[k] = acc[0];
+    dmean2d[K + k] = acc[1];
+    dconic[k] = acc[2];
+    dconic[K + k] = acc[3];
+    dconic[2 * K + k] = acc[4];
+    dopacity[k] = acc[5];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) dvalue[m * K + k] = acc[6 + m];
+}
+
+}  // namespace
+
+size_t raster_ws_bytes(int64_t K) {
+    Carver c(nullptr);
+    c.take<uint32_t>(K > 0 ? K : 1);
+    c.take<float4>(4 * (size_t)(K > 0 ? K : 1));
+    return c.off + 256;
+}
+
+gdgs_status launch_raster(const gdgs_proj& proj, const float* opacity, const float* value,
+                          int64_t K, const gdgs_bins& bins, int W, int H, float* grad, void* ws,
+                          hipStream_t st) {
+    Carver c(ws);
+    uint32_t* inv = c.take<uint32_t>(K > 0 ? K : 1);
+    float4* rec = c.take<float4>(4 * (size_t)(K > 0 ? K : 1));
+    const int nx = tiles_x(W), T = nx * tiles_y(H);
+    if (K > 0) {
+        const unsigned g = (unsigned)((K + 255) / 256);
+        hipLaunchKernelGGL(k_inv_order, dim3(g), dim3(256), 0, st, bins.order, K, inv);
+        hipLaunchKernelGGL(k_gather_records, dim3(g), dim3(256), 0, st, inv, proj, opacity, value,
+                           K, rec);
+    }
+    hipLaunchKernelGGL(k_raster_fwd, dim3(T), dim3(256), 0, st, rec, bins.rank_of_pair,
+                       bins.ranges, T, nx, W, H, K, grad);
+    GDGS_LAUNCH_CHECK();
+    return GDGS_OK;
+}
+
+size_t raster_bwd_ws_bytes(int64_t K, int64_t cap) {
+    Carver c(nullptr);
+    c.take<uint32_t>(K > 0 ? K : 1);
+    c.take<float4>(4 * (size_t)(K > 0 ? K : 1));
+    c.take<float>((size_t)kNP * (cap > 0 ? cap : 1));
+    return c.off + 256;
+}
+
+gdgs_status launch_raster_backward(const gdgs_proj& proj, const float* opacity,
+                                   const float* value, int64_t K, const gdgs_bins& bins, int W,
+                                   int H, const float* grad, const float* dgrad, float* dmean2d,
+                                   float* dconic, float* dopacity, float* dvalue, void* ws,
+                                   hipStream_t st) {
+    if (K == 0) return GDGS_OK;
+    Carver c(ws);
+    uint32_t* inv = c.take<uint32_t>(K);
+    float4* rec = c.take<float4>(4 * (size_t)K);
+    float* part = c.take<float>((size_t)kNP * (bins.capacity > 0 ? bins.capacity : 1));
+    const int nx = tiles_x(W), T = nx * tiles_y(H);
+    const unsigned g = (unsigned)((K + 255) / 256);
+    hipLaunchKernelGGL(k_inv_order, dim3(g), dim3(256), 0, st, bins.order, K, inv);
+    hipLaunchKernelGGL(k_gather_records, dim3(g), dim3(256), 0, st, inv, proj, opacity, value, K,
+                       rec);
+    hipLaunchKernelGGL(k_raster_bwd, dim3(T), dim3(256), 0, st, rec, bins.rank_of_pair,
+                       bins.ranges, T, nx, W, H, K, grad, dgrad, part, bins.capacity);
+    hipLaunchKernelGGL(k_seg_reduce, dim3(g), dim3(256), 0, st, proj, inv, bins.rank_of_pair,
+                       bins.ranges, T, nx, K, part, dmean2d, dconic, dopacity, dvalue);
+    GDGS_LAUNCH_CHECK();
+    return GDGS_OK;
+}
+
+}  // namespace gdgs

@@ -1,0 +1,105 @@
+"""GPU parity of the Poisson stage (divergence + multigrid) against closed
+forms and the oracle's exact direct solvers."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2405_05446_amd as G
+import workloads as wl
+from oracle import poisson as P
+from tests.gpu_util import say, np_
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+def solve_rhs(rho, ring, mg=None):
+    H, W = rho.shape[1:]
+    r = torch.from_numpy(np.ascontiguousarray(rho, np.float32)).cuda()
+    b = None if ring is None else torch.from_numpy(np.ascontiguousarray(ring, np.float32)).cuda()
+    u, st = G.gdgs_poisson_solve_rhs(r, b, W, H, mg)
+    torch.cuda.synchronize()
+    return np_(u).astype(np.float64), G.read_stats(st)
+
+
+@pytest.mark.parametrize("H,W,a,b", [(64, 64, 1, 1), (72, 100, 2, 3), (17, 33, 1, 2),
+                                     (3, 3, 1, 1), (5, 130, 1, 4), (800, 800, 3, 2),
+                                     (1080, 1920, 2, 5)])
+def test_sin_product_closed_form(H, W, a, b):
+    say(f"[poisson] sin-product {H}x{W} a={a} b={b}")
+    i = np.arange(H)[:, None]
+    j = np.arange(W)[None, :]
+    u = np.sin(math.pi * a * i / (H - 1)) * np.sin(math.pi * b * j / (W - 1))
+    lam = 2 * math.cos(math.pi * a / (H - 1)) + 2 * math.cos(math.pi * b / (W - 1)) - 4
+    rho = np.zeros((3, H, W))
+    for c in range(3):
+        rho[c, 1:-1, 1:-1] = (c + 1) * lam * u[1:-1, 1:-1]
+    got, st = solve_rhs(rho, None, G.mg_params(tol=1e-7, max_cycles=40))
+    for c in range(3):
+        err = np.abs(got[c] - (c + 1) * u).max()
+        say(f"  channel {c}: max-abs {err:.3e}, cycles {st['cycles'][c]}, eta {st['eta'][c]:.2e}")
+        assert err <= TOL
+    assert st["converged"]
+
+
+@pytest.mark.parametrize("H,W", [(64, 64), (72, 100), (97, 61), (800, 800), (1080, 1920)])
+def test_matches_direct_solver_with_reference_ring(H, W):
+    say(f"[poisson] vs direct {H}x{W}")
+    rng = np.random.default_rng(H + W)
+    ref = wl.reference_image(H, W, seed=1)
+    rho = np.zeros((3, H, W))
+    rho[:, 1:-1, 1:-1] = rng.laplace(0, 0.02, (3, H - 2, W - 2))
+    rho32 = rho.astype(np.float32).astype(np.float64)
+    ring32 = ref.astype(np.float32).astype(np.float64)
+    got, st = solve_rhs(rho32, ring32, G.mg_params(tol=1e-6))
+    exact = P.solve(rho32, ring32)
+    err = np.abs(got - exact).max()
+    say(f"  max-abs {err:.3e} cycles {st['cycles']} eta {st['eta']} rel_res {st['rel_res']}")
+    assert err <= TOL
+    assert st["converged"] and max(st["cycles"]) <= 20
+    # ring is copied through
+    assert np.array_equal(got[:, 0, :], ring32[:, 0, :])
+
+
+def test_gradient_input_divergence_and_integrable_field():
+    H, W = 90, 123
+    f = wl.reference_image(H, W, seed=3)
+    g = np.zeros((6, H, W))
+    g[0::2, :, :-1] = f[:, :, 1:] - f[:, :, :-1]
+    g[1::2, :-1, :] = f[:, 1:, :] - f[:, :-1, :]
+    g32 = torch.from_numpy(g.astype(np.float32)).cuda()
+    ring = torch.from_numpy(f.astype(np.float32)).cuda()
+    u, st = G.gdgs_poisson_solve(g32, ring, W, H, G.mg_params(tol=1e-7, max_cycles=40))
+    torch.cuda.synchronize()
+    exact = P.solve(P.divergence(g.astype(np.float32)), f.astype(np.float32))
+    assert np.abs(np_(u) - exact).max() <= TOL
+    assert np.abs(np_(u) - f).max() <= TOL       # integrable field recovers the image
+
+
+def test_convergence_factor_per_cycle():
+    H, W = 1080, 1920
+    rng = np.random.default_rng(1)
+    rho = np.zeros((3, H, W))
+    rho[:, 1:-1, 1:-1] = rng.normal(0, 0.05, (3, H - 2, W - 2))
+    etas = []
+    for cyc in (1, 2, 3, 4):
+        _, st = solve_rhs(rho, None, G.mg_params(tol=0.0, max_cycles=cyc))
+        etas.append(max(st["rel_res"]))
+    factors = [etas[i + 1] / etas[i] for i in range(3)]
+    say(f"[poisson] rel_res per cycle {etas}, factors {factors}")
+    assert max(factors) <= 0.2
+
+
+def test_zero_rhs_zero_ring_is_immediately_exact():
+    u, st = solve_rhs(np.zeros((3, 40, 50)), None)
+    assert np.all(u == 0) and st["converged"] and st["cycles"] == [0, 0, 0]
+
+
+def test_deterministic():
+    rng = np.random.default_rng(2)
+    rho = rng.normal(0, 0.05, (3, 300, 411))
+    a, _ = solve_rhs(rho, None)
+    b, _ = solve_rhs(rho, None)
+    assert np.array_equal(a, b)

@@ -1,0 +1,90 @@
+"""End-to-end render (project -> bin -> composite -> Poisson) against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2405_05446_amd as G
+import workloads as wl
+from oracle import composite as oc, poisson as P
+from oracle.project import project as oproject
+from oracle.render import render as orender
+from tests.gpu_util import say, np_, gpu_stages
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+def test_tiny_workload_end_to_end():
+    cfg = wl.CONFIGS["tiny"]
+    say("[render] tiny workload end to end")
+    sc = wl.make_scene(cfg["K"], seed=0, z=cfg["z"], ls=cfg["ls"])
+    cam = wl.make_camera(cfg["W"], cfg["H"])
+    ds = G.DeviceScene.from_host(sc)
+    u, st = G.gdgs_render(ds, cam, None, G.mg_params(levels=cfg["levels"], tol=1e-8,
+                                                     max_cycles=40), sync_stats=True)
+    torch.cuda.synchronize()
+    o = orender(sc, cam, None)
+    err = np.abs(np_(u) - o["u"]).max()
+    s = G.read_stats(st)
+    say(f"  max-abs {err:.3e}, stats {s}")
+    assert err <= TOL
+    assert P.relative_residual(o["u"], o["rho"]).max() <= 1e-8
+
+
+def test_ragged_posed_render_with_reference_ring():
+    H, W = 72, 100
+    sc = wl.make_scene(3000, seed=3, ls=(-3, 0.6))
+    cam = wl.make_camera(W, H, pose_index=4)
+    ring = wl.reference_image(H, W, seed=1).astype(np.float32)
+    ds = G.DeviceScene.from_host(sc)
+    u, st = G.gdgs_render(ds, cam, torch.from_numpy(ring).cuda(), G.mg_params(tol=1e-7),
+                          sync_stats=True)
+    torch.cuda.synchronize()
+    o = orender(sc, cam, ring.astype(np.float64))
+    assert np.abs(np_(u) - o["u"]).max() <= TOL
+
+
+@pytest.mark.parametrize("name", ["mid", "full"])
+def test_workload_stagewise(name):
+    cfg = wl.CONFIGS[name]
+    say(f"[render] {name} workload stage-wise")
+    sc = wl.make_scene(cfg["K"], seed=0, z=cfg["z"], ls=cfg["ls"])
+    cam = wl.make_camera(cfg["W"], cfg["H"], pose_index=0 if name == "full" else None)
+    H, W = cfg["H"], cfg["W"]
+    ring = wl.reference_image(H, W, seed=1).astype(np.float32)
+    ds = G.DeviceScene.from_host(sc)
+    mg = G.mg_params(levels=cfg["levels"], tol=cfg["tol"])
+    u, st = G.gdgs_render(ds, cam, torch.from_numpy(ring).cuda(), mg, sync_stats=True)
+    torch.cuda.synchronize()
+    s = G.read_stats(st)
+    say(f"  stats {s}")
+    g = gpu_stages(sc, cam)
+    # composite on sampled pixels vs brute force
+    o = oproject(sc, cam)
+    rows, cols = wl.sample_pixels(H, W, 150 if name == "full" else 300, seed=12)
+    ref = oc.render_grad(o, sc.opacity, sc.value, H, W, rows, cols)
+    e1 = np.abs(g["grad"][:, rows, cols] - ref).max()
+    # Poisson of the GPU's gradients vs the exact DST-I solve
+    exact = P.solve_dst(P.divergence(g["grad"].astype(np.float32)), ring.astype(np.float64))
+    e2 = np.abs(np_(u) - exact).max()
+    say(f"  composite max-abs {e1:.3e}, poisson max-abs {e2:.3e}")
+    assert e1 <= TOL and e2 <= TOL and s["converged"] and not s["overflow"]
+
+
+def test_render_capacity_overflow_status():
+    sc = wl.make_scene(2000, seed=0)
+    cam = wl.make_camera(64, 64)
+    ds = G.DeviceScene.from_host(sc)
+    with pytest.raises(G.GdgsError) as e:
+        G.gdgs_render(ds, cam, None, capacity=10, sync_stats=True)
+    assert e.value.status == 2
+
+
+def test_renderer_retries_on_overflow():
+    sc = wl.make_scene(2000, seed=0)
+    cam = wl.make_camera(64, 64)
+    r = G.Renderer(G.DeviceScene.from_host(sc), 64, 64, G.mg_params(tol=1e-8, max_cycles=40),
+                   capacity=16)
+    u = r.render(cam)
+    o = orender(sc, cam, None)
+    assert np.abs(np_(u) - o["u"]).max() <= TOL
