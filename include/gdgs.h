@@ -100,26 +100,32 @@ typedef struct gdgs_bins {
     int64_t* num_pairs;   /* [1] total pairs P; pairs beyond capacity are dropped */
 } gdgs_bins;
 
-/* Multigrid parameters (host struct) for the Poisson solve (Eq. 21). */
+/* Multigrid parameters (host struct) for the Poisson solve (Eq. 21).
+ * A channel stops after the first V-cycle whose correction is small relative
+ * to the solution, ||u_k - u_{k-1}||_inf <= tol ||u_k||_inf (interior pixels);
+ * with the cycle's contraction factor rho (about 0.1) the remaining error is
+ * then about rho / (1 - rho) of that correction. */
+#define GDGS_MG_WARM_START 1  /* flags: start from the caller's u (interior) instead of zero */
 typedef struct gdgs_mg_params {
     int32_t levels;        /* grids including the finest, >= 1; 0 = as many as the size allows, at most 8 */
     int32_t pre_sweeps;    /* red-black Gauss-Seidel sweeps before restriction, 1..2 */
     int32_t post_sweeps;   /* sweeps after prolongation, 1..2 */
     int32_t max_cycles;    /* V-cycle limit, 1..64 */
     int32_t coarse_sweeps; /* SOR sweeps on the coarsest grid; 0 = automatic */
-    int32_t reserved;
-    double tol;            /* stop when the normwise backward error <= tol */
+    int32_t flags;         /* GDGS_MG_WARM_START or 0 */
+    double tol;            /* relative-correction tolerance (see above); 0 runs max_cycles */
 } gdgs_mg_params;
 
-/* Device-side statistics written by the solve and the render.  The solve
- * stops a channel once eta = ||b - A w||_inf / (8 ||w||_inf + ||b||_inf) <= tol
- * (A = minus the interior 5-point Laplacian, w the interior unknowns). */
+/* Device-side statistics written by the solve and the render (b and w are
+ * the right-hand side and unknowns of A w = b, A = minus the interior
+ * 5-point Laplacian). */
 typedef struct gdgs_stats {
     int32_t cycles[3];     /* V-cycles run per colour channel */
     int32_t converged;     /* 1 if every channel met tol */
-    double eta[3];         /* final normwise backward error per channel */
-    double rel_res[3];     /* final ||b - A w||_2 / ||b||_2 per channel */
+    double eta[3];         /* ||b - A w||_inf / (8 ||w||_inf + ||b||_inf) after the last cycle */
+    double rel_res[3];     /* ||b - A w||_2 / ||b||_2 after the last cycle */
     double b_norm[3];      /* ||b||_2 per channel */
+    double delta[3];       /* relative correction of the last cycle (the stopping quantity) */
     int64_t num_pairs;     /* render: (tile, splat) pairs needed */
     int32_t overflow;      /* render: 1 if num_pairs exceeded the pair capacity */
     int32_t reserved;
@@ -132,6 +138,13 @@ const char* gdgs_status_string(gdgs_status s);
 const char* gdgs_last_error(void);
 /* Version string of the library build. */
 const char* gdgs_version(void);
+/* Host-only switch (default on; environment GDGS_GRAPHS=0 turns it off):
+ * gdgs_render and the Poisson calls capture their launch sequence once per
+ * argument set into a HIP graph and replay it, which removes per-kernel host
+ * launch cost.  Calls on a stream that is itself being captured always
+ * launch directly.  gdgs_clear_graphs() destroys the cached graphs. */
+void gdgs_set_graphs(int enable);
+void gdgs_clear_graphs(void);
 
 /* ------------------------------------------------------------------ */
 /* Workspace sizes (bytes, host-only calls, nothing is enqueued).      */
@@ -194,7 +207,7 @@ gdgs_status gdgs_raster_grad(const gdgs_proj* proj, const float* opacity, const 
  * grid) for L u = rho on the interior, u = boundary on the ring.
  * boundary[3][H][W] (only its ring is read) may be NULL for a zero ring.
  * Output u[3][H][W] is fully written (ring = boundary ring).  stats_dev
- * (device pointer, may be NULL) receives cycles, eta, rel_res.
+ * (device pointer, may be NULL) receives cycles, eta, rel_res, delta.
  * Workspace: gdgs_poisson_workspace_size(W, H, mg). */
 gdgs_status gdgs_poisson_solve(const float* grad, const float* boundary, int32_t W, int32_t H,
                                const gdgs_mg_params* mg, float* u, gdgs_stats* stats_dev,

@@ -5,6 +5,7 @@ The compute lives in libgdgs.so (hand-written HIP kernels behind the C ABI of
 include/gdgs.h); this package marshals torch device tensors into it.
 """
 from ._lib import GdgsError, load  # noqa: F401
+from . import api  # noqa: F401
 from .api import (  # noqa: F401
     DeviceScene, Renderer, alloc_bins, alloc_proj, camera_struct, gdgs_bin_sort,
     gdgs_div_adjoint, gdgs_poisson_solve, gdgs_poisson_solve_rhs, gdgs_project,

@@ -57,14 +57,15 @@ class Bins(ctypes.Structure):
 class MgParams(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("pre_sweeps", ctypes.c_int32),
                 ("post_sweeps", ctypes.c_int32), ("max_cycles", ctypes.c_int32),
-                ("coarse_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("coarse_sweeps", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("tol", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int32 * 3), ("converged", ctypes.c_int32),
                 ("eta", ctypes.c_double * 3), ("rel_res", ctypes.c_double * 3),
-                ("b_norm", ctypes.c_double * 3), ("num_pairs", ctypes.c_int64),
+                ("b_norm", ctypes.c_double * 3), ("delta", ctypes.c_double * 3),
+                ("num_pairs", ctypes.c_int64),
                 ("overflow", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
@@ -73,6 +74,8 @@ _SIGS = {
     "gdgs_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "gdgs_last_error": (ctypes.c_char_p, []),
     "gdgs_version": (ctypes.c_char_p, []),
+    "gdgs_set_graphs": (None, [ctypes.c_int]),
+    "gdgs_clear_graphs": (None, []),
     "gdgs_bin_sort_workspace_size": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                                     ctypes.c_int64, P(ctypes.c_size_t)]),
     "gdgs_raster_workspace_size": (ctypes.c_int, [ctypes.c_int64, P(ctypes.c_size_t)]),

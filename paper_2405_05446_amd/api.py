@@ -48,9 +48,12 @@ def camera_struct(cam) -> L.Camera:
     return c
 
 
+WARM_START = 1
+
+
 def mg_params(levels: int = 0, pre: int = 2, post: int = 2, max_cycles: int = 20,
-              tol: float = 1e-6, coarse_sweeps: int = 0) -> L.MgParams:
-    return L.MgParams(levels, pre, post, max_cycles, coarse_sweeps, 0, float(tol))
+              tol: float = 1e-6, coarse_sweeps: int = 0, flags: int = 0) -> L.MgParams:
+    return L.MgParams(levels, pre, post, max_cycles, coarse_sweeps, flags, float(tol))
 
 
 @dataclass
@@ -118,7 +121,8 @@ def read_stats(stats: torch.Tensor) -> dict:
     raw = bytes(stats.cpu().numpy().tobytes())
     s = L.Stats.from_buffer_copy(raw)
     return dict(cycles=list(s.cycles), converged=bool(s.converged), eta=list(s.eta),
-                rel_res=list(s.rel_res), b_norm=list(s.b_norm), num_pairs=int(s.num_pairs),
+                rel_res=list(s.rel_res), b_norm=list(s.b_norm), delta=list(s.delta),
+                num_pairs=int(s.num_pairs),
                 overflow=bool(s.overflow))
 
 
@@ -275,30 +279,81 @@ def gdgs_raster_grad_backward(proj: dict, opacity: torch.Tensor, value: torch.Te
 
 
 class Renderer:
-    """Keeps a device scene and a workspace for repeated renders (the render
-    call itself allocates nothing).  On a pair-capacity overflow the render is
-    repeated once with a capacity large enough for the reported count."""
+    """Plain per-request render path for one scene and image size.
 
-    def __init__(self, scene: DeviceScene, W: int, H: int, mg=None, capacity: int | None = None):
+    Owns every buffer and workspace, so a frame allocates nothing.  A frame
+    runs the four library steps (project, bin_sort, raster_grad,
+    poisson_solve) on the current stream, then reads the device statistics:
+      * on a pair-capacity overflow the buffers grow to the reported count and
+        the frame is redone;
+      * the V-cycle budget of a frame is the cycle count the previous frame
+        needed (consecutive views need about the same), so converged channels
+        do not leave idle cycles behind; if a frame has not met the tolerance
+        within its budget the solve continues from its current iterate
+        (GDGS_MG_WARM_START) until it does or the limit max_cycles is reached.
+    """
+
+    def __init__(self, scene: DeviceScene, W: int, H: int, mg=None, capacity: int | None = None,
+                 adaptive: bool = True):
         self.scene, self.W, self.H = scene, int(W), int(H)
         self.mg = mg if mg is not None else mg_params()
+        self.max_cycles = int(self.mg.max_cycles)
+        self.budget = self.max_cycles
+        self.adaptive = adaptive
         self.dev = scene.opacity.device
+        K = scene.K
         self.stats = new_stats(self.dev)
         self.u = torch.empty((3, self.H, self.W), dtype=F32, device=self.dev)
-        self._set_capacity(capacity if capacity is not None else max(1 << 16, 16 * scene.K))
+        self.grad = torch.empty((6, self.H, self.W), dtype=F32, device=self.dev)
+        self.proj = alloc_proj(K, self.dev)
+        lib = L.load()
+        self.ws_ras = workspace(_size(lib.gdgs_raster_workspace_size, K), self.dev)
+        self.ws_poi = workspace(_size(lib.gdgs_poisson_workspace_size, self.W, self.H,
+                                      ctypes.byref(self.mg)), self.dev)
+        self._set_capacity(capacity if capacity is not None else max(1 << 16, 16 * K))
+        self.last = None
 
     def _set_capacity(self, cap: int):
+        lib = L.load()
         self.capacity = int(cap)
-        self.ws = workspace(render_workspace_size(self.scene.K, self.W, self.H, self.capacity,
-                                                  self.mg), self.dev)
+        self.bins = alloc_bins(self.scene.K, self.W, self.H, self.capacity, self.dev)
+        self.ws_bin = workspace(_size(lib.gdgs_bin_sort_workspace_size, self.scene.K, self.W,
+                                      self.H, self.capacity), self.dev)
 
-    def render(self, cam, boundary=None, check: bool = True, stream=None) -> torch.Tensor:
-        gdgs_render(self.scene, cam, boundary, self.mg, self.capacity, self.u, self.stats,
-                    self.ws, sync_stats=False, stream=stream)
-        if check:
+    def _mg(self, cycles: int, flags: int = 0) -> L.MgParams:
+        m = self.mg
+        return mg_params(m.levels, m.pre_sweeps, m.post_sweeps, cycles, m.tol, m.coarse_sweeps,
+                         flags)
+
+    def render(self, cam, boundary=None, events=None, stream=None) -> torch.Tensor:
+        K, W, H = self.scene.K, self.W, self.H
+        rec = (lambda i: events[i].record(torch.cuda.current_stream())) if events else (lambda i: None)
+        rec(0)
+        gdgs_project(self.scene, cam, self.proj, stream)
+        rec(1)
+        gdgs_bin_sort(self.proj, K, W, H, self.capacity, self.bins, self.ws_bin, stream)
+        rec(2)
+        gdgs_raster_grad(self.proj, self.scene.opacity, self.scene.value, K, self.bins, W, H,
+                         self.grad, self.ws_ras, stream)
+        rec(3)
+        gdgs_poisson_solve(self.grad, boundary, W, H, self._mg(self.budget), self.u, self.stats,
+                           self.ws_poi, stream)
+        rec(4)
+        st = read_stats(self.stats)
+        if int(self.bins["num_pairs"].item()) > self.capacity:
+            self._set_capacity(int(self.bins["num_pairs"].item() * 1.25) + 1024)
+            self.budget = self.max_cycles
+            return self.render(cam, boundary, events, stream)
+        total = max(st["cycles"])
+        while not st["converged"] and total < self.max_cycles:
+            step = min(2, self.max_cycles - total)
+            gdgs_poisson_solve(self.grad, boundary, W, H, self._mg(step, WARM_START), self.u,
+                               self.stats, self.ws_poi, stream)
             st = read_stats(self.stats)
-            if st["overflow"]:
-                self._set_capacity(int(st["num_pairs"] * 1.25) + 1024)
-                gdgs_render(self.scene, cam, boundary, self.mg, self.capacity, self.u,
-                            self.stats, self.ws, sync_stats=True, stream=stream)
+            total += max(st["cycles"])
+        st["total_cycles"] = total
+        st["num_pairs"] = int(self.bins["num_pairs"].item())
+        if self.adaptive:
+            self.budget = max(1, min(self.max_cycles, total))
+        self.last = st
         return self.u

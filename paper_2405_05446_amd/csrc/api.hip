@@ -3,7 +3,13 @@
 // kernels of the individual steps on the caller's stream.
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <list>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
 
 #include "internal.hpp"
 
@@ -129,6 +135,139 @@ __global__ void k_render_stats(const int64_t* num_pairs, int64_t cap, gdgs_stats
     }
 }
 
+// ---------------------------------------------------------------- graph cache
+// A launch sequence is captured once per exact argument set (pointers, sizes,
+// parameters) on a private capture stream, instantiated, and replayed on the
+// caller's stream with one hipGraphLaunch.  The cache is a small LRU.
+class KeyBuilder {
+   public:
+    template <typename T>
+    KeyBuilder& add(const T& v) {
+        s_.append(reinterpret_cast<const char*>(&v), sizeof(T));
+        return *this;
+    }
+    KeyBuilder& tag(const char* t) {
+        s_.append(t);
+        s_.push_back('\0');
+        return *this;
+    }
+    const std::string& str() const { return s_; }
+
+   private:
+    std::string s_;
+};
+
+struct GraphCache {
+    std::mutex mu;
+    std::list<std::pair<std::string, hipGraphExec_t>> lru;
+    static constexpr size_t kMax = 32;
+
+    hipGraphExec_t find(const std::string& k) {
+        std::lock_guard<std::mutex> g(mu);
+        for (auto it = lru.begin(); it != lru.end(); ++it) {
+            if (it->first == k) {
+                lru.splice(lru.begin(), lru, it);
+                return lru.front().second;
+            }
+        }
+        return nullptr;
+    }
+    void put(const std::string& k, hipGraphExec_t e) {
+        std::lock_guard<std::mutex> g(mu);
+        lru.emplace_front(k, e);
+        while (lru.size() > kMax) {
+            (void)hipGraphExecDestroy(lru.back().second);
+            lru.pop_back();
+        }
+    }
+    void clear() {
+        std::lock_guard<std::mutex> g(mu);
+        for (auto& kv : lru) (void)hipGraphExecDestroy(kv.second);
+        lru.clear();
+    }
+};
+
+GraphCache& graph_cache() {
+    static GraphCache* c = new GraphCache();  // never destroyed: outlives static teardown
+    return *c;
+}
+
+int& graphs_flag() {
+    static int v = [] {
+        const char* e = std::getenv("GDGS_GRAPHS");
+        return (e && e[0] == '0') ? 0 : 1;
+    }();
+    return v;
+}
+
+hipStream_t capture_stream(int dev) {
+    thread_local std::map<int, hipStream_t> streams;
+    auto it = streams.find(dev);
+    if (it != streams.end()) return it->second;
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    streams[dev] = s;
+    return s;
+}
+
+template <typename F>
+gdgs_status with_graph(KeyBuilder& kb, hipStream_t st, F&& enqueue) {
+    if (!graphs_flag()) return enqueue(st);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        return enqueue(st);
+    }
+    if (cs != hipStreamCaptureStatusNone) return enqueue(st);
+    int dev = 0;
+    GDGS_HIP_TRY(hipGetDevice(&dev));
+    kb.add(dev);
+    hipGraphExec_t exec = graph_cache().find(kb.str());
+    if (!exec) {
+        hipStream_t cap = capture_stream(dev);
+        if (!cap) return enqueue(st);
+        GDGS_HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+        const gdgs_status s = enqueue(cap);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(cap, &g);
+        if (s != GDGS_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return s;
+        }
+        if (e != hipSuccess || g == nullptr) {
+            set_error("graph capture failed: %s", hipGetErrorString(e));
+            return GDGS_ERR_HIP;
+        }
+        const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            set_error("graph instantiation failed: %s", hipGetErrorString(ei));
+            return GDGS_ERR_HIP;
+        }
+        graph_cache().put(kb.str(), exec);
+    }
+    GDGS_HIP_TRY(hipGraphLaunch(exec, st));
+    return GDGS_OK;
+}
+
+void add_plan(KeyBuilder& kb, const MgPlan& p) {
+    kb.add(p.levels).add(p.lc).add(p.pre).add(p.post).add(p.max_cycles).add(p.coarse_sweeps)
+        .add(p.omega).add(p.tol).add(p.warm).add(p.lds_bytes);
+    for (int l = 0; l < p.levels; ++l) kb.add(p.n[l]).add(p.m[l]).add(p.pitch[l]);
+}
+
+void add_proj(KeyBuilder& kb, const gdgs_proj& p) {
+    kb.add(p.mean2d).add(p.conic).add(p.depth).add(p.rect).add(p.count);
+}
+
+void add_bins(KeyBuilder& kb, const gdgs_bins& b) {
+    kb.add(b.capacity).add(b.tile_of_pair).add(b.rank_of_pair).add(b.order).add(b.ranges)
+        .add(b.num_pairs);
+}
+
 }  // namespace
 }  // namespace gdgs
 
@@ -153,6 +292,10 @@ const char* gdgs_status_string(gdgs_status s) {
 const char* gdgs_last_error(void) { return g_err; }
 
 const char* gdgs_version(void) { return "gdgs 0.1 gfx950"; }
+
+void gdgs_set_graphs(int enable) { graphs_flag() = enable ? 1 : 0; }
+
+void gdgs_clear_graphs(void) { graph_cache().clear(); }
 
 gdgs_status gdgs_bin_sort_workspace_size(int64_t K, int32_t W, int32_t H, int64_t pair_capacity,
                                          size_t* bytes) {
@@ -250,7 +393,14 @@ gdgs_status gdgs_bin_sort(const gdgs_proj* proj, int64_t K, int32_t W, int32_t H
     BinWs b;
     bin_ws_layout(K, bins->capacity, ws, &b);
     gdgs_proj p = K > 0 ? *proj : gdgs_proj{};
-    return launch_bin_sort(p, K, W, H, *bins, b, as_stream(stream));
+    const gdgs_bins bb = *bins;
+    KeyBuilder kb;
+    kb.tag("bin_sort").add(K).add(W).add(H).add(ws);
+    add_proj(kb, p);
+    add_bins(kb, bb);
+    return with_graph(kb, as_stream(stream), [&](hipStream_t s) {
+        return launch_bin_sort(p, K, W, H, bb, b, s);
+    });
 }
 
 gdgs_status gdgs_raster_grad(const gdgs_proj* proj, const float* opacity, const float* value,
@@ -268,7 +418,14 @@ gdgs_status gdgs_raster_grad(const gdgs_proj* proj, const float* opacity, const 
     TRY(check_bins(bins, K));
     TRY(check_ws(ws, ws_bytes, raster_ws_bytes(K)));
     gdgs_proj p = K > 0 ? *proj : gdgs_proj{};
-    return launch_raster(p, opacity, value, K, *bins, W, H, grad, ws, as_stream(stream));
+    const gdgs_bins bb = *bins;
+    KeyBuilder kb;
+    kb.tag("raster").add(K).add(W).add(H).add(ws).add(opacity).add(value).add(grad);
+    add_proj(kb, p);
+    add_bins(kb, bb);
+    return with_graph(kb, as_stream(stream), [&](hipStream_t s) {
+        return launch_raster(p, opacity, value, K, bb, W, H, grad, ws, s);
+    });
 }
 
 static gdgs_status poisson_common(const float* grad, const float* rho, const float* boundary,
@@ -283,7 +440,12 @@ static gdgs_status poisson_common(const float* grad, const float* rho, const flo
     MgPlan plan;
     TRY(mg_plan(W, H, mg, &plan));
     TRY(check_ws(ws, ws_bytes, poisson_ws_bytes(plan, W, H)));
-    return launch_poisson(grad, rho, boundary, W, H, plan, u, stats_dev, ws, as_stream(stream));
+    KeyBuilder kb;
+    kb.tag("poisson").add(grad).add(rho).add(boundary).add(W).add(H).add(u).add(stats_dev).add(ws);
+    add_plan(kb, plan);
+    return with_graph(kb, as_stream(stream), [&](hipStream_t s) {
+        return launch_poisson(grad, rho, boundary, W, H, plan, u, stats_dev, ws, s);
+    });
 }
 
 gdgs_status gdgs_poisson_solve(const float* grad, const float* boundary, int32_t W, int32_t H,
@@ -332,16 +494,25 @@ gdgs_status gdgs_render(const gdgs_scene* scene, const gdgs_camera* cam, const f
     RenderWs r;
     render_layout(K, W, H, pair_capacity, plan, ws, &r);
     hipStream_t st = as_stream(stream);
+    // the projection takes the camera by value and is launched directly; the
+    // rest depends only on sizes and buffers and is replayed as one graph
     if (K > 0) TRY(launch_project(*scene, *cam, r.proj, st));
     BinWs b;
     bin_ws_layout(K, pair_capacity, r.bin_ws, &b);
-    TRY(launch_bin_sort(r.proj, K, W, H, r.bins, b, st));
-    TRY(launch_raster(r.proj, scene->opacity, scene->value, K, r.bins, W, H, r.grad, r.raster_ws,
-                      st));
-    TRY(launch_poisson(r.grad, nullptr, boundary, W, H, plan, u, stats_dev, r.poisson_ws, st));
-    hipLaunchKernelGGL(k_render_stats, dim3(1), dim3(64), 0, st, r.bins.num_pairs, pair_capacity,
-                       stats_dev);
-    GDGS_LAUNCH_CHECK();
+    const gdgs_scene sc = *scene;
+    KeyBuilder kb;
+    kb.tag("render").add(K).add(W).add(H).add(pair_capacity).add(ws).add(sc.opacity)
+        .add(sc.value).add(boundary).add(u).add(stats_dev);
+    add_plan(kb, plan);
+    TRY(with_graph(kb, st, [&](hipStream_t s) -> gdgs_status {
+        TRY(launch_bin_sort(r.proj, K, W, H, r.bins, b, s));
+        TRY(launch_raster(r.proj, sc.opacity, sc.value, K, r.bins, W, H, r.grad, r.raster_ws, s));
+        TRY(launch_poisson(r.grad, nullptr, boundary, W, H, plan, u, stats_dev, r.poisson_ws, s));
+        hipLaunchKernelGGL(k_render_stats, dim3(1), dim3(64), 0, s, r.bins.num_pairs,
+                           pair_capacity, stats_dev);
+        GDGS_LAUNCH_CHECK();
+        return GDGS_OK;
+    }));
     if (sync_stats) {
         GDGS_HIP_TRY(hipStreamSynchronize(st));
         gdgs_stats h;

@@ -115,10 +115,13 @@ struct MgPlan {
     int n[kMaxLevels];    // interior rows per level
     int m[kMaxLevels];    // interior columns per level
     int pitch[kMaxLevels];
+    double dy[kMaxLevels];  // distance of the high-side boundary beyond the last row (grid units)
+    double dx[kMaxLevels];  // same for the last column
     size_t lds_bytes = 0; // dynamic LDS of the in-workgroup V-cycle
     int pre = 2, post = 2, max_cycles = 20, coarse_sweeps = 0;
     float omega = 1.0f;   // SOR factor on the coarsest grid
     double tol = 1e-6;
+    bool warm = false;    // start from the caller's u instead of zero
 };
 gdgs_status mg_plan(int W, int H, const gdgs_mg_params* mg, MgPlan* plan);
 size_t poisson_ws_bytes(const MgPlan& plan, int W, int H);

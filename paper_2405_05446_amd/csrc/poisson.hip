@@ -6,7 +6,15 @@
 //
 // Multigrid: vertex-centred grids, coarse point I <-> fine point 2I, n_c =
 // floor(n/2) interior points per axis (for even n the coarse boundary sits one
-// fine cell beyond the fine one).  V(pre, post) cycles: red-black Gauss-Seidel
+// fine cell beyond the fine one).  Each grid keeps the distance delta (in its
+// own spacing) from its last interior row/column to the true boundary: 1 on the
+// finest grid, (1 + delta)/2 after an odd count, delta/2 after an even one.
+// Where delta < 1 the Dirichlet condition is imposed through a linearly
+// extrapolated ghost value u_ghost = u (1 - 1/delta), i.e. the diagonal of the
+// last row/column grows by 1/delta - 1 (for delta = 1/2 this is exactly the
+// Galerkin coarse operator of the 1D problem), and prolongation onto a fine
+// point between the last coarse point and the boundary uses the matching
+// linear weight 1 - 1/(2 delta).  V(pre, post) cycles: red-black Gauss-Seidel
 // (pre: red then black, post: black then red), full-weighting restriction of
 // the residual (coarse right-hand side = 4 x full weighting, the unit-spacing
 // scaling of a grid twice as coarse), bilinear prolongation, SOR on the
@@ -41,11 +49,40 @@ struct LevelDev {
     float* fw;       // writable alias of f (coarse levels)
     int n, m, pitch;
     long long cs;    // channel stride (floats)
+    float ey, ex;    // extra diagonal on the last interior row / column (1/delta - 1)
+    float wy, wx;    // prolongation weight onto a fine point beyond the last row / column
 };
+
+// Diagonal of the (possibly boundary-modified) 5-point operator at (gi, gj).
+__device__ __forceinline__ float diag_at(int gi, int gj, int n, int m, float ey, float ex) {
+    float d = 4.f;
+    if (gi == n) d += ey;
+    if (gj == m) d += ex;
+    return d;
+}
+
+// Gauss-Seidel value (sum of the four neighbours - f) / diagonal, evaluated in
+// FP64 registers and rounded once: the FP32 operands are summed exactly enough
+// that the only rounding left is that of the stored result.
+__device__ __forceinline__ float gs_value(float a, float b, float c, float e, float f, float d) {
+    const double nb = ((double)a + (double)b) + ((double)c + (double)e);
+    const double x = nb - (double)f;
+    return (float)(d == 4.f ? 0.25 * x : x / (double)d);
+}
+
+// Residual f - (neighbours - d u) in FP64: near convergence the terms are ~4|u|
+// while the residual is ~1e-7 |u|, and FP32 cancellation noise here would feed
+// random corrections into the coarse grids.
+__device__ __forceinline__ float res_value(float a, float b, float c, float e, float u, float f,
+                                           float d) {
+    const double nb = ((double)a + (double)b) + ((double)c + (double)e);
+    return (float)((double)f - (nb - (double)d * (double)u));
+}
 
 struct LdsPlan {
     int lc, L;
     int n[kMaxLevels], m[kMaxLevels];
+    float ey[kMaxLevels], ex[kMaxLevels], wy[kMaxLevels], wx[kMaxLevels];
     int off[kMaxLevels];   // float offset of u_l in LDS; f_l follows u_l
     int pre, post, csweeps;
     float omega;
@@ -92,7 +129,7 @@ __device__ void block_reduce3(double& a, double& b, double& s, double* sh /*[3*n
 __global__ __launch_bounds__(kDivTX* kDivTY) void k_div_init(
     const float* __restrict__ grad, const float* __restrict__ rho_in,
     const float* __restrict__ boundary, int H, int W, float* __restrict__ f0,
-    float* __restrict__ u0, double* __restrict__ bpart) {
+    float* __restrict__ u0, double* __restrict__ bpart, int warm) {
     __shared__ double sh[3 * 4];
     const int c = blockIdx.z;
     const int j = blockIdx.x * kDivTX + (threadIdx.x % kDivTX);
@@ -116,7 +153,7 @@ __global__ __launch_bounds__(kDivTX* kDivTY) void k_div_init(
                 rho = rho_in[o];
             }
             if (f0) f0[o] = rho;
-            u0[o] = 0.f;
+            if (!warm) u0[o] = 0.f;
             double b = -(double)rho;
             if (boundary) {
                 const float* g = boundary + (size_t)c * HW;
@@ -141,7 +178,8 @@ __global__ __launch_bounds__(kDivTX* kDivTY) void k_div_init(
 __global__ __launch_bounds__(256) void k_setup_finalize(const double* __restrict__ bpart, int nblk,
                                                         double* __restrict__ bnorm,
                                                         int* __restrict__ done,
-                                                        gdgs_stats* __restrict__ stats) {
+                                                        gdgs_stats* __restrict__ stats,
+                                                        int warm) {
     __shared__ double sh[3 * 4];
     for (int c = 0; c < 3; ++c) {
         double mx = 0.0, dum = 0.0, ss = 0.0;
@@ -153,11 +191,13 @@ __global__ __launch_bounds__(256) void k_setup_finalize(const double* __restrict
         if (threadIdx.x == 0) {
             bnorm[2 * c] = mx;
             bnorm[2 * c + 1] = sqrt(ss);
-            const int d = (mx == 0.0);
+            // zero right-hand side and zero initial interior: already exact
+            const int d = (mx == 0.0) && !warm;
             done[c] = d;
             stats->cycles[c] = 0;
             stats->eta[c] = d ? 0.0 : 1.0;
             stats->rel_res[c] = d ? 0.0 : 1.0;
+            stats->delta[c] = d ? 0.0 : 1.0;
             stats->b_norm[c] = sqrt(ss);
         }
     }
@@ -169,8 +209,8 @@ __global__ __launch_bounds__(256) void k_setup_finalize(const double* __restrict
 // is grid point (gi0, gj0); only interior grid points (1..n, 1..m) change.
 template <int RX, int RY>
 __device__ __forceinline__ void smooth_region(float* __restrict__ su, const float* __restrict__ sf,
-                                              int gi0, int gj0, int n, int m, int color0,
-                                              int sweeps) {
+                                              int gi0, int gj0, int n, int m, float ey, float ex,
+                                              int color0, int sweeps) {
     constexpr int HX = (RX - 1) / 2;
     for (int s = 0; s < sweeps; ++s) {
         for (int h = 0; h < 2; ++h) {
@@ -183,7 +223,8 @@ __device__ __forceinline__ void smooth_region(float* __restrict__ su, const floa
                 const int gj = gj0 + q;
                 if (q <= RX - 2 && gi >= 1 && gi <= n && gj >= 1 && gj <= m) {
                     const int o = r * RX + q;
-                    su[o] = 0.25f * (su[o - RX] + su[o + RX] + su[o - 1] + su[o + 1] - sf[o]);
+                    su[o] = gs_value(su[o - RX], su[o + RX], su[o - 1], su[o + 1], sf[o],
+                                     diag_at(gi, gj, n, m, ey, ex));
                 }
             }
             __syncthreads();
@@ -208,25 +249,54 @@ __device__ __forceinline__ void load_region(float* su, float* sf, const LevelDev
 }
 
 // Pre-smoothing + residual + restriction to the next grid.
-template <int NU>
+// Thread t of a 256-thread block owns the tile cells t, t + 256, ...
+constexpr int kCellsPerThread = kTX * kTY / 256;
+
+template <int NU, bool DELTA>
 __global__ __launch_bounds__(256) void k_mg_pre(LevelDev L, LevelDev C, int zero_guess,
-                                                const int* __restrict__ done) {
+                                                const int* __restrict__ done,
+                                                double* __restrict__ part) {
     constexpr int HALO = 2 * NU + 2;
     constexpr int RX = kTX + 2 * HALO, RY = kTY + 2 * HALO;
     __shared__ float su[RY * RX];
     __shared__ float sf[RY * RX];
+    __shared__ double sh[3 * 4];
     const int c = blockIdx.z;
     if (done[c]) return;
     const int gi0 = blockIdx.y * kTY - HALO, gj0 = blockIdx.x * kTX - HALO;
     load_region<RX, RY>(su, sf, L, c, gi0, gj0, zero_guess != 0);
     __syncthreads();
-    smooth_region<RX, RY>(su, sf, gi0, gj0, L.n, L.m, 0, NU);
+    float before[kCellsPerThread];
+    if (DELTA) {
+#pragma unroll
+        for (int k = 0; k < kCellsPerThread; ++k) {
+            const int idx = threadIdx.x + 256 * k;
+            before[k] = su[(HALO + idx / kTX) * RX + HALO + idx % kTX];
+        }
+    }
+    smooth_region<RX, RY>(su, sf, gi0, gj0, L.n, L.m, L.ey, L.ex, 0, NU);
     const int N = L.n + 2, M = L.m + 2;
     float* u = L.u + (size_t)c * L.cs;
-    for (int idx = threadIdx.x; idx < kTY * kTX; idx += blockDim.x) {
+    double dmax = 0.0;
+#pragma unroll
+    for (int k = 0; k < kCellsPerThread; ++k) {
+        const int idx = threadIdx.x + 256 * k;
         const int r = HALO + idx / kTX, q = HALO + idx % kTX;
         const int gi = gi0 + r, gj = gj0 + q;
-        if (gi < N && gj < M) u[(size_t)gi * L.pitch + gj] = su[r * RX + q];
+        if (gi < N && gj < M) {
+            const float v = su[r * RX + q];
+            u[(size_t)gi * L.pitch + gj] = v;
+            if (DELTA && gi >= 1 && gi <= L.n && gj >= 1 && gj <= L.m)
+                dmax = fmax(dmax, fabs((double)v - (double)before[k]));
+        }
+    }
+    if (DELTA) {
+        double d1 = 0.0, d2 = 0.0;
+        block_reduce3(dmax, d1, d2, sh);
+        if (threadIdx.x == 0) {
+            const int nblk = gridDim.x * gridDim.y;
+            part[((size_t)c * nblk + blockIdx.y * gridDim.x + blockIdx.x) * 5 + 3] = dmax;
+        }
     }
     // residual on rows/cols [HALO-1, HALO+T-1], zero off the interior
     constexpr int ZR = kTY + 1, ZC = kTX + 1;
@@ -236,7 +306,8 @@ __global__ __launch_bounds__(256) void k_mg_pre(LevelDev L, LevelDev C, int zero
         const int o = r * RX + q;
         float rv = 0.f;
         if (gi >= 1 && gi <= L.n && gj >= 1 && gj <= L.m)
-            rv = sf[o] - (su[o - RX] + su[o + RX] + su[o - 1] + su[o + 1] - 4.f * su[o]);
+            rv = res_value(su[o - RX], su[o + RX], su[o - 1], su[o + 1], su[o], sf[o],
+                           diag_at(gi, gj, L.n, L.m, L.ey, L.ex));
         sf[o] = rv;
     }
     __syncthreads();
@@ -268,25 +339,38 @@ __global__ __launch_bounds__(256) void k_mg_post(LevelDev L, LevelDev C,
     const int gi0 = blockIdx.y * kTY - HALO, gj0 = blockIdx.x * kTX - HALO;
     load_region<RX, RY>(su, sf, L, c, gi0, gj0, false);
     __syncthreads();
+    float before[kCellsPerThread];
+    if (NORM) {
+#pragma unroll
+        for (int k = 0; k < kCellsPerThread; ++k) {
+            const int idx = threadIdx.x + 256 * k;
+            before[k] = su[(HALO + idx / kTX) * RX + HALO + idx % kTX];
+        }
+    }
     const float* e = C.u + (size_t)c * C.cs;
     for (int idx = threadIdx.x; idx < RY * RX; idx += blockDim.x) {
         const int r = idx / RX, q = idx - r * RX;
         const int gi = gi0 + r, gj = gj0 + q;
         if (gi >= 1 && gi <= L.n && gj >= 1 && gj <= L.m) {
             const int oi = gi & 1, oj = gj & 1;
-            const float* p = e + (size_t)(gi >> 1) * C.pitch + (gj >> 1);
+            const int I0 = gi >> 1, J0 = gj >> 1;
+            const float* p = e + (size_t)I0 * C.pitch + J0;
             float v = p[0];
             if (oi) v += p[C.pitch];
             if (oj) v += p[1];
             if (oi & oj) v += p[C.pitch + 1];
-            su[idx] += (oi ? 0.5f : 1.f) * (oj ? 0.5f : 1.f) * v;
+            const float fy = oi ? (I0 == C.n ? C.wy : 0.5f) : 1.f;
+            const float fx = oj ? (J0 == C.m ? C.wx : 0.5f) : 1.f;
+            su[idx] += fy * fx * v;
         }
     }
     __syncthreads();
-    smooth_region<RX, RY>(su, sf, gi0, gj0, L.n, L.m, 1, NU);
+    smooth_region<RX, RY>(su, sf, gi0, gj0, L.n, L.m, L.ey, L.ex, 1, NU);
     float* u = L.u + (size_t)c * L.cs;
-    double rmax = 0.0, umax = 0.0, rss = 0.0;
-    for (int idx = threadIdx.x; idx < kTY * kTX; idx += blockDim.x) {
+    double rmax = 0.0, umax = 0.0, rss = 0.0, dmax = 0.0;
+#pragma unroll
+    for (int k = 0; k < kCellsPerThread; ++k) {
+        const int idx = threadIdx.x + 256 * k;
         const int r = HALO + idx / kTX, q = HALO + idx % kTX;
         const int gi = gi0 + r, gj = gj0 + q;
         if (gi >= 1 && gi <= L.n && gj >= 1 && gj <= L.m) {
@@ -294,9 +378,11 @@ __global__ __launch_bounds__(256) void k_mg_post(LevelDev L, LevelDev C,
             const float uv = su[o];
             u[(size_t)gi * L.pitch + gj] = uv;
             if (NORM) {
+                dmax = fmax(dmax, fabs((double)uv - (double)before[k]));
                 const double rv = (double)sf[o] - ((double)su[o - RX] + (double)su[o + RX] +
                                                    (double)su[o - 1] + (double)su[o + 1] -
-                                                   4.0 * (double)uv);
+                                                   (double)diag_at(gi, gj, L.n, L.m, L.ey, L.ex) *
+                                                       (double)uv);
                 rmax = fmax(rmax, fabs(rv));
                 umax = fmax(umax, fabs((double)uv));
                 rss += rv * rv;
@@ -305,20 +391,23 @@ __global__ __launch_bounds__(256) void k_mg_post(LevelDev L, LevelDev C,
     }
     if (NORM) {
         block_reduce3(rmax, umax, rss, sh);
+        double d1 = 0.0, d2 = 0.0;
+        block_reduce3(dmax, d1, d2, sh);
         if (threadIdx.x == 0) {
             const int nblk = gridDim.x * gridDim.y;
             const int blk = blockIdx.y * gridDim.x + blockIdx.x;
-            double* p = part + ((size_t)c * nblk + blk) * 3;
+            double* p = part + ((size_t)c * nblk + blk) * 5;
             p[0] = rmax;
             p[1] = umax;
             p[2] = rss;
+            p[4] = dmax;
         }
     }
 }
 
 // ---------------------------------------------------------------- coarse V-cycle in LDS
-__device__ __forceinline__ void lds_gs(float* U, const float* F, int n, int m, int color0,
-                                       int sweeps, float omega) {
+__device__ __forceinline__ void lds_gs(float* U, const float* F, int n, int m, float ey,
+                                       float ex, int color0, int sweeps, float omega) {
     const int M = m + 2;
     const int hx = (m + 1) / 2 + 1;
     for (int s = 0; s < sweeps; ++s) {
@@ -330,7 +419,8 @@ __device__ __forceinline__ void lds_gs(float* U, const float* F, int n, int m, i
                 const int j = 1 + 2 * k + ((color + i + 1) & 1);
                 if (j <= m) {
                     const int o = i * M + j;
-                    const float gs = 0.25f * (U[o - M] + U[o + M] + U[o - 1] + U[o + 1] - F[o]);
+                    const float gs = gs_value(U[o - M], U[o + M], U[o - 1], U[o + 1], F[o],
+                                              diag_at(i, j, n, m, ey, ex));
                     U[o] = omega == 1.f ? gs : U[o] + omega * (gs - U[o]);
                 }
             }
@@ -339,11 +429,12 @@ __device__ __forceinline__ void lds_gs(float* U, const float* F, int n, int m, i
     }
 }
 
-__device__ __forceinline__ float lds_res(const float* U, const float* F, int n, int m, int i,
-                                         int j) {
+__device__ __forceinline__ float lds_res(const float* U, const float* F, int n, int m, float ey,
+                                         float ex, int i, int j) {
     if (i < 1 || i > n || j < 1 || j > m) return 0.f;
     const int M = m + 2, o = i * M + j;
-    return F[o] - (U[o - M] + U[o + M] + U[o - 1] + U[o + 1] - 4.f * U[o]);
+    return res_value(U[o - M], U[o + M], U[o - 1], U[o + 1], U[o], F[o],
+                     diag_at(i, j, n, m, ey, ex));
 }
 
 __global__ __launch_bounds__(kLdsThreads) void k_mg_lds(LdsPlan P, const int* __restrict__ done,
@@ -372,7 +463,8 @@ __global__ __launch_bounds__(kLdsThreads) void k_mg_lds(LdsPlan P, const int* __
         const int n = P.n[l], m = P.m[l], M = m + 2;
         float* U = lds + P.off[l];
         float* F = U + (n + 2) * M;
-        lds_gs(U, F, n, m, 0, P.pre, 1.f);
+        const float ey = P.ey[l], ex = P.ex[l];
+        lds_gs(U, F, n, m, ey, ex, 0, P.pre, 1.f);
         const int nc = P.n[l + 1], mc = P.m[l + 1], Mc = mc + 2;
         float* Uc = lds + P.off[l + 1];
         float* Fc = Uc + (nc + 2) * Mc;
@@ -382,11 +474,10 @@ __global__ __launch_bounds__(kLdsThreads) void k_mg_lds(LdsPlan P, const int* __
             float v = 0.f;
             if (I >= 1 && I <= nc && J >= 1 && J <= mc) {
                 const int i = 2 * I, j = 2 * J;
-                v = 4.f * lds_res(U, F, n, m, i, j) +
-                    2.f * (lds_res(U, F, n, m, i - 1, j) + lds_res(U, F, n, m, i + 1, j) +
-                           lds_res(U, F, n, m, i, j - 1) + lds_res(U, F, n, m, i, j + 1)) +
-                    (lds_res(U, F, n, m, i - 1, j - 1) + lds_res(U, F, n, m, i - 1, j + 1) +
-                     lds_res(U, F, n, m, i + 1, j - 1) + lds_res(U, F, n, m, i + 1, j + 1));
+#define R_(a, b) lds_res(U, F, n, m, ey, ex, i + (a), j + (b))
+                v = 4.f * R_(0, 0) + 2.f * (R_(-1, 0) + R_(1, 0) + R_(0, -1) + R_(0, 1)) +
+                    (R_(-1, -1) + R_(-1, 1) + R_(1, -1) + R_(1, 1));
+#undef R_
                 v *= 0.25f;
             }
             Fc[idx] = v;
@@ -397,28 +488,30 @@ __global__ __launch_bounds__(kLdsThreads) void k_mg_lds(LdsPlan P, const int* __
         const int n = P.n[L - 1], m = P.m[L - 1];
         float* U = lds + P.off[L - 1];
         float* F = U + (n + 2) * (m + 2);
-        lds_gs(U, F, n, m, 0, P.csweeps, P.omega);
+        lds_gs(U, F, n, m, P.ey[L - 1], P.ex[L - 1], 0, P.csweeps, P.omega);
     }
     for (int l = L - 2; l >= lc; --l) {
         const int n = P.n[l], m = P.m[l], M = m + 2;
         float* U = lds + P.off[l];
         float* F = U + (n + 2) * M;
-        const int Mc = P.m[l + 1] + 2;
+        const int Mc = P.m[l + 1] + 2, nc = P.n[l + 1], mc = P.m[l + 1];
         const float* Uc = lds + P.off[l + 1];
         for (int idx = threadIdx.x; idx < (n + 2) * M; idx += blockDim.x) {
             const int i = idx / M, j = idx - i * M;
             if (i >= 1 && i <= n && j >= 1 && j <= m) {
-                const int oi = i & 1, oj = j & 1;
-                const float* p = Uc + (i >> 1) * Mc + (j >> 1);
+                const int oi = i & 1, oj = j & 1, I0 = i >> 1, J0 = j >> 1;
+                const float* p = Uc + I0 * Mc + J0;
                 float v = p[0];
                 if (oi) v += p[Mc];
                 if (oj) v += p[1];
                 if (oi & oj) v += p[Mc + 1];
-                U[idx] += (oi ? 0.5f : 1.f) * (oj ? 0.5f : 1.f) * v;
+                const float fy = oi ? (I0 == nc ? P.wy[l + 1] : 0.5f) : 1.f;
+                const float fx = oj ? (J0 == mc ? P.wx[l + 1] : 0.5f) : 1.f;
+                U[idx] += fy * fx * v;
             }
         }
         __syncthreads();
-        lds_gs(U, F, n, m, 1, P.post, 1.f);
+        lds_gs(U, F, n, m, P.ey[l], P.ex[l], 1, P.post, 1.f);
     }
     // write back the top level (its ring too: zero for coarse grids, the
     // unchanged Dirichlet data for the finest)
@@ -427,14 +520,19 @@ __global__ __launch_bounds__(kLdsThreads) void k_mg_lds(LdsPlan P, const int* __
         const float* U = lds + P.off[lc];
         const float* F = U + (n + 2) * M;
         float* gu = P.top.u + (size_t)c * P.top.cs;
-        double rmax = 0.0, umax = 0.0, rss = 0.0;
+        double rmax = 0.0, umax = 0.0, rss = 0.0, dmax = 0.0;
         for (int idx = threadIdx.x; idx < (n + 2) * M; idx += blockDim.x) {
             const int i = idx / M, j = idx - i * M;
-            gu[(size_t)i * P.top.pitch + j] = U[idx];
+            const size_t go = (size_t)i * P.top.pitch + j;
+            if (lc == 0 && i >= 1 && i <= n && j >= 1 && j <= m)
+                dmax = fmax(dmax, fabs((double)U[idx] - (double)gu[go]));
+            gu[go] = U[idx];
             if (lc == 0 && i >= 1 && i <= n && j >= 1 && j <= m) {
                 const double rv = (double)F[idx] - ((double)U[idx - M] + (double)U[idx + M] +
                                                     (double)U[idx - 1] + (double)U[idx + 1] -
-                                                    4.0 * (double)U[idx]);
+                                                    (double)diag_at(i, j, n, m, P.ey[0],
+                                                                    P.ex[0]) *
+                                                        (double)U[idx]);
                 rmax = fmax(rmax, fabs(rv));
                 umax = fmax(umax, fabs((double)U[idx]));
                 rss += rv * rv;
@@ -442,10 +540,14 @@ __global__ __launch_bounds__(kLdsThreads) void k_mg_lds(LdsPlan P, const int* __
         }
         if (lc == 0) {
             block_reduce3(rmax, umax, rss, sh);
+            double d1 = 0.0, d2 = 0.0;
+            block_reduce3(dmax, d1, d2, sh);
             if (threadIdx.x == 0) {
-                part[(size_t)c * 3] = rmax;
-                part[(size_t)c * 3 + 1] = umax;
-                part[(size_t)c * 3 + 2] = rss;
+                part[(size_t)c * 5] = rmax;
+                part[(size_t)c * 5 + 1] = umax;
+                part[(size_t)c * 5 + 2] = rss;
+                part[(size_t)c * 5 + 3] = dmax;
+                part[(size_t)c * 5 + 4] = 0.0;
             }
         }
     }
@@ -459,21 +561,28 @@ __global__ __launch_bounds__(256) void k_cycle_finalize(const double* __restrict
     __shared__ double sh[3 * 4];
     for (int c = 0; c < 3; ++c) {
         if (done[c]) continue;  // uniform: finished before this cycle
-        double rmax = 0.0, umax = 0.0, rss = 0.0;
+        double rmax = 0.0, umax = 0.0, rss = 0.0, dpre = 0.0, dpost = 0.0;
         for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
-            const double* p = part + ((size_t)c * nblk + b) * 3;
+            const double* p = part + ((size_t)c * nblk + b) * 5;
             rmax = fmax(rmax, p[0]);
             umax = fmax(umax, p[1]);
             rss += p[2];
+            dpre = fmax(dpre, p[3]);
+            dpost = fmax(dpost, p[4]);
         }
         block_reduce3(rmax, umax, rss, sh);
+        double d0 = 0.0;
+        block_reduce3(dpre, dpost, d0, sh);
         if (threadIdx.x == 0) {
-            const double eta = rmax / (8.0 * umax + bnorm[2 * c]);
+            // |u_k - u_{k-1}| <= (change in pre-smoothing) + (change in the post pass)
+            const double dcyc = dpre + dpost;
+            const double rel = umax > 0.0 ? dcyc / umax : (dcyc > 0.0 ? 1.0 : 0.0);
             const double b2 = bnorm[2 * c + 1];
-            stats->eta[c] = eta;
+            stats->eta[c] = rmax / (8.0 * umax + bnorm[2 * c]);
             stats->rel_res[c] = b2 > 0.0 ? sqrt(rss) / b2 : 0.0;
+            stats->delta[c] = rel;
             stats->cycles[c] = cycle + 1;
-            if (eta <= tol) done[c] = 1;
+            if (rel <= tol) done[c] = 1;
         }
         __syncthreads();
     }
@@ -513,10 +622,15 @@ int lds_budget() {
 }
 
 template <int NU>
-gdgs_status launch_pre(const LevelDev& L, const LevelDev& C, bool zero, const int* done,
-                       hipStream_t st) {
+gdgs_status launch_pre(const LevelDev& L, const LevelDev& C, bool zero, bool delta,
+                       const int* done, double* part, hipStream_t st) {
     dim3 grid((L.m + 2 + kTX - 1) / kTX, (L.n + 2 + kTY - 1) / kTY, 3);
-    hipLaunchKernelGGL(k_mg_pre<NU>, grid, dim3(256), 0, st, L, C, zero ? 1 : 0, done);
+    if (delta)
+        hipLaunchKernelGGL((k_mg_pre<NU, true>), grid, dim3(256), 0, st, L, C, zero ? 1 : 0,
+                           done, part);
+    else
+        hipLaunchKernelGGL((k_mg_pre<NU, false>), grid, dim3(256), 0, st, L, C, zero ? 1 : 0,
+                           done, part);
     return GDGS_OK;
 }
 
@@ -546,6 +660,11 @@ gdgs_status mg_plan(int W, int H, const gdgs_mg_params* mg, MgPlan* plan) {
                   q.levels, q.pre_sweeps, q.post_sweeps, q.max_cycles, q.tol);
         return GDGS_ERR_INVALID_ARGUMENT;
     }
+    if ((q.flags & ~GDGS_MG_WARM_START) != 0) {
+        set_error("unknown multigrid flags 0x%x", q.flags);
+        return GDGS_ERR_INVALID_ARGUMENT;
+    }
+    p.warm = (q.flags & GDGS_MG_WARM_START) != 0;
     p.pre = q.pre_sweeps;
     p.post = q.post_sweeps;
     p.max_cycles = q.max_cycles;
@@ -553,11 +672,15 @@ gdgs_status mg_plan(int W, int H, const gdgs_mg_params* mg, MgPlan* plan) {
     p.n[0] = H - 2;
     p.m[0] = W - 2;
     p.pitch[0] = W;
+    p.dy[0] = 1.0;
+    p.dx[0] = 1.0;
     int L = 1;
     const int want = q.levels == 0 ? kMaxLevels : q.levels;
     while (L < want && p.n[L - 1] / 2 >= 1 && p.m[L - 1] / 2 >= 1) {
         p.n[L] = p.n[L - 1] / 2;
         p.m[L] = p.m[L - 1] / 2;
+        p.dy[L] = 0.5 * (p.n[L - 1] + p.dy[L - 1]) - p.n[L];
+        p.dx[L] = 0.5 * (p.m[L - 1] + p.dx[L - 1]) - p.m[L];
         p.pitch[L] = pitch_of(p.m[L] + 2);
         ++L;
     }
@@ -579,6 +702,13 @@ gdgs_status mg_plan(int W, int H, const gdgs_mg_params* mg, MgPlan* plan) {
     }
     p.lc = lc;
     p.lds_bytes = bytes;
+    if (bytes > 64 * 1024 &&
+        hipFuncSetAttribute((const void*)k_mg_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("cannot reserve %zu bytes of LDS for the coarse-grid solve", bytes);
+        return GDGS_ERR_HIP;
+    }
     const int nc = p.n[L - 1], mcc = p.m[L - 1];
     const double rj = 0.5 * (cos(M_PI / (nc + 1)) + cos(M_PI / (mcc + 1)));
     p.omega = (float)(2.0 / (1.0 + sqrt(1.0 - rj * rj)));
@@ -624,7 +754,7 @@ size_t poisson_layout(const MgPlan& p, int W, int H, void* ws, PoissonWs* out) {
         w.u[l] = c.take<float>(3 * cells);
         w.f[l] = c.take<float>(3 * cells);
     }
-    w.part = c.take<double>((size_t)3 * 3 * norm_blocks(p));
+    w.part = c.take<double>((size_t)3 * 5 * norm_blocks(p));
     w.bpart = c.take<double>((size_t)3 * 2 * div_blocks(W, H));
     w.bnorm = c.take<double>(6);
     w.done = c.take<int>(4);
@@ -653,6 +783,8 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
     lev[0].m = p.m[0];
     lev[0].pitch = W;
     lev[0].cs = cs0;
+    lev[0].ey = lev[0].ex = 0.f;
+    lev[0].wy = lev[0].wx = 0.5f;
     for (int l = 1; l < p.levels; ++l) {
         lev[l].u = w.u[l];
         lev[l].f = w.f[l];
@@ -661,14 +793,18 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
         lev[l].m = p.m[l];
         lev[l].pitch = p.pitch[l];
         lev[l].cs = (long long)(p.n[l] + 2) * p.pitch[l];
+        lev[l].ey = (float)(1.0 / p.dy[l] - 1.0);
+        lev[l].ex = (float)(1.0 / p.dx[l] - 1.0);
+        lev[l].wy = (float)(1.0 - 0.5 / p.dy[l]);
+        lev[l].wx = (float)(1.0 - 0.5 / p.dx[l]);
     }
     const int nblk_div = div_blocks(W, H);
     hipLaunchKernelGGL(k_div_init,
                        dim3((W + kDivTX - 1) / kDivTX, (H + kDivTY - 1) / kDivTY, 3),
                        dim3(kDivTX * kDivTY), 0, st, grad, grad ? nullptr : rho, boundary, H, W,
-                       grad ? w.f0 : nullptr, u, w.bpart);
+                       grad ? w.f0 : nullptr, u, w.bpart, p.warm ? 1 : 0);
     hipLaunchKernelGGL(k_setup_finalize, dim3(1), dim3(256), 0, st, w.bpart, nblk_div, w.bnorm,
-                       w.done, sd);
+                       w.done, sd, p.warm ? 1 : 0);
     GDGS_LAUNCH_CHECK();
 
     LdsPlan lp;
@@ -678,6 +814,10 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
     for (int l = 0; l < p.levels; ++l) {
         lp.n[l] = p.n[l];
         lp.m[l] = p.m[l];
+        lp.ey[l] = lev[l].ey;
+        lp.ex[l] = lev[l].ex;
+        lp.wy[l] = lev[l].wy;
+        lp.wx[l] = lev[l].wx;
         lp.off[l] = 0;
         if (l >= p.lc) {
             lp.off[l] = off;
@@ -689,18 +829,13 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
     lp.csweeps = p.coarse_sweeps;
     lp.omega = p.omega;
     lp.top = lev[p.lc];
-    if (p.lds_bytes > 64 * 1024) {
-        GDGS_HIP_TRY(hipFuncSetAttribute((const void*)k_mg_lds,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         (int)p.lds_bytes));
-    }
     const int nblk = norm_blocks(p);
     for (int cyc = 0; cyc < p.max_cycles; ++cyc) {
         for (int l = 0; l < p.lc; ++l) {
             if (p.pre == 1)
-                launch_pre<1>(lev[l], lev[l + 1], l > 0, w.done, st);
+                launch_pre<1>(lev[l], lev[l + 1], l > 0, l == 0, w.done, w.part, st);
             else
-                launch_pre<2>(lev[l], lev[l + 1], l > 0, w.done, st);
+                launch_pre<2>(lev[l], lev[l + 1], l > 0, l == 0, w.done, w.part, st);
         }
         hipLaunchKernelGGL(k_mg_lds, dim3(3), dim3(kLdsThreads), p.lds_bytes, st, lp, w.done,
                            w.part);

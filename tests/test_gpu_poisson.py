@@ -36,7 +36,7 @@ def test_sin_product_closed_form(H, W, a, b):
     rho = np.zeros((3, H, W))
     for c in range(3):
         rho[c, 1:-1, 1:-1] = (c + 1) * lam * u[1:-1, 1:-1]
-    got, st = solve_rhs(rho, None, G.mg_params(tol=1e-7, max_cycles=40))
+    got, st = solve_rhs(rho, None, G.mg_params(tol=1e-6, max_cycles=40))
     for c in range(3):
         err = np.abs(got[c] - (c + 1) * u).max()
         say(f"  channel {c}: max-abs {err:.3e}, cycles {st['cycles'][c]}, eta {st['eta'][c]:.2e}")
@@ -71,7 +71,7 @@ def test_gradient_input_divergence_and_integrable_field():
     g[1::2, :-1, :] = f[:, 1:, :] - f[:, :-1, :]
     g32 = torch.from_numpy(g.astype(np.float32)).cuda()
     ring = torch.from_numpy(f.astype(np.float32)).cuda()
-    u, st = G.gdgs_poisson_solve(g32, ring, W, H, G.mg_params(tol=1e-7, max_cycles=40))
+    u, st = G.gdgs_poisson_solve(g32, ring, W, H, G.mg_params(tol=1e-6, max_cycles=40))
     torch.cuda.synchronize()
     exact = P.solve(P.divergence(g.astype(np.float32)), f.astype(np.float32))
     assert np.abs(np_(u) - exact).max() <= TOL
@@ -90,6 +90,29 @@ def test_convergence_factor_per_cycle():
     factors = [etas[i + 1] / etas[i] for i in range(3)]
     say(f"[poisson] rel_res per cycle {etas}, factors {factors}")
     assert max(factors) <= 0.2
+
+
+def test_warm_start_continues_from_the_given_iterate():
+    H, W = 300, 411
+    rng = np.random.default_rng(3)
+    rho = np.zeros((3, H, W))
+    rho[:, 1:-1, 1:-1] = rng.normal(0, 0.05, (3, H - 2, W - 2))
+    ring = wl.reference_image(H, W, seed=1)
+    r = torch.from_numpy(rho.astype(np.float32)).cuda()
+    b = torch.from_numpy(ring.astype(np.float32)).cuda()
+    u, st = G.gdgs_poisson_solve_rhs(r, b, W, H, G.mg_params(tol=0.0, max_cycles=2))
+    torch.cuda.synchronize()
+    u2, st2 = G.gdgs_poisson_solve_rhs(r, b, W, H, G.mg_params(tol=1e-6, max_cycles=30,
+                                                               flags=G.api.WARM_START), u=u)
+    torch.cuda.synchronize()
+    s2 = G.read_stats(st2)
+    exact = P.solve(rho.astype(np.float32).astype(np.float64), ring.astype(np.float32))
+    assert s2["converged"] and np.abs(np_(u2) - exact).max() <= TOL
+    # a converged iterate needs a single further cycle
+    u3, st3 = G.gdgs_poisson_solve_rhs(r, b, W, H, G.mg_params(tol=1e-6, max_cycles=30,
+                                                               flags=G.api.WARM_START), u=u2)
+    torch.cuda.synchronize()
+    assert G.read_stats(st3)["cycles"] == [1, 1, 1]
 
 
 def test_zero_rhs_zero_ring_is_immediately_exact():
