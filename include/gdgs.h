@@ -92,9 +92,9 @@ typedef struct gdgs_proj {
 /* Tile bins: the (tile, splat) pairs sorted by (tile, FP32 depth, splat
  * index) and each tile's range.  Device arrays, caller-owned. */
 typedef struct gdgs_bins {
-    int64_t capacity;     /* length of tile_of_pair / rank_of_pair */
+    int64_t capacity;     /* length of tile_of_pair / splat_of_pair */
     uint32_t* tile_of_pair; /* [capacity] sorted tile id (ty * ceil(W/16) + tx) */
-    uint32_t* rank_of_pair; /* [capacity] depth rank s of each sorted pair; splat = order[s] */
+    uint32_t* splat_of_pair; /* [capacity] splat index of each sorted pair */
     uint32_t* order;      /* [K] splat index of depth rank s (stable: ties by index; culled last) */
     uint32_t* ranges;     /* [2][T] start and end (half-open) of each tile, T = ceil(W/16) ceil(H/16) */
     int64_t* num_pairs;   /* [1] total pairs P; pairs beyond capacity are dropped */

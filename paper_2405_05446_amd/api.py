@@ -106,14 +106,14 @@ def alloc_bins(K: int, W: int, H: int, capacity: int, device=None) -> dict:
     T = ((W + 15) // 16) * ((H + 15) // 16)
     return dict(capacity=int(capacity),
                 tile_of_pair=torch.empty(capacity, dtype=U32, device=d),
-                rank_of_pair=torch.empty(capacity, dtype=U32, device=d),
+                splat_of_pair=torch.empty(capacity, dtype=U32, device=d),
                 order=torch.empty(max(K, 1), dtype=U32, device=d),
                 ranges=torch.empty((2, T), dtype=U32, device=d),
                 num_pairs=torch.zeros(1, dtype=torch.int64, device=d))
 
 
 def _bins_struct(b: dict) -> L.Bins:
-    return L.Bins(b["capacity"], L.ptr(b["tile_of_pair"]), L.ptr(b["rank_of_pair"]),
+    return L.Bins(b["capacity"], L.ptr(b["tile_of_pair"]), L.ptr(b["splat_of_pair"]),
                   L.ptr(b["order"]), L.ptr(b["ranges"]), L.ptr(b["num_pairs"]))
 
 

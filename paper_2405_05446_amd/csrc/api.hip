@@ -65,7 +65,7 @@ gdgs_status check_bins(const gdgs_bins* b, int64_t K) {
     REQUIRE(b->capacity >= 1 && b->capacity < (int64_t)0xFFFFFFFFll,
             "pair capacity %lld must be in [1, 2^32 - 1)", (long long)b->capacity);
     REQUIRE_PTR(b->tile_of_pair);
-    REQUIRE_PTR(b->rank_of_pair);
+    REQUIRE_PTR(b->splat_of_pair);
     REQUIRE_PTR(b->ranges);
     REQUIRE(b->num_pairs != nullptr && (reinterpret_cast<uintptr_t>(b->num_pairs) & 7u) == 0,
             "bins.num_pairs is null or not 8-byte aligned");
@@ -115,7 +115,7 @@ size_t render_layout(int64_t K, int W, int H, int64_t cap, const MgPlan& plan, v
     r.proj.count = c.take<uint32_t>(Kp);
     r.bins.capacity = cap;
     r.bins.tile_of_pair = c.take<uint32_t>(cap);
-    r.bins.rank_of_pair = c.take<uint32_t>(cap);
+    r.bins.splat_of_pair = c.take<uint32_t>(cap);
     r.bins.order = c.take<uint32_t>(Kp);
     r.bins.ranges = c.take<uint32_t>(2 * (size_t)tiles_x(W) * tiles_y(H));
     r.bins.num_pairs = c.take<int64_t>(1);
@@ -264,7 +264,7 @@ void add_proj(KeyBuilder& kb, const gdgs_proj& p) {
 }
 
 void add_bins(KeyBuilder& kb, const gdgs_bins& b) {
-    kb.add(b.capacity).add(b.tile_of_pair).add(b.rank_of_pair).add(b.order).add(b.ranges)
+    kb.add(b.capacity).add(b.tile_of_pair).add(b.splat_of_pair).add(b.order).add(b.ranges)
         .add(b.num_pairs);
 }
 

@@ -3,8 +3,8 @@
 //
 // 1. key each splat by the bits of its FP32 depth (culled splats last) and
 //    stable-radix-sort the splat indices: order[s] = splat of depth rank s;
-// 2. exclusive scan of the tile counts in rank order, then one (tile, s) pair
-//    per tile of each splat's rectangle, written in rank order;
+// 2. exclusive scan of the tile counts in rank order, then one (tile, splat)
+//    pair per tile of each splat's rectangle, written in rank order;
 // 3. stable radix sort of the pairs by tile id, then each tile's range.
 // Because step 2 emits pairs in depth-rank order and step 3 is stable, the
 // final order equals a lexicographic sort by (tile, depth bits, splat index).
@@ -291,38 +291,75 @@ __global__ __launch_bounds__(1024) void k_scan_bsums(unsigned long long* __restr
     if (t == 0) *total = (int64_t)s_carry;
 }
 
+// Pair emission for the splats of depth ranks [b * kScanTile, (b+1) * kScanTile):
+// each splat's block-local pair offset comes from a block scan of the tile
+// counts; then the block's pairs are written cooperatively and coalesced,
+// pair p finding its splat by binary search over the offsets in LDS.
 __global__ __launch_bounds__(kScanThreads) void k_emit_pairs(
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ count,
     const uint32_t* __restrict__ rect, int64_t K, const unsigned long long* __restrict__ bsum,
-    int64_t cap, int nx, uint32_t* __restrict__ tile_out, uint32_t* __restrict__ rank_out) {
+    int64_t cap, int nx, uint32_t* __restrict__ tile_out, uint32_t* __restrict__ splat_out) {
     __shared__ uint32_t s_tmp[kWaves];
+    __shared__ uint32_t s_off[kScanTile + 1];
+    __shared__ uint32_t s_k[kScanTile];
+    __shared__ uint32_t s_org[kScanTile];  // tx0 | ty0 << 16
+    __shared__ uint32_t s_w[kScanTile];    // rectangle width in tiles
     const int t = threadIdx.x;
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)t * kScanItems;
+    const int64_t sbase = (int64_t)blockIdx.x * kScanTile;
     uint32_t c[kScanItems], ks[kScanItems], sum = 0;
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
-        const int64_t s = base + i;
+        const int64_t s = sbase + (int64_t)t * kScanItems + i;
         ks[i] = s < K ? order[s] : 0u;
         c[i] = (s < K && ks[i] < (uint64_t)K) ? count[ks[i]] : 0u;
         sum += c[i];
     }
     uint32_t tot;
-    const uint32_t excl = block_excl_scan(sum, s_tmp, &tot);
-    int64_t off = (int64_t)bsum[blockIdx.x] + excl;
-#pragma unroll 1
+    uint32_t off = block_excl_scan(sum, s_tmp, &tot);
+#pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
-        if (c[i] == 0) continue;
-        const uint32_t k = ks[i];
-        const uint32_t r0 = rect[k], r1 = rect[K + k];
-        const int tx0 = r0 & 0xFFFF, tx1 = r0 >> 16, ty0 = r1 & 0xFFFF, ty1 = r1 >> 16;
-        const uint32_t s = (uint32_t)(base + i);
-        for (int ty = ty0; ty < ty1; ++ty) {
-            for (int tx = tx0; tx < tx1; ++tx) {
-                if (off < cap) {
-                    tile_out[off] = (uint32_t)(ty * nx + tx);
-                    rank_out[off] = s;
-                }
-                ++off;
+        const int j = t * kScanItems + i;
+        s_off[j] = off;
+        s_k[j] = ks[i];
+        uint32_t org = 0, w = 1;
+        if (c[i]) {
+            const uint32_t r0 = rect[ks[i]], r1 = rect[K + ks[i]];
+            org = (r0 & 0xFFFF) | ((r1 & 0xFFFF) << 16);
+            w = (r0 >> 16) - (r0 & 0xFFFF);
+        }
+        s_org[j] = org;
+        s_w[j] = w;
+        off += c[i];
+    }
+    if (t == 0) s_off[kScanTile] = tot;
+    __syncthreads();
+    const int64_t gbase = (int64_t)bsum[blockIdx.x];
+    // thread t writes pairs 4t..4t+3 of each 1024-pair window: one binary search
+    // per four pairs, then a forward walk; the four stores are contiguous
+    for (uint32_t p0 = 4u * t; p0 < tot; p0 += 4u * kScanThreads) {
+        int lo = 0, hi = kScanTile;  // last j with s_off[j] <= p0
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (s_off[mid] <= p0)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        int j = lo;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t p = p0 + q;
+            if (p >= tot) break;
+            while (s_off[j + 1] <= p) ++j;  // s_off[kScanTile] = tot > p ends the walk
+            const uint32_t k = s_k[j];
+            const uint32_t local = p - s_off[j];
+            const uint32_t org = s_org[j], w = s_w[j];
+            const uint32_t tx0 = org & 0xFFFF, ty0 = org >> 16;
+            const uint32_t dy = local / w;
+            const int64_t g = gbase + p;
+            if (g < cap) {
+                tile_out[g] = (ty0 + dy) * (uint32_t)nx + tx0 + (local - dy * w);
+                splat_out[g] = k;
             }
         }
     }
@@ -451,7 +488,7 @@ gdgs_status launch_bin_sort(const gdgs_proj& proj, int64_t K, int W, int H, cons
     // 3. stable sort of the pairs by tile, then the ranges
     const int tbits = bitlen((uint64_t)(T > 1 ? T - 1 : 1));
     s = radix_sort(ws.pkey[0], ws.pval[0], ws.pkey[1], ws.pval[1], bins.tile_of_pair,
-                   bins.rank_of_pair, bins.num_pairs, 0, bins.capacity, tbits, ws.hist,
+                   bins.splat_of_pair, bins.num_pairs, 0, bins.capacity, tbits, ws.hist,
                    ws.digit_tot, st);
     if (s != GDGS_OK) return s;
     hipLaunchKernelGGL(k_tile_ranges, dim3(2048), dim3(256), 0, st, bins.tile_of_pair,

@@ -25,8 +25,14 @@
 //    2*sweeps+2 into LDS; all sweeps run in LDS (temporal blocking: the valid
 //    region shrinks by one cell per half-sweep), so a pre-smoothing pass reads
 //    u and f once and writes u and the coarse right-hand side once; the
-//    post-smoothing pass adds the prolongated correction, smooths and on the
-//    finest grid also produces the residual norms for the stopping test;
+//    post-smoothing pass stages the coarse correction tile in LDS, adds its
+//    bilinear interpolation, smooths and on the finest grid also produces the
+//    residual and correction norms for the stopping test.  Each thread owns a
+//    fixed segment of one LDS row, so a red or black half-sweep is a strided
+//    loop with no per-cell index arithmetic.  Smoothing is FP32; residuals are
+//    evaluated in FP64 registers, because near convergence the FP32
+//    cancellation noise of f - (sum of neighbours - 4u) would otherwise be fed
+//    to the coarse grids as spurious corrections;
 //  * the coarse grids that fit in LDS together are run as a whole V-cycle by
 //    a single workgroup per channel (no launches per coarse level);
 //  * a finalize kernel evaluates eta = ||r||_inf / (8 ||w||_inf + ||b||_inf)
@@ -40,11 +46,16 @@ namespace {
 constexpr int kTX = 64;
 constexpr int kTY = 32;
 constexpr int kDivTX = 64;
-constexpr int kDivTY = 4;
+constexpr int kDivTY = 4;     // threads per block = kDivTX * kDivTY
+constexpr int kDivRows = 16;  // rows per block of the divergence kernel
 constexpr int kLdsThreads = 1024;
+constexpr int kCounters = 72; // finalize counters: [0] setup, [1 + cycle]
 
 struct LevelDev {
-    float* u;        // [3][n+2][pitch]
+    float* u;        // [3][n+2][pitch] iterate at the start and end of a cycle
+    float* ub;       // second buffer of the same shape: the pre-smoothing pass
+                     // reads u and writes ub, the post pass reads ub and writes
+                     // u, so no workgroup reads cells another one is updating
     const float* f;  // right-hand side, same layout
     float* fw;       // writable alias of f (coarse levels)
     int n, m, pitch;
@@ -61,22 +72,17 @@ __device__ __forceinline__ float diag_at(int gi, int gj, int n, int m, float ey,
     return d;
 }
 
-// Gauss-Seidel value (sum of the four neighbours - f) / diagonal, evaluated in
-// FP64 registers and rounded once: the FP32 operands are summed exactly enough
-// that the only rounding left is that of the stored result.
+// Gauss-Seidel value (sum of the four neighbours - f) / diagonal.
 __device__ __forceinline__ float gs_value(float a, float b, float c, float e, float f, float d) {
-    const double nb = ((double)a + (double)b) + ((double)c + (double)e);
-    const double x = nb - (double)f;
-    return (float)(d == 4.f ? 0.25 * x : x / (double)d);
+    const float x = ((a + b) + (c + e)) - f;
+    return d == 4.f ? 0.25f * x : x / d;
 }
 
-// Residual f - (neighbours - d u) in FP64: near convergence the terms are ~4|u|
-// while the residual is ~1e-7 |u|, and FP32 cancellation noise here would feed
-// random corrections into the coarse grids.
-__device__ __forceinline__ float res_value(float a, float b, float c, float e, float u, float f,
-                                           float d) {
+// Residual f - (neighbours - d u) in FP64 registers (see the file comment).
+__device__ __forceinline__ double res_value(float a, float b, float c, float e, float u, float f,
+                                            float d) {
     const double nb = ((double)a + (double)b) + ((double)c + (double)e);
-    return (float)((double)f - (nb - (double)d * (double)u));
+    return (double)f - (nb - (double)d * (double)u);
 }
 
 struct LdsPlan {
@@ -122,21 +128,36 @@ __device__ void block_reduce3(double& a, double& b, double& s, double* sh /*[3*n
     __syncthreads();
 }
 
+// Called by thread 0 of each of the three per-channel finalize blocks after it
+// wrote its channel's flag: the last of the three records whether all are done.
+__device__ __forceinline__ void publish_converged(int* counter, const int* done,
+                                                  gdgs_stats* stats) {
+    __threadfence();
+    if (atomicAdd(counter, 1) == 2) {
+        __threadfence();
+        const volatile int* d = done;
+        stats->converged = d[0] && d[1] && d[2];
+    }
+}
+
 // ---------------------------------------------------------------- setup
 // rho (from the gradients or given), the level-0 right-hand side f0, the
-// initial u0 (ring = boundary, interior 0), and per-block max|b|, sum b^2
-// with b = -rho + ring neighbours.
+// initial u0 (ring = boundary, interior 0 unless warm), and per-block
+// max|b|, sum b^2 with b = -rho + ring neighbours.
 __global__ __launch_bounds__(kDivTX* kDivTY) void k_div_init(
     const float* __restrict__ grad, const float* __restrict__ rho_in,
     const float* __restrict__ boundary, int H, int W, float* __restrict__ f0,
-    float* __restrict__ u0, double* __restrict__ bpart, int warm) {
+    float* __restrict__ u0, double* __restrict__ bpart, int* __restrict__ counters, int warm) {
     __shared__ double sh[3 * 4];
     const int c = blockIdx.z;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && c == 0 && threadIdx.x < kCounters)
+        counters[threadIdx.x] = 0;
     const int j = blockIdx.x * kDivTX + (threadIdx.x % kDivTX);
-    const int i = blockIdx.y * kDivTY + (threadIdx.x / kDivTX);
     const size_t HW = (size_t)H * W;
     double bmax = 0.0, bdum = 0.0, bss = 0.0;
-    if (i < H && j < W) {
+    for (int k = 0; k < kDivRows / kDivTY; ++k) {
+        const int i = blockIdx.y * kDivRows + k * kDivTY + (threadIdx.x / kDivTX);
+        if (i >= H || j >= W) continue;
         const size_t o = (size_t)c * HW + (size_t)i * W + j;
         const bool ring = (i == 0) || (i == H - 1) || (j == 0) || (j == W - 1);
         if (ring) {
@@ -162,8 +183,8 @@ __global__ __launch_bounds__(kDivTX* kDivTY) void k_div_init(
                 if (j == 1) b += g[(size_t)i * W];
                 if (j == W - 2) b += g[(size_t)i * W + W - 1];
             }
-            bmax = fabs(b);
-            bss = b * b;
+            bmax = fmax(bmax, fabs(b));
+            bss += b * b;
         }
     }
     block_reduce3(bmax, bdum, bss, sh);
@@ -175,56 +196,63 @@ __global__ __launch_bounds__(kDivTX* kDivTY) void k_div_init(
     }
 }
 
+// One block per channel.
 __global__ __launch_bounds__(256) void k_setup_finalize(const double* __restrict__ bpart, int nblk,
                                                         double* __restrict__ bnorm,
                                                         int* __restrict__ done,
+                                                        int* __restrict__ counters,
                                                         gdgs_stats* __restrict__ stats,
                                                         int warm) {
     __shared__ double sh[3 * 4];
-    for (int c = 0; c < 3; ++c) {
-        double mx = 0.0, dum = 0.0, ss = 0.0;
-        for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
-            mx = fmax(mx, bpart[((size_t)c * nblk + b) * 2]);
-            ss += bpart[((size_t)c * nblk + b) * 2 + 1];
-        }
-        block_reduce3(mx, dum, ss, sh);
-        if (threadIdx.x == 0) {
-            bnorm[2 * c] = mx;
-            bnorm[2 * c + 1] = sqrt(ss);
-            // zero right-hand side and zero initial interior: already exact
-            const int d = (mx == 0.0) && !warm;
-            done[c] = d;
-            stats->cycles[c] = 0;
-            stats->eta[c] = d ? 0.0 : 1.0;
-            stats->rel_res[c] = d ? 0.0 : 1.0;
-            stats->delta[c] = d ? 0.0 : 1.0;
-            stats->b_norm[c] = sqrt(ss);
-        }
+    const int c = blockIdx.x;
+    double mx = 0.0, dum = 0.0, ss = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+        mx = fmax(mx, bpart[((size_t)c * nblk + b) * 2]);
+        ss += bpart[((size_t)c * nblk + b) * 2 + 1];
     }
-    if (threadIdx.x == 0) stats->converged = done[0] && done[1] && done[2];
+    block_reduce3(mx, dum, ss, sh);
+    if (threadIdx.x == 0) {
+        bnorm[2 * c] = mx;
+        bnorm[2 * c + 1] = sqrt(ss);
+        // zero right-hand side and zero initial interior: already exact
+        const int d = (mx == 0.0) && !warm;
+        done[c] = d;
+        stats->cycles[c] = 0;
+        stats->eta[c] = d ? 0.0 : 1.0;
+        stats->rel_res[c] = d ? 0.0 : 1.0;
+        stats->delta[c] = d ? 0.0 : 1.0;
+        stats->b_norm[c] = sqrt(ss);
+        publish_converged(&counters[0], done, stats);
+    }
 }
 
 // ---------------------------------------------------------------- smoothing
 // Red-black Gauss-Seidel half-sweeps on an LDS region RX x RY whose cell (0,0)
 // is grid point (gi0, gj0); only interior grid points (1..n, 1..m) change.
+// Thread t owns LDS row 1 + t / TPR and every TPR-th cell of one colour in it.
 template <int RX, int RY>
-__device__ __forceinline__ void smooth_region(float* __restrict__ su, const float* __restrict__ sf,
-                                              int gi0, int gj0, int n, int m, float ey, float ex,
-                                              int color0, int sweeps) {
-    constexpr int HX = (RX - 1) / 2;
+__device__ __forceinline__ void smooth_rows(float* __restrict__ su, const float* __restrict__ sf,
+                                            int gi0, int gj0, int n, int m, float ey, float ex,
+                                            int color0, int sweeps) {
+    constexpr int NR = RY - 2;
+    constexpr int TPR = 256 / NR;
+    const int t = threadIdx.x;
+    const int r = 1 + t / TPR, sgm = t % TPR;
+    const int gi = gi0 + r;
+    const bool row_ok = (t < NR * TPR) && gi >= 1 && gi <= n;
+    const int qlo = max(1, 1 - gj0), qhi = min(RX - 2, m - gj0);
+    const int qm = m - gj0;  // local column of the last interior column
+    const float drow = 4.f + (gi == n ? ey : 0.f);
     for (int s = 0; s < sweeps; ++s) {
         for (int h = 0; h < 2; ++h) {
-            const int color = color0 ^ h;
-            for (int idx = threadIdx.x; idx < (RY - 2) * HX; idx += blockDim.x) {
-                const int r = 1 + idx / HX;
-                const int k = idx - (r - 1) * HX;
-                const int gi = gi0 + r;
-                const int q = 1 + 2 * k + ((color + gi + gj0 + 1) & 1);
-                const int gj = gj0 + q;
-                if (q <= RX - 2 && gi >= 1 && gi <= n && gj >= 1 && gj <= m) {
-                    const int o = r * RX + q;
-                    su[o] = gs_value(su[o - RX], su[o + RX], su[o - 1], su[o + 1], sf[o],
-                                     diag_at(gi, gj, n, m, ey, ex));
+            if (row_ok) {
+                const int color = color0 ^ h;
+                int q = qlo + ((color + gi + gj0 + qlo) & 1) + 2 * sgm;
+                float* row = su + r * RX;
+                const float* frow = sf + r * RX;
+                for (; q <= qhi; q += 2 * TPR) {
+                    const float d = q == qm ? drow + ex : drow;
+                    row[q] = gs_value(row[q - RX], row[q + RX], row[q - 1], row[q + 1], frow[q], d);
                 }
             }
             __syncthreads();
@@ -233,10 +261,11 @@ __device__ __forceinline__ void smooth_region(float* __restrict__ su, const floa
 }
 
 template <int RX, int RY>
-__device__ __forceinline__ void load_region(float* su, float* sf, const LevelDev& L, int c, int gi0,
-                                            int gj0, bool zero_guess) {
+__device__ __forceinline__ void load_region(float* su, float* sf, const LevelDev& L,
+                                            const float* usrc, int c, int gi0, int gj0,
+                                            bool zero_guess) {
     const int N = L.n + 2, M = L.m + 2;
-    const float* u = L.u + (size_t)c * L.cs;
+    const float* u = usrc + (size_t)c * L.cs;
     const float* f = L.f + (size_t)c * L.cs;
     for (int idx = threadIdx.x; idx < RY * RX; idx += blockDim.x) {
         const int r = idx / RX, q = idx - r * RX;
@@ -248,10 +277,10 @@ __device__ __forceinline__ void load_region(float* su, float* sf, const LevelDev
     }
 }
 
-// Pre-smoothing + residual + restriction to the next grid.
 // Thread t of a 256-thread block owns the tile cells t, t + 256, ...
 constexpr int kCellsPerThread = kTX * kTY / 256;
 
+// Pre-smoothing + residual + restriction to the next grid.
 template <int NU, bool DELTA>
 __global__ __launch_bounds__(256) void k_mg_pre(LevelDev L, LevelDev C, int zero_guess,
                                                 const int* __restrict__ done,
@@ -264,7 +293,7 @@ __global__ __launch_bounds__(256) void k_mg_pre(LevelDev L, LevelDev C, int zero
     const int c = blockIdx.z;
     if (done[c]) return;
     const int gi0 = blockIdx.y * kTY - HALO, gj0 = blockIdx.x * kTX - HALO;
-    load_region<RX, RY>(su, sf, L, c, gi0, gj0, zero_guess != 0);
+    load_region<RX, RY>(su, sf, L, L.u, c, gi0, gj0, zero_guess != 0);
     __syncthreads();
     float before[kCellsPerThread];
     if (DELTA) {
@@ -273,10 +302,11 @@ __global__ __launch_bounds__(256) void k_mg_pre(LevelDev L, LevelDev C, int zero
             const int idx = threadIdx.x + 256 * k;
             before[k] = su[(HALO + idx / kTX) * RX + HALO + idx % kTX];
         }
+        __syncthreads();  // every snapshot is taken before any cell changes
     }
-    smooth_region<RX, RY>(su, sf, gi0, gj0, L.n, L.m, L.ey, L.ex, 0, NU);
+    smooth_rows<RX, RY>(su, sf, gi0, gj0, L.n, L.m, L.ey, L.ex, 0, NU);
     const int N = L.n + 2, M = L.m + 2;
-    float* u = L.u + (size_t)c * L.cs;
+    float* u = L.ub + (size_t)c * L.cs;
     double dmax = 0.0;
 #pragma unroll
     for (int k = 0; k < kCellsPerThread; ++k) {
@@ -290,25 +320,27 @@ __global__ __launch_bounds__(256) void k_mg_pre(LevelDev L, LevelDev C, int zero
                 dmax = fmax(dmax, fabs((double)v - (double)before[k]));
         }
     }
-    if (DELTA) {
-        double d1 = 0.0, d2 = 0.0;
-        block_reduce3(dmax, d1, d2, sh);
-        if (threadIdx.x == 0) {
-            const int nblk = gridDim.x * gridDim.y;
-            part[((size_t)c * nblk + blockIdx.y * gridDim.x + blockIdx.x) * 5 + 3] = dmax;
+    // residual on rows/cols [HALO-1, HALO+T-1], zero off the interior; thread t
+    // owns every TPR-th cell of one row
+    {
+        constexpr int ZR = kTY + 1, ZC = kTX + 1;
+        constexpr int TPR = 256 / ZR;
+        const int t = threadIdx.x;
+        if (t < ZR * TPR) {
+            const int r = HALO - 1 + t / TPR;
+            const int gi = gi0 + r;
+            const bool row_in = gi >= 1 && gi <= L.n;
+            const float drow = 4.f + (gi == L.n ? L.ey : 0.f);
+            for (int q = HALO - 1 + t % TPR; q < HALO - 1 + ZC; q += TPR) {
+                const int gj = gj0 + q;
+                const int o = r * RX + q;
+                float rv = 0.f;
+                if (row_in && gj >= 1 && gj <= L.m)
+                    rv = (float)res_value(su[o - RX], su[o + RX], su[o - 1], su[o + 1], su[o],
+                                          sf[o], gj == L.m ? drow + L.ex : drow);
+                sf[o] = rv;
+            }
         }
-    }
-    // residual on rows/cols [HALO-1, HALO+T-1], zero off the interior
-    constexpr int ZR = kTY + 1, ZC = kTX + 1;
-    for (int idx = threadIdx.x; idx < ZR * ZC; idx += blockDim.x) {
-        const int r = HALO - 1 + idx / ZC, q = HALO - 1 + idx % ZC;
-        const int gi = gi0 + r, gj = gj0 + q;
-        const int o = r * RX + q;
-        float rv = 0.f;
-        if (gi >= 1 && gi <= L.n && gj >= 1 && gj <= L.m)
-            rv = res_value(su[o - RX], su[o + RX], su[o - 1], su[o + 1], su[o], sf[o],
-                           diag_at(gi, gj, L.n, L.m, L.ey, L.ex));
-        sf[o] = rv;
     }
     __syncthreads();
     const int I0 = blockIdx.y * (kTY / 2), J0 = blockIdx.x * (kTX / 2);
@@ -322,22 +354,46 @@ __global__ __launch_bounds__(256) void k_mg_pre(LevelDev L, LevelDev C, int zero
             fc[(size_t)I * C.pitch + J] = 0.25f * v;
         }
     }
+    if (DELTA) {
+        double d1 = 0.0, d2 = 0.0;
+        block_reduce3(dmax, d1, d2, sh);
+        if (threadIdx.x == 0) {
+            const int nblk = gridDim.x * gridDim.y;
+            part[((size_t)c * nblk + blockIdx.y * gridDim.x + blockIdx.x) * 5 + 3] = dmax;
+        }
+    }
 }
 
-// Prolongation + correction + post-smoothing (+ residual norms on the finest grid).
+// Prolongation + correction + post-smoothing (+ residual and correction norms
+// on the finest grid).
 template <int NU, bool NORM>
 __global__ __launch_bounds__(256) void k_mg_post(LevelDev L, LevelDev C,
                                                  const int* __restrict__ done,
                                                  double* __restrict__ part) {
     constexpr int HALO = 2 * NU + 2;
     constexpr int RX = kTX + 2 * HALO, RY = kTY + 2 * HALO;
+    constexpr int CX = RX / 2 + 2, CY = RY / 2 + 2;  // staged coarse tile
     __shared__ float su[RY * RX];
     __shared__ float sf[RY * RX];
+    __shared__ float se[CY * CX];
     __shared__ double sh[3 * 4];
     const int c = blockIdx.z;
     if (done[c]) return;
     const int gi0 = blockIdx.y * kTY - HALO, gj0 = blockIdx.x * kTX - HALO;
-    load_region<RX, RY>(su, sf, L, c, gi0, gj0, false);
+    load_region<RX, RY>(su, sf, L, L.ub, c, gi0, gj0, false);
+    // coarse rows (gi0 >> 1) .. ((gi0 + RY - 1) >> 1) + 1, columns alike
+    const int ci0 = gi0 >> 1, cj0 = gj0 >> 1;
+    {
+        const float* e = C.u + (size_t)c * C.cs;
+        const int NC = C.n + 2, MC = C.m + 2;
+        for (int idx = threadIdx.x; idx < CY * CX; idx += blockDim.x) {
+            const int a = idx / CX, b = idx - a * CX;
+            const int I = ci0 + a, J = cj0 + b;
+            se[idx] = ((unsigned)I < (unsigned)NC && (unsigned)J < (unsigned)MC)
+                          ? e[(size_t)I * C.pitch + J]
+                          : 0.f;
+        }
+    }
     __syncthreads();
     float before[kCellsPerThread];
     if (NORM) {
@@ -346,43 +402,43 @@ __global__ __launch_bounds__(256) void k_mg_post(LevelDev L, LevelDev C,
             const int idx = threadIdx.x + 256 * k;
             before[k] = su[(HALO + idx / kTX) * RX + HALO + idx % kTX];
         }
+        __syncthreads();  // every snapshot is taken before any cell changes
     }
-    const float* e = C.u + (size_t)c * C.cs;
     for (int idx = threadIdx.x; idx < RY * RX; idx += blockDim.x) {
         const int r = idx / RX, q = idx - r * RX;
         const int gi = gi0 + r, gj = gj0 + q;
         if (gi >= 1 && gi <= L.n && gj >= 1 && gj <= L.m) {
             const int oi = gi & 1, oj = gj & 1;
             const int I0 = gi >> 1, J0 = gj >> 1;
-            const float* p = e + (size_t)I0 * C.pitch + J0;
+            const float* p = se + (I0 - ci0) * CX + (J0 - cj0);
             float v = p[0];
-            if (oi) v += p[C.pitch];
+            if (oi) v += p[CX];
             if (oj) v += p[1];
-            if (oi & oj) v += p[C.pitch + 1];
+            if (oi & oj) v += p[CX + 1];
             const float fy = oi ? (I0 == C.n ? C.wy : 0.5f) : 1.f;
             const float fx = oj ? (J0 == C.m ? C.wx : 0.5f) : 1.f;
             su[idx] += fy * fx * v;
         }
     }
     __syncthreads();
-    smooth_region<RX, RY>(su, sf, gi0, gj0, L.n, L.m, L.ey, L.ex, 1, NU);
+    smooth_rows<RX, RY>(su, sf, gi0, gj0, L.n, L.m, L.ey, L.ex, 1, NU);
     float* u = L.u + (size_t)c * L.cs;
+    const int N = L.n + 2, M = L.m + 2;
     double rmax = 0.0, umax = 0.0, rss = 0.0, dmax = 0.0;
 #pragma unroll
     for (int k = 0; k < kCellsPerThread; ++k) {
         const int idx = threadIdx.x + 256 * k;
         const int r = HALO + idx / kTX, q = HALO + idx % kTX;
         const int gi = gi0 + r, gj = gj0 + q;
+        const int o = r * RX + q;
+        // ring cells too: they keep the boundary (or zero) values in both buffers
+        if (gi < N && gj < M) u[(size_t)gi * L.pitch + gj] = su[o];
         if (gi >= 1 && gi <= L.n && gj >= 1 && gj <= L.m) {
-            const int o = r * RX + q;
             const float uv = su[o];
-            u[(size_t)gi * L.pitch + gj] = uv;
             if (NORM) {
                 dmax = fmax(dmax, fabs((double)uv - (double)before[k]));
-                const double rv = (double)sf[o] - ((double)su[o - RX] + (double)su[o + RX] +
-                                                   (double)su[o - 1] + (double)su[o + 1] -
-                                                   (double)diag_at(gi, gj, L.n, L.m, L.ey, L.ex) *
-                                                       (double)uv);
+                const double rv = res_value(su[o - RX], su[o + RX], su[o - 1], su[o + 1], uv,
+                                            sf[o], diag_at(gi, gj, L.n, L.m, L.ey, L.ex));
                 rmax = fmax(rmax, fabs(rv));
                 umax = fmax(umax, fabs((double)uv));
                 rss += rv * rv;
@@ -433,10 +489,9 @@ __device__ __forceinline__ float lds_res(const float* U, const float* F, int n, 
                                          float ex, int i, int j) {
     if (i < 1 || i > n || j < 1 || j > m) return 0.f;
     const int M = m + 2, o = i * M + j;
-    return res_value(U[o - M], U[o + M], U[o - 1], U[o + 1], U[o], F[o],
-                     diag_at(i, j, n, m, ey, ex));
+    return (float)res_value(U[o - M], U[o + M], U[o - 1], U[o + 1], U[o], F[o],
+                            diag_at(i, j, n, m, ey, ex));
 }
-
 __global__ __launch_bounds__(kLdsThreads) void k_mg_lds(LdsPlan P, const int* __restrict__ done,
                                                         double* __restrict__ part) {
     extern __shared__ float lds[];
@@ -528,11 +583,8 @@ __global__ __launch_bounds__(kLdsThreads) void k_mg_lds(LdsPlan P, const int* __
                 dmax = fmax(dmax, fabs((double)U[idx] - (double)gu[go]));
             gu[go] = U[idx];
             if (lc == 0 && i >= 1 && i <= n && j >= 1 && j <= m) {
-                const double rv = (double)F[idx] - ((double)U[idx - M] + (double)U[idx + M] +
-                                                    (double)U[idx - 1] + (double)U[idx + 1] -
-                                                    (double)diag_at(i, j, n, m, P.ey[0],
-                                                                    P.ex[0]) *
-                                                        (double)U[idx]);
+                const double rv = res_value(U[idx - M], U[idx + M], U[idx - 1], U[idx + 1],
+                                            U[idx], F[idx], diag_at(i, j, n, m, P.ey[0], P.ex[0]));
                 rmax = fmax(rmax, fabs(rv));
                 umax = fmax(umax, fabs((double)U[idx]));
                 rss += rv * rv;
@@ -553,14 +605,16 @@ __global__ __launch_bounds__(kLdsThreads) void k_mg_lds(LdsPlan P, const int* __
     }
 }
 
+// One block per channel.
 __global__ __launch_bounds__(256) void k_cycle_finalize(const double* __restrict__ part, int nblk,
                                                         const double* __restrict__ bnorm,
                                                         int* __restrict__ done,
+                                                        int* __restrict__ counters,
                                                         gdgs_stats* __restrict__ stats, int cycle,
                                                         double tol) {
     __shared__ double sh[3 * 4];
-    for (int c = 0; c < 3; ++c) {
-        if (done[c]) continue;  // uniform: finished before this cycle
+    const int c = blockIdx.x;
+    if (!done[c]) {  // uniform: finished before this cycle otherwise
         double rmax = 0.0, umax = 0.0, rss = 0.0, dpre = 0.0, dpost = 0.0;
         for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
             const double* p = part + ((size_t)c * nblk + b) * 5;
@@ -584,9 +638,8 @@ __global__ __launch_bounds__(256) void k_cycle_finalize(const double* __restrict
             stats->cycles[c] = cycle + 1;
             if (rel <= tol) done[c] = 1;
         }
-        __syncthreads();
     }
-    if (threadIdx.x == 0) stats->converged = done[0] && done[1] && done[2];
+    if (threadIdx.x == 0) publish_converged(&counters[1 + cycle], done, stats);
 }
 
 // ---------------------------------------------------------------- divergence adjoint
@@ -715,9 +768,11 @@ gdgs_status mg_plan(int W, int H, const gdgs_mg_params* mg, MgPlan* plan) {
     if (q.coarse_sweeps > 0) {
         p.coarse_sweeps = q.coarse_sweeps;
     } else {
-        // enough SOR sweeps for a 1e-6 error reduction, (omega - 1)^k <= 1e-6
+        // SOR sweeps for a 1e-3 error reduction, (omega - 1)^k <= 1e-3: the
+        // coarsest correction only has to be small against the V-cycle's own
+        // contraction (about 0.1)
         const double rho = p.omega - 1.0;
-        int k = rho > 0.0 ? (int)ceil(log(1e-6) / log(rho)) : 4;
+        int k = rho > 0.0 ? (int)ceil(log(1e-3) / log(rho)) : 4;
         if (k < 4) k = 4;
         if (k > 4096) k = 4096;
         p.coarse_sweeps = k;
@@ -729,12 +784,15 @@ gdgs_status mg_plan(int W, int H, const gdgs_mg_params* mg, MgPlan* plan) {
 namespace {
 struct PoissonWs {
     float* f0;
+    float* u0b;  // second buffer of the finest grid
     float* u[kMaxLevels];
+    float* ub[kMaxLevels];
     float* f[kMaxLevels];
     double* part;
     double* bpart;
     double* bnorm;
     int* done;
+    int* counters;
     gdgs_stats* stats;
 };
 
@@ -743,21 +801,26 @@ int norm_blocks(const MgPlan& p) {
     return ((p.m[0] + 2 + kTX - 1) / kTX) * ((p.n[0] + 2 + kTY - 1) / kTY);
 }
 
-int div_blocks(int W, int H) { return ((W + kDivTX - 1) / kDivTX) * ((H + kDivTY - 1) / kDivTY); }
+int div_blocks(int W, int H) {
+    return ((W + kDivTX - 1) / kDivTX) * ((H + kDivRows - 1) / kDivRows);
+}
 
 size_t poisson_layout(const MgPlan& p, int W, int H, void* ws, PoissonWs* out) {
     Carver c(ws);
     PoissonWs w{};
     w.f0 = c.take<float>((size_t)3 * H * W);
+    w.u0b = c.take<float>((size_t)3 * H * W);
     for (int l = 1; l < p.levels; ++l) {
         const size_t cells = (size_t)(p.n[l] + 2) * p.pitch[l];
         w.u[l] = c.take<float>(3 * cells);
+        w.ub[l] = c.take<float>(3 * cells);
         w.f[l] = c.take<float>(3 * cells);
     }
     w.part = c.take<double>((size_t)3 * 5 * norm_blocks(p));
     w.bpart = c.take<double>((size_t)3 * 2 * div_blocks(W, H));
     w.bnorm = c.take<double>(6);
     w.done = c.take<int>(4);
+    w.counters = c.take<int>(kCounters);
     w.stats = c.take<gdgs_stats>(1);
     if (out) *out = w;
     return c.off + 256;
@@ -777,6 +840,7 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
     const long long cs0 = (long long)H * W;
     LevelDev lev[kMaxLevels];
     lev[0].u = u;
+    lev[0].ub = w.u0b;
     lev[0].f = grad ? w.f0 : rho;
     lev[0].fw = nullptr;
     lev[0].n = p.n[0];
@@ -787,6 +851,7 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
     lev[0].wy = lev[0].wx = 0.5f;
     for (int l = 1; l < p.levels; ++l) {
         lev[l].u = w.u[l];
+        lev[l].ub = w.ub[l];
         lev[l].f = w.f[l];
         lev[l].fw = w.f[l];
         lev[l].n = p.n[l];
@@ -800,11 +865,11 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
     }
     const int nblk_div = div_blocks(W, H);
     hipLaunchKernelGGL(k_div_init,
-                       dim3((W + kDivTX - 1) / kDivTX, (H + kDivTY - 1) / kDivTY, 3),
+                       dim3((W + kDivTX - 1) / kDivTX, (H + kDivRows - 1) / kDivRows, 3),
                        dim3(kDivTX * kDivTY), 0, st, grad, grad ? nullptr : rho, boundary, H, W,
-                       grad ? w.f0 : nullptr, u, w.bpart, p.warm ? 1 : 0);
-    hipLaunchKernelGGL(k_setup_finalize, dim3(1), dim3(256), 0, st, w.bpart, nblk_div, w.bnorm,
-                       w.done, sd, p.warm ? 1 : 0);
+                       grad ? w.f0 : nullptr, u, w.bpart, w.counters, p.warm ? 1 : 0);
+    hipLaunchKernelGGL(k_setup_finalize, dim3(3), dim3(256), 0, st, w.bpart, nblk_div, w.bnorm,
+                       w.done, w.counters, sd, p.warm ? 1 : 0);
     GDGS_LAUNCH_CHECK();
 
     LdsPlan lp;
@@ -845,8 +910,8 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
             else
                 launch_post<2>(lev[l], lev[l + 1], l == 0, w.done, w.part, st);
         }
-        hipLaunchKernelGGL(k_cycle_finalize, dim3(1), dim3(256), 0, st, w.part, nblk, w.bnorm,
-                           w.done, sd, cyc, p.tol);
+        hipLaunchKernelGGL(k_cycle_finalize, dim3(3), dim3(256), 0, st, w.part, nblk, w.bnorm,
+                           w.done, w.counters, sd, cyc, p.tol);
         GDGS_LAUNCH_CHECK();
     }
     return GDGS_OK;

@@ -2,10 +2,13 @@
 // Eq. 11, applied to the projected field in Sec. 2.2 "Projection", Eq. 20) and
 // its reverse-mode derivative.
 //
-// Forward: one workgroup per 16x16 screen tile, one thread per pixel.  The
-// tile's pairs (already in front-to-back order) are consumed in batches of
-// 256: every thread fetches one 64-byte splat record into LDS, then all
-// threads walk the batch reading the records as LDS broadcasts.  A pixel stops
+// Forward: a transpose kernel packs each splat into a 64-byte record (read
+// with three float4 loads, coalesced by splat index); then one workgroup per
+// 16x16 screen tile, one thread per pixel.  The tile's pairs (already in
+// front-to-back order) are consumed in batches of 256: every thread fetches
+// one record into LDS, then all threads walk the batch reading the records as
+// LDS broadcasts.  A wave covers 4 pixel rows of the tile and skips, as a
+// whole, every splat whose support rows miss them.  A pixel stops
 // accumulating once its transmittance is below 1e-7; the tile stops when all
 // its pixels have.  Splat means are stored relative to the pixel origin of
 // the splat's tile rectangle, so d = p - mu is computed from small numbers.
@@ -34,86 +37,144 @@ __global__ void k_inv_order(const uint32_t* __restrict__ order, int64_t K,
     }
 }
 
-// Record of splat k at its depth rank inv[k].
-__global__ __launch_bounds__(256) void k_gather_records(
-    const uint32_t* __restrict__ inv, gdgs_proj proj, const float* __restrict__ opacity,
-    const float* __restrict__ value, int64_t K, float4* __restrict__ rec) {
+// Record of splat k: (mx, my, ox, oy), (a, 2b, c, alpha), (v0..v3),
+// (v4, v5, ylo, yhi).  [ylo, yhi] bounds the image rows of the support with a
+// small safety margin (+-inf if the FP32 conic is not positive definite).
+__global__ __launch_bounds__(256) void k_build_records(gdgs_proj proj,
+                                                       const float* __restrict__ opacity,
+                                                       const float* __restrict__ value, int64_t K,
+                                                       float4* __restrict__ rec) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= K) return;
     if (proj.count[k] == 0) return;
-    const uint32_t s = inv[k];
-    if (s >= (uint64_t)K) return;
     const uint32_t r0 = proj.rect[k], r1 = proj.rect[K + k];
-    float4* r = rec + 4 * (size_t)s;
-    r[0] = make_float4(proj.mean2d[k], proj.mean2d[K + k], (float)(kTile * (int)(r0 & 0xFFFF)),
-                       (float)(kTile * (int)(r1 & 0xFFFF)));
-    r[1] = make_float4(proj.conic[k], 2.f * proj.conic[K + k], proj.conic[2 * K + k], opacity[k]);
+    const float ox = (float)(kTile * (int)(r0 & 0xFFFF)), oy = (float)(kTile * (int)(r1 & 0xFFFF));
+    const float mx = proj.mean2d[k], my = proj.mean2d[K + k];
+    const float ca = proj.conic[k], cb = proj.conic[K + k], cc = proj.conic[2 * K + k];
+    const float det = ca * cc - cb * cb;
+    float ylo = -INFINITY, yhi = INFINITY;
+    if (det > 0.f && ca > 0.f) {
+        const float ry = sqrtf(kEcut * (ca / det)) * 1.0001f + 1e-3f;
+        ylo = oy + my - ry;
+        yhi = oy + my + ry;
+    }
+    float4* r = rec + 4 * (size_t)k;
+    r[0] = make_float4(mx, my, ox, oy);
+    r[1] = make_float4(ca, 2.f * cb, cc, opacity[k]);
     r[2] = make_float4(value[k], value[K + k], value[2 * K + k], value[3 * K + k]);
-    r[3] = make_float4(value[4 * K + k], value[5 * K + k], 0.f, 0.f);
+    r[3] = make_float4(value[4 * K + k], value[5 * K + k], ylo, yhi);
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const int lane = __lane_id();
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Row-band mask of a record: bit b set if the support rows [ylo, yhi] meet
+// the pixel-centre rows of band b (rows 4b..4b+3 of the tile).
+__device__ __forceinline__ uint32_t band_mask(float ylo, float yhi, int ty) {
+    uint32_t m = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const float lo = (float)(ty * kTile + 4 * b) + 0.5f, hi = lo + 3.f;
+        if (!(yhi < lo || ylo > hi)) m |= 1u << b;
+    }
+    return m;
+}
+
+// Composite one splat record into a pixel (the Eq. 20 update).
+__device__ __forceinline__ void blend(const float4& r0, const float4& r1, const float4& r2,
+                                      const float4& r3, float fpx, float fpy, float& Tr,
+                                      float (&acc)[6]) {
+    const float dx = (fpx - r0.z) - r0.x;
+    const float dy = (fpy - r0.w) - r0.y;
+    const float E = dx * (r1.x * dx + r1.y * dy) + r1.z * dy * dy;
+    if (E <= kEcut && Tr >= kTmin) {
+        const float al = r1.w * __expf(-E);
+        const float w = al * Tr;
+        acc[0] += r2.x * w;
+        acc[1] += r2.y * w;
+        acc[2] += r2.z * w;
+        acc[3] += r2.w * w;
+        acc[4] += r3.x * w;
+        acc[5] += r3.y * w;
+        Tr = Tr - al * Tr;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_raster_fwd(const float4* __restrict__ rec,
-                                                    const uint32_t* __restrict__ rank_of_pair,
+                                                    const uint32_t* __restrict__ splat_of_pair,
                                                     const uint32_t* __restrict__ ranges, int T,
                                                     int nx, int W, int H, int64_t K,
                                                     float* __restrict__ grad) {
-    __shared__ float4 s_r0[kBatch], s_r1[kBatch], s_r2[kBatch], s_r3[kBatch];
+    // slot kBatch holds an inert record (alpha 0) used to pad the wave lists
+    __shared__ float4 s_r0[kBatch + 1], s_r1[kBatch + 1], s_r2[kBatch + 1], s_r3[kBatch + 1];
+    __shared__ uint32_t s_mask[kBatch];
+    __shared__ int s_list[4][kBatch + 4];
     const int tile = blockIdx.x;
     const int tx = tile % nx, ty = tile / nx;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = __lane_id(), wv = t >> 6;
     const int px = tx * kTile + (t & 15), py = ty * kTile + (t >> 4);
     const bool inside = px < W && py < H;
     const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+    const uint64_t lt = lanemask_lt();
     const uint32_t start = ranges[tile], end = ranges[T + tile];
+    if (t == 0) {
+        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+        s_r0[kBatch] = z;
+        s_r1[kBatch] = z;
+        s_r2[kBatch] = z;
+        s_r3[kBatch] = z;
+    }
     float Tr = inside ? 1.f : 0.f;
-    float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f, acc4 = 0.f, acc5 = 0.f;
+    float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     for (uint32_t b0 = start; b0 < end; b0 += kBatch) {
         const int n = (int)min((uint32_t)kBatch, end - b0);
         __syncthreads();
         if (t < n) {
-            const uint32_t s = rank_of_pair[b0 + t];
+            const uint32_t s = splat_of_pair[b0 + t];
+            uint32_t m = 0;
             if (s < (uint64_t)K) {
                 const float4* r = rec + 4 * (size_t)s;
+                const float4 r3 = r[3];
                 s_r0[t] = r[0];
                 s_r1[t] = r[1];
                 s_r2[t] = r[2];
-                s_r3[t] = r[3];
-            } else {  // never produced by the binning; contributes nothing
-                s_r0[t] = make_float4(0.f, 0.f, 0.f, 0.f);
-                s_r1[t] = make_float4(0.f, 0.f, 0.f, 0.f);
-                s_r2[t] = make_float4(0.f, 0.f, 0.f, 0.f);
-                s_r3[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+                s_r3[t] = r3;
+                m = band_mask(r3.z, r3.w, ty);
             }
+            s_mask[t] = m;
         }
         __syncthreads();
-        for (int j = 0; j < n; ++j) {
-            const float4 r0 = s_r0[j], r1 = s_r1[j];
-            const float dx = (fpx - r0.z) - r0.x;
-            const float dy = (fpy - r0.w) - r0.y;
-            const float E = dx * (r1.x * dx + r1.y * dy) + r1.z * dy * dy;
-            if (E <= kEcut && Tr >= kTmin) {
-                const float4 r2 = s_r2[j], r3 = s_r3[j];
-                const float al = r1.w * __expf(-E);
-                const float w = al * Tr;
-                acc0 += r2.x * w;
-                acc1 += r2.y * w;
-                acc2 += r2.z * w;
-                acc3 += r2.w * w;
-                acc4 += r3.x * w;
-                acc5 += r3.y * w;
-                Tr = Tr - al * Tr;
-            }
+        // this wave's list of batch entries whose support meets its rows
+        int cnt = 0;
+        for (int c0 = 0; c0 < n; c0 += 64) {
+            const int e = c0 + lane;
+            const bool hit = e < n && ((s_mask[e] >> wv) & 1u);
+            const uint64_t m = __ballot(hit);
+            if (hit) s_list[wv][cnt + __popcll(m & lt)] = e;
+            cnt += __popcll(m);
+        }
+        const int cnt4 = (cnt + 3) & ~3;
+        if (lane < cnt4 - cnt) s_list[wv][cnt + lane] = kBatch;
+        __builtin_amdgcn_wave_barrier();
+        for (int i = 0; i < cnt4; i += 4) {
+            const int4 jj = *reinterpret_cast<const int4*>(&s_list[wv][i]);
+            const float4 a0 = s_r0[jj.x], a1 = s_r0[jj.y], a2 = s_r0[jj.z], a3 = s_r0[jj.w];
+            const float4 c0 = s_r1[jj.x], c1 = s_r1[jj.y], c2 = s_r1[jj.z], c3 = s_r1[jj.w];
+            const float4 v0 = s_r2[jj.x], v1 = s_r2[jj.y], v2 = s_r2[jj.z], v3 = s_r2[jj.w];
+            const float4 e0 = s_r3[jj.x], e1 = s_r3[jj.y], e2 = s_r3[jj.z], e3 = s_r3[jj.w];
+            blend(a0, c0, v0, e0, fpx, fpy, Tr, acc);
+            blend(a1, c1, v1, e1, fpx, fpy, Tr, acc);
+            blend(a2, c2, v2, e2, fpx, fpy, Tr, acc);
+            blend(a3, c3, v3, e3, fpx, fpy, Tr, acc);
         }
         if (__syncthreads_count(Tr >= kTmin) == 0) break;
     }
     if (inside) {
         const size_t HW = (size_t)H * W, p = (size_t)py * W + px;
-        grad[p] = acc0;
-        grad[HW + p] = acc1;
-        grad[2 * HW + p] = acc2;
-        grad[3 * HW + p] = acc3;
-        grad[4 * HW + p] = acc4;
-        grad[5 * HW + p] = acc5;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) grad[m * HW + p] = acc[m];
     }
 }
 
@@ -128,7 +189,7 @@ constexpr int kNP = 12;
 constexpr int kBatchB = 128;
 
 __global__ __launch_bounds__(256) void k_raster_bwd(const float4* __restrict__ rec,
-                                                    const uint32_t* __restrict__ rank_of_pair,
+                                                    const uint32_t* __restrict__ splat_of_pair,
                                                     const uint32_t* __restrict__ ranges, int T,
                                                     int nx, int W, int H, int64_t K,
                                                     const float* __restrict__ grad,
@@ -143,6 +204,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(const float4* __restrict__ r
     const bool inside = px < W && py < H;
     const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
     const size_t HW = (size_t)H * W, pp = (size_t)py * W + px;
+    const float wy_lo = (float)(ty * kTile + 4 * wv) + 0.5f, wy_hi = wy_lo + 3.f;
     float out[6], del[6];
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
@@ -156,7 +218,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(const float4* __restrict__ r
         const int n = (int)min((uint32_t)kBatchB, end - b0);
         __syncthreads();
         if (t < n) {
-            const uint32_t s = rank_of_pair[b0 + t];
+            const uint32_t s = splat_of_pair[b0 + t];
             if (s < (uint64_t)K) {
                 const float4* r = rec + 4 * (size_t)s;
                 s_r0[t] = r[0];
@@ -172,6 +234,14 @@ __global__ __launch_bounds__(256) void k_raster_bwd(const float4* __restrict__ r
         }
         __syncthreads();
         for (int j = 0; j < n; ++j) {
+            const float4 r3 = s_r3[j];
+            if (r3.w < wy_lo || r3.z > wy_hi) {  // wave-uniform: rows missed
+                if (lane == 0) {
+#pragma unroll
+                    for (int q = 0; q < kNP; ++q) s_p[wv][q][j] = 0.f;
+                }
+                continue;
+            }
             const float4 r0 = s_r0[j], r1 = s_r1[j];
             const float dx = (fpx - r0.z) - r0.x;
             const float dy = (fpy - r0.w) - r0.y;
@@ -181,7 +251,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(const float4* __restrict__ r
 #pragma unroll
             for (int q = 0; q < kNP; ++q) g[q] = 0.f;
             if (on) {
-                const float4 r2 = s_r2[j], r3 = s_r3[j];
+                const float4 r2 = s_r2[j];
                 const float G = __expf(-E);
                 const float al = r1.w * G;
                 const float w = al * Tr;
@@ -235,7 +305,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(const float4* __restrict__ r
 
 // Per splat: sum its pair records over the tiles of its rectangle.
 __global__ __launch_bounds__(256) void k_seg_reduce(
-    gdgs_proj proj, const uint32_t* __restrict__ inv, const uint32_t* __restrict__ rank_of_pair,
+    gdgs_proj proj, const uint32_t* __restrict__ inv, const uint32_t* __restrict__ splat_of_pair,
     const uint32_t* __restrict__ ranges, int T, int nx, int64_t K, const float* __restrict__ part,
     float* __restrict__ dmean2d, float* __restrict__ dconic, float* __restrict__ dopacity,
     float* __restrict__ dvalue) {
@@ -252,14 +322,16 @@ __global__ __launch_bounds__(256) void k_seg_reduce(
             for (int tx = tx0; tx < tx1; ++tx) {
                 const int tl = ty * nx + tx;
                 uint32_t lo = ranges[tl], hi = ranges[T + tl];
+                // the tile's pairs are in depth-rank order: search rank s
                 while (lo < hi) {
                     const uint32_t mid = lo + ((hi - lo) >> 1);
-                    if (rank_of_pair[mid] < s)
+                    const uint32_t km = splat_of_pair[mid];
+                    if ((km < (uint64_t)K ? inv[km] : 0xFFFFFFFFu) < s)
                         lo = mid + 1;
                     else
                         hi = mid;
                 }
-                if (lo < ranges[T + tl] && rank_of_pair[lo] == s) {
+                if (lo < ranges[T + tl] && splat_of_pair[lo] == (uint32_t)k) {
                     const float* p = part + (size_t)lo * kNP;
 #pragma unroll
                     for (int q = 0; q < kNP; ++q) acc[q] += p[q];
@@ -281,7 +353,6 @@ __global__ __launch_bounds__(256) void k_seg_reduce(
 
 size_t raster_ws_bytes(int64_t K) {
     Carver c(nullptr);
-    c.take<uint32_t>(K > 0 ? K : 1);
     c.take<float4>(4 * (size_t)(K > 0 ? K : 1));
     return c.off + 256;
 }
@@ -290,16 +361,14 @@ gdgs_status launch_raster(const gdgs_proj& proj, const float* opacity, const flo
                           int64_t K, const gdgs_bins& bins, int W, int H, float* grad, void* ws,
                           hipStream_t st) {
     Carver c(ws);
-    uint32_t* inv = c.take<uint32_t>(K > 0 ? K : 1);
     float4* rec = c.take<float4>(4 * (size_t)(K > 0 ? K : 1));
     const int nx = tiles_x(W), T = nx * tiles_y(H);
     if (K > 0) {
         const unsigned g = (unsigned)((K + 255) / 256);
-        hipLaunchKernelGGL(k_inv_order, dim3(g), dim3(256), 0, st, bins.order, K, inv);
-        hipLaunchKernelGGL(k_gather_records, dim3(g), dim3(256), 0, st, inv, proj, opacity, value,
-                           K, rec);
+        hipLaunchKernelGGL(k_build_records, dim3(g), dim3(256), 0, st, proj, opacity, value, K,
+                           rec);
     }
-    hipLaunchKernelGGL(k_raster_fwd, dim3(T), dim3(256), 0, st, rec, bins.rank_of_pair,
+    hipLaunchKernelGGL(k_raster_fwd, dim3(T), dim3(256), 0, st, rec, bins.splat_of_pair,
                        bins.ranges, T, nx, W, H, K, grad);
     GDGS_LAUNCH_CHECK();
     return GDGS_OK;
@@ -326,11 +395,10 @@ gdgs_status launch_raster_backward(const gdgs_proj& proj, const float* opacity,
     const int nx = tiles_x(W), T = nx * tiles_y(H);
     const unsigned g = (unsigned)((K + 255) / 256);
     hipLaunchKernelGGL(k_inv_order, dim3(g), dim3(256), 0, st, bins.order, K, inv);
-    hipLaunchKernelGGL(k_gather_records, dim3(g), dim3(256), 0, st, inv, proj, opacity, value, K,
-                       rec);
-    hipLaunchKernelGGL(k_raster_bwd, dim3(T), dim3(256), 0, st, rec, bins.rank_of_pair,
+    hipLaunchKernelGGL(k_build_records, dim3(g), dim3(256), 0, st, proj, opacity, value, K, rec);
+    hipLaunchKernelGGL(k_raster_bwd, dim3(T), dim3(256), 0, st, rec, bins.splat_of_pair,
                        bins.ranges, T, nx, W, H, K, grad, dgrad, part, bins.capacity);
-    hipLaunchKernelGGL(k_seg_reduce, dim3(g), dim3(256), 0, st, proj, inv, bins.rank_of_pair,
+    hipLaunchKernelGGL(k_seg_reduce, dim3(g), dim3(256), 0, st, proj, inv, bins.splat_of_pair,
                        bins.ranges, T, nx, K, part, dmean2d, dconic, dopacity, dvalue);
     GDGS_LAUNCH_CHECK();
     return GDGS_OK;

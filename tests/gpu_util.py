@@ -42,7 +42,7 @@ def gpu_stages(scene: wl.Scene, cam: wl.Camera, capacity: int | None = None):
         tx0=(rect[0] & 0xFFFF).astype(np.int64), tx1=(rect[0] >> 16).astype(np.int64),
         ty0=(rect[1] & 0xFFFF).astype(np.int64), ty1=(rect[1] >> 16).astype(np.int64),
         num_pairs=P, tiles=u32(bins["tile_of_pair"])[:n].astype(np.int64),
-        ranks=u32(bins["rank_of_pair"])[:n].astype(np.int64),
+        splats=u32(bins["splat_of_pair"])[:n].astype(np.int64),
         order=u32(bins["order"])[:K].astype(np.int64), ranges=u32(bins["ranges"]),
         grad=np_(grad).astype(np.float64))
     out["mean2d"] = np.stack([out["mean2d_rel"][0] + 16 * out["tx0"],

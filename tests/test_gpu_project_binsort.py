@@ -68,7 +68,7 @@ def test_bin_sort_is_bit_exact(name, cfg):
     dbits = g["depth"].view(np.uint32).astype(np.int64)
     o = np.lexsort((splats, dbits[splats], tiles))
     assert np.array_equal(g["tiles"], tiles[o])
-    assert np.array_equal(g["order"][g["ranks"]], splats[o])
+    assert np.array_equal(g["splats"], splats[o])
     # depth order: permutation, sorted by (count>0 ? depth bits : max, index)
     key = np.where(g["count"] > 0, dbits, 0xFFFFFFFF)
     assert np.array_equal(g["order"], np.lexsort((np.arange(K), key)))
@@ -85,6 +85,6 @@ def test_bin_sort_matches_oracle_pairs():
     g = gpu_stages(sc, cam)
     o = oproject(sc, cam)
     ot, os_ = ob.sorted_pairs(o, 100)
-    gs = g["order"][g["ranks"]]
+    gs = g["splats"]
     if np.array_equal(g["count"], o["count"]):
         assert np.array_equal(g["tiles"], ot) and np.array_equal(gs, os_)
