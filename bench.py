@@ -3,7 +3,8 @@ with 1,000,000 gradient splats on one GPU.
 
 One step = one frame of the whole path for one seeded camera pose: projection,
 tile binning and depth sort, six-channel gradient compositing, divergence and
-multigrid Poisson solve (8 levels, V(2,2), stop at eta <= 1e-6) with the
+multigrid Poisson solve (8 levels, V(2,2), stop at a 1e-6 relative
+correction) with the
 reference image's ring as Dirichlet data.  Steps cycle over 100 seeded poses.
 Inputs are resident in device memory before timing starts.
 
@@ -27,12 +28,18 @@ METRIC = "render+Poisson Mpix/s at 1080p/1M splats; p50/p99 batched vs plain on 
 HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TFLOPS = 78.6   # FP32 vector FMA without packed math (256 CU x 2.4 GHz x 128 flop)
 
-# Algorithmic bytes per unit of work of the memory-bound stages (no re-reads):
+# Algorithmic work per unit (what the method must move or compute, no re-reads):
 #  multigrid, per finest interior point, per channel, per V(2,2) cycle: the
 #  pre-smoothing pass reads u, f and writes u (12 B) plus a quarter-size coarse
 #  right-hand side (1 B); the post pass reads u, f and a quarter-size
 #  correction and writes u (13 B); coarser grids add 1/4 + 1/16 + ... = 1/3.
 MG_BYTES_PER_POINT_CYCLE = 26.0 * 4.0 / 3.0
+#  the finest-grid post pass alone: 13 B per interior point per channel.
+MG_POST_BYTES_PER_POINT = 13.0
+#  compositing, per (pixel, splat) contribution of Eq. 20: offsets 2, exponent
+#  E 7 (2 mul + 2 fma + 1 mul counted 2 per fma), exp 1, alpha*G 1, w = a*T 1,
+#  six value FMAs 12, transmittance update 2 = 26 flops.
+RASTER_FLOPS_PER_CONTRIB = 26.0
 
 
 def parse():
@@ -104,22 +111,36 @@ def main():
     # (outside the timed region) sizes the pair capacity and the cycle budget
     r = G.Renderer(ds, W, H, mg)
     r.render(cams[0], ring)
-    stream = torch.cuda.current_stream()
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
+    # per-launch events of the two largest kernels, recorded inside the
+    # library on the stream the kernels run on
+    NT = 64
+    k_ev = {name: ([torch.cuda.Event(enable_timing=True) for _ in range(NT)],
+                   [torch.cuda.Event(enable_timing=True) for _ in range(NT)])
+            for name in ("raster", "mg_post_fine")}
+    for name, (a0, a1) in k_ev.items():
+        G.api.set_kernel_timer(name, a0, a1)
 
     for i in range(args.warmup):
         r.render(cams[i % len(cams)], ring)
     torch.cuda.synchronize()
 
-    cycles = []
+    cycles, k_ms = [], {"raster": [], "mg_post_fine": []}
     t0 = time.perf_counter()
     for i in range(args.steps):
         r.render(cams[i % len(cams)], ring, events=ev[i])
-        cycles.append(r.last["total_cycles"])
+        cyc = r.last["total_cycles"]
+        cycles.append(cyc)
+        # render() synchronised on its statistics: this frame's events are done
+        k_ms["raster"].append(k_ev["raster"][0][0].elapsed_time(k_ev["raster"][1][0]))
+        n_post = min(NT, max(r.last["cycles"]))
+        k_ms["mg_post_fine"].append([k_ev["mg_post_fine"][0][j].elapsed_time(
+            k_ev["mg_post_fine"][1][j]) for j in range(n_post)])
         if not r.last["converged"]:
             print(f"warning: frame {i} did not converge: {r.last}", file=sys.stderr)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    G.api.set_kernel_timer(None)
     ms = (t1 - t0) * 1e3 / args.steps
     stage_ms = np.array([[ev[i][s].elapsed_time(ev[i][s + 1]) for s in range(4)]
                          for i in range(args.steps)])
@@ -127,10 +148,36 @@ def main():
     P = r.last["num_pairs"]
     names = ["project", "bin_sort", "raster", "poisson"]
     mean_stage = stage_ms.mean(axis=0)
-
-    # roofline of the Poisson stage (memory bound): algorithmic bytes / time
-    npts = (H - 2) * (W - 2)
     mean_cycles = float(np.mean(cycles))
+
+    # algorithmic work of the timed frames (untimed recount of the same poses)
+    contrib = []
+    for i in range(args.steps):
+        r.render(cams[i % len(cams)], ring)
+        contrib.append(G.api.gdgs_raster_count(r.proj, ds.opacity, ds.value, K, r.bins, W, H,
+                                               r.ws_ras))
+    npts = (H - 2) * (W - 2)
+    raster_us = float(np.mean(k_ms["raster"])) * 1e3
+    raster_tflops = RASTER_FLOPS_PER_CONTRIB * float(np.mean(contrib)) / (raster_us * 1e-6) / 1e12
+    post_all = [x for f in k_ms["mg_post_fine"] for x in f]
+    post_us = float(np.mean(post_all)) * 1e3
+    post_gbs = MG_POST_BYTES_PER_POINT * 3 * npts / (post_us * 1e-6) / 1e9
+    per_frame = {"raster": raster_us, "mg_post_fine": post_us * mean_cycles}
+    kern = {
+        "raster": {"kernel": "k_raster_fwd", "bound": "alu", "achieved": round(raster_tflops, 3),
+                   "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                   "frac": round(raster_tflops / VALU_PEAK_TFLOPS, 4), "traffic": None,
+                   "avg_launch_us": round(raster_us, 2), "launches_per_step": 1,
+                   "work_per_launch": f"{RASTER_FLOPS_PER_CONTRIB:.0f} flop x "
+                                      f"{float(np.mean(contrib)):.4g} contributions"},
+        "mg_post_fine": {"kernel": "k_mg_post<2,true> (finest grid)", "bound": "hbm",
+                         "achieved": round(post_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(post_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                         "avg_launch_us": round(post_us, 2),
+                         "launches_per_step": round(mean_cycles, 2),
+                         "work_per_launch": f"{MG_POST_BYTES_PER_POINT:.0f} B x 3 x {npts} points"},
+    }
+    dominant = max(per_frame, key=per_frame.get)
     poisson_bytes = 3 * npts * (MG_BYTES_PER_POINT_CYCLE * mean_cycles + 16.0)
     poisson_gbs = poisson_bytes / (mean_stage[3] * 1e-3) / 1e9
 
@@ -148,14 +195,16 @@ def main():
         "dtype": "f32",
         "data": "synthetic (seeded scene and poses; no dataset)",
         "config": {"workload": f"plain render+Poisson, {W}x{H}, {K} gradient splats, "
-                               f"8-level V(2,2) multigrid to eta<=1e-6, 100 seeded poses",
+                               f"8-level V(2,2) multigrid to a 1e-6 relative correction, 100 seeded poses",
                    "W": W, "H": H, "splats": K, "pairs": P, "mg_cycles_mean": mean_cycles},
         "latency_ms": {"p50": round(float(np.percentile(frame_ms, 50)), 4),
                        "p99": round(float(np.percentile(frame_ms, 99)), 4)},
         "stages_ms": {n: round(float(v), 4) for n, v in zip(names, mean_stage)},
-        "roofline": {"bound": "hbm", "achieved": round(poisson_gbs, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(poisson_gbs / HBM_PEAK_GBS, 4),
-                     "traffic": None, "kernel": "poisson stage"},
+        "roofline": kern[dominant],
+        "kernels": kern,
+        "poisson_stage": {"achieved_GBs": round(poisson_gbs, 1),
+                          "frac": round(poisson_gbs / HBM_PEAK_GBS, 4),
+                          "model": "26 B x 4/3 per point per channel per V-cycle + 16 B setup"},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, cams[0], ring_np, args.cpu_pixels)

@@ -145,6 +145,16 @@ const char* gdgs_version(void);
  * launch directly.  gdgs_clear_graphs() destroys the cached graphs. */
 void gdgs_set_graphs(int enable);
 void gdgs_clear_graphs(void);
+/* Host-only profiling hook (up to 4 names at once).  While set, the i-th
+ * launch of the named kernel in each later call (i < n) is bracketed by
+ * hipEventRecord(start_events[i]) and hipEventRecord(stop_events[i]) on its
+ * stream (inside captured graphs the records become event nodes, re-recorded
+ * on every replay).  Names: "raster" (the compositing kernel), "mg_pre_fine"
+ * and "mg_post_fine" (the finest-grid multigrid passes, once per V-cycle).
+ * The events (hipEvent_t) belong to the caller.  n <= 0 clears that name,
+ * kernel NULL clears all. */
+gdgs_status gdgs_set_kernel_timer(const char* kernel, void** start_events, void** stop_events,
+                                  int n);
 
 /* ------------------------------------------------------------------ */
 /* Workspace sizes (bytes, host-only calls, nothing is enqueued).      */
@@ -198,6 +208,14 @@ gdgs_status gdgs_bin_sort(const gdgs_proj* proj, int64_t K, int32_t W, int32_t H
 gdgs_status gdgs_raster_grad(const gdgs_proj* proj, const float* opacity, const float* value,
                              int64_t K, const gdgs_bins* bins, int32_t W, int32_t H, float* grad,
                              void* ws, size_t ws_bytes, void* stream);
+
+/* Profiling companion of gdgs_raster_grad: the same traversal without an
+ * image; counts[0] (device, uint64) receives the number of (pixel, splat)
+ * contributions the composite makes (terms of the sum of Eq. 20 with a non-zero
+ * opacity), counts[1] is zeroed.  Same workspace as gdgs_raster_grad. */
+gdgs_status gdgs_raster_count(const gdgs_proj* proj, const float* opacity, const float* value,
+                              int64_t K, const gdgs_bins* bins, int32_t W, int32_t H,
+                              uint64_t* counts, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------ */
 /* Step 4, Poisson reconstruction (Sec. 2.1 Eq. 13-16; Sec. 2.2 Eq. 21) with

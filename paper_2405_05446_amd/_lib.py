@@ -76,6 +76,8 @@ _SIGS = {
     "gdgs_version": (ctypes.c_char_p, []),
     "gdgs_set_graphs": (None, [ctypes.c_int]),
     "gdgs_clear_graphs": (None, []),
+    "gdgs_set_kernel_timer": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_int]),
     "gdgs_bin_sort_workspace_size": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                                     ctypes.c_int64, P(ctypes.c_size_t)]),
     "gdgs_raster_workspace_size": (ctypes.c_int, [ctypes.c_int64, P(ctypes.c_size_t)]),
@@ -94,6 +96,9 @@ _SIGS = {
     "gdgs_raster_grad": (ctypes.c_int, [P(Proj), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                         P(Bins), ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "gdgs_raster_count": (ctypes.c_int, [P(Proj), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                         P(Bins), ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "gdgs_poisson_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                           ctypes.c_int32, P(MgParams), ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,

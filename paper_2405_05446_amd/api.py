@@ -248,6 +248,40 @@ def gdgs_render(scene: DeviceScene, cam, boundary: torch.Tensor | None, mg=None,
     return u, stats
 
 
+def set_kernel_timer(name: str | None, starts=None, stops=None):
+    """Bracket launches of a named library kernel with torch CUDA events
+    (see gdgs_set_kernel_timer).  starts/stops: equal-length lists of
+    torch.cuda.Event(enable_timing=True); name None clears every timer."""
+    lib = L.load()
+    if name is None:
+        L.check(lib.gdgs_set_kernel_timer(None, None, None, 0))
+        return
+    n = len(starts)
+    for e in list(starts) + list(stops):
+        if e.cuda_event == 0:
+            e.record()          # create the underlying event
+    torch.cuda.synchronize()
+    A = (ctypes.c_void_p * n)(*[e.cuda_event for e in starts])
+    B = (ctypes.c_void_p * n)(*[e.cuda_event for e in stops])
+    set_kernel_timer._keep = getattr(set_kernel_timer, "_keep", {})
+    set_kernel_timer._keep[name] = (A, B)   # the library keeps the pointers
+    L.check(lib.gdgs_set_kernel_timer(name.encode(), A, B, n))
+
+
+def gdgs_raster_count(proj: dict, opacity: torch.Tensor, value: torch.Tensor, K: int, bins: dict,
+                      W: int, H: int, ws: torch.Tensor | None = None, stream=None) -> int:
+    """Number of (pixel, splat) contributions of the composite (profiling)."""
+    lib = L.load()
+    dev = bins["ranges"].device
+    counts = torch.zeros(2, dtype=torch.int64, device=dev)
+    need = _size(lib.gdgs_raster_workspace_size, K)
+    ws = ws if ws is not None else workspace(need, dev)
+    L.check(lib.gdgs_raster_count(ctypes.byref(_proj_struct(proj)), L.ptr(opacity), L.ptr(value),
+                                  K, ctypes.byref(_bins_struct(bins)), W, H, L.ptr(counts),
+                                  L.ptr(ws), ws.numel(), L.stream_handle(stream)))
+    return int(counts[0].item())
+
+
 def gdgs_div_adjoint(lam: torch.Tensor, W: int, H: int, dgrad=None, stream=None) -> torch.Tensor:
     lib = L.load()
     _need(lam, (3, H, W), F32, "lam")

@@ -28,6 +28,25 @@ void set_error(const char* fmt, ...) {
 
 void clear_error() { g_err[0] = '\0'; }
 
+KernelTimer* kernel_timers() {
+    static KernelTimer t[kMaxTimers];
+    return t;
+}
+
+bool timer_events(const char* name, hipEvent_t* start, hipEvent_t* stop) {
+    KernelTimer* ts = kernel_timers();
+    for (int k = 0; k < kMaxTimers; ++k) {
+        KernelTimer& t = ts[k];
+        if (t.n <= 0 || std::strncmp(t.name, name, sizeof(t.name)) != 0) continue;
+        const int i = t.next++;
+        if (i >= t.n) return false;
+        *start = t.starts[i];
+        *stop = t.stops[i];
+        return true;
+    }
+    return false;
+}
+
 namespace {
 
 bool aligned4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
@@ -151,6 +170,7 @@ class KeyBuilder {
         s_.push_back('\0');
         return *this;
     }
+    void s_append(const char* t) { tag(t); }
     const std::string& str() const { return s_; }
 
    private:
@@ -213,8 +233,18 @@ hipStream_t capture_stream(int dev) {
     return s;
 }
 
+void add_timer(KeyBuilder& kb) {
+    const KernelTimer* ts = kernel_timers();
+    for (int k = 0; k < kMaxTimers; ++k) {
+        kb.add(ts[k].n).add(ts[k].starts).add(ts[k].stops);
+        kb.s_append(ts[k].name);
+    }
+}
+
 template <typename F>
 gdgs_status with_graph(KeyBuilder& kb, hipStream_t st, F&& enqueue) {
+    for (int k = 0; k < kMaxTimers; ++k) kernel_timers()[k].next = 0;  // pairs from 0 per call
+    add_timer(kb);
     if (!graphs_flag()) return enqueue(st);
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
@@ -296,6 +326,35 @@ const char* gdgs_version(void) { return "gdgs 0.1 gfx950"; }
 void gdgs_set_graphs(int enable) { graphs_flag() = enable ? 1 : 0; }
 
 void gdgs_clear_graphs(void) { graph_cache().clear(); }
+
+gdgs_status gdgs_set_kernel_timer(const char* kernel, void** start_events, void** stop_events,
+                                  int n) {
+    clear_error();
+    KernelTimer* ts = kernel_timers();
+    if (kernel == nullptr) {
+        for (int k = 0; k < kMaxTimers; ++k) ts[k] = KernelTimer();
+        return GDGS_OK;
+    }
+    REQUIRE(std::strlen(kernel) < sizeof(ts[0].name), "kernel name too long");
+    int slot = -1;
+    for (int k = 0; k < kMaxTimers; ++k)
+        if (ts[k].n > 0 && std::strncmp(ts[k].name, kernel, sizeof(ts[k].name)) == 0) slot = k;
+    if (n <= 0) {
+        if (slot >= 0) ts[slot] = KernelTimer();
+        return GDGS_OK;
+    }
+    REQUIRE(start_events != nullptr && stop_events != nullptr, "event arrays are null");
+    for (int k = 0; slot < 0 && k < kMaxTimers; ++k)
+        if (ts[k].n <= 0) slot = k;
+    REQUIRE(slot >= 0, "at most %d kernel timers", kMaxTimers);
+    KernelTimer& t = ts[slot];
+    t = KernelTimer();
+    std::strncpy(t.name, kernel, sizeof(t.name) - 1);
+    t.starts = reinterpret_cast<hipEvent_t*>(start_events);
+    t.stops = reinterpret_cast<hipEvent_t*>(stop_events);
+    t.n = n;
+    return GDGS_OK;
+}
 
 gdgs_status gdgs_bin_sort_workspace_size(int64_t K, int32_t W, int32_t H, int64_t pair_capacity,
                                          size_t* bytes) {
@@ -426,6 +485,27 @@ gdgs_status gdgs_raster_grad(const gdgs_proj* proj, const float* opacity, const 
     return with_graph(kb, as_stream(stream), [&](hipStream_t s) {
         return launch_raster(p, opacity, value, K, bb, W, H, grad, ws, s);
     });
+}
+
+gdgs_status gdgs_raster_count(const gdgs_proj* proj, const float* opacity, const float* value,
+                              int64_t K, const gdgs_bins* bins, int32_t W, int32_t H,
+                              uint64_t* counts, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    REQUIRE(K >= 0 && K < (int64_t)0xFFFFFFFFll, "K = %lld out of range", (long long)K);
+    TRY(check_size(W, H));
+    REQUIRE(counts != nullptr && (reinterpret_cast<uintptr_t>(counts) & 7u) == 0,
+            "counts is null or not 8-byte aligned");
+    if (K > 0) {
+        TRY(check_proj(proj));
+        REQUIRE_PTR(opacity);
+        REQUIRE_PTR(value);
+    }
+    TRY(check_bins(bins, K));
+    TRY(check_ws(ws, ws_bytes, raster_ws_bytes(K)));
+    gdgs_proj p = K > 0 ? *proj : gdgs_proj{};
+    return launch_raster_count(p, opacity, value, K, *bins, W, H,
+                               reinterpret_cast<unsigned long long*>(counts), ws,
+                               as_stream(stream));
 }
 
 static gdgs_status poisson_common(const float* grad, const float* rho, const float* boundary,

@@ -25,7 +25,7 @@ constexpr float kTmin = 1e-7f;
 // Multigrid: at most this many grids, each channel's coarse grids that fit
 // together in kLdsBudget bytes of LDS are solved inside one workgroup.
 constexpr int kMaxLevels = 8;
-constexpr int kLdsBudget = 120 * 1024;
+constexpr int kLdsBudget = 150 * 1024;
 
 // ---------------------------------------------------------------- errors
 void set_error(const char* fmt, ...);
@@ -101,6 +101,9 @@ size_t raster_ws_bytes(int64_t K);
 gdgs_status launch_raster(const gdgs_proj& proj, const float* opacity, const float* value,
                           int64_t K, const gdgs_bins& bins, int W, int H, float* grad,
                           void* ws, hipStream_t st);
+gdgs_status launch_raster_count(const gdgs_proj& proj, const float* opacity, const float* value,
+                                int64_t K, const gdgs_bins& bins, int W, int H,
+                                unsigned long long* counts, void* ws, hipStream_t st);
 size_t raster_bwd_ws_bytes(int64_t K, int64_t cap);
 gdgs_status launch_raster_backward(const gdgs_proj& proj, const float* opacity,
                                    const float* value, int64_t K, const gdgs_bins& bins, int W,
@@ -130,6 +133,20 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
                            int H, const MgPlan& plan, float* u, gdgs_stats* stats, void* ws,
                            hipStream_t st);
 gdgs_status launch_div_adjoint(const float* lam, int W, int H, float* dgrad, hipStream_t st);
+
+// ---------------------------------------------------------------- timing hook
+// Optional per-launch event timing of one named kernel (set through the C ABI).
+struct KernelTimer {
+    char name[32] = {0};
+    hipEvent_t* starts = nullptr;
+    hipEvent_t* stops = nullptr;
+    int n = 0;
+    int next = 0;
+};
+constexpr int kMaxTimers = 4;
+KernelTimer* kernel_timers();  // [kMaxTimers]
+// Event pair (start, stop) to bracket this launch of `name` with, or false.
+bool timer_events(const char* name, hipEvent_t* start, hipEvent_t* stop);
 
 // Fill a u32 array with a value (graph-capture friendly, no memset nodes).
 gdgs_status launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st);

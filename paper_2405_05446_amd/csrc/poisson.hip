@@ -90,6 +90,7 @@ struct LdsPlan {
     int n[kMaxLevels], m[kMaxLevels];
     float ey[kMaxLevels], ex[kMaxLevels], wy[kMaxLevels], wx[kMaxLevels];
     int off[kMaxLevels];   // float offset of u_l in LDS; f_l follows u_l
+    int scratch;           // float offset of the residual scratch
     int pre, post, csweeps;
     float omega;
     LevelDev top;          // global arrays of level lc
@@ -280,8 +281,10 @@ __device__ __forceinline__ void load_region(float* su, float* sf, const LevelDev
 // Thread t of a 256-thread block owns the tile cells t, t + 256, ...
 constexpr int kCellsPerThread = kTX * kTY / 256;
 
-// Pre-smoothing + residual + restriction to the next grid.
-template <int NU, bool DELTA>
+// Pre-smoothing + residual + restriction to the next grid.  FINE (the finest
+// grid only): record the largest change of u and evaluate the residual in
+// FP64; coarser grids carry small corrections and stay in FP32.
+template <int NU, bool FINE>
 __global__ __launch_bounds__(256) void k_mg_pre(LevelDev L, LevelDev C, int zero_guess,
                                                 const int* __restrict__ done,
                                                 double* __restrict__ part) {
@@ -296,7 +299,7 @@ __global__ __launch_bounds__(256) void k_mg_pre(LevelDev L, LevelDev C, int zero
     load_region<RX, RY>(su, sf, L, L.u, c, gi0, gj0, zero_guess != 0);
     __syncthreads();
     float before[kCellsPerThread];
-    if (DELTA) {
+    if (FINE) {
 #pragma unroll
         for (int k = 0; k < kCellsPerThread; ++k) {
             const int idx = threadIdx.x + 256 * k;
@@ -316,7 +319,7 @@ __global__ __launch_bounds__(256) void k_mg_pre(LevelDev L, LevelDev C, int zero
         if (gi < N && gj < M) {
             const float v = su[r * RX + q];
             u[(size_t)gi * L.pitch + gj] = v;
-            if (DELTA && gi >= 1 && gi <= L.n && gj >= 1 && gj <= L.m)
+            if (FINE && gi >= 1 && gi <= L.n && gj >= 1 && gj <= L.m)
                 dmax = fmax(dmax, fabs((double)v - (double)before[k]));
         }
     }
@@ -335,9 +338,15 @@ __global__ __launch_bounds__(256) void k_mg_pre(LevelDev L, LevelDev C, int zero
                 const int gj = gj0 + q;
                 const int o = r * RX + q;
                 float rv = 0.f;
-                if (row_in && gj >= 1 && gj <= L.m)
-                    rv = (float)res_value(su[o - RX], su[o + RX], su[o - 1], su[o + 1], su[o],
-                                          sf[o], gj == L.m ? drow + L.ex : drow);
+                if (row_in && gj >= 1 && gj <= L.m) {
+                    const float d = gj == L.m ? drow + L.ex : drow;
+                    if (FINE)
+                        rv = (float)res_value(su[o - RX], su[o + RX], su[o - 1], su[o + 1], su[o],
+                                              sf[o], d);
+                    else
+                        rv = sf[o] - (((su[o - RX] + su[o + RX]) + (su[o - 1] + su[o + 1])) -
+                                      d * su[o]);
+                }
                 sf[o] = rv;
             }
         }
@@ -354,7 +363,7 @@ __global__ __launch_bounds__(256) void k_mg_pre(LevelDev L, LevelDev C, int zero
             fc[(size_t)I * C.pitch + J] = 0.25f * v;
         }
     }
-    if (DELTA) {
+    if (FINE) {
         double d1 = 0.0, d2 = 0.0;
         block_reduce3(dmax, d1, d2, sh);
         if (threadIdx.x == 0) {
@@ -364,12 +373,13 @@ __global__ __launch_bounds__(256) void k_mg_pre(LevelDev L, LevelDev C, int zero
     }
 }
 
-// Prolongation + correction + post-smoothing (+ residual and correction norms
-// on the finest grid).
-template <int NU, bool NORM>
+// Prolongation + correction + post-smoothing.  FINE (the finest grid only):
+// also the residual and correction norms of the cycle.
+template <int NU, bool FINE>
 __global__ __launch_bounds__(256) void k_mg_post(LevelDev L, LevelDev C,
                                                  const int* __restrict__ done,
                                                  double* __restrict__ part) {
+    constexpr bool NORM = FINE;
     constexpr int HALO = 2 * NU + 2;
     constexpr int RX = kTX + 2 * HALO, RY = kTY + 2 * HALO;
     constexpr int CX = RX / 2 + 2, CY = RY / 2 + 2;  // staged coarse tile
@@ -462,22 +472,37 @@ __global__ __launch_bounds__(256) void k_mg_post(LevelDev L, LevelDev C,
 }
 
 // ---------------------------------------------------------------- coarse V-cycle in LDS
+// Thread layout for a grid of n interior rows: tpr threads share a row,
+// rows 1 + t / tpr, stepping by rpp rows per pass.
+struct RowMap {
+    int tpr, rpp, r0, sg;
+    bool active;
+    __device__ RowMap(int rows) {
+        const int nt = blockDim.x, t = threadIdx.x;
+        tpr = rows > 0 ? max(1, nt / rows) : nt;
+        rpp = nt / tpr;
+        r0 = t / tpr;
+        sg = t % tpr;
+        active = t < rpp * tpr;
+    }
+};
+
 __device__ __forceinline__ void lds_gs(float* U, const float* F, int n, int m, float ey,
                                        float ex, int color0, int sweeps, float omega) {
     const int M = m + 2;
-    const int hx = (m + 1) / 2 + 1;
+    const RowMap rm(n);
     for (int s = 0; s < sweeps; ++s) {
         for (int h = 0; h < 2; ++h) {
             const int color = color0 ^ h;
-            for (int idx = threadIdx.x; idx < n * hx; idx += blockDim.x) {
-                const int i = 1 + idx / hx;
-                const int k = idx - (i - 1) * hx;
-                const int j = 1 + 2 * k + ((color + i + 1) & 1);
-                if (j <= m) {
-                    const int o = i * M + j;
-                    const float gs = gs_value(U[o - M], U[o + M], U[o - 1], U[o + 1], F[o],
-                                              diag_at(i, j, n, m, ey, ex));
-                    U[o] = omega == 1.f ? gs : U[o] + omega * (gs - U[o]);
+            if (rm.active) {
+                for (int i = 1 + rm.r0; i <= n; i += rm.rpp) {
+                    const float drow = 4.f + (i == n ? ey : 0.f);
+                    for (int j = 1 + ((color + i + 1) & 1) + 2 * rm.sg; j <= m; j += 2 * rm.tpr) {
+                        const int o = i * M + j;
+                        const float gs = gs_value(U[o - M], U[o + M], U[o - 1], U[o + 1], F[o],
+                                                  j == m ? drow + ex : drow);
+                        U[o] = omega == 1.f ? gs : U[o] + omega * (gs - U[o]);
+                    }
                 }
             }
             __syncthreads();
@@ -485,13 +510,28 @@ __device__ __forceinline__ void lds_gs(float* U, const float* F, int n, int m, f
     }
 }
 
-__device__ __forceinline__ float lds_res(const float* U, const float* F, int n, int m, float ey,
-                                         float ex, int i, int j) {
-    if (i < 1 || i > n || j < 1 || j > m) return 0.f;
-    const int M = m + 2, o = i * M + j;
-    return (float)res_value(U[o - M], U[o + M], U[o - 1], U[o + 1], U[o], F[o],
-                            diag_at(i, j, n, m, ey, ex));
+// R = F - A U on the interior (FP64 registers), 0 on the ring.
+__device__ __forceinline__ void lds_residual(const float* U, const float* F, float* R, int n,
+                                             int m, float ey, float ex) {
+    const int M = m + 2;
+    const RowMap rm(n + 2);
+    if (rm.active) {
+        for (int i = rm.r0; i <= n + 1; i += rm.rpp) {
+            const bool row_in = i >= 1 && i <= n;
+            const float drow = 4.f + (i == n ? ey : 0.f);
+            for (int j = rm.sg; j <= m + 1; j += rm.tpr) {
+                const int o = i * M + j;
+                float r = 0.f;
+                if (row_in && j >= 1 && j <= m)
+                    r = (float)res_value(U[o - M], U[o + M], U[o - 1], U[o + 1], U[o], F[o],
+                                         j == m ? drow + ex : drow);
+                R[o] = r;
+            }
+        }
+    }
+    __syncthreads();
 }
+
 __global__ __launch_bounds__(kLdsThreads) void k_mg_lds(LdsPlan P, const int* __restrict__ done,
                                                         double* __restrict__ part) {
     extern __shared__ float lds[];
@@ -499,6 +539,7 @@ __global__ __launch_bounds__(kLdsThreads) void k_mg_lds(LdsPlan P, const int* __
     const int c = blockIdx.x;
     if (done[c]) return;
     const int lc = P.lc, L = P.L;
+    float* R = lds + P.scratch;
     // load the top level
     {
         const int n = P.n[lc], m = P.m[lc], M = m + 2;
@@ -506,11 +547,15 @@ __global__ __launch_bounds__(kLdsThreads) void k_mg_lds(LdsPlan P, const int* __
         float* F = U + (n + 2) * M;
         const float* gu = P.top.u + (size_t)c * P.top.cs;
         const float* gf = P.top.f + (size_t)c * P.top.cs;
-        for (int idx = threadIdx.x; idx < (n + 2) * M; idx += blockDim.x) {
-            const int i = idx / M, j = idx - i * M;
-            const size_t o = (size_t)i * P.top.pitch + j;
-            U[idx] = (lc == 0) ? gu[o] : 0.f;
-            F[idx] = (i >= 1 && i <= n && j >= 1 && j <= m) ? gf[o] : 0.f;
+        const RowMap rm(n + 2);
+        if (rm.active) {
+            for (int i = rm.r0; i <= n + 1; i += rm.rpp) {
+                for (int j = rm.sg; j <= m + 1; j += rm.tpr) {
+                    const size_t o = (size_t)i * P.top.pitch + j;
+                    U[i * M + j] = (lc == 0) ? gu[o] : 0.f;
+                    F[i * M + j] = (i >= 1 && i <= n && j >= 1 && j <= m) ? gf[o] : 0.f;
+                }
+            }
         }
         __syncthreads();
     }
@@ -520,22 +565,24 @@ __global__ __launch_bounds__(kLdsThreads) void k_mg_lds(LdsPlan P, const int* __
         float* F = U + (n + 2) * M;
         const float ey = P.ey[l], ex = P.ex[l];
         lds_gs(U, F, n, m, ey, ex, 0, P.pre, 1.f);
+        lds_residual(U, F, R, n, m, ey, ex);
         const int nc = P.n[l + 1], mc = P.m[l + 1], Mc = mc + 2;
         float* Uc = lds + P.off[l + 1];
         float* Fc = Uc + (nc + 2) * Mc;
-        for (int idx = threadIdx.x; idx < (nc + 2) * Mc; idx += blockDim.x) {
-            const int I = idx / Mc, J = idx - I * Mc;
-            Uc[idx] = 0.f;
-            float v = 0.f;
-            if (I >= 1 && I <= nc && J >= 1 && J <= mc) {
-                const int i = 2 * I, j = 2 * J;
-#define R_(a, b) lds_res(U, F, n, m, ey, ex, i + (a), j + (b))
-                v = 4.f * R_(0, 0) + 2.f * (R_(-1, 0) + R_(1, 0) + R_(0, -1) + R_(0, 1)) +
-                    (R_(-1, -1) + R_(-1, 1) + R_(1, -1) + R_(1, 1));
-#undef R_
-                v *= 0.25f;
+        const RowMap rm(nc + 2);
+        if (rm.active) {
+            for (int I = rm.r0; I <= nc + 1; I += rm.rpp) {
+                for (int J = rm.sg; J <= mc + 1; J += rm.tpr) {
+                    float v = 0.f;
+                    if (I >= 1 && I <= nc && J >= 1 && J <= mc) {
+                        const int o = 2 * I * M + 2 * J;
+                        v = 0.25f * (4.f * R[o] + 2.f * (R[o - 1] + R[o + 1] + R[o - M] + R[o + M]) +
+                                     (R[o - M - 1] + R[o - M + 1] + R[o + M - 1] + R[o + M + 1]));
+                    }
+                    Uc[I * Mc + J] = 0.f;
+                    Fc[I * Mc + J] = v;
+                }
             }
-            Fc[idx] = v;
         }
         __syncthreads();
     }
@@ -551,18 +598,21 @@ __global__ __launch_bounds__(kLdsThreads) void k_mg_lds(LdsPlan P, const int* __
         float* F = U + (n + 2) * M;
         const int Mc = P.m[l + 1] + 2, nc = P.n[l + 1], mc = P.m[l + 1];
         const float* Uc = lds + P.off[l + 1];
-        for (int idx = threadIdx.x; idx < (n + 2) * M; idx += blockDim.x) {
-            const int i = idx / M, j = idx - i * M;
-            if (i >= 1 && i <= n && j >= 1 && j <= m) {
-                const int oi = i & 1, oj = j & 1, I0 = i >> 1, J0 = j >> 1;
-                const float* p = Uc + I0 * Mc + J0;
-                float v = p[0];
-                if (oi) v += p[Mc];
-                if (oj) v += p[1];
-                if (oi & oj) v += p[Mc + 1];
+        const RowMap rm(n);
+        if (rm.active) {
+            for (int i = 1 + rm.r0; i <= n; i += rm.rpp) {
+                const int oi = i & 1, I0 = i >> 1;
                 const float fy = oi ? (I0 == nc ? P.wy[l + 1] : 0.5f) : 1.f;
-                const float fx = oj ? (J0 == mc ? P.wx[l + 1] : 0.5f) : 1.f;
-                U[idx] += fy * fx * v;
+                for (int j = 1 + rm.sg; j <= m; j += rm.tpr) {
+                    const int oj = j & 1, J0 = j >> 1;
+                    const float* p = Uc + I0 * Mc + J0;
+                    float v = p[0];
+                    if (oi) v += p[Mc];
+                    if (oj) v += p[1];
+                    if (oi & oj) v += p[Mc + 1];
+                    const float fx = oj ? (J0 == mc ? P.wx[l + 1] : 0.5f) : 1.f;
+                    U[i * M + j] += fy * fx * v;
+                }
             }
         }
         __syncthreads();
@@ -576,18 +626,24 @@ __global__ __launch_bounds__(kLdsThreads) void k_mg_lds(LdsPlan P, const int* __
         const float* F = U + (n + 2) * M;
         float* gu = P.top.u + (size_t)c * P.top.cs;
         double rmax = 0.0, umax = 0.0, rss = 0.0, dmax = 0.0;
-        for (int idx = threadIdx.x; idx < (n + 2) * M; idx += blockDim.x) {
-            const int i = idx / M, j = idx - i * M;
-            const size_t go = (size_t)i * P.top.pitch + j;
-            if (lc == 0 && i >= 1 && i <= n && j >= 1 && j <= m)
-                dmax = fmax(dmax, fabs((double)U[idx] - (double)gu[go]));
-            gu[go] = U[idx];
-            if (lc == 0 && i >= 1 && i <= n && j >= 1 && j <= m) {
-                const double rv = res_value(U[idx - M], U[idx + M], U[idx - 1], U[idx + 1],
-                                            U[idx], F[idx], diag_at(i, j, n, m, P.ey[0], P.ex[0]));
-                rmax = fmax(rmax, fabs(rv));
-                umax = fmax(umax, fabs((double)U[idx]));
-                rss += rv * rv;
+        const RowMap rm(n + 2);
+        if (rm.active) {
+            for (int i = rm.r0; i <= n + 1; i += rm.rpp) {
+                for (int j = rm.sg; j <= m + 1; j += rm.tpr) {
+                    const int idx = i * M + j;
+                    const size_t go = (size_t)i * P.top.pitch + j;
+                    const bool in = i >= 1 && i <= n && j >= 1 && j <= m;
+                    if (lc == 0 && in) {
+                        dmax = fmax(dmax, fabs((double)U[idx] - (double)gu[go]));
+                        const double rv =
+                            res_value(U[idx - M], U[idx + M], U[idx - 1], U[idx + 1], U[idx],
+                                      F[idx], diag_at(i, j, n, m, P.ey[0], P.ex[0]));
+                        rmax = fmax(rmax, fabs(rv));
+                        umax = fmax(umax, fabs((double)U[idx]));
+                        rss += rv * rv;
+                    }
+                    gu[go] = U[idx];
+                }
             }
         }
         if (lc == 0) {
@@ -605,7 +661,12 @@ __global__ __launch_bounds__(kLdsThreads) void k_mg_lds(LdsPlan P, const int* __
     }
 }
 
-// One block per channel.
+// End-of-cycle bookkeeping, one block per channel still running: reduce the
+// per-block partials, write the statistics, raise the channel's flag when the
+// relative correction is <= tol; the last of the three blocks records whether
+// every channel is done.  (Only these three blocks synchronise through
+// memory: a device-scope fence per block of a large grid would write back
+// the L2 of its die each time.)
 __global__ __launch_bounds__(256) void k_cycle_finalize(const double* __restrict__ part, int nblk,
                                                         const double* __restrict__ bnorm,
                                                         int* __restrict__ done,
@@ -678,23 +739,31 @@ template <int NU>
 gdgs_status launch_pre(const LevelDev& L, const LevelDev& C, bool zero, bool delta,
                        const int* done, double* part, hipStream_t st) {
     dim3 grid((L.m + 2 + kTX - 1) / kTX, (L.n + 2 + kTY - 1) / kTY, 3);
+    hipEvent_t ev0, ev1;
+    const bool timed = delta && timer_events("mg_pre_fine", &ev0, &ev1);
+    if (timed) GDGS_HIP_TRY(hipEventRecord(ev0, st));
     if (delta)
         hipLaunchKernelGGL((k_mg_pre<NU, true>), grid, dim3(256), 0, st, L, C, zero ? 1 : 0,
                            done, part);
     else
         hipLaunchKernelGGL((k_mg_pre<NU, false>), grid, dim3(256), 0, st, L, C, zero ? 1 : 0,
                            done, part);
+    if (timed) GDGS_HIP_TRY(hipEventRecord(ev1, st));
     return GDGS_OK;
 }
 
 template <int NU>
-gdgs_status launch_post(const LevelDev& L, const LevelDev& C, bool norm, const int* done,
+gdgs_status launch_post(const LevelDev& L, const LevelDev& C, bool fine, const int* done,
                         double* part, hipStream_t st) {
     dim3 grid((L.m + 2 + kTX - 1) / kTX, (L.n + 2 + kTY - 1) / kTY, 3);
-    if (norm)
+    hipEvent_t ev0, ev1;
+    const bool timed = fine && timer_events("mg_post_fine", &ev0, &ev1);
+    if (timed) GDGS_HIP_TRY(hipEventRecord(ev0, st));
+    if (fine)
         hipLaunchKernelGGL((k_mg_post<NU, true>), grid, dim3(256), 0, st, L, C, done, part);
     else
         hipLaunchKernelGGL((k_mg_post<NU, false>), grid, dim3(256), 0, st, L, C, done, part);
+    if (timed) GDGS_HIP_TRY(hipEventRecord(ev1, st));
     return GDGS_OK;
 }
 
@@ -738,16 +807,19 @@ gdgs_status mg_plan(int W, int H, const gdgs_mg_params* mg, MgPlan* plan) {
         ++L;
     }
     p.levels = L;
-    // coarse grids that fit in one workgroup's LDS
+    // coarse grids that fit in one workgroup's LDS: u and f of every grid
+    // from lc down, plus a residual scratch as large as grid lc (for L > 1)
     const size_t budget = (size_t)lds_budget();
     size_t bytes = 0;
     int lc = L;
     while (lc > 0) {
-        const size_t b = 2 * sizeof(float) * (size_t)(p.n[lc - 1] + 2) * (p.m[lc - 1] + 2);
-        if (bytes + b > budget) break;
-        bytes += b;
+        const size_t cells = (size_t)(p.n[lc - 1] + 2) * (p.m[lc - 1] + 2);
+        const size_t scratch = (lc - 1 < L - 1) ? sizeof(float) * cells : 0;
+        if (bytes + 2 * sizeof(float) * cells + scratch > budget) break;
+        bytes += 2 * sizeof(float) * cells;
         --lc;
     }
+    if (lc < L - 1) bytes += sizeof(float) * (size_t)(p.n[lc] + 2) * (p.m[lc] + 2);
     if (lc == L) {
         set_error("coarsest grid %dx%d does not fit in LDS; use more multigrid levels",
                   p.n[L - 1], p.m[L - 1]);
@@ -889,6 +961,7 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
             off += 2 * (p.n[l] + 2) * (p.m[l] + 2);
         }
     }
+    lp.scratch = off;
     lp.pre = p.pre;
     lp.post = p.post;
     lp.csweeps = p.coarse_sweeps;

@@ -82,14 +82,17 @@ __device__ __forceinline__ uint32_t band_mask(float ylo, float yhi, int ty) {
     return m;
 }
 
-// Composite one splat record into a pixel (the Eq. 20 update).
+// Composite one splat record into a pixel (the Eq. 20 update); counts the
+// contributions when asked to.
+template <bool COUNT>
 __device__ __forceinline__ void blend(const float4& r0, const float4& r1, const float4& r2,
                                       const float4& r3, float fpx, float fpy, float& Tr,
-                                      float (&acc)[6]) {
+                                      float (&acc)[6], uint32_t& ncon) {
     const float dx = (fpx - r0.z) - r0.x;
     const float dy = (fpy - r0.w) - r0.y;
     const float E = dx * (r1.x * dx + r1.y * dy) + r1.z * dy * dy;
     if (E <= kEcut && Tr >= kTmin) {
+        if (COUNT && r1.w > 0.f) ++ncon;
         const float al = r1.w * __expf(-E);
         const float w = al * Tr;
         acc[0] += r2.x * w;
@@ -102,11 +105,15 @@ __device__ __forceinline__ void blend(const float4& r0, const float4& r1, const 
     }
 }
 
+// COUNT: write no image; add the number of (pixel, splat) contributions of
+// the block to counts[0] (profiling only).
+template <bool COUNT>
 __global__ __launch_bounds__(256) void k_raster_fwd(const float4* __restrict__ rec,
                                                     const uint32_t* __restrict__ splat_of_pair,
                                                     const uint32_t* __restrict__ ranges, int T,
                                                     int nx, int W, int H, int64_t K,
-                                                    float* __restrict__ grad) {
+                                                    float* __restrict__ grad,
+                                                    unsigned long long* __restrict__ counts) {
     // slot kBatch holds an inert record (alpha 0) used to pad the wave lists
     __shared__ float4 s_r0[kBatch + 1], s_r1[kBatch + 1], s_r2[kBatch + 1], s_r3[kBatch + 1];
     __shared__ uint32_t s_mask[kBatch];
@@ -128,6 +135,7 @@ __global__ __launch_bounds__(256) void k_raster_fwd(const float4* __restrict__ r
     }
     float Tr = inside ? 1.f : 0.f;
     float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    uint32_t ncon = 0;
     for (uint32_t b0 = start; b0 < end; b0 += kBatch) {
         const int n = (int)min((uint32_t)kBatch, end - b0);
         __syncthreads();
@@ -164,12 +172,19 @@ __global__ __launch_bounds__(256) void k_raster_fwd(const float4* __restrict__ r
             const float4 c0 = s_r1[jj.x], c1 = s_r1[jj.y], c2 = s_r1[jj.z], c3 = s_r1[jj.w];
             const float4 v0 = s_r2[jj.x], v1 = s_r2[jj.y], v2 = s_r2[jj.z], v3 = s_r2[jj.w];
             const float4 e0 = s_r3[jj.x], e1 = s_r3[jj.y], e2 = s_r3[jj.z], e3 = s_r3[jj.w];
-            blend(a0, c0, v0, e0, fpx, fpy, Tr, acc);
-            blend(a1, c1, v1, e1, fpx, fpy, Tr, acc);
-            blend(a2, c2, v2, e2, fpx, fpy, Tr, acc);
-            blend(a3, c3, v3, e3, fpx, fpy, Tr, acc);
+            blend<COUNT>(a0, c0, v0, e0, fpx, fpy, Tr, acc, ncon);
+            blend<COUNT>(a1, c1, v1, e1, fpx, fpy, Tr, acc, ncon);
+            blend<COUNT>(a2, c2, v2, e2, fpx, fpy, Tr, acc, ncon);
+            blend<COUNT>(a3, c3, v3, e3, fpx, fpy, Tr, acc, ncon);
         }
         if (__syncthreads_count(Tr >= kTmin) == 0) break;
+    }
+    if (COUNT) {
+        unsigned long long v = (unsigned long long)ncon;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+        if (lane == 0) atomicAdd(counts, v);
+        return;
     }
     if (inside) {
         const size_t HW = (size_t)H * W, p = (size_t)py * W + px;
@@ -368,8 +383,31 @@ gdgs_status launch_raster(const gdgs_proj& proj, const float* opacity, const flo
         hipLaunchKernelGGL(k_build_records, dim3(g), dim3(256), 0, st, proj, opacity, value, K,
                            rec);
     }
-    hipLaunchKernelGGL(k_raster_fwd, dim3(T), dim3(256), 0, st, rec, bins.splat_of_pair,
-                       bins.ranges, T, nx, W, H, K, grad);
+    hipEvent_t ev0, ev1;
+    const bool timed = timer_events("raster", &ev0, &ev1);
+    if (timed) GDGS_HIP_TRY(hipEventRecord(ev0, st));
+    hipLaunchKernelGGL(k_raster_fwd<false>, dim3(T), dim3(256), 0, st, rec, bins.splat_of_pair,
+                       bins.ranges, T, nx, W, H, K, grad, nullptr);
+    if (timed) GDGS_HIP_TRY(hipEventRecord(ev1, st));
+    GDGS_LAUNCH_CHECK();
+    return GDGS_OK;
+}
+
+gdgs_status launch_raster_count(const gdgs_proj& proj, const float* opacity, const float* value,
+                                int64_t K, const gdgs_bins& bins, int W, int H,
+                                unsigned long long* counts, void* ws, hipStream_t st) {
+    Carver c(ws);
+    float4* rec = c.take<float4>(4 * (size_t)(K > 0 ? K : 1));
+    const int nx = tiles_x(W), T = nx * tiles_y(H);
+    gdgs_status s = launch_fill_u32(reinterpret_cast<uint32_t*>(counts), 2, 0u, st);
+    if (s != GDGS_OK) return s;
+    if (K > 0) {
+        const unsigned g = (unsigned)((K + 255) / 256);
+        hipLaunchKernelGGL(k_build_records, dim3(g), dim3(256), 0, st, proj, opacity, value, K,
+                           rec);
+    }
+    hipLaunchKernelGGL(k_raster_fwd<true>, dim3(T), dim3(256), 0, st, rec, bins.splat_of_pair,
+                       bins.ranges, T, nx, W, H, K, nullptr, counts);
     GDGS_LAUNCH_CHECK();
     return GDGS_OK;
 }
