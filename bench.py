@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--H", type=int, default=1080)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=400)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -96,6 +98,16 @@ def main():
     import paper_2405_05446_amd as G
     import workloads as wl
 
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": 4 * n}), flush=True)
+        return
+
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     W, H, K = args.W, args.H, args.K
@@ -128,14 +140,13 @@ def main():
     cycles, k_ms = [], {"raster": [], "mg_post_fine": []}
     t0 = time.perf_counter()
     for i in range(args.steps):
+        G.api.rewind_kernel_timers()
         r.render(cams[i % len(cams)], ring, events=ev[i])
-        cyc = r.last["total_cycles"]
-        cycles.append(cyc)
+        cycles.append(r.last["total_cycles"])
         # render() synchronised on its statistics: this frame's events are done
-        k_ms["raster"].append(k_ev["raster"][0][0].elapsed_time(k_ev["raster"][1][0]))
-        n_post = min(NT, max(r.last["cycles"]))
-        k_ms["mg_post_fine"].append([k_ev["mg_post_fine"][0][j].elapsed_time(
-            k_ev["mg_post_fine"][1][j]) for j in range(n_post)])
+        for name, (a0, a1) in k_ev.items():
+            k_ms[name].append([a0[j].elapsed_time(a1[j])
+                               for j in range(G.api.kernel_timer_count(name))])
         if not r.last["converged"]:
             print(f"warning: frame {i} did not converge: {r.last}", file=sys.stderr)
     torch.cuda.synchronize()
@@ -157,7 +168,7 @@ def main():
         contrib.append(G.api.gdgs_raster_count(r.proj, ds.opacity, ds.value, K, r.bins, W, H,
                                                r.ws_ras))
     npts = (H - 2) * (W - 2)
-    raster_us = float(np.mean(k_ms["raster"])) * 1e3
+    raster_us = float(np.mean([x for f in k_ms["raster"] for x in f])) * 1e3
     raster_tflops = RASTER_FLOPS_PER_CONTRIB * float(np.mean(contrib)) / (raster_us * 1e-6) / 1e12
     post_all = [x for f in k_ms["mg_post_fine"] for x in f]
     post_us = float(np.mean(post_all)) * 1e3

@@ -145,16 +145,24 @@ const char* gdgs_version(void);
  * launch directly.  gdgs_clear_graphs() destroys the cached graphs. */
 void gdgs_set_graphs(int enable);
 void gdgs_clear_graphs(void);
-/* Host-only profiling hook (up to 4 names at once).  While set, the i-th
- * launch of the named kernel in each later call (i < n) is bracketed by
- * hipEventRecord(start_events[i]) and hipEventRecord(stop_events[i]) on its
- * stream (inside captured graphs the records become event nodes, re-recorded
- * on every replay).  Names: "raster" (the compositing kernel), "mg_pre_fine"
- * and "mg_post_fine" (the finest-grid multigrid passes, once per V-cycle).
- * The events (hipEvent_t) belong to the caller.  n <= 0 clears that name,
- * kernel NULL clears all. */
+/* Host-only profiling hook (up to 4 names at once).  After arming, the i-th
+ * launch of the named kernel (i < n, counted over all later calls until the
+ * next gdgs_rewind_kernel_timers or re-arming) is bracketed by
+ * hipEventRecord(start_events[i]) and hipEventRecord(stop_events[i]) on the
+ * stream it runs on; later launches are not timed.  Calls that would launch
+ * a timed kernel bypass the graph cache for that kernel (events recorded as
+ * graph nodes do not reliably bracket their neighbour), so timed figures are
+ * those of direct launches.  Names: "raster" (the compositing kernel),
+ * "mg_pre_fine" and "mg_post_fine" (the finest-grid multigrid passes, once
+ * per V-cycle).  The events (hipEvent_t) belong to the caller and must
+ * outlive the timer.  n <= 0 clears that name, kernel NULL clears all. */
 gdgs_status gdgs_set_kernel_timer(const char* kernel, void** start_events, void** stop_events,
                                   int n);
+/* Start every armed timer at pair 0 again. */
+void gdgs_rewind_kernel_timers(void);
+/* Number of launches of `kernel` bracketed since arming or the last rewind
+ * (at most its n); 0 for a name that is not armed. */
+int gdgs_kernel_timer_count(const char* kernel);
 
 /* ------------------------------------------------------------------ */
 /* Workspace sizes (bytes, host-only calls, nothing is enqueued).      */

@@ -268,6 +268,16 @@ def set_kernel_timer(name: str | None, starts=None, stops=None):
     L.check(lib.gdgs_set_kernel_timer(name.encode(), A, B, n))
 
 
+def rewind_kernel_timers():
+    """Start every armed kernel timer at its first event pair again."""
+    L.load().gdgs_rewind_kernel_timers()
+
+
+def kernel_timer_count(name: str) -> int:
+    """Launches of `name` bracketed since arming or the last rewind."""
+    return int(L.load().gdgs_kernel_timer_count(name.encode()))
+
+
 def gdgs_raster_count(proj: dict, opacity: torch.Tensor, value: torch.Tensor, K: int, bins: dict,
                       W: int, H: int, ws: torch.Tensor | None = None, stream=None) -> int:
     """Number of (pixel, splat) contributions of the composite (profiling)."""

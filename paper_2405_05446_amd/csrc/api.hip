@@ -11,6 +11,7 @@
 #include <string>
 #include <utility>
 
+#include "graph.hpp"
 #include "internal.hpp"
 
 namespace gdgs {
@@ -45,6 +46,80 @@ bool timer_events(const char* name, hipEvent_t* start, hipEvent_t* stop) {
         return true;
     }
     return false;
+}
+
+namespace {
+struct GraphCache {
+    std::mutex mu;
+    std::list<std::pair<std::string, hipGraphExec_t>> lru;
+    static constexpr size_t kMax = 32;
+
+    hipGraphExec_t find(const std::string& k) {
+        std::lock_guard<std::mutex> g(mu);
+        for (auto it = lru.begin(); it != lru.end(); ++it) {
+            if (it->first == k) {
+                lru.splice(lru.begin(), lru, it);
+                return lru.front().second;
+            }
+        }
+        return nullptr;
+    }
+    void put(const std::string& k, hipGraphExec_t e) {
+        std::lock_guard<std::mutex> g(mu);
+        lru.emplace_front(k, e);
+        while (lru.size() > kMax) {
+            (void)hipGraphExecDestroy(lru.back().second);
+            lru.pop_back();
+        }
+    }
+    void clear() {
+        std::lock_guard<std::mutex> g(mu);
+        for (auto& kv : lru) (void)hipGraphExecDestroy(kv.second);
+        lru.clear();
+    }
+};
+
+GraphCache& graph_cache_impl() {
+    static GraphCache* c = new GraphCache();  // never destroyed: outlives static teardown
+    return *c;
+}
+
+}  // namespace
+
+hipGraphExec_t graph_find(const std::string& key) { return graph_cache_impl().find(key); }
+void graph_put(const std::string& key, hipGraphExec_t exec) { graph_cache_impl().put(key, exec); }
+
+int& graphs_flag() {
+    static int v = [] {
+        const char* e = std::getenv("GDGS_GRAPHS");
+        return (e && e[0] == '0') ? 0 : 1;
+    }();
+    return v;
+}
+
+hipStream_t capture_stream(int dev) {
+    thread_local std::map<int, hipStream_t> streams;
+    auto it = streams.find(dev);
+    if (it != streams.end()) return it->second;
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    streams[dev] = s;
+    return s;
+}
+
+
+bool timer_active(const char* name) {
+    const KernelTimer* ts = kernel_timers();
+    for (int k = 0; k < kMaxTimers; ++k)
+        if (ts[k].n > 0 && std::strncmp(ts[k].name, name, sizeof(ts[k].name)) == 0) return true;
+    return false;
+}
+
+void reset_timers() {
+    for (int k = 0; k < kMaxTimers; ++k) kernel_timers()[k].next = 0;
 }
 
 namespace {
@@ -154,135 +229,6 @@ __global__ void k_render_stats(const int64_t* num_pairs, int64_t cap, gdgs_stats
     }
 }
 
-// ---------------------------------------------------------------- graph cache
-// A launch sequence is captured once per exact argument set (pointers, sizes,
-// parameters) on a private capture stream, instantiated, and replayed on the
-// caller's stream with one hipGraphLaunch.  The cache is a small LRU.
-class KeyBuilder {
-   public:
-    template <typename T>
-    KeyBuilder& add(const T& v) {
-        s_.append(reinterpret_cast<const char*>(&v), sizeof(T));
-        return *this;
-    }
-    KeyBuilder& tag(const char* t) {
-        s_.append(t);
-        s_.push_back('\0');
-        return *this;
-    }
-    void s_append(const char* t) { tag(t); }
-    const std::string& str() const { return s_; }
-
-   private:
-    std::string s_;
-};
-
-struct GraphCache {
-    std::mutex mu;
-    std::list<std::pair<std::string, hipGraphExec_t>> lru;
-    static constexpr size_t kMax = 32;
-
-    hipGraphExec_t find(const std::string& k) {
-        std::lock_guard<std::mutex> g(mu);
-        for (auto it = lru.begin(); it != lru.end(); ++it) {
-            if (it->first == k) {
-                lru.splice(lru.begin(), lru, it);
-                return lru.front().second;
-            }
-        }
-        return nullptr;
-    }
-    void put(const std::string& k, hipGraphExec_t e) {
-        std::lock_guard<std::mutex> g(mu);
-        lru.emplace_front(k, e);
-        while (lru.size() > kMax) {
-            (void)hipGraphExecDestroy(lru.back().second);
-            lru.pop_back();
-        }
-    }
-    void clear() {
-        std::lock_guard<std::mutex> g(mu);
-        for (auto& kv : lru) (void)hipGraphExecDestroy(kv.second);
-        lru.clear();
-    }
-};
-
-GraphCache& graph_cache() {
-    static GraphCache* c = new GraphCache();  // never destroyed: outlives static teardown
-    return *c;
-}
-
-int& graphs_flag() {
-    static int v = [] {
-        const char* e = std::getenv("GDGS_GRAPHS");
-        return (e && e[0] == '0') ? 0 : 1;
-    }();
-    return v;
-}
-
-hipStream_t capture_stream(int dev) {
-    thread_local std::map<int, hipStream_t> streams;
-    auto it = streams.find(dev);
-    if (it != streams.end()) return it->second;
-    hipStream_t s = nullptr;
-    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
-        (void)hipGetLastError();
-        return nullptr;
-    }
-    streams[dev] = s;
-    return s;
-}
-
-void add_timer(KeyBuilder& kb) {
-    const KernelTimer* ts = kernel_timers();
-    for (int k = 0; k < kMaxTimers; ++k) {
-        kb.add(ts[k].n).add(ts[k].starts).add(ts[k].stops);
-        kb.s_append(ts[k].name);
-    }
-}
-
-template <typename F>
-gdgs_status with_graph(KeyBuilder& kb, hipStream_t st, F&& enqueue) {
-    for (int k = 0; k < kMaxTimers; ++k) kernel_timers()[k].next = 0;  // pairs from 0 per call
-    add_timer(kb);
-    if (!graphs_flag()) return enqueue(st);
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
-        (void)hipGetLastError();
-        return enqueue(st);
-    }
-    if (cs != hipStreamCaptureStatusNone) return enqueue(st);
-    int dev = 0;
-    GDGS_HIP_TRY(hipGetDevice(&dev));
-    kb.add(dev);
-    hipGraphExec_t exec = graph_cache().find(kb.str());
-    if (!exec) {
-        hipStream_t cap = capture_stream(dev);
-        if (!cap) return enqueue(st);
-        GDGS_HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-        const gdgs_status s = enqueue(cap);
-        hipGraph_t g = nullptr;
-        const hipError_t e = hipStreamEndCapture(cap, &g);
-        if (s != GDGS_OK) {
-            if (g) (void)hipGraphDestroy(g);
-            return s;
-        }
-        if (e != hipSuccess || g == nullptr) {
-            set_error("graph capture failed: %s", hipGetErrorString(e));
-            return GDGS_ERR_HIP;
-        }
-        const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (ei != hipSuccess) {
-            set_error("graph instantiation failed: %s", hipGetErrorString(ei));
-            return GDGS_ERR_HIP;
-        }
-        graph_cache().put(kb.str(), exec);
-    }
-    GDGS_HIP_TRY(hipGraphLaunch(exec, st));
-    return GDGS_OK;
-}
-
 void add_plan(KeyBuilder& kb, const MgPlan& p) {
     kb.add(p.levels).add(p.lc).add(p.pre).add(p.post).add(p.max_cycles).add(p.coarse_sweeps)
         .add(p.omega).add(p.tol).add(p.warm).add(p.lds_bytes);
@@ -325,7 +271,7 @@ const char* gdgs_version(void) { return "gdgs 0.1 gfx950"; }
 
 void gdgs_set_graphs(int enable) { graphs_flag() = enable ? 1 : 0; }
 
-void gdgs_clear_graphs(void) { graph_cache().clear(); }
+void gdgs_clear_graphs(void) { graph_cache_impl().clear(); }
 
 gdgs_status gdgs_set_kernel_timer(const char* kernel, void** start_events, void** stop_events,
                                   int n) {
@@ -354,6 +300,17 @@ gdgs_status gdgs_set_kernel_timer(const char* kernel, void** start_events, void*
     t.stops = reinterpret_cast<hipEvent_t*>(stop_events);
     t.n = n;
     return GDGS_OK;
+}
+
+void gdgs_rewind_kernel_timers(void) { reset_timers(); }
+
+int gdgs_kernel_timer_count(const char* kernel) {
+    if (kernel == nullptr) return 0;
+    const KernelTimer* ts = kernel_timers();
+    for (int k = 0; k < kMaxTimers; ++k)
+        if (ts[k].n > 0 && std::strncmp(ts[k].name, kernel, sizeof(ts[k].name)) == 0)
+            return ts[k].next < ts[k].n ? ts[k].next : ts[k].n;
+    return 0;
 }
 
 gdgs_status gdgs_bin_sort_workspace_size(int64_t K, int32_t W, int32_t H, int64_t pair_capacity,
@@ -457,9 +414,8 @@ gdgs_status gdgs_bin_sort(const gdgs_proj* proj, int64_t K, int32_t W, int32_t H
     kb.tag("bin_sort").add(K).add(W).add(H).add(ws);
     add_proj(kb, p);
     add_bins(kb, bb);
-    return with_graph(kb, as_stream(stream), [&](hipStream_t s) {
-        return launch_bin_sort(p, K, W, H, bb, b, s);
-    });
+    return with_graph(kb, as_stream(stream),
+                      [&](hipStream_t s) { return launch_bin_sort(p, K, W, H, bb, b, s); });
 }
 
 gdgs_status gdgs_raster_grad(const gdgs_proj* proj, const float* opacity, const float* value,
@@ -482,9 +438,10 @@ gdgs_status gdgs_raster_grad(const gdgs_proj* proj, const float* opacity, const 
     kb.tag("raster").add(K).add(W).add(H).add(ws).add(opacity).add(value).add(grad);
     add_proj(kb, p);
     add_bins(kb, bb);
-    return with_graph(kb, as_stream(stream), [&](hipStream_t s) {
-        return launch_raster(p, opacity, value, K, bb, W, H, grad, ws, s);
-    });
+    return with_graph(
+        kb, as_stream(stream),
+        [&](hipStream_t s) { return launch_raster(p, opacity, value, K, bb, W, H, grad, ws, s); },
+        {"raster"});
 }
 
 gdgs_status gdgs_raster_count(const gdgs_proj* proj, const float* opacity, const float* value,
@@ -523,9 +480,12 @@ static gdgs_status poisson_common(const float* grad, const float* rho, const flo
     KeyBuilder kb;
     kb.tag("poisson").add(grad).add(rho).add(boundary).add(W).add(H).add(u).add(stats_dev).add(ws);
     add_plan(kb, plan);
-    return with_graph(kb, as_stream(stream), [&](hipStream_t s) {
-        return launch_poisson(grad, rho, boundary, W, H, plan, u, stats_dev, ws, s);
-    });
+    return with_graph(
+        kb, as_stream(stream),
+        [&](hipStream_t s) {
+            return launch_poisson(grad, rho, boundary, W, H, plan, u, stats_dev, ws, s, &kb);
+        },
+        {"mg_pre_fine", "mg_post_fine"});
 }
 
 gdgs_status gdgs_poisson_solve(const float* grad, const float* boundary, int32_t W, int32_t H,
@@ -584,15 +544,20 @@ gdgs_status gdgs_render(const gdgs_scene* scene, const gdgs_camera* cam, const f
     kb.tag("render").add(K).add(W).add(H).add(pair_capacity).add(ws).add(sc.opacity)
         .add(sc.value).add(boundary).add(u).add(stats_dev);
     add_plan(kb, plan);
-    TRY(with_graph(kb, st, [&](hipStream_t s) -> gdgs_status {
-        TRY(launch_bin_sort(r.proj, K, W, H, r.bins, b, s));
-        TRY(launch_raster(r.proj, sc.opacity, sc.value, K, r.bins, W, H, r.grad, r.raster_ws, s));
-        TRY(launch_poisson(r.grad, nullptr, boundary, W, H, plan, u, stats_dev, r.poisson_ws, s));
-        hipLaunchKernelGGL(k_render_stats, dim3(1), dim3(64), 0, s, r.bins.num_pairs,
-                           pair_capacity, stats_dev);
-        GDGS_LAUNCH_CHECK();
-        return GDGS_OK;
-    }));
+    TRY(with_graph(
+        kb, st,
+        [&](hipStream_t s) -> gdgs_status {
+            TRY(launch_bin_sort(r.proj, K, W, H, r.bins, b, s));
+            TRY(launch_raster(r.proj, sc.opacity, sc.value, K, r.bins, W, H, r.grad, r.raster_ws,
+                              s));
+            TRY(launch_poisson(r.grad, nullptr, boundary, W, H, plan, u, stats_dev, r.poisson_ws,
+                               s, &kb));
+            hipLaunchKernelGGL(k_render_stats, dim3(1), dim3(64), 0, s, r.bins.num_pairs,
+                               pair_capacity, stats_dev);
+            GDGS_LAUNCH_CHECK();
+            return GDGS_OK;
+        },
+        {"raster", "mg_pre_fine", "mg_post_fine"}));
     if (sync_stats) {
         GDGS_HIP_TRY(hipStreamSynchronize(st));
         gdgs_stats h;

@@ -27,6 +27,16 @@ constexpr float kTmin = 1e-7f;
 constexpr int kMaxLevels = 8;
 constexpr int kLdsBudget = 150 * 1024;
 
+// Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin by
+// linear block id.  xcd_remap turns linear id b of nb into a logical index so
+// that every XCD receives one contiguous range: neighbouring tiles (shared
+// halos, shared splat records) then meet in the same L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    const int fq = nb / kXcds, r = nb % kXcds, x = b % kXcds, k = b / kXcds;
+    return x < r ? x * (fq + 1) + k : r * (fq + 1) + (x - r) * fq + k;
+}
+
 // ---------------------------------------------------------------- errors
 void set_error(const char* fmt, ...);
 void clear_error();
@@ -129,9 +139,12 @@ struct MgPlan {
 gdgs_status mg_plan(int W, int H, const gdgs_mg_params* mg, MgPlan* plan);
 size_t poisson_ws_bytes(const MgPlan& plan, int W, int H);
 // grad != nullptr: divergence of grad; else rho is the right-hand side.
+class KeyBuilder;
+// key: graph-cache key of the whole call (extended per segment when the solve
+// is split so that timed kernels launch directly); may be null.
 gdgs_status launch_poisson(const float* grad, const float* rho, const float* boundary, int W,
                            int H, const MgPlan& plan, float* u, gdgs_stats* stats, void* ws,
-                           hipStream_t st);
+                           hipStream_t st, const KeyBuilder* key = nullptr);
 gdgs_status launch_div_adjoint(const float* lam, int W, int H, float* dgrad, hipStream_t st);
 
 // ---------------------------------------------------------------- timing hook
@@ -147,6 +160,8 @@ constexpr int kMaxTimers = 4;
 KernelTimer* kernel_timers();  // [kMaxTimers]
 // Event pair (start, stop) to bracket this launch of `name` with, or false.
 bool timer_events(const char* name, hipEvent_t* start, hipEvent_t* stop);
+// Timed launches count from pair 0 again (called at every ABI entry).
+void reset_timers();
 
 // Fill a u32 array with a value (graph-capture friendly, no memset nodes).
 gdgs_status launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st);

@@ -38,6 +38,7 @@
 //  * a finalize kernel evaluates eta = ||r||_inf / (8 ||w||_inf + ||b||_inf)
 //    per channel and raises a device flag; every later kernel of a finished
 //    channel returns immediately, so no host synchronisation is needed.
+#include "graph.hpp"
 #include "internal.hpp"
 
 namespace gdgs {
@@ -278,6 +279,21 @@ __device__ __forceinline__ void load_region(float* su, float* sf, const LevelDev
     }
 }
 
+// Logical (tile x, tile y, channel) of this block under the XCD remap.
+struct TileId {
+    int tx, ty, c;
+    __device__ TileId() {
+        const int gx = gridDim.x, gy = gridDim.y;
+        const int nb = gx * gy * gridDim.z;
+        const int b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+        const int L = xcd_remap(b, nb);
+        c = L / (gx * gy);
+        const int rem = L - c * gx * gy;
+        ty = rem / gx;
+        tx = rem - ty * gx;
+    }
+};
+
 // Thread t of a 256-thread block owns the tile cells t, t + 256, ...
 constexpr int kCellsPerThread = kTX * kTY / 256;
 
@@ -293,9 +309,10 @@ __global__ __launch_bounds__(256) void k_mg_pre(LevelDev L, LevelDev C, int zero
     __shared__ float su[RY * RX];
     __shared__ float sf[RY * RX];
     __shared__ double sh[3 * 4];
-    const int c = blockIdx.z;
+    const TileId id;
+    const int c = id.c;
     if (done[c]) return;
-    const int gi0 = blockIdx.y * kTY - HALO, gj0 = blockIdx.x * kTX - HALO;
+    const int gi0 = id.ty * kTY - HALO, gj0 = id.tx * kTX - HALO;
     load_region<RX, RY>(su, sf, L, L.u, c, gi0, gj0, zero_guess != 0);
     __syncthreads();
     float before[kCellsPerThread];
@@ -352,7 +369,7 @@ __global__ __launch_bounds__(256) void k_mg_pre(LevelDev L, LevelDev C, int zero
         }
     }
     __syncthreads();
-    const int I0 = blockIdx.y * (kTY / 2), J0 = blockIdx.x * (kTX / 2);
+    const int I0 = id.ty * (kTY / 2), J0 = id.tx * (kTX / 2);
     float* fc = C.fw + (size_t)c * C.cs;
     for (int idx = threadIdx.x; idx < (kTY / 2) * (kTX / 2); idx += blockDim.x) {
         const int I = I0 + idx / (kTX / 2), J = J0 + idx % (kTX / 2);
@@ -368,7 +385,7 @@ __global__ __launch_bounds__(256) void k_mg_pre(LevelDev L, LevelDev C, int zero
         block_reduce3(dmax, d1, d2, sh);
         if (threadIdx.x == 0) {
             const int nblk = gridDim.x * gridDim.y;
-            part[((size_t)c * nblk + blockIdx.y * gridDim.x + blockIdx.x) * 5 + 3] = dmax;
+            part[((size_t)c * nblk + id.ty * gridDim.x + id.tx) * 5 + 3] = dmax;
         }
     }
 }
@@ -387,9 +404,10 @@ __global__ __launch_bounds__(256) void k_mg_post(LevelDev L, LevelDev C,
     __shared__ float sf[RY * RX];
     __shared__ float se[CY * CX];
     __shared__ double sh[3 * 4];
-    const int c = blockIdx.z;
+    const TileId id;
+    const int c = id.c;
     if (done[c]) return;
-    const int gi0 = blockIdx.y * kTY - HALO, gj0 = blockIdx.x * kTX - HALO;
+    const int gi0 = id.ty * kTY - HALO, gj0 = id.tx * kTX - HALO;
     load_region<RX, RY>(su, sf, L, L.ub, c, gi0, gj0, false);
     // coarse rows (gi0 >> 1) .. ((gi0 + RY - 1) >> 1) + 1, columns alike
     const int ci0 = gi0 >> 1, cj0 = gj0 >> 1;
@@ -461,7 +479,7 @@ __global__ __launch_bounds__(256) void k_mg_post(LevelDev L, LevelDev C,
         block_reduce3(dmax, d1, d2, sh);
         if (threadIdx.x == 0) {
             const int nblk = gridDim.x * gridDim.y;
-            const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+            const int blk = id.ty * gridDim.x + id.tx;
             double* p = part + ((size_t)c * nblk + blk) * 5;
             p[0] = rmax;
             p[1] = umax;
@@ -905,7 +923,7 @@ size_t poisson_ws_bytes(const MgPlan& plan, int W, int H) {
 
 gdgs_status launch_poisson(const float* grad, const float* rho, const float* boundary, int W,
                            int H, const MgPlan& p, float* u, gdgs_stats* stats, void* ws,
-                           hipStream_t st) {
+                           hipStream_t st, const KeyBuilder* key) {
     PoissonWs w;
     poisson_layout(p, W, H, ws, &w);
     gdgs_stats* sd = stats ? stats : w.stats;
@@ -936,13 +954,16 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
         lev[l].wx = (float)(1.0 - 0.5 / p.dx[l]);
     }
     const int nblk_div = div_blocks(W, H);
-    hipLaunchKernelGGL(k_div_init,
-                       dim3((W + kDivTX - 1) / kDivTX, (H + kDivRows - 1) / kDivRows, 3),
-                       dim3(kDivTX * kDivTY), 0, st, grad, grad ? nullptr : rho, boundary, H, W,
-                       grad ? w.f0 : nullptr, u, w.bpart, w.counters, p.warm ? 1 : 0);
-    hipLaunchKernelGGL(k_setup_finalize, dim3(3), dim3(256), 0, st, w.bpart, nblk_div, w.bnorm,
-                       w.done, w.counters, sd, p.warm ? 1 : 0);
-    GDGS_LAUNCH_CHECK();
+    auto setup = [&](hipStream_t s) -> gdgs_status {
+        hipLaunchKernelGGL(k_div_init,
+                           dim3((W + kDivTX - 1) / kDivTX, (H + kDivRows - 1) / kDivRows, 3),
+                           dim3(kDivTX * kDivTY), 0, s, grad, grad ? nullptr : rho, boundary, H,
+                           W, grad ? w.f0 : nullptr, u, w.bpart, w.counters, p.warm ? 1 : 0);
+        hipLaunchKernelGGL(k_setup_finalize, dim3(3), dim3(256), 0, s, w.bpart, nblk_div,
+                           w.bnorm, w.done, w.counters, sd, p.warm ? 1 : 0);
+        GDGS_LAUNCH_CHECK();
+        return GDGS_OK;
+    };
 
     LdsPlan lp;
     lp.lc = p.lc;
@@ -968,24 +989,62 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
     lp.omega = p.omega;
     lp.top = lev[p.lc];
     const int nblk = norm_blocks(p);
-    for (int cyc = 0; cyc < p.max_cycles; ++cyc) {
-        for (int l = 0; l < p.lc; ++l) {
-            if (p.pre == 1)
-                launch_pre<1>(lev[l], lev[l + 1], l > 0, l == 0, w.done, w.part, st);
-            else
-                launch_pre<2>(lev[l], lev[l + 1], l > 0, l == 0, w.done, w.part, st);
-        }
-        hipLaunchKernelGGL(k_mg_lds, dim3(3), dim3(kLdsThreads), p.lds_bytes, st, lp, w.done,
+    auto pre = [&](int l, hipStream_t s) {
+        if (p.pre == 1)
+            launch_pre<1>(lev[l], lev[l + 1], l > 0, l == 0, w.done, w.part, s);
+        else
+            launch_pre<2>(lev[l], lev[l + 1], l > 0, l == 0, w.done, w.part, s);
+    };
+    auto post = [&](int l, hipStream_t s) {
+        if (p.post == 1)
+            launch_post<1>(lev[l], lev[l + 1], l == 0, w.done, w.part, s);
+        else
+            launch_post<2>(lev[l], lev[l + 1], l == 0, w.done, w.part, s);
+    };
+    // everything of a cycle between the finest pre and post passes
+    auto body = [&](hipStream_t s) -> gdgs_status {
+        for (int l = 1; l < p.lc; ++l) pre(l, s);
+        hipLaunchKernelGGL(k_mg_lds, dim3(3), dim3(kLdsThreads), p.lds_bytes, s, lp, w.done,
                            w.part);
-        for (int l = p.lc - 1; l >= 0; --l) {
-            if (p.post == 1)
-                launch_post<1>(lev[l], lev[l + 1], l == 0, w.done, w.part, st);
-            else
-                launch_post<2>(lev[l], lev[l + 1], l == 0, w.done, w.part, st);
-        }
-        hipLaunchKernelGGL(k_cycle_finalize, dim3(3), dim3(256), 0, st, w.part, nblk, w.bnorm,
+        for (int l = p.lc - 1; l >= 1; --l) post(l, s);
+        GDGS_LAUNCH_CHECK();
+        return GDGS_OK;
+    };
+    auto finalize = [&](int cyc, hipStream_t s) -> gdgs_status {
+        hipLaunchKernelGGL(k_cycle_finalize, dim3(3), dim3(256), 0, s, w.part, nblk, w.bnorm,
                            w.done, w.counters, sd, cyc, p.tol);
         GDGS_LAUNCH_CHECK();
+        return GDGS_OK;
+    };
+    const bool split = key && p.lc > 0 && (timer_active("mg_pre_fine") || timer_active("mg_post_fine"));
+    if (!split) {
+        gdgs_status r = setup(st);
+        if (r != GDGS_OK) return r;
+        for (int cyc = 0; cyc < p.max_cycles; ++cyc) {
+            if (p.lc > 0) pre(0, st);
+            r = body(st);
+            if (r != GDGS_OK) return r;
+            if (p.lc > 0) post(0, st);
+            r = finalize(cyc, st);
+            if (r != GDGS_OK) return r;
+        }
+        return GDGS_OK;
+    }
+    // timed finest passes launch directly between their events; the rest of
+    // each cycle is replayed from cached graphs
+    KeyBuilder ks = *key;
+    ks.tag("setup");
+    gdgs_status r = with_graph(ks, st, setup);
+    if (r != GDGS_OK) return r;
+    for (int cyc = 0; cyc < p.max_cycles; ++cyc) {
+        pre(0, st);
+        KeyBuilder kbd = *key;
+        kbd.tag("body");
+        r = with_graph(kbd, st, body);
+        if (r != GDGS_OK) return r;
+        post(0, st);
+        r = finalize(cyc, st);
+        if (r != GDGS_OK) return r;
     }
     return GDGS_OK;
 }

@@ -118,7 +118,7 @@ __global__ __launch_bounds__(256) void k_raster_fwd(const float4* __restrict__ r
     __shared__ float4 s_r0[kBatch + 1], s_r1[kBatch + 1], s_r2[kBatch + 1], s_r3[kBatch + 1];
     __shared__ uint32_t s_mask[kBatch];
     __shared__ int s_list[4][kBatch + 4];
-    const int tile = blockIdx.x;
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = tile % nx, ty = tile / nx;
     const int t = threadIdx.x, lane = __lane_id(), wv = t >> 6;
     const int px = tx * kTile + (t & 15), py = ty * kTile + (t >> 4);
@@ -154,9 +154,11 @@ __global__ __launch_bounds__(256) void k_raster_fwd(const float4* __restrict__ r
             s_mask[t] = m;
         }
         __syncthreads();
-        // this wave's list of batch entries whose support meets its rows
+        // this wave's list of batch entries whose support meets its rows (empty
+        // once all 64 pixels of the wave have stopped accumulating)
+        const bool wave_live = __ballot(Tr >= kTmin) != 0ull;
         int cnt = 0;
-        for (int c0 = 0; c0 < n; c0 += 64) {
+        for (int c0 = 0; wave_live && c0 < n; c0 += 64) {
             const int e = c0 + lane;
             const bool hit = e < n && ((s_mask[e] >> wv) & 1u);
             const uint64_t m = __ballot(hit);
