@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--H", type=int, default=1080)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=400)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -85,6 +88,63 @@ def cpu_baseline(scene, cam, ring, npix):
                        f"pixels ({t2 - t1:.2f} s, extrapolated x{H * W / rows.size:.0f} to the "
                        f"frame), DST-I Poisson of the full frame ({t3 - t2:.2f} s)",
                 frame_seconds=round(frame, 2))
+
+
+def serving_leg(G, wl, torch, nreq: int, streams: int, budget: int = 4 << 30):
+    """Mixed-size serving on one GPU: a resident 500k-splat scene, nreq requests
+    with sizes uniform over 256^2, 512^2, 800^2 and 1920x1080 (seed 7), poses
+    1000+i, reference rings.  The plain path is the library's server with one
+    stream (one request at a time, FIFO); the batched path admits up to
+    `streams` requests at once under the same 4 GiB memory budget.  Reports
+    saturation throughput (all requests arrive at once) and p50/p99 latency
+    (completion seen by the host minus scheduled arrival) for Poisson arrivals
+    at fractions of the plain path's saturation rate."""
+    cfg = wl.CONFIGS["serve"]
+    sc = wl.make_scene(cfg["K"], seed=0, z=cfg["z"], ls=cfg["ls"])
+    ds = G.DeviceScene.from_host(sc)
+    reqs = wl.serving_requests(nreq, seed=7)
+    cams = [wl.make_camera(W, H, pose_index=i) for (W, H), i in reqs]
+    rings = {sz: torch.from_numpy(wl.reference_image(sz[1], sz[0], seed=1).astype(np.float32))
+             .cuda() for sz in wl.SERVE_SIZES}
+    outs = [torch.empty((3, H, W), dtype=torch.float32, device="cuda") for (W, H), _ in reqs]
+    px = float(sum(W * H for (W, H), _ in reqs))
+    mg = G.mg_params(levels=cfg["levels"], tol=cfg["tol"])
+    torch.cuda.synchronize()
+
+    def run(srv, offsets):
+        t0 = G.now_ns() + 20_000_000        # every submission is in before the first arrival
+        for k, ((W, H), _) in enumerate(reqs):
+            srv.submit(cams[k], rings[(W, H)], u=outs[k], tag=k,
+                       arrival_ns=t0 + int(offsets[k] * 1e9))
+        done = srv.drain(len(reqs), timeout_s=300)
+        bad = [c for c in done if c["status"] != 0 or not c["converged"]]
+        lat = np.array([(c["done_ns"] - c["arrival_ns"]) / 1e6 for c in done])
+        span = (max(c["done_ns"] for c in done) - t0) / 1e9
+        return {"Mpix_s": round(px / span / 1e6, 2), "req_s": round(len(done) / span, 2),
+                "p50_ms": round(float(np.percentile(lat, 50, method="inverted_cdf")), 3),
+                "p99_ms": round(float(np.percentile(lat, 99, method="inverted_cdf")), 3),
+                "not_converged_or_failed": len(bad)}
+
+    zeros = np.zeros(nreq)
+    res = {"requests": nreq, "splats": cfg["K"], "sizes": [list(s) for s in wl.SERVE_SIZES],
+           "total_Mpix": round(px / 1e6, 2), "budget_GiB": budget / 2**30,
+           "batched_streams": streams}
+    with G.Server(ds, budget=budget, streams=1, mg=mg) as plain, \
+            G.Server(ds, budget=budget, streams=streams, mg=mg) as batched:
+        run(plain, zeros)                   # warm-up: graphs, capacities, cycle budgets
+        run(batched, zeros)
+        sat_p = run(plain, zeros)
+        sat_b = run(batched, zeros)
+        res["saturation"] = {"plain": sat_p, "batched": sat_b}
+        qps = []
+        for f in (0.5, 0.75, 1.0, 1.5):
+            q = f * sat_p["req_s"]
+            off = wl.poisson_arrivals(nreq, q, seed=7)
+            qps.append({"qps": round(q, 2), "x_plain_saturation": f,
+                        "plain": run(plain, off), "batched": run(batched, off)})
+        res["poisson_arrivals"] = qps
+        res["batched_state"] = batched.state()
+    return res
 
 
 def main():
@@ -217,6 +277,8 @@ def main():
                           "frac": round(poisson_gbs / HBM_PEAK_GBS, 4),
                           "model": "26 B x 4/3 per point per channel per V-cycle + 16 B setup"},
     }
+    if not args.no_serve:
+        out["serving"] = serving_leg(G, wl, torch, args.serve_requests, args.serve_streams)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, cams[0], ring_np, args.cpu_pixels)
     print(json.dumps(out), flush=True)

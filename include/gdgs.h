@@ -56,7 +56,8 @@ typedef enum gdgs_status {
     GDGS_ERR_BUDGET = 4,           /* serving: request does not fit the memory budget */
     GDGS_ERR_HIP = 5,              /* a HIP runtime call failed */
     GDGS_ERR_UNSUPPORTED = 6,      /* valid request this build does not handle */
-    GDGS_ERR_NOT_READY = 7         /* serving: nothing finished yet */
+    GDGS_ERR_NOT_READY = 7,        /* serving: nothing finished yet */
+    GDGS_ERR_CANCELLED = 8         /* serving: the request was cancelled */
 } gdgs_status;
 
 /* Splat scene, K splats (Sec. 1.2: Sigma = R S S^T R^T).  Device pointers. */
@@ -106,13 +107,21 @@ typedef struct gdgs_bins {
  * with the cycle's contraction factor rho (about 0.1) the remaining error is
  * then about rho / (1 - rho) of that correction. */
 #define GDGS_MG_WARM_START 1  /* flags: start from the caller's u (interior) instead of zero */
+/* flags: continue the previous solve in the same workspace.  Setup is skipped:
+ * the right-hand side, its norms, each channel's convergence flag and its
+ * cycle count (stats cycles[] keep counting) carry over, and channels that
+ * had already converged are left as they are.  Requires the same W, H, grid
+ * parameters, u, stats and workspace as the call it continues, with nothing
+ * written to them since.  Calls totalling n cycles give bit for bit the
+ * result of one call with max_cycles = n. */
+#define GDGS_MG_RESUME 2
 typedef struct gdgs_mg_params {
     int32_t levels;        /* grids including the finest, >= 1; 0 = as many as the size allows, at most 8 */
     int32_t pre_sweeps;    /* red-black Gauss-Seidel sweeps before restriction, 1..2 */
     int32_t post_sweeps;   /* sweeps after prolongation, 1..2 */
     int32_t max_cycles;    /* V-cycle limit, 1..64 */
     int32_t coarse_sweeps; /* SOR sweeps on the coarsest grid; 0 = automatic */
-    int32_t flags;         /* GDGS_MG_WARM_START or 0 */
+    int32_t flags;         /* GDGS_MG_WARM_START, GDGS_MG_RESUME or 0 */
     double tol;            /* relative-correction tolerance (see above); 0 runs max_cycles */
 } gdgs_mg_params;
 
@@ -278,6 +287,86 @@ gdgs_status gdgs_raster_grad_backward(const gdgs_proj* proj, const float* opacit
                                       int32_t W, int32_t H, const float* grad, const float* dgrad,
                                       float* dmean2d, float* dconic, float* dopacity,
                                       float* dvalue, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------ */
+/* Serving: continuous batching of render + Poisson requests (one GPU).
+ * The paper's method produces one view per camera pose (Algorithm 1 takes
+ * the poses as input; Sec. 2.2 renders each view by projection, compositing
+ * and the Poisson solve of Eq. 21).  A server keeps one scene resident and
+ * runs many such views, of mixed image sizes, concurrently:
+ *   - a native scheduler thread admits requests in arrival order whenever
+ *     one of `streams` HIP streams is free and the request's transient state
+ *     fits the memory budget (one device allocation of hbm_budget bytes,
+ *     made at creation; nothing is allocated afterwards);
+ *   - each request runs the same kernels as gdgs_render on its own stream,
+ *     so its result is bit for bit the one it would have alone: the Poisson
+ *     solve is resumed (GDGS_MG_RESUME) until it converges or mg.max_cycles
+ *     is reached, and a pair-capacity overflow re-runs the request with a
+ *     larger capacity;
+ *   - finished requests are reported through gdgs_server_poll.
+ * Device buffers named in a request (boundary, u) must stay valid and
+ * untouched until its completion has been polled; the scene's arrays must
+ * outlive the server.  All calls are thread-safe. */
+typedef struct gdgs_server gdgs_server;
+
+typedef struct gdgs_server_params {
+    int64_t hbm_budget;   /* bytes of device memory for in-flight requests */
+    int32_t streams;      /* requests in flight at once, 1..16 (1 = plain FIFO) */
+    int32_t reserved;     /* 0 */
+    gdgs_mg_params mg;    /* solver parameters of every request; flags must be 0 */
+} gdgs_server_params;
+
+typedef struct gdgs_request {
+    gdgs_camera cam;        /* image size and pose */
+    const float* boundary;  /* device [3][H][W], ring read; NULL = zero ring */
+    float* u;               /* device [3][H][W], receives the reconstruction */
+    uint64_t tag;           /* caller's value, returned in the completion */
+    int64_t arrival_ns;     /* gdgs_now_ns() time before which the request is not
+                               started; 0 = on submission */
+} gdgs_request;
+
+typedef struct gdgs_completion {
+    int64_t id;          /* from gdgs_server_submit */
+    uint64_t tag;
+    int32_t status;      /* GDGS_OK, GDGS_ERR_CANCELLED, GDGS_ERR_BUDGET or GDGS_ERR_HIP */
+    int32_t converged;   /* every channel met mg.tol */
+    int32_t cycles;      /* V-cycles of the slowest channel */
+    int32_t attempts;    /* admissions (2 or more after a capacity re-run) */
+    int64_t num_pairs;   /* (tile, splat) pairs of the view */
+    int64_t arrival_ns;  /* scheduled (or submission) time */
+    int64_t admit_ns;    /* first start */
+    int64_t done_ns;     /* completion seen by the scheduler */
+} gdgs_completion;
+
+typedef struct gdgs_server_state {
+    int64_t budget_bytes, used_bytes, peak_bytes; /* arena size, in use (incl. idle slots), peak */
+    int64_t submitted, completed;
+    int32_t waiting, running, idle_slots, streams;
+} gdgs_server_state;
+
+/* Steady-clock nanoseconds, the time base of arrival and completion times. */
+int64_t gdgs_now_ns(void);
+/* Creates the server on the current device (allocates the budget, the
+ * streams and the scheduler thread).  scene: device arrays, kept by pointer. */
+gdgs_status gdgs_server_create(const gdgs_scene* scene, const gdgs_server_params* params,
+                               gdgs_server** out);
+/* Queues a request; *id identifies it.  GDGS_ERR_BUDGET if its state can
+ * never fit the budget, GDGS_ERR_INVALID_ARGUMENT for a bad camera or
+ * buffer. */
+gdgs_status gdgs_server_submit(gdgs_server* srv, const gdgs_request* req, int64_t* id);
+/* Moves up to `max` completions into out[0..*n), oldest first, waiting up to
+ * wait_us microseconds for the first one (0 = do not wait). */
+gdgs_status gdgs_server_poll(gdgs_server* srv, gdgs_completion* out, int32_t max,
+                             int32_t wait_us, int32_t* n);
+/* A waiting request completes at once with GDGS_ERR_CANCELLED; a running one
+ * completes so after its current run.  GDGS_ERR_INVALID_ARGUMENT for an
+ * unknown or finished id. */
+gdgs_status gdgs_server_cancel(gdgs_server* srv, int64_t id);
+gdgs_status gdgs_server_query(gdgs_server* srv, gdgs_server_state* out);
+/* Cancels every request (running ones stop after their current run), waits
+ * for the device work, frees everything.  Completions not yet polled are
+ * dropped. */
+gdgs_status gdgs_server_destroy(gdgs_server* srv);
 
 #ifdef __cplusplus
 }

@@ -12,3 +12,4 @@ from .api import (  # noqa: F401
     gdgs_project_2d, gdgs_raster_grad, gdgs_raster_grad_backward, gdgs_render, mg_params,
     new_stats, read_stats, render_workspace_size, workspace,
 )
+from .serve import Server, now_ns  # noqa: F401

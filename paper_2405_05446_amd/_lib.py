@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(HERE, "libgdgs.so")
 OK = 0
 STATUS = {0: "GDGS_OK", 1: "GDGS_ERR_INVALID_ARGUMENT", 2: "GDGS_ERR_CAPACITY",
           3: "GDGS_ERR_WORKSPACE", 4: "GDGS_ERR_BUDGET", 5: "GDGS_ERR_HIP",
-          6: "GDGS_ERR_UNSUPPORTED", 7: "GDGS_ERR_NOT_READY"}
+          6: "GDGS_ERR_UNSUPPORTED", 7: "GDGS_ERR_NOT_READY", 8: "GDGS_ERR_CANCELLED"}
+ERR_BUDGET, ERR_CANCELLED = 4, 8
 
 
 class GdgsError(RuntimeError):
@@ -67,6 +68,32 @@ class Stats(ctypes.Structure):
                 ("b_norm", ctypes.c_double * 3), ("delta", ctypes.c_double * 3),
                 ("num_pairs", ctypes.c_int64),
                 ("overflow", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class ServerParams(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_int64), ("streams", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("mg", MgParams)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("cam", Camera), ("boundary", ctypes.c_void_p), ("u", ctypes.c_void_p),
+                ("tag", ctypes.c_uint64), ("arrival_ns", ctypes.c_int64)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("tag", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("cycles", ctypes.c_int32),
+                ("attempts", ctypes.c_int32), ("num_pairs", ctypes.c_int64),
+                ("arrival_ns", ctypes.c_int64), ("admit_ns", ctypes.c_int64),
+                ("done_ns", ctypes.c_int64)]
+
+
+class ServerState(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_int64), ("used_bytes", ctypes.c_int64),
+                ("peak_bytes", ctypes.c_int64), ("submitted", ctypes.c_int64),
+                ("completed", ctypes.c_int64), ("waiting", ctypes.c_int32),
+                ("running", ctypes.c_int32), ("idle_slots", ctypes.c_int32),
+                ("streams", ctypes.c_int32)]
 
 
 P = ctypes.POINTER
@@ -120,6 +147,14 @@ _SIGS = {
                                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                  ctypes.c_void_p, ctypes.c_void_p,
                                                  ctypes.c_size_t, ctypes.c_void_p]),
+    "gdgs_now_ns": (ctypes.c_int64, []),
+    "gdgs_server_create": (ctypes.c_int, [P(Scene), P(ServerParams), P(ctypes.c_void_p)]),
+    "gdgs_server_submit": (ctypes.c_int, [ctypes.c_void_p, P(Request), P(ctypes.c_int64)]),
+    "gdgs_server_poll": (ctypes.c_int, [ctypes.c_void_p, P(Completion), ctypes.c_int32,
+                                        ctypes.c_int32, P(ctypes.c_int32)]),
+    "gdgs_server_cancel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    "gdgs_server_query": (ctypes.c_int, [ctypes.c_void_p, P(ServerState)]),
+    "gdgs_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
 }
 
 _lib = None

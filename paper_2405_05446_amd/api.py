@@ -49,6 +49,7 @@ def camera_struct(cam) -> L.Camera:
 
 
 WARM_START = 1
+RESUME = 2
 
 
 def mg_params(levels: int = 0, pre: int = 2, post: int = 2, max_cycles: int = 20,
@@ -219,6 +220,12 @@ def gdgs_poisson_solve_rhs(rho: torch.Tensor, boundary: torch.Tensor | None, W: 
     return _poisson("gdgs_poisson_solve_rhs", rho, 3, boundary, W, H, mg, u, stats, ws, stream)
 
 
+def poisson_workspace_size(W: int, H: int, mg=None) -> int:
+    lib = L.load()
+    mg = mg if mg is not None else mg_params()
+    return _size(lib.gdgs_poisson_workspace_size, W, H, ctypes.byref(mg))
+
+
 def render_workspace_size(K: int, W: int, H: int, capacity: int, mg=None) -> int:
     lib = L.load()
     mg = mg if mg is not None else mg_params()
@@ -334,7 +341,8 @@ class Renderer:
         needed (consecutive views need about the same), so converged channels
         do not leave idle cycles behind; if a frame has not met the tolerance
         within its budget the solve continues from its current iterate
-        (GDGS_MG_WARM_START) until it does or the limit max_cycles is reached.
+        (GDGS_MG_RESUME) until it does or the limit max_cycles is reached; the
+        result is therefore the same whatever the budget was.
     """
 
     def __init__(self, scene: DeviceScene, W: int, H: int, mg=None, capacity: int | None = None,
@@ -391,10 +399,10 @@ class Renderer:
         total = max(st["cycles"])
         while not st["converged"] and total < self.max_cycles:
             step = min(2, self.max_cycles - total)
-            gdgs_poisson_solve(self.grad, boundary, W, H, self._mg(step, WARM_START), self.u,
+            gdgs_poisson_solve(self.grad, boundary, W, H, self._mg(step, RESUME), self.u,
                                self.stats, self.ws_poi, stream)
             st = read_stats(self.stats)
-            total += max(st["cycles"])
+            total = max(st["cycles"])     # cycle counts accumulate over resumed calls
         st["total_cycles"] = total
         st["num_pairs"] = int(self.bins["num_pairs"].item())
         if self.adaptive:

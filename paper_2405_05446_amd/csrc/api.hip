@@ -52,7 +52,7 @@ namespace {
 struct GraphCache {
     std::mutex mu;
     std::list<std::pair<std::string, hipGraphExec_t>> lru;
-    static constexpr size_t kMax = 32;
+    static constexpr size_t kMax = 128;
 
     hipGraphExec_t find(const std::string& k) {
         std::lock_guard<std::mutex> g(mu);
@@ -187,15 +187,8 @@ gdgs_status check_ws(void* ws, size_t have, size_t need) {
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
-// Everything gdgs_render carves out of its workspace.
-struct RenderWs {
-    gdgs_proj proj;
-    gdgs_bins bins;
-    float* grad;
-    void* bin_ws;
-    void* raster_ws;
-    void* poisson_ws;
-};
+}  // namespace
+
 
 size_t render_layout(int64_t K, int W, int H, int64_t cap, const MgPlan& plan, void* ws,
                      RenderWs* out) {
@@ -221,6 +214,7 @@ size_t render_layout(int64_t K, int W, int H, int64_t cap, const MgPlan& plan, v
     return c.off + 256;
 }
 
+namespace {
 __global__ void k_render_stats(const int64_t* num_pairs, int64_t cap, gdgs_stats* stats) {
     if (threadIdx.x == 0) {
         const int64_t p = *num_pairs;
@@ -228,10 +222,18 @@ __global__ void k_render_stats(const int64_t* num_pairs, int64_t cap, gdgs_stats
         stats->overflow = p > cap ? 1 : 0;
     }
 }
+}  // namespace
+
+gdgs_status launch_render_stats(const int64_t* num_pairs, int64_t cap, gdgs_stats* stats,
+                                hipStream_t st) {
+    hipLaunchKernelGGL(k_render_stats, dim3(1), dim3(64), 0, st, num_pairs, cap, stats);
+    GDGS_LAUNCH_CHECK();
+    return GDGS_OK;
+}
 
 void add_plan(KeyBuilder& kb, const MgPlan& p) {
     kb.add(p.levels).add(p.lc).add(p.pre).add(p.post).add(p.max_cycles).add(p.coarse_sweeps)
-        .add(p.omega).add(p.tol).add(p.warm).add(p.lds_bytes);
+        .add(p.omega).add(p.tol).add(p.warm).add(p.resume).add(p.lds_bytes);
     for (int l = 0; l < p.levels; ++l) kb.add(p.n[l]).add(p.m[l]).add(p.pitch[l]);
 }
 
@@ -244,7 +246,6 @@ void add_bins(KeyBuilder& kb, const gdgs_bins& b) {
         .add(b.num_pairs);
 }
 
-}  // namespace
 }  // namespace gdgs
 
 using namespace gdgs;
@@ -261,6 +262,7 @@ const char* gdgs_status_string(gdgs_status s) {
         case GDGS_ERR_HIP: return "HIP runtime error";
         case GDGS_ERR_UNSUPPORTED: return "unsupported";
         case GDGS_ERR_NOT_READY: return "not ready";
+        case GDGS_ERR_CANCELLED: return "cancelled";
     }
     return "unknown status";
 }
@@ -552,10 +554,7 @@ gdgs_status gdgs_render(const gdgs_scene* scene, const gdgs_camera* cam, const f
                               s));
             TRY(launch_poisson(r.grad, nullptr, boundary, W, H, plan, u, stats_dev, r.poisson_ws,
                                s, &kb));
-            hipLaunchKernelGGL(k_render_stats, dim3(1), dim3(64), 0, s, r.bins.num_pairs,
-                               pair_capacity, stats_dev);
-            GDGS_LAUNCH_CHECK();
-            return GDGS_OK;
+            return launch_render_stats(r.bins.num_pairs, pair_capacity, stats_dev, s);
         },
         {"raster", "mg_pre_fine", "mg_post_fine"}));
     if (sync_stats) {

@@ -36,6 +36,11 @@ int& graphs_flag();
 hipStream_t capture_stream(int dev);
 bool timer_active(const char* name);
 
+// Key parts shared by the entry points (defined in api.hip).
+void add_plan(KeyBuilder& kb, const MgPlan& p);
+void add_proj(KeyBuilder& kb, const gdgs_proj& p);
+void add_bins(KeyBuilder& kb, const gdgs_bins& b);
+
 // Enqueue `enqueue(stream)` through the graph cache.  Direct launches instead
 // when graphs are off, when the stream is itself being captured, or when one
 // of the `timed` kernels has an active timer (events recorded as graph nodes

@@ -135,6 +135,7 @@ struct MgPlan {
     float omega = 1.0f;   // SOR factor on the coarsest grid
     double tol = 1e-6;
     bool warm = false;    // start from the caller's u instead of zero
+    bool resume = false;  // continue the previous solve (setup skipped)
 };
 gdgs_status mg_plan(int W, int H, const gdgs_mg_params* mg, MgPlan* plan);
 size_t poisson_ws_bytes(const MgPlan& plan, int W, int H);
@@ -146,6 +147,23 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
                            int H, const MgPlan& plan, float* u, gdgs_stats* stats, void* ws,
                            hipStream_t st, const KeyBuilder* key = nullptr);
 gdgs_status launch_div_adjoint(const float* lam, int W, int H, float* dgrad, hipStream_t st);
+
+// ---------------------------------------------------------------- whole frame
+// Everything one render carves out of its workspace.
+struct RenderWs {
+    gdgs_proj proj;
+    gdgs_bins bins;
+    float* grad;
+    void* bin_ws;
+    void* raster_ws;
+    void* poisson_ws;
+};
+// Bytes of the render workspace (ws may be null: size only).
+size_t render_layout(int64_t K, int W, int H, int64_t cap, const MgPlan& plan, void* ws,
+                     RenderWs* out);
+// stats->num_pairs and stats->overflow from the binning's pair count.
+gdgs_status launch_render_stats(const int64_t* num_pairs, int64_t cap, gdgs_stats* stats,
+                                hipStream_t st);
 
 // ---------------------------------------------------------------- timing hook
 // Optional per-launch event timing of one named kernel (set through the C ABI).

@@ -228,6 +228,11 @@ __global__ __launch_bounds__(256) void k_setup_finalize(const double* __restrict
     }
 }
 
+// Start of a resumed solve: only the per-call finalize counters restart.
+__global__ void k_resume(int* __restrict__ counters) {
+    if (threadIdx.x < kCounters) counters[threadIdx.x] = 0;
+}
+
 // ---------------------------------------------------------------- smoothing
 // Red-black Gauss-Seidel half-sweeps on an LDS region RX x RY whose cell (0,0)
 // is grid point (gi0, gj0); only interior grid points (1..n, 1..m) change.
@@ -714,7 +719,7 @@ __global__ __launch_bounds__(256) void k_cycle_finalize(const double* __restrict
             stats->eta[c] = rmax / (8.0 * umax + bnorm[2 * c]);
             stats->rel_res[c] = b2 > 0.0 ? sqrt(rss) / b2 : 0.0;
             stats->delta[c] = rel;
-            stats->cycles[c] = cycle + 1;
+            stats->cycles[c] += 1;  // zeroed by setup; accumulates over resumed calls
             if (rel <= tol) done[c] = 1;
         }
     }
@@ -800,11 +805,12 @@ gdgs_status mg_plan(int W, int H, const gdgs_mg_params* mg, MgPlan* plan) {
                   q.levels, q.pre_sweeps, q.post_sweeps, q.max_cycles, q.tol);
         return GDGS_ERR_INVALID_ARGUMENT;
     }
-    if ((q.flags & ~GDGS_MG_WARM_START) != 0) {
+    if ((q.flags & ~(GDGS_MG_WARM_START | GDGS_MG_RESUME)) != 0) {
         set_error("unknown multigrid flags 0x%x", q.flags);
         return GDGS_ERR_INVALID_ARGUMENT;
     }
     p.warm = (q.flags & GDGS_MG_WARM_START) != 0;
+    p.resume = (q.flags & GDGS_MG_RESUME) != 0;
     p.pre = q.pre_sweeps;
     p.post = q.post_sweeps;
     p.max_cycles = q.max_cycles;
@@ -955,6 +961,11 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
     }
     const int nblk_div = div_blocks(W, H);
     auto setup = [&](hipStream_t s) -> gdgs_status {
+        if (p.resume) {
+            hipLaunchKernelGGL(k_resume, dim3(1), dim3(128), 0, s, w.counters);
+            GDGS_LAUNCH_CHECK();
+            return GDGS_OK;
+        }
         hipLaunchKernelGGL(k_div_init,
                            dim3((W + kDivTX - 1) / kDivTX, (H + kDivRows - 1) / kDivRows, 3),
                            dim3(kDivTX * kDivTY), 0, s, grad, grad ? nullptr : rho, boundary, H,

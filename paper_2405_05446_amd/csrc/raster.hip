@@ -118,7 +118,9 @@ __global__ __launch_bounds__(256) void k_raster_fwd(const float4* __restrict__ r
     __shared__ float4 s_r0[kBatch + 1], s_r1[kBatch + 1], s_r2[kBatch + 1], s_r3[kBatch + 1];
     __shared__ uint32_t s_mask[kBatch];
     __shared__ int s_list[4][kBatch + 4];
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    // natural order: tile costs are uneven, and round-robin dispatch over the
+    // XCDs balances them better than giving each XCD one band of the image
+    const int tile = blockIdx.x;
     const int tx = tile % nx, ty = tile / nx;
     const int t = threadIdx.x, lane = __lane_id(), wv = t >> 6;
     const int px = tx * kTile + (t & 15), py = ty * kTile + (t >> 4);

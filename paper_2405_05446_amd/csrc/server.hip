@@ -1,0 +1,515 @@
+// Render server: one resident scene, many concurrent views of mixed sizes.
+//
+// A native scheduler thread owns the device side.  It admits requests through
+// the scheduling core (arrival order, free stream, memory budget), enqueues
+// each request's frame on the request's own stream -- the projection with
+// the request's camera, a copy of its boundary ring into its slot, then the
+// binning, compositing and Poisson solve as one cached graph per slot and
+// size, a copy of the result to the caller's buffer and of the statistics to
+// pinned host memory -- and records an event.  When the event has fired it
+// reads the statistics: a pair overflow sends the request back to the queue
+// with a larger capacity, an unconverged solve is resumed two V-cycles at a
+// time (GDGS_MG_RESUME: bit for bit the same as one longer solve), and a
+// finished request is moved to the completion queue.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <tuple>
+#include <unordered_map>
+#include <vector>
+
+#include "graph.hpp"
+#include "internal.hpp"
+#include "sched.hpp"
+
+namespace gdgs {
+namespace {
+
+int64_t steady_ns() {
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+// Copies the one-pixel ring of a [3][H][W] image (the only part of the
+// boundary the solve reads).
+__global__ void k_copy_ring(const float* __restrict__ src, float* __restrict__ dst, int W, int H) {
+    const int nring = 2 * W + 2 * (H - 2);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 3 * nring) return;
+    const int c = i / nring, k = i % nring;
+    int y, x;
+    if (k < W) {
+        y = 0;
+        x = k;
+    } else if (k < 2 * W) {
+        y = H - 1;
+        x = k - W;
+    } else {
+        const int q = k - 2 * W;
+        y = 1 + (q >> 1);
+        x = (q & 1) ? W - 1 : 0;
+    }
+    const size_t o = (size_t)c * H * W + (size_t)y * W + x;
+    dst[o] = src[o];
+}
+
+// A request's slot: the render workspace, then the solution, the boundary
+// copy and the statistics.
+struct SlotLayout {
+    RenderWs rw;
+    float* u;
+    float* boundary;
+    gdgs_stats* stats;
+};
+
+size_t slot_layout(int64_t K, int W, int H, int64_t cap, const MgPlan& plan, char* base,
+                   SlotLayout* out) {
+    const size_t rbytes = render_layout(K, W, H, cap, plan, base, out ? &out->rw : nullptr);
+    Carver c(base ? base + rbytes : nullptr);
+    float* u = c.take<float>((size_t)3 * W * H);
+    float* b = c.take<float>((size_t)3 * W * H);
+    gdgs_stats* st = c.take<gdgs_stats>(1);
+    if (out) {
+        out->u = u;
+        out->boundary = b;
+        out->stats = st;
+    }
+    return rbytes + c.off + 256;
+}
+
+struct Payload {
+    gdgs_camera cam;
+    const float* boundary;
+    float* u;
+};
+
+}  // namespace
+}  // namespace gdgs
+
+struct gdgs_server {
+    int dev = 0;
+    uint64_t uid = 0;
+    gdgs_scene scene{};
+    gdgs_mg_params mg{};
+    char* arena = nullptr;
+    size_t arena_bytes = 0;
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> events;
+    std::vector<int64_t> running;      // request id per stream, -1 if idle
+    gdgs_stats* host_stats = nullptr;  // pinned, one per stream
+    gdgs::sched::Core* core = nullptr;
+    std::unordered_map<int64_t, gdgs::Payload> payload;
+    std::map<std::tuple<int, int, int, int>, gdgs::MgPlan> plans;  // (W, H, cycles, flags)
+    std::deque<gdgs_completion> done;
+    std::mutex mu;
+    std::condition_variable wake;       // scheduler: new work or stop
+    std::condition_variable done_cv;    // pollers: a completion
+    std::thread thread;
+    bool stop = false;
+    int64_t next_id = 1;
+    int64_t submitted = 0, completed = 0;
+    gdgs_status fatal = GDGS_OK;
+
+    // Plans are cached per size, cycle budget and flags (mg_plan also sets
+    // kernel attributes, which is not free).
+    const gdgs::MgPlan* plan(int W, int H, int cycles, int flags) {
+        const auto key = std::make_tuple(W, H, cycles, flags);
+        auto it = plans.find(key);
+        if (it != plans.end()) return &it->second;
+        gdgs_mg_params q = mg;
+        q.max_cycles = cycles;
+        q.flags = flags;
+        gdgs::MgPlan p;
+        if (gdgs::mg_plan(W, H, &q, &p) != GDGS_OK) return nullptr;
+        return &plans.emplace(key, p).first->second;
+    }
+    size_t slot_bytes(int W, int H, int64_t cap) {
+        const gdgs::MgPlan* p = plan(W, H, mg.max_cycles, 0);
+        if (!p) return SIZE_MAX / 2;
+        return gdgs::slot_layout(scene.K, W, H, cap, *p, nullptr, nullptr);
+    }
+
+    void complete(const gdgs::sched::Request& r, int32_t status) {
+        gdgs_completion c{};
+        c.id = r.id;
+        c.tag = r.tag;
+        c.status = status;
+        c.converged = r.converged ? 1 : 0;
+        c.cycles = r.cycles;
+        c.attempts = r.attempts;
+        c.num_pairs = r.num_pairs;
+        c.arrival_ns = r.arrival_ns;
+        c.admit_ns = r.admit_ns;
+        c.done_ns = gdgs::steady_ns();
+        done.push_back(c);
+        ++completed;
+        payload.erase(r.id);
+        done_cv.notify_all();
+    }
+
+    // First run of an admission (new request or capacity re-run).
+    gdgs_status enqueue_first(gdgs::sched::Request* r) {
+        using namespace gdgs;
+        const Payload& p = payload.at(r->id);
+        const int W = r->W, H = r->H, s = r->stream;
+        hipStream_t st = streams[s];
+        const MgPlan* plan = this->plan(W, H, r->run_cycles, 0);
+        if (!plan) return GDGS_ERR_INVALID_ARGUMENT;
+        char* base = arena + r->slot.off;
+        SlotLayout L;
+        slot_layout(scene.K, W, H, r->cap, *plan, base, &L);
+        const int64_t K = scene.K;
+        if (K > 0) {
+            const gdgs_status e = launch_project(scene, p.cam, L.rw.proj, st);
+            if (e != GDGS_OK) return e;
+        }
+        const float* bnd = nullptr;
+        if (p.boundary) {
+            const int nring = 3 * (2 * W + 2 * (H - 2));
+            hipLaunchKernelGGL(k_copy_ring, dim3((nring + 255) / 256), dim3(256), 0, st,
+                               p.boundary, L.boundary, W, H);
+            GDGS_LAUNCH_CHECK();
+            bnd = L.boundary;
+        }
+        BinWs b;
+        bin_ws_layout(K, r->cap, L.rw.bin_ws, &b);
+        const gdgs_scene sc = scene;
+        const int64_t cap = r->cap;
+        KeyBuilder kb;
+        kb.tag("server").add(uid).add(base).add(W).add(H).add(cap).add(K).add(sc.opacity)
+            .add(sc.value).add(bnd);
+        add_plan(kb, *plan);
+        gdgs_status e = with_graph(kb, st, [&](hipStream_t q) -> gdgs_status {
+            gdgs_status t = launch_bin_sort(L.rw.proj, K, W, H, L.rw.bins, b, q);
+            if (t != GDGS_OK) return t;
+            t = launch_raster(L.rw.proj, sc.opacity, sc.value, K, L.rw.bins, W, H, L.rw.grad,
+                              L.rw.raster_ws, q);
+            if (t != GDGS_OK) return t;
+            t = launch_poisson(L.rw.grad, nullptr, bnd, W, H, *plan, L.u, L.stats,
+                               L.rw.poisson_ws, q);
+            if (t != GDGS_OK) return t;
+            return launch_render_stats(L.rw.bins.num_pairs, cap, L.stats, q);
+        });
+        if (e != GDGS_OK) return e;
+        return finish_enqueue(r, L, p, st);
+    }
+
+    // A resumed run: more V-cycles of the same solve in the same slot.
+    gdgs_status enqueue_resume(gdgs::sched::Request* r) {
+        using namespace gdgs;
+        const Payload& p = payload.at(r->id);
+        const int W = r->W, H = r->H;
+        hipStream_t st = streams[r->stream];
+        const MgPlan* plan = this->plan(W, H, r->run_cycles, GDGS_MG_RESUME);
+        if (!plan) return GDGS_ERR_INVALID_ARGUMENT;
+        char* base = arena + r->slot.off;
+        SlotLayout L;
+        slot_layout(scene.K, W, H, r->cap, *plan, base, &L);
+        const float* bnd = p.boundary ? L.boundary : nullptr;
+        KeyBuilder kb;
+        kb.tag("server-resume").add(uid).add(base).add(W).add(H).add(r->cap).add(scene.K)
+            .add(bnd);
+        add_plan(kb, *plan);
+        gdgs_status e = with_graph(kb, st, [&](hipStream_t q) -> gdgs_status {
+            return launch_poisson(L.rw.grad, nullptr, bnd, W, H, *plan, L.u, L.stats,
+                                  L.rw.poisson_ws, q);
+        });
+        if (e != GDGS_OK) return e;
+        return finish_enqueue(r, L, p, st);
+    }
+
+    gdgs_status finish_enqueue(gdgs::sched::Request* r, const gdgs::SlotLayout& L,
+                               const gdgs::Payload& p, hipStream_t st) {
+        const size_t ubytes = sizeof(float) * 3 * (size_t)r->W * r->H;
+        GDGS_HIP_TRY(hipMemcpyAsync(p.u, L.u, ubytes, hipMemcpyDeviceToDevice, st));
+        GDGS_HIP_TRY(hipMemcpyAsync(&host_stats[r->stream], L.stats, sizeof(gdgs_stats),
+                                    hipMemcpyDeviceToHost, st));
+        GDGS_HIP_TRY(hipEventRecord(events[r->stream], st));
+        return GDGS_OK;
+    }
+
+    void fail(gdgs::sched::Request* r, gdgs_status e) {
+        // the request's device work may be partial: report it and retire the
+        // slot as if finished (its memory stays valid for later requests)
+        if (fatal == GDGS_OK) fatal = e;
+        running[r->stream] = -1;
+        r->cancelled = true;  // retire without resuming or learning from it
+        core->finish_run(r, false, r->num_pairs, true, r->cycles);
+        complete(*r, e);
+        core->forget(r->id);
+    }
+
+    void loop() {
+        using gdgs::sched::Next;
+        (void)hipSetDevice(dev);
+        std::unique_lock<std::mutex> lk(mu);
+        for (;;) {
+            bool progress = false;
+            for (size_t s = 0; s < streams.size(); ++s) {
+                const int64_t id = running[s];
+                if (id < 0) continue;
+                const hipError_t q = hipEventQuery(events[s]);
+                if (q == hipErrorNotReady) continue;
+                progress = true;
+                gdgs::sched::Request* r = core->find(id);
+                if (q != hipSuccess) {
+                    (void)hipGetLastError();
+                    fail(r, GDGS_ERR_HIP);
+                    continue;
+                }
+                const gdgs_stats& hs = host_stats[s];
+                const int cyc = std::max(hs.cycles[0], std::max(hs.cycles[1], hs.cycles[2]));
+                const Next nx = core->finish_run(r, hs.overflow != 0, hs.num_pairs,
+                                                 hs.converged != 0, cyc);
+                if (nx == Next::Resume) {
+                    const gdgs_status e = enqueue_resume(r);
+                    if (e != GDGS_OK) fail(r, e);
+                } else {
+                    running[s] = -1;
+                    if (nx == Next::Complete) {
+                        complete(*r, r->cancelled ? GDGS_ERR_CANCELLED : GDGS_OK);
+                        core->forget(id);
+                    }
+                }
+            }
+            for (int64_t id : core->take_rejected()) {
+                gdgs::sched::Request* r = core->find(id);
+                complete(*r, GDGS_ERR_BUDGET);
+                core->forget(id);
+                progress = true;
+            }
+            while (gdgs::sched::Request* r = core->admit(gdgs::steady_ns())) {
+                progress = true;
+                running[r->stream] = r->id;
+                const gdgs_status e = enqueue_first(r);
+                if (e != GDGS_OK) fail(r, e);
+            }
+            if (stop && core->waiting() == 0 && core->running() == 0) break;
+            if (progress) continue;
+            if (core->running() > 0) {
+                // device work in flight: poll its events again shortly
+                lk.unlock();
+                std::this_thread::yield();
+                lk.lock();
+            } else {
+                const int64_t t = core->next_arrival();
+                if (t == INT64_MAX)
+                    wake.wait(lk);
+                else
+                    wake.wait_for(lk, std::chrono::nanoseconds(std::max<int64_t>(0, t - gdgs::steady_ns())));
+            }
+        }
+    }
+};
+
+using namespace gdgs;
+
+namespace {
+
+#define SREQ(cond, ...)                       \
+    do {                                      \
+        if (!(cond)) {                        \
+            set_error(__VA_ARGS__);           \
+            return GDGS_ERR_INVALID_ARGUMENT; \
+        }                                     \
+    } while (0)
+
+bool al4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+int64_t gdgs_now_ns(void) { return steady_ns(); }
+
+gdgs_status gdgs_server_create(const gdgs_scene* scene, const gdgs_server_params* params,
+                               gdgs_server** out) {
+    clear_error();
+    SREQ(scene && params && out, "scene, params or out is null");
+    const int64_t K = scene->K;
+    SREQ(K >= 0 && K < (int64_t)0xFFFFFFFFll, "K = %lld out of range", (long long)K);
+    if (K > 0)
+        SREQ(scene->mean && scene->log_scale && scene->quat && scene->opacity && scene->value &&
+                 al4(scene->mean) && al4(scene->log_scale) && al4(scene->quat) &&
+                 al4(scene->opacity) && al4(scene->value),
+             "scene arrays must be non-null and 4-byte aligned");
+    SREQ(params->streams >= 1 && params->streams <= 16, "streams = %d, must be 1..16",
+         params->streams);
+    SREQ(params->hbm_budget >= (1 << 20), "hbm_budget must be at least 1 MiB");
+    SREQ(params->mg.flags == 0, "server solver flags must be 0");
+    MgPlan probe;
+    if (mg_plan(64, 64, &params->mg, &probe) != GDGS_OK) return GDGS_ERR_INVALID_ARGUMENT;
+
+    static std::atomic<uint64_t> uids{1};
+    gdgs_server* s = new gdgs_server();
+    s->uid = uids.fetch_add(1);
+    s->scene = *scene;
+    s->mg = params->mg;
+    s->arena_bytes = (size_t)params->hbm_budget & ~(size_t)255;
+    auto cleanup = [&](hipError_t e, const char* what) {
+        set_error("%s: %s", what, hipGetErrorString(e));
+        for (auto ev : s->events) (void)hipEventDestroy(ev);
+        for (auto st : s->streams) (void)hipStreamDestroy(st);
+        if (s->host_stats) (void)hipHostFree(s->host_stats);
+        if (s->arena) (void)hipFree(s->arena);
+        delete s;
+        return GDGS_ERR_HIP;
+    };
+    hipError_t e = hipGetDevice(&s->dev);
+    if (e != hipSuccess) return cleanup(e, "hipGetDevice");
+    e = hipMalloc(reinterpret_cast<void**>(&s->arena), s->arena_bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        s->arena = nullptr;
+        const gdgs_status r = cleanup(e, "allocating the memory budget");
+        return r == GDGS_ERR_HIP ? GDGS_ERR_BUDGET : r;
+    }
+    e = hipHostMalloc(reinterpret_cast<void**>(&s->host_stats),
+                      sizeof(gdgs_stats) * params->streams, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        s->host_stats = nullptr;
+        return cleanup(e, "hipHostMalloc");
+    }
+    for (int k = 0; k < params->streams; ++k) {
+        hipStream_t st = nullptr;
+        e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e != hipSuccess) return cleanup(e, "hipStreamCreate");
+        s->streams.push_back(st);
+        hipEvent_t ev = nullptr;
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess) return cleanup(e, "hipEventCreate");
+        s->events.push_back(ev);
+    }
+    s->running.assign(params->streams, -1);
+    sched::Core::Config cfg;
+    cfg.budget = s->arena_bytes;
+    cfg.streams = params->streams;
+    cfg.max_cycles = params->mg.max_cycles;
+    cfg.resume_cycles = 2;
+    cfg.initial_cap = std::max<int64_t>(1 << 16, 4 * K);
+    cfg.slot_bytes = [s](int32_t W, int32_t H, int64_t cap) { return s->slot_bytes(W, H, cap); };
+    s->core = new sched::Core(cfg);
+    s->thread = std::thread([s] { s->loop(); });
+    *out = s;
+    return GDGS_OK;
+}
+
+gdgs_status gdgs_server_submit(gdgs_server* srv, const gdgs_request* req, int64_t* id) {
+    clear_error();
+    SREQ(srv && req && id, "server, request or id is null");
+    const gdgs_camera& cam = req->cam;
+    SREQ(cam.W >= 3 && cam.H >= 3 && cam.W / 16 < 65535 && cam.H / 16 < 65535,
+         "image size %dx%d out of range", cam.W, cam.H);
+    SREQ(cam.fx > 0 && cam.fy > 0, "focal lengths must be positive");
+    SREQ(req->u && al4(req->u), "u is null or not 4-byte aligned");
+    SREQ(!req->boundary || al4(req->boundary), "boundary is not 4-byte aligned");
+    std::lock_guard<std::mutex> g(srv->mu);
+    SREQ(!srv->stop, "server is shutting down");
+    const int64_t rid = srv->next_id++;
+    const int64_t t = req->arrival_ns > 0 ? req->arrival_ns : steady_ns();
+    if (!srv->core->submit(rid, req->tag, cam.W, cam.H, t)) {
+        set_error("a %dx%d request needs more than the %zu-byte budget", cam.W, cam.H,
+                  srv->arena_bytes);
+        return GDGS_ERR_BUDGET;
+    }
+    srv->payload[rid] = Payload{cam, req->boundary, req->u};
+    ++srv->submitted;
+    *id = rid;
+    srv->wake.notify_all();
+    return GDGS_OK;
+}
+
+gdgs_status gdgs_server_poll(gdgs_server* srv, gdgs_completion* out, int32_t max, int32_t wait_us,
+                             int32_t* n) {
+    clear_error();
+    SREQ(srv && n && (max == 0 || out) && max >= 0, "bad poll arguments");
+    std::unique_lock<std::mutex> lk(srv->mu);
+    if (srv->done.empty() && wait_us > 0)
+        srv->done_cv.wait_for(lk, std::chrono::microseconds(wait_us),
+                              [&] { return !srv->done.empty(); });
+    int32_t k = 0;
+    while (k < max && !srv->done.empty()) {
+        out[k++] = srv->done.front();
+        srv->done.pop_front();
+    }
+    *n = k;
+    return GDGS_OK;
+}
+
+gdgs_status gdgs_server_cancel(gdgs_server* srv, int64_t id) {
+    clear_error();
+    SREQ(srv, "server is null");
+    std::lock_guard<std::mutex> g(srv->mu);
+    sched::Request* r = srv->core->find(id);
+    SREQ(r && r->phase != sched::Phase::Done && !r->cancelled,
+         "request %lld is unknown, finished or already cancelled", (long long)id);
+    if (srv->core->cancel(id)) {
+        srv->complete(*r, GDGS_ERR_CANCELLED);
+        srv->core->forget(id);
+    }
+    srv->wake.notify_all();
+    return GDGS_OK;
+}
+
+gdgs_status gdgs_server_query(gdgs_server* srv, gdgs_server_state* out) {
+    clear_error();
+    SREQ(srv && out, "server or out is null");
+    std::lock_guard<std::mutex> g(srv->mu);
+    const sched::Arena& a = srv->core->pool().arena();
+    out->budget_bytes = (int64_t)a.size();
+    out->used_bytes = (int64_t)a.used();
+    out->peak_bytes = (int64_t)a.peak();
+    out->submitted = srv->submitted;
+    out->completed = srv->completed;
+    out->waiting = (int32_t)srv->core->waiting();
+    out->running = srv->core->running();
+    out->idle_slots = (int32_t)srv->core->pool().idle_count();
+    out->streams = (int32_t)srv->streams.size();
+    if (srv->fatal != GDGS_OK) {
+        set_error("a request failed on the device (%d)", (int)srv->fatal);
+        return srv->fatal;
+    }
+    return GDGS_OK;
+}
+
+gdgs_status gdgs_server_destroy(gdgs_server* srv) {
+    clear_error();
+    if (!srv) return GDGS_OK;
+    {
+        std::lock_guard<std::mutex> g(srv->mu);
+        srv->stop = true;
+        std::vector<int64_t> ids;
+        for (const auto& kv : srv->payload) ids.push_back(kv.first);
+        for (int64_t id : ids) {
+            sched::Request* r = srv->core->find(id);
+            if (r && srv->core->cancel(id)) {
+                srv->complete(*r, GDGS_ERR_CANCELLED);
+                srv->core->forget(id);
+            }
+        }
+        srv->wake.notify_all();
+    }
+    if (srv->thread.joinable()) srv->thread.join();
+    gdgs_status st = GDGS_OK;
+    for (auto s : srv->streams)
+        if (hipStreamSynchronize(s) != hipSuccess) st = GDGS_ERR_HIP;
+    for (auto ev : srv->events) (void)hipEventDestroy(ev);
+    for (auto s : srv->streams) (void)hipStreamDestroy(s);
+    if (srv->host_stats) (void)hipHostFree(srv->host_stats);
+    if (srv->arena) (void)hipFree(srv->arena);
+    delete srv->core;
+    delete srv;
+    if (st != GDGS_OK) set_error("a server stream failed while draining");
+    return st;
+}
+
+}  // extern "C"

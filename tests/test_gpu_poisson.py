@@ -115,6 +115,37 @@ def test_warm_start_continues_from_the_given_iterate():
     assert G.read_stats(st3)["cycles"] == [1, 1, 1]
 
 
+def test_resumed_calls_equal_one_call_bit_for_bit():
+    """GDGS_MG_RESUME: 1 + 2 + 3 cycles in three calls == 6 cycles in one call,
+    also after a channel has converged (its flag and cycle count carry over)."""
+    H, W = 257, 390
+    rng = np.random.default_rng(4)
+    rho = np.zeros((3, H, W))
+    rho[:, 1:-1, 1:-1] = rng.normal(0, 0.05, (3, H - 2, W - 2))
+    rho[2] = 0.0                      # channel 2 is exact from the start
+    ring = wl.reference_image(H, W, seed=1)
+    ring[2] = 0.0
+    r = torch.from_numpy(rho.astype(np.float32)).cuda()
+    b = torch.from_numpy(ring.astype(np.float32)).cuda()
+    for tol in (0.0, 1e-5):
+        one, st1 = G.gdgs_poisson_solve_rhs(r, b, W, H, G.mg_params(tol=tol, max_cycles=6))
+        torch.cuda.synchronize()
+        s1 = G.read_stats(st1)
+        u = torch.empty_like(one)
+        st = G.new_stats()
+        ws = G.workspace(G.api.poisson_workspace_size(W, H))
+        for k, cyc in enumerate((1, 2, 3)):
+            G.gdgs_poisson_solve_rhs(r, b, W, H, G.mg_params(tol=tol, max_cycles=cyc,
+                                                           flags=G.api.RESUME if k else 0),
+                                     u=u, stats=st, ws=ws)
+        torch.cuda.synchronize()
+        s3 = G.read_stats(st)
+        say(f"[poisson] tol {tol}: one call {s1['cycles']}, resumed {s3['cycles']}")
+        assert s3["cycles"] == s1["cycles"] and s3["converged"] == s1["converged"]
+        assert torch.equal(u, one)
+    assert s1["cycles"][2] == 0
+
+
 def test_zero_rhs_zero_ring_is_immediately_exact():
     u, st = solve_rhs(np.zeros((3, 40, 50)), None)
     assert np.all(u == 0) and st["converged"] and st["cycles"] == [0, 0, 0]

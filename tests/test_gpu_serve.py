@@ -1,0 +1,121 @@
+"""Render server (continuous batching of mixed-size views of one resident
+scene): results in the mix equal the same request alone, capacity re-runs,
+resumed solves, budget admission, cancellation and scheduled arrivals."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2405_05446_amd as G
+import workloads as wl
+from oracle.render import render as orender
+from tests.gpu_util import say, np_
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(64, 48), (128, 96), (200, 160), (320, 180)]
+MG = dict(tol=1e-6, max_cycles=30)
+
+
+@pytest.fixture(scope="module")
+def scene():
+    sc = wl.make_scene(20000, seed=0, z=(2.0, 20.0), ls=(-5.0, 0.7))
+    return sc, G.DeviceScene.from_host(sc)
+
+
+def rings():
+    return {(W, H): torch.from_numpy(wl.reference_image(H, W, seed=1).astype(np.float32)).cuda()
+            for W, H in SIZES}
+
+
+def requests(n, seed=7):
+    rng = np.random.default_rng(seed)
+    return [(SIZES[int(rng.integers(len(SIZES)))], i) for i in range(n)]
+
+
+def test_mixed_equals_alone_and_plain_renderer(scene):
+    sc, ds = scene
+    reqs = requests(24)
+    ring = rings()
+    # alone: one request at a time through a one-stream server
+    alone = {}
+    with G.Server(ds, budget=1 << 30, streams=1, mg=G.mg_params(**MG)) as srv:
+        for (W, H), i in reqs:
+            rid, u = srv.submit(wl.make_camera(W, H, pose_index=i), ring[(W, H)], tag=i)
+            c = srv.drain(1)[0]
+            assert c["status"] == 0 and c["converged"] == 1 and c["tag"] == i
+            alone[i] = u.clone()
+    # mixed: everything at once over four streams
+    with G.Server(ds, budget=1 << 30, streams=4, mg=G.mg_params(**MG)) as srv:
+        for (W, H), i in reqs:
+            srv.submit(wl.make_camera(W, H, pose_index=i), ring[(W, H)], tag=i)
+        done = srv.drain(len(reqs))
+        st = srv.state()
+    say(f"[serve] mixed: {len(done)} done, state {st}")
+    assert sorted(c["tag"] for c in done) == list(range(len(reqs)))
+    for c in done:
+        assert c["status"] == 0 and c["converged"] == 1
+        assert torch.equal(c["u"], alone[c["tag"]]), c
+        assert c["admit_ns"] >= c["arrival_ns"] and c["done_ns"] >= c["admit_ns"]
+    assert st["running"] == 0 and st["waiting"] == 0 and st["peak_bytes"] <= st["budget_bytes"]
+    # the plain per-request path gives the same bits
+    for (W, H), i in reqs[:6]:
+        r = G.Renderer(ds, W, H, G.mg_params(**MG))
+        u = r.render(wl.make_camera(W, H, pose_index=i), ring[(W, H)])
+        torch.cuda.synchronize()
+        assert torch.equal(u, alone[i])
+
+
+def test_small_view_against_the_oracle(scene):
+    sc, ds = scene
+    W, H = 64, 48
+    ring = torch.from_numpy(wl.reference_image(H, W, seed=1).astype(np.float32)).cuda()
+    cam = wl.make_camera(W, H, pose_index=3)
+    with G.Server(ds, budget=256 << 20, streams=2, mg=G.mg_params(**MG)) as srv:
+        srv.submit(cam, ring)
+        c = srv.drain(1)[0]
+    o = orender(sc, cam, np_(ring).astype(np.float64))
+    err = np.abs(np_(c["u"]) - o["u"]).max()
+    say(f"[serve] 64x48 vs oracle max-abs {err:.3e}")
+    assert c["status"] == 0 and err <= 1e-4
+
+
+def test_capacity_rerun_and_cycle_limit():
+    # large splats: far more pairs than the initial capacity of 65536
+    sc = wl.make_scene(5000, seed=5, z=(2.0, 6.0), ls=(-2.0, 0.3))
+    ds = G.DeviceScene.from_host(sc)
+    W, H = 320, 180
+    cam = wl.make_camera(W, H, pose_index=2)
+    with G.Server(ds, budget=1 << 30, streams=2, mg=G.mg_params(**MG)) as srv:
+        srv.submit(cam, None)
+        c = srv.drain(1)[0]
+    say(f"[serve] big splats: {c['num_pairs']} pairs, attempts {c['attempts']}")
+    assert c["status"] == 0 and c["num_pairs"] > 65536 and c["attempts"] >= 2
+    r = G.Renderer(ds, W, H, G.mg_params(**MG))
+    assert torch.equal(r.render(cam), c["u"])
+    # one V-cycle allowed: reported as not converged, 1 cycle
+    with G.Server(ds, budget=1 << 30, streams=1, mg=G.mg_params(tol=1e-12, max_cycles=1)) as srv:
+        srv.submit(cam, None)
+        c1 = srv.drain(1)[0]
+    assert c1["status"] == 0 and c1["converged"] == 0 and c1["cycles"] == 1
+
+
+def test_budget_cancel_and_scheduled_arrival(scene):
+    sc, ds = scene
+    with G.Server(ds, budget=64 << 20, streams=2, mg=G.mg_params(**MG)) as srv:
+        with pytest.raises(G.GdgsError) as e:
+            srv.submit(wl.make_camera(1920, 1080), None)      # cannot fit 64 MiB
+        assert e.value.status == 4
+        # a request scheduled 30 s ahead is cancelled while it waits
+        far = G.now_ns() + 30_000_000_000
+        rid, _ = srv.submit(wl.make_camera(64, 48), None, tag=5, arrival_ns=far)
+        srv.cancel(rid)
+        c = srv.drain(1)[0]
+        assert c["id"] == rid and c["status"] == 8
+        with pytest.raises(G.GdgsError):
+            srv.cancel(rid)
+        # a request scheduled 50 ms ahead does not start before then
+        t = G.now_ns() + 50_000_000
+        srv.submit(wl.make_camera(64, 48, pose_index=1), None, tag=6, arrival_ns=t)
+        c = srv.drain(1)[0]
+        assert c["status"] == 0 and c["arrival_ns"] == t and c["admit_ns"] >= t
+        assert srv.state()["completed"] == 2

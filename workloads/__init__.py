@@ -77,6 +77,24 @@ CONFIGS = {
                   levels=8, tol=1e-6, ring="reference"),
 }
 
+# Serving mix: request sizes drawn uniformly from these (W, H).
+SERVE_SIZES = [(256, 256), (512, 512), (800, 800), (1920, 1080)]
+
+
+def serving_requests(n: int = 256, seed: int = 7):
+    """n requests: (W, H) uniform over SERVE_SIZES and pose index i (pose(i)
+    is the camera pose of request i; focal length W)."""
+    rng = np.random.default_rng(seed)
+    return [(SERVE_SIZES[int(k)], i) for i, k in enumerate(rng.integers(0, len(SERVE_SIZES), n))]
+
+
+def poisson_arrivals(n: int, qps: float, seed: int = 7) -> np.ndarray:
+    """Arrival offsets in seconds of a Poisson process of rate qps (first at 0)."""
+    rng = np.random.default_rng(seed + 1)
+    gaps = rng.exponential(1.0 / qps, n)
+    gaps[0] = 0.0
+    return np.cumsum(gaps)
+
 
 def make_scene(K: int, seed: int = 0, z=(2.0, 6.0), ls=(-4.0, 0.5),
                xy=(-1.0, 1.0)) -> Scene:
