@@ -44,8 +44,15 @@
 namespace gdgs {
 namespace {
 
-constexpr int kTX = 64;
-constexpr int kTY = 32;
+// Tiles of the grid kernels: 64 x 32 where the grid is large; 32 x 16 on
+// grids too small to fill the chip with 64 x 32 tiles, whose kernels are
+// bound by the latency of one block's chain of phases rather than by
+// bandwidth (a smaller tile shortens that chain).
+constexpr int kTX = 64, kTY = 32;
+constexpr int kTXs = 32, kTYs = 16;
+constexpr int kTXf = 32, kTYf = 32;   // finest grid
+constexpr int kSmallTileBelow = 4096;
+constexpr int kLdsTopCells = 4096;    // largest grid solved inside one workgroup  // blocks of 64 x 32 under which small tiles are used
 constexpr int kDivTX = 64;
 constexpr int kDivTY = 4;     // threads per block = kDivTX * kDivTY
 constexpr int kDivRows = 16;  // rows per block of the divergence kernel
@@ -300,32 +307,32 @@ struct TileId {
 };
 
 // Thread t of a 256-thread block owns the tile cells t, t + 256, ...
-constexpr int kCellsPerThread = kTX * kTY / 256;
 
 // Pre-smoothing + residual + restriction to the next grid.  FINE (the finest
 // grid only): record the largest change of u and evaluate the residual in
 // FP64; coarser grids carry small corrections and stay in FP32.
-template <int NU, bool FINE>
+template <int NU, bool FINE, int TX, int TY>
 __global__ __launch_bounds__(256) void k_mg_pre(LevelDev L, LevelDev C, int zero_guess,
                                                 const int* __restrict__ done,
                                                 double* __restrict__ part) {
     constexpr int HALO = 2 * NU + 2;
-    constexpr int RX = kTX + 2 * HALO, RY = kTY + 2 * HALO;
+    constexpr int CPT = TX * TY / 256;
+    constexpr int RX = TX + 2 * HALO, RY = TY + 2 * HALO;
     __shared__ float su[RY * RX];
     __shared__ float sf[RY * RX];
     __shared__ double sh[3 * 4];
     const TileId id;
     const int c = id.c;
     if (done[c]) return;
-    const int gi0 = id.ty * kTY - HALO, gj0 = id.tx * kTX - HALO;
+    const int gi0 = id.ty * TY - HALO, gj0 = id.tx * TX - HALO;
     load_region<RX, RY>(su, sf, L, L.u, c, gi0, gj0, zero_guess != 0);
     __syncthreads();
-    float before[kCellsPerThread];
+    float before[CPT];
     if (FINE) {
 #pragma unroll
-        for (int k = 0; k < kCellsPerThread; ++k) {
+        for (int k = 0; k < CPT; ++k) {
             const int idx = threadIdx.x + 256 * k;
-            before[k] = su[(HALO + idx / kTX) * RX + HALO + idx % kTX];
+            before[k] = su[(HALO + idx / TX) * RX + HALO + idx % TX];
         }
         __syncthreads();  // every snapshot is taken before any cell changes
     }
@@ -334,9 +341,9 @@ __global__ __launch_bounds__(256) void k_mg_pre(LevelDev L, LevelDev C, int zero
     float* u = L.ub + (size_t)c * L.cs;
     double dmax = 0.0;
 #pragma unroll
-    for (int k = 0; k < kCellsPerThread; ++k) {
+    for (int k = 0; k < CPT; ++k) {
         const int idx = threadIdx.x + 256 * k;
-        const int r = HALO + idx / kTX, q = HALO + idx % kTX;
+        const int r = HALO + idx / TX, q = HALO + idx % TX;
         const int gi = gi0 + r, gj = gj0 + q;
         if (gi < N && gj < M) {
             const float v = su[r * RX + q];
@@ -348,7 +355,7 @@ __global__ __launch_bounds__(256) void k_mg_pre(LevelDev L, LevelDev C, int zero
     // residual on rows/cols [HALO-1, HALO+T-1], zero off the interior; thread t
     // owns every TPR-th cell of one row
     {
-        constexpr int ZR = kTY + 1, ZC = kTX + 1;
+        constexpr int ZR = TY + 1, ZC = TX + 1;
         constexpr int TPR = 256 / ZR;
         const int t = threadIdx.x;
         if (t < ZR * TPR) {
@@ -374,10 +381,10 @@ __global__ __launch_bounds__(256) void k_mg_pre(LevelDev L, LevelDev C, int zero
         }
     }
     __syncthreads();
-    const int I0 = id.ty * (kTY / 2), J0 = id.tx * (kTX / 2);
+    const int I0 = id.ty * (TY / 2), J0 = id.tx * (TX / 2);
     float* fc = C.fw + (size_t)c * C.cs;
-    for (int idx = threadIdx.x; idx < (kTY / 2) * (kTX / 2); idx += blockDim.x) {
-        const int I = I0 + idx / (kTX / 2), J = J0 + idx % (kTX / 2);
+    for (int idx = threadIdx.x; idx < (TY / 2) * (TX / 2); idx += blockDim.x) {
+        const int I = I0 + idx / (TX / 2), J = J0 + idx % (TX / 2);
         if (I >= 1 && I <= C.n && J >= 1 && J <= C.m) {
             const int o = (2 * I - gi0) * RX + (2 * J - gj0);
             const float v = 4.f * sf[o] + 2.f * (sf[o - 1] + sf[o + 1] + sf[o - RX] + sf[o + RX]) +
@@ -397,13 +404,14 @@ __global__ __launch_bounds__(256) void k_mg_pre(LevelDev L, LevelDev C, int zero
 
 // Prolongation + correction + post-smoothing.  FINE (the finest grid only):
 // also the residual and correction norms of the cycle.
-template <int NU, bool FINE>
+template <int NU, bool FINE, int TX, int TY>
 __global__ __launch_bounds__(256) void k_mg_post(LevelDev L, LevelDev C,
                                                  const int* __restrict__ done,
                                                  double* __restrict__ part) {
     constexpr bool NORM = FINE;
     constexpr int HALO = 2 * NU + 2;
-    constexpr int RX = kTX + 2 * HALO, RY = kTY + 2 * HALO;
+    constexpr int CPT = TX * TY / 256;
+    constexpr int RX = TX + 2 * HALO, RY = TY + 2 * HALO;
     constexpr int CX = RX / 2 + 2, CY = RY / 2 + 2;  // staged coarse tile
     __shared__ float su[RY * RX];
     __shared__ float sf[RY * RX];
@@ -412,7 +420,7 @@ __global__ __launch_bounds__(256) void k_mg_post(LevelDev L, LevelDev C,
     const TileId id;
     const int c = id.c;
     if (done[c]) return;
-    const int gi0 = id.ty * kTY - HALO, gj0 = id.tx * kTX - HALO;
+    const int gi0 = id.ty * TY - HALO, gj0 = id.tx * TX - HALO;
     load_region<RX, RY>(su, sf, L, L.ub, c, gi0, gj0, false);
     // coarse rows (gi0 >> 1) .. ((gi0 + RY - 1) >> 1) + 1, columns alike
     const int ci0 = gi0 >> 1, cj0 = gj0 >> 1;
@@ -428,12 +436,12 @@ __global__ __launch_bounds__(256) void k_mg_post(LevelDev L, LevelDev C,
         }
     }
     __syncthreads();
-    float before[kCellsPerThread];
+    float before[CPT];
     if (NORM) {
 #pragma unroll
-        for (int k = 0; k < kCellsPerThread; ++k) {
+        for (int k = 0; k < CPT; ++k) {
             const int idx = threadIdx.x + 256 * k;
-            before[k] = su[(HALO + idx / kTX) * RX + HALO + idx % kTX];
+            before[k] = su[(HALO + idx / TX) * RX + HALO + idx % TX];
         }
         __syncthreads();  // every snapshot is taken before any cell changes
     }
@@ -459,9 +467,9 @@ __global__ __launch_bounds__(256) void k_mg_post(LevelDev L, LevelDev C,
     const int N = L.n + 2, M = L.m + 2;
     double rmax = 0.0, umax = 0.0, rss = 0.0, dmax = 0.0;
 #pragma unroll
-    for (int k = 0; k < kCellsPerThread; ++k) {
+    for (int k = 0; k < CPT; ++k) {
         const int idx = threadIdx.x + 256 * k;
-        const int r = HALO + idx / kTX, q = HALO + idx % kTX;
+        const int r = HALO + idx / TX, q = HALO + idx % TX;
         const int gi = gi0 + r, gj = gj0 + q;
         const int o = r * RX + q;
         // ring cells too: they keep the boundary (or zero) values in both buffers
@@ -758,19 +766,31 @@ int lds_budget() {
     return cached;
 }
 
+bool small_tiles(const LevelDev& L) {
+    const int nb = ((L.m + 2 + kTX - 1) / kTX) * ((L.n + 2 + kTY - 1) / kTY) * 3;
+    return nb < kSmallTileBelow;
+}
+
 template <int NU>
 gdgs_status launch_pre(const LevelDev& L, const LevelDev& C, bool zero, bool delta,
                        const int* done, double* part, hipStream_t st) {
-    dim3 grid((L.m + 2 + kTX - 1) / kTX, (L.n + 2 + kTY - 1) / kTY, 3);
     hipEvent_t ev0, ev1;
     const bool timed = delta && timer_events("mg_pre_fine", &ev0, &ev1);
     if (timed) GDGS_HIP_TRY(hipEventRecord(ev0, st));
-    if (delta)
-        hipLaunchKernelGGL((k_mg_pre<NU, true>), grid, dim3(256), 0, st, L, C, zero ? 1 : 0,
+    const int z = zero ? 1 : 0;
+    if (delta) {
+        dim3 grid((L.m + 2 + kTXf - 1) / kTXf, (L.n + 2 + kTYf - 1) / kTYf, 3);
+        hipLaunchKernelGGL((k_mg_pre<NU, true, kTXf, kTYf>), grid, dim3(256), 0, st, L, C, z,
                            done, part);
-    else
-        hipLaunchKernelGGL((k_mg_pre<NU, false>), grid, dim3(256), 0, st, L, C, zero ? 1 : 0,
+    } else if (small_tiles(L)) {
+        dim3 grid((L.m + 2 + kTXs - 1) / kTXs, (L.n + 2 + kTYs - 1) / kTYs, 3);
+        hipLaunchKernelGGL((k_mg_pre<NU, false, kTXs, kTYs>), grid, dim3(256), 0, st, L, C, z,
                            done, part);
+    } else {
+        dim3 grid((L.m + 2 + kTX - 1) / kTX, (L.n + 2 + kTY - 1) / kTY, 3);
+        hipLaunchKernelGGL((k_mg_pre<NU, false, kTX, kTY>), grid, dim3(256), 0, st, L, C, z,
+                           done, part);
+    }
     if (timed) GDGS_HIP_TRY(hipEventRecord(ev1, st));
     return GDGS_OK;
 }
@@ -778,14 +798,22 @@ gdgs_status launch_pre(const LevelDev& L, const LevelDev& C, bool zero, bool del
 template <int NU>
 gdgs_status launch_post(const LevelDev& L, const LevelDev& C, bool fine, const int* done,
                         double* part, hipStream_t st) {
-    dim3 grid((L.m + 2 + kTX - 1) / kTX, (L.n + 2 + kTY - 1) / kTY, 3);
     hipEvent_t ev0, ev1;
     const bool timed = fine && timer_events("mg_post_fine", &ev0, &ev1);
     if (timed) GDGS_HIP_TRY(hipEventRecord(ev0, st));
-    if (fine)
-        hipLaunchKernelGGL((k_mg_post<NU, true>), grid, dim3(256), 0, st, L, C, done, part);
-    else
-        hipLaunchKernelGGL((k_mg_post<NU, false>), grid, dim3(256), 0, st, L, C, done, part);
+    if (fine) {
+        dim3 grid((L.m + 2 + kTXf - 1) / kTXf, (L.n + 2 + kTYf - 1) / kTYf, 3);
+        hipLaunchKernelGGL((k_mg_post<NU, true, kTXf, kTYf>), grid, dim3(256), 0, st, L, C, done,
+                           part);
+    } else if (small_tiles(L)) {
+        dim3 grid((L.m + 2 + kTXs - 1) / kTXs, (L.n + 2 + kTYs - 1) / kTYs, 3);
+        hipLaunchKernelGGL((k_mg_post<NU, false, kTXs, kTYs>), grid, dim3(256), 0, st, L, C,
+                           done, part);
+    } else {
+        dim3 grid((L.m + 2 + kTX - 1) / kTX, (L.n + 2 + kTY - 1) / kTY, 3);
+        hipLaunchKernelGGL((k_mg_post<NU, false, kTX, kTY>), grid, dim3(256), 0, st, L, C,
+                           done, part);
+    }
     if (timed) GDGS_HIP_TRY(hipEventRecord(ev1, st));
     return GDGS_OK;
 }
@@ -840,6 +868,9 @@ gdgs_status mg_plan(int W, int H, const gdgs_mg_params* mg, MgPlan* plan) {
         const size_t cells = (size_t)(p.n[lc - 1] + 2) * (p.m[lc - 1] + 2);
         const size_t scratch = (lc - 1 < L - 1) ? sizeof(float) * cells : 0;
         if (bytes + 2 * sizeof(float) * cells + scratch > budget) break;
+        // a larger top grid would leave the chip idle while one workgroup per
+        // channel smooths it; the tiled kernels take it instead
+        if (lc - 1 < L - 1 && cells > (size_t)kLdsTopCells) break;
         bytes += 2 * sizeof(float) * cells;
         --lc;
     }
@@ -894,7 +925,7 @@ struct PoissonWs {
 
 int norm_blocks(const MgPlan& p) {
     if (p.lc == 0) return 1;
-    return ((p.m[0] + 2 + kTX - 1) / kTX) * ((p.n[0] + 2 + kTY - 1) / kTY);
+    return ((p.m[0] + 2 + kTXf - 1) / kTXf) * ((p.n[0] + 2 + kTYf - 1) / kTYf);
 }
 
 int div_blocks(int W, int H) {
