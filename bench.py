@@ -42,6 +42,30 @@ MG_POST_BYTES_PER_POINT = 13.0
 RASTER_FLOPS_PER_CONTRIB = 26.0
 
 
+PROFILE = os.path.join(ROOT, "profiles", "hbm_counters_render_1080p_1M.md")
+
+
+def measured_traffic(kernel: str):
+    """Calibrated HBM bytes per launch of `kernel` from the committed rocprofv3
+    counter summary, or None when there is none or the kernel's source file
+    has changed since the counters were taken (its hash no longer matches)."""
+    import hashlib
+    try:
+        lines = open(PROFILE).read().splitlines()
+    except OSError:
+        return None
+    for ln in lines:
+        cells = [c.strip() for c in ln.strip().strip("|").split("|")]
+        if len(cells) == 7 and cells[0] == f"`{kernel}`":
+            src = os.path.join(ROOT, "paper_2405_05446_amd", "csrc", cells[1])
+            try:
+                h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+            except OSError:
+                return None
+            return int(cells[6]) if h == cells[2] else None
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -234,23 +258,30 @@ def main():
     post_us = float(np.mean(post_all)) * 1e3
     post_gbs = MG_POST_BYTES_PER_POINT * 3 * npts / (post_us * 1e-6) / 1e9
     per_frame = {"raster": raster_us, "mg_post_fine": post_us * mean_cycles}
+    k_raster, k_post = "k_raster_fwd<false>", "k_mg_post<2, true, 32, 32>"
+    t_raster, t_post = measured_traffic(k_raster), measured_traffic(k_post)
     kern = {
-        "raster": {"kernel": "k_raster_fwd", "bound": "alu", "achieved": round(raster_tflops, 3),
+        "raster": {"kernel": k_raster, "bound": "alu", "achieved": round(raster_tflops, 3),
                    "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                   "frac": round(raster_tflops / VALU_PEAK_TFLOPS, 4), "traffic": None,
+                   "frac": round(raster_tflops / VALU_PEAK_TFLOPS, 4), "traffic": t_raster,
                    "avg_launch_us": round(raster_us, 2), "launches_per_step": 1,
                    "work_per_launch": f"{RASTER_FLOPS_PER_CONTRIB:.0f} flop x "
                                       f"{float(np.mean(contrib)):.4g} contributions"},
-        "mg_post_fine": {"kernel": "k_mg_post<2,true> (finest grid)", "bound": "hbm",
+        "mg_post_fine": {"kernel": k_post, "bound": "hbm",
                          "achieved": round(post_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(post_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                         "frac": round(post_gbs / HBM_PEAK_GBS, 4), "traffic": t_post,
                          "avg_launch_us": round(post_us, 2),
                          "launches_per_step": round(mean_cycles, 2),
                          "work_per_launch": f"{MG_POST_BYTES_PER_POINT:.0f} B x 3 x {npts} points"},
     }
+    if t_post is not None:
+        kern["mg_post_fine"]["traffic_GBs"] = round(t_post / (post_us * 1e-6) / 1e9, 1)
     dominant = max(per_frame, key=per_frame.get)
     poisson_bytes = 3 * npts * (MG_BYTES_PER_POINT_CYCLE * mean_cycles + 16.0)
     poisson_gbs = poisson_bytes / (mean_stage[3] * 1e-3) / 1e9
+    # the same stage against the unfused model (each red-black sweep reading u
+    # and f and writing u: 88 B per point per cycle with the hierarchy)
+    unfused_gbs = 3 * npts * 88.0 * mean_cycles / (mean_stage[3] * 1e-3) / 1e9
 
     out = {
         "metric": METRIC,
@@ -275,7 +306,10 @@ def main():
         "kernels": kern,
         "poisson_stage": {"achieved_GBs": round(poisson_gbs, 1),
                           "frac": round(poisson_gbs / HBM_PEAK_GBS, 4),
-                          "model": "26 B x 4/3 per point per channel per V-cycle + 16 B setup"},
+                          "model": "26 B x 4/3 per point per channel per V-cycle + 16 B setup "
+                                   "(two fused smoothing passes per grid per cycle)",
+                          "unfused_model_GBs": round(unfused_gbs, 1),
+                          "unfused_model_frac": round(unfused_gbs / HBM_PEAK_GBS, 4)},
     }
     if not args.no_serve:
         out["serving"] = serving_leg(G, wl, torch, args.serve_requests, args.serve_streams)
