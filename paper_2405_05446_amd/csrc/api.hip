@@ -111,6 +111,40 @@ hipStream_t capture_stream(int dev) {
 }
 
 
+bool channel_streams(hipStream_t st, ChannelStreams* out) {
+    static const bool enabled = [] {
+        const char* e = std::getenv("GDGS_CHANNEL_STREAMS");
+        return !(e && e[0] == '0');
+    }();
+    if (!enabled) return false;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    thread_local std::map<std::pair<int, hipStream_t>, ChannelStreams> table;
+    const auto k = std::make_pair(dev, st);
+    auto it = table.find(k);
+    if (it != table.end()) {
+        *out = it->second;
+        return true;
+    }
+    ChannelStreams c{};
+    bool ok = true;
+    for (int i = 0; i < 2 && ok; ++i)
+        ok = hipStreamCreateWithFlags(&c.aux[i], hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&c.fork, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; i < 2 && ok; ++i)
+        ok = hipEventCreateWithFlags(&c.join[i], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        return false;
+    }
+    table.emplace(k, c);
+    *out = c;
+    return true;
+}
+
 bool timer_active(const char* name) {
     const KernelTimer* ts = kernel_timers();
     for (int k = 0; k < kMaxTimers; ++k)
@@ -482,12 +516,9 @@ static gdgs_status poisson_common(const float* grad, const float* rho, const flo
     KeyBuilder kb;
     kb.tag("poisson").add(grad).add(rho).add(boundary).add(W).add(H).add(u).add(stats_dev).add(ws);
     add_plan(kb, plan);
-    return with_graph(
-        kb, as_stream(stream),
-        [&](hipStream_t s) {
-            return launch_poisson(grad, rho, boundary, W, H, plan, u, stats_dev, ws, s, &kb);
-        },
-        {"mg_pre_fine", "mg_post_fine"});
+    // the solve caches its own graph segments (one per colour channel)
+    return launch_poisson(grad, rho, boundary, W, H, plan, u, stats_dev, ws, as_stream(stream),
+                          &kb);
 }
 
 gdgs_status gdgs_poisson_solve(const float* grad, const float* boundary, int32_t W, int32_t H,
@@ -546,17 +577,19 @@ gdgs_status gdgs_render(const gdgs_scene* scene, const gdgs_camera* cam, const f
     kb.tag("render").add(K).add(W).add(H).add(pair_capacity).add(ws).add(sc.opacity)
         .add(sc.value).add(boundary).add(u).add(stats_dev);
     add_plan(kb, plan);
+    KeyBuilder kr = kb;
+    kr.tag("bin+raster");
     TRY(with_graph(
-        kb, st,
+        kr, st,
         [&](hipStream_t s) -> gdgs_status {
             TRY(launch_bin_sort(r.proj, K, W, H, r.bins, b, s));
-            TRY(launch_raster(r.proj, sc.opacity, sc.value, K, r.bins, W, H, r.grad, r.raster_ws,
-                              s));
-            TRY(launch_poisson(r.grad, nullptr, boundary, W, H, plan, u, stats_dev, r.poisson_ws,
-                               s, &kb));
-            return launch_render_stats(r.bins.num_pairs, pair_capacity, stats_dev, s);
+            return launch_raster(r.proj, sc.opacity, sc.value, K, r.bins, W, H, r.grad,
+                                 r.raster_ws, s);
         },
-        {"raster", "mg_pre_fine", "mg_post_fine"}));
+        {"raster"}));
+    TRY(launch_poisson(r.grad, nullptr, boundary, W, H, plan, u, stats_dev, r.poisson_ws, st,
+                       &kb));
+    TRY(launch_render_stats(r.bins.num_pairs, pair_capacity, stats_dev, st));
     if (sync_stats) {
         GDGS_HIP_TRY(hipStreamSynchronize(st));
         gdgs_stats h;

@@ -36,6 +36,17 @@ int& graphs_flag();
 hipStream_t capture_stream(int dev);
 bool timer_active(const char* name);
 
+// Two helper streams and fork/join events bound to a caller stream (created
+// on first use, per thread; kept until the process ends).  false when they
+// cannot be created or the environment sets GDGS_CHANNEL_STREAMS=0 (then the
+// solve runs all channels in each launch on the caller's stream).
+struct ChannelStreams {
+    hipStream_t aux[2];
+    hipEvent_t fork;
+    hipEvent_t join[2];
+};
+bool channel_streams(hipStream_t st, ChannelStreams* out);
+
 // Key parts shared by the entry points (defined in api.hip).
 void add_plan(KeyBuilder& kb, const MgPlan& p);
 void add_proj(KeyBuilder& kb, const gdgs_proj& p);

@@ -38,6 +38,8 @@
 //  * a finalize kernel evaluates eta = ||r||_inf / (8 ||w||_inf + ||b||_inf)
 //    per channel and raises a device flag; every later kernel of a finished
 //    channel returns immediately, so no host synchronisation is needed.
+#include <functional>
+
 #include "graph.hpp"
 #include "internal.hpp"
 
@@ -57,7 +59,8 @@ constexpr int kDivTX = 64;
 constexpr int kDivTY = 4;     // threads per block = kDivTX * kDivTY
 constexpr int kDivRows = 16;  // rows per block of the divergence kernel
 constexpr int kLdsThreads = 1024;
-constexpr int kCounters = 72; // finalize counters: [0] setup, [1 + cycle]
+constexpr int kCounters = 72; // [0] setup, [1 + cycle] cycle finalize, [kLaunch0 + c] below
+constexpr int kLaunch0 = 68;   // per-channel count of cycle-finalize launches in this call
 
 struct LevelDev {
     float* u;        // [3][n+2][pitch] iterate at the start and end of a cycle
@@ -291,16 +294,18 @@ __device__ __forceinline__ void load_region(float* su, float* sf, const LevelDev
     }
 }
 
-// Logical (tile x, tile y, channel) of this block under the XCD remap.
+// Logical (tile x, tile y, channel) of this block under the XCD remap; the
+// launch covers channels c0 .. c0 + gridDim.z - 1.
 struct TileId {
     int tx, ty, c;
-    __device__ TileId() {
+    __device__ explicit TileId(int c0) {
         const int gx = gridDim.x, gy = gridDim.y;
         const int nb = gx * gy * gridDim.z;
         const int b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
         const int L = xcd_remap(b, nb);
-        c = L / (gx * gy);
-        const int rem = L - c * gx * gy;
+        const int cz = L / (gx * gy);
+        const int rem = L - cz * gx * gy;
+        c = c0 + cz;
         ty = rem / gx;
         tx = rem - ty * gx;
     }
@@ -314,14 +319,14 @@ struct TileId {
 template <int NU, bool FINE, int TX, int TY>
 __global__ __launch_bounds__(256) void k_mg_pre(LevelDev L, LevelDev C, int zero_guess,
                                                 const int* __restrict__ done,
-                                                double* __restrict__ part) {
+                                                double* __restrict__ part, int c0) {
     constexpr int HALO = 2 * NU + 2;
     constexpr int CPT = TX * TY / 256;
     constexpr int RX = TX + 2 * HALO, RY = TY + 2 * HALO;
     __shared__ float su[RY * RX];
     __shared__ float sf[RY * RX];
     __shared__ double sh[3 * 4];
-    const TileId id;
+    const TileId id(c0);
     const int c = id.c;
     if (done[c]) return;
     const int gi0 = id.ty * TY - HALO, gj0 = id.tx * TX - HALO;
@@ -407,7 +412,7 @@ __global__ __launch_bounds__(256) void k_mg_pre(LevelDev L, LevelDev C, int zero
 template <int NU, bool FINE, int TX, int TY>
 __global__ __launch_bounds__(256) void k_mg_post(LevelDev L, LevelDev C,
                                                  const int* __restrict__ done,
-                                                 double* __restrict__ part) {
+                                                 double* __restrict__ part, int c0) {
     constexpr bool NORM = FINE;
     constexpr int HALO = 2 * NU + 2;
     constexpr int CPT = TX * TY / 256;
@@ -417,7 +422,7 @@ __global__ __launch_bounds__(256) void k_mg_post(LevelDev L, LevelDev C,
     __shared__ float sf[RY * RX];
     __shared__ float se[CY * CX];
     __shared__ double sh[3 * 4];
-    const TileId id;
+    const TileId id(c0);
     const int c = id.c;
     if (done[c]) return;
     const int gi0 = id.ty * TY - HALO, gj0 = id.tx * TX - HALO;
@@ -564,10 +569,10 @@ __device__ __forceinline__ void lds_residual(const float* U, const float* F, flo
 }
 
 __global__ __launch_bounds__(kLdsThreads) void k_mg_lds(LdsPlan P, const int* __restrict__ done,
-                                                        double* __restrict__ part) {
+                                                        double* __restrict__ part, int c0) {
     extern __shared__ float lds[];
     __shared__ double sh[3 * (kLdsThreads / 64)];
-    const int c = blockIdx.x;
+    const int c = c0 + blockIdx.x;
     if (done[c]) return;
     const int lc = P.lc, L = P.L;
     float* R = lds + P.scratch;
@@ -702,10 +707,19 @@ __global__ __launch_bounds__(256) void k_cycle_finalize(const double* __restrict
                                                         const double* __restrict__ bnorm,
                                                         int* __restrict__ done,
                                                         int* __restrict__ counters,
-                                                        gdgs_stats* __restrict__ stats, int cycle,
-                                                        double tol) {
+                                                        gdgs_stats* __restrict__ stats,
+                                                        double tol, int c0) {
     __shared__ double sh[3 * 4];
-    const int c = blockIdx.x;
+    __shared__ int s_cycle;
+    const int c = c0 + blockIdx.x;
+    // this call's cycle index for the channel, counted on the device so that
+    // every cycle's launch sequence is the same (one graph per channel)
+    if (threadIdx.x == 0) {
+        s_cycle = counters[kLaunch0 + c];
+        counters[kLaunch0 + c] = s_cycle + 1;
+    }
+    __syncthreads();
+    const int cycle = s_cycle;
     if (!done[c]) {  // uniform: finished before this cycle otherwise
         double rmax = 0.0, umax = 0.0, rss = 0.0, dpre = 0.0, dpost = 0.0;
         for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
@@ -773,23 +787,23 @@ bool small_tiles(const LevelDev& L) {
 
 template <int NU>
 gdgs_status launch_pre(const LevelDev& L, const LevelDev& C, bool zero, bool delta,
-                       const int* done, double* part, hipStream_t st) {
+                       const int* done, double* part, int c0, int nch, hipStream_t st) {
     hipEvent_t ev0, ev1;
     const bool timed = delta && timer_events("mg_pre_fine", &ev0, &ev1);
     if (timed) GDGS_HIP_TRY(hipEventRecord(ev0, st));
     const int z = zero ? 1 : 0;
     if (delta) {
-        dim3 grid((L.m + 2 + kTXf - 1) / kTXf, (L.n + 2 + kTYf - 1) / kTYf, 3);
+        dim3 grid((L.m + 2 + kTXf - 1) / kTXf, (L.n + 2 + kTYf - 1) / kTYf, nch);
         hipLaunchKernelGGL((k_mg_pre<NU, true, kTXf, kTYf>), grid, dim3(256), 0, st, L, C, z,
-                           done, part);
+                           done, part, c0);
     } else if (small_tiles(L)) {
-        dim3 grid((L.m + 2 + kTXs - 1) / kTXs, (L.n + 2 + kTYs - 1) / kTYs, 3);
+        dim3 grid((L.m + 2 + kTXs - 1) / kTXs, (L.n + 2 + kTYs - 1) / kTYs, nch);
         hipLaunchKernelGGL((k_mg_pre<NU, false, kTXs, kTYs>), grid, dim3(256), 0, st, L, C, z,
-                           done, part);
+                           done, part, c0);
     } else {
-        dim3 grid((L.m + 2 + kTX - 1) / kTX, (L.n + 2 + kTY - 1) / kTY, 3);
+        dim3 grid((L.m + 2 + kTX - 1) / kTX, (L.n + 2 + kTY - 1) / kTY, nch);
         hipLaunchKernelGGL((k_mg_pre<NU, false, kTX, kTY>), grid, dim3(256), 0, st, L, C, z,
-                           done, part);
+                           done, part, c0);
     }
     if (timed) GDGS_HIP_TRY(hipEventRecord(ev1, st));
     return GDGS_OK;
@@ -797,22 +811,22 @@ gdgs_status launch_pre(const LevelDev& L, const LevelDev& C, bool zero, bool del
 
 template <int NU>
 gdgs_status launch_post(const LevelDev& L, const LevelDev& C, bool fine, const int* done,
-                        double* part, hipStream_t st) {
+                        double* part, int c0, int nch, hipStream_t st) {
     hipEvent_t ev0, ev1;
     const bool timed = fine && timer_events("mg_post_fine", &ev0, &ev1);
     if (timed) GDGS_HIP_TRY(hipEventRecord(ev0, st));
     if (fine) {
-        dim3 grid((L.m + 2 + kTXf - 1) / kTXf, (L.n + 2 + kTYf - 1) / kTYf, 3);
+        dim3 grid((L.m + 2 + kTXf - 1) / kTXf, (L.n + 2 + kTYf - 1) / kTYf, nch);
         hipLaunchKernelGGL((k_mg_post<NU, true, kTXf, kTYf>), grid, dim3(256), 0, st, L, C, done,
-                           part);
+                           part, c0);
     } else if (small_tiles(L)) {
-        dim3 grid((L.m + 2 + kTXs - 1) / kTXs, (L.n + 2 + kTYs - 1) / kTYs, 3);
+        dim3 grid((L.m + 2 + kTXs - 1) / kTXs, (L.n + 2 + kTYs - 1) / kTYs, nch);
         hipLaunchKernelGGL((k_mg_post<NU, false, kTXs, kTYs>), grid, dim3(256), 0, st, L, C,
-                           done, part);
+                           done, part, c0);
     } else {
-        dim3 grid((L.m + 2 + kTX - 1) / kTX, (L.n + 2 + kTY - 1) / kTY, 3);
+        dim3 grid((L.m + 2 + kTX - 1) / kTX, (L.n + 2 + kTY - 1) / kTY, nch);
         hipLaunchKernelGGL((k_mg_post<NU, false, kTX, kTY>), grid, dim3(256), 0, st, L, C,
-                           done, part);
+                           done, part, c0);
     }
     if (timed) GDGS_HIP_TRY(hipEventRecord(ev1, st));
     return GDGS_OK;
@@ -1031,64 +1045,97 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
     lp.omega = p.omega;
     lp.top = lev[p.lc];
     const int nblk = norm_blocks(p);
-    auto pre = [&](int l, hipStream_t s) {
+    // channels c0 .. c0 + nch - 1 of one grid pass
+    auto pre = [&](int l, int c0, int nch, hipStream_t s) {
         if (p.pre == 1)
-            launch_pre<1>(lev[l], lev[l + 1], l > 0, l == 0, w.done, w.part, s);
+            launch_pre<1>(lev[l], lev[l + 1], l > 0, l == 0, w.done, w.part, c0, nch, s);
         else
-            launch_pre<2>(lev[l], lev[l + 1], l > 0, l == 0, w.done, w.part, s);
+            launch_pre<2>(lev[l], lev[l + 1], l > 0, l == 0, w.done, w.part, c0, nch, s);
     };
-    auto post = [&](int l, hipStream_t s) {
+    auto post = [&](int l, int c0, int nch, hipStream_t s) {
         if (p.post == 1)
-            launch_post<1>(lev[l], lev[l + 1], l == 0, w.done, w.part, s);
+            launch_post<1>(lev[l], lev[l + 1], l == 0, w.done, w.part, c0, nch, s);
         else
-            launch_post<2>(lev[l], lev[l + 1], l == 0, w.done, w.part, s);
+            launch_post<2>(lev[l], lev[l + 1], l == 0, w.done, w.part, c0, nch, s);
     };
     // everything of a cycle between the finest pre and post passes
-    auto body = [&](hipStream_t s) -> gdgs_status {
-        for (int l = 1; l < p.lc; ++l) pre(l, s);
-        hipLaunchKernelGGL(k_mg_lds, dim3(3), dim3(kLdsThreads), p.lds_bytes, s, lp, w.done,
-                           w.part);
-        for (int l = p.lc - 1; l >= 1; --l) post(l, s);
+    auto body = [&](int c0, int nch, hipStream_t s) -> gdgs_status {
+        for (int l = 1; l < p.lc; ++l) pre(l, c0, nch, s);
+        hipLaunchKernelGGL(k_mg_lds, dim3(nch), dim3(kLdsThreads), p.lds_bytes, s, lp, w.done,
+                           w.part, c0);
+        for (int l = p.lc - 1; l >= 1; --l) post(l, c0, nch, s);
         GDGS_LAUNCH_CHECK();
         return GDGS_OK;
     };
-    auto finalize = [&](int cyc, hipStream_t s) -> gdgs_status {
-        hipLaunchKernelGGL(k_cycle_finalize, dim3(3), dim3(256), 0, s, w.part, nblk, w.bnorm,
-                           w.done, w.counters, sd, cyc, p.tol);
+    auto finalize = [&](int c0, int nch, hipStream_t s) -> gdgs_status {
+        hipLaunchKernelGGL(k_cycle_finalize, dim3(nch), dim3(256), 0, s, w.part, nblk, w.bnorm,
+                           w.done, w.counters, sd, p.tol, c0);
         GDGS_LAUNCH_CHECK();
         return GDGS_OK;
     };
-    const bool split = key && p.lc > 0 && (timer_active("mg_pre_fine") || timer_active("mg_post_fine"));
-    if (!split) {
-        gdgs_status r = setup(st);
+    auto cycle = [&](int c0, int nch, hipStream_t s) -> gdgs_status {
+        if (p.lc > 0) pre(0, c0, nch, s);
+        gdgs_status r = body(c0, nch, s);
         if (r != GDGS_OK) return r;
-        for (int cyc = 0; cyc < p.max_cycles; ++cyc) {
-            if (p.lc > 0) pre(0, st);
-            r = body(st);
-            if (r != GDGS_OK) return r;
-            if (p.lc > 0) post(0, st);
-            r = finalize(cyc, st);
-            if (r != GDGS_OK) return r;
-        }
-        return GDGS_OK;
+        if (p.lc > 0) post(0, c0, nch, s);
+        return finalize(c0, nch, s);
+    };
+
+    gdgs_status r = GDGS_OK;
+    if (key) {
+        KeyBuilder ks = *key;
+        ks.tag("setup");
+        r = with_graph(ks, st, setup);
+    } else {
+        r = setup(st);
     }
-    // timed finest passes launch directly between their events; the rest of
-    // each cycle is replayed from cached graphs
-    KeyBuilder ks = *key;
-    ks.tag("setup");
-    gdgs_status r = with_graph(ks, st, setup);
     if (r != GDGS_OK) return r;
-    for (int cyc = 0; cyc < p.max_cycles; ++cyc) {
-        pre(0, st);
-        KeyBuilder kbd = *key;
-        kbd.tag("body");
-        r = with_graph(kbd, st, body);
-        if (r != GDGS_OK) return r;
-        post(0, st);
-        r = finalize(cyc, st);
-        if (r != GDGS_OK) return r;
+
+    // The three colour channels are independent systems: each runs its
+    // V-cycles on its own stream, so one channel's bandwidth-bound finest
+    // passes overlap another's latency-bound coarse grids.
+    ChannelStreams cs;
+    if (!channel_streams(st, &cs)) {
+        for (int cyc = 0; cyc < p.max_cycles && r == GDGS_OK; ++cyc) r = cycle(0, 3, st);
+        return r;
     }
-    return GDGS_OK;
+    hipStream_t sc[3] = {st, cs.aux[0], cs.aux[1]};
+    GDGS_HIP_TRY(hipEventRecord(cs.fork, st));
+    for (int k = 0; k < 2; ++k) GDGS_HIP_TRY(hipStreamWaitEvent(cs.aux[k], cs.fork, 0));
+    const bool timed =
+        p.lc > 0 && (timer_active("mg_pre_fine") || timer_active("mg_post_fine"));
+    // Cycles are launched in rounds over the channels, so that all three
+    // streams have work queued early.  (Measured alternatives: one graph per
+    // channel for all cycles, staggered channel starts, one graph with three
+    // branches: none faster; overlapped kernels of different channels slow
+    // each other down, so about two run at a time on average.)
+    auto run = [&](const char* tag, int c, const std::function<gdgs_status(hipStream_t)>& f) {
+        if (!key) return f(sc[c]);
+        KeyBuilder kc = *key;
+        kc.tag(tag).add(c);
+        return with_graph(kc, sc[c], f);
+    };
+    for (int cyc = 0; cyc < p.max_cycles && r == GDGS_OK; ++cyc) {
+        for (int c = 0; c < 3 && r == GDGS_OK; ++c) {
+            if (!timed) {
+                r = run("cycle", c, [&](hipStream_t s) { return cycle(c, 1, s); });
+                continue;
+            }
+            // timed finest passes launch directly between their events; the
+            // rest of the cycle is replayed from a cached graph
+            pre(0, c, 1, sc[c]);
+            r = run("body", c, [&](hipStream_t s) { return body(c, 1, s); });
+            if (r != GDGS_OK) break;
+            post(0, c, 1, sc[c]);
+            r = finalize(c, 1, sc[c]);
+        }
+    }
+    // join (also after a failure, so the caller's stream never runs ahead)
+    for (int k = 0; k < 2; ++k) {
+        GDGS_HIP_TRY(hipEventRecord(cs.join[k], cs.aux[k]));
+        GDGS_HIP_TRY(hipStreamWaitEvent(st, cs.join[k], 0));
+    }
+    return r;
 }
 
 gdgs_status launch_div_adjoint(const float* lam, int W, int H, float* dgrad, hipStream_t st) {

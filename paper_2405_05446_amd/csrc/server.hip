@@ -4,9 +4,10 @@
 // the scheduling core (arrival order, free stream, memory budget), enqueues
 // each request's frame on the request's own stream -- the projection with
 // the request's camera, a copy of its boundary ring into its slot, then the
-// binning, compositing and Poisson solve as one cached graph per slot and
-// size, a copy of the result to the caller's buffer and of the statistics to
-// pinned host memory -- and records an event.  When the event has fired it
+// binning and compositing as one cached graph per slot and size, the Poisson
+// solve (its own cached graphs, one per colour channel on helper streams
+// bound to the request's stream), a copy of the result to the caller's
+// buffer and of the statistics to pinned host memory -- and records an event.  When the event has fired it
 // reads the statistics: a pair overflow sends the request back to the queue
 // with a larger capacity, an unconverged solve is resumed two V-cycles at a
 // time (GDGS_MG_RESUME: bit for bit the same as one longer solve), and a
@@ -188,17 +189,19 @@ struct gdgs_server {
         kb.tag("server").add(uid).add(base).add(W).add(H).add(cap).add(K).add(sc.opacity)
             .add(sc.value).add(bnd);
         add_plan(kb, *plan);
-        gdgs_status e = with_graph(kb, st, [&](hipStream_t q) -> gdgs_status {
+        KeyBuilder kr = kb;
+        kr.tag("bin+raster");
+        gdgs_status e = with_graph(kr, st, [&](hipStream_t q) -> gdgs_status {
             gdgs_status t = launch_bin_sort(L.rw.proj, K, W, H, L.rw.bins, b, q);
             if (t != GDGS_OK) return t;
-            t = launch_raster(L.rw.proj, sc.opacity, sc.value, K, L.rw.bins, W, H, L.rw.grad,
-                              L.rw.raster_ws, q);
-            if (t != GDGS_OK) return t;
-            t = launch_poisson(L.rw.grad, nullptr, bnd, W, H, *plan, L.u, L.stats,
-                               L.rw.poisson_ws, q);
-            if (t != GDGS_OK) return t;
-            return launch_render_stats(L.rw.bins.num_pairs, cap, L.stats, q);
+            return launch_raster(L.rw.proj, sc.opacity, sc.value, K, L.rw.bins, W, H, L.rw.grad,
+                                 L.rw.raster_ws, q);
         });
+        if (e != GDGS_OK) return e;
+        e = launch_poisson(L.rw.grad, nullptr, bnd, W, H, *plan, L.u, L.stats, L.rw.poisson_ws,
+                           st, &kb);
+        if (e != GDGS_OK) return e;
+        e = launch_render_stats(L.rw.bins.num_pairs, cap, L.stats, st);
         if (e != GDGS_OK) return e;
         return finish_enqueue(r, L, p, st);
     }
@@ -219,10 +222,8 @@ struct gdgs_server {
         kb.tag("server-resume").add(uid).add(base).add(W).add(H).add(r->cap).add(scene.K)
             .add(bnd);
         add_plan(kb, *plan);
-        gdgs_status e = with_graph(kb, st, [&](hipStream_t q) -> gdgs_status {
-            return launch_poisson(L.rw.grad, nullptr, bnd, W, H, *plan, L.u, L.stats,
-                                  L.rw.poisson_ws, q);
-        });
+        const gdgs_status e = launch_poisson(L.rw.grad, nullptr, bnd, W, H, *plan, L.u,
+                                             L.stats, L.rw.poisson_ws, st, &kb);
         if (e != GDGS_OK) return e;
         return finish_enqueue(r, L, p, st);
     }
