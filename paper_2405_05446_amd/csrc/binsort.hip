@@ -145,16 +145,22 @@ __global__ __launch_bounds__(256) void k_radix_scan(uint32_t* __restrict__ hist,
     if (t == 0) digit_tot[d] = tot;
 }
 
+// Up to three value arrays travel with the keys.
+struct Vals {
+    const uint32_t* in[3];
+    uint32_t* out[3];
+};
+
+template <int NV>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
-    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
-    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const int64_t* n_dev,
-    int64_t n_host, int64_t cap, int shift, int bits, const uint32_t* __restrict__ hist,
-    const uint32_t* __restrict__ digit_tot) {
+    const uint32_t* __restrict__ kin, uint32_t* __restrict__ kout, Vals vals,
+    const int64_t* n_dev, int64_t n_host, int64_t cap, int shift, int bits,
+    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ digit_tot) {
     __shared__ uint32_t s_base[kRadix];
     __shared__ uint32_t s_wcnt[kWaves][kRadix];
     __shared__ uint32_t s_tstart[kRadix];
     __shared__ uint32_t s_key[kSortTile];
-    __shared__ uint32_t s_val[kSortTile];
+    __shared__ uint32_t s_val[NV][kSortTile];
     __shared__ uint32_t s_tmp[kWaves];
     const int G = gridDim.x, b = blockIdx.x, t = threadIdx.x, lane = __lane_id(), w = t >> 6;
     const uint32_t mask = (1u << bits) - 1u;
@@ -169,14 +175,15 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     for (int64_t tlo = lo; tlo < hi; tlo += kSortTile) {
         for (int i = t; i < kWaves * kRadix; i += kSortThreads) (&s_wcnt[0][0])[i] = 0u;
         __syncthreads();
-        uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
+        uint32_t key[kSortItems], val[NV][kSortItems], rank[kSortItems];
         const int64_t wbase = tlo + (int64_t)w * 64 * kSortItems;
 #pragma unroll
         for (int r = 0; r < kSortItems; ++r) {
             const int64_t i = wbase + r * 64 + lane;
             const bool valid = i < hi;
             key[r] = valid ? kin[i] : 0u;
-            val[r] = valid ? vin[i] : 0u;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) val[v][r] = valid ? vals.in[v][i] : 0u;
         }
 #pragma unroll
         for (int r = 0; r < kSortItems; ++r) {
@@ -208,7 +215,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
                 const uint32_t d = (key[r] >> shift) & mask;
                 const uint32_t pos = s_tstart[d] + s_wcnt[w][d] + rank[r];
                 s_key[pos] = key[r];
-                s_val[pos] = val[r];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) s_val[v][pos] = val[v][r];
             }
         }
         __syncthreads();
@@ -218,7 +226,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
             const uint32_t d = (k >> shift) & mask;
             const uint32_t g = s_base[d] + ((uint32_t)p - s_tstart[d]);
             kout[g] = k;
-            vout[g] = s_val[p];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) vals.out[v][g] = s_val[v][p];
         }
         __syncthreads();
         s_base[t] += tot_t;
@@ -235,11 +244,17 @@ __global__ void k_depth_keys(const float* __restrict__ depth, const uint32_t* __
 }
 
 constexpr int kScanThreads = 256;
-constexpr int kScanItems = 8;
+constexpr int kScanItems = 2;   // 512 splats per block: enough blocks to hide the emission's latency
 constexpr int kScanTile = kScanThreads * kScanItems;
 
-__global__ __launch_bounds__(kScanThreads) void k_count_reduce(const uint32_t* __restrict__ order,
-                                                               const uint32_t* __restrict__ count,
+__device__ __forceinline__ uint32_t rect_count(uint32_t r0, uint32_t r1) {
+    return ((r0 >> 16) - (r0 & 0xFFFFu)) * ((r1 >> 16) - (r1 & 0xFFFFu));
+}
+
+// Block sums of the tile counts in depth-rank order (rect0/rect1: the
+// rectangles permuted into rank order by the depth sort; count = area).
+__global__ __launch_bounds__(kScanThreads) void k_count_reduce(const uint32_t* __restrict__ rect0,
+                                                               const uint32_t* __restrict__ rect1,
                                                                int64_t K,
                                                                unsigned long long* __restrict__ bsum) {
     __shared__ uint32_t s_tmp[kWaves];
@@ -249,10 +264,7 @@ __global__ __launch_bounds__(kScanThreads) void k_count_reduce(const uint32_t* _
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
         const int64_t s = base + i;
-        if (s < K) {
-            const uint32_t k = order[s];
-            if (k < (uint64_t)K) sum += count[k];
-        }
+        if (s < K) sum += rect_count(rect0[s], rect1[s]);
     }
     uint32_t tot;
     block_excl_scan(sum, s_tmp, &tot);
@@ -296,8 +308,8 @@ __global__ __launch_bounds__(1024) void k_scan_bsums(unsigned long long* __restr
 // counts; then the block's pairs are written cooperatively and coalesced,
 // pair p finding its splat by binary search over the offsets in LDS.
 __global__ __launch_bounds__(kScanThreads) void k_emit_pairs(
-    const uint32_t* __restrict__ order, const uint32_t* __restrict__ count,
-    const uint32_t* __restrict__ rect, int64_t K, const unsigned long long* __restrict__ bsum,
+    const uint32_t* __restrict__ order, const uint32_t* __restrict__ rect0,
+    const uint32_t* __restrict__ rect1, int64_t K, const unsigned long long* __restrict__ bsum,
     int64_t cap, int nx, uint32_t* __restrict__ tile_out, uint32_t* __restrict__ splat_out) {
     __shared__ uint32_t s_tmp[kWaves];
     __shared__ uint32_t s_off[kScanTile + 1];
@@ -306,12 +318,17 @@ __global__ __launch_bounds__(kScanThreads) void k_emit_pairs(
     __shared__ uint32_t s_w[kScanTile];    // rectangle width in tiles
     const int t = threadIdx.x;
     const int64_t sbase = (int64_t)blockIdx.x * kScanTile;
-    uint32_t c[kScanItems], ks[kScanItems], sum = 0;
+    uint32_t c[kScanItems], ks[kScanItems], r0[kScanItems], r1[kScanItems], sum = 0;
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
         const int64_t s = sbase + (int64_t)t * kScanItems + i;
         ks[i] = s < K ? order[s] : 0u;
-        c[i] = (s < K && ks[i] < (uint64_t)K) ? count[ks[i]] : 0u;
+        r0[i] = s < K ? rect0[s] : 0u;
+        r1[i] = s < K ? rect1[s] : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        c[i] = ks[i] < (uint64_t)K ? rect_count(r0[i], r1[i]) : 0u;
         sum += c[i];
     }
     uint32_t tot;
@@ -323,9 +340,8 @@ __global__ __launch_bounds__(kScanThreads) void k_emit_pairs(
         s_k[j] = ks[i];
         uint32_t org = 0, w = 1;
         if (c[i]) {
-            const uint32_t r0 = rect[ks[i]], r1 = rect[K + ks[i]];
-            org = (r0 & 0xFFFF) | ((r1 & 0xFFFF) << 16);
-            w = (r0 >> 16) - (r0 & 0xFFFF);
+            org = (r0[i] & 0xFFFF) | ((r1[i] & 0xFFFF) << 16);
+            w = (r0[i] >> 16) - (r0[i] & 0xFFFF);
         }
         s_org[j] = org;
         s_w[j] = w;
@@ -392,28 +408,33 @@ int bitlen(uint64_t x) {
     return b;
 }
 
-// One full LSD sort of (key, val) pairs over `bits` key bits.  X_0 = (k0, v0);
-// pass p writes X_{p+1}, alternating between (k0, v0) and (k1, v1); the last
-// pass writes (kfin, vfin).
-gdgs_status radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uint32_t* kfin,
-                       uint32_t* vfin, const int64_t* n_dev, int64_t n_host, int64_t cap,
-                       int key_bits, uint32_t* hist, uint32_t* digit_tot, hipStream_t st) {
+// One full LSD sort of keys with NV value arrays over `key_bits` key bits.
+// Pass 0 reads (kin0, vin0[]); pass p > 0 reads buffer set (p + 1) & 1 ... as
+// written by pass p - 1: pass p writes set (p + 1) & 1, the last pass writes
+// (kfin, vfin[]).  buf sets: (kb[i], vb[v][i]).
+template <int NV>
+gdgs_status radix_sort(const uint32_t* kin0, const uint32_t* const* vin0, uint32_t* const* kb,
+                       uint32_t* const (*vb)[2], uint32_t* kfin, uint32_t* const* vfin,
+                       const int64_t* n_dev, int64_t n_host, int64_t cap, int key_bits,
+                       uint32_t* hist, uint32_t* digit_tot, hipStream_t st) {
     const int G = sort_grid(cap);
     const int passes = (key_bits + 7) / 8;
-    uint32_t* kb[2] = {k0, k1};
-    uint32_t* vb[2] = {v0, v1};
     for (int p = 0; p < passes; ++p) {
         const int shift = 8 * p;
         const int bits = key_bits - shift < 8 ? key_bits - shift : 8;
-        const uint32_t* kin = kb[p & 1];
-        const uint32_t* vin = vb[p & 1];
-        uint32_t* kout = (p == passes - 1) ? kfin : kb[(p + 1) & 1];
-        uint32_t* vout = (p == passes - 1) ? vfin : vb[(p + 1) & 1];
+        const bool last = p == passes - 1;
+        const uint32_t* kin = p == 0 ? kin0 : kb[p & 1];
+        uint32_t* kout = last ? kfin : kb[(p + 1) & 1];
+        Vals vals{};
+        for (int v = 0; v < NV; ++v) {
+            vals.in[v] = p == 0 ? vin0[v] : vb[v][p & 1];
+            vals.out[v] = last ? vfin[v] : vb[v][(p + 1) & 1];
+        }
         hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(kSortThreads), 0, st, kin, n_dev, n_host,
                            cap, shift, bits, hist);
         hipLaunchKernelGGL(k_radix_scan, dim3(kRadix), dim3(256), 0, st, hist, G, digit_tot);
-        hipLaunchKernelGGL(k_radix_scatter, dim3(G), dim3(kSortThreads), 0, st, kin, vin, kout,
-                           vout, n_dev, n_host, cap, shift, bits, hist, digit_tot);
+        hipLaunchKernelGGL(k_radix_scatter<NV>, dim3(G), dim3(kSortThreads), 0, st, kin, kout,
+                           vals, n_dev, n_host, cap, shift, bits, hist, digit_tot);
     }
     GDGS_LAUNCH_CHECK();
     return GDGS_OK;
@@ -436,6 +457,8 @@ size_t bin_ws_layout(int64_t K, int64_t cap, void* ws, BinWs* out) {
     for (int i = 0; i < 2; ++i) {
         b.dkey[i] = c.take<uint32_t>(Kp);
         b.dval[i] = c.take<uint32_t>(Kp);
+        b.drect[0][i] = c.take<uint32_t>(Kp);
+        b.drect[1][i] = c.take<uint32_t>(Kp);
         b.pkey[i] = c.take<uint32_t>(cp);
         b.pval[i] = c.take<uint32_t>(cp);
     }
@@ -469,28 +492,43 @@ gdgs_status launch_bin_sort(const gdgs_proj& proj, int64_t K, int W, int H, cons
         GDGS_LAUNCH_CHECK();
         return GDGS_OK;
     }
-    // 1. depth order of the splats
+    // 1. depth order of the splats; their rectangles ride along, so that the
+    //    scan and the emission read them in rank order without gathers
     hipLaunchKernelGGL(k_depth_keys, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, st,
                        proj.depth, proj.count, K, ws.dkey[0], ws.dval[0]);
-    s = radix_sort(ws.dkey[0], ws.dval[0], ws.dkey[1], ws.dval[1],
-                   ws.dkey[0], bins.order, nullptr, K, K, 32, ws.hist,
-                   ws.digit_tot, st);
-    if (s != GDGS_OK) return s;
+    {
+        const uint32_t* vin0[3] = {ws.dval[0], proj.rect, proj.rect + K};
+        uint32_t* const kb[2] = {ws.dkey[0], ws.dkey[1]};
+        uint32_t* const vb[3][2] = {{ws.dval[0], ws.dval[1]},
+                                    {ws.drect[0][0], ws.drect[0][1]},
+                                    {ws.drect[1][0], ws.drect[1][1]}};
+        uint32_t* const vfin[3] = {bins.order, ws.drect[0][0], ws.drect[1][0]};
+        s = radix_sort<3>(ws.dkey[0], vin0, kb, vb, ws.dkey[0], vfin, nullptr, K, K, 32, ws.hist,
+                          ws.digit_tot, st);
+        if (s != GDGS_OK) return s;
+    }
+    const uint32_t* rect0 = ws.drect[0][0];
+    const uint32_t* rect1 = ws.drect[1][0];
     // 2. scan of tile counts in rank order, pair emission
     const int64_t nb = (K + kScanTile - 1) / kScanTile;
     unsigned long long* bsum = reinterpret_cast<unsigned long long*>(ws.bsum);
-    hipLaunchKernelGGL(k_count_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, st, bins.order,
-                       proj.count, K, bsum);
+    hipLaunchKernelGGL(k_count_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, st, rect0,
+                       rect1, K, bsum);
     hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(1024), 0, st, bsum, nb, bins.num_pairs);
     hipLaunchKernelGGL(k_emit_pairs, dim3((unsigned)nb), dim3(kScanThreads), 0, st, bins.order,
-                       proj.count, proj.rect, K, bsum, bins.capacity, nx, ws.pkey[0], ws.pval[0]);
+                       rect0, rect1, K, bsum, bins.capacity, nx, ws.pkey[0], ws.pval[0]);
     GDGS_LAUNCH_CHECK();
     // 3. stable sort of the pairs by tile, then the ranges
     const int tbits = bitlen((uint64_t)(T > 1 ? T - 1 : 1));
-    s = radix_sort(ws.pkey[0], ws.pval[0], ws.pkey[1], ws.pval[1], bins.tile_of_pair,
-                   bins.splat_of_pair, bins.num_pairs, 0, bins.capacity, tbits, ws.hist,
-                   ws.digit_tot, st);
-    if (s != GDGS_OK) return s;
+    {
+        const uint32_t* vin0[1] = {ws.pval[0]};
+        uint32_t* const kb[2] = {ws.pkey[0], ws.pkey[1]};
+        uint32_t* const vb[1][2] = {{ws.pval[0], ws.pval[1]}};
+        uint32_t* const vfin[1] = {bins.splat_of_pair};
+        s = radix_sort<1>(ws.pkey[0], vin0, kb, vb, bins.tile_of_pair, vfin, bins.num_pairs, 0,
+                          bins.capacity, tbits, ws.hist, ws.digit_tot, st);
+        if (s != GDGS_OK) return s;
+    }
     hipLaunchKernelGGL(k_tile_ranges, dim3(2048), dim3(256), 0, st, bins.tile_of_pair,
                        bins.num_pairs, bins.capacity, bins.ranges, T);
     GDGS_LAUNCH_CHECK();

@@ -87,6 +87,7 @@ int sort_grid(int64_t cap);
 struct BinWs {
     uint32_t* dkey[2];   // depth-sort ping-pong keys [K]
     uint32_t* dval[2];   // depth-sort ping-pong values [K]
+    uint32_t* drect[2][2]; // rectangle words riding with the depth sort [word][ping-pong][K]
     uint32_t* pkey[2];   // pair ping-pong keys [cap]
     uint32_t* pval[2];   // pair ping-pong values [cap]
     uint32_t* hist;      // [256][G]

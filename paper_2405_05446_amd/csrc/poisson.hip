@@ -53,6 +53,7 @@ namespace {
 constexpr int kTX = 64, kTY = 32;
 constexpr int kTXs = 32, kTYs = 16;
 constexpr int kTXf = 32, kTYf = 32;   // finest grid
+constexpr int kNTf = 256, kNTs = 256; // threads per block: finest grid, small tiles
 constexpr int kSmallTileBelow = 4096;
 constexpr int kLdsTopCells = 4096;    // largest grid solved inside one workgroup  // blocks of 64 x 32 under which small tiles are used
 constexpr int kDivTX = 64;
@@ -167,6 +168,7 @@ __global__ __launch_bounds__(kDivTX* kDivTY) void k_div_init(
     const int j = blockIdx.x * kDivTX + (threadIdx.x % kDivTX);
     const size_t HW = (size_t)H * W;
     double bmax = 0.0, bdum = 0.0, bss = 0.0;
+#pragma unroll
     for (int k = 0; k < kDivRows / kDivTY; ++k) {
         const int i = blockIdx.y * kDivRows + k * kDivTY + (threadIdx.x / kDivTX);
         if (i >= H || j >= W) continue;
@@ -247,12 +249,12 @@ __global__ void k_resume(int* __restrict__ counters) {
 // Red-black Gauss-Seidel half-sweeps on an LDS region RX x RY whose cell (0,0)
 // is grid point (gi0, gj0); only interior grid points (1..n, 1..m) change.
 // Thread t owns LDS row 1 + t / TPR and every TPR-th cell of one colour in it.
-template <int RX, int RY>
+template <int RX, int RY, int NT>
 __device__ __forceinline__ void smooth_rows(float* __restrict__ su, const float* __restrict__ sf,
                                             int gi0, int gj0, int n, int m, float ey, float ex,
                                             int color0, int sweeps) {
     constexpr int NR = RY - 2;
-    constexpr int TPR = 256 / NR;
+    constexpr int TPR = NT / NR;
     const int t = threadIdx.x;
     const int r = 1 + t / TPR, sgm = t % TPR;
     const int gi = gi0 + r;
@@ -277,20 +279,35 @@ __device__ __forceinline__ void smooth_rows(float* __restrict__ su, const float*
     }
 }
 
-template <int RX, int RY>
+// All of a thread's global loads are issued before the first LDS store (a
+// fixed trip count lets the compiler keep them in flight together instead of
+// waiting for each iteration's loads in turn).
+template <int RX, int RY, int NT>
 __device__ __forceinline__ void load_region(float* su, float* sf, const LevelDev& L,
                                             const float* usrc, int c, int gi0, int gj0,
                                             bool zero_guess) {
+    constexpr int NI = (RY * RX + NT - 1) / NT;
     const int N = L.n + 2, M = L.m + 2;
     const float* u = usrc + (size_t)c * L.cs;
     const float* f = L.f + (size_t)c * L.cs;
-    for (int idx = threadIdx.x; idx < RY * RX; idx += blockDim.x) {
+    float vu[NI], vf[NI];
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int idx = threadIdx.x + k * NT;
         const int r = idx / RX, q = idx - r * RX;
         const int gi = gi0 + r, gj = gj0 + q;
-        const bool in = (unsigned)gi < (unsigned)N && (unsigned)gj < (unsigned)M;
+        const bool in = idx < RY * RX && (unsigned)gi < (unsigned)N && (unsigned)gj < (unsigned)M;
         const size_t o = (size_t)gi * L.pitch + gj;
-        su[idx] = (in && !zero_guess) ? u[o] : 0.f;
-        sf[idx] = in ? f[o] : 0.f;
+        vu[k] = (in && !zero_guess) ? u[o] : 0.f;
+        vf[k] = in ? f[o] : 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int idx = threadIdx.x + k * NT;
+        if (idx < RY * RX) {
+            su[idx] = vu[k];
+            sf[idx] = vf[k];
+        }
     }
 }
 
@@ -311,43 +328,43 @@ struct TileId {
     }
 };
 
-// Thread t of a 256-thread block owns the tile cells t, t + 256, ...
+// Thread t of an NT-thread block owns the tile cells t, t + NT, ...
 
 // Pre-smoothing + residual + restriction to the next grid.  FINE (the finest
 // grid only): record the largest change of u and evaluate the residual in
 // FP64; coarser grids carry small corrections and stay in FP32.
-template <int NU, bool FINE, int TX, int TY>
-__global__ __launch_bounds__(256) void k_mg_pre(LevelDev L, LevelDev C, int zero_guess,
+template <int NU, bool FINE, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_mg_pre(LevelDev L, LevelDev C, int zero_guess,
                                                 const int* __restrict__ done,
                                                 double* __restrict__ part, int c0) {
     constexpr int HALO = 2 * NU + 2;
-    constexpr int CPT = TX * TY / 256;
+    constexpr int CPT = TX * TY / NT;
     constexpr int RX = TX + 2 * HALO, RY = TY + 2 * HALO;
     __shared__ float su[RY * RX];
     __shared__ float sf[RY * RX];
-    __shared__ double sh[3 * 4];
+    __shared__ double sh[3 * (NT / 64)];
     const TileId id(c0);
     const int c = id.c;
     if (done[c]) return;
     const int gi0 = id.ty * TY - HALO, gj0 = id.tx * TX - HALO;
-    load_region<RX, RY>(su, sf, L, L.u, c, gi0, gj0, zero_guess != 0);
+    load_region<RX, RY, NT>(su, sf, L, L.u, c, gi0, gj0, zero_guess != 0);
     __syncthreads();
     float before[CPT];
     if (FINE) {
 #pragma unroll
         for (int k = 0; k < CPT; ++k) {
-            const int idx = threadIdx.x + 256 * k;
+            const int idx = threadIdx.x + NT * k;
             before[k] = su[(HALO + idx / TX) * RX + HALO + idx % TX];
         }
         __syncthreads();  // every snapshot is taken before any cell changes
     }
-    smooth_rows<RX, RY>(su, sf, gi0, gj0, L.n, L.m, L.ey, L.ex, 0, NU);
+    smooth_rows<RX, RY, NT>(su, sf, gi0, gj0, L.n, L.m, L.ey, L.ex, 0, NU);
     const int N = L.n + 2, M = L.m + 2;
     float* u = L.ub + (size_t)c * L.cs;
     double dmax = 0.0;
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
-        const int idx = threadIdx.x + 256 * k;
+        const int idx = threadIdx.x + NT * k;
         const int r = HALO + idx / TX, q = HALO + idx % TX;
         const int gi = gi0 + r, gj = gj0 + q;
         if (gi < N && gj < M) {
@@ -361,7 +378,7 @@ __global__ __launch_bounds__(256) void k_mg_pre(LevelDev L, LevelDev C, int zero
     // owns every TPR-th cell of one row
     {
         constexpr int ZR = TY + 1, ZC = TX + 1;
-        constexpr int TPR = 256 / ZR;
+        constexpr int TPR = NT / ZR;
         const int t = threadIdx.x;
         if (t < ZR * TPR) {
             const int r = HALO - 1 + t / TPR;
@@ -409,35 +426,44 @@ __global__ __launch_bounds__(256) void k_mg_pre(LevelDev L, LevelDev C, int zero
 
 // Prolongation + correction + post-smoothing.  FINE (the finest grid only):
 // also the residual and correction norms of the cycle.
-template <int NU, bool FINE, int TX, int TY>
-__global__ __launch_bounds__(256) void k_mg_post(LevelDev L, LevelDev C,
+template <int NU, bool FINE, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_mg_post(LevelDev L, LevelDev C,
                                                  const int* __restrict__ done,
                                                  double* __restrict__ part, int c0) {
     constexpr bool NORM = FINE;
     constexpr int HALO = 2 * NU + 2;
-    constexpr int CPT = TX * TY / 256;
+    constexpr int CPT = TX * TY / NT;
     constexpr int RX = TX + 2 * HALO, RY = TY + 2 * HALO;
     constexpr int CX = RX / 2 + 2, CY = RY / 2 + 2;  // staged coarse tile
     __shared__ float su[RY * RX];
     __shared__ float sf[RY * RX];
     __shared__ float se[CY * CX];
-    __shared__ double sh[3 * 4];
+    __shared__ double sh[3 * (NT / 64)];
     const TileId id(c0);
     const int c = id.c;
     if (done[c]) return;
     const int gi0 = id.ty * TY - HALO, gj0 = id.tx * TX - HALO;
-    load_region<RX, RY>(su, sf, L, L.ub, c, gi0, gj0, false);
+    load_region<RX, RY, NT>(su, sf, L, L.ub, c, gi0, gj0, false);
     // coarse rows (gi0 >> 1) .. ((gi0 + RY - 1) >> 1) + 1, columns alike
     const int ci0 = gi0 >> 1, cj0 = gj0 >> 1;
     {
         const float* e = C.u + (size_t)c * C.cs;
         const int NC = C.n + 2, MC = C.m + 2;
-        for (int idx = threadIdx.x; idx < CY * CX; idx += blockDim.x) {
+        constexpr int NE = (CY * CX + NT - 1) / NT;
+        float ve[NE];
+#pragma unroll
+        for (int k = 0; k < NE; ++k) {
+            const int idx = threadIdx.x + k * NT;
             const int a = idx / CX, b = idx - a * CX;
             const int I = ci0 + a, J = cj0 + b;
-            se[idx] = ((unsigned)I < (unsigned)NC && (unsigned)J < (unsigned)MC)
-                          ? e[(size_t)I * C.pitch + J]
-                          : 0.f;
+            ve[k] = (idx < CY * CX && (unsigned)I < (unsigned)NC && (unsigned)J < (unsigned)MC)
+                        ? e[(size_t)I * C.pitch + J]
+                        : 0.f;
+        }
+#pragma unroll
+        for (int k = 0; k < NE; ++k) {
+            const int idx = threadIdx.x + k * NT;
+            if (idx < CY * CX) se[idx] = ve[k];
         }
     }
     __syncthreads();
@@ -445,7 +471,7 @@ __global__ __launch_bounds__(256) void k_mg_post(LevelDev L, LevelDev C,
     if (NORM) {
 #pragma unroll
         for (int k = 0; k < CPT; ++k) {
-            const int idx = threadIdx.x + 256 * k;
+            const int idx = threadIdx.x + NT * k;
             before[k] = su[(HALO + idx / TX) * RX + HALO + idx % TX];
         }
         __syncthreads();  // every snapshot is taken before any cell changes
@@ -467,13 +493,13 @@ __global__ __launch_bounds__(256) void k_mg_post(LevelDev L, LevelDev C,
         }
     }
     __syncthreads();
-    smooth_rows<RX, RY>(su, sf, gi0, gj0, L.n, L.m, L.ey, L.ex, 1, NU);
+    smooth_rows<RX, RY, NT>(su, sf, gi0, gj0, L.n, L.m, L.ey, L.ex, 1, NU);
     float* u = L.u + (size_t)c * L.cs;
     const int N = L.n + 2, M = L.m + 2;
     double rmax = 0.0, umax = 0.0, rss = 0.0, dmax = 0.0;
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
-        const int idx = threadIdx.x + 256 * k;
+        const int idx = threadIdx.x + NT * k;
         const int r = HALO + idx / TX, q = HALO + idx % TX;
         const int gi = gi0 + r, gj = gj0 + q;
         const int o = r * RX + q;
@@ -722,13 +748,26 @@ __global__ __launch_bounds__(256) void k_cycle_finalize(const double* __restrict
     const int cycle = s_cycle;
     if (!done[c]) {  // uniform: finished before this cycle otherwise
         double rmax = 0.0, umax = 0.0, rss = 0.0, dpre = 0.0, dpost = 0.0;
-        for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
-            const double* p = part + ((size_t)c * nblk + b) * 5;
-            rmax = fmax(rmax, p[0]);
-            umax = fmax(umax, p[1]);
-            rss += p[2];
-            dpre = fmax(dpre, p[3]);
-            dpost = fmax(dpost, p[4]);
+        // four blocks' partials per thread and round, loaded before use
+        const int nt = blockDim.x;
+        for (int b0 = threadIdx.x; b0 < nblk; b0 += 4 * nt) {
+            double v[4][5];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int b = b0 + k * nt;
+                const double* p = part + ((size_t)c * nblk + (b < nblk ? b : 0)) * 5;
+#pragma unroll
+                for (int q = 0; q < 5; ++q) v[k][q] = p[q];
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (b0 + k * nt >= nblk) break;
+                rmax = fmax(rmax, v[k][0]);
+                umax = fmax(umax, v[k][1]);
+                rss += v[k][2];
+                dpre = fmax(dpre, v[k][3]);
+                dpost = fmax(dpost, v[k][4]);
+            }
         }
         block_reduce3(rmax, umax, rss, sh);
         double d0 = 0.0;
@@ -794,15 +833,15 @@ gdgs_status launch_pre(const LevelDev& L, const LevelDev& C, bool zero, bool del
     const int z = zero ? 1 : 0;
     if (delta) {
         dim3 grid((L.m + 2 + kTXf - 1) / kTXf, (L.n + 2 + kTYf - 1) / kTYf, nch);
-        hipLaunchKernelGGL((k_mg_pre<NU, true, kTXf, kTYf>), grid, dim3(256), 0, st, L, C, z,
+        hipLaunchKernelGGL((k_mg_pre<NU, true, kTXf, kTYf, kNTf>), grid, dim3(kNTf), 0, st, L, C, z,
                            done, part, c0);
     } else if (small_tiles(L)) {
         dim3 grid((L.m + 2 + kTXs - 1) / kTXs, (L.n + 2 + kTYs - 1) / kTYs, nch);
-        hipLaunchKernelGGL((k_mg_pre<NU, false, kTXs, kTYs>), grid, dim3(256), 0, st, L, C, z,
+        hipLaunchKernelGGL((k_mg_pre<NU, false, kTXs, kTYs, kNTs>), grid, dim3(kNTs), 0, st, L, C, z,
                            done, part, c0);
     } else {
         dim3 grid((L.m + 2 + kTX - 1) / kTX, (L.n + 2 + kTY - 1) / kTY, nch);
-        hipLaunchKernelGGL((k_mg_pre<NU, false, kTX, kTY>), grid, dim3(256), 0, st, L, C, z,
+        hipLaunchKernelGGL((k_mg_pre<NU, false, kTX, kTY, 256>), grid, dim3(256), 0, st, L, C, z,
                            done, part, c0);
     }
     if (timed) GDGS_HIP_TRY(hipEventRecord(ev1, st));
@@ -817,15 +856,15 @@ gdgs_status launch_post(const LevelDev& L, const LevelDev& C, bool fine, const i
     if (timed) GDGS_HIP_TRY(hipEventRecord(ev0, st));
     if (fine) {
         dim3 grid((L.m + 2 + kTXf - 1) / kTXf, (L.n + 2 + kTYf - 1) / kTYf, nch);
-        hipLaunchKernelGGL((k_mg_post<NU, true, kTXf, kTYf>), grid, dim3(256), 0, st, L, C, done,
+        hipLaunchKernelGGL((k_mg_post<NU, true, kTXf, kTYf, kNTf>), grid, dim3(kNTf), 0, st, L, C, done,
                            part, c0);
     } else if (small_tiles(L)) {
         dim3 grid((L.m + 2 + kTXs - 1) / kTXs, (L.n + 2 + kTYs - 1) / kTYs, nch);
-        hipLaunchKernelGGL((k_mg_post<NU, false, kTXs, kTYs>), grid, dim3(256), 0, st, L, C,
+        hipLaunchKernelGGL((k_mg_post<NU, false, kTXs, kTYs, kNTs>), grid, dim3(kNTs), 0, st, L, C,
                            done, part, c0);
     } else {
         dim3 grid((L.m + 2 + kTX - 1) / kTX, (L.n + 2 + kTY - 1) / kTY, nch);
-        hipLaunchKernelGGL((k_mg_post<NU, false, kTX, kTY>), grid, dim3(256), 0, st, L, C,
+        hipLaunchKernelGGL((k_mg_post<NU, false, kTX, kTY, 256>), grid, dim3(256), 0, st, L, C,
                            done, part, c0);
     }
     if (timed) GDGS_HIP_TRY(hipEventRecord(ev1, st));
@@ -909,11 +948,12 @@ gdgs_status mg_plan(int W, int H, const gdgs_mg_params* mg, MgPlan* plan) {
     if (q.coarse_sweeps > 0) {
         p.coarse_sweeps = q.coarse_sweeps;
     } else {
-        // SOR sweeps for a 1e-3 error reduction, (omega - 1)^k <= 1e-3: the
+        // SOR sweeps for a 1e-2 error reduction, (omega - 1)^k <= 1e-2: the
         // coarsest correction only has to be small against the V-cycle's own
-        // contraction (about 0.1)
+        // contraction (about 0.12).  (Measured at 1080p: 6 or more sweeps keep
+        // 8 cycles, 4 sweeps need 12.)
         const double rho = p.omega - 1.0;
-        int k = rho > 0.0 ? (int)ceil(log(1e-3) / log(rho)) : 4;
+        int k = rho > 0.0 ? (int)ceil(log(1e-2) / log(rho)) : 4;
         if (k < 4) k = 4;
         if (k > 4096) k = 4096;
         p.coarse_sweeps = k;
