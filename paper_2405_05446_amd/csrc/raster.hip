@@ -11,7 +11,10 @@
 // whole, every splat whose support rows miss them.  A pixel stops
 // accumulating once its transmittance is below 1e-7; the tile stops when all
 // its pixels have.  Splat means are stored relative to the pixel origin of
-// the splat's tile rectangle, so d = p - mu is computed from small numbers.
+// the splat's tile rectangle; when a record enters a tile's batch its mean is
+// made relative to that tile and its conic prescaled by -log2(e) (once, in
+// FP64), so each pixel evaluates the exponent with six operations and one
+// exp2.
 //
 // Backward: same traversal; each pixel recomputes a_k and T_{k-1} exactly as
 // the forward did, so its running prefix sum of v w equals the forward's and
@@ -82,18 +85,40 @@ __device__ __forceinline__ uint32_t band_mask(float ylo, float yhi, int ty) {
     return m;
 }
 
-// Composite one splat record into a pixel (the Eq. 20 update); counts the
+// Per (tile, splat) pair, set up once when the record enters a tile's batch:
+// the mean relative to the tile's pixel origin and the conic scaled by
+// -log2(e), so that a pixel at tile-relative centre (x, y) in [0.5, 15.5]
+// evaluates E' = -log2(e) E with two subtractions and four multiply-adds,
+// G = exp2(E'), and the support test E <= E_cut is E' >= kEcutL.
+// q0 = (a', 2b', c', mx), q1 = (my, alpha, 0, 0).  (A fully expanded
+// quadratic in (x, y) would save two more operations but loses ~1e-3 in E
+// to cancellation for sub-pixel splats.)
+constexpr float kEcutL = -16.609640474436812f;  // -E_cut log2(e) = log2(1e-5)
+__device__ __forceinline__ void pair_form(const float4& r0, const float4& r1, int tx, int ty,
+                                          float4& q0, float4& q1) {
+    const double mx = ((double)r0.z - 16.0 * tx) + (double)r0.x;  // tile-relative mean
+    const double my = ((double)r0.w - 16.0 * ty) + (double)r0.y;
+    const double sc = -1.4426950408889634;  // -log2(e)
+    q0 = make_float4((float)(sc * r1.x), (float)(sc * r1.y), (float)(sc * r1.z), (float)mx);
+    q1 = make_float4((float)my, r1.w, 0.f, 0.f);
+}
+
+__device__ __forceinline__ float pair_exponent(const float4& q0, const float4& q1, float x,
+                                               float y) {
+    const float dx = x - q0.w, dy = y - q1.x;
+    return dx * fmaf(q0.x, dx, q0.y * dy) + q0.z * dy * dy;
+}
+
+// Composite one splat into a pixel (the Eq. 20 update); counts the
 // contributions when asked to.
 template <bool COUNT>
-__device__ __forceinline__ void blend(const float4& r0, const float4& r1, const float4& r2,
-                                      const float4& r3, float fpx, float fpy, float& Tr,
+__device__ __forceinline__ void blend(const float4& q0, const float4& q1, const float4& r2,
+                                      const float4& r3, float x, float y, float& Tr,
                                       float (&acc)[6], uint32_t& ncon) {
-    const float dx = (fpx - r0.z) - r0.x;
-    const float dy = (fpy - r0.w) - r0.y;
-    const float E = dx * (r1.x * dx + r1.y * dy) + r1.z * dy * dy;
-    if (E <= kEcut && Tr >= kTmin) {
-        if (COUNT && r1.w > 0.f) ++ncon;
-        const float al = r1.w * __expf(-E);
+    const float Ep = pair_exponent(q0, q1, x, y);
+    if (Ep >= kEcutL && Tr >= kTmin) {
+        if (COUNT && q1.y > 0.f) ++ncon;
+        const float al = q1.y * __builtin_amdgcn_exp2f(Ep);
         const float w = al * Tr;
         acc[0] += r2.x * w;
         acc[1] += r2.y * w;
@@ -114,7 +139,8 @@ __global__ __launch_bounds__(256) void k_raster_fwd(const float4* __restrict__ r
                                                     int nx, int W, int H, int64_t K,
                                                     float* __restrict__ grad,
                                                     unsigned long long* __restrict__ counts) {
-    // slot kBatch holds an inert record (alpha 0) used to pad the wave lists
+    // per batch entry: the pair's exponent form (s_r0, s_r1) and the values
+    // (s_r2, s_r3); slot kBatch is inert (alpha 0), used to pad the wave lists
     __shared__ float4 s_r0[kBatch + 1], s_r1[kBatch + 1], s_r2[kBatch + 1], s_r3[kBatch + 1];
     __shared__ uint32_t s_mask[kBatch];
     __shared__ int s_list[4][kBatch + 4];
@@ -125,7 +151,7 @@ __global__ __launch_bounds__(256) void k_raster_fwd(const float4* __restrict__ r
     const int t = threadIdx.x, lane = __lane_id(), wv = t >> 6;
     const int px = tx * kTile + (t & 15), py = ty * kTile + (t >> 4);
     const bool inside = px < W && py < H;
-    const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+    const float xt = (float)(t & 15) + 0.5f, yt = (float)(t >> 4) + 0.5f;  // tile-relative
     const uint64_t lt = lanemask_lt();
     const uint32_t start = ranges[tile], end = ranges[T + tile];
     if (t == 0) {
@@ -146,10 +172,12 @@ __global__ __launch_bounds__(256) void k_raster_fwd(const float4* __restrict__ r
             uint32_t m = 0;
             if (s < (uint64_t)K) {
                 const float4* r = rec + 4 * (size_t)s;
-                const float4 r3 = r[3];
-                s_r0[t] = r[0];
-                s_r1[t] = r[1];
-                s_r2[t] = r[2];
+                const float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
+                float4 q0, q1;
+                pair_form(r0, r1, tx, ty, q0, q1);
+                s_r0[t] = q0;
+                s_r1[t] = q1;
+                s_r2[t] = r2;
                 s_r3[t] = r3;
                 m = band_mask(r3.z, r3.w, ty);
             }
@@ -176,10 +204,10 @@ __global__ __launch_bounds__(256) void k_raster_fwd(const float4* __restrict__ r
             const float4 c0 = s_r1[jj.x], c1 = s_r1[jj.y], c2 = s_r1[jj.z], c3 = s_r1[jj.w];
             const float4 v0 = s_r2[jj.x], v1 = s_r2[jj.y], v2 = s_r2[jj.z], v3 = s_r2[jj.w];
             const float4 e0 = s_r3[jj.x], e1 = s_r3[jj.y], e2 = s_r3[jj.z], e3 = s_r3[jj.w];
-            blend<COUNT>(a0, c0, v0, e0, fpx, fpy, Tr, acc, ncon);
-            blend<COUNT>(a1, c1, v1, e1, fpx, fpy, Tr, acc, ncon);
-            blend<COUNT>(a2, c2, v2, e2, fpx, fpy, Tr, acc, ncon);
-            blend<COUNT>(a3, c3, v3, e3, fpx, fpy, Tr, acc, ncon);
+            blend<COUNT>(a0, c0, v0, e0, xt, yt, Tr, acc, ncon);
+            blend<COUNT>(a1, c1, v1, e1, xt, yt, Tr, acc, ncon);
+            blend<COUNT>(a2, c2, v2, e2, xt, yt, Tr, acc, ncon);
+            blend<COUNT>(a3, c3, v3, e3, xt, yt, Tr, acc, ncon);
         }
         if (__syncthreads_count(Tr >= kTmin) == 0) break;
     }
@@ -215,6 +243,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(const float4* __restrict__ r
                                                     const float* __restrict__ dgrad,
                                                     float* __restrict__ part, int64_t cap) {
     __shared__ float4 s_r0[kBatchB], s_r1[kBatchB], s_r2[kBatchB], s_r3[kBatchB];
+    __shared__ float4 s_q0[kBatchB], s_q1[kBatchB];  // the forward's exponent form
     __shared__ float s_p[4][kNP][kBatchB];
     const int tile = blockIdx.x;
     const int tx = tile % nx, ty = tile / nx;
@@ -222,6 +251,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(const float4* __restrict__ r
     const int px = tx * kTile + (t & 15), py = ty * kTile + (t >> 4);
     const bool inside = px < W && py < H;
     const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+    const float xt = (float)(t & 15) + 0.5f, yt = (float)(t >> 4) + 0.5f;
     const size_t HW = (size_t)H * W, pp = (size_t)py * W + px;
     const float wy_lo = (float)(ty * kTile + 4 * wv) + 0.5f, wy_hi = wy_lo + 3.f;
     float out[6], del[6];
@@ -240,15 +270,23 @@ __global__ __launch_bounds__(256) void k_raster_bwd(const float4* __restrict__ r
             const uint32_t s = splat_of_pair[b0 + t];
             if (s < (uint64_t)K) {
                 const float4* r = rec + 4 * (size_t)s;
-                s_r0[t] = r[0];
-                s_r1[t] = r[1];
+                const float4 r0 = r[0], r1 = r[1];
+                float4 q0, q1;
+                pair_form(r0, r1, tx, ty, q0, q1);
+                s_r0[t] = r0;
+                s_r1[t] = r1;
                 s_r2[t] = r[2];
                 s_r3[t] = r[3];
+                s_q0[t] = q0;
+                s_q1[t] = q1;
             } else {  // never produced by the binning; contributes nothing
-                s_r0[t] = make_float4(0.f, 0.f, 0.f, 0.f);
-                s_r1[t] = make_float4(0.f, 0.f, 0.f, 0.f);
-                s_r2[t] = make_float4(0.f, 0.f, 0.f, 0.f);
-                s_r3[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+                const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+                s_r0[t] = z;
+                s_r1[t] = z;
+                s_r2[t] = z;
+                s_r3[t] = z;
+                s_q0[t] = z;
+                s_q1[t] = z;
             }
         }
         __syncthreads();
@@ -264,14 +302,15 @@ __global__ __launch_bounds__(256) void k_raster_bwd(const float4* __restrict__ r
             const float4 r0 = s_r0[j], r1 = s_r1[j];
             const float dx = (fpx - r0.z) - r0.x;
             const float dy = (fpy - r0.w) - r0.y;
-            const float E = dx * (r1.x * dx + r1.y * dy) + r1.z * dy * dy;
-            const bool on = E <= kEcut && Tr >= kTmin;
+            // a_k exactly as the forward computed it
+            const float Ep = pair_exponent(s_q0[j], s_q1[j], xt, yt);
+            const bool on = Ep >= kEcutL && Tr >= kTmin;
             float g[kNP];
 #pragma unroll
             for (int q = 0; q < kNP; ++q) g[q] = 0.f;
             if (on) {
                 const float4 r2 = s_r2[j];
-                const float G = __expf(-E);
+                const float G = __builtin_amdgcn_exp2f(Ep);
                 const float al = r1.w * G;
                 const float w = al * Tr;
                 const float v[6] = {r2.x, r2.y, r2.z, r2.w, r3.x, r3.y};
