@@ -53,3 +53,15 @@ def test_host_only_calls_validate_arguments(lib):
     assert g(10, 2, 64, 100, ctypes.byref(n)) == 1     # W < 3
     assert g(10, 64, 64, 0, ctypes.byref(n)) == 1      # zero capacity
     assert g(10, 64, 64, 100, ctypes.byref(n)) == 0
+
+
+def test_image_size_limits(lib):
+    # tile rectangles pack 16-bit tile coordinates: at most 65535 tiles a side
+    n = ctypes.c_size_t(0)
+    g = lib.gdgs_bin_sort_workspace_size
+    g.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                  ctypes.POINTER(ctypes.c_size_t)]
+    assert g(10, 16 * 65535 + 1, 64, 100, ctypes.byref(n)) == 1
+    assert g(10, 64, 16 * 65535 + 1, 100, ctypes.byref(n)) == 1
+    assert g(10, 16 * 65535, 64, 100, ctypes.byref(n)) == 0
+    assert g(10, 3, 3, 100, ctypes.byref(n)) == 0
