@@ -94,6 +94,11 @@ def cpu_baseline(scene, cam, ring, npix):
     from oracle.project import project
 
     H, W = cam.H, cam.W
+    try:     # one thread throughout, BLAS included, so that `cores` is exact
+        from threadpoolctl import threadpool_limits
+        limit = threadpool_limits(1)
+    except ImportError:
+        limit = None
     t0 = time.perf_counter()
     proj = project(scene, cam)
     t1 = time.perf_counter()
@@ -104,6 +109,8 @@ def cpu_baseline(scene, cam, ring, npix):
     grad = rng.laplace(0.0, 0.01, (6, H, W))
     P.solve_dst(P.divergence(grad), ring, workers=1)
     t3 = time.perf_counter()
+    if limit is not None:
+        limit.unregister()
     per_px = (t2 - t1) / rows.size
     frame = (t1 - t0) + per_px * H * W + (t3 - t2)
     return dict(value=round(H * W / frame / 1e6, 8), unit="Mpix/s", cores=1, kind="oracle",
