@@ -142,11 +142,15 @@ gdgs_status mg_plan(int W, int H, const gdgs_mg_params* mg, MgPlan* plan);
 size_t poisson_ws_bytes(const MgPlan& plan, int W, int H);
 // grad != nullptr: divergence of grad; else rho is the right-hand side.
 class KeyBuilder;
-// key: graph-cache key of the whole call (extended per segment when the solve
-// is split so that timed kernels launch directly); may be null.
+// key: graph-cache key of the whole call (extended per segment); may be null.
+// channel_parallel: run each colour channel's V-cycles on its own helper
+// stream (lowest latency for one solve); false runs all channels in each
+// launch on `st`, the whole solve replayed as one graph (least host work,
+// for callers that already overlap many solves).
 gdgs_status launch_poisson(const float* grad, const float* rho, const float* boundary, int W,
                            int H, const MgPlan& plan, float* u, gdgs_stats* stats, void* ws,
-                           hipStream_t st, const KeyBuilder* key = nullptr);
+                           hipStream_t st, const KeyBuilder* key = nullptr,
+                           bool channel_parallel = true);
 gdgs_status launch_div_adjoint(const float* lam, int W, int H, float* dgrad, hipStream_t st);
 
 // ---------------------------------------------------------------- whole frame

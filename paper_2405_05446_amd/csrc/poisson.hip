@@ -1014,7 +1014,7 @@ size_t poisson_ws_bytes(const MgPlan& plan, int W, int H) {
 
 gdgs_status launch_poisson(const float* grad, const float* rho, const float* boundary, int W,
                            int H, const MgPlan& p, float* u, gdgs_stats* stats, void* ws,
-                           hipStream_t st, const KeyBuilder* key) {
+                           hipStream_t st, const KeyBuilder* key, bool channel_parallel) {
     PoissonWs w;
     poisson_layout(p, W, H, ws, &w);
     gdgs_stats* sd = stats ? stats : w.stats;
@@ -1134,16 +1134,41 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
     // The three colour channels are independent systems: each runs its
     // V-cycles on its own stream, so one channel's bandwidth-bound finest
     // passes overlap another's latency-bound coarse grids.
+    const bool timed =
+        p.lc > 0 && (timer_active("mg_pre_fine") || timer_active("mg_post_fine"));
     ChannelStreams cs;
-    if (!channel_streams(st, &cs)) {
-        for (int cyc = 0; cyc < p.max_cycles && r == GDGS_OK; ++cyc) r = cycle(0, 3, st);
+    if (!channel_parallel || !channel_streams(st, &cs)) {
+        // all channels in each launch, on the caller's stream
+        if (!timed) {
+            auto all = [&](hipStream_t s) -> gdgs_status {
+                gdgs_status t = GDGS_OK;
+                for (int cyc = 0; cyc < p.max_cycles && t == GDGS_OK; ++cyc) t = cycle(0, 3, s);
+                return t;
+            };
+            if (!key) return all(st);
+            KeyBuilder ka = *key;
+            ka.tag("cycles3");
+            return with_graph(ka, st, all);
+        }
+        for (int cyc = 0; cyc < p.max_cycles && r == GDGS_OK; ++cyc) {
+            pre(0, 0, 3, st);
+            auto mid = [&](hipStream_t s) { return body(0, 3, s); };
+            if (key) {
+                KeyBuilder kb = *key;
+                kb.tag("body3");
+                r = with_graph(kb, st, mid);
+            } else {
+                r = mid(st);
+            }
+            if (r != GDGS_OK) break;
+            post(0, 0, 3, st);
+            r = finalize(0, 3, st);
+        }
         return r;
     }
     hipStream_t sc[3] = {st, cs.aux[0], cs.aux[1]};
     GDGS_HIP_TRY(hipEventRecord(cs.fork, st));
     for (int k = 0; k < 2; ++k) GDGS_HIP_TRY(hipStreamWaitEvent(cs.aux[k], cs.fork, 0));
-    const bool timed =
-        p.lc > 0 && (timer_active("mg_pre_fine") || timer_active("mg_post_fine"));
     // Cycles are launched in rounds over the channels, so that all three
     // streams have work queued early.  (Measured alternatives: one graph per
     // channel for all cycles, staggered channel starts, one graph with three

@@ -5,9 +5,8 @@
 // each request's frame on the request's own stream -- the projection with
 // the request's camera, a copy of its boundary ring into its slot, then the
 // binning and compositing as one cached graph per slot and size, the Poisson
-// solve (its own cached graphs, one per colour channel on helper streams
-// bound to the request's stream), a copy of the result to the caller's
-// buffer and of the statistics to pinned host memory -- and records an event.  When the event has fired it
+// solve as another, a copy of the result to the caller's buffer and of the
+// statistics to pinned host memory -- and records an event.  When the event has fired it
 // reads the statistics: a pair overflow sends the request back to the queue
 // with a larger capacity, an unconverged solve is resumed two V-cycles at a
 // time (GDGS_MG_RESUME: bit for bit the same as one longer solve), and a
@@ -198,8 +197,10 @@ struct gdgs_server {
                                  L.rw.raster_ws, q);
         });
         if (e != GDGS_OK) return e;
+        // requests already overlap one another: the solve stays on the
+        // request's stream as one graph
         e = launch_poisson(L.rw.grad, nullptr, bnd, W, H, *plan, L.u, L.stats, L.rw.poisson_ws,
-                           st, &kb);
+                           st, &kb, false);
         if (e != GDGS_OK) return e;
         e = launch_render_stats(L.rw.bins.num_pairs, cap, L.stats, st);
         if (e != GDGS_OK) return e;
@@ -223,7 +224,7 @@ struct gdgs_server {
             .add(bnd);
         add_plan(kb, *plan);
         const gdgs_status e = launch_poisson(L.rw.grad, nullptr, bnd, W, H, *plan, L.u,
-                                             L.stats, L.rw.poisson_ws, st, &kb);
+                                             L.stats, L.rw.poisson_ws, st, &kb, false);
         if (e != GDGS_OK) return e;
         return finish_enqueue(r, L, p, st);
     }
