@@ -210,7 +210,7 @@ def main():
     mg = G.mg_params(levels=cfg["levels"], tol=cfg["tol"])
     cams = [wl.make_camera(W, H, pose_index=i) for i in range(100)]
 
-    # the plain per-request path: one Renderer owns all buffers; a probe frame
+    # the plain per-view path: a Renderer owns all buffers; a probe frame
     # (outside the timed region) sizes the pair capacity and the cycle budget
     r = G.Renderer(ds, W, H, mg)
     r.render(cams[0], ring)
@@ -221,7 +221,7 @@ def main():
     # passes takes them out of the per-channel graphs (one direct launch and
     # two event records per pass), which changes how the frame runs, so those
     # are timed in a separate pass over the same poses below.
-    NT = 64
+    NT = max(64, args.steps + 16)
     k_ev = {name: ([torch.cuda.Event(enable_timing=True) for _ in range(NT)],
                    [torch.cuda.Event(enable_timing=True) for _ in range(NT)])
             for name in ("raster", "mg_post_fine")}
@@ -235,28 +235,32 @@ def main():
         a0, a1 = k_ev[name]
         return [a0[j].elapsed_time(a1[j]) for j in range(G.api.kernel_timer_count(name))]
 
+    # frames are rendered as a sequence: one view at a time on the GPU, the
+    # host enqueueing view i + 1 before it settles view i (Renderer.render_sequence)
     arm(["raster"])
-    for i in range(args.warmup):
-        r.render(cams[i % len(cams)], ring)
+    r.render_sequence([cams[i % len(cams)] for i in range(args.warmup)], ring)
     torch.cuda.synchronize()
 
-    cycles, k_ms = [], {"raster": [], "mg_post_fine": []}
+    cycles, k_ms, last = [], {"raster": [], "mg_post_fine": []}, {}
+
+    def on_frame(i, u, st):
+        cycles.append(st["total_cycles"])
+        last.update(st)
+        if not st["converged"]:
+            print(f"warning: frame {i} did not converge: {st}", file=sys.stderr)
+
+    G.api.rewind_kernel_timers()
     t0 = time.perf_counter()
-    for i in range(args.steps):
-        G.api.rewind_kernel_timers()
-        r.render(cams[i % len(cams)], ring, events=ev[i])
-        cycles.append(r.last["total_cycles"])
-        # render() synchronised on its statistics: this frame's events are done
-        k_ms["raster"].append(read("raster"))
-        if not r.last["converged"]:
-            print(f"warning: frame {i} did not converge: {r.last}", file=sys.stderr)
+    r.render_sequence([cams[i % len(cams)] for i in range(args.steps)], ring, events=ev,
+                      on_frame=on_frame)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    k_ms["raster"].append(read("raster"))
     ms = (t1 - t0) * 1e3 / args.steps
     stage_ms = np.array([[ev[i][s].elapsed_time(ev[i][s + 1]) for s in range(4)]
                          for i in range(args.steps)])
     frame_ms = np.array([ev[i][0].elapsed_time(ev[i][4]) for i in range(args.steps)])
-    P = r.last["num_pairs"]
+    P = last["num_pairs"]
     names = ["project", "bin_sort", "raster", "poisson"]
     mean_stage = stage_ms.mean(axis=0)
     mean_cycles = float(np.mean(cycles))

@@ -377,25 +377,47 @@ class Renderer:
         return mg_params(m.levels, m.pre_sweeps, m.post_sweeps, cycles, m.tol, m.coarse_sweeps,
                          flags)
 
-    def render(self, cam, boundary=None, events=None, stream=None) -> torch.Tensor:
+    def _enqueue(self, cam, boundary, events, stream):
+        """Enqueue one frame (no waiting): the four steps, then an asynchronous
+        copy of its statistics and pair count to pinned host memory."""
         K, W, H = self.scene.K, self.W, self.H
-        rec = (lambda i: events[i].record(torch.cuda.current_stream())) if events else (lambda i: None)
+        s = stream if stream is not None else torch.cuda.current_stream(self.dev)
+        if not hasattr(self, "_h_stats"):
+            self._h_stats = torch.empty(STATS_BYTES, dtype=torch.uint8, pin_memory=True)
+            self._h_pairs = torch.empty(1, dtype=torch.int64, pin_memory=True)
+            self._done = torch.cuda.Event()
+        rec = (lambda i: events[i].record(s)) if events else (lambda i: None)
         rec(0)
-        gdgs_project(self.scene, cam, self.proj, stream)
+        gdgs_project(self.scene, cam, self.proj, s)
         rec(1)
-        gdgs_bin_sort(self.proj, K, W, H, self.capacity, self.bins, self.ws_bin, stream)
+        gdgs_bin_sort(self.proj, K, W, H, self.capacity, self.bins, self.ws_bin, s)
         rec(2)
         gdgs_raster_grad(self.proj, self.scene.opacity, self.scene.value, K, self.bins, W, H,
-                         self.grad, self.ws_ras, stream)
+                         self.grad, self.ws_ras, s)
         rec(3)
         gdgs_poisson_solve(self.grad, boundary, W, H, self._mg(self.budget), self.u, self.stats,
-                           self.ws_poi, stream)
+                           self.ws_poi, s)
         rec(4)
-        st = read_stats(self.stats)
-        if int(self.bins["num_pairs"].item()) > self.capacity:
-            self._set_capacity(int(self.bins["num_pairs"].item() * 1.25) + 1024)
+        with torch.cuda.stream(s):
+            self._h_stats.copy_(self.stats, non_blocking=True)
+            self._h_pairs.copy_(self.bins["num_pairs"], non_blocking=True)
+        self._done.record(s)
+
+    def _finish(self, cam, boundary, events, stream) -> torch.Tensor:
+        """Wait for the enqueued frame (only it) and settle it: a pair overflow
+        grows the buffers and renders the frame again; an unconverged solve
+        is resumed."""
+        self._done.synchronize()
+        raw = bytes(self._h_stats.numpy().tobytes())
+        sr = L.Stats.from_buffer_copy(raw)
+        st = dict(cycles=list(sr.cycles), converged=bool(sr.converged), eta=list(sr.eta),
+                  rel_res=list(sr.rel_res), b_norm=list(sr.b_norm), delta=list(sr.delta))
+        pairs = int(self._h_pairs[0])
+        if pairs > self.capacity:
+            self._set_capacity(int(pairs * 1.25) + 1024)
             self.budget = self.max_cycles
             return self.render(cam, boundary, events, stream)
+        W, H = self.W, self.H
         total = max(st["cycles"])
         while not st["converged"] and total < self.max_cycles:
             step = min(2, self.max_cycles - total)
@@ -404,8 +426,41 @@ class Renderer:
             st = read_stats(self.stats)
             total = max(st["cycles"])     # cycle counts accumulate over resumed calls
         st["total_cycles"] = total
-        st["num_pairs"] = int(self.bins["num_pairs"].item())
+        st["num_pairs"] = pairs
         if self.adaptive:
             self.budget = max(1, min(self.max_cycles, total))
         self.last = st
         return self.u
+
+    def render(self, cam, boundary=None, events=None, stream=None) -> torch.Tensor:
+        self._enqueue(cam, boundary, events, stream)
+        return self._finish(cam, boundary, events, stream)
+
+    def render_sequence(self, cams, boundary=None, events=None, on_frame=None, stream=None):
+        """Render views one after another without the host waiting in between:
+        frame i + 1 is enqueued before frame i is settled.  Two buffer sets
+        alternate (this renderer and a twin), so frame i's result stays intact
+        until on_frame(i, u, stats) has seen it; results equal render()'s."""
+        if not hasattr(self, "_twin"):
+            self._twin = Renderer(self.scene, self.W, self.H, self.mg, self.capacity,
+                                  self.adaptive)
+        rs = [self, self._twin]
+        prev = None
+        for i, cam in enumerate(cams):
+            r = rs[i % 2]
+            if prev is not None:
+                r.budget = prev[0].budget
+            r._enqueue(cam, boundary, events[i] if events else None, stream)
+            if prev is not None:
+                pr, pcam, pi = prev
+                u = pr._finish(pcam, boundary, events[pi] if events else None, stream)
+                r.budget = max(r.budget, pr.budget)
+                if on_frame is not None:
+                    on_frame(pi, u, pr.last)
+            prev = (r, cam, i)
+        if prev is not None:
+            pr, pcam, pi = prev
+            u = pr._finish(pcam, boundary, events[pi] if events else None, stream)
+            self.budget = self._twin.budget = pr.budget
+            if on_frame is not None:
+                on_frame(pi, u, pr.last)
