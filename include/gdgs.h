@@ -99,6 +99,10 @@ typedef struct gdgs_bins {
     uint32_t* order;      /* [K] splat index of depth rank s (stable: ties by index; culled last) */
     uint32_t* ranges;     /* [2][T] start and end (half-open) of each tile, T = ceil(W/16) ceil(H/16) */
     int64_t* num_pairs;   /* [1] total pairs P; pairs beyond capacity are dropped */
+    uint32_t* tile_order; /* [T] or NULL: the tiles, those with the most pairs first (by
+                           * floor(log2(pairs)), ties by tile id; empty tiles last).  Only
+                           * the order in which the compositing kernels take the tiles;
+                           * NULL takes them by tile id.  Images do not depend on it. */
 } gdgs_bins;
 
 /* Multigrid parameters (host struct) for the Poisson solve (Eq. 21).
@@ -208,6 +212,7 @@ gdgs_status gdgs_project_2d(const float* mean2d, const float* conic, const float
  * by FP32 depth (culled last), one (tile, rank) pair per tile of each splat's
  * rectangle, stable radix sort of the pairs by tile, tile ranges.  The pair
  * order equals a lexicographic sort by (tile, FP32 depth bits, splat index).
+ * If bins->tile_order is not NULL it receives the heaviest-first tile order.
  * Writes bins->num_pairs = P on the device; only the first min(P, capacity)
  * pairs are kept and later steps use those (check P after the stream syncs).
  * Workspace: gdgs_bin_sort_workspace_size(K, W, H, bins->capacity). */

@@ -52,7 +52,8 @@ class Proj(ctypes.Structure):
 class Bins(ctypes.Structure):
     _fields_ = [("capacity", ctypes.c_int64), ("tile_of_pair", ctypes.c_void_p),
                 ("splat_of_pair", ctypes.c_void_p), ("order", ctypes.c_void_p),
-                ("ranges", ctypes.c_void_p), ("num_pairs", ctypes.c_void_p)]
+                ("ranges", ctypes.c_void_p), ("num_pairs", ctypes.c_void_p),
+                ("tile_order", ctypes.c_void_p)]
 
 
 class MgParams(ctypes.Structure):

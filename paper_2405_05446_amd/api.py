@@ -102,7 +102,10 @@ def _proj_struct(p: dict) -> L.Proj:
                   L.ptr(p["count"]))
 
 
-def alloc_bins(K: int, W: int, H: int, capacity: int, device=None) -> dict:
+def alloc_bins(K: int, W: int, H: int, capacity: int, device=None,
+               tile_order: bool = True) -> dict:
+    """Device arrays of gdgs_bins; tile_order=False leaves the heaviest-first
+    tile schedule out (the compositing kernels then take tiles by id)."""
     d = _dev(device)
     T = ((W + 15) // 16) * ((H + 15) // 16)
     return dict(capacity=int(capacity),
@@ -110,12 +113,14 @@ def alloc_bins(K: int, W: int, H: int, capacity: int, device=None) -> dict:
                 splat_of_pair=torch.empty(capacity, dtype=U32, device=d),
                 order=torch.empty(max(K, 1), dtype=U32, device=d),
                 ranges=torch.empty((2, T), dtype=U32, device=d),
-                num_pairs=torch.zeros(1, dtype=torch.int64, device=d))
+                num_pairs=torch.zeros(1, dtype=torch.int64, device=d),
+                tile_order=torch.empty(T, dtype=U32, device=d) if tile_order else None)
 
 
 def _bins_struct(b: dict) -> L.Bins:
     return L.Bins(b["capacity"], L.ptr(b["tile_of_pair"]), L.ptr(b["splat_of_pair"]),
-                  L.ptr(b["order"]), L.ptr(b["ranges"]), L.ptr(b["num_pairs"]))
+                  L.ptr(b["order"]), L.ptr(b["ranges"]), L.ptr(b["num_pairs"]),
+                  L.ptr(b.get("tile_order")))
 
 
 def read_stats(stats: torch.Tensor) -> dict:

@@ -240,8 +240,9 @@ size_t render_layout(int64_t K, int W, int H, int64_t cap, const MgPlan& plan, v
     r.bins.order = c.take<uint32_t>(Kp);
     r.bins.ranges = c.take<uint32_t>(2 * (size_t)tiles_x(W) * tiles_y(H));
     r.bins.num_pairs = c.take<int64_t>(1);
+    r.bins.tile_order = c.take<uint32_t>((size_t)tiles_x(W) * tiles_y(H));
     r.grad = c.take<float>((size_t)6 * W * H);
-    r.bin_ws = c.take<char>(bin_ws_layout(K, cap, nullptr, nullptr));
+    r.bin_ws = c.take<char>(bin_ws_layout(K, cap, num_tiles(W, H), nullptr, nullptr));
     r.raster_ws = c.take<char>(raster_ws_bytes(K));
     r.poisson_ws = c.take<char>(poisson_ws_bytes(plan, W, H));
     if (out) *out = r;
@@ -277,7 +278,7 @@ void add_proj(KeyBuilder& kb, const gdgs_proj& p) {
 
 void add_bins(KeyBuilder& kb, const gdgs_bins& b) {
     kb.add(b.capacity).add(b.tile_of_pair).add(b.splat_of_pair).add(b.order).add(b.ranges)
-        .add(b.num_pairs);
+        .add(b.num_pairs).add(b.tile_order);
 }
 
 }  // namespace gdgs
@@ -357,7 +358,7 @@ gdgs_status gdgs_bin_sort_workspace_size(int64_t K, int32_t W, int32_t H, int64_
     TRY(check_size(W, H));
     REQUIRE(pair_capacity >= 1 && pair_capacity < (int64_t)0xFFFFFFFFll,
             "pair capacity %lld out of range", (long long)pair_capacity);
-    *bytes = bin_ws_layout(K, pair_capacity, nullptr, nullptr);
+    *bytes = bin_ws_layout(K, pair_capacity, num_tiles(W, H), nullptr, nullptr);
     return GDGS_OK;
 }
 
@@ -441,9 +442,10 @@ gdgs_status gdgs_bin_sort(const gdgs_proj* proj, int64_t K, int32_t W, int32_t H
     TRY(check_size(W, H));
     if (K > 0) TRY(check_proj(proj));
     TRY(check_bins(bins, K));
-    TRY(check_ws(ws, ws_bytes, bin_ws_layout(K, bins->capacity, nullptr, nullptr)));
+    TRY(check_ws(ws, ws_bytes,
+                 bin_ws_layout(K, bins->capacity, num_tiles(W, H), nullptr, nullptr)));
     BinWs b;
-    bin_ws_layout(K, bins->capacity, ws, &b);
+    bin_ws_layout(K, bins->capacity, num_tiles(W, H), ws, &b);
     gdgs_proj p = K > 0 ? *proj : gdgs_proj{};
     const gdgs_bins bb = *bins;
     KeyBuilder kb;
@@ -571,7 +573,7 @@ gdgs_status gdgs_render(const gdgs_scene* scene, const gdgs_camera* cam, const f
     // rest depends only on sizes and buffers and is replayed as one graph
     if (K > 0) TRY(launch_project(*scene, *cam, r.proj, st));
     BinWs b;
-    bin_ws_layout(K, pair_capacity, r.bin_ws, &b);
+    bin_ws_layout(K, pair_capacity, num_tiles(W, H), r.bin_ws, &b);
     const gdgs_scene sc = *scene;
     KeyBuilder kb;
     kb.tag("render").add(K).add(W).add(H).add(pair_capacity).add(ws).add(sc.opacity)

@@ -393,6 +393,107 @@ __global__ void k_tile_ranges(const uint32_t* __restrict__ tiles, const int64_t*
     }
 }
 
+// Heaviest-first schedule of the tiles for the compositing kernels: a stable
+// counting sort of the tile ids by floor(log2(pairs)), largest first, empty
+// tiles last.  A tile's compositing time grows with its pair count, and the
+// hardware dispatches blocks in launch order, so starting the long tiles
+// first keeps them from finishing alone at the end of the launch.  Two
+// passes over blocks of kOrdThreads tiles: per-block key counts, then each
+// block places its tiles after those of every larger key and of the earlier
+// blocks with the same key.
+constexpr int kOrdThreads = 256;
+constexpr int kOrdWaves = kOrdThreads / 64;
+constexpr int kOrdKeys = 33;  // key 32 - bitlen(pairs): 0 (most) ... 32 (empty)
+constexpr int kOrdGroups = kOrdThreads / kOrdKeys;
+
+int tile_blocks(int64_t T) { return (int)((T + kOrdThreads - 1) / kOrdThreads); }
+
+__device__ __forceinline__ int tile_key(const uint32_t* __restrict__ ranges, int T, int i) {
+    const uint32_t n = ranges[T + i] - ranges[i];
+    return n == 0 ? 32 : __clz(n);  // __clz(n) = 32 - bitlen(n)
+}
+
+// Rank of this lane among the wave's valid lanes with the same key (lane
+// order); wc[key] receives the wave's count of each key present.
+__device__ __forceinline__ uint32_t wave_key_rank(int k, bool valid, uint32_t* wc) {
+    const uint64_t lt = lanemask_lt();
+    uint32_t rank = 0;
+    uint64_t rest = __ballot(valid);
+    while (rest) {
+        const int lk = __shfl(k, __ffsll((unsigned long long)rest) - 1);
+        const uint64_t m = __ballot(valid && k == lk);
+        if (valid && k == lk) rank = (uint32_t)__popcll(m & lt);
+        if (__lane_id() == 0) wc[lk] = (uint32_t)__popcll(m);
+        rest &= ~m;
+    }
+    return rank;
+}
+
+__global__ __launch_bounds__(kOrdThreads) void k_tile_hist(const uint32_t* __restrict__ ranges,
+                                                            int T, uint32_t* __restrict__ bh) {
+    __shared__ uint32_t s_wc[kOrdWaves][kOrdKeys];
+    const int t = threadIdx.x, wv = t >> 6;
+    const int i = blockIdx.x * kOrdThreads + t;
+    for (int j = t; j < kOrdWaves * kOrdKeys; j += kOrdThreads) (&s_wc[0][0])[j] = 0;
+    __syncthreads();
+    const bool valid = i < T;
+    wave_key_rank(valid ? tile_key(ranges, T, i) : 0, valid, s_wc[wv]);
+    __syncthreads();
+    if (t < kOrdKeys) {
+        uint32_t c = 0;
+        for (int w = 0; w < kOrdWaves; ++w) c += s_wc[w][t];
+        bh[(size_t)blockIdx.x * kOrdKeys + t] = c;
+    }
+}
+
+__global__ __launch_bounds__(kOrdThreads) void k_tile_place(const uint32_t* __restrict__ ranges,
+                                                             int T, const uint32_t* __restrict__ bh,
+                                                             uint32_t* __restrict__ order) {
+    __shared__ uint32_t s_wc[kOrdWaves][kOrdKeys];
+    __shared__ uint32_t s_tot[kOrdGroups][kOrdKeys], s_pre[kOrdGroups][kOrdKeys];
+    __shared__ uint32_t s_base[kOrdKeys];
+    const int t = threadIdx.x, wv = t >> 6, b = blockIdx.x, nb = gridDim.x;
+    const int i = b * kOrdThreads + t;
+    for (int j = t; j < kOrdWaves * kOrdKeys; j += kOrdThreads) (&s_wc[0][0])[j] = 0;
+    // per key: tiles in all blocks and in the blocks before this one, summed
+    // by kOrdGroups groups of kOrdKeys threads over strided blocks
+    if (t < kOrdGroups * kOrdKeys) {
+        const int q = t / kOrdKeys, k = t - q * kOrdKeys;
+        uint32_t tot = 0, pre = 0;
+        for (int g = q; g < nb; g += kOrdGroups) {
+            const uint32_t v = bh[(size_t)g * kOrdKeys + k];
+            tot += v;
+            pre += g < b ? v : 0u;
+        }
+        s_tot[q][k] = tot;
+        s_pre[q][k] = pre;
+    }
+    __syncthreads();
+    const bool valid = i < T;
+    const int key = valid ? tile_key(ranges, T, i) : 0;
+    const uint32_t rank = wave_key_rank(key, valid, s_wc[wv]);
+    if (t < 64) {  // wave 0: exclusive scan of the key totals
+        uint32_t tot = 0, pre = 0;
+        if (t < kOrdKeys)
+            for (int q = 0; q < kOrdGroups; ++q) {
+                tot += s_tot[q][t];
+                pre += s_pre[q][t];
+            }
+        uint32_t inc = tot;
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t v = __shfl_up(inc, d);
+            if (t >= d) inc += v;
+        }
+        if (t < kOrdKeys) s_base[t] = inc - tot + pre;
+    }
+    __syncthreads();
+    if (valid) {
+        uint32_t slot = s_base[key] + rank;
+        for (int w = 0; w < wv; ++w) slot += s_wc[w][key];
+        order[slot] = (uint32_t)i;
+    }
+}
+
 __global__ void k_fill_u32(uint32_t* __restrict__ p, size_t n, uint32_t v) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x)
@@ -449,7 +550,7 @@ int sort_grid(int64_t cap) {
     return (int)g;
 }
 
-size_t bin_ws_layout(int64_t K, int64_t cap, void* ws, BinWs* out) {
+size_t bin_ws_layout(int64_t K, int64_t cap, int64_t T, void* ws, BinWs* out) {
     Carver c(ws);
     BinWs b;
     const int64_t Kp = K > 0 ? K : 1;
@@ -466,6 +567,7 @@ size_t bin_ws_layout(int64_t K, int64_t cap, void* ws, BinWs* out) {
     b.hist = c.take<uint32_t>((size_t)kRadix * G);
     b.digit_tot = c.take<uint32_t>(kRadix);
     b.bsum = c.take<uint32_t>(2 * ((Kp + kScanTile - 1) / kScanTile + 1));
+    b.tile_bh = c.take<uint32_t>((size_t)kOrdKeys * tile_blocks(T > 0 ? T : 1));
     if (out) *out = b;
     return c.off + 256;
 }
@@ -479,6 +581,17 @@ gdgs_status launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st) {
     return GDGS_OK;
 }
 
+namespace {
+gdgs_status launch_tile_order(const uint32_t* ranges, int T, uint32_t* bh, uint32_t* order,
+                              hipStream_t st) {
+    const int nb = tile_blocks(T);
+    hipLaunchKernelGGL(k_tile_hist, dim3(nb), dim3(kOrdThreads), 0, st, ranges, T, bh);
+    hipLaunchKernelGGL(k_tile_place, dim3(nb), dim3(kOrdThreads), 0, st, ranges, T, bh, order);
+    GDGS_LAUNCH_CHECK();
+    return GDGS_OK;
+}
+}  // namespace
+
 gdgs_status launch_bin_sort(const gdgs_proj& proj, int64_t K, int W, int H, const gdgs_bins& bins,
                             const BinWs& ws, hipStream_t st) {
     const int nx = tiles_x(W), T = nx * tiles_y(H);
@@ -489,6 +602,10 @@ gdgs_status launch_bin_sort(const gdgs_proj& proj, int64_t K, int W, int H, cons
         hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(1024), 0, st,
                            reinterpret_cast<unsigned long long*>(ws.bsum), (int64_t)0,
                            bins.num_pairs);
+        if (bins.tile_order) {  // every tile empty: the order by id
+            s = launch_tile_order(bins.ranges, T, ws.tile_bh, bins.tile_order, st);
+            if (s != GDGS_OK) return s;
+        }
         GDGS_LAUNCH_CHECK();
         return GDGS_OK;
     }
@@ -532,6 +649,7 @@ gdgs_status launch_bin_sort(const gdgs_proj& proj, int64_t K, int W, int H, cons
     hipLaunchKernelGGL(k_tile_ranges, dim3(2048), dim3(256), 0, st, bins.tile_of_pair,
                        bins.num_pairs, bins.capacity, bins.ranges, T);
     GDGS_LAUNCH_CHECK();
+    if (bins.tile_order) return launch_tile_order(bins.ranges, T, ws.tile_bh, bins.tile_order, st);
     return GDGS_OK;
 }
 

@@ -78,6 +78,7 @@ struct Carver {
 
 inline int tiles_x(int W) { return (W + kTile - 1) / kTile; }
 inline int tiles_y(int H) { return (H + kTile - 1) / kTile; }
+inline int64_t num_tiles(int W, int H) { return (int64_t)tiles_x(W) * tiles_y(H); }
 
 // ---------------------------------------------------------------- sort
 // Sizes of the radix-sort launch for n (or a device-side n up to cap) keys.
@@ -93,8 +94,9 @@ struct BinWs {
     uint32_t* hist;      // [256][G]
     uint32_t* digit_tot; // [256]
     uint32_t* bsum;      // [nb] block sums of tile counts
+    uint32_t* tile_bh;   // [ceil(T/256)][33] per-block key counts of the tile order
 };
-size_t bin_ws_layout(int64_t K, int64_t cap, void* ws, BinWs* out);
+size_t bin_ws_layout(int64_t K, int64_t cap, int64_t T, void* ws, BinWs* out);
 
 gdgs_status launch_bin_sort(const gdgs_proj& proj, int64_t K, int W, int H, const gdgs_bins& bins,
                             const BinWs& ws, hipStream_t st);

@@ -99,10 +99,14 @@ __device__ __forceinline__ double res_value(float a, float b, float c, float e, 
 
 struct LdsPlan {
     int lc, L;
+    int lw;                // levels lw .. L-1 are run by one wave (lw == L: none)
     int n[kMaxLevels], m[kMaxLevels];
     float ey[kMaxLevels], ex[kMaxLevels], wy[kMaxLevels], wx[kMaxLevels];
     int off[kMaxLevels];   // float offset of u_l in LDS; f_l follows u_l
-    int scratch;           // float offset of the residual scratch
+    int roff[kMaxLevels];  // float offset of the residual of level l (l < L-1)
+    uint32_t mg_m[kMaxLevels], mg_h[kMaxLevels];  // division magics for m and (m+1)/2
+    int zero0, zero1;      // float range cleared at entry: coarse grids and residuals
+    int trash;             // float offset of 64 cells that take the stores of unused slots
     int pre, post, csweeps;
     float omega;
     LevelDev top;          // global arrays of level lc
@@ -549,49 +553,252 @@ struct RowMap {
     }
 };
 
-__device__ __forceinline__ void lds_gs(float* U, const float* F, int n, int m, float ey,
-                                       float ex, int color0, int sweeps, float omega) {
-    const int M = m + 2;
-    const RowMap rm(n);
+// q / d for q d < 2^32 with mg = floor(2^32 / d) + 1 (d >= 2), exact.
+__device__ __forceinline__ int udiv(int q, int d, uint32_t mg) {
+    const int h = (int)__umulhi((uint32_t)q, mg);
+    return d == 1 ? q : h;
+}
+
+// One wave's LDS operations are performed in order; this only keeps the
+// compiler from moving LDS accesses across the point.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The group of threads running a coarse-grid operation: the whole workgroup
+// (NT = blockDim.x, __syncthreads between steps) or wave 0 alone.
+template <int NT>
+__device__ __forceinline__ void group_sync() {
+    if (NT == 64)
+        wave_sync();
+    else
+        __syncthreads();
+}
+
+struct LdsGrid {
+    float* U;
+    float* F;
+    int n, m, M, h;    // interior size, row pitch, cells of one colour per row
+    uint32_t mg_m, mg_h;
+    float ey, ex;
+};
+
+__device__ __forceinline__ LdsGrid lds_grid(const LdsPlan& P, float* lds, int l) {
+    LdsGrid g;
+    g.n = P.n[l];
+    g.m = P.m[l];
+    g.M = g.m + 2;
+    g.h = (g.m + 1) >> 1;
+    g.U = lds + P.off[l];
+    g.F = g.U + (g.n + 2) * g.M;
+    g.mg_m = P.mg_m[l];
+    g.mg_h = P.mg_h[l];
+    g.ey = P.ey[l];
+    g.ex = P.ex[l];
+    return g;
+}
+
+// Slot q of colour c: row 1 + q / h, the (q % h)-th point of that colour in
+// the row (red: i + j even).  Slots past the grid read cell (1, 1) and store
+// to the thread's trash cell, so that no load or store is conditional and a
+// thread issues the loads of all its slots before it waits for them.
+struct Slot {
+    int r;      // LDS offset read
+    float* w;   // LDS address written
+    float rd;   // 1 / diagonal
+};
+
+__device__ __forceinline__ Slot colour_slot(const LdsGrid& g, int c, int q, float* trash) {
+    const int r = udiv(q, g.h, g.mg_h);
+    const int i = 1 + r, j = 1 + ((c + i + 1) & 1) + 2 * (q - r * g.h);
+    float d = 4.f;
+    if (i == g.n) d += g.ey;
+    if (j == g.m) d += g.ex;
+    const bool ok = i <= g.n && j <= g.m;
+    Slot s;
+    s.r = ok ? i * g.M + j : g.M + 1;
+    s.w = ok ? g.U + s.r : trash;
+    s.rd = 1.f / d;
+    return s;
+}
+
+// Red-black Gauss-Seidel (SOR = false) or SOR with omega, sweeps x (colour
+// c0, then the other).  Points of one colour read only the other colour.
+// The first NT * KPT slots of each colour are held in registers; slots beyond
+// (only a large coarsest grid has them) are walked one at a time.
+template <int NT, int KPT, bool SOR>
+__device__ void lds_smooth_k(const LdsGrid& g, int c0, int sweeps, float omega, int t,
+                             float* trash) {
+    Slot sl[2][KPT];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int k = 0; k < KPT; ++k) sl[c][k] = colour_slot(g, c, t + NT * k, trash);
+    const int slots = g.n * g.h, M = g.M;
+    const float* U = g.U;
+    const float* F = g.F;
+    auto value = [&](int q, float rd) -> float {
+        const float x = ((U[q - M] + U[q + M]) + (U[q - 1] + U[q + 1])) - F[q];
+        const float gs = x * rd;
+        return SOR ? U[q] + omega * (gs - U[q]) : gs;
+    };
+    auto half = [&](const Slot* sc, int c) {
+        float v[KPT];
+#pragma unroll
+        for (int k = 0; k < KPT; ++k) v[k] = value(sc[k].r, sc[k].rd);
+#pragma unroll
+        for (int k = 0; k < KPT; ++k) *sc[k].w = v[k];
+        for (int q = t + NT * KPT; q < slots; q += NT) {
+            const Slot s = colour_slot(g, c, q, trash);
+            *s.w = value(s.r, s.rd);
+        }
+        group_sync<NT>();
+    };
     for (int s = 0; s < sweeps; ++s) {
-        for (int h = 0; h < 2; ++h) {
-            const int color = color0 ^ h;
-            if (rm.active) {
-                for (int i = 1 + rm.r0; i <= n; i += rm.rpp) {
-                    const float drow = 4.f + (i == n ? ey : 0.f);
-                    for (int j = 1 + ((color + i + 1) & 1) + 2 * rm.sg; j <= m; j += 2 * rm.tpr) {
-                        const int o = i * M + j;
-                        const float gs = gs_value(U[o - M], U[o + M], U[o - 1], U[o + 1], F[o],
-                                                  j == m ? drow + ex : drow);
-                        U[o] = omega == 1.f ? gs : U[o] + omega * (gs - U[o]);
-                    }
-                }
-            }
-            __syncthreads();
+        if (c0 == 0) {
+            half(sl[0], 0);
+            half(sl[1], 1);
+        } else {
+            half(sl[1], 1);
+            half(sl[0], 0);
         }
     }
 }
 
-// R = F - A U on the interior (FP64 registers), 0 on the ring.
-__device__ __forceinline__ void lds_residual(const float* U, const float* F, float* R, int n,
-                                             int m, float ey, float ex) {
-    const int M = m + 2;
-    const RowMap rm(n + 2);
-    if (rm.active) {
-        for (int i = rm.r0; i <= n + 1; i += rm.rpp) {
-            const bool row_in = i >= 1 && i <= n;
-            const float drow = 4.f + (i == n ? ey : 0.f);
-            for (int j = rm.sg; j <= m + 1; j += rm.tpr) {
-                const int o = i * M + j;
-                float r = 0.f;
-                if (row_in && j >= 1 && j <= m)
-                    r = (float)res_value(U[o - M], U[o + M], U[o - 1], U[o + 1], U[o], F[o],
-                                         j == m ? drow + ex : drow);
-                R[o] = r;
-            }
-        }
+template <int NT>
+__device__ void lds_smooth(const LdsGrid& g, int c0, int sweeps, float omega, int t,
+                           float* trash) {
+    const int per = (g.n * g.h + NT - 1) / NT;  // slots of a colour per thread
+    if (omega != 1.f) {
+        if (NT == 64 && per > 2)
+            lds_smooth_k<NT, 4, true>(g, c0, sweeps, omega, t, trash);
+        else if (per > 1)
+            lds_smooth_k<NT, 2, true>(g, c0, sweeps, omega, t, trash);
+        else
+            lds_smooth_k<NT, 1, true>(g, c0, sweeps, omega, t, trash);
+    } else {
+        if (NT == 64 && per > 2)
+            lds_smooth_k<NT, 4, false>(g, c0, sweeps, omega, t, trash);
+        else if (per > 1)
+            lds_smooth_k<NT, 2, false>(g, c0, sweeps, omega, t, trash);
+        else
+            lds_smooth_k<NT, 1, false>(g, c0, sweeps, omega, t, trash);
     }
-    __syncthreads();
+}
+
+// Interior point q of grid g (row-major over the n x m interior), clamped to
+// the last point past the end.
+__device__ __forceinline__ void interior_point(const LdsGrid& g, int q, int& i, int& j) {
+    const int r = udiv(q, g.m, g.mg_m);
+    i = 1 + r;
+    j = 1 + q - r * g.m;
+}
+
+// R = F - A U on the interior (evaluated in FP64, stored FP32); the ring of R
+// stays zero from the kernel's entry.  B points per thread and pass.
+template <int NT, int B>
+__device__ void lds_residual(const LdsGrid& g, float* R, int t, float* trash) {
+    const int cells = g.n * g.m, M = g.M;
+    const float* U = g.U;
+    for (int q0 = 0; q0 < cells; q0 += B * NT) {
+        float v[B];
+        float* dst[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int q = q0 + t + b * NT;
+            int i, j;
+            interior_point(g, q < cells ? q : cells - 1, i, j);
+            const int o = i * M + j;
+            float d = 4.f;
+            if (i == g.n) d += g.ey;
+            if (j == g.m) d += g.ex;
+            v[b] = (float)res_value(U[o - M], U[o + M], U[o - 1], U[o + 1], U[o], g.F[o], d);
+            dst[b] = q < cells ? R + o : trash;
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) *dst[b] = v[b];
+    }
+    group_sync<NT>();
+}
+
+// Full-weighting restriction of R (grid g) to the right-hand side of grid cg
+// (times 4: the unit-spacing scaling of the coarse operator).
+template <int NT, int B>
+__device__ void lds_restrict(const LdsGrid& g, const float* R, const LdsGrid& cg, int t,
+                             float* trash) {
+    const int cells = cg.n * cg.m, M = g.M;
+    for (int q0 = 0; q0 < cells; q0 += B * NT) {
+        float v[B];
+        float* dst[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int q = q0 + t + b * NT;
+            int I, J;
+            interior_point(cg, q < cells ? q : cells - 1, I, J);
+            const int o = 2 * I * M + 2 * J;
+            v[b] = 0.25f * (4.f * R[o] + 2.f * (R[o - 1] + R[o + 1] + R[o - M] + R[o + M]) +
+                            (R[o - M - 1] + R[o - M + 1] + R[o + M - 1] + R[o + M + 1]));
+            dst[b] = q < cells ? cg.F + I * cg.M + J : trash;
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) *dst[b] = v[b];
+    }
+    group_sync<NT>();
+}
+
+// Bilinear prolongation of the coarse correction onto the interior of g;
+// wy / wx weight fine points between the last coarse point and the boundary.
+template <int NT, int B>
+__device__ void lds_prolong(const LdsGrid& g, const LdsGrid& cg, float wy, float wx, int t,
+                            float* trash) {
+    const int cells = g.n * g.m, Mc = cg.M;
+    const float* Uc = cg.U;
+    for (int q0 = 0; q0 < cells; q0 += B * NT) {
+        float v[B];
+        float* dst[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int q = q0 + t + b * NT;
+            int i, j;
+            interior_point(g, q < cells ? q : cells - 1, i, j);
+            const int o = i * g.M + j;
+            const bool oi = i & 1, oj = j & 1;
+            const int I0 = i >> 1, J0 = j >> 1;
+            const float fy = oi ? (I0 == cg.n ? wy : 0.5f) : 1.f;
+            const float fx = oj ? (J0 == cg.m ? wx : 0.5f) : 1.f;
+            const float* p = Uc + I0 * Mc + J0;  // rows I0 + 1 <= nc + 1: in the grid
+            float w = p[0];
+            const float a = p[Mc], c = p[1], e = p[Mc + 1];
+            if (oi) w += a;
+            if (oj) w += c;
+            if (oi && oj) w += e;
+            v[b] = g.U[o] + fy * fx * w;
+            dst[b] = q < cells ? g.U + o : trash;
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) *dst[b] = v[b];
+    }
+    group_sync<NT>();
+}
+
+// Levels lw .. L-1 of the V-cycle below a grid already restricted, run by
+// wave 0 alone: these grids hold at most 64 x 4 points of a colour.
+__device__ void lds_wave_tail(const LdsPlan& P, float* lds, int lane, float* trash) {
+    const int L = P.L;
+    for (int l = P.lw; l < L - 1; ++l) {
+        const LdsGrid g = lds_grid(P, lds, l);
+        lds_smooth<64>(g, 0, P.pre, 1.f, lane, trash);
+        lds_residual<64, 8>(g, lds + P.roff[l], lane, trash);
+        lds_restrict<64, 4>(g, lds + P.roff[l], lds_grid(P, lds, l + 1), lane, trash);
+    }
+    lds_smooth<64>(lds_grid(P, lds, L - 1), 0, P.csweeps, P.omega, lane, trash);
+    for (int l = L - 2; l >= P.lw; --l) {
+        const LdsGrid g = lds_grid(P, lds, l);
+        lds_prolong<64, 8>(g, lds_grid(P, lds, l + 1), P.wy[l + 1], P.wx[l + 1], lane, trash);
+        lds_smooth<64>(g, 1, P.post, 1.f, lane, trash);
+    }
 }
 
 __global__ __launch_bounds__(kLdsThreads) void k_mg_lds(LdsPlan P, const int* __restrict__ done,
@@ -600,9 +807,9 @@ __global__ __launch_bounds__(kLdsThreads) void k_mg_lds(LdsPlan P, const int* __
     __shared__ double sh[3 * (kLdsThreads / 64)];
     const int c = c0 + blockIdx.x;
     if (done[c]) return;
-    const int lc = P.lc, L = P.L;
-    float* R = lds + P.scratch;
-    // load the top level
+    const int lc = P.lc, L = P.L, t = threadIdx.x;
+    // load the top level; clear the coarser grids and the residuals (their
+    // rings stay zero for the whole cycle)
     {
         const int n = P.n[lc], m = P.m[lc], M = m + 2;
         float* U = lds + P.off[lc];
@@ -619,66 +826,28 @@ __global__ __launch_bounds__(kLdsThreads) void k_mg_lds(LdsPlan P, const int* __
                 }
             }
         }
+        for (int i = P.zero0 + t; i < P.zero1; i += kLdsThreads) lds[i] = 0.f;
         __syncthreads();
     }
-    for (int l = lc; l < L - 1; ++l) {
-        const int n = P.n[l], m = P.m[l], M = m + 2;
-        float* U = lds + P.off[l];
-        float* F = U + (n + 2) * M;
-        const float ey = P.ey[l], ex = P.ex[l];
-        lds_gs(U, F, n, m, ey, ex, 0, P.pre, 1.f);
-        lds_residual(U, F, R, n, m, ey, ex);
-        const int nc = P.n[l + 1], mc = P.m[l + 1], Mc = mc + 2;
-        float* Uc = lds + P.off[l + 1];
-        float* Fc = Uc + (nc + 2) * Mc;
-        const RowMap rm(nc + 2);
-        if (rm.active) {
-            for (int I = rm.r0; I <= nc + 1; I += rm.rpp) {
-                for (int J = rm.sg; J <= mc + 1; J += rm.tpr) {
-                    float v = 0.f;
-                    if (I >= 1 && I <= nc && J >= 1 && J <= mc) {
-                        const int o = 2 * I * M + 2 * J;
-                        v = 0.25f * (4.f * R[o] + 2.f * (R[o - 1] + R[o + 1] + R[o - M] + R[o + M]) +
-                                     (R[o - M - 1] + R[o - M + 1] + R[o + M - 1] + R[o + M + 1]));
-                    }
-                    Uc[I * Mc + J] = 0.f;
-                    Fc[I * Mc + J] = v;
-                }
-            }
-        }
-        __syncthreads();
+    float* trash = lds + P.trash + (t & 63);
+    const int lb = P.lw < L - 1 ? P.lw : L - 1;  // first level below the workgroup's levels
+    for (int l = lc; l < lb; ++l) {
+        const LdsGrid g = lds_grid(P, lds, l);
+        lds_smooth<kLdsThreads>(g, 0, P.pre, 1.f, t, trash);
+        lds_residual<kLdsThreads, 2>(g, lds + P.roff[l], t, trash);
+        lds_restrict<kLdsThreads, 1>(g, lds + P.roff[l], lds_grid(P, lds, l + 1), t, trash);
     }
-    {
-        const int n = P.n[L - 1], m = P.m[L - 1];
-        float* U = lds + P.off[L - 1];
-        float* F = U + (n + 2) * (m + 2);
-        lds_gs(U, F, n, m, P.ey[L - 1], P.ex[L - 1], 0, P.csweeps, P.omega);
-    }
-    for (int l = L - 2; l >= lc; --l) {
-        const int n = P.n[l], m = P.m[l], M = m + 2;
-        float* U = lds + P.off[l];
-        float* F = U + (n + 2) * M;
-        const int Mc = P.m[l + 1] + 2, nc = P.n[l + 1], mc = P.m[l + 1];
-        const float* Uc = lds + P.off[l + 1];
-        const RowMap rm(n);
-        if (rm.active) {
-            for (int i = 1 + rm.r0; i <= n; i += rm.rpp) {
-                const int oi = i & 1, I0 = i >> 1;
-                const float fy = oi ? (I0 == nc ? P.wy[l + 1] : 0.5f) : 1.f;
-                for (int j = 1 + rm.sg; j <= m; j += rm.tpr) {
-                    const int oj = j & 1, J0 = j >> 1;
-                    const float* p = Uc + I0 * Mc + J0;
-                    float v = p[0];
-                    if (oi) v += p[Mc];
-                    if (oj) v += p[1];
-                    if (oi & oj) v += p[Mc + 1];
-                    const float fx = oj ? (J0 == mc ? P.wx[l + 1] : 0.5f) : 1.f;
-                    U[i * M + j] += fy * fx * v;
-                }
-            }
-        }
+    if (P.lw < L) {
+        if (t < 64) lds_wave_tail(P, lds, t, trash);
         __syncthreads();
-        lds_gs(U, F, n, m, P.ey[l], P.ex[l], 1, P.post, 1.f);
+    } else {
+        lds_smooth<kLdsThreads>(lds_grid(P, lds, L - 1), 0, P.csweeps, P.omega, t, trash);
+    }
+    for (int l = lb - 1; l >= lc; --l) {
+        const LdsGrid g = lds_grid(P, lds, l);
+        lds_prolong<kLdsThreads, 2>(g, lds_grid(P, lds, l + 1), P.wy[l + 1], P.wx[l + 1], t,
+                                    trash);
+        lds_smooth<kLdsThreads>(g, 1, P.post, 1.f, t, trash);
     }
     // write back the top level (its ring too: zero for coarse grids, the
     // unchanged Dirichlet data for the finest)
@@ -913,22 +1082,22 @@ gdgs_status mg_plan(int W, int H, const gdgs_mg_params* mg, MgPlan* plan) {
     }
     p.levels = L;
     // coarse grids that fit in one workgroup's LDS: u and f of every grid
-    // from lc down, plus a residual scratch as large as grid lc (for L > 1)
+    // from lc down, plus the residual of every grid but the coarsest
     const size_t budget = (size_t)lds_budget();
     size_t bytes = 0;
     int lc = L;
     while (lc > 0) {
         const size_t cells = (size_t)(p.n[lc - 1] + 2) * (p.m[lc - 1] + 2);
-        const size_t scratch = (lc - 1 < L - 1) ? sizeof(float) * cells : 0;
-        if (bytes + 2 * sizeof(float) * cells + scratch > budget) break;
+        const size_t add = sizeof(float) * cells * (lc - 1 < L - 1 ? 3 : 2);
+        if (bytes + add > budget) break;
         // a larger top grid would leave the chip idle while one workgroup per
         // channel smooths it; the tiled kernels take it instead
         if (lc - 1 < L - 1 && cells > (size_t)kLdsTopCells) break;
-        bytes += 2 * sizeof(float) * cells;
+        bytes += add;
         --lc;
     }
-    if (lc < L - 1) bytes += sizeof(float) * (size_t)(p.n[lc] + 2) * (p.m[lc] + 2);
-    if (lc == L) {
+    bytes += 64 * sizeof(float);  // trash cells
+    if (lc == L || bytes > budget) {
         set_error("coarsest grid %dx%d does not fit in LDS; use more multigrid levels",
                   p.n[L - 1], p.m[L - 1]);
         return GDGS_ERR_UNSUPPORTED;
@@ -963,6 +1132,46 @@ gdgs_status mg_plan(int W, int H, const gdgs_mg_params* mg, MgPlan* plan) {
 }
 
 namespace {
+uint32_t div_magic(int d) { return d >= 2 ? (uint32_t)((1ull << 32) / (uint64_t)d + 1) : 0u; }
+
+// LDS layout of the coarse V-cycle: u_l, f_l for l = lc .. L-1, then the
+// residuals of lc .. L-2, then 64 trash cells; levels whose colour classes
+// fit 4 points per lane of one wave are run by wave 0 alone.
+LdsPlan lds_plan(const MgPlan& p, const LevelDev* lev) {
+    LdsPlan lp{};
+    lp.lc = p.lc;
+    lp.L = p.levels;
+    int off = 0;
+    for (int l = 0; l < p.levels; ++l) {
+        lp.n[l] = p.n[l];
+        lp.m[l] = p.m[l];
+        lp.ey[l] = lev[l].ey;
+        lp.ex[l] = lev[l].ex;
+        lp.wy[l] = lev[l].wy;
+        lp.wx[l] = lev[l].wx;
+        lp.mg_m[l] = div_magic(p.m[l]);
+        lp.mg_h[l] = div_magic((p.m[l] + 1) / 2);
+        if (l >= p.lc) {
+            lp.off[l] = off;
+            off += 2 * (p.n[l] + 2) * (p.m[l] + 2);
+        }
+    }
+    lp.zero0 = p.lc + 1 < p.levels ? lp.off[p.lc + 1] : off;
+    for (int l = p.lc; l < p.levels - 1; ++l) {
+        lp.roff[l] = off;
+        off += (p.n[l] + 2) * (p.m[l] + 2);
+    }
+    if (p.lc == p.levels - 1) lp.zero0 = off;
+    lp.zero1 = off;
+    lp.trash = off;
+    lp.lw = p.levels;
+    for (int l = p.levels - 1; l > p.lc; --l) {
+        if (p.n[l] * ((p.m[l] + 1) / 2) > 64 * 4) break;
+        lp.lw = l;
+    }
+    return lp;
+}
+
 struct PoissonWs {
     float* f0;
     float* u0b;  // second buffer of the finest grid
@@ -1061,24 +1270,7 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
         return GDGS_OK;
     };
 
-    LdsPlan lp;
-    lp.lc = p.lc;
-    lp.L = p.levels;
-    int off = 0;
-    for (int l = 0; l < p.levels; ++l) {
-        lp.n[l] = p.n[l];
-        lp.m[l] = p.m[l];
-        lp.ey[l] = lev[l].ey;
-        lp.ex[l] = lev[l].ex;
-        lp.wy[l] = lev[l].wy;
-        lp.wx[l] = lev[l].wx;
-        lp.off[l] = 0;
-        if (l >= p.lc) {
-            lp.off[l] = off;
-            off += 2 * (p.n[l] + 2) * (p.m[l] + 2);
-        }
-    }
-    lp.scratch = off;
+    LdsPlan lp = lds_plan(p, lev);
     lp.pre = p.pre;
     lp.post = p.post;
     lp.csweeps = p.coarse_sweeps;

@@ -135,7 +135,8 @@ __device__ __forceinline__ void blend(const float4& q0, const float4& q1, const 
 template <bool COUNT>
 __global__ __launch_bounds__(256) void k_raster_fwd(const float4* __restrict__ rec,
                                                     const uint32_t* __restrict__ splat_of_pair,
-                                                    const uint32_t* __restrict__ ranges, int T,
+                                                    const uint32_t* __restrict__ ranges,
+                                                    const uint32_t* __restrict__ tile_order, int T,
                                                     int nx, int W, int H, int64_t K,
                                                     float* __restrict__ grad,
                                                     unsigned long long* __restrict__ counts) {
@@ -144,9 +145,11 @@ __global__ __launch_bounds__(256) void k_raster_fwd(const float4* __restrict__ r
     __shared__ float4 s_r0[kBatch + 1], s_r1[kBatch + 1], s_r2[kBatch + 1], s_r3[kBatch + 1];
     __shared__ uint32_t s_mask[kBatch];
     __shared__ int s_list[4][kBatch + 4];
-    // natural order: tile costs are uneven, and round-robin dispatch over the
-    // XCDs balances them better than giving each XCD one band of the image
-    const int tile = blockIdx.x;
+    // blocks take the tiles heaviest first (or by id): round-robin dispatch
+    // over the XCDs balances the uneven tile costs better than giving each
+    // XCD one band of the image
+    const uint32_t tile = tile_order ? tile_order[blockIdx.x] : blockIdx.x;
+    if (tile >= (uint32_t)T) return;
     const int tx = tile % nx, ty = tile / nx;
     const int t = threadIdx.x, lane = __lane_id(), wv = t >> 6;
     const int px = tx * kTile + (t & 15), py = ty * kTile + (t >> 4);
@@ -237,7 +240,8 @@ constexpr int kBatchB = 128;
 
 __global__ __launch_bounds__(256) void k_raster_bwd(const float4* __restrict__ rec,
                                                     const uint32_t* __restrict__ splat_of_pair,
-                                                    const uint32_t* __restrict__ ranges, int T,
+                                                    const uint32_t* __restrict__ ranges,
+                                                    const uint32_t* __restrict__ tile_order, int T,
                                                     int nx, int W, int H, int64_t K,
                                                     const float* __restrict__ grad,
                                                     const float* __restrict__ dgrad,
@@ -245,7 +249,8 @@ __global__ __launch_bounds__(256) void k_raster_bwd(const float4* __restrict__ r
     __shared__ float4 s_r0[kBatchB], s_r1[kBatchB], s_r2[kBatchB], s_r3[kBatchB];
     __shared__ float4 s_q0[kBatchB], s_q1[kBatchB];  // the forward's exponent form
     __shared__ float s_p[4][kNP][kBatchB];
-    const int tile = blockIdx.x;
+    const uint32_t tile = tile_order ? tile_order[blockIdx.x] : blockIdx.x;
+    if (tile >= (uint32_t)T) return;
     const int tx = tile % nx, ty = tile / nx;
     const int t = threadIdx.x, lane = __lane_id(), wv = t >> 6;
     const int px = tx * kTile + (t & 15), py = ty * kTile + (t >> 4);
@@ -430,7 +435,7 @@ gdgs_status launch_raster(const gdgs_proj& proj, const float* opacity, const flo
     const bool timed = timer_events("raster", &ev0, &ev1);
     if (timed) GDGS_HIP_TRY(hipEventRecord(ev0, st));
     hipLaunchKernelGGL(k_raster_fwd<false>, dim3(T), dim3(256), 0, st, rec, bins.splat_of_pair,
-                       bins.ranges, T, nx, W, H, K, grad, nullptr);
+                       bins.ranges, bins.tile_order, T, nx, W, H, K, grad, nullptr);
     if (timed) GDGS_HIP_TRY(hipEventRecord(ev1, st));
     GDGS_LAUNCH_CHECK();
     return GDGS_OK;
@@ -450,7 +455,7 @@ gdgs_status launch_raster_count(const gdgs_proj& proj, const float* opacity, con
                            rec);
     }
     hipLaunchKernelGGL(k_raster_fwd<true>, dim3(T), dim3(256), 0, st, rec, bins.splat_of_pair,
-                       bins.ranges, T, nx, W, H, K, nullptr, counts);
+                       bins.ranges, bins.tile_order, T, nx, W, H, K, nullptr, counts);
     GDGS_LAUNCH_CHECK();
     return GDGS_OK;
 }
@@ -478,7 +483,8 @@ gdgs_status launch_raster_backward(const gdgs_proj& proj, const float* opacity,
     hipLaunchKernelGGL(k_inv_order, dim3(g), dim3(256), 0, st, bins.order, K, inv);
     hipLaunchKernelGGL(k_build_records, dim3(g), dim3(256), 0, st, proj, opacity, value, K, rec);
     hipLaunchKernelGGL(k_raster_bwd, dim3(T), dim3(256), 0, st, rec, bins.splat_of_pair,
-                       bins.ranges, T, nx, W, H, K, grad, dgrad, part, bins.capacity);
+                       bins.ranges, bins.tile_order, T, nx, W, H, K, grad, dgrad, part,
+                       bins.capacity);
     hipLaunchKernelGGL(k_seg_reduce, dim3(g), dim3(256), 0, st, proj, inv, bins.splat_of_pair,
                        bins.ranges, T, nx, K, part, dmean2d, dconic, dopacity, dvalue);
     GDGS_LAUNCH_CHECK();

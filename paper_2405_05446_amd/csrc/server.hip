@@ -181,7 +181,7 @@ struct gdgs_server {
             bnd = L.boundary;
         }
         BinWs b;
-        bin_ws_layout(K, r->cap, L.rw.bin_ws, &b);
+        bin_ws_layout(K, r->cap, num_tiles(W, H), L.rw.bin_ws, &b);
         const gdgs_scene sc = scene;
         const int64_t cap = r->cap;
         KeyBuilder kb;

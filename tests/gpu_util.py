@@ -44,6 +44,7 @@ def gpu_stages(scene: wl.Scene, cam: wl.Camera, capacity: int | None = None):
         num_pairs=P, tiles=u32(bins["tile_of_pair"])[:n].astype(np.int64),
         splats=u32(bins["splat_of_pair"])[:n].astype(np.int64),
         order=u32(bins["order"])[:K].astype(np.int64), ranges=u32(bins["ranges"]),
+        tile_order=u32(bins["tile_order"]).astype(np.int64),
         grad=np_(grad).astype(np.float64))
     out["mean2d"] = np.stack([out["mean2d_rel"][0] + 16 * out["tx0"],
                               out["mean2d_rel"][1] + 16 * out["ty0"]])

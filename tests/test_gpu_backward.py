@@ -73,6 +73,12 @@ def test_raster_backward_alone_matches_oracle():
                                      dev(ref["dgrad"]))
     for name in g:
         assert torch.equal(g[name], g2[name])
+    # tiles taken by id instead of heaviest first: the same bits
+    b_id = dict(bins, tile_order=None)
+    g3 = G.gdgs_raster_grad_backward(proj, t["opacity"], t["value"], K, b_id, W, H, grad,
+                                     dev(ref["dgrad"]))
+    for name in g:
+        assert torch.equal(g[name], g3[name])
 
 
 def test_adjoint_identity_at_differentiation_workload_size():

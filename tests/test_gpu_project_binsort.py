@@ -77,6 +77,10 @@ def test_bin_sort_is_bit_exact(name, cfg):
     assert np.array_equal(g["ranges"][0][nonempty], start[nonempty])
     assert np.array_equal(g["ranges"][1][nonempty], end[nonempty])
     assert np.all(g["ranges"][1][~nonempty] == g["ranges"][0][~nonempty])
+    # heaviest-first schedule: tile ids stably sorted by 32 - bitlen(pairs)
+    n = (end - start).astype(np.int64)
+    bitlen = np.where(n > 0, np.floor(np.log2(np.maximum(n, 1))).astype(np.int64) + 1, 0)
+    assert np.array_equal(g["tile_order"], np.lexsort((np.arange(T), 32 - bitlen)))
 
 
 def test_bin_sort_matches_oracle_pairs():

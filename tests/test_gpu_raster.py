@@ -32,6 +32,23 @@ def test_raster_full_image_matches_oracle(K, W, H, ls, pose):
     assert err <= TOL
 
 
+def test_tile_order_changes_no_bit():
+    """The heaviest-first tile schedule only reorders independent blocks."""
+    sc = wl.make_scene(20000, seed=4, z=(2, 20), ls=(-4, 0.7))
+    W, H = 333, 190
+    cam = wl.make_camera(W, H, pose_index=7)
+    ds = G.DeviceScene.from_host(sc)
+    proj = G.gdgs_project(ds, cam)
+    bins = G.gdgs_bin_sort(proj, sc.K, W, H, 1 << 20)
+    a = G.gdgs_raster_grad(proj, ds.opacity, ds.value, sc.K, bins, W, H)
+    b = G.gdgs_raster_grad(proj, ds.opacity, ds.value, sc.K, dict(bins, tile_order=None), W, H)
+    torch.cuda.synchronize()
+    order = np_(bins["tile_order"]).view(np.uint32)
+    assert np.array_equal(np.sort(order), np.arange(order.size))
+    assert not np.array_equal(order, np.arange(order.size))
+    assert torch.equal(a, b)
+
+
 def test_raster_sampled_pixels_mid_workload():
     cfg = wl.CONFIGS["mid"]
     say("[raster] mid workload, sampled pixels")
