@@ -252,13 +252,18 @@ __global__ void k_resume(int* __restrict__ counters) {
 // ---------------------------------------------------------------- smoothing
 // Red-black Gauss-Seidel half-sweeps on an LDS region RX x RY whose cell (0,0)
 // is grid point (gi0, gj0); only interior grid points (1..n, 1..m) change.
-// Thread t owns LDS row 1 + t / TPR and every TPR-th cell of one colour in it.
+// Thread t owns LDS row 1 + t / TPR and every TPR-th point of one colour in
+// it, KR points per colour.  A half-sweep loads the neighbours of all of a
+// thread's points before it stores any (points of one colour read only the
+// other colour); a slot off the row reads cell (1, 1) and stores to the
+// thread's trash cell, so no access is conditional.
 template <int RX, int RY, int NT>
 __device__ __forceinline__ void smooth_rows(float* __restrict__ su, const float* __restrict__ sf,
-                                            int gi0, int gj0, int n, int m, float ey, float ex,
-                                            int color0, int sweeps) {
+                                            float* trash, int gi0, int gj0, int n, int m,
+                                            float ey, float ex, int color0, int sweeps) {
     constexpr int NR = RY - 2;
     constexpr int TPR = NT / NR;
+    constexpr int KR = ((RX - 1) / 2 + TPR - 1) / TPR;
     const int t = threadIdx.x;
     const int r = 1 + t / TPR, sgm = t % TPR;
     const int gi = gi0 + r;
@@ -266,54 +271,79 @@ __device__ __forceinline__ void smooth_rows(float* __restrict__ su, const float*
     const int qlo = max(1, 1 - gj0), qhi = min(RX - 2, m - gj0);
     const int qm = m - gj0;  // local column of the last interior column
     const float drow = 4.f + (gi == n ? ey : 0.f);
+    int ro[2][KR];
+    float* wo[2][KR];
+    float rd[2][KR];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int q0 = qlo + ((c + gi + gj0 + qlo) & 1) + 2 * sgm;
+#pragma unroll
+        for (int k = 0; k < KR; ++k) {
+            const int q = q0 + 2 * TPR * k;
+            const bool ok = row_ok && q <= qhi;
+            ro[c][k] = ok ? r * RX + q : RX + 1;
+            wo[c][k] = ok ? su + r * RX + q : trash;
+            rd[c][k] = 1.f / (q == qm ? drow + ex : drow);
+        }
+    }
+    auto half = [&](const int* o, float* const* w, const float* d) {
+        float v[KR];
+#pragma unroll
+        for (int k = 0; k < KR; ++k) {
+            const int q = o[k];
+            v[k] = (((su[q - RX] + su[q + RX]) + (su[q - 1] + su[q + 1])) - sf[q]) * d[k];
+        }
+#pragma unroll
+        for (int k = 0; k < KR; ++k) *w[k] = v[k];
+        __syncthreads();
+    };
     for (int s = 0; s < sweeps; ++s) {
-        for (int h = 0; h < 2; ++h) {
-            if (row_ok) {
-                const int color = color0 ^ h;
-                int q = qlo + ((color + gi + gj0 + qlo) & 1) + 2 * sgm;
-                float* row = su + r * RX;
-                const float* frow = sf + r * RX;
-                for (; q <= qhi; q += 2 * TPR) {
-                    const float d = q == qm ? drow + ex : drow;
-                    row[q] = gs_value(row[q - RX], row[q + RX], row[q - 1], row[q + 1], frow[q], d);
-                }
-            }
-            __syncthreads();
+        if (color0 == 0) {
+            half(ro[0], wo[0], rd[0]);
+            half(ro[1], wo[1], rd[1]);
+        } else {
+            half(ro[1], wo[1], rd[1]);
+            half(ro[0], wo[0], rd[0]);
         }
     }
 }
 
-// All of a thread's global loads are issued before the first LDS store (a
-// fixed trip count lets the compiler keep them in flight together instead of
-// waiting for each iteration's loads in turn).
+// A thread's share of an RY x RX region of a grid (cell (0,0) = grid point
+// (gi0, gj0)), held in registers: every global load is issued before the
+// first one is waited for, then stored to LDS (zero outside the grid).
 template <int RX, int RY, int NT>
-__device__ __forceinline__ void load_region(float* su, float* sf, const LevelDev& L,
-                                            const float* usrc, int c, int gi0, int gj0,
-                                            bool zero_guess) {
-    constexpr int NI = (RY * RX + NT - 1) / NT;
-    const int N = L.n + 2, M = L.m + 2;
-    const float* u = usrc + (size_t)c * L.cs;
-    const float* f = L.f + (size_t)c * L.cs;
-    float vu[NI], vf[NI];
+struct RegionRegs {
+    static constexpr int NI = (RY * RX + NT - 1) / NT;
+    float a[NI], b[NI];
+    // a <- x, b <- y (y may be null: b unused)
+    __device__ __forceinline__ void load(const LevelDev& L, const float* x, const float* y, int c,
+                                         int gi0, int gj0) {
+        const int N = L.n + 2, M = L.m + 2;
+        const float* xc = x ? x + (size_t)c * L.cs : nullptr;
+        const float* yc = y ? y + (size_t)c * L.cs : nullptr;
 #pragma unroll
-    for (int k = 0; k < NI; ++k) {
-        const int idx = threadIdx.x + k * NT;
-        const int r = idx / RX, q = idx - r * RX;
-        const int gi = gi0 + r, gj = gj0 + q;
-        const bool in = idx < RY * RX && (unsigned)gi < (unsigned)N && (unsigned)gj < (unsigned)M;
-        const size_t o = (size_t)gi * L.pitch + gj;
-        vu[k] = (in && !zero_guess) ? u[o] : 0.f;
-        vf[k] = in ? f[o] : 0.f;
-    }
-#pragma unroll
-    for (int k = 0; k < NI; ++k) {
-        const int idx = threadIdx.x + k * NT;
-        if (idx < RY * RX) {
-            su[idx] = vu[k];
-            sf[idx] = vf[k];
+        for (int k = 0; k < NI; ++k) {
+            const int idx = threadIdx.x + k * NT;
+            const int r = idx / RX, q = idx - r * RX;
+            const int gi = gi0 + r, gj = gj0 + q;
+            const bool in =
+                idx < RY * RX && (unsigned)gi < (unsigned)N && (unsigned)gj < (unsigned)M;
+            const size_t o = (size_t)gi * L.pitch + gj;
+            a[k] = (in && xc) ? xc[o] : 0.f;
+            b[k] = (in && yc) ? yc[o] : 0.f;
         }
     }
-}
+    __device__ __forceinline__ void store(float* sa, float* sb) const {
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            const int idx = threadIdx.x + k * NT;
+            if (idx < RY * RX) {
+                sa[idx] = a[k];
+                if (sb) sb[idx] = b[k];
+            }
+        }
+    }
+};
 
 // Logical (tile x, tile y, channel) of this block under the XCD remap; the
 // launch covers channels c0 .. c0 + gridDim.z - 1.
@@ -336,7 +366,9 @@ struct TileId {
 
 // Pre-smoothing + residual + restriction to the next grid.  FINE (the finest
 // grid only): record the largest change of u and evaluate the residual in
-// FP64; coarser grids carry small corrections and stay in FP32.
+// FP64; coarser grids carry small corrections and stay in FP32.  A finished
+// channel returns at once on the finest grid; on coarser grids, whose blocks
+// are few and latency-bound, the done flag is read together with the tile.
 template <int NU, bool FINE, int TX, int TY, int NT>
 __global__ __launch_bounds__(NT) void k_mg_pre(LevelDev L, LevelDev C, int zero_guess,
                                                 const int* __restrict__ done,
@@ -346,12 +378,19 @@ __global__ __launch_bounds__(NT) void k_mg_pre(LevelDev L, LevelDev C, int zero_
     constexpr int RX = TX + 2 * HALO, RY = TY + 2 * HALO;
     __shared__ float su[RY * RX];
     __shared__ float sf[RY * RX];
+    __shared__ float s_trash[NT];
     __shared__ double sh[3 * (NT / 64)];
     const TileId id(c0);
     const int c = id.c;
-    if (done[c]) return;
+    if (FINE && done[c]) return;
+    const int dn = FINE ? 0 : done[c];
     const int gi0 = id.ty * TY - HALO, gj0 = id.tx * TX - HALO;
-    load_region<RX, RY, NT>(su, sf, L, L.u, c, gi0, gj0, zero_guess != 0);
+    {
+        RegionRegs<RX, RY, NT> reg;
+        reg.load(L, zero_guess ? nullptr : L.u, L.f, c, gi0, gj0);
+        if (dn) return;
+        reg.store(su, sf);
+    }
     __syncthreads();
     float before[CPT];
     if (FINE) {
@@ -362,7 +401,8 @@ __global__ __launch_bounds__(NT) void k_mg_pre(LevelDev L, LevelDev C, int zero_
         }
         __syncthreads();  // every snapshot is taken before any cell changes
     }
-    smooth_rows<RX, RY, NT>(su, sf, gi0, gj0, L.n, L.m, L.ey, L.ex, 0, NU);
+    smooth_rows<RX, RY, NT>(su, sf, s_trash + threadIdx.x, gi0, gj0, L.n, L.m, L.ey, L.ex, 0,
+                            NU);
     const int N = L.n + 2, M = L.m + 2;
     float* u = L.ub + (size_t)c * L.cs;
     double dmax = 0.0;
@@ -379,32 +419,38 @@ __global__ __launch_bounds__(NT) void k_mg_pre(LevelDev L, LevelDev C, int zero_
         }
     }
     // residual on rows/cols [HALO-1, HALO+T-1], zero off the interior; thread t
-    // owns every TPR-th cell of one row
+    // owns every TPR-th cell of one row (all loads before the stores: each
+    // cell's residual overwrites only its own f)
     {
         constexpr int ZR = TY + 1, ZC = TX + 1;
         constexpr int TPR = NT / ZR;
+        constexpr int KZ = (ZC + TPR - 1) / TPR;
         const int t = threadIdx.x;
-        if (t < ZR * TPR) {
-            const int r = HALO - 1 + t / TPR;
-            const int gi = gi0 + r;
-            const bool row_in = gi >= 1 && gi <= L.n;
-            const float drow = 4.f + (gi == L.n ? L.ey : 0.f);
-            for (int q = HALO - 1 + t % TPR; q < HALO - 1 + ZC; q += TPR) {
-                const int gj = gj0 + q;
-                const int o = r * RX + q;
-                float rv = 0.f;
-                if (row_in && gj >= 1 && gj <= L.m) {
-                    const float d = gj == L.m ? drow + L.ex : drow;
-                    if (FINE)
-                        rv = (float)res_value(su[o - RX], su[o + RX], su[o - 1], su[o + 1], su[o],
-                                              sf[o], d);
-                    else
-                        rv = sf[o] - (((su[o - RX] + su[o + RX]) + (su[o - 1] + su[o + 1])) -
-                                      d * su[o]);
-                }
-                sf[o] = rv;
-            }
+        const int r = HALO - 1 + t / TPR;
+        const int gi = gi0 + r;
+        const bool row_in = t < ZR * TPR && gi >= 1 && gi <= L.n;
+        const float drow = 4.f + (gi == L.n ? L.ey : 0.f);
+        float rv[KZ];
+        float* dst[KZ];
+#pragma unroll
+        for (int k = 0; k < KZ; ++k) {
+            const int q = HALO - 1 + t % TPR + TPR * k;
+            const int gj = gj0 + q;
+            const bool live = t < ZR * TPR && q < HALO - 1 + ZC;
+            const bool in = live && row_in && gj >= 1 && gj <= L.m;
+            const int o = live ? r * RX + q : RX + 1;
+            const float d = gj == L.m ? drow + L.ex : drow;
+            float v;
+            if (FINE)
+                v = (float)res_value(su[o - RX], su[o + RX], su[o - 1], su[o + 1], su[o], sf[o],
+                                     d);
+            else
+                v = sf[o] - (((su[o - RX] + su[o + RX]) + (su[o - 1] + su[o + 1])) - d * su[o]);
+            rv[k] = in ? v : 0.f;
+            dst[k] = live ? sf + o : s_trash + t;
         }
+#pragma unroll
+        for (int k = 0; k < KZ; ++k) *dst[k] = rv[k];
     }
     __syncthreads();
     const int I0 = id.ty * (TY / 2), J0 = id.tx * (TX / 2);
@@ -429,7 +475,8 @@ __global__ __launch_bounds__(NT) void k_mg_pre(LevelDev L, LevelDev C, int zero_
 }
 
 // Prolongation + correction + post-smoothing.  FINE (the finest grid only):
-// also the residual and correction norms of the cycle.
+// also the residual and correction norms of the cycle.  The done flag is
+// handled as in k_mg_pre.
 template <int NU, bool FINE, int TX, int TY, int NT>
 __global__ __launch_bounds__(NT) void k_mg_post(LevelDev L, LevelDev C,
                                                  const int* __restrict__ done,
@@ -442,15 +489,18 @@ __global__ __launch_bounds__(NT) void k_mg_post(LevelDev L, LevelDev C,
     __shared__ float su[RY * RX];
     __shared__ float sf[RY * RX];
     __shared__ float se[CY * CX];
+    __shared__ float s_trash[NT];
     __shared__ double sh[3 * (NT / 64)];
     const TileId id(c0);
     const int c = id.c;
-    if (done[c]) return;
+    if (FINE && done[c]) return;
+    const int dn = FINE ? 0 : done[c];
     const int gi0 = id.ty * TY - HALO, gj0 = id.tx * TX - HALO;
-    load_region<RX, RY, NT>(su, sf, L, L.ub, c, gi0, gj0, false);
     // coarse rows (gi0 >> 1) .. ((gi0 + RY - 1) >> 1) + 1, columns alike
     const int ci0 = gi0 >> 1, cj0 = gj0 >> 1;
     {
+        RegionRegs<RX, RY, NT> reg;
+        reg.load(L, L.ub, L.f, c, gi0, gj0);
         const float* e = C.u + (size_t)c * C.cs;
         const int NC = C.n + 2, MC = C.m + 2;
         constexpr int NE = (CY * CX + NT - 1) / NT;
@@ -464,6 +514,8 @@ __global__ __launch_bounds__(NT) void k_mg_post(LevelDev L, LevelDev C,
                         ? e[(size_t)I * C.pitch + J]
                         : 0.f;
         }
+        if (dn) return;
+        reg.store(su, sf);
 #pragma unroll
         for (int k = 0; k < NE; ++k) {
             const int idx = threadIdx.x + k * NT;
@@ -480,24 +532,40 @@ __global__ __launch_bounds__(NT) void k_mg_post(LevelDev L, LevelDev C,
         }
         __syncthreads();  // every snapshot is taken before any cell changes
     }
-    for (int idx = threadIdx.x; idx < RY * RX; idx += blockDim.x) {
-        const int r = idx / RX, q = idx - r * RX;
-        const int gi = gi0 + r, gj = gj0 + q;
-        if (gi >= 1 && gi <= L.n && gj >= 1 && gj <= L.m) {
+    // bilinear prolongation of the correction onto the interior points of the
+    // region (all of a thread's loads before its stores: each point changes
+    // only itself)
+    {
+        constexpr int NI = (RY * RX + NT - 1) / NT;
+        float v[NI];
+        float* dst[NI];
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            const int i0 = threadIdx.x + k * NT;
+            const bool live = i0 < RY * RX;
+            const int idx = live ? i0 : 0;
+            const int r = idx / RX, q = idx - r * RX;
+            const int gi = gi0 + r, gj = gj0 + q;
+            const bool in = gi >= 1 && gi <= L.n && gj >= 1 && gj <= L.m;
             const int oi = gi & 1, oj = gj & 1;
             const int I0 = gi >> 1, J0 = gj >> 1;
             const float* p = se + (I0 - ci0) * CX + (J0 - cj0);
-            float v = p[0];
-            if (oi) v += p[CX];
-            if (oj) v += p[1];
-            if (oi & oj) v += p[CX + 1];
+            float w = p[0];
+            const float pa = p[CX], pb = p[1], pc = p[CX + 1];
+            if (oi) w += pa;
+            if (oj) w += pb;
+            if (oi & oj) w += pc;
             const float fy = oi ? (I0 == C.n ? C.wy : 0.5f) : 1.f;
             const float fx = oj ? (J0 == C.m ? C.wx : 0.5f) : 1.f;
-            su[idx] += fy * fx * v;
+            v[k] = su[idx] + fy * fx * w;
+            dst[k] = (live && in) ? su + idx : s_trash + threadIdx.x;
         }
+#pragma unroll
+        for (int k = 0; k < NI; ++k) *dst[k] = v[k];
     }
     __syncthreads();
-    smooth_rows<RX, RY, NT>(su, sf, gi0, gj0, L.n, L.m, L.ey, L.ex, 1, NU);
+    smooth_rows<RX, RY, NT>(su, sf, s_trash + threadIdx.x, gi0, gj0, L.n, L.m, L.ey, L.ex, 1,
+                            NU);
     float* u = L.u + (size_t)c * L.cs;
     const int N = L.n + 2, M = L.m + 2;
     double rmax = 0.0, umax = 0.0, rss = 0.0, dmax = 0.0;
@@ -672,14 +740,14 @@ __device__ void lds_smooth(const LdsGrid& g, int c0, int sweeps, float omega, in
                            float* trash) {
     const int per = (g.n * g.h + NT - 1) / NT;  // slots of a colour per thread
     if (omega != 1.f) {
-        if (NT == 64 && per > 2)
+        if (per > 2)
             lds_smooth_k<NT, 4, true>(g, c0, sweeps, omega, t, trash);
         else if (per > 1)
             lds_smooth_k<NT, 2, true>(g, c0, sweeps, omega, t, trash);
         else
             lds_smooth_k<NT, 1, true>(g, c0, sweeps, omega, t, trash);
     } else {
-        if (NT == 64 && per > 2)
+        if (per > 2)
             lds_smooth_k<NT, 4, false>(g, c0, sweeps, omega, t, trash);
         else if (per > 1)
             lds_smooth_k<NT, 2, false>(g, c0, sweeps, omega, t, trash);
@@ -806,26 +874,42 @@ __global__ __launch_bounds__(kLdsThreads) void k_mg_lds(LdsPlan P, const int* __
     extern __shared__ float lds[];
     __shared__ double sh[3 * (kLdsThreads / 64)];
     const int c = c0 + blockIdx.x;
-    if (done[c]) return;
     const int lc = P.lc, L = P.L, t = threadIdx.x;
-    // load the top level; clear the coarser grids and the residuals (their
-    // rings stay zero for the whole cycle)
+    // load the top level (the done flag is read together with its first
+    // chunk); clear the coarser grids and the residuals (their rings stay zero
+    // for the whole cycle)
     {
+        constexpr int KL = 4;  // points per thread and chunk, loaded before stored
         const int n = P.n[lc], m = P.m[lc], M = m + 2;
+        const int cells = (n + 2) * M;
         float* U = lds + P.off[lc];
-        float* F = U + (n + 2) * M;
+        float* F = U + cells;
         const float* gu = P.top.u + (size_t)c * P.top.cs;
         const float* gf = P.top.f + (size_t)c * P.top.cs;
-        const RowMap rm(n + 2);
-        if (rm.active) {
-            for (int i = rm.r0; i <= n + 1; i += rm.rpp) {
-                for (int j = rm.sg; j <= m + 1; j += rm.tpr) {
-                    const size_t o = (size_t)i * P.top.pitch + j;
-                    U[i * M + j] = (lc == 0) ? gu[o] : 0.f;
-                    F[i * M + j] = (i >= 1 && i <= n && j >= 1 && j <= m) ? gf[o] : 0.f;
-                }
+        const int dn = done[c];
+        for (int q0 = 0; q0 < cells; q0 += KL * kLdsThreads) {
+            float vu[KL], vf[KL];
+            int at[KL];
+#pragma unroll
+            for (int k = 0; k < KL; ++k) {
+                const int q = q0 + t + k * kLdsThreads;
+                const int i = q / M, j = q - i * M;
+                const bool live = q < cells;
+                const bool in = live && i >= 1 && i <= n && j >= 1 && j <= m;
+                const size_t o = (size_t)i * P.top.pitch + j;
+                vu[k] = (lc == 0 && live) ? gu[o] : 0.f;
+                vf[k] = in ? gf[o] : 0.f;
+                at[k] = live ? q : -1;
             }
+            if (dn) return;  // uniform over the block
+#pragma unroll
+            for (int k = 0; k < KL; ++k)
+                if (at[k] >= 0) {
+                    U[at[k]] = vu[k];
+                    F[at[k]] = vf[k];
+                }
         }
+        if (dn) return;
         for (int i = P.zero0 + t; i < P.zero1; i += kLdsThreads) lds[i] = 0.f;
         __syncthreads();
     }
