@@ -145,16 +145,10 @@ __device__ void block_reduce3(double& a, double& b, double& s, double* sh /*[3*n
     __syncthreads();
 }
 
-// Called by thread 0 of each of the three per-channel finalize blocks after it
-// wrote its channel's flag: the last of the three records whether all are done.
-__device__ __forceinline__ void publish_converged(int* counter, const int* done,
-                                                  gdgs_stats* stats) {
-    __threadfence();
-    if (atomicAdd(counter, 1) == 2) {
-        __threadfence();
-        const volatile int* d = done;
-        stats->converged = d[0] && d[1] && d[2];
-    }
+// After the last cycle of a call (on the caller's stream, behind every
+// channel's work): whether all three channels met the tolerance.
+__global__ void k_publish_converged(const int* __restrict__ done, gdgs_stats* __restrict__ stats) {
+    if (threadIdx.x == 0) stats->converged = done[0] && done[1] && done[2];
 }
 
 // ---------------------------------------------------------------- setup
@@ -240,7 +234,6 @@ __global__ __launch_bounds__(256) void k_setup_finalize(const double* __restrict
         stats->rel_res[c] = d ? 0.0 : 1.0;
         stats->delta[c] = d ? 0.0 : 1.0;
         stats->b_norm[c] = sqrt(ss);
-        publish_converged(&counters[0], done, stats);
     }
 }
 
@@ -602,6 +595,258 @@ __global__ __launch_bounds__(NT) void k_mg_post(LevelDev L, LevelDev C,
             p[2] = rss;
             p[4] = dmax;
         }
+    }
+}
+
+// ---------------------------------------------------------------- finest grid in register strips
+// On the finest grid each wave owns a region of kSR rows x kSW columns in
+// registers, two adjacent columns per lane (even column in e, odd column in
+// o); the neighbour columns of the lanes on either side come through DPP lane
+// shifts, so smoothing, residual and restriction use no LDS and no barrier.
+// A wave's output is the region minus a halo of kSH cells (2 x 2 half-sweeps
+// shrink the valid region by 4, the residual and the restriction stencil by
+// one each); the halo cells are loaded and smoothed redundantly.  The region
+// origin is even in both directions, so a lane's even column is coarse
+// column (origin / 2 + lane) and the parity of a row is that of its index.
+constexpr int kSR = 32, kSW = 128, kSH = 6;
+constexpr int kSTX = kSW - 2 * kSH, kSTY = kSR - 2 * kSH;  // output tile 116 x 20
+constexpr int kSWaves = 4;                                  // waves (tiles) per block
+
+int strip_tiles_x(int m) { return (m + 2 + kSTX - 1) / kSTX; }
+int strip_tiles(int n, int m) { return strip_tiles_x(m) * ((n + 2 + kSTY - 1) / kSTY); }
+
+// lane l receives lane l-1's v (lane 0: 0) / lane l+1's v (lane 63: 0)
+__device__ __forceinline__ float from_left(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float from_right(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, true));
+}
+
+struct Strip {
+    int c, tile, gi0, gj0, je, lane;
+    bool ok;
+    __device__ Strip(int c0, int ntiles, int tiles_x) {
+        const int nbx = gridDim.x, nb = nbx * gridDim.y;
+        const int Lb = xcd_remap(blockIdx.x + nbx * blockIdx.y, nb);
+        c = c0 + Lb / nbx;
+        tile = (Lb % nbx) * kSWaves + (threadIdx.x >> 6);
+        ok = tile < ntiles;
+        const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+        gi0 = ty * kSTY - kSH;
+        gj0 = tx * kSTX - kSH;
+        lane = threadIdx.x & 63;
+        je = gj0 + 2 * lane;
+    }
+};
+
+// Rows of x (channel c) into e/o registers; zero outside the array.
+__device__ __forceinline__ void strip_load(const LevelDev& L, const float* x, const Strip& S,
+                                           float (&e)[kSR], float (&o)[kSR]) {
+    const float* xc = x + (size_t)S.c * L.cs;
+    const bool ce = S.je >= 0 && S.je <= L.m + 1, co = S.je + 1 >= 0 && S.je + 1 <= L.m + 1;
+#pragma unroll
+    for (int r = 0; r < kSR; ++r) {
+        const int gi = S.gi0 + r;
+        const bool rok = gi >= 0 && gi <= L.n + 1;
+        const float* row = xc + (size_t)(rok ? gi : 0) * L.pitch;
+        e[r] = (rok && ce) ? row[S.je] : 0.f;
+        o[r] = (rok && co) ? row[S.je + 1] : 0.f;
+    }
+}
+
+// Red-black half-sweep of colour col (0 red: i + j even) on the strip.  In a
+// row exactly one of e, o has the colour; rows 0 and kSR-1 are never updated.
+__device__ __forceinline__ void strip_half(float (&e)[kSR], float (&o)[kSR],
+                                           const float (&fe)[kSR], const float (&fo)[kSR],
+                                           int col, const Strip& S, const LevelDev& L,
+                                           bool ine, bool ino, float rde, float rdo, float rde_n,
+                                           float rdo_n) {
+#pragma unroll
+    for (int r = 1; r < kSR - 1; ++r) {
+        const int gi = S.gi0 + r;
+        const bool rin = gi >= 1 && gi <= L.n;
+        const bool last = gi == L.n;
+        if (((r + col) & 1) == 0) {  // even column has the colour
+            const float x = ((e[r - 1] + e[r + 1]) + (from_left(o[r]) + o[r])) - fe[r];
+            const float v = x * (last ? rde_n : rde);
+            e[r] = (rin && ine) ? v : e[r];
+        } else {
+            const float x = ((o[r - 1] + o[r + 1]) + (e[r] + from_right(e[r]))) - fo[r];
+            const float v = x * (last ? rdo_n : rdo);
+            o[r] = (rin && ino) ? v : o[r];
+        }
+    }
+}
+
+// Finest-grid pre-smoothing + FP64 residual + restriction (see k_mg_pre).
+template <int NU>
+__global__ __launch_bounds__(64 * kSWaves) void k_fine_pre(LevelDev L, LevelDev C,
+                                                            const int* __restrict__ done,
+                                                            double* __restrict__ part, int c0,
+                                                            int ntiles, int tiles_x) {
+    const Strip S(c0, ntiles, tiles_x);
+    if (!S.ok || done[S.c]) return;
+    float e[kSR], o[kSR], fe[kSR], fo[kSR];
+    strip_load(L, L.u, S, e, o);
+    strip_load(L, L.f, S, fe, fo);
+    const int jo = S.je + 1;
+    const bool ine = S.je >= 1 && S.je <= L.m, ino = jo >= 1 && jo <= L.m;
+    const float de = 4.f + (S.je == L.m ? L.ex : 0.f), dn_e = de + L.ey;
+    const float dd = 4.f + (jo == L.m ? L.ex : 0.f), dn_o = dd + L.ey;
+    const float rde = 1.f / de, rdo = 1.f / dd, rde_n = 1.f / dn_e, rdo_n = 1.f / dn_o;
+#pragma unroll
+    for (int s = 0; s < NU; ++s) {
+        strip_half(e, o, fe, fo, 0, S, L, ine, ino, rde, rdo, rde_n, rdo_n);
+        strip_half(e, o, fe, fo, 1, S, L, ine, ino, rde, rdo, rde_n, rdo_n);
+    }
+    // output tile: rows [kSH, kSR - kSH), lanes [kSH/2, 64 - kSH/2)
+    const bool lane_out = S.lane >= kSH / 2 && S.lane < 64 - kSH / 2;
+    const float* u0 = L.u + (size_t)S.c * L.cs;
+    float* ub = L.ub + (size_t)S.c * L.cs;
+    double dmax = 0.0;
+#pragma unroll
+    for (int r = kSH; r < kSR - kSH; ++r) {
+        const int gi = S.gi0 + r;
+        if (!lane_out || gi > L.n + 1) continue;
+        const size_t ro = (size_t)gi * L.pitch;
+        const bool rin = gi >= 1 && gi <= L.n;
+        if (S.je <= L.m + 1) {
+            ub[ro + S.je] = e[r];
+            if (rin && ine) dmax = fmax(dmax, fabs((double)e[r] - (double)u0[ro + S.je]));
+        }
+        if (jo <= L.m + 1) {
+            ub[ro + jo] = o[r];
+            if (rin && ino) dmax = fmax(dmax, fabs((double)o[r] - (double)u0[ro + jo]));
+        }
+    }
+    // residual (FP64 registers, stored FP32 over f) on rows and columns one
+    // beyond the output tile; zero off the interior
+#pragma unroll
+    for (int r = kSH - 1; r <= kSR - kSH; ++r) {
+        const int gi = S.gi0 + r;
+        const bool rin = gi >= 1 && gi <= L.n;
+        const bool last = gi == L.n;
+        const double re = res_value(e[r - 1], e[r + 1], from_left(o[r]), o[r], e[r], fe[r],
+                                    last ? dn_e : de);
+        const double ro_ = res_value(o[r - 1], o[r + 1], e[r], from_right(e[r]), o[r], fo[r],
+                                     last ? dn_o : dd);
+        fe[r] = (rin && ine) ? (float)re : 0.f;
+        fo[r] = (rin && ino) ? (float)ro_ : 0.f;
+    }
+    // full weighting at the even points of the output tile
+    float* fc = C.fw + (size_t)S.c * C.cs;
+    const int J = S.je >> 1;
+#pragma unroll
+    for (int r = kSH; r < kSR - kSH; r += 2) {
+        const int I = (S.gi0 + r) >> 1;
+        const float v = 4.f * fe[r] +
+                        2.f * (from_left(fo[r]) + fo[r] + fe[r - 1] + fe[r + 1]) +
+                        (from_left(fo[r - 1]) + fo[r - 1] + from_left(fo[r + 1]) + fo[r + 1]);
+        if (lane_out && I >= 1 && I <= C.n && J >= 1 && J <= C.m)
+            fc[(size_t)I * C.pitch + J] = 0.25f * v;
+    }
+    dmax = wave_max_d(dmax);
+    if (S.lane == 0) part[((size_t)S.c * ntiles + S.tile) * 5 + 3] = dmax;
+}
+
+// Finest-grid prolongation + correction + post-smoothing + norms (see k_mg_post).
+template <int NU>
+__global__ __launch_bounds__(64 * kSWaves) void k_fine_post(LevelDev L, LevelDev C,
+                                                             const int* __restrict__ done,
+                                                             double* __restrict__ part, int c0,
+                                                             int ntiles, int tiles_x) {
+    constexpr int KC = kSR / 2 + 1;  // coarse rows under the region
+    const Strip S(c0, ntiles, tiles_x);
+    if (!S.ok || done[S.c]) return;
+    float e[kSR], o[kSR], fe[kSR], fo[kSR], E[KC];
+    strip_load(L, L.ub, S, e, o);
+    strip_load(L, L.f, S, fe, fo);
+    const int ci0 = S.gi0 >> 1, J0 = S.je >> 1;
+    {
+        const float* ec = C.u + (size_t)S.c * C.cs;
+        const bool cj = J0 >= 0 && J0 <= C.m + 1;
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            const int I = ci0 + k;
+            E[k] = (cj && I >= 0 && I <= C.n + 1) ? ec[(size_t)I * C.pitch + J0] : 0.f;
+        }
+    }
+    const int jo = S.je + 1;
+    const bool ine = S.je >= 1 && S.je <= L.m, ino = jo >= 1 && jo <= L.m;
+    // bilinear prolongation: e has oj = 0, o has oj = 1 (coarse columns J0, J0 + 1)
+    const float fxo = J0 == C.m ? C.wx : 0.5f;
+#pragma unroll
+    for (int r = 0; r < kSR; ++r) {
+        const int gi = S.gi0 + r;
+        const bool rin = gi >= 1 && gi <= L.n;
+        const int k = r >> 1;
+        const bool oi = r & 1;
+        const float fy = oi ? ((ci0 + k) == C.n ? C.wy : 0.5f) : 1.f;
+        const float p0 = E[k], pa = oi ? E[k + 1] : 0.f;
+        const float q0 = from_right(p0), qa = from_right(pa);
+        float we = p0;
+        if (oi) we += pa;
+        float wo = p0;
+        if (oi) wo += pa;
+        wo += q0;
+        if (oi) wo += qa;
+        if (rin && ine) e[r] += fy * 1.f * we;
+        if (rin && ino) o[r] += fy * fxo * wo;
+    }
+    const float de = 4.f + (S.je == L.m ? L.ex : 0.f), dn_e = de + L.ey;
+    const float dd = 4.f + (jo == L.m ? L.ex : 0.f), dn_o = dd + L.ey;
+    const float rde = 1.f / de, rdo = 1.f / dd, rde_n = 1.f / dn_e, rdo_n = 1.f / dn_o;
+#pragma unroll
+    for (int s = 0; s < NU; ++s) {
+        strip_half(e, o, fe, fo, 1, S, L, ine, ino, rde, rdo, rde_n, rdo_n);
+        strip_half(e, o, fe, fo, 0, S, L, ine, ino, rde, rdo, rde_n, rdo_n);
+    }
+    // store the output tile; norms over its interior points
+    const bool lane_out = S.lane >= kSH / 2 && S.lane < 64 - kSH / 2;
+    const float* ubc = L.ub + (size_t)S.c * L.cs;
+    float* u = L.u + (size_t)S.c * L.cs;
+    double rmax = 0.0, umax = 0.0, rss = 0.0, dmax = 0.0;
+#pragma unroll
+    for (int r = kSH; r < kSR - kSH; ++r) {
+        const int gi = S.gi0 + r;
+        const bool rin = gi >= 1 && gi <= L.n;
+        const bool last = gi == L.n;
+        const double re = res_value(e[r - 1], e[r + 1], from_left(o[r]), o[r], e[r], fe[r],
+                                    last ? dn_e : de);
+        const double ro_ = res_value(o[r - 1], o[r + 1], e[r], from_right(e[r]), o[r], fo[r],
+                                     last ? dn_o : dd);
+        if (!lane_out || gi > L.n + 1) continue;
+        const size_t ro = (size_t)gi * L.pitch;
+        if (S.je <= L.m + 1) {
+            u[ro + S.je] = e[r];
+            if (rin && ine) {
+                dmax = fmax(dmax, fabs((double)e[r] - (double)ubc[ro + S.je]));
+                rmax = fmax(rmax, fabs(re));
+                umax = fmax(umax, fabs((double)e[r]));
+                rss += re * re;
+            }
+        }
+        if (jo <= L.m + 1) {
+            u[ro + jo] = o[r];
+            if (rin && ino) {
+                dmax = fmax(dmax, fabs((double)o[r] - (double)ubc[ro + jo]));
+                rmax = fmax(rmax, fabs(ro_));
+                umax = fmax(umax, fabs((double)o[r]));
+                rss += ro_ * ro_;
+            }
+        }
+    }
+    rmax = wave_max_d(rmax);
+    umax = wave_max_d(umax);
+    rss = wave_sum_d(rss);
+    dmax = wave_max_d(dmax);
+    if (S.lane == 0) {
+        double* p = part + ((size_t)S.c * ntiles + S.tile) * 5;
+        p[0] = rmax;
+        p[1] = umax;
+        p[2] = rss;
+        p[4] = dmax;
     }
 }
 
@@ -978,66 +1223,55 @@ __global__ __launch_bounds__(kLdsThreads) void k_mg_lds(LdsPlan P, const int* __
 
 // End-of-cycle bookkeeping, one block per channel still running: reduce the
 // per-block partials, write the statistics, raise the channel's flag when the
-// relative correction is <= tol; the last of the three blocks records whether
-// every channel is done.  (Only these three blocks synchronise through
+// relative correction is <= tol.  (Only these blocks synchronise through
 // memory: a device-scope fence per block of a large grid would write back
 // the L2 of its die each time.)
-__global__ __launch_bounds__(256) void k_cycle_finalize(const double* __restrict__ part, int nblk,
-                                                        const double* __restrict__ bnorm,
-                                                        int* __restrict__ done,
-                                                        int* __restrict__ counters,
-                                                        gdgs_stats* __restrict__ stats,
-                                                        double tol, int c0) {
-    __shared__ double sh[3 * 4];
-    __shared__ int s_cycle;
+constexpr int kFinThreads = 256;
+__global__ __launch_bounds__(kFinThreads) void k_cycle_finalize(const double* __restrict__ part,
+                                                               int nblk,
+                                                               const double* __restrict__ bnorm,
+                                                               int* __restrict__ done,
+                                                               gdgs_stats* __restrict__ stats,
+                                                               double tol, int c0) {
+    __shared__ double sh[3 * (kFinThreads / 64)];
     const int c = c0 + blockIdx.x;
-    // this call's cycle index for the channel, counted on the device so that
-    // every cycle's launch sequence is the same (one graph per channel)
+    if (done[c]) return;  // uniform: finished before this cycle
+    double rmax = 0.0, umax = 0.0, rss = 0.0, dpre = 0.0, dpost = 0.0;
+    // two blocks' partials per thread and round, loaded before use
+    constexpr int nt = kFinThreads;
+    for (int b0 = threadIdx.x; b0 < nblk; b0 += 2 * nt) {
+        double v[2][5];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int b = b0 + k * nt;
+            const double* p = part + ((size_t)c * nblk + (b < nblk ? b : 0)) * 5;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) v[k][q] = p[q];
+        }
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            if (b0 + k * nt >= nblk) break;
+            rmax = fmax(rmax, v[k][0]);
+            umax = fmax(umax, v[k][1]);
+            rss += v[k][2];
+            dpre = fmax(dpre, v[k][3]);
+            dpost = fmax(dpost, v[k][4]);
+        }
+    }
+    block_reduce3(rmax, umax, rss, sh);
+    double d0 = 0.0;
+    block_reduce3(dpre, dpost, d0, sh);
     if (threadIdx.x == 0) {
-        s_cycle = counters[kLaunch0 + c];
-        counters[kLaunch0 + c] = s_cycle + 1;
+        // |u_k - u_{k-1}| <= (change in pre-smoothing) + (change in the post pass)
+        const double dcyc = dpre + dpost;
+        const double rel = umax > 0.0 ? dcyc / umax : (dcyc > 0.0 ? 1.0 : 0.0);
+        const double b2 = bnorm[2 * c + 1];
+        stats->eta[c] = rmax / (8.0 * umax + bnorm[2 * c]);
+        stats->rel_res[c] = b2 > 0.0 ? sqrt(rss) / b2 : 0.0;
+        stats->delta[c] = rel;
+        stats->cycles[c] += 1;  // zeroed by setup; accumulates over resumed calls
+        if (rel <= tol) done[c] = 1;
     }
-    __syncthreads();
-    const int cycle = s_cycle;
-    if (!done[c]) {  // uniform: finished before this cycle otherwise
-        double rmax = 0.0, umax = 0.0, rss = 0.0, dpre = 0.0, dpost = 0.0;
-        // four blocks' partials per thread and round, loaded before use
-        const int nt = blockDim.x;
-        for (int b0 = threadIdx.x; b0 < nblk; b0 += 4 * nt) {
-            double v[4][5];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int b = b0 + k * nt;
-                const double* p = part + ((size_t)c * nblk + (b < nblk ? b : 0)) * 5;
-#pragma unroll
-                for (int q = 0; q < 5; ++q) v[k][q] = p[q];
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if (b0 + k * nt >= nblk) break;
-                rmax = fmax(rmax, v[k][0]);
-                umax = fmax(umax, v[k][1]);
-                rss += v[k][2];
-                dpre = fmax(dpre, v[k][3]);
-                dpost = fmax(dpost, v[k][4]);
-            }
-        }
-        block_reduce3(rmax, umax, rss, sh);
-        double d0 = 0.0;
-        block_reduce3(dpre, dpost, d0, sh);
-        if (threadIdx.x == 0) {
-            // |u_k - u_{k-1}| <= (change in pre-smoothing) + (change in the post pass)
-            const double dcyc = dpre + dpost;
-            const double rel = umax > 0.0 ? dcyc / umax : (dcyc > 0.0 ? 1.0 : 0.0);
-            const double b2 = bnorm[2 * c + 1];
-            stats->eta[c] = rmax / (8.0 * umax + bnorm[2 * c]);
-            stats->rel_res[c] = b2 > 0.0 ? sqrt(rss) / b2 : 0.0;
-            stats->delta[c] = rel;
-            stats->cycles[c] += 1;  // zeroed by setup; accumulates over resumed calls
-            if (rel <= tol) done[c] = 1;
-        }
-    }
-    if (threadIdx.x == 0) publish_converged(&counters[1 + cycle], done, stats);
 }
 
 // ---------------------------------------------------------------- divergence adjoint
@@ -1085,9 +1319,10 @@ gdgs_status launch_pre(const LevelDev& L, const LevelDev& C, bool zero, bool del
     if (timed) GDGS_HIP_TRY(hipEventRecord(ev0, st));
     const int z = zero ? 1 : 0;
     if (delta) {
-        dim3 grid((L.m + 2 + kTXf - 1) / kTXf, (L.n + 2 + kTYf - 1) / kTYf, nch);
-        hipLaunchKernelGGL((k_mg_pre<NU, true, kTXf, kTYf, kNTf>), grid, dim3(kNTf), 0, st, L, C, z,
-                           done, part, c0);
+        const int nt = strip_tiles(L.n, L.m);
+        dim3 grid((nt + kSWaves - 1) / kSWaves, nch);
+        hipLaunchKernelGGL((k_fine_pre<NU>), grid, dim3(64 * kSWaves), 0, st, L, C, done, part, c0,
+                           nt, strip_tiles_x(L.m));
     } else if (small_tiles(L)) {
         dim3 grid((L.m + 2 + kTXs - 1) / kTXs, (L.n + 2 + kTYs - 1) / kTYs, nch);
         hipLaunchKernelGGL((k_mg_pre<NU, false, kTXs, kTYs, kNTs>), grid, dim3(kNTs), 0, st, L, C, z,
@@ -1108,9 +1343,10 @@ gdgs_status launch_post(const LevelDev& L, const LevelDev& C, bool fine, const i
     const bool timed = fine && timer_events("mg_post_fine", &ev0, &ev1);
     if (timed) GDGS_HIP_TRY(hipEventRecord(ev0, st));
     if (fine) {
-        dim3 grid((L.m + 2 + kTXf - 1) / kTXf, (L.n + 2 + kTYf - 1) / kTYf, nch);
-        hipLaunchKernelGGL((k_mg_post<NU, true, kTXf, kTYf, kNTf>), grid, dim3(kNTf), 0, st, L, C, done,
-                           part, c0);
+        const int nt = strip_tiles(L.n, L.m);
+        dim3 grid((nt + kSWaves - 1) / kSWaves, nch);
+        hipLaunchKernelGGL((k_fine_post<NU>), grid, dim3(64 * kSWaves), 0, st, L, C, done, part,
+                           c0, nt, strip_tiles_x(L.m));
     } else if (small_tiles(L)) {
         dim3 grid((L.m + 2 + kTXs - 1) / kTXs, (L.n + 2 + kTYs - 1) / kTYs, nch);
         hipLaunchKernelGGL((k_mg_post<NU, false, kTXs, kTYs, kNTs>), grid, dim3(kNTs), 0, st, L, C,
@@ -1272,7 +1508,7 @@ struct PoissonWs {
 
 int norm_blocks(const MgPlan& p) {
     if (p.lc == 0) return 1;
-    return ((p.m[0] + 2 + kTXf - 1) / kTXf) * ((p.n[0] + 2 + kTYf - 1) / kTYf);
+    return strip_tiles(p.n[0], p.m[0]);
 }
 
 int div_blocks(int W, int H) {
@@ -1384,8 +1620,8 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
         return GDGS_OK;
     };
     auto finalize = [&](int c0, int nch, hipStream_t s) -> gdgs_status {
-        hipLaunchKernelGGL(k_cycle_finalize, dim3(nch), dim3(256), 0, s, w.part, nblk, w.bnorm,
-                           w.done, w.counters, sd, p.tol, c0);
+        hipLaunchKernelGGL(k_cycle_finalize, dim3(nch), dim3(kFinThreads), 0, s, w.part, nblk,
+                           w.bnorm, w.done, sd, p.tol, c0);
         GDGS_LAUNCH_CHECK();
         return GDGS_OK;
     };
@@ -1407,76 +1643,84 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
     }
     if (r != GDGS_OK) return r;
 
-    // The three colour channels are independent systems: each runs its
-    // V-cycles on its own stream, so one channel's bandwidth-bound finest
-    // passes overlap another's latency-bound coarse grids.
-    const bool timed =
-        p.lc > 0 && (timer_active("mg_pre_fine") || timer_active("mg_post_fine"));
-    ChannelStreams cs;
-    if (!channel_parallel || !channel_streams(st, &cs)) {
-        // all channels in each launch, on the caller's stream
-        if (!timed) {
-            auto all = [&](hipStream_t s) -> gdgs_status {
-                gdgs_status t = GDGS_OK;
-                for (int cyc = 0; cyc < p.max_cycles && t == GDGS_OK; ++cyc) t = cycle(0, 3, s);
-                return t;
-            };
-            if (!key) return all(st);
-            KeyBuilder ka = *key;
-            ka.tag("cycles3");
-            return with_graph(ka, st, all);
-        }
-        for (int cyc = 0; cyc < p.max_cycles && r == GDGS_OK; ++cyc) {
-            pre(0, 0, 3, st);
-            auto mid = [&](hipStream_t s) { return body(0, 3, s); };
-            if (key) {
-                KeyBuilder kb = *key;
-                kb.tag("body3");
-                r = with_graph(kb, st, mid);
-            } else {
-                r = mid(st);
+    auto run_cycles = [&]() -> gdgs_status {
+        // The three colour channels are independent systems: each runs its
+        // V-cycles on its own stream, so one channel's bandwidth-bound finest
+        // passes overlap another's latency-bound coarse grids.
+        const bool timed =
+            p.lc > 0 && (timer_active("mg_pre_fine") || timer_active("mg_post_fine"));
+        ChannelStreams cs;
+        if (!channel_parallel || !channel_streams(st, &cs)) {
+            // all channels in each launch, on the caller's stream
+            if (!timed) {
+                auto all = [&](hipStream_t s) -> gdgs_status {
+                    gdgs_status t = GDGS_OK;
+                    for (int cyc = 0; cyc < p.max_cycles && t == GDGS_OK; ++cyc)
+                        t = cycle(0, 3, s);
+                    return t;
+                };
+                if (!key) return all(st);
+                KeyBuilder ka = *key;
+                ka.tag("cycles3");
+                return with_graph(ka, st, all);
             }
-            if (r != GDGS_OK) break;
-            post(0, 0, 3, st);
-            r = finalize(0, 3, st);
+            for (int cyc = 0; cyc < p.max_cycles && r == GDGS_OK; ++cyc) {
+                pre(0, 0, 3, st);
+                auto mid = [&](hipStream_t s) { return body(0, 3, s); };
+                if (key) {
+                    KeyBuilder kb = *key;
+                    kb.tag("body3");
+                    r = with_graph(kb, st, mid);
+                } else {
+                    r = mid(st);
+                }
+                if (r != GDGS_OK) break;
+                post(0, 0, 3, st);
+                r = finalize(0, 3, st);
+            }
+            return r;
+        }
+        hipStream_t sc[3] = {st, cs.aux[0], cs.aux[1]};
+        GDGS_HIP_TRY(hipEventRecord(cs.fork, st));
+        for (int k = 0; k < 2; ++k) GDGS_HIP_TRY(hipStreamWaitEvent(cs.aux[k], cs.fork, 0));
+        // Cycles are launched in rounds over the channels, so that all three
+        // streams have work queued early.  (Measured alternatives: one graph per
+        // channel for all cycles, staggered channel starts, one graph with three
+        // branches: none faster; overlapped kernels of different channels slow
+        // each other down, so about two run at a time on average.)
+        auto run = [&](const char* tag, int c, const std::function<gdgs_status(hipStream_t)>& f) {
+            if (!key) return f(sc[c]);
+            KeyBuilder kc = *key;
+            kc.tag(tag).add(c);
+            return with_graph(kc, sc[c], f);
+        };
+        for (int cyc = 0; cyc < p.max_cycles && r == GDGS_OK; ++cyc) {
+            for (int c = 0; c < 3 && r == GDGS_OK; ++c) {
+                if (!timed) {
+                    r = run("cycle", c, [&](hipStream_t s) { return cycle(c, 1, s); });
+                    continue;
+                }
+                // timed finest passes launch directly between their events; the
+                // rest of the cycle is replayed from a cached graph
+                pre(0, c, 1, sc[c]);
+                r = run("body", c, [&](hipStream_t s) { return body(c, 1, s); });
+                if (r != GDGS_OK) break;
+                post(0, c, 1, sc[c]);
+                r = finalize(c, 1, sc[c]);
+            }
+        }
+        // join (also after a failure, so the caller's stream never runs ahead)
+        for (int k = 0; k < 2; ++k) {
+            GDGS_HIP_TRY(hipEventRecord(cs.join[k], cs.aux[k]));
+            GDGS_HIP_TRY(hipStreamWaitEvent(st, cs.join[k], 0));
         }
         return r;
-    }
-    hipStream_t sc[3] = {st, cs.aux[0], cs.aux[1]};
-    GDGS_HIP_TRY(hipEventRecord(cs.fork, st));
-    for (int k = 0; k < 2; ++k) GDGS_HIP_TRY(hipStreamWaitEvent(cs.aux[k], cs.fork, 0));
-    // Cycles are launched in rounds over the channels, so that all three
-    // streams have work queued early.  (Measured alternatives: one graph per
-    // channel for all cycles, staggered channel starts, one graph with three
-    // branches: none faster; overlapped kernels of different channels slow
-    // each other down, so about two run at a time on average.)
-    auto run = [&](const char* tag, int c, const std::function<gdgs_status(hipStream_t)>& f) {
-        if (!key) return f(sc[c]);
-        KeyBuilder kc = *key;
-        kc.tag(tag).add(c);
-        return with_graph(kc, sc[c], f);
     };
-    for (int cyc = 0; cyc < p.max_cycles && r == GDGS_OK; ++cyc) {
-        for (int c = 0; c < 3 && r == GDGS_OK; ++c) {
-            if (!timed) {
-                r = run("cycle", c, [&](hipStream_t s) { return cycle(c, 1, s); });
-                continue;
-            }
-            // timed finest passes launch directly between their events; the
-            // rest of the cycle is replayed from a cached graph
-            pre(0, c, 1, sc[c]);
-            r = run("body", c, [&](hipStream_t s) { return body(c, 1, s); });
-            if (r != GDGS_OK) break;
-            post(0, c, 1, sc[c]);
-            r = finalize(c, 1, sc[c]);
-        }
-    }
-    // join (also after a failure, so the caller's stream never runs ahead)
-    for (int k = 0; k < 2; ++k) {
-        GDGS_HIP_TRY(hipEventRecord(cs.join[k], cs.aux[k]));
-        GDGS_HIP_TRY(hipStreamWaitEvent(st, cs.join[k], 0));
-    }
-    return r;
+    r = run_cycles();
+    if (r != GDGS_OK) return r;
+    hipLaunchKernelGGL(k_publish_converged, dim3(1), dim3(64), 0, st, w.done, sd);
+    GDGS_LAUNCH_CHECK();
+    return GDGS_OK;
 }
 
 gdgs_status launch_div_adjoint(const float* lam, int W, int H, float* dgrad, hipStream_t st) {
