@@ -599,18 +599,21 @@ __global__ __launch_bounds__(NT) void k_mg_post(LevelDev L, LevelDev C,
 }
 
 // ---------------------------------------------------------------- finest grid in register strips
-// On the finest grid each wave owns a region of kSR rows x kSW columns in
-// registers, two adjacent columns per lane (even column in e, odd column in
-// o); the neighbour columns of the lanes on either side come through DPP lane
-// shifts, so smoothing, residual and restriction use no LDS and no barrier.
-// A wave's output is the region minus a halo of kSH cells (2 x 2 half-sweeps
-// shrink the valid region by 4, the residual and the restriction stencil by
-// one each); the halo cells are loaded and smoothed redundantly.  The region
-// origin is even in both directions, so a lane's even column is coarse
-// column (origin / 2 + lane) and the parity of a row is that of its index.
-constexpr int kSR = 32, kSW = 128, kSH = 6;
-constexpr int kSTX = kSW - 2 * kSH, kSTY = kSR - 2 * kSH;  // output tile 116 x 20
-constexpr int kSWaves = 4;                                  // waves (tiles) per block
+// On the finest grid a block owns a region of kSR rows x kSW columns, held in
+// registers: kSNW waves stacked vertically, kSWR rows each, two adjacent
+// columns per lane (even column in e, odd column in o).  The neighbour
+// columns of the lanes on either side come through DPP lane shifts; the rows
+// just above and below a wave's own (ghost rows) are refreshed from the
+// neighbouring waves through LDS after every half-sweep (one barrier).  The
+// region's outermost rows and columns are not refreshed, so the block's
+// output is the region minus a halo of kSH cells (2 x 2 half-sweeps shrink
+// the valid region by 4, the residual and the restriction stencil by one
+// each).  The region origin is even in both directions, so a lane's even
+// column is coarse column (origin / 2 + lane) and a row's parity is that of
+// its index in the region (kSWR is even).
+constexpr int kSWR = 12, kSNW = 4, kSW = 128, kSH = 6;
+constexpr int kSR = kSWR * kSNW;
+constexpr int kSTX = kSW - 2 * kSH, kSTY = kSR - 2 * kSH;  // output tile 116 x 36
 
 int strip_tiles_x(int m) { return (m + 2 + kSTX - 1) / kSTX; }
 int strip_tiles(int n, int m) { return strip_tiles_x(m) * ((n + 2 + kSTY - 1) / kSTY); }
@@ -623,146 +626,209 @@ __device__ __forceinline__ float from_right(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, true));
 }
 
+// This wave's place: channel, tile, region origin, first region row (r0) and
+// the grid column of its lane's even column.
 struct Strip {
-    int c, tile, gi0, gj0, je, lane;
-    bool ok;
-    __device__ Strip(int c0, int ntiles, int tiles_x) {
+    int c, tile, gi0, gj0, r0, je, lane, w;
+    __device__ Strip(int c0, int tiles_x) {
         const int nbx = gridDim.x, nb = nbx * gridDim.y;
         const int Lb = xcd_remap(blockIdx.x + nbx * blockIdx.y, nb);
         c = c0 + Lb / nbx;
-        tile = (Lb % nbx) * kSWaves + (threadIdx.x >> 6);
-        ok = tile < ntiles;
+        tile = Lb % nbx;
         const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
         gi0 = ty * kSTY - kSH;
         gj0 = tx * kSTX - kSH;
+        w = threadIdx.x >> 6;
         lane = threadIdx.x & 63;
+        r0 = w * kSWR;
         je = gj0 + 2 * lane;
     }
+    // this lane's share of the partial-norm array slot
+    __device__ int slot(int ntiles) const { return (c * ntiles + tile) * kSNW + w; }
 };
 
-// Rows of x (channel c) into e/o registers; zero outside the array.
+// Region rows r0 - 1 + q, q = 0 .. Q-1, of x (channel c) into e/o; zero
+// outside the array.
+template <int Q>
 __device__ __forceinline__ void strip_load(const LevelDev& L, const float* x, const Strip& S,
-                                           float (&e)[kSR], float (&o)[kSR]) {
+                                           float (&e)[Q], float (&o)[Q], int q_off) {
     const float* xc = x + (size_t)S.c * L.cs;
     const bool ce = S.je >= 0 && S.je <= L.m + 1, co = S.je + 1 >= 0 && S.je + 1 <= L.m + 1;
 #pragma unroll
-    for (int r = 0; r < kSR; ++r) {
-        const int gi = S.gi0 + r;
+    for (int q = 0; q < Q; ++q) {
+        const int gi = S.gi0 + S.r0 + q - q_off;
         const bool rok = gi >= 0 && gi <= L.n + 1;
         const float* row = xc + (size_t)(rok ? gi : 0) * L.pitch;
-        e[r] = (rok && ce) ? row[S.je] : 0.f;
-        o[r] = (rok && co) ? row[S.je + 1] : 0.f;
+        e[q] = (rok && ce) ? row[S.je] : 0.f;
+        o[q] = (rok && co) ? row[S.je + 1] : 0.f;
     }
 }
 
-// Red-black half-sweep of colour col (0 red: i + j even) on the strip.  In a
-// row exactly one of e, o has the colour; rows 0 and kSR-1 are never updated.
-__device__ __forceinline__ void strip_half(float (&e)[kSR], float (&o)[kSR],
-                                           const float (&fe)[kSR], const float (&fo)[kSR],
+// Exchange of ghost rows: this wave's first and last own rows (e/o index 1
+// and kSWR) go out, the neighbours' come into index 0 and kSWR + 1.  buf
+// alternates between calls so one barrier per exchange suffices.
+__device__ __forceinline__ void strip_exchange(float (&e)[kSWR + 2], float (&o)[kSWR + 2],
+                                               float2 (*sx)[kSNW][2][64], int buf,
+                                               const Strip& S) {
+    sx[buf][S.w][0][S.lane] = make_float2(e[1], o[1]);
+    sx[buf][S.w][1][S.lane] = make_float2(e[kSWR], o[kSWR]);
+    __syncthreads();
+    if (S.w > 0) {
+        const float2 t = sx[buf][S.w - 1][1][S.lane];
+        e[0] = t.x;
+        o[0] = t.y;
+    }
+    if (S.w < kSNW - 1) {
+        const float2 t = sx[buf][S.w + 1][0][S.lane];
+        e[kSWR + 1] = t.x;
+        o[kSWR + 1] = t.y;
+    }
+}
+
+struct StripDiag {
+    float de, dd, dn_e, dn_o, rde, rdo, rde_n, rdo_n;
+    bool ine, ino;
+    __device__ StripDiag(const LevelDev& L, const Strip& S) {
+        const int jo = S.je + 1;
+        ine = S.je >= 1 && S.je <= L.m;
+        ino = jo >= 1 && jo <= L.m;
+        de = 4.f + (S.je == L.m ? L.ex : 0.f);
+        dd = 4.f + (jo == L.m ? L.ex : 0.f);
+        dn_e = de + L.ey;
+        dn_o = dd + L.ey;
+        rde = 1.f / de;
+        rdo = 1.f / dd;
+        rde_n = 1.f / dn_e;
+        rdo_n = 1.f / dn_o;
+    }
+};
+
+// Red-black half-sweep of colour col (0 red: i + j even) over the wave's own
+// rows; in a row exactly one of e, o has the colour.  The region's first and
+// last rows are not updated (their outer neighbours are not held).
+__device__ __forceinline__ void strip_half(float (&e)[kSWR + 2], float (&o)[kSWR + 2],
+                                           const float (&fe)[kSWR], const float (&fo)[kSWR],
                                            int col, const Strip& S, const LevelDev& L,
-                                           bool ine, bool ino, float rde, float rdo, float rde_n,
-                                           float rdo_n) {
+                                           const StripDiag& D) {
 #pragma unroll
-    for (int r = 1; r < kSR - 1; ++r) {
-        const int gi = S.gi0 + r;
-        const bool rin = gi >= 1 && gi <= L.n;
+    for (int q = 1; q <= kSWR; ++q) {
+        const int R = S.r0 + q - 1;  // region row; parity that of q - 1
+        const int gi = S.gi0 + R;
+        const bool upd = gi >= 1 && gi <= L.n && R >= 1 && R <= kSR - 2;
         const bool last = gi == L.n;
-        if (((r + col) & 1) == 0) {  // even column has the colour
-            const float x = ((e[r - 1] + e[r + 1]) + (from_left(o[r]) + o[r])) - fe[r];
-            const float v = x * (last ? rde_n : rde);
-            e[r] = (rin && ine) ? v : e[r];
+        if (((q - 1 + col) & 1) == 0) {  // even column has the colour
+            const float x = ((e[q - 1] + e[q + 1]) + (from_left(o[q]) + o[q])) - fe[q - 1];
+            const float v = x * (last ? D.rde_n : D.rde);
+            e[q] = (upd && D.ine) ? v : e[q];
         } else {
-            const float x = ((o[r - 1] + o[r + 1]) + (e[r] + from_right(e[r]))) - fo[r];
-            const float v = x * (last ? rdo_n : rdo);
-            o[r] = (rin && ino) ? v : o[r];
+            const float x = ((o[q - 1] + o[q + 1]) + (e[q] + from_right(e[q]))) - fo[q - 1];
+            const float v = x * (last ? D.rdo_n : D.rdo);
+            o[q] = (upd && D.ino) ? v : o[q];
         }
     }
 }
 
 // Finest-grid pre-smoothing + FP64 residual + restriction (see k_mg_pre).
 template <int NU>
-__global__ __launch_bounds__(64 * kSWaves) void k_fine_pre(LevelDev L, LevelDev C,
-                                                            const int* __restrict__ done,
-                                                            double* __restrict__ part, int c0,
-                                                            int ntiles, int tiles_x) {
-    const Strip S(c0, ntiles, tiles_x);
-    if (!S.ok || done[S.c]) return;
-    float e[kSR], o[kSR], fe[kSR], fo[kSR];
-    strip_load(L, L.u, S, e, o);
-    strip_load(L, L.f, S, fe, fo);
-    const int jo = S.je + 1;
-    const bool ine = S.je >= 1 && S.je <= L.m, ino = jo >= 1 && jo <= L.m;
-    const float de = 4.f + (S.je == L.m ? L.ex : 0.f), dn_e = de + L.ey;
-    const float dd = 4.f + (jo == L.m ? L.ex : 0.f), dn_o = dd + L.ey;
-    const float rde = 1.f / de, rdo = 1.f / dd, rde_n = 1.f / dn_e, rdo_n = 1.f / dn_o;
+__global__ __launch_bounds__(64 * kSNW) void k_fine_pre(LevelDev L, LevelDev C,
+                                                         const int* __restrict__ done,
+                                                         double* __restrict__ part, int c0,
+                                                         int ntiles, int tiles_x) {
+    __shared__ float2 sx[2][kSNW][2][64];
+    const Strip S(c0, tiles_x);
+    if (done[S.c]) return;  // uniform over the block
+    float e[kSWR + 2], o[kSWR + 2], fe[kSWR], fo[kSWR];
+    strip_load<kSWR + 2>(L, L.u, S, e, o, 1);
+    strip_load<kSWR>(L, L.f, S, fe, fo, 0);
+    const StripDiag D(L, S);
+    int buf = 0;
 #pragma unroll
     for (int s = 0; s < NU; ++s) {
-        strip_half(e, o, fe, fo, 0, S, L, ine, ino, rde, rdo, rde_n, rdo_n);
-        strip_half(e, o, fe, fo, 1, S, L, ine, ino, rde, rdo, rde_n, rdo_n);
+        strip_half(e, o, fe, fo, 0, S, L, D);
+        strip_exchange(e, o, sx, buf, S);
+        buf ^= 1;
+        strip_half(e, o, fe, fo, 1, S, L, D);
+        strip_exchange(e, o, sx, buf, S);
+        buf ^= 1;
     }
-    // output tile: rows [kSH, kSR - kSH), lanes [kSH/2, 64 - kSH/2)
+    // output rows: region rows [kSH, kSR - kSH); lanes [kSH/2, 64 - kSH/2)
     const bool lane_out = S.lane >= kSH / 2 && S.lane < 64 - kSH / 2;
+    const int jo = S.je + 1;
     const float* u0 = L.u + (size_t)S.c * L.cs;
     float* ub = L.ub + (size_t)S.c * L.cs;
     double dmax = 0.0;
 #pragma unroll
-    for (int r = kSH; r < kSR - kSH; ++r) {
-        const int gi = S.gi0 + r;
-        if (!lane_out || gi > L.n + 1) continue;
+    for (int q = 1; q <= kSWR; ++q) {
+        const int R = S.r0 + q - 1, gi = S.gi0 + R;
+        if (!lane_out || R < kSH || R >= kSR - kSH || gi > L.n + 1) continue;
         const size_t ro = (size_t)gi * L.pitch;
         const bool rin = gi >= 1 && gi <= L.n;
         if (S.je <= L.m + 1) {
-            ub[ro + S.je] = e[r];
-            if (rin && ine) dmax = fmax(dmax, fabs((double)e[r] - (double)u0[ro + S.je]));
+            ub[ro + S.je] = e[q];
+            if (rin && D.ine) dmax = fmax(dmax, fabs((double)e[q] - (double)u0[ro + S.je]));
         }
         if (jo <= L.m + 1) {
-            ub[ro + jo] = o[r];
-            if (rin && ino) dmax = fmax(dmax, fabs((double)o[r] - (double)u0[ro + jo]));
+            ub[ro + jo] = o[q];
+            if (rin && D.ino) dmax = fmax(dmax, fabs((double)o[q] - (double)u0[ro + jo]));
         }
     }
-    // residual (FP64 registers, stored FP32 over f) on rows and columns one
-    // beyond the output tile; zero off the interior
+    // residual (FP64 registers, stored FP32 over f) on the own rows; zero off
+    // the interior
 #pragma unroll
-    for (int r = kSH - 1; r <= kSR - kSH; ++r) {
-        const int gi = S.gi0 + r;
+    for (int q = 1; q <= kSWR; ++q) {
+        const int gi = S.gi0 + S.r0 + q - 1;
         const bool rin = gi >= 1 && gi <= L.n;
         const bool last = gi == L.n;
-        const double re = res_value(e[r - 1], e[r + 1], from_left(o[r]), o[r], e[r], fe[r],
-                                    last ? dn_e : de);
-        const double ro_ = res_value(o[r - 1], o[r + 1], e[r], from_right(e[r]), o[r], fo[r],
-                                     last ? dn_o : dd);
-        fe[r] = (rin && ine) ? (float)re : 0.f;
-        fo[r] = (rin && ino) ? (float)ro_ : 0.f;
+        const double re = res_value(e[q - 1], e[q + 1], from_left(o[q]), o[q], e[q], fe[q - 1],
+                                    last ? D.dn_e : D.de);
+        const double rv = res_value(o[q - 1], o[q + 1], e[q], from_right(e[q]), o[q], fo[q - 1],
+                                    last ? D.dn_o : D.dd);
+        fe[q - 1] = (rin && D.ine) ? (float)re : 0.f;
+        fo[q - 1] = (rin && D.ino) ? (float)rv : 0.f;
     }
-    // full weighting at the even points of the output tile
+    // the residual row just above the wave (the last row of the wave above)
+    float ge = 0.f, go = 0.f;
+    sx[buf][S.w][1][S.lane] = make_float2(fe[kSWR - 1], fo[kSWR - 1]);
+    __syncthreads();
+    if (S.w > 0) {
+        const float2 t = sx[buf][S.w - 1][1][S.lane];
+        ge = t.x;
+        go = t.y;
+    }
+    // full weighting at the even points of the output tile: own rows q - 1
+    // even (region row even), neighbours above (q - 2, or the ghost) and below
     float* fc = C.fw + (size_t)S.c * C.cs;
     const int J = S.je >> 1;
 #pragma unroll
-    for (int r = kSH; r < kSR - kSH; r += 2) {
-        const int I = (S.gi0 + r) >> 1;
-        const float v = 4.f * fe[r] +
-                        2.f * (from_left(fo[r]) + fo[r] + fe[r - 1] + fe[r + 1]) +
-                        (from_left(fo[r - 1]) + fo[r - 1] + from_left(fo[r + 1]) + fo[r + 1]);
-        if (lane_out && I >= 1 && I <= C.n && J >= 1 && J <= C.m)
+    for (int q = 1; q <= kSWR; q += 2) {
+        const int R = S.r0 + q - 1;
+        const int I = (S.gi0 + R) >> 1;
+        const float ue = q >= 2 ? fe[q - 2] : ge, uo = q >= 2 ? fo[q - 2] : go;
+        const float ce = fe[q - 1], co = fo[q - 1];
+        const float be = fe[q], bo = fo[q];  // q < kSWR: row below is own
+        const float v = 4.f * ce + 2.f * (from_left(co) + co + ue + be) +
+                        (from_left(uo) + uo + from_left(bo) + bo);
+        if (lane_out && R >= kSH && R < kSR - kSH && I >= 1 && I <= C.n && J >= 1 && J <= C.m)
             fc[(size_t)I * C.pitch + J] = 0.25f * v;
     }
     dmax = wave_max_d(dmax);
-    if (S.lane == 0) part[((size_t)S.c * ntiles + S.tile) * 5 + 3] = dmax;
+    if (S.lane == 0) part[(size_t)S.slot(ntiles) * 5 + 3] = dmax;
 }
 
 // Finest-grid prolongation + correction + post-smoothing + norms (see k_mg_post).
 template <int NU>
-__global__ __launch_bounds__(64 * kSWaves) void k_fine_post(LevelDev L, LevelDev C,
-                                                             const int* __restrict__ done,
-                                                             double* __restrict__ part, int c0,
-                                                             int ntiles, int tiles_x) {
-    constexpr int KC = kSR / 2 + 1;  // coarse rows under the region
-    const Strip S(c0, ntiles, tiles_x);
-    if (!S.ok || done[S.c]) return;
-    float e[kSR], o[kSR], fe[kSR], fo[kSR], E[KC];
-    strip_load(L, L.ub, S, e, o);
-    strip_load(L, L.f, S, fe, fo);
-    const int ci0 = S.gi0 >> 1, J0 = S.je >> 1;
+__global__ __launch_bounds__(64 * kSNW) void k_fine_post(LevelDev L, LevelDev C,
+                                                          const int* __restrict__ done,
+                                                          double* __restrict__ part, int c0,
+                                                          int ntiles, int tiles_x) {
+    constexpr int KC = kSWR / 2 + 1;  // coarse rows under the wave's own rows
+    __shared__ float2 sx[2][kSNW][2][64];
+    const Strip S(c0, tiles_x);
+    if (done[S.c]) return;  // uniform over the block
+    float e[kSWR + 2], o[kSWR + 2], fe[kSWR], fo[kSWR], E[KC];
+    strip_load<kSWR + 2>(L, L.ub, S, e, o, 1);
+    strip_load<kSWR>(L, L.f, S, fe, fo, 0);
+    const int ci0 = (S.gi0 + S.r0) >> 1, J0 = S.je >> 1;
     {
         const float* ec = C.u + (size_t)S.c * C.cs;
         const bool cj = J0 >= 0 && J0 <= C.m + 1;
@@ -772,16 +838,16 @@ __global__ __launch_bounds__(64 * kSWaves) void k_fine_post(LevelDev L, LevelDev
             E[k] = (cj && I >= 0 && I <= C.n + 1) ? ec[(size_t)I * C.pitch + J0] : 0.f;
         }
     }
-    const int jo = S.je + 1;
-    const bool ine = S.je >= 1 && S.je <= L.m, ino = jo >= 1 && jo <= L.m;
-    // bilinear prolongation: e has oj = 0, o has oj = 1 (coarse columns J0, J0 + 1)
+    const StripDiag D(L, S);
+    // bilinear prolongation onto the own rows: e has oj = 0, o has oj = 1
+    // (coarse columns J0 and J0 + 1)
     const float fxo = J0 == C.m ? C.wx : 0.5f;
 #pragma unroll
-    for (int r = 0; r < kSR; ++r) {
-        const int gi = S.gi0 + r;
+    for (int q = 1; q <= kSWR; ++q) {
+        const int gi = S.gi0 + S.r0 + q - 1;
         const bool rin = gi >= 1 && gi <= L.n;
-        const int k = r >> 1;
-        const bool oi = r & 1;
+        const int k = (q - 1) >> 1;
+        const bool oi = (q - 1) & 1;
         const float fy = oi ? ((ci0 + k) == C.n ? C.wy : 0.5f) : 1.f;
         const float p0 = E[k], pa = oi ? E[k + 1] : 0.f;
         const float q0 = from_right(p0), qa = from_right(pa);
@@ -791,49 +857,54 @@ __global__ __launch_bounds__(64 * kSWaves) void k_fine_post(LevelDev L, LevelDev
         if (oi) wo += pa;
         wo += q0;
         if (oi) wo += qa;
-        if (rin && ine) e[r] += fy * 1.f * we;
-        if (rin && ino) o[r] += fy * fxo * wo;
+        if (rin && D.ine) e[q] += fy * 1.f * we;
+        if (rin && D.ino) o[q] += fy * fxo * wo;
     }
-    const float de = 4.f + (S.je == L.m ? L.ex : 0.f), dn_e = de + L.ey;
-    const float dd = 4.f + (jo == L.m ? L.ex : 0.f), dn_o = dd + L.ey;
-    const float rde = 1.f / de, rdo = 1.f / dd, rde_n = 1.f / dn_e, rdo_n = 1.f / dn_o;
+    int buf = 0;
+    strip_exchange(e, o, sx, buf, S);  // ghosts carry the correction too
+    buf ^= 1;
 #pragma unroll
     for (int s = 0; s < NU; ++s) {
-        strip_half(e, o, fe, fo, 1, S, L, ine, ino, rde, rdo, rde_n, rdo_n);
-        strip_half(e, o, fe, fo, 0, S, L, ine, ino, rde, rdo, rde_n, rdo_n);
+        strip_half(e, o, fe, fo, 1, S, L, D);
+        strip_exchange(e, o, sx, buf, S);
+        buf ^= 1;
+        strip_half(e, o, fe, fo, 0, S, L, D);
+        strip_exchange(e, o, sx, buf, S);
+        buf ^= 1;
     }
-    // store the output tile; norms over its interior points
+    // store the output rows; norms over their interior points
     const bool lane_out = S.lane >= kSH / 2 && S.lane < 64 - kSH / 2;
+    const int jo = S.je + 1;
     const float* ubc = L.ub + (size_t)S.c * L.cs;
     float* u = L.u + (size_t)S.c * L.cs;
     double rmax = 0.0, umax = 0.0, rss = 0.0, dmax = 0.0;
 #pragma unroll
-    for (int r = kSH; r < kSR - kSH; ++r) {
-        const int gi = S.gi0 + r;
+    for (int q = 1; q <= kSWR; ++q) {
+        const int R = S.r0 + q - 1, gi = S.gi0 + R;
         const bool rin = gi >= 1 && gi <= L.n;
         const bool last = gi == L.n;
-        const double re = res_value(e[r - 1], e[r + 1], from_left(o[r]), o[r], e[r], fe[r],
-                                    last ? dn_e : de);
-        const double ro_ = res_value(o[r - 1], o[r + 1], e[r], from_right(e[r]), o[r], fo[r],
-                                     last ? dn_o : dd);
-        if (!lane_out || gi > L.n + 1) continue;
+        const double re = res_value(e[q - 1], e[q + 1], from_left(o[q]), o[q], e[q], fe[q - 1],
+                                    last ? D.dn_e : D.de);
+        const double rv = res_value(o[q - 1], o[q + 1], e[q], from_right(e[q]), o[q], fo[q - 1],
+                                    last ? D.dn_o : D.dd);
+        if (!lane_out || R < kSH || R >= kSR - kSH || gi > L.n + 1) continue;
         const size_t ro = (size_t)gi * L.pitch;
         if (S.je <= L.m + 1) {
-            u[ro + S.je] = e[r];
-            if (rin && ine) {
-                dmax = fmax(dmax, fabs((double)e[r] - (double)ubc[ro + S.je]));
+            u[ro + S.je] = e[q];
+            if (rin && D.ine) {
+                dmax = fmax(dmax, fabs((double)e[q] - (double)ubc[ro + S.je]));
                 rmax = fmax(rmax, fabs(re));
-                umax = fmax(umax, fabs((double)e[r]));
+                umax = fmax(umax, fabs((double)e[q]));
                 rss += re * re;
             }
         }
         if (jo <= L.m + 1) {
-            u[ro + jo] = o[r];
-            if (rin && ino) {
-                dmax = fmax(dmax, fabs((double)o[r] - (double)ubc[ro + jo]));
-                rmax = fmax(rmax, fabs(ro_));
-                umax = fmax(umax, fabs((double)o[r]));
-                rss += ro_ * ro_;
+            u[ro + jo] = o[q];
+            if (rin && D.ino) {
+                dmax = fmax(dmax, fabs((double)o[q] - (double)ubc[ro + jo]));
+                rmax = fmax(rmax, fabs(rv));
+                umax = fmax(umax, fabs((double)o[q]));
+                rss += rv * rv;
             }
         }
     }
@@ -842,7 +913,7 @@ __global__ __launch_bounds__(64 * kSWaves) void k_fine_post(LevelDev L, LevelDev
     rss = wave_sum_d(rss);
     dmax = wave_max_d(dmax);
     if (S.lane == 0) {
-        double* p = part + ((size_t)S.c * ntiles + S.tile) * 5;
+        double* p = part + (size_t)S.slot(ntiles) * 5;
         p[0] = rmax;
         p[1] = umax;
         p[2] = rss;
@@ -1320,9 +1391,8 @@ gdgs_status launch_pre(const LevelDev& L, const LevelDev& C, bool zero, bool del
     const int z = zero ? 1 : 0;
     if (delta) {
         const int nt = strip_tiles(L.n, L.m);
-        dim3 grid((nt + kSWaves - 1) / kSWaves, nch);
-        hipLaunchKernelGGL((k_fine_pre<NU>), grid, dim3(64 * kSWaves), 0, st, L, C, done, part, c0,
-                           nt, strip_tiles_x(L.m));
+        hipLaunchKernelGGL((k_fine_pre<NU>), dim3(nt, nch), dim3(64 * kSNW), 0, st, L, C, done,
+                           part, c0, nt, strip_tiles_x(L.m));
     } else if (small_tiles(L)) {
         dim3 grid((L.m + 2 + kTXs - 1) / kTXs, (L.n + 2 + kTYs - 1) / kTYs, nch);
         hipLaunchKernelGGL((k_mg_pre<NU, false, kTXs, kTYs, kNTs>), grid, dim3(kNTs), 0, st, L, C, z,
@@ -1344,9 +1414,8 @@ gdgs_status launch_post(const LevelDev& L, const LevelDev& C, bool fine, const i
     if (timed) GDGS_HIP_TRY(hipEventRecord(ev0, st));
     if (fine) {
         const int nt = strip_tiles(L.n, L.m);
-        dim3 grid((nt + kSWaves - 1) / kSWaves, nch);
-        hipLaunchKernelGGL((k_fine_post<NU>), grid, dim3(64 * kSWaves), 0, st, L, C, done, part,
-                           c0, nt, strip_tiles_x(L.m));
+        hipLaunchKernelGGL((k_fine_post<NU>), dim3(nt, nch), dim3(64 * kSNW), 0, st, L, C, done,
+                           part, c0, nt, strip_tiles_x(L.m));
     } else if (small_tiles(L)) {
         dim3 grid((L.m + 2 + kTXs - 1) / kTXs, (L.n + 2 + kTYs - 1) / kTYs, nch);
         hipLaunchKernelGGL((k_mg_post<NU, false, kTXs, kTYs, kNTs>), grid, dim3(kNTs), 0, st, L, C,
@@ -1508,7 +1577,7 @@ struct PoissonWs {
 
 int norm_blocks(const MgPlan& p) {
     if (p.lc == 0) return 1;
-    return strip_tiles(p.n[0], p.m[0]);
+    return strip_tiles(p.n[0], p.m[0]) * kSNW;
 }
 
 int div_blocks(int W, int H) {
