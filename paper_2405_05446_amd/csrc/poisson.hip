@@ -605,12 +605,14 @@ __global__ __launch_bounds__(NT) void k_mg_post(LevelDev L, LevelDev C,
 // columns of the lanes on either side come through DPP lane shifts; the rows
 // just above and below a wave's own (ghost rows) are refreshed from the
 // neighbouring waves through LDS after every half-sweep (one barrier).  The
-// region's outermost rows and columns are not refreshed, so the block's
-// output is the region minus a halo of kSH cells (2 x 2 half-sweeps shrink
-// the valid region by 4, the residual and the restriction stencil by one
-// each).  The region origin is even in both directions, so a lane's even
+// region's outer ghost rows and edge columns are not refreshed, so the
+// block's output is the region minus a halo of kSH cells (2 x 2 half-sweeps
+// shrink the valid region by 4, the residual and the restriction stencil by
+// one each).  The region origin is even in both directions, so a lane's even
 // column is coarse column (origin / 2 + lane) and a row's parity is that of
-// its index in the region (kSWR is even).
+// its index in the region (kSWR is even).  Blocks whose region and ghost rows
+// lie inside the interior (most of them) take a path without any boundary
+// test: every point is updated and the diagonal is 4.
 constexpr int kSWR = 12, kSNW = 4, kSW = 128, kSH = 6;
 constexpr int kSR = kSWR * kSNW;
 constexpr int kSTX = kSW - 2 * kSH, kSTY = kSR - 2 * kSH;  // output tile 116 x 36
@@ -638,29 +640,44 @@ struct Strip {
         const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
         gi0 = ty * kSTY - kSH;
         gj0 = tx * kSTX - kSH;
-        w = threadIdx.x >> 6;
+        w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: scalar row math
         lane = threadIdx.x & 63;
         r0 = w * kSWR;
         je = gj0 + 2 * lane;
     }
-    // this lane's share of the partial-norm array slot
+    // the region and its outer ghost rows hold interior points only
+    __device__ bool interior(const LevelDev& L) const {
+        return gi0 - 1 >= 1 && gi0 + kSR <= L.n && gj0 >= 1 && gj0 + kSW - 1 <= L.m;
+    }
     __device__ int slot(int ntiles) const { return (c * ntiles + tile) * kSNW + w; }
 };
 
 // Region rows r0 - 1 + q, q = 0 .. Q-1, of x (channel c) into e/o; zero
-// outside the array.
-template <int Q>
+// outside the array (addresses clamped into it: every load unconditional).
+template <bool INT, int Q>
 __device__ __forceinline__ void strip_load(const LevelDev& L, const float* x, const Strip& S,
                                            float (&e)[Q], float (&o)[Q], int q_off) {
     const float* xc = x + (size_t)S.c * L.cs;
-    const bool ce = S.je >= 0 && S.je <= L.m + 1, co = S.je + 1 >= 0 && S.je + 1 <= L.m + 1;
+    const int jo = S.je + 1;
+    if (INT) {
+        const float* pe = xc + (size_t)(S.gi0 + S.r0 - q_off) * L.pitch + S.je;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            e[q] = pe[(size_t)q * L.pitch];
+            o[q] = pe[(size_t)q * L.pitch + 1];
+        }
+        return;
+    }
+    const bool ce = S.je >= 0 && S.je <= L.m + 1, co = jo >= 0 && jo <= L.m + 1;
+    const int je_c = min(max(S.je, 0), L.m + 1), jo_c = min(max(jo, 0), L.m + 1);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int gi = S.gi0 + S.r0 + q - q_off;
         const bool rok = gi >= 0 && gi <= L.n + 1;
-        const float* row = xc + (size_t)(rok ? gi : 0) * L.pitch;
-        e[q] = (rok && ce) ? row[S.je] : 0.f;
-        o[q] = (rok && co) ? row[S.je + 1] : 0.f;
+        const int ro = min(max(gi, 0), L.n + 1) * L.pitch;
+        const float ve = xc[ro + je_c], vo = xc[ro + jo_c];
+        e[q] = (rok && ce) ? ve : 0.f;
+        o[q] = (rok && co) ? vo : 0.f;
     }
 }
 
@@ -704,87 +721,102 @@ struct StripDiag {
 };
 
 // Red-black half-sweep of colour col (0 red: i + j even) over the wave's own
-// rows; in a row exactly one of e, o has the colour.  The region's first and
-// last rows are not updated (their outer neighbours are not held).
+// rows; in a row exactly one of e, o has the colour.
+template <bool INT>
 __device__ __forceinline__ void strip_half(float (&e)[kSWR + 2], float (&o)[kSWR + 2],
                                            const float (&fe)[kSWR], const float (&fo)[kSWR],
                                            int col, const Strip& S, const LevelDev& L,
                                            const StripDiag& D) {
 #pragma unroll
     for (int q = 1; q <= kSWR; ++q) {
-        const int R = S.r0 + q - 1;  // region row; parity that of q - 1
-        const int gi = S.gi0 + R;
-        const bool upd = gi >= 1 && gi <= L.n && R >= 1 && R <= kSR - 2;
-        const bool last = gi == L.n;
+        const int gi = S.gi0 + S.r0 + q - 1;  // parity that of q - 1
+        const bool upd = INT || (gi >= 1 && gi <= L.n);
+        const bool last = !INT && gi == L.n;
         if (((q - 1 + col) & 1) == 0) {  // even column has the colour
             const float x = ((e[q - 1] + e[q + 1]) + (from_left(o[q]) + o[q])) - fe[q - 1];
-            const float v = x * (last ? D.rde_n : D.rde);
-            e[q] = (upd && D.ine) ? v : e[q];
+            if (INT) {
+                e[q] = x * 0.25f;
+            } else {
+                const float v = x * (last ? D.rde_n : D.rde);
+                e[q] = (upd && D.ine) ? v : e[q];
+            }
         } else {
             const float x = ((o[q - 1] + o[q + 1]) + (e[q] + from_right(e[q]))) - fo[q - 1];
-            const float v = x * (last ? D.rdo_n : D.rdo);
-            o[q] = (upd && D.ino) ? v : o[q];
+            if (INT) {
+                o[q] = x * 0.25f;
+            } else {
+                const float v = x * (last ? D.rdo_n : D.rdo);
+                o[q] = (upd && D.ino) ? v : o[q];
+            }
         }
     }
 }
 
-// Finest-grid pre-smoothing + FP64 residual + restriction (see k_mg_pre).
-template <int NU>
-__global__ __launch_bounds__(64 * kSNW) void k_fine_pre(LevelDev L, LevelDev C,
-                                                         const int* __restrict__ done,
-                                                         double* __restrict__ part, int c0,
-                                                         int ntiles, int tiles_x) {
-    __shared__ float2 sx[2][kSNW][2][64];
-    const Strip S(c0, tiles_x);
-    if (done[S.c]) return;  // uniform over the block
-    float e[kSWR + 2], o[kSWR + 2], fe[kSWR], fo[kSWR];
-    strip_load<kSWR + 2>(L, L.u, S, e, o, 1);
-    strip_load<kSWR>(L, L.f, S, fe, fo, 0);
+// FP64 residuals of the even- and odd-column points of own row q.
+template <bool INT>
+__device__ __forceinline__ void strip_residual(const float (&e)[kSWR + 2],
+                                               const float (&o)[kSWR + 2], float fe_q, float fo_q,
+                                               int q, bool last, const StripDiag& D, double& re,
+                                               double& ro) {
+    re = res_value(e[q - 1], e[q + 1], from_left(o[q]), o[q], e[q], fe_q,
+                   INT ? 4.f : (last ? D.dn_e : D.de));
+    ro = res_value(o[q - 1], o[q + 1], e[q], from_right(e[q]), o[q], fo_q,
+                   INT ? 4.f : (last ? D.dn_o : D.dd));
+}
+
+template <int NU, bool INT>
+__device__ __forceinline__ void fine_pre_body(const LevelDev& L, const LevelDev& C,
+                                              double* __restrict__ part, int ntiles,
+                                              const Strip& S, float2 (*sx)[kSNW][2][64]) {
+    float e[kSWR + 2], o[kSWR + 2], fe[kSWR], fo[kSWR], be[kSWR], bo[kSWR];
+    strip_load<INT, kSWR + 2>(L, L.u, S, e, o, 1);
+    strip_load<INT, kSWR>(L, L.f, S, fe, fo, 0);
+#pragma unroll
+    for (int q = 0; q < kSWR; ++q) {
+        be[q] = e[q + 1];
+        bo[q] = o[q + 1];
+    }
     const StripDiag D(L, S);
     int buf = 0;
 #pragma unroll
     for (int s = 0; s < NU; ++s) {
-        strip_half(e, o, fe, fo, 0, S, L, D);
+        strip_half<INT>(e, o, fe, fo, 0, S, L, D);
         strip_exchange(e, o, sx, buf, S);
         buf ^= 1;
-        strip_half(e, o, fe, fo, 1, S, L, D);
+        strip_half<INT>(e, o, fe, fo, 1, S, L, D);
         strip_exchange(e, o, sx, buf, S);
         buf ^= 1;
     }
-    // output rows: region rows [kSH, kSR - kSH); lanes [kSH/2, 64 - kSH/2)
+    // output rows: region rows [kSH, kSR - kSH); lanes [kSH/2, 64 - kSH/2).
+    // (The largest change is taken in FP32: |a - b| of two FP32 values is
+    // within one rounding of the exact difference.)
     const bool lane_out = S.lane >= kSH / 2 && S.lane < 64 - kSH / 2;
     const int jo = S.je + 1;
-    const float* u0 = L.u + (size_t)S.c * L.cs;
     float* ub = L.ub + (size_t)S.c * L.cs;
-    double dmax = 0.0;
+    float dmaxf = 0.f;
 #pragma unroll
     for (int q = 1; q <= kSWR; ++q) {
         const int R = S.r0 + q - 1, gi = S.gi0 + R;
-        if (!lane_out || R < kSH || R >= kSR - kSH || gi > L.n + 1) continue;
+        if (R < kSH || R >= kSR - kSH || (!INT && gi > L.n + 1)) continue;
+        const bool rin = INT || (gi >= 1 && gi <= L.n);
+        const bool ie = lane_out && rin && (INT || D.ine), io = lane_out && rin && (INT || D.ino);
+        dmaxf = fmaxf(dmaxf, ie ? fabsf(e[q] - be[q - 1]) : 0.f);
+        dmaxf = fmaxf(dmaxf, io ? fabsf(o[q] - bo[q - 1]) : 0.f);
+        if (!lane_out) continue;
         const size_t ro = (size_t)gi * L.pitch;
-        const bool rin = gi >= 1 && gi <= L.n;
-        if (S.je <= L.m + 1) {
-            ub[ro + S.je] = e[q];
-            if (rin && D.ine) dmax = fmax(dmax, fabs((double)e[q] - (double)u0[ro + S.je]));
-        }
-        if (jo <= L.m + 1) {
-            ub[ro + jo] = o[q];
-            if (rin && D.ino) dmax = fmax(dmax, fabs((double)o[q] - (double)u0[ro + jo]));
-        }
+        if (INT || S.je <= L.m + 1) ub[ro + S.je] = e[q];
+        if (INT || jo <= L.m + 1) ub[ro + jo] = o[q];
     }
     // residual (FP64 registers, stored FP32 over f) on the own rows; zero off
     // the interior
 #pragma unroll
     for (int q = 1; q <= kSWR; ++q) {
         const int gi = S.gi0 + S.r0 + q - 1;
-        const bool rin = gi >= 1 && gi <= L.n;
-        const bool last = gi == L.n;
-        const double re = res_value(e[q - 1], e[q + 1], from_left(o[q]), o[q], e[q], fe[q - 1],
-                                    last ? D.dn_e : D.de);
-        const double rv = res_value(o[q - 1], o[q + 1], e[q], from_right(e[q]), o[q], fo[q - 1],
-                                    last ? D.dn_o : D.dd);
-        fe[q - 1] = (rin && D.ine) ? (float)re : 0.f;
-        fo[q - 1] = (rin && D.ino) ? (float)rv : 0.f;
+        const bool rin = INT || (gi >= 1 && gi <= L.n);
+        double re, rv;
+        strip_residual<INT>(e, o, fe[q - 1], fo[q - 1], q, !INT && gi == L.n, D, re, rv);
+        fe[q - 1] = (rin && (INT || D.ine)) ? (float)re : 0.f;
+        fo[q - 1] = (rin && (INT || D.ino)) ? (float)rv : 0.f;
     }
     // the residual row just above the wave (the last row of the wave above)
     float ge = 0.f, go = 0.f;
@@ -805,37 +837,55 @@ __global__ __launch_bounds__(64 * kSNW) void k_fine_pre(LevelDev L, LevelDev C,
         const int I = (S.gi0 + R) >> 1;
         const float ue = q >= 2 ? fe[q - 2] : ge, uo = q >= 2 ? fo[q - 2] : go;
         const float ce = fe[q - 1], co = fo[q - 1];
-        const float be = fe[q], bo = fo[q];  // q < kSWR: row below is own
-        const float v = 4.f * ce + 2.f * (from_left(co) + co + ue + be) +
-                        (from_left(uo) + uo + from_left(bo) + bo);
-        if (lane_out && R >= kSH && R < kSR - kSH && I >= 1 && I <= C.n && J >= 1 && J <= C.m)
+        const float bwe = fe[q], bwo = fo[q];  // q < kSWR: the row below is own
+        const float v = 4.f * ce + 2.f * (from_left(co) + co + ue + bwe) +
+                        (from_left(uo) + uo + from_left(bwo) + bwo);
+        if (R < kSH || R >= kSR - kSH || !lane_out) continue;
+        if (INT || (I >= 1 && I <= C.n && J >= 1 && J <= C.m))
             fc[(size_t)I * C.pitch + J] = 0.25f * v;
     }
-    dmax = wave_max_d(dmax);
+    const double dmax = wave_max_d((double)dmaxf);
     if (S.lane == 0) part[(size_t)S.slot(ntiles) * 5 + 3] = dmax;
 }
 
-// Finest-grid prolongation + correction + post-smoothing + norms (see k_mg_post).
+// Finest-grid pre-smoothing + FP64 residual + restriction (see k_mg_pre).
 template <int NU>
-__global__ __launch_bounds__(64 * kSNW) void k_fine_post(LevelDev L, LevelDev C,
-                                                          const int* __restrict__ done,
-                                                          double* __restrict__ part, int c0,
-                                                          int ntiles, int tiles_x) {
-    constexpr int KC = kSWR / 2 + 1;  // coarse rows under the wave's own rows
+__global__ __launch_bounds__(64 * kSNW) void k_fine_pre(LevelDev L, LevelDev C,
+                                                         const int* __restrict__ done,
+                                                         double* __restrict__ part, int c0,
+                                                         int ntiles, int tiles_x) {
     __shared__ float2 sx[2][kSNW][2][64];
     const Strip S(c0, tiles_x);
     if (done[S.c]) return;  // uniform over the block
-    float e[kSWR + 2], o[kSWR + 2], fe[kSWR], fo[kSWR], E[KC];
-    strip_load<kSWR + 2>(L, L.ub, S, e, o, 1);
-    strip_load<kSWR>(L, L.f, S, fe, fo, 0);
+    if (S.interior(L))
+        fine_pre_body<NU, true>(L, C, part, ntiles, S, sx);
+    else
+        fine_pre_body<NU, false>(L, C, part, ntiles, S, sx);
+}
+
+template <int NU, bool INT>
+__device__ __forceinline__ void fine_post_body(const LevelDev& L, const LevelDev& C,
+                                               double* __restrict__ part, int ntiles,
+                                               const Strip& S, float2 (*sx)[kSNW][2][64]) {
+    constexpr int KC = kSWR / 2 + 1;  // coarse rows under the wave's own rows
+    float e[kSWR + 2], o[kSWR + 2], fe[kSWR], fo[kSWR], E[KC], be[kSWR], bo[kSWR];
+    strip_load<INT, kSWR + 2>(L, L.ub, S, e, o, 1);
+    strip_load<INT, kSWR>(L, L.f, S, fe, fo, 0);
+#pragma unroll
+    for (int q = 0; q < kSWR; ++q) {
+        be[q] = e[q + 1];
+        bo[q] = o[q + 1];
+    }
     const int ci0 = (S.gi0 + S.r0) >> 1, J0 = S.je >> 1;
     {
         const float* ec = C.u + (size_t)S.c * C.cs;
         const bool cj = J0 >= 0 && J0 <= C.m + 1;
+        const int Jc = min(max(J0, 0), C.m + 1);
 #pragma unroll
         for (int k = 0; k < KC; ++k) {
             const int I = ci0 + k;
-            E[k] = (cj && I >= 0 && I <= C.n + 1) ? ec[(size_t)I * C.pitch + J0] : 0.f;
+            const float v = ec[(size_t)min(max(I, 0), C.n + 1) * C.pitch + Jc];
+            E[k] = (cj && I >= 0 && I <= C.n + 1) ? v : 0.f;
         }
     }
     const StripDiag D(L, S);
@@ -845,7 +895,7 @@ __global__ __launch_bounds__(64 * kSNW) void k_fine_post(LevelDev L, LevelDev C,
 #pragma unroll
     for (int q = 1; q <= kSWR; ++q) {
         const int gi = S.gi0 + S.r0 + q - 1;
-        const bool rin = gi >= 1 && gi <= L.n;
+        const bool rin = INT || (gi >= 1 && gi <= L.n);
         const int k = (q - 1) >> 1;
         const bool oi = (q - 1) & 1;
         const float fy = oi ? ((ci0 + k) == C.n ? C.wy : 0.5f) : 1.f;
@@ -857,61 +907,54 @@ __global__ __launch_bounds__(64 * kSNW) void k_fine_post(LevelDev L, LevelDev C,
         if (oi) wo += pa;
         wo += q0;
         if (oi) wo += qa;
-        if (rin && D.ine) e[q] += fy * 1.f * we;
-        if (rin && D.ino) o[q] += fy * fxo * wo;
+        const float ve = e[q] + fy * 1.f * we, vo = o[q] + fy * fxo * wo;
+        e[q] = (rin && (INT || D.ine)) ? ve : e[q];
+        o[q] = (rin && (INT || D.ino)) ? vo : o[q];
     }
     int buf = 0;
     strip_exchange(e, o, sx, buf, S);  // ghosts carry the correction too
     buf ^= 1;
 #pragma unroll
     for (int s = 0; s < NU; ++s) {
-        strip_half(e, o, fe, fo, 1, S, L, D);
+        strip_half<INT>(e, o, fe, fo, 1, S, L, D);
         strip_exchange(e, o, sx, buf, S);
         buf ^= 1;
-        strip_half(e, o, fe, fo, 0, S, L, D);
+        strip_half<INT>(e, o, fe, fo, 0, S, L, D);
         strip_exchange(e, o, sx, buf, S);
         buf ^= 1;
     }
-    // store the output rows; norms over their interior points
+    // store the output rows; norms over their interior points (the largest
+    // change and |u| in FP32: exact or within one rounding)
     const bool lane_out = S.lane >= kSH / 2 && S.lane < 64 - kSH / 2;
     const int jo = S.je + 1;
-    const float* ubc = L.ub + (size_t)S.c * L.cs;
     float* u = L.u + (size_t)S.c * L.cs;
-    double rmax = 0.0, umax = 0.0, rss = 0.0, dmax = 0.0;
+    double rmax = 0.0, rss = 0.0;
+    float dmaxf = 0.f, umaxf = 0.f;
 #pragma unroll
     for (int q = 1; q <= kSWR; ++q) {
         const int R = S.r0 + q - 1, gi = S.gi0 + R;
-        const bool rin = gi >= 1 && gi <= L.n;
-        const bool last = gi == L.n;
-        const double re = res_value(e[q - 1], e[q + 1], from_left(o[q]), o[q], e[q], fe[q - 1],
-                                    last ? D.dn_e : D.de);
-        const double rv = res_value(o[q - 1], o[q + 1], e[q], from_right(e[q]), o[q], fo[q - 1],
-                                    last ? D.dn_o : D.dd);
-        if (!lane_out || R < kSH || R >= kSR - kSH || gi > L.n + 1) continue;
+        if (R < kSH || R >= kSR - kSH || (!INT && gi > L.n + 1)) continue;
+        const bool rin = INT || (gi >= 1 && gi <= L.n);
+        double re, rv;
+        strip_residual<INT>(e, o, fe[q - 1], fo[q - 1], q, !INT && gi == L.n, D, re, rv);
+        const bool ie = lane_out && rin && (INT || D.ine), io = lane_out && rin && (INT || D.ino);
+        dmaxf = fmaxf(dmaxf, ie ? fabsf(e[q] - be[q - 1]) : 0.f);
+        dmaxf = fmaxf(dmaxf, io ? fabsf(o[q] - bo[q - 1]) : 0.f);
+        umaxf = fmaxf(umaxf, ie ? fabsf(e[q]) : 0.f);
+        umaxf = fmaxf(umaxf, io ? fabsf(o[q]) : 0.f);
+        rmax = fmax(rmax, ie ? fabs(re) : 0.0);
+        rmax = fmax(rmax, io ? fabs(rv) : 0.0);
+        rss += ie ? re * re : 0.0;
+        rss += io ? rv * rv : 0.0;
+        if (!lane_out) continue;
         const size_t ro = (size_t)gi * L.pitch;
-        if (S.je <= L.m + 1) {
-            u[ro + S.je] = e[q];
-            if (rin && D.ine) {
-                dmax = fmax(dmax, fabs((double)e[q] - (double)ubc[ro + S.je]));
-                rmax = fmax(rmax, fabs(re));
-                umax = fmax(umax, fabs((double)e[q]));
-                rss += re * re;
-            }
-        }
-        if (jo <= L.m + 1) {
-            u[ro + jo] = o[q];
-            if (rin && D.ino) {
-                dmax = fmax(dmax, fabs((double)o[q] - (double)ubc[ro + jo]));
-                rmax = fmax(rmax, fabs(rv));
-                umax = fmax(umax, fabs((double)o[q]));
-                rss += rv * rv;
-            }
-        }
+        if (INT || S.je <= L.m + 1) u[ro + S.je] = e[q];
+        if (INT || jo <= L.m + 1) u[ro + jo] = o[q];
     }
     rmax = wave_max_d(rmax);
-    umax = wave_max_d(umax);
+    const double umax = wave_max_d((double)umaxf);
     rss = wave_sum_d(rss);
-    dmax = wave_max_d(dmax);
+    const double dmax = wave_max_d((double)dmaxf);
     if (S.lane == 0) {
         double* p = part + (size_t)S.slot(ntiles) * 5;
         p[0] = rmax;
@@ -919,6 +962,21 @@ __global__ __launch_bounds__(64 * kSNW) void k_fine_post(LevelDev L, LevelDev C,
         p[2] = rss;
         p[4] = dmax;
     }
+}
+
+// Finest-grid prolongation + correction + post-smoothing + norms (see k_mg_post).
+template <int NU>
+__global__ __launch_bounds__(64 * kSNW) void k_fine_post(LevelDev L, LevelDev C,
+                                                          const int* __restrict__ done,
+                                                          double* __restrict__ part, int c0,
+                                                          int ntiles, int tiles_x) {
+    __shared__ float2 sx[2][kSNW][2][64];
+    const Strip S(c0, tiles_x);
+    if (done[S.c]) return;  // uniform over the block
+    if (S.interior(L))
+        fine_post_body<NU, true>(L, C, part, ntiles, S, sx);
+    else
+        fine_post_body<NU, false>(L, C, part, ntiles, S, sx);
 }
 
 // ---------------------------------------------------------------- coarse V-cycle in LDS
