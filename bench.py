@@ -77,6 +77,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=400)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-laplacian", action="store_true",
+                    help="skip the Laplacian-splat form measurement")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -176,6 +178,36 @@ def serving_leg(G, wl, torch, nreq: int, streams: int, budget: int = 4 << 30):
         res["poisson_arrivals"] = qps
         res["batched_state"] = batched.state()
     return res
+
+
+def laplacian_leg(G, wl, torch, scene, cams, ring, mg, W, H, frames: int):
+    """The Laplacian-splat form (Sec. 2.2) on the same splats and poses: three
+    composited channels are the right-hand side (no divergence).  Frames as a
+    sequence, like the headline figure."""
+    sc = wl.laplacian_scene(scene, seed=0)
+    ds = G.DeviceScene.from_host(sc)
+    r = G.Renderer(ds, W, H, mg)
+    r.render(cams[0], ring)
+    seq = [cams[i % len(cams)] for i in range(frames)]
+    r.render_sequence(seq[:5], ring)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(frames)]
+    cyc = []
+    t0 = time.perf_counter()
+    r.render_sequence(seq, ring, events=ev,
+                      on_frame=lambda i, u, st: cyc.append((st["total_cycles"], st["converged"])))
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / frames
+    stage = np.array([[ev[i][k].elapsed_time(ev[i][k + 1]) for k in range(4)]
+                      for i in range(frames)]).mean(0)
+    return {"workload": f"Laplacian splats (3 values each), {W}x{H}, {sc.opacity.shape[0]} "
+                        "splats, same poses and solver",
+            "Mpix_s": round(H * W / (ms * 1e-3) / 1e6, 2), "ms_per_frame": round(ms, 4),
+            "frames": frames,
+            "stages_ms": {n: round(float(v), 4)
+                          for n, v in zip(("project", "bin_sort", "raster", "poisson"), stage)},
+            "mg_cycles_mean": float(np.mean([c for c, _ in cyc])),
+            "not_converged": int(sum(1 for _, ok in cyc if not ok))}
 
 
 def main():
@@ -349,6 +381,9 @@ def main():
                           "unfused_model_GBs": round(unfused_gbs, 1),
                           "unfused_model_frac": round(unfused_gbs / HBM_PEAK_GBS, 4)},
     }
+    if not args.no_laplacian:
+        out["laplacian_form"] = laplacian_leg(G, wl, torch, scene, cams, ring, mg, W, H,
+                                              min(args.steps, 50))
     if not args.no_serve:
         out["serving"] = serving_leg(G, wl, torch, args.serve_requests, args.serve_streams)
     if not args.no_cpu_baseline:

@@ -231,6 +231,17 @@ gdgs_status gdgs_raster_grad(const gdgs_proj* proj, const float* opacity, const 
                              int64_t K, const gdgs_bins* bins, int32_t W, int32_t H, float* grad,
                              void* ws, size_t ws_bytes, void* stream);
 
+/* Step 3 of the Laplacian-splat form (Sec. 2.2 "Projection" and Eq. 20 with
+ * splats that carry the Laplacian of each colour channel instead of its
+ * gradient): the same compositing with three values per splat,
+ *   rho[c][p] = sum_k lap[c][k] a_k T_{k-1},  c = 0, 1, 2,
+ * whose result is the right-hand side of the Poisson equation (Eq. 21)
+ * directly, with no divergence step (gdgs_poisson_solve_rhs).  lap is [3][K];
+ * rho[3][H][W] is fully written.  Workspace: gdgs_raster_workspace_size(K). */
+gdgs_status gdgs_raster_laplacian(const gdgs_proj* proj, const float* opacity, const float* lap,
+                                  int64_t K, const gdgs_bins* bins, int32_t W, int32_t H,
+                                  float* rho, void* ws, size_t ws_bytes, void* stream);
+
 /* Profiling companion of gdgs_raster_grad: the same traversal without an
  * image; counts[0] (device, uint64) receives the number of (pixel, splat)
  * contributions the composite makes (terms of the sum of Eq. 20 with a non-zero
@@ -270,6 +281,16 @@ gdgs_status gdgs_render(const gdgs_scene* scene, const gdgs_camera* cam, const f
                         const gdgs_mg_params* mg, int64_t pair_capacity, float* u,
                         gdgs_stats* stats_dev, int sync_stats, void* ws, size_t ws_bytes,
                         void* stream);
+
+/* gdgs_render for Laplacian splats (Sec. 2.2): scene->value is [3][K] (the
+ * Laplacian of each colour channel carried by the splat); steps 1, 2, the
+ * three-channel composite of gdgs_raster_laplacian and the Poisson solve with
+ * that composite as rho.  Same workspace, statistics and errors as
+ * gdgs_render. */
+gdgs_status gdgs_render_laplacian(const gdgs_scene* scene, const gdgs_camera* cam,
+                                  const float* boundary, const gdgs_mg_params* mg,
+                                  int64_t pair_capacity, float* u, gdgs_stats* stats_dev,
+                                  int sync_stats, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------ */
 /* Backward pass (gradients of a loss on u through the Poisson solve and the

@@ -1,7 +1,11 @@
 """End-to-end oracle of the three steps of the method (Sec. 2.2 and Algorithm 1):
 project the splats (Eq. 19), composite the projected gradient field front to
 back (Eq. 20), and recover the image by solving the 2D Poisson equation
-(Eq. 21) on the divergence of the composited gradients (Sec. 1.5 and Eq. 14)."""
+(Eq. 21) on the divergence of the composited gradients (Sec. 1.5 and Eq. 14).
+
+render_laplacian is the literal form of Sec. 2.2: the splats carry the
+Laplacian of each colour channel, the composite of those three values is the
+right-hand side of Eq. 21 itself (no divergence step).  Test oracle only."""
 from __future__ import annotations
 
 import numpy as np
@@ -18,3 +22,14 @@ def render(scene, cam, boundary=None) -> dict:
     rho = poisson.divergence(grad)
     u = poisson.solve(rho, boundary)
     return dict(proj=proj, grad=grad, rho=rho, u=u)
+
+
+def render_laplacian(scene, cam, boundary=None) -> dict:
+    """Laplacian splats (scene.value is [3][K]): proj, rho[3][H][W] (the
+    composite) and u[3][H][W] with L u = rho on the interior, u = boundary
+    (or zero) on the ring."""
+    proj = project(scene, cam)
+    rho = composite.render_grad(proj, scene.opacity, scene.value, cam.H, cam.W)
+    u = poisson.solve(rho, boundary)
+    return dict(proj=proj, rho=rho, u=u)
+

@@ -126,6 +126,10 @@ _SIGS = {
     "gdgs_raster_grad": (ctypes.c_int, [P(Proj), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                         P(Bins), ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "gdgs_raster_laplacian": (ctypes.c_int, [P(Proj), ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_int64, P(Bins), ctypes.c_int32,
+                                             ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_size_t, ctypes.c_void_p]),
     "gdgs_raster_count": (ctypes.c_int, [P(Proj), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                          P(Bins), ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
@@ -140,6 +144,10 @@ _SIGS = {
     "gdgs_render": (ctypes.c_int, [P(Scene), P(Camera), ctypes.c_void_p, P(MgParams),
                                    ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                    ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "gdgs_render_laplacian": (ctypes.c_int, [P(Scene), P(Camera), ctypes.c_void_p, P(MgParams),
+                                             ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
+                                             ctypes.c_void_p]),
     "gdgs_div_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                         ctypes.c_void_p, ctypes.c_void_p]),
     "gdgs_raster_grad_backward": (ctypes.c_int, [P(Proj), ctypes.c_void_p, ctypes.c_void_p,

@@ -63,7 +63,7 @@ class DeviceScene:
     log_scale: torch.Tensor  # [3][K]
     quat: torch.Tensor       # [4][K]
     opacity: torch.Tensor    # [K]
-    value: torch.Tensor      # [6][K]
+    value: torch.Tensor      # [6][K] image gradients, or [3][K] Laplacians (Laplacian form)
 
     @property
     def K(self) -> int:
@@ -76,13 +76,20 @@ class DeviceScene:
         return DeviceScene(t(scene.mean), t(scene.log_scale), t(scene.quat), t(scene.opacity),
                            t(scene.value))
 
-    def struct(self) -> L.Scene:
+    @property
+    def nch(self) -> int:
+        return int(self.value.shape[0])
+
+    def struct(self, nch: int | None = None) -> L.Scene:
         K = self.K
+        nch = self.nch if nch is None else nch
+        if nch not in (3, 6):
+            raise ValueError("value must have 6 (gradient) or 3 (Laplacian) rows")
         _need(self.mean, (3, K), F32, "mean")
         _need(self.log_scale, (3, K), F32, "log_scale")
         _need(self.quat, (4, K), F32, "quat")
         _need(self.opacity, (K,), F32, "opacity")
-        _need(self.value, (6, K), F32, "value")
+        _need(self.value, (nch, K), F32, "value")
         return L.Scene(L.ptr(self.mean), L.ptr(self.log_scale), L.ptr(self.quat),
                        L.ptr(self.opacity), L.ptr(self.value), K)
 
@@ -253,10 +260,53 @@ def gdgs_render(scene: DeviceScene, cam, boundary: torch.Tensor | None, mg=None,
     if ws is None:
         ws = workspace(render_workspace_size(scene.K, W, H, capacity, mg), dev)
     c = camera_struct(cam)
-    L.check(lib.gdgs_render(ctypes.byref(scene.struct()), ctypes.byref(c), L.ptr(boundary),
+    L.check(lib.gdgs_render(ctypes.byref(scene.struct(6)), ctypes.byref(c), L.ptr(boundary),
                             ctypes.byref(mg), capacity, L.ptr(u), L.ptr(stats),
                             1 if sync_stats else 0, L.ptr(ws), ws.numel(),
                             L.stream_handle(stream)))
+    return u, stats
+
+
+def gdgs_raster_laplacian(proj: dict, opacity: torch.Tensor, lap: torch.Tensor, K: int,
+                          bins: dict, W: int, H: int, rho: torch.Tensor | None = None,
+                          ws: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Three-channel composite of Laplacian splats (lap [3][K]) -> rho [3][H][W]."""
+    lib = L.load()
+    dev = bins["ranges"].device
+    _need(opacity, (K,), F32, "opacity")
+    _need(lap, (3, K), F32, "lap")
+    rho = rho if rho is not None else torch.empty((3, H, W), dtype=F32, device=dev)
+    if rho.dtype != F32 or not rho.is_contiguous() or rho.numel() < 3 * H * W:
+        raise ValueError("rho must be a contiguous float32 buffer of at least 3*H*W values")
+    need = _size(lib.gdgs_raster_workspace_size, K)
+    ws = ws if ws is not None else workspace(need, dev)
+    L.check(lib.gdgs_raster_laplacian(ctypes.byref(_proj_struct(proj)), L.ptr(opacity),
+                                      L.ptr(lap), K, ctypes.byref(_bins_struct(bins)), W, H,
+                                      L.ptr(rho), L.ptr(ws), ws.numel(), L.stream_handle(stream)))
+    return rho
+
+
+def gdgs_render_laplacian(scene: DeviceScene, cam, boundary: torch.Tensor | None, mg=None,
+                          capacity: int | None = None, u=None, stats=None, ws=None,
+                          sync_stats=False, stream=None):
+    """gdgs_render for a scene of Laplacian splats (scene.value is [3][K])."""
+    lib = L.load()
+    dev = scene.opacity.device
+    W, H = int(cam.W), int(cam.H)
+    mg = mg if mg is not None else mg_params()
+    capacity = int(capacity if capacity is not None else max(1 << 16, 16 * scene.K))
+    if boundary is not None:
+        _need(boundary, (3, H, W), F32, "boundary")
+    u = u if u is not None else torch.empty((3, H, W), dtype=F32, device=dev)
+    _need(u, (3, H, W), F32, "u")
+    stats = stats if stats is not None else new_stats(dev)
+    if ws is None:
+        ws = workspace(render_workspace_size(scene.K, W, H, capacity, mg), dev)
+    c = camera_struct(cam)
+    L.check(lib.gdgs_render_laplacian(ctypes.byref(scene.struct(3)), ctypes.byref(c),
+                                      L.ptr(boundary), ctypes.byref(mg), capacity, L.ptr(u),
+                                      L.ptr(stats), 1 if sync_stats else 0, L.ptr(ws),
+                                      ws.numel(), L.stream_handle(stream)))
     return u, stats
 
 
@@ -353,6 +403,11 @@ class Renderer:
     def __init__(self, scene: DeviceScene, W: int, H: int, mg=None, capacity: int | None = None,
                  adaptive: bool = True):
         self.scene, self.W, self.H = scene, int(W), int(H)
+        # six values per splat: gradient splats; three: Laplacian splats
+        # (Sec. 2.2), whose composite is the right-hand side itself
+        if scene.nch not in (3, 6):
+            raise ValueError("scene.value must have 6 (gradient) or 3 (Laplacian) rows")
+        self.laplacian = scene.nch == 3
         self.mg = mg if mg is not None else mg_params()
         self.max_cycles = int(self.mg.max_cycles)
         self.budget = self.max_cycles
@@ -397,11 +452,14 @@ class Renderer:
         rec(1)
         gdgs_bin_sort(self.proj, K, W, H, self.capacity, self.bins, self.ws_bin, s)
         rec(2)
-        gdgs_raster_grad(self.proj, self.scene.opacity, self.scene.value, K, self.bins, W, H,
-                         self.grad, self.ws_ras, s)
+        if self.laplacian:
+            gdgs_raster_laplacian(self.proj, self.scene.opacity, self.scene.value, K, self.bins,
+                                  W, H, self.grad, self.ws_ras, s)
+        else:
+            gdgs_raster_grad(self.proj, self.scene.opacity, self.scene.value, K, self.bins, W, H,
+                             self.grad, self.ws_ras, s)
         rec(3)
-        gdgs_poisson_solve(self.grad, boundary, W, H, self._mg(self.budget), self.u, self.stats,
-                           self.ws_poi, s)
+        self._solve(boundary, self._mg(self.budget), s)
         rec(4)
         with torch.cuda.stream(s):
             self._h_stats.copy_(self.stats, non_blocking=True)
@@ -426,8 +484,7 @@ class Renderer:
         total = max(st["cycles"])
         while not st["converged"] and total < self.max_cycles:
             step = min(2, self.max_cycles - total)
-            gdgs_poisson_solve(self.grad, boundary, W, H, self._mg(step, RESUME), self.u,
-                               self.stats, self.ws_poi, stream)
+            self._solve(boundary, self._mg(step, RESUME), stream)
             st = read_stats(self.stats)
             total = max(st["cycles"])     # cycle counts accumulate over resumed calls
         st["total_cycles"] = total
@@ -436,6 +493,14 @@ class Renderer:
             self.budget = max(1, min(self.max_cycles, total))
         self.last = st
         return self.u
+
+    def _solve(self, boundary, mg, stream):
+        if self.laplacian:  # the first three planes hold rho
+            gdgs_poisson_solve_rhs(self.grad[:3], boundary, self.W, self.H, mg, self.u,
+                                   self.stats, self.ws_poi, stream)
+        else:
+            gdgs_poisson_solve(self.grad, boundary, self.W, self.H, mg, self.u, self.stats,
+                               self.ws_poi, stream)
 
     def render(self, cam, boundary=None, events=None, stream=None) -> torch.Tensor:
         self._enqueue(cam, boundary, events, stream)

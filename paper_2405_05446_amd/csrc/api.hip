@@ -456,13 +456,14 @@ gdgs_status gdgs_bin_sort(const gdgs_proj* proj, int64_t K, int32_t W, int32_t H
                       [&](hipStream_t s) { return launch_bin_sort(p, K, W, H, bb, b, s); });
 }
 
-gdgs_status gdgs_raster_grad(const gdgs_proj* proj, const float* opacity, const float* value,
-                             int64_t K, const gdgs_bins* bins, int32_t W, int32_t H, float* grad,
-                             void* ws, size_t ws_bytes, void* stream) {
+static gdgs_status raster_common(const gdgs_proj* proj, const float* opacity,
+                                 const float* value, int64_t K, const gdgs_bins* bins, int32_t W,
+                                 int32_t H, float* out, void* ws, size_t ws_bytes, void* stream,
+                                 int nch) {
     clear_error();
     REQUIRE(K >= 0 && K < (int64_t)0xFFFFFFFFll, "K = %lld out of range", (long long)K);
     TRY(check_size(W, H));
-    REQUIRE_PTR(grad);
+    REQUIRE_PTR(out);
     if (K > 0) {
         TRY(check_proj(proj));
         REQUIRE_PTR(opacity);
@@ -473,13 +474,27 @@ gdgs_status gdgs_raster_grad(const gdgs_proj* proj, const float* opacity, const 
     gdgs_proj p = K > 0 ? *proj : gdgs_proj{};
     const gdgs_bins bb = *bins;
     KeyBuilder kb;
-    kb.tag("raster").add(K).add(W).add(H).add(ws).add(opacity).add(value).add(grad);
+    kb.tag("raster").add(nch).add(K).add(W).add(H).add(ws).add(opacity).add(value).add(out);
     add_proj(kb, p);
     add_bins(kb, bb);
     return with_graph(
         kb, as_stream(stream),
-        [&](hipStream_t s) { return launch_raster(p, opacity, value, K, bb, W, H, grad, ws, s); },
+        [&](hipStream_t s) {
+            return launch_raster(p, opacity, value, K, bb, W, H, out, ws, s, nch);
+        },
         {"raster"});
+}
+
+gdgs_status gdgs_raster_grad(const gdgs_proj* proj, const float* opacity, const float* value,
+                             int64_t K, const gdgs_bins* bins, int32_t W, int32_t H, float* grad,
+                             void* ws, size_t ws_bytes, void* stream) {
+    return raster_common(proj, opacity, value, K, bins, W, H, grad, ws, ws_bytes, stream, 6);
+}
+
+gdgs_status gdgs_raster_laplacian(const gdgs_proj* proj, const float* opacity, const float* lap,
+                                  int64_t K, const gdgs_bins* bins, int32_t W, int32_t H,
+                                  float* rho, void* ws, size_t ws_bytes, void* stream) {
+    return raster_common(proj, opacity, lap, K, bins, W, H, rho, ws, ws_bytes, stream, 3);
 }
 
 gdgs_status gdgs_raster_count(const gdgs_proj* proj, const float* opacity, const float* value,
@@ -539,10 +554,12 @@ gdgs_status gdgs_poisson_solve_rhs(const float* rho, const float* boundary, int3
     return poisson_common(nullptr, rho, boundary, W, H, mg, u, stats_dev, ws, ws_bytes, stream);
 }
 
-gdgs_status gdgs_render(const gdgs_scene* scene, const gdgs_camera* cam, const float* boundary,
-                        const gdgs_mg_params* mg, int64_t pair_capacity, float* u,
-                        gdgs_stats* stats_dev, int sync_stats, void* ws, size_t ws_bytes,
-                        void* stream) {
+// nch 6: gradient splats (composite, divergence, solve); nch 3: Laplacian
+// splats (the composite is the right-hand side).
+static gdgs_status render_common(const gdgs_scene* scene, const gdgs_camera* cam,
+                                 const float* boundary, const gdgs_mg_params* mg,
+                                 int64_t pair_capacity, float* u, gdgs_stats* stats_dev,
+                                 int sync_stats, void* ws, size_t ws_bytes, void* stream, int nch) {
     clear_error();
     REQUIRE(scene != nullptr && cam != nullptr, "scene or camera is null");
     const int64_t K = scene->K;
@@ -576,7 +593,7 @@ gdgs_status gdgs_render(const gdgs_scene* scene, const gdgs_camera* cam, const f
     bin_ws_layout(K, pair_capacity, num_tiles(W, H), r.bin_ws, &b);
     const gdgs_scene sc = *scene;
     KeyBuilder kb;
-    kb.tag("render").add(K).add(W).add(H).add(pair_capacity).add(ws).add(sc.opacity)
+    kb.tag("render").add(nch).add(K).add(W).add(H).add(pair_capacity).add(ws).add(sc.opacity)
         .add(sc.value).add(boundary).add(u).add(stats_dev);
     add_plan(kb, plan);
     KeyBuilder kr = kb;
@@ -586,11 +603,12 @@ gdgs_status gdgs_render(const gdgs_scene* scene, const gdgs_camera* cam, const f
         [&](hipStream_t s) -> gdgs_status {
             TRY(launch_bin_sort(r.proj, K, W, H, r.bins, b, s));
             return launch_raster(r.proj, sc.opacity, sc.value, K, r.bins, W, H, r.grad,
-                                 r.raster_ws, s);
+                                 r.raster_ws, s, nch);
         },
         {"raster"}));
-    TRY(launch_poisson(r.grad, nullptr, boundary, W, H, plan, u, stats_dev, r.poisson_ws, st,
-                       &kb));
+    // the Laplacian composite (first three planes of the gradient buffer) is rho
+    TRY(launch_poisson(nch == 6 ? r.grad : nullptr, nch == 6 ? nullptr : r.grad, boundary, W, H,
+                       plan, u, stats_dev, r.poisson_ws, st, &kb));
     TRY(launch_render_stats(r.bins.num_pairs, pair_capacity, stats_dev, st));
     if (sync_stats) {
         GDGS_HIP_TRY(hipStreamSynchronize(st));
@@ -603,6 +621,22 @@ gdgs_status gdgs_render(const gdgs_scene* scene, const gdgs_camera* cam, const f
         }
     }
     return GDGS_OK;
+}
+
+gdgs_status gdgs_render(const gdgs_scene* scene, const gdgs_camera* cam, const float* boundary,
+                        const gdgs_mg_params* mg, int64_t pair_capacity, float* u,
+                        gdgs_stats* stats_dev, int sync_stats, void* ws, size_t ws_bytes,
+                        void* stream) {
+    return render_common(scene, cam, boundary, mg, pair_capacity, u, stats_dev, sync_stats, ws,
+                         ws_bytes, stream, 6);
+}
+
+gdgs_status gdgs_render_laplacian(const gdgs_scene* scene, const gdgs_camera* cam,
+                                  const float* boundary, const gdgs_mg_params* mg,
+                                  int64_t pair_capacity, float* u, gdgs_stats* stats_dev,
+                                  int sync_stats, void* ws, size_t ws_bytes, void* stream) {
+    return render_common(scene, cam, boundary, mg, pair_capacity, u, stats_dev, sync_stats, ws,
+                         ws_bytes, stream, 3);
 }
 
 gdgs_status gdgs_div_adjoint(const float* lam, int32_t W, int32_t H, float* dgrad, void* stream) {

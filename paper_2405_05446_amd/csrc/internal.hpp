@@ -111,9 +111,10 @@ gdgs_status launch_project_2d(const float* mean2d, const float* conic, const flo
 // 64-byte per-splat record in depth-rank order: (mx, my, ox, oy),
 // (a, 2b, c, alpha), (v0..v3), (v4, v5, 0, 0).
 size_t raster_ws_bytes(int64_t K);
+// nch: value rows and output channels (6 image gradients, or 3 Laplacians)
 gdgs_status launch_raster(const gdgs_proj& proj, const float* opacity, const float* value,
                           int64_t K, const gdgs_bins& bins, int W, int H, float* grad,
-                          void* ws, hipStream_t st);
+                          void* ws, hipStream_t st, int nch = 6);
 gdgs_status launch_raster_count(const gdgs_proj& proj, const float* opacity, const float* value,
                                 int64_t K, const gdgs_bins& bins, int W, int H,
                                 unsigned long long* counts, void* ws, hipStream_t st);

@@ -16,6 +16,9 @@
 // FP64), so each pixel evaluates the exponent with six operations and one
 // exp2.
 //
+// The same kernel composites the three Laplacian channels of the Laplacian
+// splats of Sec. 2.2 (NCH = 3: records carry v0..v2, zero beyond).
+//
 // Backward: same traversal; each pixel recomputes a_k and T_{k-1} exactly as
 // the forward did, so its running prefix sum of v w equals the forward's and
 // the suffix S_k = out - prefix_k needs no division by transmittance.  For
@@ -46,7 +49,7 @@ __global__ void k_inv_order(const uint32_t* __restrict__ order, int64_t K,
 __global__ __launch_bounds__(256) void k_build_records(gdgs_proj proj,
                                                        const float* __restrict__ opacity,
                                                        const float* __restrict__ value, int64_t K,
-                                                       float4* __restrict__ rec) {
+                                                       int nch, float4* __restrict__ rec) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= K) return;
     if (proj.count[k] == 0) return;
@@ -64,8 +67,10 @@ __global__ __launch_bounds__(256) void k_build_records(gdgs_proj proj,
     float4* r = rec + 4 * (size_t)k;
     r[0] = make_float4(mx, my, ox, oy);
     r[1] = make_float4(ca, 2.f * cb, cc, opacity[k]);
-    r[2] = make_float4(value[k], value[K + k], value[2 * K + k], value[3 * K + k]);
-    r[3] = make_float4(value[4 * K + k], value[5 * K + k], ylo, yhi);
+    // value rows past nch (the Laplacian form has three) are zero
+    auto v = [&](int m) { return m < nch ? value[(size_t)m * K + k] : 0.f; };
+    r[2] = make_float4(v(0), v(1), v(2), v(3));
+    r[3] = make_float4(v(4), v(5), ylo, yhi);
 }
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
@@ -111,10 +116,10 @@ __device__ __forceinline__ float pair_exponent(const float4& q0, const float4& q
 
 // Composite one splat into a pixel (the Eq. 20 update); counts the
 // contributions when asked to.
-template <bool COUNT>
+template <bool COUNT, int NCH>
 __device__ __forceinline__ void blend(const float4& q0, const float4& q1, const float4& r2,
                                       const float4& r3, float x, float y, float& Tr,
-                                      float (&acc)[6], uint32_t& ncon) {
+                                      float (&acc)[NCH], uint32_t& ncon) {
     const float Ep = pair_exponent(q0, q1, x, y);
     if (Ep >= kEcutL && Tr >= kTmin) {
         if (COUNT && q1.y > 0.f) ++ncon;
@@ -123,16 +128,19 @@ __device__ __forceinline__ void blend(const float4& q0, const float4& q1, const 
         acc[0] += r2.x * w;
         acc[1] += r2.y * w;
         acc[2] += r2.z * w;
-        acc[3] += r2.w * w;
-        acc[4] += r3.x * w;
-        acc[5] += r3.y * w;
+        if constexpr (NCH == 6) {
+            acc[3] += r2.w * w;
+            acc[4] += r3.x * w;
+            acc[5] += r3.y * w;
+        }
         Tr = Tr - al * Tr;
     }
 }
 
 // COUNT: write no image; add the number of (pixel, splat) contributions of
-// the block to counts[0] (profiling only).
-template <bool COUNT>
+// the block to counts[0] (profiling only).  NCH: channels written (6 image
+// gradients, or 3 Laplacians).
+template <bool COUNT, int NCH>
 __global__ __launch_bounds__(256) void k_raster_fwd(const float4* __restrict__ rec,
                                                     const uint32_t* __restrict__ splat_of_pair,
                                                     const uint32_t* __restrict__ ranges,
@@ -165,7 +173,9 @@ __global__ __launch_bounds__(256) void k_raster_fwd(const float4* __restrict__ r
         s_r3[kBatch] = z;
     }
     float Tr = inside ? 1.f : 0.f;
-    float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float acc[NCH];
+#pragma unroll
+    for (int m = 0; m < NCH; ++m) acc[m] = 0.f;
     uint32_t ncon = 0;
     for (uint32_t b0 = start; b0 < end; b0 += kBatch) {
         const int n = (int)min((uint32_t)kBatch, end - b0);
@@ -181,7 +191,7 @@ __global__ __launch_bounds__(256) void k_raster_fwd(const float4* __restrict__ r
                 s_r0[t] = q0;
                 s_r1[t] = q1;
                 s_r2[t] = r2;
-                s_r3[t] = r3;
+                if (NCH > 4) s_r3[t] = r3;
                 m = band_mask(r3.z, r3.w, ty);
             }
             s_mask[t] = m;
@@ -206,11 +216,13 @@ __global__ __launch_bounds__(256) void k_raster_fwd(const float4* __restrict__ r
             const float4 a0 = s_r0[jj.x], a1 = s_r0[jj.y], a2 = s_r0[jj.z], a3 = s_r0[jj.w];
             const float4 c0 = s_r1[jj.x], c1 = s_r1[jj.y], c2 = s_r1[jj.z], c3 = s_r1[jj.w];
             const float4 v0 = s_r2[jj.x], v1 = s_r2[jj.y], v2 = s_r2[jj.z], v3 = s_r2[jj.w];
-            const float4 e0 = s_r3[jj.x], e1 = s_r3[jj.y], e2 = s_r3[jj.z], e3 = s_r3[jj.w];
-            blend<COUNT>(a0, c0, v0, e0, xt, yt, Tr, acc, ncon);
-            blend<COUNT>(a1, c1, v1, e1, xt, yt, Tr, acc, ncon);
-            blend<COUNT>(a2, c2, v2, e2, xt, yt, Tr, acc, ncon);
-            blend<COUNT>(a3, c3, v3, e3, xt, yt, Tr, acc, ncon);
+            const float4 zz = make_float4(0.f, 0.f, 0.f, 0.f);
+            const float4 e0 = NCH > 4 ? s_r3[jj.x] : zz, e1 = NCH > 4 ? s_r3[jj.y] : zz;
+            const float4 e2 = NCH > 4 ? s_r3[jj.z] : zz, e3 = NCH > 4 ? s_r3[jj.w] : zz;
+            blend<COUNT, NCH>(a0, c0, v0, e0, xt, yt, Tr, acc, ncon);
+            blend<COUNT, NCH>(a1, c1, v1, e1, xt, yt, Tr, acc, ncon);
+            blend<COUNT, NCH>(a2, c2, v2, e2, xt, yt, Tr, acc, ncon);
+            blend<COUNT, NCH>(a3, c3, v3, e3, xt, yt, Tr, acc, ncon);
         }
         if (__syncthreads_count(Tr >= kTmin) == 0) break;
     }
@@ -224,7 +236,7 @@ __global__ __launch_bounds__(256) void k_raster_fwd(const float4* __restrict__ r
     if (inside) {
         const size_t HW = (size_t)H * W, p = (size_t)py * W + px;
 #pragma unroll
-        for (int m = 0; m < 6; ++m) grad[m * HW + p] = acc[m];
+        for (int m = 0; m < NCH; ++m) grad[m * HW + p] = acc[m];
     }
 }
 
@@ -422,20 +434,26 @@ size_t raster_ws_bytes(int64_t K) {
 
 gdgs_status launch_raster(const gdgs_proj& proj, const float* opacity, const float* value,
                           int64_t K, const gdgs_bins& bins, int W, int H, float* grad, void* ws,
-                          hipStream_t st) {
+                          hipStream_t st, int nch) {
     Carver c(ws);
     float4* rec = c.take<float4>(4 * (size_t)(K > 0 ? K : 1));
     const int nx = tiles_x(W), T = nx * tiles_y(H);
     if (K > 0) {
         const unsigned g = (unsigned)((K + 255) / 256);
         hipLaunchKernelGGL(k_build_records, dim3(g), dim3(256), 0, st, proj, opacity, value, K,
-                           rec);
+                           nch, rec);
     }
     hipEvent_t ev0, ev1;
     const bool timed = timer_events("raster", &ev0, &ev1);
     if (timed) GDGS_HIP_TRY(hipEventRecord(ev0, st));
-    hipLaunchKernelGGL(k_raster_fwd<false>, dim3(T), dim3(256), 0, st, rec, bins.splat_of_pair,
-                       bins.ranges, bins.tile_order, T, nx, W, H, K, grad, nullptr);
+    if (nch == 3)
+        hipLaunchKernelGGL((k_raster_fwd<false, 3>), dim3(T), dim3(256), 0, st, rec,
+                           bins.splat_of_pair, bins.ranges, bins.tile_order, T, nx, W, H, K, grad,
+                           nullptr);
+    else
+        hipLaunchKernelGGL((k_raster_fwd<false, 6>), dim3(T), dim3(256), 0, st, rec,
+                           bins.splat_of_pair, bins.ranges, bins.tile_order, T, nx, W, H, K, grad,
+                           nullptr);
     if (timed) GDGS_HIP_TRY(hipEventRecord(ev1, st));
     GDGS_LAUNCH_CHECK();
     return GDGS_OK;
@@ -452,10 +470,11 @@ gdgs_status launch_raster_count(const gdgs_proj& proj, const float* opacity, con
     if (K > 0) {
         const unsigned g = (unsigned)((K + 255) / 256);
         hipLaunchKernelGGL(k_build_records, dim3(g), dim3(256), 0, st, proj, opacity, value, K,
-                           rec);
+                           6, rec);
     }
-    hipLaunchKernelGGL(k_raster_fwd<true>, dim3(T), dim3(256), 0, st, rec, bins.splat_of_pair,
-                       bins.ranges, bins.tile_order, T, nx, W, H, K, nullptr, counts);
+    hipLaunchKernelGGL((k_raster_fwd<true, 6>), dim3(T), dim3(256), 0, st, rec,
+                       bins.splat_of_pair, bins.ranges, bins.tile_order, T, nx, W, H, K, nullptr,
+                       counts);
     GDGS_LAUNCH_CHECK();
     return GDGS_OK;
 }
@@ -481,7 +500,8 @@ gdgs_status launch_raster_backward(const gdgs_proj& proj, const float* opacity,
     const int nx = tiles_x(W), T = nx * tiles_y(H);
     const unsigned g = (unsigned)((K + 255) / 256);
     hipLaunchKernelGGL(k_inv_order, dim3(g), dim3(256), 0, st, bins.order, K, inv);
-    hipLaunchKernelGGL(k_build_records, dim3(g), dim3(256), 0, st, proj, opacity, value, K, rec);
+    hipLaunchKernelGGL(k_build_records, dim3(g), dim3(256), 0, st, proj, opacity, value, K, 6,
+                       rec);
     hipLaunchKernelGGL(k_raster_bwd, dim3(T), dim3(256), 0, st, rec, bins.splat_of_pair,
                        bins.ranges, bins.tile_order, T, nx, W, H, K, grad, dgrad, part,
                        bins.capacity);

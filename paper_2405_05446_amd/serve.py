@@ -35,7 +35,7 @@ class Server:
         self.mg = mg if mg is not None else mg_params()
         p = L.ServerParams(int(budget), int(streams), 0, self.mg)
         h = ctypes.c_void_p()
-        L.check(self.lib.gdgs_server_create(ctypes.byref(scene.struct()), ctypes.byref(p),
+        L.check(self.lib.gdgs_server_create(ctypes.byref(scene.struct(6)), ctypes.byref(p),
                                             ctypes.byref(h)))
         self.h = h
         self.live: dict[int, tuple] = {}    # id -> (u, boundary) kept alive until completed

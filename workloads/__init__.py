@@ -32,7 +32,8 @@ class Scene:
     mean[3][K] world position, log_scale[3][K] per-axis log standard scale,
     quat[4][K] rotation quaternion (w, x, y, z), opacity[K] in (0, 1),
     value[6][K] gradient amplitudes, channel index 2*c + d with c in RGB and
-    d = 0 for the derivative along image columns, 1 along image rows.
+    d = 0 for the derivative along image columns, 1 along image rows (or
+    value[3][K], one Laplacian per colour channel, in the Laplacian-splat form).
     """
     mean: np.ndarray
     log_scale: np.ndarray
@@ -114,6 +115,16 @@ def make_scene(K: int, seed: int = 0, z=(2.0, 6.0), ls=(-4.0, 0.5),
     f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
     return Scene(mean=f32(np.stack([mx, my, mz])), log_scale=f32(log_scale.T),
                  quat=f32(q.T), opacity=f32(opacity), value=f32(value.T))
+
+
+def laplacian_scene(scene: Scene, seed: int = 0) -> Scene:
+    """The same splats carrying three Laplacian values each (the Laplacian-splat
+    form): Laplace(0, 0.05) draws, K x 3, from their own generator (seed + 2000)."""
+    rng = np.random.default_rng(seed + 2000)
+    K = scene.opacity.shape[0]
+    lap = rng.laplace(0.0, 0.05, (K, 3))
+    return Scene(mean=scene.mean, log_scale=scene.log_scale, quat=scene.quat,
+                 opacity=scene.opacity, value=np.ascontiguousarray(lap.T, dtype=np.float32))
 
 
 def _axis_angle(axis: np.ndarray, angle: float) -> np.ndarray:
