@@ -77,6 +77,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=400)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-trajectory", action="store_true",
+                    help="skip the cold/warm-start camera-path measurement")
     ap.add_argument("--no-laplacian", action="store_true",
                     help="skip the Laplacian-splat form measurement")
     ap.add_argument("--serve-requests", type=int, default=256)
@@ -208,6 +210,28 @@ def laplacian_leg(G, wl, torch, scene, cams, ring, mg, W, H, frames: int):
                           for n, v in zip(("project", "bin_sort", "raster", "poisson"), stage)},
             "mg_cycles_mean": float(np.mean([c for c, _ in cyc])),
             "not_converged": int(sum(1 for _, ok in cyc if not ok))}
+
+
+def trajectory_leg(G, wl, torch, ds, ring, mg, W, H, frames: int):
+    """Consecutive views of a smoothly moving camera, each solve started cold
+    (zero interior) or warm (the previous frame's image, GDGS_MG_WARM_START):
+    same tolerance, fewer V-cycles when warm."""
+    cams = [wl.trajectory_camera(W, H, i) for i in range(frames)]
+    res = {}
+    for warm in (False, True):
+        r = G.Renderer(ds, W, H, mg, warm_start=warm)
+        r.render_sequence(cams[:4], ring)
+        torch.cuda.synchronize()
+        cyc = []
+        t0 = time.perf_counter()
+        r.render_sequence(cams, ring, on_frame=lambda i, u, st: cyc.append(st["total_cycles"]))
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / frames
+        res["warm" if warm else "cold"] = {
+            "Mpix_s": round(H * W / (ms * 1e-3) / 1e6, 2), "ms_per_frame": round(ms, 4),
+            "mg_cycles_mean": round(float(np.mean(cyc)), 3)}
+    return {"workload": f"{frames} frames of a camera path (0.02 deg and 5e-4 units per "
+                        f"frame), {W}x{H}, same scene and solver", **res}
 
 
 def main():
@@ -381,6 +405,8 @@ def main():
                           "unfused_model_GBs": round(unfused_gbs, 1),
                           "unfused_model_frac": round(unfused_gbs / HBM_PEAK_GBS, 4)},
     }
+    if not args.no_trajectory:
+        out["trajectory"] = trajectory_leg(G, wl, torch, ds, ring, mg, W, H, min(args.steps, 50))
     if not args.no_laplacian:
         out["laplacian_form"] = laplacian_leg(G, wl, torch, scene, cams, ring, mg, W, H,
                                               min(args.steps, 50))

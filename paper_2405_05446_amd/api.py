@@ -401,8 +401,13 @@ class Renderer:
     """
 
     def __init__(self, scene: DeviceScene, W: int, H: int, mg=None, capacity: int | None = None,
-                 adaptive: bool = True):
+                 adaptive: bool = True, warm_start: bool = False):
         self.scene, self.W, self.H = scene, int(W), int(H)
+        # warm_start: each frame's solve starts from the previous frame's image
+        # (GDGS_MG_WARM_START) instead of zero; for consecutive views of a
+        # moving camera it needs fewer V-cycles to the same tolerance
+        self.warm_start = warm_start
+        self._prev_u = None
         # six values per splat: gradient splats; three: Laplacian splats
         # (Sec. 2.2), whose composite is the right-hand side itself
         if scene.nch not in (3, 6):
@@ -459,7 +464,13 @@ class Renderer:
             gdgs_raster_grad(self.proj, self.scene.opacity, self.scene.value, K, self.bins, W, H,
                              self.grad, self.ws_ras, s)
         rec(3)
-        self._solve(boundary, self._mg(self.budget), s)
+        flags = 0
+        if self.warm_start and self._prev_u is not None:
+            if self._prev_u is not self.u:
+                with torch.cuda.stream(s):
+                    self.u.copy_(self._prev_u, non_blocking=True)
+            flags = WARM_START
+        self._solve(boundary, self._mg(self.budget, flags), s)
         rec(4)
         with torch.cuda.stream(s):
             self._h_stats.copy_(self.stats, non_blocking=True)
@@ -489,6 +500,7 @@ class Renderer:
             total = max(st["cycles"])     # cycle counts accumulate over resumed calls
         st["total_cycles"] = total
         st["num_pairs"] = pairs
+        self._prev_u = self.u
         if self.adaptive:
             self.budget = max(1, min(self.max_cycles, total))
         self.last = st
@@ -510,16 +522,22 @@ class Renderer:
         """Render views one after another without the host waiting in between:
         frame i + 1 is enqueued before frame i is settled.  Two buffer sets
         alternate (this renderer and a twin), so frame i's result stays intact
-        until on_frame(i, u, stats) has seen it; results equal render()'s."""
+        until on_frame(i, u, stats) has seen it; results equal render()'s.
+        With warm_start, frame i starts from frame i - 1's image as it stands
+        when frame i is enqueued (before any resumed cycles of frame i - 1),
+        so results meet the same tolerance but may differ from render()'s in
+        the last bits."""
         if not hasattr(self, "_twin"):
             self._twin = Renderer(self.scene, self.W, self.H, self.mg, self.capacity,
-                                  self.adaptive)
+                                  self.adaptive, self.warm_start)
         rs = [self, self._twin]
         prev = None
         for i, cam in enumerate(cams):
             r = rs[i % 2]
             if prev is not None:
                 r.budget = prev[0].budget
+                if self.warm_start:
+                    r._prev_u = prev[0].u
             r._enqueue(cam, boundary, events[i] if events else None, stream)
             if prev is not None:
                 pr, pcam, pi = prev

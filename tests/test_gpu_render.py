@@ -163,3 +163,27 @@ def test_render_sequence_equals_render_frame_by_frame():
     for i, (u, st) in got.items():
         assert st["converged"] and torch.equal(u, want[i]), i
     assert seq.capacity > 64
+
+
+def test_warm_start_along_a_trajectory_meets_the_tolerance_in_fewer_cycles():
+    """Consecutive views of a moving camera (Sec. 2.2: one view per pose):
+    starting each solve from the previous image gives the same images within
+    the image tolerance, in fewer V-cycles."""
+    W, H, K = 320, 180, 20000
+    sc = wl.make_scene(K, seed=0, z=(2.0, 20.0), ls=(-5.0, 0.7))
+    ds = G.DeviceScene.from_host(sc)
+    ring = torch.from_numpy(wl.reference_image(H, W, seed=1).astype(np.float32)).cuda()
+    mg = G.mg_params(tol=1e-6, max_cycles=30)
+    cams = [wl.trajectory_camera(W, H, i) for i in range(8)]
+    out = {}
+    for warm in (False, True):
+        r = G.Renderer(ds, W, H, mg, warm_start=warm)
+        us, cyc = [], []
+        r.render_sequence(cams, ring, on_frame=lambda i, u, st: (us.append(u.clone()),
+                                                                 cyc.append(st["total_cycles"])))
+        torch.cuda.synchronize()
+        out[warm] = (us, cyc)
+    say(f"[render] trajectory cycles cold {out[False][1]} warm {out[True][1]}")
+    for a, b in zip(out[False][0], out[True][0]):
+        assert (a - b).abs().max().item() <= 1e-4
+    assert sum(out[True][1][1:]) < sum(out[False][1][1:])

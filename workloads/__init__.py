@@ -157,6 +157,22 @@ def make_camera(W: int, H: int, fx: float | None = None, pose_index: int | None 
     return cam
 
 
+def trajectory_camera(W: int, H: int, i: int, seed: int = 11,
+                      deg_per_frame: float = 0.02, step: float = 5e-4) -> Camera:
+    """Frame i of a smooth camera path: rotation about a fixed axis (uniform on
+    the sphere, seed) by i * deg_per_frame degrees, centre moved i * step
+    along a fixed unit direction (seed + 1); fx = fy = W."""
+    rng = np.random.default_rng(seed)
+    axis = rng.normal(0.0, 1.0, 3)
+    axis /= np.linalg.norm(axis)
+    d = np.random.default_rng(seed + 1).normal(0.0, 1.0, 3)
+    d /= np.linalg.norm(d)
+    R = _axis_angle(axis, math.radians(deg_per_frame * i))
+    cam = make_camera(W, H)
+    cam.R, cam.t = R, -R @ (d * step * i)
+    return cam
+
+
 def reference_image(H: int, W: int, seed: int = 1) -> np.ndarray:
     """Smooth seeded reference image [3][H][W] (FP64): 0.5 plus four products
     of sines with random amplitudes in [-0.1, 0.1], integer frequencies 1..3
