@@ -296,6 +296,19 @@ gdgs_status gdgs_render_laplacian(const gdgs_scene* scene, const gdgs_camera* ca
 /* Backward pass (gradients of a loss on u through the Poisson solve and the
  * compositing; the particle-parameter gradients of Sec. 1.1, Eq. 5-7). */
 
+/* Reverse mode of gdgs_project (Sec. 1.2 Eq. 10 / Sec. 2.2 Eq. 19, the
+ * particle-parameter gradients of Sec. 1.1): from dL/dmean2d[2][K] and
+ * dL/dconic[3][K] (with respect to the image-plane mean and the conic
+ * (a, b, c) as gdgs_project writes them) to dL/dmean[3][K] (world),
+ * dL/dlog_scale[3][K] and dL/dquat[4][K] (the raw quaternion, through its
+ * normalisation).  The chain: conic -> Sigma2D -> (J W, Sigma) -> camera-space
+ * mean and (R, S) -> quaternion and log-scales; FP64 inside, FP32 stored.
+ * Culled splats (zero quaternion, z_c <= 0.2, det <= 0) get zeros.  The
+ * outputs are fully written; the depth gets no gradient (it only orders). */
+gdgs_status gdgs_project_backward(const gdgs_scene* scene, const gdgs_camera* cam,
+                                  const float* dmean2d, const float* dconic, float* dmean,
+                                  float* dlog_scale, float* dquat, void* stream);
+
 /* Transpose of the divergence: dgrad[6][H][W] from lam[3][H][W] (interior
  * read, taken as 0 elsewhere): dgx = lam[i][j] - lam[i][j+1],
  * dgy = lam[i][j] - lam[i+1][j]. */

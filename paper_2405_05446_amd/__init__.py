@@ -9,7 +9,8 @@ from . import api  # noqa: F401
 from .api import (  # noqa: F401
     DeviceScene, Renderer, alloc_bins, alloc_proj, camera_struct, gdgs_bin_sort,
     gdgs_div_adjoint, gdgs_poisson_solve, gdgs_poisson_solve_rhs, gdgs_project,
-    gdgs_project_2d, gdgs_raster_grad, gdgs_raster_grad_backward, gdgs_render, mg_params,
-    new_stats, read_stats, render_workspace_size, workspace,
+    gdgs_project_2d, gdgs_project_backward, gdgs_raster_grad, gdgs_raster_grad_backward,
+    gdgs_raster_laplacian, gdgs_render, gdgs_render_laplacian, mg_params, new_stats, read_stats,
+    render_workspace_size, workspace,
 )
 from .serve import Server, now_ns  # noqa: F401

@@ -148,6 +148,9 @@ _SIGS = {
                                              ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
                                              ctypes.c_void_p]),
+    "gdgs_project_backward": (ctypes.c_int, [P(Scene), P(Camera), ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p]),
     "gdgs_div_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                         ctypes.c_void_p, ctypes.c_void_p]),
     "gdgs_raster_grad_backward": (ctypes.c_int, [P(Proj), ctypes.c_void_p, ctypes.c_void_p,

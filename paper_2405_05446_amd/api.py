@@ -267,6 +267,26 @@ def gdgs_render(scene: DeviceScene, cam, boundary: torch.Tensor | None, mg=None,
     return u, stats
 
 
+def gdgs_project_backward(scene: DeviceScene, cam, dmean2d: torch.Tensor, dconic: torch.Tensor,
+                          stream=None) -> dict:
+    """dL/d(mean2d [2][K], conic [3][K]) -> dL/d(mean [3][K], log_scale [3][K],
+    quat [4][K]) through the projection."""
+    lib = L.load()
+    K = scene.K
+    dev = scene.opacity.device
+    _need(dmean2d, (2, K), F32, "dmean2d")
+    _need(dconic, (3, K), F32, "dconic")
+    out = dict(mean=torch.empty((3, K), dtype=F32, device=dev),
+               log_scale=torch.empty((3, K), dtype=F32, device=dev),
+               quat=torch.empty((4, K), dtype=F32, device=dev))
+    c = camera_struct(cam)
+    L.check(lib.gdgs_project_backward(ctypes.byref(scene.struct()), ctypes.byref(c),
+                                      L.ptr(dmean2d), L.ptr(dconic), L.ptr(out["mean"]),
+                                      L.ptr(out["log_scale"]), L.ptr(out["quat"]),
+                                      L.stream_handle(stream)))
+    return out
+
+
 def gdgs_raster_laplacian(proj: dict, opacity: torch.Tensor, lap: torch.Tensor, K: int,
                           bins: dict, W: int, H: int, rho: torch.Tensor | None = None,
                           ws: torch.Tensor | None = None, stream=None) -> torch.Tensor:

@@ -11,7 +11,9 @@ Sec. 1.1, Eq. 5-7, through the Poisson reconstruction of Eq. 21):
      another right-hand side) -- gdgs_poisson_solve_rhs;
   2. divergence adjoint: dL/dgrad = D^T lam -- gdgs_div_adjoint;
   3. reverse compositing with transmittance recomputed per pixel --
-     gdgs_raster_grad_backward.
+     gdgs_raster_grad_backward;
+  4. (render3d only) reverse projection to the world means, log-scales and
+     quaternions -- gdgs_project_backward.
 Every step runs in libgdgs; this module only sequences the calls.
 """
 from __future__ import annotations
@@ -62,3 +64,47 @@ def render(mean2d, conic, opacity, value, depth, W: int, H: int, boundary=None, 
     """u[3][H][W] recovered from rasteriser-level gradient splats; differentiable
     in mean2d, conic, opacity and value."""
     return GDGSRenderFn.apply(mean2d, conic, opacity, value, depth, W, H, boundary, mg, capacity)
+
+
+class GDGSRender3DFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, mean, log_scale, quat, opacity, value, cam, W: int, H: int, boundary=None,
+                mg=None, capacity: int | None = None):
+        ds = A.DeviceScene(mean.detach().contiguous(), log_scale.detach().contiguous(),
+                           quat.detach().contiguous(), opacity.detach().contiguous(),
+                           value.detach().contiguous())
+        K = ds.K
+        mg = mg if mg is not None else A.mg_params()
+        proj = A.gdgs_project(ds, cam)
+        cap = int(capacity if capacity is not None else max(1 << 16, 16 * K))
+        bins = A.gdgs_bin_sort(proj, K, W, H, cap)
+        P = int(bins["num_pairs"].item())
+        if P > cap:
+            cap = int(P * 1.25) + 1024
+            bins = A.gdgs_bin_sort(proj, K, W, H, cap)
+        grad = A.gdgs_raster_grad(proj, ds.opacity, ds.value, K, bins, W, H)
+        u, stats = A.gdgs_poisson_solve(grad, boundary, W, H, mg)
+        ctx.ds, ctx.cam, ctx.proj, ctx.bins, ctx.grad = ds, cam, proj, bins, grad
+        ctx.W, ctx.H, ctx.K, ctx.mg, ctx.stats = W, H, K, mg, stats
+        return u
+
+    @staticmethod
+    def backward(ctx, du):
+        ds, W, H, K = ctx.ds, ctx.W, ctx.H, ctx.K
+        du = du.contiguous().to(torch.float32)
+        lam, _ = A.gdgs_poisson_solve_rhs(du, None, W, H, ctx.mg)
+        dgrad = A.gdgs_div_adjoint(lam, W, H)
+        g = A.gdgs_raster_grad_backward(ctx.proj, ds.opacity, ds.value, K, ctx.bins, W, H,
+                                        ctx.grad, dgrad)
+        g3 = A.gdgs_project_backward(ds, ctx.cam, g["mean2d"], g["conic"])
+        return (g3["mean"], g3["log_scale"], g3["quat"], g["opacity"], g["value"], None, None,
+                None, None, None, None)
+
+
+def render3d(mean, log_scale, quat, opacity, value, cam, boundary=None, mg=None,
+             capacity: int | None = None):
+    """u[3][H][W] of a view of 3D gradient splats; differentiable in the world
+    means, log-scales, quaternions, opacities and gradient values."""
+    return GDGSRender3DFn.apply(mean, log_scale, quat, opacity, value, cam, int(cam.W),
+                                int(cam.H), boundary, mg, capacity)
+

@@ -422,6 +422,27 @@ gdgs_status gdgs_project(const gdgs_scene* scene, const gdgs_camera* cam, const 
     return launch_project(*scene, *cam, *out, as_stream(stream));
 }
 
+gdgs_status gdgs_project_backward(const gdgs_scene* scene, const gdgs_camera* cam,
+                                  const float* dmean2d, const float* dconic, float* dmean,
+                                  float* dlog_scale, float* dquat, void* stream) {
+    clear_error();
+    REQUIRE(scene != nullptr && cam != nullptr, "scene or camera is null");
+    const int64_t K = scene->K;
+    REQUIRE(K >= 0 && K < (int64_t)0xFFFFFFFFll, "K = %lld out of range", (long long)K);
+    REQUIRE(cam->fx > 0 && cam->fy > 0, "focal lengths must be positive");
+    if (K == 0) return GDGS_OK;
+    REQUIRE_PTR(scene->mean);
+    REQUIRE_PTR(scene->log_scale);
+    REQUIRE_PTR(scene->quat);
+    REQUIRE_PTR(dmean2d);
+    REQUIRE_PTR(dconic);
+    REQUIRE_PTR(dmean);
+    REQUIRE_PTR(dlog_scale);
+    REQUIRE_PTR(dquat);
+    return launch_project_backward(*scene, *cam, dmean2d, dconic, dmean, dlog_scale, dquat,
+                                   as_stream(stream));
+}
+
 gdgs_status gdgs_project_2d(const float* mean2d, const float* conic, const float* depth,
                             int64_t K, int32_t W, int32_t H, const gdgs_proj* out, void* stream) {
     clear_error();

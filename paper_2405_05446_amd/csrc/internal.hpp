@@ -104,6 +104,9 @@ gdgs_status launch_bin_sort(const gdgs_proj& proj, int64_t K, int W, int H, cons
 // ---------------------------------------------------------------- project
 gdgs_status launch_project(const gdgs_scene& s, const gdgs_camera& cam, const gdgs_proj& out,
                            hipStream_t st);
+gdgs_status launch_project_backward(const gdgs_scene& s, const gdgs_camera& cam,
+                                    const float* dmean2d, const float* dconic, float* gmean,
+                                    float* glog, float* gquat, hipStream_t st);
 gdgs_status launch_project_2d(const float* mean2d, const float* conic, const float* depth,
                               int64_t K, int W, int H, const gdgs_proj& out, hipStream_t st);
 
