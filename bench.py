@@ -77,6 +77,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=400)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-train", action="store_true",
+                    help="skip the Algorithm-1 iteration measurement")
     ap.add_argument("--no-trajectory", action="store_true",
                     help="skip the cold/warm-start camera-path measurement")
     ap.add_argument("--no-laplacian", action="store_true",
@@ -232,6 +234,37 @@ def trajectory_leg(G, wl, torch, ds, ring, mg, W, H, frames: int):
             "mg_cycles_mean": round(float(np.mean(cyc)), 3)}
     return {"workload": f"{frames} frames of a camera path (0.02 deg and 5e-4 units per "
                         f"frame), {W}x{H}, same scene and solver", **res}
+
+
+def train_leg(G, wl, torch, steps: int):
+    """Algorithm-1 iterations (render, Eq. 22 loss, reverse chain to the 3D
+    parameters, Adam) on the differentiation workload: 512x512, 100k splats,
+    a target rendered from a perturbed copy of the scene."""
+    from paper_2405_05446_amd import train as TR
+    cfg = wl.CONFIGS["diff"]
+    W, H, K = cfg["W"], cfg["H"], cfg["K"]
+    truth = wl.make_scene(K, seed=0, z=cfg["z"], ls=cfg["ls"])
+    cam = wl.make_camera(W, H, pose_index=0)
+    target, _ = G.gdgs_render(G.DeviceScene.from_host(truth), cam, None, sync_stats=True)
+    start = wl.make_scene(K, seed=0, z=cfg["z"], ls=cfg["ls"])
+    rng = np.random.default_rng(1)
+    start.value = (start.value * (1.0 + 0.5 * rng.normal(size=start.value.shape))).astype(
+        np.float32)
+    tr = TR.Trainer(G.DeviceScene.from_host(start))
+    first = tr.step(cam, target)["loss"]
+    for _ in range(2):
+        tr.step(cam, target)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    last = None
+    for _ in range(steps):
+        last = tr.step(cam, target)["loss"]
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    return {"workload": f"Algorithm-1 iterations, {W}x{H}, {K} splats, one view, target "
+                        "rendered from the unperturbed scene",
+            "ms_per_step": round(ms, 3), "steps_per_s": round(1e3 / ms, 1),
+            "loss_first": round(first, 6), "loss_last": round(last, 6), "steps": steps + 3}
 
 
 def main():
@@ -405,6 +438,8 @@ def main():
                           "unfused_model_GBs": round(unfused_gbs, 1),
                           "unfused_model_frac": round(unfused_gbs / HBM_PEAK_GBS, 4)},
     }
+    if not args.no_train:
+        out["train_step"] = train_leg(G, wl, torch, 10)
     if not args.no_trajectory:
         out["trajectory"] = trajectory_leg(G, wl, torch, ds, ring, mg, W, H, min(args.steps, 50))
     if not args.no_laplacian:

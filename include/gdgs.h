@@ -309,6 +309,28 @@ gdgs_status gdgs_project_backward(const gdgs_scene* scene, const gdgs_camera* ca
                                   const float* dmean2d, const float* dconic, float* dmean,
                                   float* dlog_scale, float* dquat, void* stream);
 
+/* Image loss of an optimisation step (Sec. 2.3, Eq. 22, the loss Algorithm 1
+ * evaluates each iteration) between the rendered image c[3][H][W] and the
+ * observed im[3][H][W]:
+ *   L = (1 - lam) mean|c - im| + beta mean|grad c - grad im| + lam (1 - mean SSIM),
+ * forward differences along columns and rows; SSIM per channel over an
+ * 11 x 11 Gaussian window (sigma 1.5, normalised, zero padding), C1 = 1e-4,
+ * C2 = 9e-4.  loss_dev (device, 4 doubles) receives L and its three terms;
+ * dc[3][H][W] (may be NULL) receives dL/dc.  Workspace:
+ * gdgs_image_loss_workspace_size(W, H). */
+gdgs_status gdgs_image_loss_workspace_size(int32_t W, int32_t H, size_t* bytes);
+gdgs_status gdgs_image_loss(const float* c, const float* im, int32_t W, int32_t H, double lam,
+                            double beta, double* loss_dev, float* dc, void* ws, size_t ws_bytes,
+                            void* stream);
+
+/* One Adam update (Kingma and Ba) of n parameters at step t >= 1:
+ * m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ * param -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps), then clamped
+ * to [lo, hi] if lo < hi.  All arrays device, in place. */
+gdgs_status gdgs_adam_step(float* param, const float* grad, float* m, float* v, int64_t n,
+                           int32_t t, float lr, float beta1, float beta2, float eps, float lo,
+                           float hi, void* stream);
+
 /* Transpose of the divergence: dgrad[6][H][W] from lam[3][H][W] (interior
  * read, taken as 0 elsewhere): dgx = lam[i][j] - lam[i][j+1],
  * dgy = lam[i][j] - lam[i+1][j]. */

@@ -69,7 +69,18 @@ def gradients(params: dict, H: int, W: int, target: np.ndarray):
     """Loss and exact dl/d(mean2d, conic, opacity, value) (FP64)."""
     solver = _Solver(H, W)
     fw = forward(params, H, W, target, solver)
-    lam = solver(fw["e"])             # L_int lam = e, zero ring
+    return gradients_from_du(params, H, W, fw["e"], fw, solver)
+
+
+def gradients_from_du(params: dict, H: int, W: int, du: np.ndarray, fw=None, solver=None):
+    """dl/d(mean2d, conic, opacity, value) for any loss whose gradient with
+    respect to u is du[3][H][W] (its ring is not used: u's ring is data)."""
+    solver = solver or _Solver(H, W)
+    if fw is None:
+        fw = forward(params, H, W, np.zeros((3, H, W)), solver)
+    e = np.zeros((3, H, W))
+    e[:, 1:-1, 1:-1] = np.asarray(du, dtype=np.float64)[:, 1:-1, 1:-1]
+    lam = solver(e)                   # L_int lam = e, zero ring
     dgrad = poisson.div_adjoint(lam)
     proj = fw["proj"]
     K = np.asarray(params["opacity"]).shape[0]

@@ -287,6 +287,36 @@ def gdgs_project_backward(scene: DeviceScene, cam, dmean2d: torch.Tensor, dconic
     return out
 
 
+def gdgs_image_loss(c: torch.Tensor, im: torch.Tensor, lam: float = 0.2, beta: float = 0.1,
+                    want_grad: bool = True, ws=None, stream=None):
+    """Eq. 22 between images c, im [3][H][W]: (loss [4] float64 device tensor
+    (L, L1 term, gradient term, D_SSIM), dL/dc or None)."""
+    lib = L.load()
+    H, W = int(c.shape[1]), int(c.shape[2])
+    _need(c, (3, H, W), F32, "c")
+    _need(im, (3, H, W), F32, "im")
+    out = torch.zeros(4, dtype=torch.float64, device=c.device)
+    dc = torch.empty_like(c) if want_grad else None
+    need = _size(lib.gdgs_image_loss_workspace_size, W, H)
+    ws = ws if ws is not None else workspace(need, c.device)
+    L.check(lib.gdgs_image_loss(L.ptr(c), L.ptr(im), W, H, float(lam), float(beta), L.ptr(out),
+                                L.ptr(dc), L.ptr(ws), ws.numel(), L.stream_handle(stream)))
+    return out, dc
+
+
+def gdgs_adam_step(param: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor,
+                   t: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+                   eps: float = 1e-15, lo: float = 0.0, hi: float = 0.0, stream=None):
+    """In-place Adam update of param (and its moments m, v) at step t >= 1;
+    clamped to [lo, hi] when lo < hi."""
+    lib = L.load()
+    for name, x in (("grad", grad), ("m", m), ("v", v)):
+        _need(x, tuple(param.shape), F32, name)
+    L.check(lib.gdgs_adam_step(L.ptr(param), L.ptr(grad), L.ptr(m), L.ptr(v), param.numel(),
+                               int(t), float(lr), float(beta1), float(beta2), float(eps),
+                               float(lo), float(hi), L.stream_handle(stream)))
+
+
 def gdgs_raster_laplacian(proj: dict, opacity: torch.Tensor, lap: torch.Tensor, K: int,
                           bins: dict, W: int, H: int, rho: torch.Tensor | None = None,
                           ws: torch.Tensor | None = None, stream=None) -> torch.Tensor:

@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgdgs.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["project.hip", "binsort.hip", "raster.hip", "poisson.hip", "api.hip", "server.hip"]
+SOURCES = ["project.hip", "binsort.hip", "raster.hip", "poisson.hip", "loss.hip", "api.hip",
+           "server.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 ARCH = os.environ.get("GDGS_ARCH", "gfx950")

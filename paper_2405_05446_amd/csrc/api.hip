@@ -422,6 +422,47 @@ gdgs_status gdgs_project(const gdgs_scene* scene, const gdgs_camera* cam, const 
     return launch_project(*scene, *cam, *out, as_stream(stream));
 }
 
+gdgs_status gdgs_image_loss_workspace_size(int32_t W, int32_t H, size_t* bytes) {
+    clear_error();
+    REQUIRE(bytes != nullptr, "bytes is null");
+    TRY(check_size(W, H));
+    *bytes = loss_ws_bytes(W, H);
+    return GDGS_OK;
+}
+
+gdgs_status gdgs_image_loss(const float* c, const float* im, int32_t W, int32_t H, double lam,
+                            double beta, double* loss_dev, float* dc, void* ws, size_t ws_bytes,
+                            void* stream) {
+    clear_error();
+    TRY(check_size(W, H));
+    REQUIRE_PTR(c);
+    REQUIRE_PTR(im);
+    if (dc) REQUIRE_PTR(dc);
+    REQUIRE(loss_dev != nullptr && (reinterpret_cast<uintptr_t>(loss_dev) & 7u) == 0,
+            "loss_dev is null or not 8-byte aligned");
+    REQUIRE(lam >= 0.0 && lam <= 1.0 && beta >= 0.0, "need 0 <= lam <= 1 and beta >= 0");
+    TRY(check_ws(ws, ws_bytes, loss_ws_bytes(W, H)));
+    return launch_image_loss(c, im, W, H, lam, beta, loss_dev, dc, ws, as_stream(stream));
+}
+
+gdgs_status gdgs_adam_step(float* param, const float* grad, float* m, float* v, int64_t n,
+                           int32_t t, float lr, float beta1, float beta2, float eps, float lo,
+                           float hi, void* stream) {
+    clear_error();
+    REQUIRE(n >= 0, "n must be >= 0");
+    REQUIRE(t >= 1, "step t must be >= 1");
+    REQUIRE(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f,
+            "invalid Adam constants");
+    if (n > 0) {
+        REQUIRE_PTR(param);
+        REQUIRE_PTR(grad);
+        REQUIRE_PTR(m);
+        REQUIRE_PTR(v);
+    }
+    return launch_adam(param, grad, m, v, n, t, lr, beta1, beta2, eps, lo, hi,
+                       as_stream(stream));
+}
+
 gdgs_status gdgs_project_backward(const gdgs_scene* scene, const gdgs_camera* cam,
                                   const float* dmean2d, const float* dconic, float* dmean,
                                   float* dlog_scale, float* dquat, void* stream) {

@@ -107,6 +107,11 @@ gdgs_status launch_project(const gdgs_scene& s, const gdgs_camera& cam, const gd
 gdgs_status launch_project_backward(const gdgs_scene& s, const gdgs_camera& cam,
                                     const float* dmean2d, const float* dconic, float* gmean,
                                     float* glog, float* gquat, hipStream_t st);
+size_t loss_ws_bytes(int W, int H);
+gdgs_status launch_image_loss(const float* c, const float* im, int W, int H, double lam,
+                              double beta, double* out, float* dc, void* ws, hipStream_t st);
+gdgs_status launch_adam(float* p, const float* g, float* m, float* v, int64_t n, int t, float lr,
+                        float b1, float b2, float eps, float lo, float hi, hipStream_t st);
 gdgs_status launch_project_2d(const float* mean2d, const float* conic, const float* depth,
                               int64_t K, int W, int H, const gdgs_proj& out, hipStream_t st);
 
