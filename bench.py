@@ -267,6 +267,35 @@ def train_leg(G, wl, torch, steps: int):
             "loss_first": round(first, 6), "loss_last": round(last, 6), "steps": steps + 3}
 
 
+def sparsity_leg(G, wl, torch, scene, cam, ring, mg, W, H):
+    """Hard threshold of Eq. 24 on the composited Laplacian before the solve
+    (Laplacian form, one pose): non-zero fraction of rho and the MSE of the
+    reconstruction against the unthresholded one, for thresholds at fixed
+    fractions of the mean |rho|, and at the two absolute thresholds of the
+    paper's sparsity experiment (Sec. 3.1), on synthetic splats."""
+    ds = G.DeviceScene.from_host(wl.laplacian_scene(scene, seed=0))
+    r0 = G.Renderer(ds, W, H, mg)
+    u0 = r0.render(cam, ring).clone()
+    mean_abs = float(r0.grad[:3].abs().mean())
+    ms0 = float((u0[:, 1:-1, 1:-1] ** 2).mean())
+    n = 3 * H * W
+    rows = []
+    for t in (0.003, 0.004) + tuple(f * mean_abs for f in (0.25, 0.5, 1.0, 2.0)):
+        r = G.Renderer(ds, W, H, mg, threshold=t)
+        u = r.render(cam, ring)
+        torch.cuda.synchronize()
+        mse = float(((u - u0)[:, 1:-1, 1:-1] ** 2).mean())
+        nz = (r.grad[:3] != 0).any(0).float()
+        nz = torch.nn.functional.pad(nz, (0, (-W) % 16, 0, (-H) % 16))
+        tiles = nz.reshape(nz.shape[0] // 16, 16, nz.shape[1] // 16, 16).amax((1, 3))
+        rows.append({"t": t, "t_over_mean_abs_rho": round(t / mean_abs, 4),
+                     "nonzero_frac": round(int(r.nonzero.item()) / n, 4),
+                     "zero_tile_frac": round(1.0 - float(tiles.mean()), 4), "mse": mse,
+                     "rel_rmse": (mse / ms0) ** 0.5 if ms0 > 0 else None})
+    return {"workload": f"Laplacian splats, {W}x{H}, {scene.opacity.shape[0]} splats, one pose",
+            "mean_abs_rho": mean_abs, "thresholds": rows}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -445,6 +474,7 @@ def main():
     if not args.no_laplacian:
         out["laplacian_form"] = laplacian_leg(G, wl, torch, scene, cams, ring, mg, W, H,
                                               min(args.steps, 50))
+        out["sparsity"] = sparsity_leg(G, wl, torch, scene, cams[0], ring, mg, W, H)
     if not args.no_serve:
         out["serving"] = serving_leg(G, wl, torch, args.serve_requests, args.serve_streams)
     if not args.no_cpu_baseline:

@@ -323,6 +323,12 @@ gdgs_status gdgs_image_loss(const float* c, const float* im, int32_t W, int32_t 
                             double beta, double* loss_dev, float* dc, void* ws, size_t ws_bytes,
                             void* stream);
 
+/* Hard threshold of Sec. 3.1 (Eq. 24), in place on x[n] (device):
+ * x = x if |x| >= t else 0 (t >= 0), the sparse representation of a
+ * Laplacian field before the Poisson solve.  nonzero_dev (device uint64, may
+ * be NULL) receives the number of non-zero values left. */
+gdgs_status gdgs_threshold(float* x, int64_t n, float t, uint64_t* nonzero_dev, void* stream);
+
 /* One Adam update (Kingma and Ba) of n parameters at step t >= 1:
  * m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
  * param -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps), then clamped

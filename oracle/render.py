@@ -24,12 +24,20 @@ def render(scene, cam, boundary=None) -> dict:
     return dict(proj=proj, grad=grad, rho=rho, u=u)
 
 
-def render_laplacian(scene, cam, boundary=None) -> dict:
+def threshold(x: np.ndarray, t: float) -> np.ndarray:
+    """Hard threshold of Sec. 3.1 (Eq. 24): x where |x| >= t, else 0."""
+    x = np.asarray(x)
+    return np.where(np.abs(x) >= t, x, np.zeros_like(x))
+
+
+def render_laplacian(scene, cam, boundary=None, t: float = 0.0) -> dict:
     """Laplacian splats (scene.value is [3][K]): proj, rho[3][H][W] (the
-    composite) and u[3][H][W] with L u = rho on the interior, u = boundary
-    (or zero) on the ring."""
+    composite, hard-thresholded at t when t > 0) and u[3][H][W] with
+    L u = rho on the interior, u = boundary (or zero) on the ring."""
     proj = project(scene, cam)
     rho = composite.render_grad(proj, scene.opacity, scene.value, cam.H, cam.W)
+    if t > 0.0:
+        rho = threshold(rho, t)
     u = poisson.solve(rho, boundary)
     return dict(proj=proj, rho=rho, u=u)
 

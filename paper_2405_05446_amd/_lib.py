@@ -157,6 +157,8 @@ _SIGS = {
                                        ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_size_t, ctypes.c_void_p]),
+    "gdgs_threshold": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_float,
+                                      ctypes.c_void_p, ctypes.c_void_p]),
     "gdgs_adam_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
                                       ctypes.c_float, ctypes.c_float, ctypes.c_float,

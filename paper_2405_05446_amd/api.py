@@ -304,6 +304,18 @@ def gdgs_image_loss(c: torch.Tensor, im: torch.Tensor, lam: float = 0.2, beta: f
     return out, dc
 
 
+def gdgs_threshold(x: torch.Tensor, t: float, count: bool = True, stream=None):
+    """In-place hard threshold (Eq. 24) of a float32 device tensor; returns a
+    device int64 tensor with the non-zero count (or None)."""
+    lib = L.load()
+    if x.dtype != F32 or not x.is_contiguous() or not x.is_cuda:
+        raise ValueError("x must be a contiguous float32 device tensor")
+    nz = torch.zeros(1, dtype=torch.int64, device=x.device) if count else None
+    L.check(lib.gdgs_threshold(L.ptr(x), x.numel(), float(t), L.ptr(nz),
+                               L.stream_handle(stream)))
+    return nz
+
+
 def gdgs_adam_step(param: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor,
                    t: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
                    eps: float = 1e-15, lo: float = 0.0, hi: float = 0.0, stream=None):
@@ -451,8 +463,13 @@ class Renderer:
     """
 
     def __init__(self, scene: DeviceScene, W: int, H: int, mg=None, capacity: int | None = None,
-                 adaptive: bool = True, warm_start: bool = False):
+                 adaptive: bool = True, warm_start: bool = False, threshold: float = 0.0):
         self.scene, self.W, self.H = scene, int(W), int(H)
+        # threshold (Laplacian form only): the hard threshold of Eq. 24 applied
+        # to the composited Laplacian before the solve; the non-zero count of
+        # each frame is kept in self.nonzero (device)
+        self.threshold = float(threshold)
+        self.nonzero = None
         # warm_start: each frame's solve starts from the previous frame's image
         # (GDGS_MG_WARM_START) instead of zero; for consecutive views of a
         # moving camera it needs fewer V-cycles to the same tolerance
@@ -463,6 +480,8 @@ class Renderer:
         if scene.nch not in (3, 6):
             raise ValueError("scene.value must have 6 (gradient) or 3 (Laplacian) rows")
         self.laplacian = scene.nch == 3
+        if self.threshold > 0.0 and not self.laplacian:
+            raise ValueError("the threshold applies to the Laplacian form")
         self.mg = mg if mg is not None else mg_params()
         self.max_cycles = int(self.mg.max_cycles)
         self.budget = self.max_cycles
@@ -510,6 +529,8 @@ class Renderer:
         if self.laplacian:
             gdgs_raster_laplacian(self.proj, self.scene.opacity, self.scene.value, K, self.bins,
                                   W, H, self.grad, self.ws_ras, s)
+            if self.threshold > 0.0:
+                self.nonzero = gdgs_threshold(self.grad[:3], self.threshold, stream=s)
         else:
             gdgs_raster_grad(self.proj, self.scene.opacity, self.scene.value, K, self.bins, W, H,
                              self.grad, self.ws_ras, s)

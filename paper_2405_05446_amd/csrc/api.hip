@@ -422,6 +422,18 @@ gdgs_status gdgs_project(const gdgs_scene* scene, const gdgs_camera* cam, const 
     return launch_project(*scene, *cam, *out, as_stream(stream));
 }
 
+gdgs_status gdgs_threshold(float* x, int64_t n, float t, uint64_t* nonzero_dev, void* stream) {
+    clear_error();
+    REQUIRE(n >= 0, "n must be >= 0");
+    REQUIRE(t >= 0.f, "threshold must be >= 0");
+    if (n > 0) REQUIRE_PTR(x);
+    if (nonzero_dev)
+        REQUIRE((reinterpret_cast<uintptr_t>(nonzero_dev) & 7u) == 0,
+                "nonzero_dev is not 8-byte aligned");
+    return launch_threshold(x, n, t, reinterpret_cast<unsigned long long*>(nonzero_dev),
+                            as_stream(stream));
+}
+
 gdgs_status gdgs_image_loss_workspace_size(int32_t W, int32_t H, size_t* bytes) {
     clear_error();
     REQUIRE(bytes != nullptr, "bytes is null");

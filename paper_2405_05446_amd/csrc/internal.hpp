@@ -108,6 +108,8 @@ gdgs_status launch_project_backward(const gdgs_scene& s, const gdgs_camera& cam,
                                     const float* dmean2d, const float* dconic, float* gmean,
                                     float* glog, float* gquat, hipStream_t st);
 size_t loss_ws_bytes(int W, int H);
+gdgs_status launch_threshold(float* x, int64_t n, float t, unsigned long long* nz,
+                             hipStream_t st);
 gdgs_status launch_image_loss(const float* c, const float* im, int W, int H, double lam,
                               double beta, double* out, float* dc, void* ws, hipStream_t st);
 gdgs_status launch_adam(float* p, const float* g, float* m, float* v, int64_t n, int t, float lr,

@@ -1,6 +1,7 @@
 // Image loss of the method's optimisation (GDGS Sec. 2.3 "Loss Function",
 // Eq. 22, evaluated in every iteration of Algorithm 1) and its gradient with
-// respect to the rendered image, plus the Adam update of the parameters.
+// respect to the rendered image, the Adam update of the parameters, and the
+// hard threshold of Sec. 3.1 (Eq. 24).
 //
 // L = (1 - lam) mean|c - im| + beta mean|grad c - grad im| + lam (1 - mean SSIM)
 // with forward differences along columns and rows, and SSIM per colour
@@ -41,6 +42,10 @@ Taps make_taps() {
     }
     for (int i = 0; i < 2 * kLR + 1; ++i) t.w[i] = (float)(v[i] / s);
     return t;
+}
+
+__global__ void k_zero_u64(unsigned long long* p) {
+    if (threadIdx.x == 0) *p = 0ull;
 }
 
 __device__ __forceinline__ double block_sum_d(double x, double* sh) {
@@ -240,7 +245,37 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
     }
 }
 
+// Hard threshold T of Sec. 3.1 (Eq. 24): x if |x| >= t, else 0, in place;
+// counts the values that remain non-zero.
+__global__ void k_threshold(float* __restrict__ x, int64_t n, float t,
+                            unsigned long long* __restrict__ nz) {
+    unsigned long long c = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float v = x[i];
+        const float r = fabsf(v) >= t ? v : 0.f;
+        x[i] = r;
+        c += r != 0.f ? 1ull : 0ull;
+    }
+    for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
+    if (nz && (threadIdx.x & 63) == 0 && c) atomicAdd(nz, c);
+}
+
 }  // namespace
+
+gdgs_status launch_threshold(float* x, int64_t n, float t, unsigned long long* nz,
+                             hipStream_t st) {
+    if (nz) {
+        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, nz);
+    }
+    if (n > 0) {
+        int64_t blocks = (n + 255) / 256;
+        if (blocks > 4096) blocks = 4096;
+        hipLaunchKernelGGL(k_threshold, dim3((unsigned)blocks), dim3(256), 0, st, x, n, t, nz);
+    }
+    GDGS_LAUNCH_CHECK();
+    return GDGS_OK;
+}
 
 size_t loss_ws_bytes(int W, int H) {
     const size_t HW = (size_t)W * H;

@@ -74,3 +74,35 @@ def test_renderer_equals_render_entry_point():
         assert r.last["converged"]
         # same kernels; the resumed path of the Renderer continues bit for bit
         assert (u - u2).abs().max().item() <= 1e-6
+
+
+def test_threshold_kernel_is_exact_and_counts():
+    rng = np.random.default_rng(4)
+    x = rng.laplace(0.0, 0.01, 100003).astype(np.float32)
+    t = np.float32(0.007)
+    g = torch.from_numpy(x).cuda()
+    nz = G.api.gdgs_threshold(g, float(t))
+    torch.cuda.synchronize()
+    ref = np.where(np.abs(x) >= t, x, np.float32(0.0))
+    assert np.array_equal(np_(g), ref)
+    assert int(nz.item()) == int(np.count_nonzero(ref))
+
+
+def test_thresholded_laplacian_render_solves_the_sparse_field():
+    from oracle import poisson as P
+    H, W, K = 60, 90, 3000
+    sc = wl.laplacian_scene(wl.make_scene(K, seed=5, ls=(-3, 0.6)), seed=5)
+    cam = wl.make_camera(W, H, pose_index=4)
+    ds = G.DeviceScene.from_host(sc)
+    proj = G.gdgs_project(ds, cam)
+    bins = G.gdgs_bin_sort(proj, K, W, H, 16 * K)
+    rho = np_(G.api.gdgs_raster_laplacian(proj, ds.opacity, ds.value, K, bins, W, H))
+    t = float(np.float32(0.5 * np.abs(rho).mean()))
+    r = G.Renderer(ds, W, H, G.mg_params(tol=1e-6, max_cycles=40), threshold=t)
+    u = np_(r.render(cam))
+    nz = int(r.nonzero.item())
+    rho_t = np.where(np.abs(rho) >= np.float32(t), rho, np.float32(0.0))
+    ref = P.solve(rho_t.astype(np.float64), None)
+    err = np.abs(u - ref).max()
+    say(f"[laplacian] threshold {t:.3g}: {nz / rho.size:.2%} non-zero, max-abs {err:.2e}")
+    assert nz == int(np.count_nonzero(rho_t)) and err <= TOL

@@ -59,3 +59,19 @@ def test_composite_matches_the_gradient_forms_channels():
     g6 = composite.render_grad(proj, sc.opacity, six, H, W)
     o = render_laplacian(sc, cam)
     assert np.array_equal(g6[:3], o["rho"]) and np.abs(g6[3:]).max() == 0.0
+
+
+def test_hard_threshold_of_eq_24():
+    from oracle.render import threshold
+    x = np.array([-0.5, 0.002, 0.003, -0.003, 0.0, 0.0031])
+    assert np.array_equal(threshold(x, 0.003), np.array([-0.5, 0.0, 0.003, -0.003, 0.0, 0.0031]))
+    assert np.array_equal(threshold(x, 0.0), x)
+    # thresholding the composite before the solve: u solves L u = T(rho)
+    sc = _scene(4)
+    cam = wl.make_camera(W, H, pose_index=3)
+    full = render_laplacian(sc, cam)
+    t = 0.5 * np.abs(full["rho"]).mean()
+    o = render_laplacian(sc, cam, t=t)
+    assert 0 < np.count_nonzero(o["rho"]) < np.count_nonzero(full["rho"])
+    lap = poisson.laplacian(o["u"])
+    assert np.abs(lap[:, 1:-1, 1:-1] - threshold(full["rho"], t)[:, 1:-1, 1:-1]).max() < 1e-10
