@@ -7,8 +7,8 @@ Laplacian(u) = rho (Eq. 16), and in image space Laplacian(c) = rho2D (Eq. 21).
 The paper names direct (Gaussian elimination, LU) and iterative solvers; the
 oracle uses exact direct solves of the discrete system.
 
-Readings where the paper is silent (its boundary condition is Neumann; the
-workloads here fix Dirichlet data instead):
+Readings where the paper is silent (its boundary condition is Neumann, built
+below; the main workloads fix Dirichlet data instead):
 * grid = the H x W pixel grid, spacing 1; unknowns are the (H-2) x (W-2)
   interior pixels, the one-pixel outer ring holds Dirichlet values g;
 * gradients are forward differences, gx[i,j] ~ f[i,j+1] - f[i,j] (channel
@@ -150,3 +150,108 @@ def backward_error(u: np.ndarray, rho: np.ndarray, boundary=None) -> np.ndarray:
     num = np.abs(r).max(axis=(1, 2))
     den = 8.0 * np.abs(w).max(axis=(1, 2)) + np.abs(b).max(axis=(1, 2))
     return num / np.where(den > 0, den, 1.0)
+
+
+# ---------------------------------------------------------------- Neumann
+# The paper's own boundary condition for the reconstruction is Neumann
+# (Sec. 1.5 and Sec. 2.2, Eq. 21), with the image defined up to a constant.
+# Reading used here: every one of the H x W pixels is an unknown and no flux
+# crosses the image border, i.e. the discrete Laplacian at a pixel sums only
+# its neighbours inside the image (these are the normal equations of the
+# least-squares fit of forward-difference gradients, Eq. 13-14, over the
+# differences that lie inside the image).  The system is singular with the
+# constants as null space: rho is replaced by its compatible part (minus its
+# mean) and the solution is fixed by a zero mean per channel.
+
+
+def divergence_neumann(grad: np.ndarray) -> np.ndarray:
+    """rho[3][H][W] on every pixel from grad[6][H][W]: the backward-difference
+    divergence of the forward differences that lie inside the image (gx in
+    the last column and gy in the last row would cross the border: dropped)."""
+    grad = np.asarray(grad, dtype=np.float64)
+    gx = grad[0::2].copy()
+    gy = grad[1::2].copy()
+    gx[:, :, -1] = 0.0
+    gy[:, -1, :] = 0.0
+    rho = gx + gy
+    rho[:, :, 1:] -= gx[:, :, :-1]
+    rho[:, 1:, :] -= gy[:, :-1, :]
+    return rho
+
+
+def laplacian_neumann(u: np.ndarray) -> np.ndarray:
+    """Graph Laplacian of the pixel grid: sum over the neighbours inside the
+    image of (u_neighbour - u), on every pixel of u[C][H][W]."""
+    u = np.asarray(u, dtype=np.float64)
+    out = np.zeros(u.shape)
+    dy = u[:, 1:, :] - u[:, :-1, :]
+    dx = u[:, :, 1:] - u[:, :, :-1]
+    out[:, :-1, :] += dy
+    out[:, 1:, :] -= dy
+    out[:, :, :-1] += dx
+    out[:, :, 1:] -= dx
+    return out
+
+
+def neumann_matrix(H: int, W: int) -> np.ndarray:
+    """Dense -L for the H x W grid with no flux across the border (row-major
+    unknowns): the degree of each pixel on the diagonal, -1 per neighbour."""
+    def path(k):
+        T = 2.0 * np.eye(k) - np.eye(k, k=1) - np.eye(k, k=-1)
+        if k > 0:
+            T[0, 0] -= 1.0
+            T[-1, -1] -= 1.0
+        return T
+    return np.kron(np.eye(H), path(W)) + np.kron(path(H), np.eye(W))
+
+
+def solve_neumann_dense(rho: np.ndarray) -> np.ndarray:
+    """Zero-mean u with L u = rho - mean(rho), per channel, from the bordered
+    system [A 1; 1^T 0] [u; s] = [mean(rho) - rho; 0] (A = -L), by LU."""
+    rho = np.asarray(rho, dtype=np.float64)
+    C, H, W = rho.shape
+    N = H * W
+    K = np.zeros((N + 1, N + 1))
+    K[:N, :N] = neumann_matrix(H, W)
+    K[:N, N] = 1.0
+    K[N, :N] = 1.0
+    lu = scipy.linalg.lu_factor(K)
+    u = np.zeros(rho.shape)
+    for c in range(C):
+        b = np.zeros(N + 1)
+        b[:N] = -(rho[c] - rho[c].mean()).ravel()
+        u[c] = scipy.linalg.lu_solve(lu, b)[:N].reshape(H, W)
+    return u
+
+
+def neumann_eigenvalues(H: int, W: int) -> np.ndarray:
+    """Eigenvalues of -L on the cosine basis cos(pi p (i + 1/2) / H) cos(pi q
+    (j + 1/2) / W): (2 - 2cos(pi p / H)) + (2 - 2cos(pi q / W)), p < H, q < W."""
+    p = np.arange(H)[:, None]
+    q = np.arange(W)[None, :]
+    return (2.0 - 2.0 * np.cos(np.pi * p / H)) + (2.0 - 2.0 * np.cos(np.pi * q / W))
+
+
+def solve_neumann_dct(rho: np.ndarray, workers: int = -1) -> np.ndarray:
+    """Zero-mean u with L u = rho - mean(rho), by diagonalising -L with the
+    type-II discrete cosine transform; the constant mode is set to zero."""
+    rho = np.asarray(rho, dtype=np.float64)
+    C, H, W = rho.shape
+    lam = neumann_eigenvalues(H, W)
+    lam[0, 0] = 1.0
+    u = np.zeros(rho.shape)
+    for c in range(C):
+        bh = scipy.fft.dctn(-rho[c], type=2, norm="ortho", workers=workers)
+        bh /= lam
+        bh[0, 0] = 0.0
+        u[c] = scipy.fft.idctn(bh, type=2, norm="ortho", workers=workers)
+    return u
+
+
+def solve_neumann(rho: np.ndarray) -> np.ndarray:
+    """Exact Neumann solve with zero-mean gauge: dense up to 2500 pixels, DCT
+    beyond."""
+    C, H, W = np.shape(rho)
+    if H * W <= 2500:
+        return solve_neumann_dense(rho)
+    return solve_neumann_dct(rho)
