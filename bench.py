@@ -81,6 +81,8 @@ def parse():
                     help="skip the Algorithm-1 iteration measurement")
     ap.add_argument("--no-trajectory", action="store_true",
                     help="skip the cold/warm-start camera-path measurement")
+    ap.add_argument("--no-neumann", action="store_true",
+                    help="skip the Neumann-condition leg")
     ap.add_argument("--no-laplacian", action="store_true",
                     help="skip the Laplacian-splat form measurement")
     ap.add_argument("--serve-requests", type=int, default=256)
@@ -206,6 +208,33 @@ def laplacian_leg(G, wl, torch, scene, cams, ring, mg, W, H, frames: int):
                       for i in range(frames)]).mean(0)
     return {"workload": f"Laplacian splats (3 values each), {W}x{H}, {sc.opacity.shape[0]} "
                         "splats, same poses and solver",
+            "Mpix_s": round(H * W / (ms * 1e-3) / 1e6, 2), "ms_per_frame": round(ms, 4),
+            "frames": frames,
+            "stages_ms": {n: round(float(v), 4)
+                          for n, v in zip(("project", "bin_sort", "raster", "poisson"), stage)},
+            "mg_cycles_mean": float(np.mean([c for c, _ in cyc])),
+            "not_converged": int(sum(1 for _, ok in cyc if not ok))}
+
+
+def neumann_leg(G, wl, torch, ds, cams, mg, W, H, frames: int):
+    """The paper's boundary condition for Eq. 21: no flux across the image
+    border, every pixel unknown, zero-mean image (GDGS_MG_NEUMANN), on the same
+    gradient splats and poses as the headline figure.  Frames as a sequence."""
+    r = G.Renderer(ds, W, H, mg, neumann=True)
+    r.render(cams[0])
+    seq = [cams[i % len(cams)] for i in range(frames)]
+    r.render_sequence(seq[:5])
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(frames)]
+    cyc = []
+    t0 = time.perf_counter()
+    r.render_sequence(seq, events=ev,
+                      on_frame=lambda i, u, st: cyc.append((st["total_cycles"], st["converged"])))
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / frames
+    stage = np.array([[ev[i][k].elapsed_time(ev[i][k + 1]) for k in range(4)]
+                      for i in range(frames)]).mean(0)
+    return {"workload": f"Neumann condition, {W}x{H}, {ds.K} gradient splats, same poses",
             "Mpix_s": round(H * W / (ms * 1e-3) / 1e6, 2), "ms_per_frame": round(ms, 4),
             "frames": frames,
             "stages_ms": {n: round(float(v), 4)
@@ -405,7 +434,7 @@ def main():
     ch_per_launch = 3.0 * mean_cycles / post_launches
     post_bytes = MG_POST_BYTES_PER_POINT * ch_per_launch * npts
     post_gbs = post_bytes / (post_us * 1e-6) / 1e9
-    k_raster, k_post = "k_raster_fwd<false>", "k_fine_post<2>"
+    k_raster, k_post = "k_raster_fwd<false>", "k_fine_post<2, false>"
     t_raster, t_post = measured_traffic(k_raster), measured_traffic(k_post)
     kern = {
         "raster": {"kernel": k_raster, "bound": "alu", "achieved": round(raster_tflops, 3),
@@ -471,6 +500,8 @@ def main():
         out["train_step"] = train_leg(G, wl, torch, 10)
     if not args.no_trajectory:
         out["trajectory"] = trajectory_leg(G, wl, torch, ds, ring, mg, W, H, min(args.steps, 50))
+    if not args.no_neumann:
+        out["neumann"] = neumann_leg(G, wl, torch, ds, cams, mg, W, H, min(args.steps, 50))
     if not args.no_laplacian:
         out["laplacian_form"] = laplacian_leg(G, wl, torch, scene, cams, ring, mg, W, H,
                                               min(args.steps, 50))

@@ -119,13 +119,27 @@ typedef struct gdgs_bins {
  * written to them since.  Calls totalling n cycles give bit for bit the
  * result of one call with max_cycles = n. */
 #define GDGS_MG_RESUME 2
+/* flags: the paper's Neumann condition (Sec. 1.5 and Sec. 2.2, Eq. 21)
+ * instead of Dirichlet data on the image ring.  Every one of the H x W pixels
+ * is an unknown and no flux crosses the image border: the Laplacian at a
+ * pixel sums only its neighbours inside the image, and with gradients the
+ * divergence drops the differences that would cross the border (gx in the
+ * last column, gy in the last row).  The problem is singular: rho is replaced
+ * by rho - mean(rho) per channel and u is returned with zero mean per
+ * channel.  boundary must be NULL.  The finest grid lives in the workspace
+ * (padded), so the workspace is larger than for the Dirichlet problem;
+ * GDGS_MG_WARM_START reads the caller's u as the starting image, and
+ * GDGS_MG_RESUME continues from the workspace.  stats: b = mean(rho) - rho
+ * over all pixels, and the residual norms are over all pixels.  Not
+ * available to the server or the differentiable solve. */
+#define GDGS_MG_NEUMANN 4
 typedef struct gdgs_mg_params {
     int32_t levels;        /* grids including the finest, >= 1; 0 = as many as the size allows, at most 8 */
     int32_t pre_sweeps;    /* red-black Gauss-Seidel sweeps before restriction, 1..2 */
     int32_t post_sweeps;   /* sweeps after prolongation, 1..2 */
     int32_t max_cycles;    /* V-cycle limit, 1..64 */
     int32_t coarse_sweeps; /* SOR sweeps on the coarsest grid; 0 = automatic */
-    int32_t flags;         /* GDGS_MG_WARM_START, GDGS_MG_RESUME or 0 */
+    int32_t flags;         /* GDGS_MG_WARM_START, GDGS_MG_RESUME, GDGS_MG_NEUMANN (or-ed) or 0 */
     double tol;            /* relative-correction tolerance (see above); 0 runs max_cycles */
 } gdgs_mg_params;
 

@@ -50,6 +50,7 @@ def camera_struct(cam) -> L.Camera:
 
 WARM_START = 1
 RESUME = 2
+NEUMANN = 4  # no flux across the image border, zero-mean image (boundary must be None)
 
 
 def mg_params(levels: int = 0, pre: int = 2, post: int = 2, max_cycles: int = 20,
@@ -463,7 +464,8 @@ class Renderer:
     """
 
     def __init__(self, scene: DeviceScene, W: int, H: int, mg=None, capacity: int | None = None,
-                 adaptive: bool = True, warm_start: bool = False, threshold: float = 0.0):
+                 adaptive: bool = True, warm_start: bool = False, threshold: float = 0.0,
+                 neumann: bool = False):
         self.scene, self.W, self.H = scene, int(W), int(H)
         # threshold (Laplacian form only): the hard threshold of Eq. 24 applied
         # to the composited Laplacian before the solve; the non-zero count of
@@ -483,6 +485,9 @@ class Renderer:
         if self.threshold > 0.0 and not self.laplacian:
             raise ValueError("the threshold applies to the Laplacian form")
         self.mg = mg if mg is not None else mg_params()
+        # neumann: the paper's boundary condition (GDGS_MG_NEUMANN) instead of
+        # Dirichlet data on the image ring; boundary must then be None
+        self.neumann = bool(neumann) or bool(self.mg.flags & NEUMANN)
         self.max_cycles = int(self.mg.max_cycles)
         self.budget = self.max_cycles
         self.adaptive = adaptive
@@ -495,7 +500,7 @@ class Renderer:
         lib = L.load()
         self.ws_ras = workspace(_size(lib.gdgs_raster_workspace_size, K), self.dev)
         self.ws_poi = workspace(_size(lib.gdgs_poisson_workspace_size, self.W, self.H,
-                                      ctypes.byref(self.mg)), self.dev)
+                                      ctypes.byref(self._mg(self.max_cycles))), self.dev)
         self._set_capacity(capacity if capacity is not None else max(1 << 16, 16 * K))
         self.last = None
 
@@ -509,7 +514,7 @@ class Renderer:
     def _mg(self, cycles: int, flags: int = 0) -> L.MgParams:
         m = self.mg
         return mg_params(m.levels, m.pre_sweeps, m.post_sweeps, cycles, m.tol, m.coarse_sweeps,
-                         flags)
+                         flags | (NEUMANN if self.neumann else 0))
 
     def _enqueue(self, cam, boundary, events, stream):
         """Enqueue one frame (no waiting): the four steps, then an asynchronous
@@ -600,7 +605,7 @@ class Renderer:
         the last bits."""
         if not hasattr(self, "_twin"):
             self._twin = Renderer(self.scene, self.W, self.H, self.mg, self.capacity,
-                                  self.adaptive, self.warm_start)
+                                  self.adaptive, self.warm_start, self.threshold, self.neumann)
         rs = [self, self._twin]
         prev = None
         for i, cam in enumerate(cams):

@@ -23,6 +23,15 @@ import torch
 from . import api as A
 
 
+def _dirichlet_only(mg):
+    """The reverse chain here is that of the Dirichlet problem (the adjoint of
+    the interior divergence); the Neumann solve is not differentiated."""
+    mg = mg if mg is not None else A.mg_params()
+    if mg.flags & A.NEUMANN:
+        raise ValueError("the differentiable render supports the Dirichlet problem only")
+    return mg
+
+
 class GDGSRenderFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, mean2d, conic, opacity, value, depth, W: int, H: int, boundary=None,
@@ -33,7 +42,7 @@ class GDGSRenderFn(torch.autograd.Function):
         opacity = opacity.detach().contiguous()
         value = value.detach().contiguous()
         depth = depth.detach().contiguous()
-        mg = mg if mg is not None else A.mg_params()
+        mg = _dirichlet_only(mg)
         proj = A.gdgs_project_2d(mean2d, conic, depth, W, H)
         cap = int(capacity if capacity is not None else max(1 << 16, 16 * K))
         bins = A.gdgs_bin_sort(proj, K, W, H, cap)
@@ -74,7 +83,7 @@ class GDGSRender3DFn(torch.autograd.Function):
                            quat.detach().contiguous(), opacity.detach().contiguous(),
                            value.detach().contiguous())
         K = ds.K
-        mg = mg if mg is not None else A.mg_params()
+        mg = _dirichlet_only(mg)
         proj = A.gdgs_project(ds, cam)
         cap = int(capacity if capacity is not None else max(1 << 16, 16 * K))
         bins = A.gdgs_bin_sort(proj, K, W, H, cap)

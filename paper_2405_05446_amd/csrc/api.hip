@@ -268,7 +268,7 @@ gdgs_status launch_render_stats(const int64_t* num_pairs, int64_t cap, gdgs_stat
 
 void add_plan(KeyBuilder& kb, const MgPlan& p) {
     kb.add(p.levels).add(p.lc).add(p.pre).add(p.post).add(p.max_cycles).add(p.coarse_sweeps)
-        .add(p.omega).add(p.tol).add(p.warm).add(p.resume).add(p.lds_bytes);
+        .add(p.omega).add(p.tol).add(p.warm).add(p.resume).add(p.neumann).add(p.lds_bytes);
     for (int l = 0; l < p.levels; ++l) kb.add(p.n[l]).add(p.m[l]).add(p.pitch[l]);
 }
 
@@ -603,6 +603,7 @@ static gdgs_status poisson_common(const float* grad, const float* rho, const flo
                            "stats_dev not 8-byte aligned");
     MgPlan plan;
     TRY(mg_plan(W, H, mg, &plan));
+    REQUIRE(!(plan.neumann && boundary), "the Neumann problem takes no boundary data");
     TRY(check_ws(ws, ws_bytes, poisson_ws_bytes(plan, W, H)));
     KeyBuilder kb;
     kb.tag("poisson").add(grad).add(rho).add(boundary).add(W).add(H).add(u).add(stats_dev).add(ws);
@@ -656,6 +657,7 @@ static gdgs_status render_common(const gdgs_scene* scene, const gdgs_camera* cam
     const int W = cam->W, H = cam->H;
     MgPlan plan;
     TRY(mg_plan(W, H, mg, &plan));
+    REQUIRE(!(plan.neumann && boundary), "the Neumann problem takes no boundary data");
     TRY(check_ws(ws, ws_bytes, render_layout(K, W, H, pair_capacity, plan, nullptr, nullptr)));
     RenderWs r;
     render_layout(K, W, H, pair_capacity, plan, ws, &r);

@@ -74,11 +74,34 @@ struct LevelDev {
     long long cs;    // channel stride (floats)
     float ey, ex;    // extra diagonal on the last interior row / column (1/delta - 1)
     float wy, wx;    // prolongation weight onto a fine point beyond the last row / column
+    // Neumann, finest grid: per channel, the mean that the FP32 right-hand side
+    // keeps after centring (below its rounding); subtracted from every FP64
+    // residual so that the residual has zero sum, as the singular coarse
+    // problems need.  Null otherwise.
+    const double* fofs;
 };
 
+// Neumann boundary terms, the same on every grid (kernels take them under
+// their compile-time switch NM; the Dirichlet problem has none).  A pixel on
+// the border has one neighbour fewer: the diagonal drops by one per missing
+// neighbour.  Coarse point I sits on fine point 2I, so the first fine point
+// (and the last one when the count n is odd) lies outside the coarse points
+// and takes the nearest one's value (prolongation weight 1); restriction is
+// the transpose of that prolongation, i.e. the residual of such a point counts
+// twice in full weighting, which keeps the sum of the coarse right-hand side
+// equal to the sum of the fine residual.
+constexpr float kNmDiag = -1.f;  // extra diagonal on a first or last row / column
+constexpr float kNmW = 1.f;      // prolongation weight onto a fine point outside the coarse points
+__device__ __forceinline__ float nm_scale(int g, int n) {
+    return (g == 1 || (g == n && (n & 1))) ? 2.f : 1.f;
+}
+
 // Diagonal of the (possibly boundary-modified) 5-point operator at (gi, gj).
-__device__ __forceinline__ float diag_at(int gi, int gj, int n, int m, float ey, float ex) {
+__device__ __forceinline__ float diag_at(int gi, int gj, int n, int m, float ey, float ex,
+                                         float ey0, float ex0) {
     float d = 4.f;
+    if (gi == 1) d += ey0;
+    if (gj == 1) d += ex0;
     if (gi == n) d += ey;
     if (gj == m) d += ex;
     return d;
@@ -102,6 +125,7 @@ struct LdsPlan {
     int lw;                // levels lw .. L-1 are run by one wave (lw == L: none)
     int n[kMaxLevels], m[kMaxLevels];
     float ey[kMaxLevels], ex[kMaxLevels], wy[kMaxLevels], wx[kMaxLevels];
+    const double* fofs;    // offset of the finest grid's residual (see LevelDev), or null
     int off[kMaxLevels];   // float offset of u_l in LDS; f_l follows u_l
     int roff[kMaxLevels];  // float offset of the residual of level l (l < L-1)
     uint32_t mg_m[kMaxLevels], mg_h[kMaxLevels];  // division magics for m and (m+1)/2
@@ -237,6 +261,158 @@ __global__ __launch_bounds__(256) void k_setup_finalize(const double* __restrict
     }
 }
 
+// ---------------------------------------------------------------- Neumann set-up and gauge
+// The Neumann problem keeps its finest grid in padded workspace arrays: pixel
+// (i, j) at (i + 1, j + 1), a zero ring around the H x W pixels.  The kernels
+// below cover the padded grid with the block shape of k_div_init.
+
+// Sum of a block's doubles into thread 0 (any block size that is a multiple of 64).
+__device__ double block_sum(double v, double* sh /*[3 * nwaves]*/) {
+    double a = 0.0, b = 0.0;
+    block_reduce3(a, b, v, sh);
+    return v;
+}
+
+// rho on every pixel (the backward-difference divergence of the forward
+// differences inside the image, or given), f0 = rho, u0 = 0 or the caller's
+// image, zero rings in u0, u0b and f0; per-block sum of rho.
+__global__ __launch_bounds__(kDivTX* kDivTY) void k_nm_init(
+    const float* __restrict__ grad, const float* __restrict__ rho_in,
+    const float* __restrict__ uprev, int H, int W, int pitch, float* __restrict__ f0,
+    float* __restrict__ u0, float* __restrict__ u0b, double* __restrict__ bpart,
+    int* __restrict__ counters) {
+    __shared__ double sh[3 * 4];
+    const int c = blockIdx.z;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && c == 0 && threadIdx.x < kCounters)
+        counters[threadIdx.x] = 0;
+    const int pj = blockIdx.x * kDivTX + (threadIdx.x % kDivTX);
+    const size_t HW = (size_t)H * W, cs = (size_t)(H + 2) * pitch;
+    double sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < kDivRows / kDivTY; ++k) {
+        const int pi = blockIdx.y * kDivRows + k * kDivTY + (threadIdx.x / kDivTX);
+        if (pi >= H + 2 || pj >= W + 2) continue;
+        const size_t po = (size_t)c * cs + (size_t)pi * pitch + pj;
+        const int i = pi - 1, j = pj - 1;
+        if (i < 0 || i >= H || j < 0 || j >= W) {
+            f0[po] = 0.f;
+            u0[po] = 0.f;
+            u0b[po] = 0.f;
+            continue;
+        }
+        const size_t p = (size_t)i * W + j;
+        float rho;
+        if (grad) {
+            const float* gx = grad + (size_t)(2 * c) * HW;
+            const float* gy = grad + (size_t)(2 * c + 1) * HW;
+            const float ax = j < W - 1 ? gx[p] : 0.f, bx = j > 0 ? gx[p - 1] : 0.f;
+            const float ay = i < H - 1 ? gy[p] : 0.f, by = i > 0 ? gy[p - W] : 0.f;
+            rho = (ax - bx) + (ay - by);
+        } else {
+            rho = rho_in[(size_t)c * HW + p];
+        }
+        f0[po] = rho;
+        u0[po] = uprev ? uprev[(size_t)c * HW + p] : 0.f;
+        sum += (double)rho;
+    }
+    sum = block_sum(sum, sh);
+    if (threadIdx.x == 0) {
+        const int nblk = gridDim.x * gridDim.y;
+        bpart[((size_t)c * nblk + blockIdx.y * gridDim.x + blockIdx.x) * 2] = sum;
+    }
+}
+
+// One block per channel: out[c] = scale * (sum of the per-block values, which
+// are stride doubles apart).
+__global__ __launch_bounds__(256) void k_nm_mean(const double* __restrict__ bpart, int nblk,
+                                                 int stride, double scale,
+                                                 double* __restrict__ out) {
+    __shared__ double sh[3 * 4];
+    const int c = blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+        s += bpart[((size_t)c * nblk + b) * stride];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) out[c] = s * scale;
+}
+
+// f0 <- f0 - mean (the compatible part of rho, to FP32 rounding); per-block
+// max|b| and sum b^2 of b = mean - rho (the form k_setup_finalize reduces), and
+// the per-block sum of the centred FP32 values (spart).
+__global__ __launch_bounds__(kDivTX* kDivTY) void k_nm_center(float* __restrict__ f0, int H,
+                                                              int W, int pitch,
+                                                              const double* __restrict__ mean,
+                                                              double* __restrict__ bpart,
+                                                              double* __restrict__ spart) {
+    __shared__ double sh[3 * 4];
+    const int c = blockIdx.z;
+    const int pj = blockIdx.x * kDivTX + (threadIdx.x % kDivTX);
+    const size_t cs = (size_t)(H + 2) * pitch;
+    const float mu = (float)mean[c];
+    double bmax = 0.0, bdum = 0.0, bss = 0.0;
+#pragma unroll
+    for (int k = 0; k < kDivRows / kDivTY; ++k) {
+        const int pi = blockIdx.y * kDivRows + k * kDivTY + (threadIdx.x / kDivTX);
+        if (pi < 1 || pi > H || pj < 1 || pj > W) continue;
+        float* f = f0 + (size_t)c * cs + (size_t)pi * pitch + pj;
+        const float v = *f - mu;
+        *f = v;
+        bmax = fmax(bmax, fabs((double)v));
+        bss += (double)v * (double)v;
+        bdum += (double)v;
+    }
+    double x0 = 0.0;
+    block_reduce3(bmax, x0, bss, sh);
+    bdum = block_sum(bdum, sh);
+    if (threadIdx.x == 0) {
+        const int nblk = gridDim.x * gridDim.y;
+        const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+        bpart[((size_t)c * nblk + blk) * 2] = bmax;
+        bpart[((size_t)c * nblk + blk) * 2 + 1] = bss;
+        spart[(size_t)c * nblk + blk] = bdum;
+    }
+}
+
+// Per-block sum of the solution over the pixels.
+__global__ __launch_bounds__(kDivTX* kDivTY) void k_nm_usum(const float* __restrict__ u0, int H,
+                                                            int W, int pitch,
+                                                            double* __restrict__ bpart) {
+    __shared__ double sh[3 * 4];
+    const int c = blockIdx.z;
+    const int pj = blockIdx.x * kDivTX + (threadIdx.x % kDivTX);
+    const size_t cs = (size_t)(H + 2) * pitch;
+    double sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < kDivRows / kDivTY; ++k) {
+        const int pi = blockIdx.y * kDivRows + k * kDivTY + (threadIdx.x / kDivTX);
+        if (pi < 1 || pi > H || pj < 1 || pj > W) continue;
+        sum += (double)u0[(size_t)c * cs + (size_t)pi * pitch + pj];
+    }
+    sum = block_sum(sum, sh);
+    if (threadIdx.x == 0) {
+        const int nblk = gridDim.x * gridDim.y;
+        bpart[((size_t)c * nblk + blockIdx.y * gridDim.x + blockIdx.x) * 2] = sum;
+    }
+}
+
+// The caller's image: the pixels of the padded solution minus its mean.
+__global__ __launch_bounds__(kDivTX* kDivTY) void k_nm_out(const float* __restrict__ u0, int H,
+                                                           int W, int pitch,
+                                                           const double* __restrict__ mean,
+                                                           float* __restrict__ u) {
+    const int c = blockIdx.z;
+    const int j = blockIdx.x * kDivTX + (threadIdx.x % kDivTX);
+    const size_t cs = (size_t)(H + 2) * pitch, HW = (size_t)H * W;
+    const float mu = (float)mean[c];
+#pragma unroll
+    for (int k = 0; k < kDivRows / kDivTY; ++k) {
+        const int i = blockIdx.y * kDivRows + k * kDivTY + (threadIdx.x / kDivTX);
+        if (i >= H || j >= W) continue;
+        u[(size_t)c * HW + (size_t)i * W + j] =
+            u0[(size_t)c * cs + (size_t)(i + 1) * pitch + j + 1] - mu;
+    }
+}
+
 // Start of a resumed solve: only the per-call finalize counters restart.
 __global__ void k_resume(int* __restrict__ counters) {
     if (threadIdx.x < kCounters) counters[threadIdx.x] = 0;
@@ -250,10 +426,11 @@ __global__ void k_resume(int* __restrict__ counters) {
 // thread's points before it stores any (points of one colour read only the
 // other colour); a slot off the row reads cell (1, 1) and stores to the
 // thread's trash cell, so no access is conditional.
-template <int RX, int RY, int NT>
+template <int RX, int RY, int NT, bool NM>
 __device__ __forceinline__ void smooth_rows(float* __restrict__ su, const float* __restrict__ sf,
-                                            float* trash, int gi0, int gj0, int n, int m,
-                                            float ey, float ex, int color0, int sweeps) {
+                                            float* trash, int gi0, int gj0, const LevelDev& L,
+                                            int color0, int sweeps) {
+    const int n = L.n, m = L.m;
     constexpr int NR = RY - 2;
     constexpr int TPR = NT / NR;
     constexpr int KR = ((RX - 1) / 2 + TPR - 1) / TPR;
@@ -262,8 +439,9 @@ __device__ __forceinline__ void smooth_rows(float* __restrict__ su, const float*
     const int gi = gi0 + r;
     const bool row_ok = (t < NR * TPR) && gi >= 1 && gi <= n;
     const int qlo = max(1, 1 - gj0), qhi = min(RX - 2, m - gj0);
-    const int qm = m - gj0;  // local column of the last interior column
-    const float drow = 4.f + (gi == n ? ey : 0.f);
+    const int qm = m - gj0, q1 = 1 - gj0;  // local columns of the last / first interior column
+    float drow = 4.f + (gi == n ? L.ey : 0.f);
+    if (NM && gi == 1) drow += kNmDiag;
     int ro[2][KR];
     float* wo[2][KR];
     float rd[2][KR];
@@ -276,7 +454,9 @@ __device__ __forceinline__ void smooth_rows(float* __restrict__ su, const float*
             const bool ok = row_ok && q <= qhi;
             ro[c][k] = ok ? r * RX + q : RX + 1;
             wo[c][k] = ok ? su + r * RX + q : trash;
-            rd[c][k] = 1.f / (q == qm ? drow + ex : drow);
+            float dq = q == qm ? drow + L.ex : drow;
+            if (NM && q == q1) dq += kNmDiag;
+            rd[c][k] = 1.f / dq;
         }
     }
     auto half = [&](const int* o, float* const* w, const float* d) {
@@ -362,7 +542,7 @@ struct TileId {
 // FP64; coarser grids carry small corrections and stay in FP32.  A finished
 // channel returns at once on the finest grid; on coarser grids, whose blocks
 // are few and latency-bound, the done flag is read together with the tile.
-template <int NU, bool FINE, int TX, int TY, int NT>
+template <int NU, bool FINE, int TX, int TY, int NT, bool NM>
 __global__ __launch_bounds__(NT) void k_mg_pre(LevelDev L, LevelDev C, int zero_guess,
                                                 const int* __restrict__ done,
                                                 double* __restrict__ part, int c0) {
@@ -394,8 +574,7 @@ __global__ __launch_bounds__(NT) void k_mg_pre(LevelDev L, LevelDev C, int zero_
         }
         __syncthreads();  // every snapshot is taken before any cell changes
     }
-    smooth_rows<RX, RY, NT>(su, sf, s_trash + threadIdx.x, gi0, gj0, L.n, L.m, L.ey, L.ex, 0,
-                            NU);
+    smooth_rows<RX, RY, NT, NM>(su, sf, s_trash + threadIdx.x, gi0, gj0, L, 0, NU);
     const int N = L.n + 2, M = L.m + 2;
     float* u = L.ub + (size_t)c * L.cs;
     double dmax = 0.0;
@@ -422,7 +601,9 @@ __global__ __launch_bounds__(NT) void k_mg_pre(LevelDev L, LevelDev C, int zero_
         const int r = HALO - 1 + t / TPR;
         const int gi = gi0 + r;
         const bool row_in = t < ZR * TPR && gi >= 1 && gi <= L.n;
-        const float drow = 4.f + (gi == L.n ? L.ey : 0.f);
+        float drow = 4.f + (gi == L.n ? L.ey : 0.f);
+        if (NM && gi == 1) drow += kNmDiag;
+        const float srow = NM ? nm_scale(gi, L.n) : 1.f;
         float rv[KZ];
         float* dst[KZ];
 #pragma unroll
@@ -432,14 +613,15 @@ __global__ __launch_bounds__(NT) void k_mg_pre(LevelDev L, LevelDev C, int zero_
             const bool live = t < ZR * TPR && q < HALO - 1 + ZC;
             const bool in = live && row_in && gj >= 1 && gj <= L.m;
             const int o = live ? r * RX + q : RX + 1;
-            const float d = gj == L.m ? drow + L.ex : drow;
+            float d = gj == L.m ? drow + L.ex : drow;
+            if (NM && gj == 1) d += kNmDiag;
             float v;
             if (FINE)
                 v = (float)res_value(su[o - RX], su[o + RX], su[o - 1], su[o + 1], su[o], sf[o],
                                      d);
             else
                 v = sf[o] - (((su[o - RX] + su[o + RX]) + (su[o - 1] + su[o + 1])) - d * su[o]);
-            rv[k] = in ? v : 0.f;
+            rv[k] = in ? (NM ? v * (srow * nm_scale(gj, L.m)) : v) : 0.f;
             dst[k] = live ? sf + o : s_trash + t;
         }
 #pragma unroll
@@ -470,7 +652,7 @@ __global__ __launch_bounds__(NT) void k_mg_pre(LevelDev L, LevelDev C, int zero_
 // Prolongation + correction + post-smoothing.  FINE (the finest grid only):
 // also the residual and correction norms of the cycle.  The done flag is
 // handled as in k_mg_pre.
-template <int NU, bool FINE, int TX, int TY, int NT>
+template <int NU, bool FINE, int TX, int TY, int NT, bool NM>
 __global__ __launch_bounds__(NT) void k_mg_post(LevelDev L, LevelDev C,
                                                  const int* __restrict__ done,
                                                  double* __restrict__ part, int c0) {
@@ -548,8 +730,8 @@ __global__ __launch_bounds__(NT) void k_mg_post(LevelDev L, LevelDev C,
             if (oi) w += pa;
             if (oj) w += pb;
             if (oi & oj) w += pc;
-            const float fy = oi ? (I0 == C.n ? C.wy : 0.5f) : 1.f;
-            const float fx = oj ? (J0 == C.m ? C.wx : 0.5f) : 1.f;
+            const float fy = oi ? ((NM && I0 == 0) ? kNmW : (I0 == C.n ? C.wy : 0.5f)) : 1.f;
+            const float fx = oj ? ((NM && J0 == 0) ? kNmW : (J0 == C.m ? C.wx : 0.5f)) : 1.f;
             v[k] = su[idx] + fy * fx * w;
             dst[k] = (live && in) ? su + idx : s_trash + threadIdx.x;
         }
@@ -557,8 +739,7 @@ __global__ __launch_bounds__(NT) void k_mg_post(LevelDev L, LevelDev C,
         for (int k = 0; k < NI; ++k) *dst[k] = v[k];
     }
     __syncthreads();
-    smooth_rows<RX, RY, NT>(su, sf, s_trash + threadIdx.x, gi0, gj0, L.n, L.m, L.ey, L.ex, 1,
-                            NU);
+    smooth_rows<RX, RY, NT, NM>(su, sf, s_trash + threadIdx.x, gi0, gj0, L, 1, NU);
     float* u = L.u + (size_t)c * L.cs;
     const int N = L.n + 2, M = L.m + 2;
     double rmax = 0.0, umax = 0.0, rss = 0.0, dmax = 0.0;
@@ -575,7 +756,8 @@ __global__ __launch_bounds__(NT) void k_mg_post(LevelDev L, LevelDev C,
             if (NORM) {
                 dmax = fmax(dmax, fabs((double)uv - (double)before[k]));
                 const double rv = res_value(su[o - RX], su[o + RX], su[o - 1], su[o + 1], uv,
-                                            sf[o], diag_at(gi, gj, L.n, L.m, L.ey, L.ex));
+                                            sf[o], diag_at(gi, gj, L.n, L.m, L.ey, L.ex,
+                                                           NM ? kNmDiag : 0.f, NM ? kNmDiag : 0.f));
                 rmax = fmax(rmax, fabs(rv));
                 umax = fmax(umax, fabs((double)uv));
                 rss += rv * rv;
@@ -645,9 +827,11 @@ struct Strip {
         r0 = w * kSWR;
         je = gj0 + 2 * lane;
     }
-    // the region and its outer ghost rows hold interior points only
+    // the region and its outer ghost rows hold interior points only, and the
+    // region holds no first or last interior row or column (whose diagonal and
+    // transfer weights may differ)
     __device__ bool interior(const LevelDev& L) const {
-        return gi0 - 1 >= 1 && gi0 + kSR <= L.n && gj0 >= 1 && gj0 + kSW - 1 <= L.m;
+        return gi0 - 1 >= 1 && gi0 + kSR <= L.n && gj0 >= 2 && gj0 + kSW <= L.m;
     }
     __device__ int slot(int ntiles) const { return (c * ntiles + tile) * kSNW + w; }
 };
@@ -702,42 +886,68 @@ __device__ __forceinline__ void strip_exchange(float (&e)[kSWR + 2], float (&o)[
     }
 }
 
+// Diagonal of the lane's even (e) and odd (o) column on a middle and on the
+// last (l) interior row, with their reciprocals, for boundary blocks.  NM:
+// the Neumann problem, whose first row has one neighbour fewer as well (the
+// finest grid has n >= 3 rows, so no row is both first and last); otherwise
+// the first row is a middle row, known at compile time.
+template <bool NM>
 struct StripDiag {
-    float de, dd, dn_e, dn_o, rde, rdo, rde_n, rdo_n;
+    float de, dd, dl_e, dl_o;
+    float rde, rdo, rdl_e, rdl_o, rdf_e, rdf_o;
+    int n;
     bool ine, ino;
     __device__ StripDiag(const LevelDev& L, const Strip& S) {
         const int jo = S.je + 1;
+        n = L.n;
         ine = S.je >= 1 && S.je <= L.m;
         ino = jo >= 1 && jo <= L.m;
         de = 4.f + (S.je == L.m ? L.ex : 0.f);
         dd = 4.f + (jo == L.m ? L.ex : 0.f);
-        dn_e = de + L.ey;
-        dn_o = dd + L.ey;
+        if (NM) {
+            if (S.je == 1) de += kNmDiag;
+            if (jo == 1) dd += kNmDiag;
+        }
+        dl_e = de + L.ey;
+        dl_o = dd + L.ey;
         rde = 1.f / de;
         rdo = 1.f / dd;
-        rde_n = 1.f / dn_e;
-        rdo_n = 1.f / dn_o;
+        rdl_e = 1.f / dl_e;
+        rdl_o = 1.f / dl_o;
+        rdf_e = NM ? 1.f / (de + kNmDiag) : 0.f;
+        rdf_o = NM ? 1.f / (dd + kNmDiag) : 0.f;
+    }
+    __device__ float diag_e(int gi) const {
+        return (NM && gi == 1) ? de + kNmDiag : (gi == n ? dl_e : de);
+    }
+    __device__ float diag_o(int gi) const {
+        return (NM && gi == 1) ? dd + kNmDiag : (gi == n ? dl_o : dd);
+    }
+    __device__ float rdiag_e(int gi) const {
+        return (NM && gi == 1) ? rdf_e : (gi == n ? rdl_e : rde);
+    }
+    __device__ float rdiag_o(int gi) const {
+        return (NM && gi == 1) ? rdf_o : (gi == n ? rdl_o : rdo);
     }
 };
 
 // Red-black half-sweep of colour col (0 red: i + j even) over the wave's own
 // rows; in a row exactly one of e, o has the colour.
-template <bool INT>
+template <bool INT, bool NM>
 __device__ __forceinline__ void strip_half(float (&e)[kSWR + 2], float (&o)[kSWR + 2],
                                            const float (&fe)[kSWR], const float (&fo)[kSWR],
                                            int col, const Strip& S, const LevelDev& L,
-                                           const StripDiag& D) {
+                                           const StripDiag<NM>& D) {
 #pragma unroll
     for (int q = 1; q <= kSWR; ++q) {
         const int gi = S.gi0 + S.r0 + q - 1;  // parity that of q - 1
         const bool upd = INT || (gi >= 1 && gi <= L.n);
-        const bool last = !INT && gi == L.n;
         if (((q - 1 + col) & 1) == 0) {  // even column has the colour
             const float x = ((e[q - 1] + e[q + 1]) + (from_left(o[q]) + o[q])) - fe[q - 1];
             if (INT) {
                 e[q] = x * 0.25f;
             } else {
-                const float v = x * (last ? D.rde_n : D.rde);
+                const float v = x * D.rdiag_e(gi);
                 e[q] = (upd && D.ine) ? v : e[q];
             }
         } else {
@@ -745,29 +955,30 @@ __device__ __forceinline__ void strip_half(float (&e)[kSWR + 2], float (&o)[kSWR
             if (INT) {
                 o[q] = x * 0.25f;
             } else {
-                const float v = x * (last ? D.rdo_n : D.rdo);
+                const float v = x * D.rdiag_o(gi);
                 o[q] = (upd && D.ino) ? v : o[q];
             }
         }
     }
 }
 
-// FP64 residuals of the even- and odd-column points of own row q.
-template <bool INT>
+// FP64 residuals of the even- and odd-column points of own row q (grid row gi).
+template <bool INT, bool NM>
 __device__ __forceinline__ void strip_residual(const float (&e)[kSWR + 2],
                                                const float (&o)[kSWR + 2], float fe_q, float fo_q,
-                                               int q, bool last, const StripDiag& D, double& re,
-                                               double& ro) {
+                                               int q, int gi, const StripDiag<NM>& D, double ofs,
+                                               double& re, double& ro) {
     re = res_value(e[q - 1], e[q + 1], from_left(o[q]), o[q], e[q], fe_q,
-                   INT ? 4.f : (last ? D.dn_e : D.de));
+                   INT ? 4.f : D.diag_e(gi)) - ofs;
     ro = res_value(o[q - 1], o[q + 1], e[q], from_right(e[q]), o[q], fo_q,
-                   INT ? 4.f : (last ? D.dn_o : D.dd));
+                   INT ? 4.f : D.diag_o(gi)) - ofs;
 }
 
-template <int NU, bool INT>
+template <int NU, bool INT, bool NM>
 __device__ __forceinline__ void fine_pre_body(const LevelDev& L, const LevelDev& C,
                                               double* __restrict__ part, int ntiles,
                                               const Strip& S, float2 (*sx)[kSNW][2][64]) {
+    const double ofs = NM ? L.fofs[S.c] : 0.0;
     float e[kSWR + 2], o[kSWR + 2], fe[kSWR], fo[kSWR], be[kSWR], bo[kSWR];
     strip_load<INT, kSWR + 2>(L, L.u, S, e, o, 1);
     strip_load<INT, kSWR>(L, L.f, S, fe, fo, 0);
@@ -776,14 +987,14 @@ __device__ __forceinline__ void fine_pre_body(const LevelDev& L, const LevelDev&
         be[q] = e[q + 1];
         bo[q] = o[q + 1];
     }
-    const StripDiag D(L, S);
+    const StripDiag<NM> D(L, S);
     int buf = 0;
 #pragma unroll
     for (int s = 0; s < NU; ++s) {
-        strip_half<INT>(e, o, fe, fo, 0, S, L, D);
+        strip_half<INT, NM>(e, o, fe, fo, 0, S, L, D);
         strip_exchange(e, o, sx, buf, S);
         buf ^= 1;
-        strip_half<INT>(e, o, fe, fo, 1, S, L, D);
+        strip_half<INT, NM>(e, o, fe, fo, 1, S, L, D);
         strip_exchange(e, o, sx, buf, S);
         buf ^= 1;
     }
@@ -814,9 +1025,17 @@ __device__ __forceinline__ void fine_pre_body(const LevelDev& L, const LevelDev&
         const int gi = S.gi0 + S.r0 + q - 1;
         const bool rin = INT || (gi >= 1 && gi <= L.n);
         double re, rv;
-        strip_residual<INT>(e, o, fe[q - 1], fo[q - 1], q, !INT && gi == L.n, D, re, rv);
-        fe[q - 1] = (rin && (INT || D.ine)) ? (float)re : 0.f;
-        fo[q - 1] = (rin && (INT || D.ino)) ? (float)rv : 0.f;
+        strip_residual<INT, NM>(e, o, fe[q - 1], fo[q - 1], q, gi, D, ofs, re, rv);
+        if (INT) {
+            fe[q - 1] = (float)re;
+            fo[q - 1] = (float)rv;
+        } else {
+            const float sr = NM ? nm_scale(gi, L.n) : 1.f;
+            const float se = NM ? sr * nm_scale(S.je, L.m) : 1.f;
+            const float so = NM ? sr * nm_scale(S.je + 1, L.m) : 1.f;
+            fe[q - 1] = (rin && D.ine) ? (float)re * se : 0.f;
+            fo[q - 1] = (rin && D.ino) ? (float)rv * so : 0.f;
+        }
     }
     // the residual row just above the wave (the last row of the wave above)
     float ge = 0.f, go = 0.f;
@@ -849,7 +1068,8 @@ __device__ __forceinline__ void fine_pre_body(const LevelDev& L, const LevelDev&
 }
 
 // Finest-grid pre-smoothing + FP64 residual + restriction (see k_mg_pre).
-template <int NU>
+// NM: the Neumann problem (residual offset).
+template <int NU, bool NM>
 __global__ __launch_bounds__(64 * kSNW) void k_fine_pre(LevelDev L, LevelDev C,
                                                          const int* __restrict__ done,
                                                          double* __restrict__ part, int c0,
@@ -858,15 +1078,16 @@ __global__ __launch_bounds__(64 * kSNW) void k_fine_pre(LevelDev L, LevelDev C,
     const Strip S(c0, tiles_x);
     if (done[S.c]) return;  // uniform over the block
     if (S.interior(L))
-        fine_pre_body<NU, true>(L, C, part, ntiles, S, sx);
+        fine_pre_body<NU, true, NM>(L, C, part, ntiles, S, sx);
     else
-        fine_pre_body<NU, false>(L, C, part, ntiles, S, sx);
+        fine_pre_body<NU, false, NM>(L, C, part, ntiles, S, sx);
 }
 
-template <int NU, bool INT>
+template <int NU, bool INT, bool NM>
 __device__ __forceinline__ void fine_post_body(const LevelDev& L, const LevelDev& C,
                                                double* __restrict__ part, int ntiles,
                                                const Strip& S, float2 (*sx)[kSNW][2][64]) {
+    const double ofs = NM ? L.fofs[S.c] : 0.0;
     constexpr int KC = kSWR / 2 + 1;  // coarse rows under the wave's own rows
     float e[kSWR + 2], o[kSWR + 2], fe[kSWR], fo[kSWR], E[KC], be[kSWR], bo[kSWR];
     strip_load<INT, kSWR + 2>(L, L.ub, S, e, o, 1);
@@ -888,17 +1109,18 @@ __device__ __forceinline__ void fine_post_body(const LevelDev& L, const LevelDev
             E[k] = (cj && I >= 0 && I <= C.n + 1) ? v : 0.f;
         }
     }
-    const StripDiag D(L, S);
+    const StripDiag<NM> D(L, S);
     // bilinear prolongation onto the own rows: e has oj = 0, o has oj = 1
     // (coarse columns J0 and J0 + 1)
-    const float fxo = J0 == C.m ? C.wx : 0.5f;
+    const float fxo = (NM && J0 == 0) ? kNmW : (J0 == C.m ? C.wx : 0.5f);
 #pragma unroll
     for (int q = 1; q <= kSWR; ++q) {
         const int gi = S.gi0 + S.r0 + q - 1;
         const bool rin = INT || (gi >= 1 && gi <= L.n);
         const int k = (q - 1) >> 1;
         const bool oi = (q - 1) & 1;
-        const float fy = oi ? ((ci0 + k) == C.n ? C.wy : 0.5f) : 1.f;
+        const float fy =
+            oi ? ((NM && (ci0 + k) == 0) ? kNmW : ((ci0 + k) == C.n ? C.wy : 0.5f)) : 1.f;
         const float p0 = E[k], pa = oi ? E[k + 1] : 0.f;
         const float q0 = from_right(p0), qa = from_right(pa);
         float we = p0;
@@ -916,10 +1138,10 @@ __device__ __forceinline__ void fine_post_body(const LevelDev& L, const LevelDev
     buf ^= 1;
 #pragma unroll
     for (int s = 0; s < NU; ++s) {
-        strip_half<INT>(e, o, fe, fo, 1, S, L, D);
+        strip_half<INT, NM>(e, o, fe, fo, 1, S, L, D);
         strip_exchange(e, o, sx, buf, S);
         buf ^= 1;
-        strip_half<INT>(e, o, fe, fo, 0, S, L, D);
+        strip_half<INT, NM>(e, o, fe, fo, 0, S, L, D);
         strip_exchange(e, o, sx, buf, S);
         buf ^= 1;
     }
@@ -936,7 +1158,7 @@ __device__ __forceinline__ void fine_post_body(const LevelDev& L, const LevelDev
         if (R < kSH || R >= kSR - kSH || (!INT && gi > L.n + 1)) continue;
         const bool rin = INT || (gi >= 1 && gi <= L.n);
         double re, rv;
-        strip_residual<INT>(e, o, fe[q - 1], fo[q - 1], q, !INT && gi == L.n, D, re, rv);
+        strip_residual<INT, NM>(e, o, fe[q - 1], fo[q - 1], q, gi, D, ofs, re, rv);
         const bool ie = lane_out && rin && (INT || D.ine), io = lane_out && rin && (INT || D.ino);
         dmaxf = fmaxf(dmaxf, ie ? fabsf(e[q] - be[q - 1]) : 0.f);
         dmaxf = fmaxf(dmaxf, io ? fabsf(o[q] - bo[q - 1]) : 0.f);
@@ -965,7 +1187,7 @@ __device__ __forceinline__ void fine_post_body(const LevelDev& L, const LevelDev
 }
 
 // Finest-grid prolongation + correction + post-smoothing + norms (see k_mg_post).
-template <int NU>
+template <int NU, bool NM>
 __global__ __launch_bounds__(64 * kSNW) void k_fine_post(LevelDev L, LevelDev C,
                                                           const int* __restrict__ done,
                                                           double* __restrict__ part, int c0,
@@ -974,9 +1196,9 @@ __global__ __launch_bounds__(64 * kSNW) void k_fine_post(LevelDev L, LevelDev C,
     const Strip S(c0, tiles_x);
     if (done[S.c]) return;  // uniform over the block
     if (S.interior(L))
-        fine_post_body<NU, true>(L, C, part, ntiles, S, sx);
+        fine_post_body<NU, true, NM>(L, C, part, ntiles, S, sx);
     else
-        fine_post_body<NU, false>(L, C, part, ntiles, S, sx);
+        fine_post_body<NU, false, NM>(L, C, part, ntiles, S, sx);
 }
 
 // ---------------------------------------------------------------- coarse V-cycle in LDS
@@ -1052,10 +1274,13 @@ struct Slot {
     float rd;   // 1 / diagonal
 };
 
+template <bool NM>
 __device__ __forceinline__ Slot colour_slot(const LdsGrid& g, int c, int q, float* trash) {
     const int r = udiv(q, g.h, g.mg_h);
     const int i = 1 + r, j = 1 + ((c + i + 1) & 1) + 2 * (q - r * g.h);
     float d = 4.f;
+    if (NM && i == 1) d += kNmDiag;
+    if (NM && j == 1) d += kNmDiag;
     if (i == g.n) d += g.ey;
     if (j == g.m) d += g.ex;
     const bool ok = i <= g.n && j <= g.m;
@@ -1070,14 +1295,14 @@ __device__ __forceinline__ Slot colour_slot(const LdsGrid& g, int c, int q, floa
 // c0, then the other).  Points of one colour read only the other colour.
 // The first NT * KPT slots of each colour are held in registers; slots beyond
 // (only a large coarsest grid has them) are walked one at a time.
-template <int NT, int KPT, bool SOR>
+template <int NT, int KPT, bool SOR, bool NM>
 __device__ void lds_smooth_k(const LdsGrid& g, int c0, int sweeps, float omega, int t,
                              float* trash) {
     Slot sl[2][KPT];
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
-        for (int k = 0; k < KPT; ++k) sl[c][k] = colour_slot(g, c, t + NT * k, trash);
+        for (int k = 0; k < KPT; ++k) sl[c][k] = colour_slot<NM>(g, c, t + NT * k, trash);
     const int slots = g.n * g.h, M = g.M;
     const float* U = g.U;
     const float* F = g.F;
@@ -1093,7 +1318,7 @@ __device__ void lds_smooth_k(const LdsGrid& g, int c0, int sweeps, float omega, 
 #pragma unroll
         for (int k = 0; k < KPT; ++k) *sc[k].w = v[k];
         for (int q = t + NT * KPT; q < slots; q += NT) {
-            const Slot s = colour_slot(g, c, q, trash);
+            const Slot s = colour_slot<NM>(g, c, q, trash);
             *s.w = value(s.r, s.rd);
         }
         group_sync<NT>();
@@ -1109,24 +1334,24 @@ __device__ void lds_smooth_k(const LdsGrid& g, int c0, int sweeps, float omega, 
     }
 }
 
-template <int NT>
+template <int NT, bool NM>
 __device__ void lds_smooth(const LdsGrid& g, int c0, int sweeps, float omega, int t,
                            float* trash) {
     const int per = (g.n * g.h + NT - 1) / NT;  // slots of a colour per thread
     if (omega != 1.f) {
         if (per > 2)
-            lds_smooth_k<NT, 4, true>(g, c0, sweeps, omega, t, trash);
+            lds_smooth_k<NT, 4, true, NM>(g, c0, sweeps, omega, t, trash);
         else if (per > 1)
-            lds_smooth_k<NT, 2, true>(g, c0, sweeps, omega, t, trash);
+            lds_smooth_k<NT, 2, true, NM>(g, c0, sweeps, omega, t, trash);
         else
-            lds_smooth_k<NT, 1, true>(g, c0, sweeps, omega, t, trash);
+            lds_smooth_k<NT, 1, true, NM>(g, c0, sweeps, omega, t, trash);
     } else {
         if (per > 2)
-            lds_smooth_k<NT, 4, false>(g, c0, sweeps, omega, t, trash);
+            lds_smooth_k<NT, 4, false, NM>(g, c0, sweeps, omega, t, trash);
         else if (per > 1)
-            lds_smooth_k<NT, 2, false>(g, c0, sweeps, omega, t, trash);
+            lds_smooth_k<NT, 2, false, NM>(g, c0, sweeps, omega, t, trash);
         else
-            lds_smooth_k<NT, 1, false>(g, c0, sweeps, omega, t, trash);
+            lds_smooth_k<NT, 1, false, NM>(g, c0, sweeps, omega, t, trash);
     }
 }
 
@@ -1140,8 +1365,8 @@ __device__ __forceinline__ void interior_point(const LdsGrid& g, int q, int& i, 
 
 // R = F - A U on the interior (evaluated in FP64, stored FP32); the ring of R
 // stays zero from the kernel's entry.  B points per thread and pass.
-template <int NT, int B>
-__device__ void lds_residual(const LdsGrid& g, float* R, int t, float* trash) {
+template <int NT, int B, bool NM>
+__device__ void lds_residual(const LdsGrid& g, float* R, int t, float* trash, double ofs) {
     const int cells = g.n * g.m, M = g.M;
     const float* U = g.U;
     for (int q0 = 0; q0 < cells; q0 += B * NT) {
@@ -1153,10 +1378,11 @@ __device__ void lds_residual(const LdsGrid& g, float* R, int t, float* trash) {
             int i, j;
             interior_point(g, q < cells ? q : cells - 1, i, j);
             const int o = i * M + j;
-            float d = 4.f;
-            if (i == g.n) d += g.ey;
-            if (j == g.m) d += g.ex;
-            v[b] = (float)res_value(U[o - M], U[o + M], U[o - 1], U[o + 1], U[o], g.F[o], d);
+            const float d =
+                diag_at(i, j, g.n, g.m, g.ey, g.ex, NM ? kNmDiag : 0.f, NM ? kNmDiag : 0.f);
+            const float r =
+                (float)(res_value(U[o - M], U[o + M], U[o - 1], U[o + 1], U[o], g.F[o], d) - ofs);
+            v[b] = NM ? r * (nm_scale(i, g.n) * nm_scale(j, g.m)) : r;
             dst[b] = q < cells ? R + o : trash;
         }
 #pragma unroll
@@ -1191,8 +1417,9 @@ __device__ void lds_restrict(const LdsGrid& g, const float* R, const LdsGrid& cg
 }
 
 // Bilinear prolongation of the coarse correction onto the interior of g;
-// wy / wx weight fine points between the last coarse point and the boundary.
-template <int NT, int B>
+// wy / wx weight fine points between the last coarse point and the boundary
+// (Neumann: also those before the first coarse point, weight kNmW).
+template <int NT, int B, bool NM>
 __device__ void lds_prolong(const LdsGrid& g, const LdsGrid& cg, float wy, float wx, int t,
                             float* trash) {
     const int cells = g.n * g.m, Mc = cg.M;
@@ -1208,8 +1435,8 @@ __device__ void lds_prolong(const LdsGrid& g, const LdsGrid& cg, float wy, float
             const int o = i * g.M + j;
             const bool oi = i & 1, oj = j & 1;
             const int I0 = i >> 1, J0 = j >> 1;
-            const float fy = oi ? (I0 == cg.n ? wy : 0.5f) : 1.f;
-            const float fx = oj ? (J0 == cg.m ? wx : 0.5f) : 1.f;
+            const float fy = oi ? ((NM && I0 == 0) ? kNmW : (I0 == cg.n ? wy : 0.5f)) : 1.f;
+            const float fx = oj ? ((NM && J0 == 0) ? kNmW : (J0 == cg.m ? wx : 0.5f)) : 1.f;
             const float* p = Uc + I0 * Mc + J0;  // rows I0 + 1 <= nc + 1: in the grid
             float w = p[0];
             const float a = p[Mc], c = p[1], e = p[Mc + 1];
@@ -1227,22 +1454,24 @@ __device__ void lds_prolong(const LdsGrid& g, const LdsGrid& cg, float wy, float
 
 // Levels lw .. L-1 of the V-cycle below a grid already restricted, run by
 // wave 0 alone: these grids hold at most 64 x 4 points of a colour.
+template <bool NM>
 __device__ void lds_wave_tail(const LdsPlan& P, float* lds, int lane, float* trash) {
     const int L = P.L;
     for (int l = P.lw; l < L - 1; ++l) {
         const LdsGrid g = lds_grid(P, lds, l);
-        lds_smooth<64>(g, 0, P.pre, 1.f, lane, trash);
-        lds_residual<64, 8>(g, lds + P.roff[l], lane, trash);
+        lds_smooth<64, NM>(g, 0, P.pre, 1.f, lane, trash);
+        lds_residual<64, 8, NM>(g, lds + P.roff[l], lane, trash, 0.0);
         lds_restrict<64, 4>(g, lds + P.roff[l], lds_grid(P, lds, l + 1), lane, trash);
     }
-    lds_smooth<64>(lds_grid(P, lds, L - 1), 0, P.csweeps, P.omega, lane, trash);
+    lds_smooth<64, NM>(lds_grid(P, lds, L - 1), 0, P.csweeps, P.omega, lane, trash);
     for (int l = L - 2; l >= P.lw; --l) {
         const LdsGrid g = lds_grid(P, lds, l);
-        lds_prolong<64, 8>(g, lds_grid(P, lds, l + 1), P.wy[l + 1], P.wx[l + 1], lane, trash);
-        lds_smooth<64>(g, 1, P.post, 1.f, lane, trash);
+        lds_prolong<64, 8, NM>(g, lds_grid(P, lds, l + 1), P.wy[l + 1], P.wx[l + 1], lane, trash);
+        lds_smooth<64, NM>(g, 1, P.post, 1.f, lane, trash);
     }
 }
 
+template <bool NM>
 __global__ __launch_bounds__(kLdsThreads) void k_mg_lds(LdsPlan P, const int* __restrict__ done,
                                                         double* __restrict__ part, int c0) {
     extern __shared__ float lds[];
@@ -1291,21 +1520,22 @@ __global__ __launch_bounds__(kLdsThreads) void k_mg_lds(LdsPlan P, const int* __
     const int lb = P.lw < L - 1 ? P.lw : L - 1;  // first level below the workgroup's levels
     for (int l = lc; l < lb; ++l) {
         const LdsGrid g = lds_grid(P, lds, l);
-        lds_smooth<kLdsThreads>(g, 0, P.pre, 1.f, t, trash);
-        lds_residual<kLdsThreads, 2>(g, lds + P.roff[l], t, trash);
+        lds_smooth<kLdsThreads, NM>(g, 0, P.pre, 1.f, t, trash);
+        lds_residual<kLdsThreads, 2, NM>(g, lds + P.roff[l], t, trash,
+                                     (NM && l == 0) ? P.fofs[c] : 0.0);
         lds_restrict<kLdsThreads, 1>(g, lds + P.roff[l], lds_grid(P, lds, l + 1), t, trash);
     }
     if (P.lw < L) {
-        if (t < 64) lds_wave_tail(P, lds, t, trash);
+        if (t < 64) lds_wave_tail<NM>(P, lds, t, trash);
         __syncthreads();
     } else {
-        lds_smooth<kLdsThreads>(lds_grid(P, lds, L - 1), 0, P.csweeps, P.omega, t, trash);
+        lds_smooth<kLdsThreads, NM>(lds_grid(P, lds, L - 1), 0, P.csweeps, P.omega, t, trash);
     }
     for (int l = lb - 1; l >= lc; --l) {
         const LdsGrid g = lds_grid(P, lds, l);
-        lds_prolong<kLdsThreads, 2>(g, lds_grid(P, lds, l + 1), P.wy[l + 1], P.wx[l + 1], t,
-                                    trash);
-        lds_smooth<kLdsThreads>(g, 1, P.post, 1.f, t, trash);
+        lds_prolong<kLdsThreads, 2, NM>(g, lds_grid(P, lds, l + 1), P.wy[l + 1], P.wx[l + 1], t,
+                                        trash);
+        lds_smooth<kLdsThreads, NM>(g, 1, P.post, 1.f, t, trash);
     }
     // write back the top level (its ring too: zero for coarse grids, the
     // unchanged Dirichlet data for the finest)
@@ -1326,7 +1556,9 @@ __global__ __launch_bounds__(kLdsThreads) void k_mg_lds(LdsPlan P, const int* __
                         dmax = fmax(dmax, fabs((double)U[idx] - (double)gu[go]));
                         const double rv =
                             res_value(U[idx - M], U[idx + M], U[idx - 1], U[idx + 1], U[idx],
-                                      F[idx], diag_at(i, j, n, m, P.ey[0], P.ex[0]));
+                                      F[idx], diag_at(i, j, n, m, P.ey[0], P.ex[0],
+                                                      NM ? kNmDiag : 0.f, NM ? kNmDiag : 0.f)) -
+                            ((NM && lc == 0) ? P.fofs[c] : 0.0);
                         rmax = fmax(rmax, fabs(rv));
                         umax = fmax(umax, fabs((double)U[idx]));
                         rss += rv * rv;
@@ -1440,7 +1672,7 @@ bool small_tiles(const LevelDev& L) {
     return nb < kSmallTileBelow;
 }
 
-template <int NU>
+template <int NU, bool NM>
 gdgs_status launch_pre(const LevelDev& L, const LevelDev& C, bool zero, bool delta,
                        const int* done, double* part, int c0, int nch, hipStream_t st) {
     hipEvent_t ev0, ev1;
@@ -1449,22 +1681,22 @@ gdgs_status launch_pre(const LevelDev& L, const LevelDev& C, bool zero, bool del
     const int z = zero ? 1 : 0;
     if (delta) {
         const int nt = strip_tiles(L.n, L.m);
-        hipLaunchKernelGGL((k_fine_pre<NU>), dim3(nt, nch), dim3(64 * kSNW), 0, st, L, C, done,
-                           part, c0, nt, strip_tiles_x(L.m));
+        hipLaunchKernelGGL((k_fine_pre<NU, NM>), dim3(nt, nch), dim3(64 * kSNW), 0, st, L, C,
+                           done, part, c0, nt, strip_tiles_x(L.m));
     } else if (small_tiles(L)) {
         dim3 grid((L.m + 2 + kTXs - 1) / kTXs, (L.n + 2 + kTYs - 1) / kTYs, nch);
-        hipLaunchKernelGGL((k_mg_pre<NU, false, kTXs, kTYs, kNTs>), grid, dim3(kNTs), 0, st, L, C, z,
+        hipLaunchKernelGGL((k_mg_pre<NU, false, kTXs, kTYs, kNTs, NM>), grid, dim3(kNTs), 0, st, L, C, z,
                            done, part, c0);
     } else {
         dim3 grid((L.m + 2 + kTX - 1) / kTX, (L.n + 2 + kTY - 1) / kTY, nch);
-        hipLaunchKernelGGL((k_mg_pre<NU, false, kTX, kTY, 256>), grid, dim3(256), 0, st, L, C, z,
+        hipLaunchKernelGGL((k_mg_pre<NU, false, kTX, kTY, 256, NM>), grid, dim3(256), 0, st, L, C, z,
                            done, part, c0);
     }
     if (timed) GDGS_HIP_TRY(hipEventRecord(ev1, st));
     return GDGS_OK;
 }
 
-template <int NU>
+template <int NU, bool NM>
 gdgs_status launch_post(const LevelDev& L, const LevelDev& C, bool fine, const int* done,
                         double* part, int c0, int nch, hipStream_t st) {
     hipEvent_t ev0, ev1;
@@ -1472,15 +1704,15 @@ gdgs_status launch_post(const LevelDev& L, const LevelDev& C, bool fine, const i
     if (timed) GDGS_HIP_TRY(hipEventRecord(ev0, st));
     if (fine) {
         const int nt = strip_tiles(L.n, L.m);
-        hipLaunchKernelGGL((k_fine_post<NU>), dim3(nt, nch), dim3(64 * kSNW), 0, st, L, C, done,
-                           part, c0, nt, strip_tiles_x(L.m));
+        hipLaunchKernelGGL((k_fine_post<NU, NM>), dim3(nt, nch), dim3(64 * kSNW), 0, st, L, C,
+                           done, part, c0, nt, strip_tiles_x(L.m));
     } else if (small_tiles(L)) {
         dim3 grid((L.m + 2 + kTXs - 1) / kTXs, (L.n + 2 + kTYs - 1) / kTYs, nch);
-        hipLaunchKernelGGL((k_mg_post<NU, false, kTXs, kTYs, kNTs>), grid, dim3(kNTs), 0, st, L, C,
+        hipLaunchKernelGGL((k_mg_post<NU, false, kTXs, kTYs, kNTs, NM>), grid, dim3(kNTs), 0, st, L, C,
                            done, part, c0);
     } else {
         dim3 grid((L.m + 2 + kTX - 1) / kTX, (L.n + 2 + kTY - 1) / kTY, nch);
-        hipLaunchKernelGGL((k_mg_post<NU, false, kTX, kTY, 256>), grid, dim3(256), 0, st, L, C,
+        hipLaunchKernelGGL((k_mg_post<NU, false, kTX, kTY, 256, NM>), grid, dim3(256), 0, st, L, C,
                            done, part, c0);
     }
     if (timed) GDGS_HIP_TRY(hipEventRecord(ev1, st));
@@ -1502,24 +1734,30 @@ gdgs_status mg_plan(int W, int H, const gdgs_mg_params* mg, MgPlan* plan) {
                   q.levels, q.pre_sweeps, q.post_sweeps, q.max_cycles, q.tol);
         return GDGS_ERR_INVALID_ARGUMENT;
     }
-    if ((q.flags & ~(GDGS_MG_WARM_START | GDGS_MG_RESUME)) != 0) {
+    if ((q.flags & ~(GDGS_MG_WARM_START | GDGS_MG_RESUME | GDGS_MG_NEUMANN)) != 0) {
         set_error("unknown multigrid flags 0x%x", q.flags);
         return GDGS_ERR_INVALID_ARGUMENT;
     }
     p.warm = (q.flags & GDGS_MG_WARM_START) != 0;
     p.resume = (q.flags & GDGS_MG_RESUME) != 0;
+    p.neumann = (q.flags & GDGS_MG_NEUMANN) != 0;
     p.pre = q.pre_sweeps;
     p.post = q.post_sweeps;
     p.max_cycles = q.max_cycles;
     p.tol = q.tol;
-    p.n[0] = H - 2;
-    p.m[0] = W - 2;
-    p.pitch[0] = W;
+    // Dirichlet: the interior pixels, in the caller's image; Neumann: every
+    // pixel, in a padded array of the workspace (zero ring)
+    p.n[0] = p.neumann ? H : H - 2;
+    p.m[0] = p.neumann ? W : W - 2;
+    p.pitch[0] = p.neumann ? pitch_of(W + 2) : W;
     p.dy[0] = 1.0;
     p.dx[0] = 1.0;
     int L = 1;
     const int want = q.levels == 0 ? kMaxLevels : q.levels;
-    while (L < want && p.n[L - 1] / 2 >= 1 && p.m[L - 1] / 2 >= 1) {
+    // (Neumann: no 1 x 1 grid, whose only point has no neighbour and only the
+    // constant mode)
+    while (L < want && p.n[L - 1] / 2 >= 1 && p.m[L - 1] / 2 >= 1 &&
+           !(p.neumann && p.n[L - 1] / 2 == 1 && p.m[L - 1] / 2 == 1)) {
         p.n[L] = p.n[L - 1] / 2;
         p.m[L] = p.m[L - 1] / 2;
         p.dy[L] = 0.5 * (p.n[L - 1] + p.dy[L - 1]) - p.n[L];
@@ -1552,14 +1790,18 @@ gdgs_status mg_plan(int W, int H, const gdgs_mg_params* mg, MgPlan* plan) {
     p.lc = lc;
     p.lds_bytes = bytes;
     if (bytes > 64 * 1024 &&
-        hipFuncSetAttribute((const void*)k_mg_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)bytes) != hipSuccess) {
+        hipFuncSetAttribute(p.neumann ? (const void*)k_mg_lds<true> : (const void*)k_mg_lds<false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) {
         (void)hipGetLastError();
         set_error("cannot reserve %zu bytes of LDS for the coarse-grid solve", bytes);
         return GDGS_ERR_HIP;
     }
     const int nc = p.n[L - 1], mcc = p.m[L - 1];
-    const double rj = 0.5 * (cos(M_PI / (nc + 1)) + cos(M_PI / (mcc + 1)));
+    // Jacobi's spectral radius on the coarsest grid.  Neumann: its largest
+    // eigenvalue below the constant mode's 1, that of the slowest non-constant
+    // mode, which is constant along the shorter side
+    const double rj = p.neumann ? 0.5 * (1.0 + cos(M_PI / (nc > mcc ? nc : mcc)))
+                                : 0.5 * (cos(M_PI / (nc + 1)) + cos(M_PI / (mcc + 1)));
     p.omega = (float)(2.0 / (1.0 + sqrt(1.0 - rj * rj)));
     if (q.coarse_sweeps > 0) {
         p.coarse_sweeps = q.coarse_sweeps;
@@ -1596,6 +1838,7 @@ LdsPlan lds_plan(const MgPlan& p, const LevelDev* lev) {
         lp.ex[l] = lev[l].ex;
         lp.wy[l] = lev[l].wy;
         lp.wx[l] = lev[l].wx;
+
         lp.mg_m[l] = div_magic(p.m[l]);
         lp.mg_h[l] = div_magic((p.m[l] + 1) / 2);
         if (l >= p.lc) {
@@ -1622,6 +1865,9 @@ LdsPlan lds_plan(const MgPlan& p, const LevelDev* lev) {
 struct PoissonWs {
     float* f0;
     float* u0b;  // second buffer of the finest grid
+    float* u0;   // Neumann: the finest grid's iterate (padded); Dirichlet: null (the caller's u)
+    double* mean;  // Neumann: mean of rho [0..2], of the solution [3..5], residual offset [6..8]
+    double* spart; // Neumann: per-block sums of the centred right-hand side
     float* u[kMaxLevels];
     float* ub[kMaxLevels];
     float* f[kMaxLevels];
@@ -1642,11 +1888,18 @@ int div_blocks(int W, int H) {
     return ((W + kDivTX - 1) / kDivTX) * ((H + kDivRows - 1) / kDivRows);
 }
 
+// blocks of the set-up kernels: the image, or the padded Neumann grid
+int setup_blocks(const MgPlan& p, int W, int H) {
+    return p.neumann ? div_blocks(W + 2, H + 2) : div_blocks(W, H);
+}
+
 size_t poisson_layout(const MgPlan& p, int W, int H, void* ws, PoissonWs* out) {
     Carver c(ws);
     PoissonWs w{};
-    w.f0 = c.take<float>((size_t)3 * H * W);
-    w.u0b = c.take<float>((size_t)3 * H * W);
+    const size_t fine = p.neumann ? (size_t)3 * (H + 2) * p.pitch[0] : (size_t)3 * H * W;
+    w.f0 = c.take<float>(fine);
+    w.u0b = c.take<float>(fine);
+    w.u0 = p.neumann ? c.take<float>(fine) : nullptr;
     for (int l = 1; l < p.levels; ++l) {
         const size_t cells = (size_t)(p.n[l] + 2) * p.pitch[l];
         w.u[l] = c.take<float>(3 * cells);
@@ -1654,8 +1907,10 @@ size_t poisson_layout(const MgPlan& p, int W, int H, void* ws, PoissonWs* out) {
         w.f[l] = c.take<float>(3 * cells);
     }
     w.part = c.take<double>((size_t)3 * 5 * norm_blocks(p));
-    w.bpart = c.take<double>((size_t)3 * 2 * div_blocks(W, H));
+    w.bpart = c.take<double>((size_t)3 * 2 * setup_blocks(p, W, H));
     w.bnorm = c.take<double>(6);
+    w.mean = c.take<double>(9);
+    w.spart = c.take<double>((size_t)3 * setup_blocks(p, W, H));
     w.done = c.take<int>(4);
     w.counters = c.take<int>(kCounters);
     w.stats = c.take<gdgs_stats>(1);
@@ -1674,16 +1929,16 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
     PoissonWs w;
     poisson_layout(p, W, H, ws, &w);
     gdgs_stats* sd = stats ? stats : w.stats;
-    const long long cs0 = (long long)H * W;
+    const bool nm = p.neumann;
     LevelDev lev[kMaxLevels];
-    lev[0].u = u;
+    lev[0].u = nm ? w.u0 : u;
     lev[0].ub = w.u0b;
-    lev[0].f = grad ? w.f0 : rho;
+    lev[0].f = (grad || nm) ? w.f0 : rho;
     lev[0].fw = nullptr;
     lev[0].n = p.n[0];
     lev[0].m = p.m[0];
-    lev[0].pitch = W;
-    lev[0].cs = cs0;
+    lev[0].pitch = p.pitch[0];
+    lev[0].cs = (long long)(p.n[0] + 2) * p.pitch[0];
     lev[0].ey = lev[0].ex = 0.f;
     lev[0].wy = lev[0].wx = 0.5f;
     for (int l = 1; l < p.levels; ++l) {
@@ -1700,10 +1955,37 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
         lev[l].wy = (float)(1.0 - 0.5 / p.dy[l]);
         lev[l].wx = (float)(1.0 - 0.5 / p.dx[l]);
     }
-    const int nblk_div = div_blocks(W, H);
+    for (int l = 0; l < p.levels; ++l) {
+        LevelDev& v = lev[l];
+        v.fofs = (nm && l == 0) ? w.mean + 6 : nullptr;
+        if (nm) {
+            // Neumann: the last row / column has one neighbour fewer and the
+            // fine point beyond the last coarse point takes its value (the
+            // first-edge terms are the kernels' constants kNmDiag, kNmW)
+            v.ey = v.ex = kNmDiag;
+            v.wy = v.wx = kNmW;
+        }
+    }
+    const int nblk_div = setup_blocks(p, W, H);
+    const dim3 grid_pad((W + 2 + kDivTX - 1) / kDivTX, (H + 2 + kDivRows - 1) / kDivRows, 3);
     auto setup = [&](hipStream_t s) -> gdgs_status {
         if (p.resume) {
             hipLaunchKernelGGL(k_resume, dim3(1), dim3(128), 0, s, w.counters);
+            GDGS_LAUNCH_CHECK();
+            return GDGS_OK;
+        }
+        if (nm) {
+            hipLaunchKernelGGL(k_nm_init, grid_pad, dim3(kDivTX * kDivTY), 0, s, grad,
+                               grad ? nullptr : rho, p.warm ? u : nullptr, H, W, p.pitch[0], w.f0,
+                               w.u0, w.u0b, w.bpart, w.counters);
+            hipLaunchKernelGGL(k_nm_mean, dim3(3), dim3(256), 0, s, w.bpart, nblk_div, 2,
+                               1.0 / ((double)H * W), w.mean);
+            hipLaunchKernelGGL(k_nm_center, grid_pad, dim3(kDivTX * kDivTY), 0, s, w.f0, H, W,
+                               p.pitch[0], w.mean, w.bpart, w.spart);
+            hipLaunchKernelGGL(k_nm_mean, dim3(3), dim3(256), 0, s, w.spart, nblk_div, 1,
+                               1.0 / ((double)H * W), w.mean + 6);
+            hipLaunchKernelGGL(k_setup_finalize, dim3(3), dim3(256), 0, s, w.bpart, nblk_div,
+                               w.bnorm, w.done, w.counters, sd, p.warm ? 1 : 0);
             GDGS_LAUNCH_CHECK();
             return GDGS_OK;
         }
@@ -1718,6 +2000,7 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
     };
 
     LdsPlan lp = lds_plan(p, lev);
+    lp.fofs = lev[0].fofs;
     lp.pre = p.pre;
     lp.post = p.post;
     lp.csweeps = p.coarse_sweeps;
@@ -1726,22 +2009,32 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
     const int nblk = norm_blocks(p);
     // channels c0 .. c0 + nch - 1 of one grid pass
     auto pre = [&](int l, int c0, int nch, hipStream_t s) {
+        const LevelDev &a = lev[l], &b = lev[l + 1];
         if (p.pre == 1)
-            launch_pre<1>(lev[l], lev[l + 1], l > 0, l == 0, w.done, w.part, c0, nch, s);
+            nm ? launch_pre<1, true>(a, b, l > 0, l == 0, w.done, w.part, c0, nch, s)
+               : launch_pre<1, false>(a, b, l > 0, l == 0, w.done, w.part, c0, nch, s);
         else
-            launch_pre<2>(lev[l], lev[l + 1], l > 0, l == 0, w.done, w.part, c0, nch, s);
+            nm ? launch_pre<2, true>(a, b, l > 0, l == 0, w.done, w.part, c0, nch, s)
+               : launch_pre<2, false>(a, b, l > 0, l == 0, w.done, w.part, c0, nch, s);
     };
     auto post = [&](int l, int c0, int nch, hipStream_t s) {
+        const LevelDev &a = lev[l], &b = lev[l + 1];
         if (p.post == 1)
-            launch_post<1>(lev[l], lev[l + 1], l == 0, w.done, w.part, c0, nch, s);
+            nm ? launch_post<1, true>(a, b, l == 0, w.done, w.part, c0, nch, s)
+               : launch_post<1, false>(a, b, l == 0, w.done, w.part, c0, nch, s);
         else
-            launch_post<2>(lev[l], lev[l + 1], l == 0, w.done, w.part, c0, nch, s);
+            nm ? launch_post<2, true>(a, b, l == 0, w.done, w.part, c0, nch, s)
+               : launch_post<2, false>(a, b, l == 0, w.done, w.part, c0, nch, s);
     };
     // everything of a cycle between the finest pre and post passes
     auto body = [&](int c0, int nch, hipStream_t s) -> gdgs_status {
         for (int l = 1; l < p.lc; ++l) pre(l, c0, nch, s);
-        hipLaunchKernelGGL(k_mg_lds, dim3(nch), dim3(kLdsThreads), p.lds_bytes, s, lp, w.done,
-                           w.part, c0);
+        if (nm)
+            hipLaunchKernelGGL((k_mg_lds<true>), dim3(nch), dim3(kLdsThreads), p.lds_bytes, s, lp,
+                               w.done, w.part, c0);
+        else
+            hipLaunchKernelGGL((k_mg_lds<false>), dim3(nch), dim3(kLdsThreads), p.lds_bytes, s, lp,
+                               w.done, w.part, c0);
         for (int l = p.lc - 1; l >= 1; --l) post(l, c0, nch, s);
         GDGS_LAUNCH_CHECK();
         return GDGS_OK;
@@ -1845,6 +2138,28 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
     };
     r = run_cycles();
     if (r != GDGS_OK) return r;
+    if (nm) {
+        // zero-mean gauge, written to the caller's image
+        auto gauge = [&](hipStream_t s) -> gdgs_status {
+            hipLaunchKernelGGL(k_nm_usum, grid_pad, dim3(kDivTX * kDivTY), 0, s, w.u0, H, W,
+                               p.pitch[0], w.bpart);
+            hipLaunchKernelGGL(k_nm_mean, dim3(3), dim3(256), 0, s, w.bpart, nblk_div, 2,
+                               1.0 / ((double)H * W), w.mean + 3);
+            hipLaunchKernelGGL(k_nm_out,
+                               dim3((W + kDivTX - 1) / kDivTX, (H + kDivRows - 1) / kDivRows, 3),
+                               dim3(kDivTX * kDivTY), 0, s, w.u0, H, W, p.pitch[0], w.mean + 3, u);
+            GDGS_LAUNCH_CHECK();
+            return GDGS_OK;
+        };
+        if (key) {
+            KeyBuilder kg = *key;
+            kg.tag("gauge");
+            r = with_graph(kg, st, gauge);
+        } else {
+            r = gauge(st);
+        }
+        if (r != GDGS_OK) return r;
+    }
     hipLaunchKernelGGL(k_publish_converged, dim3(1), dim3(64), 0, st, w.done, sd);
     GDGS_LAUNCH_CHECK();
     return GDGS_OK;
