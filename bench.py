@@ -183,7 +183,42 @@ def serving_leg(G, wl, torch, nreq: int, streams: int, budget: int = 4 << 30):
                         "plain": run(plain, off), "batched": run(batched, off)})
         res["poisson_arrivals"] = qps
         res["batched_state"] = batched.state()
+        ring = rings[(1920, 1080)]
+        paths = {}
+        for warm in (False, True):
+            camera_paths(G, wl, batched, ring, streams, 4, warm)   # warm-up
+            paths["warm" if warm else "cold"] = camera_paths(G, wl, batched, ring, streams, 20, warm)
+        res["camera_paths"] = paths
     return res
+
+
+def camera_paths(G, wl, srv, ring, clients: int, frames: int, warm: bool):
+    """`clients` independent moving cameras at 1920x1080 (trajectory seeds
+    11, 12, ...) through the batched server; each client submits its next view
+    when the previous one completes, with that image as the starting point of
+    the solve when warm (the request's u_init) or from zero when cold."""
+    W, H = 1920, 1080
+    cams = [[wl.trajectory_camera(W, H, i, seed=11 + c) for i in range(frames)]
+            for c in range(clients)]
+    cyc, bad = [], 0
+    t0 = time.perf_counter()
+    for c in range(clients):
+        srv.submit(cams[c][0], ring, tag=c * 100000)
+    left = clients
+    while left:
+        for d in srv.poll(64, wait_us=2000):
+            c, i = divmod(int(d["tag"]), 100000)
+            cyc.append(d["cycles"])
+            bad += int(d["status"] != 0 or not d["converged"])
+            if i + 1 < frames:
+                srv.submit(cams[c][i + 1], ring, tag=c * 100000 + i + 1,
+                           u_init=d["u"] if warm else None)
+            else:
+                left -= 1
+    span = time.perf_counter() - t0
+    return {"clients": clients, "frames_per_client": frames,
+            "Mpix_s": round(clients * frames * W * H / span / 1e6, 2),
+            "mg_cycles_mean": round(float(np.mean(cyc)), 3), "not_converged_or_failed": bad}
 
 
 def laplacian_leg(G, wl, torch, scene, cams, ring, mg, W, H, frames: int):

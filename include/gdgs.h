@@ -404,6 +404,12 @@ typedef struct gdgs_request {
     uint64_t tag;           /* caller's value, returned in the completion */
     int64_t arrival_ns;     /* gdgs_now_ns() time before which the request is not
                                started; 0 = on submission */
+    const float* u_init;    /* device [3][H][W] or NULL: the solve starts from this
+                               image's interior instead of zero (GDGS_MG_WARM_START),
+                               e.g. the previous view of a moving camera, which needs
+                               fewer V-cycles; read when the request starts (and again
+                               on a capacity re-run), so it must stay unchanged until
+                               the completion arrives.  May be the request's own u. */
 } gdgs_request;
 
 typedef struct gdgs_completion {

@@ -78,7 +78,8 @@ class ServerParams(ctypes.Structure):
 
 class Request(ctypes.Structure):
     _fields_ = [("cam", Camera), ("boundary", ctypes.c_void_p), ("u", ctypes.c_void_p),
-                ("tag", ctypes.c_uint64), ("arrival_ns", ctypes.c_int64)]
+                ("tag", ctypes.c_uint64), ("arrival_ns", ctypes.c_int64),
+                ("u_init", ctypes.c_void_p)]
 
 
 class Completion(ctypes.Structure):

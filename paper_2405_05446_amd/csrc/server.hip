@@ -90,6 +90,7 @@ struct Payload {
     gdgs_camera cam;
     const float* boundary;
     float* u;
+    const float* u_init;  // starting image of a warm-started solve, or null
 };
 
 }  // namespace
@@ -162,7 +163,7 @@ struct gdgs_server {
         const Payload& p = payload.at(r->id);
         const int W = r->W, H = r->H, s = r->stream;
         hipStream_t st = streams[s];
-        const MgPlan* plan = this->plan(W, H, r->run_cycles, 0);
+        const MgPlan* plan = this->plan(W, H, r->run_cycles, p.u_init ? GDGS_MG_WARM_START : 0);
         if (!plan) return GDGS_ERR_INVALID_ARGUMENT;
         char* base = arena + r->slot.off;
         SlotLayout L;
@@ -197,6 +198,11 @@ struct gdgs_server {
                                  L.rw.raster_ws, q);
         });
         if (e != GDGS_OK) return e;
+        // warm start: the slot's image starts as the caller's (the solve sets
+        // the ring from the boundary and keeps the interior)
+        if (p.u_init)
+            GDGS_HIP_TRY(hipMemcpyAsync(L.u, p.u_init, sizeof(float) * 3 * (size_t)W * H,
+                                        hipMemcpyDeviceToDevice, st));
         // requests already overlap one another: the solve stays on the
         // request's stream as one graph
         e = launch_poisson(L.rw.grad, nullptr, bnd, W, H, *plan, L.u, L.stats, L.rw.poisson_ws,
@@ -414,6 +420,7 @@ gdgs_status gdgs_server_submit(gdgs_server* srv, const gdgs_request* req, int64_
     SREQ(cam.fx > 0 && cam.fy > 0, "focal lengths must be positive");
     SREQ(req->u && al4(req->u), "u is null or not 4-byte aligned");
     SREQ(!req->boundary || al4(req->boundary), "boundary is not 4-byte aligned");
+    SREQ(!req->u_init || al4(req->u_init), "u_init is not 4-byte aligned");
     std::lock_guard<std::mutex> g(srv->mu);
     SREQ(!srv->stop, "server is shutting down");
     const int64_t rid = srv->next_id++;
@@ -423,7 +430,7 @@ gdgs_status gdgs_server_submit(gdgs_server* srv, const gdgs_request* req, int64_
                   srv->arena_bytes);
         return GDGS_ERR_BUDGET;
     }
-    srv->payload[rid] = Payload{cam, req->boundary, req->u};
+    srv->payload[rid] = Payload{cam, req->boundary, req->u, req->u_init};
     ++srv->submitted;
     *id = rid;
     srv->wake.notify_all();

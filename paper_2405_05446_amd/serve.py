@@ -38,12 +38,15 @@ class Server:
         L.check(self.lib.gdgs_server_create(ctypes.byref(scene.struct(6)), ctypes.byref(p),
                                             ctypes.byref(h)))
         self.h = h
-        self.live: dict[int, tuple] = {}    # id -> (u, boundary) kept alive until completed
+        self.live: dict[int, tuple] = {}    # id -> (u, boundary, u_init) kept alive until completed
 
     def submit(self, cam, boundary: torch.Tensor | None = None, u: torch.Tensor | None = None,
-               tag: int = 0, arrival_ns: int = 0) -> tuple[int, torch.Tensor]:
+               tag: int = 0, arrival_ns: int = 0,
+               u_init: torch.Tensor | None = None) -> tuple[int, torch.Tensor]:
         """Queue one view; returns (request id, the tensor u that will hold it).
-        The caller must not touch u or boundary until the completion arrives."""
+        u_init: starting image of the solve (warm start), e.g. the previous view
+        of a moving camera.  The caller must not touch u, boundary or u_init
+        until the completion arrives."""
         W, H = int(cam.W), int(cam.H)
         dev = self.scene.opacity.device
         if u is None:
@@ -53,13 +56,17 @@ class Server:
         if boundary is not None and (tuple(boundary.shape) != (3, H, W) or boundary.dtype != F32
                                      or not boundary.is_contiguous()):
             raise ValueError("boundary must be a contiguous float32 [3][H][W] tensor")
+        if u_init is not None and (tuple(u_init.shape) != (3, H, W) or u_init.dtype != F32
+                                   or not u_init.is_contiguous()):
+            raise ValueError("u_init must be a contiguous float32 [3][H][W] tensor")
         # work queued on torch's stream (e.g. filling the boundary) must be
         # done before the server's streams read it
         torch.cuda.current_stream(dev).synchronize()
-        req = L.Request(camera_struct(cam), L.ptr(boundary), L.ptr(u), int(tag), int(arrival_ns))
+        req = L.Request(camera_struct(cam), L.ptr(boundary), L.ptr(u), int(tag), int(arrival_ns),
+                        L.ptr(u_init))
         rid = ctypes.c_int64()
         L.check(self.lib.gdgs_server_submit(self.h, ctypes.byref(req), ctypes.byref(rid)))
-        self.live[rid.value] = (u, boundary)
+        self.live[rid.value] = (u, boundary, u_init)
         return rid.value, u
 
     def poll(self, max_n: int = 64, wait_us: int = 0) -> list[dict]:
@@ -70,7 +77,7 @@ class Server:
         out = []
         for c in buf[:n.value]:
             d = {f: getattr(c, f) for f, _ in L.Completion._fields_}
-            u, _ = self.live.pop(c.id, (None, None))
+            u = self.live.pop(c.id, (None,))[0]
             d["u"] = u
             out.append(d)
         return out

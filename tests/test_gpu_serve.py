@@ -119,3 +119,37 @@ def test_budget_cancel_and_scheduled_arrival(scene):
         c = srv.drain(1)[0]
         assert c["status"] == 0 and c["arrival_ns"] == t and c["admit_ns"] >= t
         assert srv.state()["completed"] == 2
+
+
+def test_warm_started_requests_along_a_camera_path(scene):
+    # each view of a moving camera starts from the previous view's image
+    sc, ds = scene
+    W, H = 320, 180
+    cams = [wl.trajectory_camera(W, H, i) for i in range(6)]
+    mg = G.mg_params(**MG)
+    cold, warm, cyc_cold, cyc_warm = [], [], [], []
+    with G.Server(ds, budget=1 << 30, streams=2, mg=mg) as srv:
+        for cam in cams:
+            srv.submit(cam, None)
+            c = srv.drain(1)[0]
+            assert c["status"] == 0 and c["converged"] == 1
+            cold.append(c["u"].clone())
+            cyc_cold.append(c["cycles"])
+        prev = None
+        for cam in cams:
+            srv.submit(cam, None, u_init=prev)
+            c = srv.drain(1)[0]
+            assert c["status"] == 0 and c["converged"] == 1
+            warm.append(c["u"].clone())
+            cyc_warm.append(c["cycles"])
+            prev = c["u"]
+    say(f"[serve] camera path cycles cold {cyc_cold}, warm {cyc_warm}")
+    assert sum(cyc_warm[1:]) < sum(cyc_cold[1:])
+    for a, b in zip(cold, warm):
+        assert (a - b).abs().max().item() <= 1e-4
+    # the plain path's warm start gives the same bits
+    r = G.Renderer(ds, W, H, mg, warm_start=True)
+    for cam, b in zip(cams, warm):
+        u = r.render(cam)
+        torch.cuda.synchronize()
+        assert torch.equal(u, b)
