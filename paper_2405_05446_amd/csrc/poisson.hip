@@ -833,7 +833,7 @@ struct Strip {
     __device__ bool interior(const LevelDev& L) const {
         return gi0 - 1 >= 1 && gi0 + kSR <= L.n && gj0 >= 2 && gj0 + kSW <= L.m;
     }
-    __device__ int slot(int ntiles) const { return (c * ntiles + tile) * kSNW + w; }
+    __device__ int slot(int ntiles) const { return c * ntiles + tile; }
 };
 
 // Region rows r0 - 1 + q, q = 0 .. Q-1, of x (channel c) into e/o; zero
@@ -1063,8 +1063,17 @@ __device__ __forceinline__ void fine_pre_body(const LevelDev& L, const LevelDev&
         if (INT || (I >= 1 && I <= C.n && J >= 1 && J <= C.m))
             fc[(size_t)I * C.pitch + J] = 0.25f * v;
     }
+    // one partial per block: the waves' maxima combined through LDS
+    __shared__ double red[kSNW];
     const double dmax = wave_max_d((double)dmaxf);
-    if (S.lane == 0) part[(size_t)S.slot(ntiles) * 5 + 3] = dmax;
+    if (S.lane == 0) red[S.w] = dmax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+#pragma unroll
+        for (int k = 1; k < kSNW; ++k) m = fmax(m, red[k]);
+        part[(size_t)S.slot(ntiles) * 5 + 3] = m;
+    }
 }
 
 // Finest-grid pre-smoothing + FP64 residual + restriction (see k_mg_pre).
@@ -1177,12 +1186,30 @@ __device__ __forceinline__ void fine_post_body(const LevelDev& L, const LevelDev
     const double umax = wave_max_d((double)umaxf);
     rss = wave_sum_d(rss);
     const double dmax = wave_max_d((double)dmaxf);
+    // one partial per block: the waves' values combined through LDS (the sum
+    // in wave order, so the result is deterministic)
+    __shared__ double red[kSNW][4];
     if (S.lane == 0) {
+        red[S.w][0] = rmax;
+        red[S.w][1] = umax;
+        red[S.w][2] = rss;
+        red[S.w][3] = dmax;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = red[0][0], b = red[0][1], q = red[0][2], d = red[0][3];
+#pragma unroll
+        for (int k = 1; k < kSNW; ++k) {
+            a = fmax(a, red[k][0]);
+            b = fmax(b, red[k][1]);
+            q += red[k][2];
+            d = fmax(d, red[k][3]);
+        }
         double* p = part + (size_t)S.slot(ntiles) * 5;
-        p[0] = rmax;
-        p[1] = umax;
-        p[2] = rss;
-        p[4] = dmax;
+        p[0] = a;
+        p[1] = b;
+        p[2] = q;
+        p[4] = d;
     }
 }
 
@@ -1881,7 +1908,7 @@ struct PoissonWs {
 
 int norm_blocks(const MgPlan& p) {
     if (p.lc == 0) return 1;
-    return strip_tiles(p.n[0], p.m[0]) * kSNW;
+    return strip_tiles(p.n[0], p.m[0]);
 }
 
 int div_blocks(int W, int H) {
