@@ -469,7 +469,7 @@ def main():
     ch_per_launch = 3.0 * mean_cycles / post_launches
     post_bytes = MG_POST_BYTES_PER_POINT * ch_per_launch * npts
     post_gbs = post_bytes / (post_us * 1e-6) / 1e9
-    k_raster, k_post = "k_raster_fwd<false>", "k_fine_post<2, false>"
+    k_raster, k_post = "k_raster_fwd<false, 6>", "k_fine_post<2, false>"
     t_raster, t_post = measured_traffic(k_raster), measured_traffic(k_post)
     kern = {
         "raster": {"kernel": k_raster, "bound": "alu", "achieved": round(raster_tflops, 3),
