@@ -81,6 +81,7 @@ def parse():
                     help="skip the Algorithm-1 iteration measurement")
     ap.add_argument("--no-trajectory", action="store_true",
                     help="skip the cold/warm-start camera-path measurement")
+    ap.add_argument("--no-fmg", action="store_true", help="skip the full-multigrid leg")
     ap.add_argument("--no-neumann", action="store_true",
                     help="skip the Neumann-condition leg")
     ap.add_argument("--no-laplacian", action="store_true",
@@ -251,24 +252,43 @@ def laplacian_leg(G, wl, torch, scene, cams, ring, mg, W, H, frames: int):
             "not_converged": int(sum(1 for _, ok in cyc if not ok))}
 
 
-def neumann_leg(G, wl, torch, ds, cams, mg, W, H, frames: int):
-    """The paper's boundary condition for Eq. 21: no flux across the image
-    border, every pixel unknown, zero-mean image (GDGS_MG_NEUMANN), on the same
-    gradient splats and poses as the headline figure.  Frames as a sequence."""
-    r = G.Renderer(ds, W, H, mg, neumann=True)
-    r.render(cams[0])
+def _sequence_leg(G, torch, r, cams, ring, frames: int):
+    """Frames as a sequence through Renderer r (as for the headline figure):
+    ms per frame, per-stage times and V-cycles."""
+    r.render(cams[0], ring)
     seq = [cams[i % len(cams)] for i in range(frames)]
-    r.render_sequence(seq[:5])
+    r.render_sequence(seq[:5], ring)
     torch.cuda.synchronize()
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(frames)]
     cyc = []
     t0 = time.perf_counter()
-    r.render_sequence(seq, events=ev,
+    r.render_sequence(seq, ring, events=ev,
                       on_frame=lambda i, u, st: cyc.append((st["total_cycles"], st["converged"])))
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / frames
     stage = np.array([[ev[i][k].elapsed_time(ev[i][k + 1]) for k in range(4)]
                       for i in range(frames)]).mean(0)
+    return ms, stage, cyc
+
+
+def fmg_leg(G, wl, torch, ds, cams, ring, W, H, frames: int, levels: int):
+    """The headline workload with a full-multigrid start (GDGS_MG_FMG) instead
+    of a first V-cycle from zero: V-cycles per frame and time, same tolerance."""
+    mg = G.mg_params(levels=levels, tol=1e-6, flags=G.FMG)
+    ms, stage, cyc = _sequence_leg(G, torch, G.Renderer(ds, W, H, mg), cams, ring, frames)
+    return {"workload": f"full-multigrid start, {W}x{H}, {ds.K} splats, same poses and ring",
+            "Mpix_s": round(H * W / (ms * 1e-3) / 1e6, 2), "ms_per_frame": round(ms, 4),
+            "frames": frames, "poisson_ms": round(float(stage[3]), 4),
+            "mg_cycles_mean": float(np.mean([c for c, _ in cyc])),
+            "not_converged": int(sum(1 for _, ok in cyc if not ok))}
+
+
+def neumann_leg(G, wl, torch, ds, cams, mg, W, H, frames: int):
+    """The paper's boundary condition for Eq. 21: no flux across the image
+    border, every pixel unknown, zero-mean image (GDGS_MG_NEUMANN), on the same
+    gradient splats and poses as the headline figure.  Frames as a sequence."""
+    r = G.Renderer(ds, W, H, mg, neumann=True)
+    ms, stage, cyc = _sequence_leg(G, torch, r, cams, None, frames)
     return {"workload": f"Neumann condition, {W}x{H}, {ds.K} gradient splats, same poses",
             "Mpix_s": round(H * W / (ms * 1e-3) / 1e6, 2), "ms_per_frame": round(ms, 4),
             "frames": frames,
@@ -535,6 +555,9 @@ def main():
         out["train_step"] = train_leg(G, wl, torch, 10)
     if not args.no_trajectory:
         out["trajectory"] = trajectory_leg(G, wl, torch, ds, ring, mg, W, H, min(args.steps, 50))
+    if not args.no_fmg:
+        out["fmg"] = fmg_leg(G, wl, torch, ds, cams, ring, W, H, min(args.steps, 50),
+                             mg.levels)
     if not args.no_neumann:
         out["neumann"] = neumann_leg(G, wl, torch, ds, cams, mg, W, H, min(args.steps, 50))
     if not args.no_laplacian:

@@ -133,13 +133,22 @@ typedef struct gdgs_bins {
  * over all pixels, and the residual norms are over all pixels.  Not
  * available to the server or the differentiable solve. */
 #define GDGS_MG_NEUMANN 4
+/* flags: a full-multigrid start (nested iteration) instead of a first V-cycle
+ * from the initial image: the residual of the initial image is restricted to
+ * every grid, the coarse grids' problems are solved from the coarsest up, each
+ * grid starting from the interpolated solution of the one below and getting
+ * one V-cycle, and the interpolated result corrects the finest grid.  Counts
+ * as the first cycle (stats cycles[]); later cycles are ordinary V-cycles and
+ * the stopping test is the same.  Ignored with GDGS_MG_RESUME and when every
+ * grid fits in one workgroup's LDS. */
+#define GDGS_MG_FMG 8
 typedef struct gdgs_mg_params {
     int32_t levels;        /* grids including the finest, >= 1; 0 = as many as the size allows, at most 8 */
     int32_t pre_sweeps;    /* red-black Gauss-Seidel sweeps before restriction, 1..2 */
     int32_t post_sweeps;   /* sweeps after prolongation, 1..2 */
     int32_t max_cycles;    /* V-cycle limit, 1..64 */
     int32_t coarse_sweeps; /* SOR sweeps on the coarsest grid; 0 = automatic */
-    int32_t flags;         /* GDGS_MG_WARM_START, GDGS_MG_RESUME, GDGS_MG_NEUMANN (or-ed) or 0 */
+    int32_t flags;         /* GDGS_MG_WARM_START, GDGS_MG_RESUME, GDGS_MG_NEUMANN, GDGS_MG_FMG (or-ed) or 0 */
     double tol;            /* relative-correction tolerance (see above); 0 runs max_cycles */
 } gdgs_mg_params;
 

@@ -51,6 +51,7 @@ def camera_struct(cam) -> L.Camera:
 WARM_START = 1
 RESUME = 2
 NEUMANN = 4  # no flux across the image border, zero-mean image (boundary must be None)
+FMG = 8      # full-multigrid start of a fresh solve
 
 
 def mg_params(levels: int = 0, pre: int = 2, post: int = 2, max_cycles: int = 20,
@@ -513,8 +514,9 @@ class Renderer:
 
     def _mg(self, cycles: int, flags: int = 0) -> L.MgParams:
         m = self.mg
+        keep = (m.flags & FMG) | (NEUMANN if self.neumann else 0)
         return mg_params(m.levels, m.pre_sweeps, m.post_sweeps, cycles, m.tol, m.coarse_sweeps,
-                         flags | (NEUMANN if self.neumann else 0))
+                         flags | keep)
 
     def _enqueue(self, cam, boundary, events, stream):
         """Enqueue one frame (no waiting): the four steps, then an asynchronous

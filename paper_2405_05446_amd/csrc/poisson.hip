@@ -1701,9 +1701,10 @@ bool small_tiles(const LevelDev& L) {
 
 template <int NU, bool NM>
 gdgs_status launch_pre(const LevelDev& L, const LevelDev& C, bool zero, bool delta,
-                       const int* done, double* part, int c0, int nch, hipStream_t st) {
+                       const int* done, double* part, int c0, int nch, hipStream_t st,
+                       bool may_time = true) {
     hipEvent_t ev0, ev1;
-    const bool timed = delta && timer_events("mg_pre_fine", &ev0, &ev1);
+    const bool timed = delta && may_time && timer_events("mg_pre_fine", &ev0, &ev1);
     if (timed) GDGS_HIP_TRY(hipEventRecord(ev0, st));
     const int z = zero ? 1 : 0;
     if (delta) {
@@ -1725,9 +1726,9 @@ gdgs_status launch_pre(const LevelDev& L, const LevelDev& C, bool zero, bool del
 
 template <int NU, bool NM>
 gdgs_status launch_post(const LevelDev& L, const LevelDev& C, bool fine, const int* done,
-                        double* part, int c0, int nch, hipStream_t st) {
+                        double* part, int c0, int nch, hipStream_t st, bool may_time = true) {
     hipEvent_t ev0, ev1;
-    const bool timed = fine && timer_events("mg_post_fine", &ev0, &ev1);
+    const bool timed = fine && may_time && timer_events("mg_post_fine", &ev0, &ev1);
     if (timed) GDGS_HIP_TRY(hipEventRecord(ev0, st));
     if (fine) {
         const int nt = strip_tiles(L.n, L.m);
@@ -1761,13 +1762,14 @@ gdgs_status mg_plan(int W, int H, const gdgs_mg_params* mg, MgPlan* plan) {
                   q.levels, q.pre_sweeps, q.post_sweeps, q.max_cycles, q.tol);
         return GDGS_ERR_INVALID_ARGUMENT;
     }
-    if ((q.flags & ~(GDGS_MG_WARM_START | GDGS_MG_RESUME | GDGS_MG_NEUMANN)) != 0) {
+    if ((q.flags & ~(GDGS_MG_WARM_START | GDGS_MG_RESUME | GDGS_MG_NEUMANN | GDGS_MG_FMG)) != 0) {
         set_error("unknown multigrid flags 0x%x", q.flags);
         return GDGS_ERR_INVALID_ARGUMENT;
     }
     p.warm = (q.flags & GDGS_MG_WARM_START) != 0;
     p.resume = (q.flags & GDGS_MG_RESUME) != 0;
     p.neumann = (q.flags & GDGS_MG_NEUMANN) != 0;
+    p.fmg = (q.flags & GDGS_MG_FMG) != 0 && !p.resume;
     p.pre = q.pre_sweeps;
     p.post = q.post_sweeps;
     p.max_cycles = q.max_cycles;
@@ -2034,25 +2036,35 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
     lp.omega = p.omega;
     lp.top = lev[p.lc];
     const int nblk = norm_blocks(p);
-    // channels c0 .. c0 + nch - 1 of one grid pass
-    auto pre = [&](int l, int c0, int nch, hipStream_t s) {
+    // channels c0 .. c0 + nch - 1 of one grid pass.  pre_nu: nu sweeps (0: the
+    // residual of the current iterate restricted, nothing smoothed), from zero
+    // (zero) or from grid l's iterate
+    auto pre_nu = [&](int l, int nu, bool zero, int c0, int nch, hipStream_t s) {
         const LevelDev &a = lev[l], &b = lev[l + 1];
-        if (p.pre == 1)
-            nm ? launch_pre<1, true>(a, b, l > 0, l == 0, w.done, w.part, c0, nch, s)
-               : launch_pre<1, false>(a, b, l > 0, l == 0, w.done, w.part, c0, nch, s);
+        const int*  dn = w.done;
+        double* pt = w.part;
+        if (nu == 0)  // only in the full-multigrid start, which is never timed
+            nm ? launch_pre<0, true>(a, b, zero, l == 0, dn, pt, c0, nch, s, false)
+               : launch_pre<0, false>(a, b, zero, l == 0, dn, pt, c0, nch, s, false);
+        else if (nu == 1)
+            nm ? launch_pre<1, true>(a, b, zero, l == 0, dn, pt, c0, nch, s)
+               : launch_pre<1, false>(a, b, zero, l == 0, dn, pt, c0, nch, s);
         else
-            nm ? launch_pre<2, true>(a, b, l > 0, l == 0, w.done, w.part, c0, nch, s)
-               : launch_pre<2, false>(a, b, l > 0, l == 0, w.done, w.part, c0, nch, s);
+            nm ? launch_pre<2, true>(a, b, zero, l == 0, dn, pt, c0, nch, s)
+               : launch_pre<2, false>(a, b, zero, l == 0, dn, pt, c0, nch, s);
     };
-    auto post = [&](int l, int c0, int nch, hipStream_t s) {
+    // a V-cycle's pre pass: coarse grids hold corrections that start at zero
+    auto pre = [&](int l, int c0, int nch, hipStream_t s) { pre_nu(l, p.pre, l > 0, c0, nch, s); };
+    auto post_t = [&](int l, int c0, int nch, hipStream_t s, bool may_time) {
         const LevelDev &a = lev[l], &b = lev[l + 1];
         if (p.post == 1)
-            nm ? launch_post<1, true>(a, b, l == 0, w.done, w.part, c0, nch, s)
-               : launch_post<1, false>(a, b, l == 0, w.done, w.part, c0, nch, s);
+            nm ? launch_post<1, true>(a, b, l == 0, w.done, w.part, c0, nch, s, may_time)
+               : launch_post<1, false>(a, b, l == 0, w.done, w.part, c0, nch, s, may_time);
         else
-            nm ? launch_post<2, true>(a, b, l == 0, w.done, w.part, c0, nch, s)
-               : launch_post<2, false>(a, b, l == 0, w.done, w.part, c0, nch, s);
+            nm ? launch_post<2, true>(a, b, l == 0, w.done, w.part, c0, nch, s, may_time)
+               : launch_post<2, false>(a, b, l == 0, w.done, w.part, c0, nch, s, may_time);
     };
+    auto post = [&](int l, int c0, int nch, hipStream_t s) { post_t(l, c0, nch, s, true); };
     // everything of a cycle between the finest pre and post passes
     auto body = [&](int c0, int nch, hipStream_t s) -> gdgs_status {
         for (int l = 1; l < p.lc; ++l) pre(l, c0, nch, s);
@@ -2079,6 +2091,41 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
         if (p.lc > 0) post(0, c0, nch, s);
         return finalize(c0, nch, s);
     };
+    auto lds_cycle = [&](int c0, int nch, hipStream_t s) {
+        if (nm)
+            hipLaunchKernelGGL((k_mg_lds<true>), dim3(nch), dim3(kLdsThreads), p.lds_bytes, s, lp,
+                               w.done, w.part, c0);
+        else
+            hipLaunchKernelGGL((k_mg_lds<false>), dim3(nch), dim3(kLdsThreads), p.lds_bytes, s, lp,
+                               w.done, w.part, c0);
+    };
+    // Full-multigrid start (nested iteration on the error equation): the
+    // residual of the initial image is restricted down to the first grid held
+    // in LDS (pre passes without sweeps leave every coarse iterate zero, and
+    // the finest grid's second buffer equal to its iterate); that grid gets one
+    // in-LDS V-cycle from zero; then each coarser global grid, from the one
+    // above the LDS grids up to grid 1, is set to the interpolation of the
+    // grid below (a post pass onto its zero buffer) and gets one V-cycle of
+    // its own; the last interpolation corrects the finest grid (its post pass,
+    // which also takes the norms), and the cycle is finalized like any other.
+    auto fmg_cycle = [&](int c0, int nch, hipStream_t s) -> gdgs_status {
+        for (int l = 0; l < p.lc; ++l) pre_nu(l, 0, l > 0, c0, nch, s);
+        lds_cycle(c0, nch, s);
+        for (int l = p.lc - 1; l >= 1; --l) {
+            post(l, c0, nch, s);                  // interpolation onto grid l
+            pre_nu(l, p.pre, false, c0, nch, s);  // its V-cycle, from that iterate
+            for (int k = l + 1; k < p.lc; ++k) pre(k, c0, nch, s);
+            lds_cycle(c0, nch, s);
+            for (int k = p.lc - 1; k >= l; --k) post(k, c0, nch, s);
+        }
+        post_t(0, c0, nch, s, false);
+        GDGS_LAUNCH_CHECK();
+        return finalize(c0, nch, s);
+    };
+    const bool use_fmg = p.fmg && p.lc > 0;
+    auto first_or = [&](int cyc, int c0, int nch, hipStream_t s) -> gdgs_status {
+        return (cyc == 0 && use_fmg) ? fmg_cycle(c0, nch, s) : cycle(c0, nch, s);
+    };
 
     gdgs_status r = GDGS_OK;
     if (key) {
@@ -2103,7 +2150,7 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
                 auto all = [&](hipStream_t s) -> gdgs_status {
                     gdgs_status t = GDGS_OK;
                     for (int cyc = 0; cyc < p.max_cycles && t == GDGS_OK; ++cyc)
-                        t = cycle(0, 3, s);
+                        t = first_or(cyc, 0, 3, s);
                     return t;
                 };
                 if (!key) return all(st);
@@ -2112,6 +2159,10 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
                 return with_graph(ka, st, all);
             }
             for (int cyc = 0; cyc < p.max_cycles && r == GDGS_OK; ++cyc) {
+                if (cyc == 0 && use_fmg) {  // the start is not timed
+                    r = fmg_cycle(0, 3, st);
+                    continue;
+                }
                 pre(0, 0, 3, st);
                 auto mid = [&](hipStream_t s) { return body(0, 3, s); };
                 if (key) {
@@ -2143,6 +2194,10 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
         };
         for (int cyc = 0; cyc < p.max_cycles && r == GDGS_OK; ++cyc) {
             for (int c = 0; c < 3 && r == GDGS_OK; ++c) {
+                if (cyc == 0 && use_fmg) {
+                    r = run("fmg", c, [&](hipStream_t s) { return fmg_cycle(c, 1, s); });
+                    continue;
+                }
                 if (!timed) {
                     r = run("cycle", c, [&](hipStream_t s) { return cycle(c, 1, s); });
                     continue;
