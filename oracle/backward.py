@@ -20,6 +20,12 @@ v[6][K].  The chain is:
 
 ``finite_difference`` gives central differences of the same loss for the
 self-check of these formulas.
+
+neumann=True takes the paper's Neumann condition instead (every pixel an
+unknown, no flux across the border, zero-mean u): the loss is over every
+pixel, u = L+ rho with L+ the pseudo-inverse of the singular, symmetric
+Neumann Laplacian, so dl/drho = L+ (u - u_target) (the same Neumann solve),
+and the divergence adjoint is that of ``poisson.divergence_neumann``.
 """
 from __future__ import annotations
 
@@ -52,10 +58,17 @@ class _Solver:
         return u
 
 
-def forward(params: dict, H: int, W: int, target: np.ndarray, solver=None):
+def forward(params: dict, H: int, W: int, target: np.ndarray, solver=None,
+            neumann: bool = False):
     """Loss and intermediates for rasteriser-level params (FP64 copies)."""
     proj = project_2d(params["mean2d"], params["conic"], params["depth"], W, H)
     grad = composite.render_grad(proj, params["opacity"], params["value"], H, W)
+    if neumann:
+        rho = poisson.divergence_neumann(grad)
+        u = poisson.solve_neumann(rho)
+        e = u - np.asarray(target, dtype=np.float64)
+        loss = 0.5 * float((e * e).sum())
+        return dict(loss=loss, grad=grad, rho=rho, u=u, e=e, proj=proj)
     rho = poisson.divergence(grad)
     solver = solver or _Solver(H, W)
     u = solver(rho)
@@ -65,23 +78,29 @@ def forward(params: dict, H: int, W: int, target: np.ndarray, solver=None):
     return dict(loss=loss, grad=grad, rho=rho, u=u, e=e, proj=proj)
 
 
-def gradients(params: dict, H: int, W: int, target: np.ndarray):
+def gradients(params: dict, H: int, W: int, target: np.ndarray, neumann: bool = False):
     """Loss and exact dl/d(mean2d, conic, opacity, value) (FP64)."""
-    solver = _Solver(H, W)
-    fw = forward(params, H, W, target, solver)
-    return gradients_from_du(params, H, W, fw["e"], fw, solver)
+    solver = None if neumann else _Solver(H, W)
+    fw = forward(params, H, W, target, solver, neumann)
+    return gradients_from_du(params, H, W, fw["e"], fw, solver, neumann)
 
 
-def gradients_from_du(params: dict, H: int, W: int, du: np.ndarray, fw=None, solver=None):
+def gradients_from_du(params: dict, H: int, W: int, du: np.ndarray, fw=None, solver=None,
+                      neumann: bool = False):
     """dl/d(mean2d, conic, opacity, value) for any loss whose gradient with
-    respect to u is du[3][H][W] (its ring is not used: u's ring is data)."""
-    solver = solver or _Solver(H, W)
+    respect to u is du[3][H][W] (Dirichlet: its ring is not used, u's ring is
+    data; Neumann: every pixel is used)."""
     if fw is None:
-        fw = forward(params, H, W, np.zeros((3, H, W)), solver)
-    e = np.zeros((3, H, W))
-    e[:, 1:-1, 1:-1] = np.asarray(du, dtype=np.float64)[:, 1:-1, 1:-1]
-    lam = solver(e)                   # L_int lam = e, zero ring
-    dgrad = poisson.div_adjoint(lam)
+        fw = forward(params, H, W, np.zeros((3, H, W)), solver, neumann)
+    if neumann:
+        lam = poisson.solve_neumann(np.asarray(du, dtype=np.float64))   # L+ du
+        dgrad = poisson.div_adjoint_neumann(lam)
+    else:
+        solver = solver or _Solver(H, W)
+        e = np.zeros((3, H, W))
+        e[:, 1:-1, 1:-1] = np.asarray(du, dtype=np.float64)[:, 1:-1, 1:-1]
+        lam = solver(e)                   # L_int lam = e, zero ring
+        dgrad = poisson.div_adjoint(lam)
     proj = fw["proj"]
     K = np.asarray(params["opacity"]).shape[0]
     alpha = np.asarray(params["opacity"], dtype=np.float64)
@@ -130,10 +149,10 @@ def support_signature(params: dict, H: int, W: int) -> int:
 
 
 def finite_difference(params: dict, H: int, W: int, target: np.ndarray, name: str,
-                      index: tuple, rel_step: float = 1e-6):
+                      index: tuple, rel_step: float = 1e-6, neumann: bool = False):
     """Central difference of the loss in one parameter entry.  Returns
     (derivative, crossed) where crossed says the support set changed."""
-    solver = _Solver(H, W)
+    solver = None if neumann else _Solver(H, W)
     base = {k: np.array(v, dtype=np.float64) for k, v in params.items()}
     x0 = base[name][index]
     h = rel_step * max(1.0, abs(x0))
@@ -141,8 +160,8 @@ def finite_difference(params: dict, H: int, W: int, target: np.ndarray, name: st
     minus = {k: v.copy() for k, v in base.items()}
     plus[name][index] = x0 + h
     minus[name][index] = x0 - h
-    lp = forward(plus, H, W, target, solver)["loss"]
-    lm = forward(minus, H, W, target, solver)["loss"]
+    lp = forward(plus, H, W, target, solver, neumann)["loss"]
+    lm = forward(minus, H, W, target, solver, neumann)["loss"]
     crossed = support_signature(plus, H, W) != support_signature(minus, H, W)
     return (lp - lm) / (2.0 * h), crossed
 

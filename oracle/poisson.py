@@ -179,6 +179,18 @@ def divergence_neumann(grad: np.ndarray) -> np.ndarray:
     return rho
 
 
+def div_adjoint_neumann(lam: np.ndarray) -> np.ndarray:
+    """Transpose of ``divergence_neumann``: dgrad[6][H][W] with
+    dgx[i,j] = lam[i,j] - lam[i,j+1] for j < W-1 and 0 in the last column,
+    dgy[i,j] = lam[i,j] - lam[i+1,j] for i < H-1 and 0 in the last row."""
+    lam = np.asarray(lam, dtype=np.float64)
+    C, H, W = lam.shape
+    out = np.zeros((2 * C, H, W))
+    out[0::2, :, :-1] = lam[:, :, :-1] - lam[:, :, 1:]
+    out[1::2, :-1, :] = lam[:, :-1, :] - lam[:, 1:, :]
+    return out
+
+
 def laplacian_neumann(u: np.ndarray) -> np.ndarray:
     """Graph Laplacian of the pixel grid: sum over the neighbours inside the
     image of (u_neighbour - u), on every pixel of u[C][H][W]."""
