@@ -131,7 +131,8 @@ typedef struct gdgs_bins {
  * GDGS_MG_WARM_START reads the caller's u as the starting image, and
  * GDGS_MG_RESUME continues from the workspace.  stats: b = mean(rho) - rho
  * over all pixels, and the residual norms are over all pixels.  Not
- * available to the server or the differentiable solve. */
+ * available to the server; the reverse chain uses the same solve and
+ * gdgs_div_adjoint_neumann. */
 #define GDGS_MG_NEUMANN 4
 /* flags: a full-multigrid start (nested iteration) instead of a first V-cycle
  * from the initial image: the residual of the initial image is restricted to
@@ -364,6 +365,14 @@ gdgs_status gdgs_adam_step(float* param, const float* grad, float* m, float* v, 
  * read, taken as 0 elsewhere): dgx = lam[i][j] - lam[i][j+1],
  * dgy = lam[i][j] - lam[i+1][j]. */
 gdgs_status gdgs_div_adjoint(const float* lam, int32_t W, int32_t H, float* dgrad, void* stream);
+
+/* Transpose of the Neumann divergence (the reverse step of GDGS_MG_NEUMANN,
+ * Sec. 1.5 and Sec. 2.2): dgrad[6][H][W] from lam[3][H][W] (every pixel):
+ * dgx[i][j] = lam[i][j] - lam[i][j+1] for j < W-1 and 0 in the last column,
+ * dgy[i][j] = lam[i][j] - lam[i+1][j] for i < H-1 and 0 in the last row.
+ * Device arrays, caller-owned; enqueued on stream; size errors are returned. */
+gdgs_status gdgs_div_adjoint_neumann(const float* lam, int32_t W, int32_t H, float* dgrad,
+                                     void* stream);
 
 /* Reverse compositing.  Given the forward inputs, the forward output grad
  * and dL/dgrad, writes dL/d(mean2d)[2][K], dL/d(conic)[3][K],

@@ -167,6 +167,8 @@ _SIGS = {
                                       ctypes.c_void_p]),
     "gdgs_div_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                         ctypes.c_void_p, ctypes.c_void_p]),
+    "gdgs_div_adjoint_neumann": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                                ctypes.c_void_p, ctypes.c_void_p]),
     "gdgs_raster_grad_backward": (ctypes.c_int, [P(Proj), ctypes.c_void_p, ctypes.c_void_p,
                                                  ctypes.c_int64, P(Bins), ctypes.c_int32,
                                                  ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,

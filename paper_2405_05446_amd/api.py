@@ -418,12 +418,14 @@ def gdgs_raster_count(proj: dict, opacity: torch.Tensor, value: torch.Tensor, K:
     return int(counts[0].item())
 
 
-def gdgs_div_adjoint(lam: torch.Tensor, W: int, H: int, dgrad=None, stream=None) -> torch.Tensor:
+def gdgs_div_adjoint(lam: torch.Tensor, W: int, H: int, dgrad=None, stream=None,
+                     neumann: bool = False) -> torch.Tensor:
     lib = L.load()
     _need(lam, (3, H, W), F32, "lam")
     dgrad = dgrad if dgrad is not None else torch.empty((6, H, W), dtype=F32, device=lam.device)
     _need(dgrad, (6, H, W), F32, "dgrad")
-    L.check(lib.gdgs_div_adjoint(L.ptr(lam), W, H, L.ptr(dgrad), L.stream_handle(stream)))
+    fn = lib.gdgs_div_adjoint_neumann if neumann else lib.gdgs_div_adjoint
+    L.check(fn(L.ptr(lam), W, H, L.ptr(dgrad), L.stream_handle(stream)))
     return dgrad
 
 

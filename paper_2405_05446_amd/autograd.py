@@ -23,13 +23,26 @@ import torch
 from . import api as A
 
 
-def _dirichlet_only(mg):
-    """The reverse chain here is that of the Dirichlet problem (the adjoint of
-    the interior divergence); the Neumann solve is not differentiated."""
+def _forward_mg(mg, boundary):
     mg = mg if mg is not None else A.mg_params()
-    if mg.flags & A.NEUMANN:
-        raise ValueError("the differentiable render supports the Dirichlet problem only")
+    if (mg.flags & A.NEUMANN) and boundary is not None:
+        raise ValueError("the Neumann problem takes no boundary data")
     return mg
+
+
+def _adjoint(ctx, du, W, H):
+    """dl/dgrad from dl/du.  Dirichlet: the same solve with a zero ring on the
+    interior of du (u's ring is data), then the transpose of the interior
+    divergence.  Neumann: u = L+ rho with L+ the symmetric pseudo-inverse, so
+    dl/drho = L+ du, the same Neumann solve on every pixel of du, then the
+    transpose of the Neumann divergence.  The adjoint solve starts from zero
+    (warm-start and resume flags are not carried over)."""
+    m = ctx.mg
+    nm = bool(m.flags & A.NEUMANN)
+    mg = A.mg_params(m.levels, m.pre_sweeps, m.post_sweeps, m.max_cycles, m.tol,
+                     m.coarse_sweeps, m.flags & (A.NEUMANN | A.FMG))
+    lam, _ = A.gdgs_poisson_solve_rhs(du, None, W, H, mg)
+    return A.gdgs_div_adjoint(lam, W, H, neumann=nm)
 
 
 class GDGSRenderFn(torch.autograd.Function):
@@ -42,7 +55,7 @@ class GDGSRenderFn(torch.autograd.Function):
         opacity = opacity.detach().contiguous()
         value = value.detach().contiguous()
         depth = depth.detach().contiguous()
-        mg = _dirichlet_only(mg)
+        mg = _forward_mg(mg, boundary)
         proj = A.gdgs_project_2d(mean2d, conic, depth, W, H)
         cap = int(capacity if capacity is not None else max(1 << 16, 16 * K))
         bins = A.gdgs_bin_sort(proj, K, W, H, cap)
@@ -62,8 +75,7 @@ class GDGSRenderFn(torch.autograd.Function):
         opacity, value, grad = ctx.saved_tensors
         W, H, K = ctx.W, ctx.H, ctx.K
         du = du.contiguous().to(torch.float32)
-        lam, _ = A.gdgs_poisson_solve_rhs(du, None, W, H, ctx.mg)   # ring of du is not read
-        dgrad = A.gdgs_div_adjoint(lam, W, H)
+        dgrad = _adjoint(ctx, du, W, H)
         g = A.gdgs_raster_grad_backward(ctx.proj, opacity, value, K, ctx.bins, W, H, grad, dgrad)
         return g["mean2d"], g["conic"], g["opacity"], g["value"], None, None, None, None, None, None
 
@@ -83,7 +95,7 @@ class GDGSRender3DFn(torch.autograd.Function):
                            quat.detach().contiguous(), opacity.detach().contiguous(),
                            value.detach().contiguous())
         K = ds.K
-        mg = _dirichlet_only(mg)
+        mg = _forward_mg(mg, boundary)
         proj = A.gdgs_project(ds, cam)
         cap = int(capacity if capacity is not None else max(1 << 16, 16 * K))
         bins = A.gdgs_bin_sort(proj, K, W, H, cap)
@@ -101,8 +113,7 @@ class GDGSRender3DFn(torch.autograd.Function):
     def backward(ctx, du):
         ds, W, H, K = ctx.ds, ctx.W, ctx.H, ctx.K
         du = du.contiguous().to(torch.float32)
-        lam, _ = A.gdgs_poisson_solve_rhs(du, None, W, H, ctx.mg)
-        dgrad = A.gdgs_div_adjoint(lam, W, H)
+        dgrad = _adjoint(ctx, du, W, H)
         g = A.gdgs_raster_grad_backward(ctx.proj, ds.opacity, ds.value, K, ctx.bins, W, H,
                                         ctx.grad, dgrad)
         g3 = A.gdgs_project_backward(ds, ctx.cam, g["mean2d"], g["conic"])

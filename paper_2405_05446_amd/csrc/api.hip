@@ -724,6 +724,15 @@ gdgs_status gdgs_div_adjoint(const float* lam, int32_t W, int32_t H, float* dgra
     return launch_div_adjoint(lam, W, H, dgrad, as_stream(stream));
 }
 
+gdgs_status gdgs_div_adjoint_neumann(const float* lam, int32_t W, int32_t H, float* dgrad,
+                                     void* stream) {
+    clear_error();
+    TRY(check_size(W, H));
+    REQUIRE_PTR(lam);
+    REQUIRE_PTR(dgrad);
+    return launch_div_adjoint(lam, W, H, dgrad, as_stream(stream), true);
+}
+
 gdgs_status gdgs_raster_grad_backward(const gdgs_proj* proj, const float* opacity,
                                       const float* value, int64_t K, const gdgs_bins* bins,
                                       int32_t W, int32_t H, const float* grad, const float* dgrad,

@@ -166,7 +166,8 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
                            int H, const MgPlan& plan, float* u, gdgs_stats* stats, void* ws,
                            hipStream_t st, const KeyBuilder* key = nullptr,
                            bool channel_parallel = true);
-gdgs_status launch_div_adjoint(const float* lam, int W, int H, float* dgrad, hipStream_t st);
+gdgs_status launch_div_adjoint(const float* lam, int W, int H, float* dgrad, hipStream_t st,
+                               bool neumann = false);
 
 // ---------------------------------------------------------------- whole frame
 // Everything one render carves out of its workspace.

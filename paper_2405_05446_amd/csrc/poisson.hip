@@ -1679,6 +1679,21 @@ __global__ void k_div_adjoint(const float* __restrict__ lam, int H, int W,
     dgrad[(size_t)(2 * c + 1) * HW + (size_t)i * W + j] = l0 - li(i + 1, j);
 }
 
+// Transpose of the Neumann divergence (every pixel; the differences that
+// would cross the border get 0).
+__global__ void k_div_adjoint_nm(const float* __restrict__ lam, int H, int W,
+                                 float* __restrict__ dgrad) {
+    const int j = blockIdx.x * kDivTX + (threadIdx.x % kDivTX);
+    const int i = blockIdx.y * kDivTY + (threadIdx.x / kDivTX);
+    const int c = blockIdx.z;
+    if (i >= H || j >= W) return;
+    const size_t HW = (size_t)H * W, p = (size_t)i * W + j;
+    const float* L = lam + (size_t)c * HW;
+    const float l0 = L[p];
+    dgrad[(size_t)(2 * c) * HW + p] = j < W - 1 ? l0 - L[p + 1] : 0.f;
+    dgrad[(size_t)(2 * c + 1) * HW + p] = i < H - 1 ? l0 - L[p + W] : 0.f;
+}
+
 int lds_budget() {
     static int cached = -1;
     if (cached < 0) {
@@ -2247,10 +2262,13 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
     return GDGS_OK;
 }
 
-gdgs_status launch_div_adjoint(const float* lam, int W, int H, float* dgrad, hipStream_t st) {
-    hipLaunchKernelGGL(k_div_adjoint,
-                       dim3((W + kDivTX - 1) / kDivTX, (H + kDivTY - 1) / kDivTY, 3),
-                       dim3(kDivTX * kDivTY), 0, st, lam, H, W, dgrad);
+gdgs_status launch_div_adjoint(const float* lam, int W, int H, float* dgrad, hipStream_t st,
+                               bool neumann) {
+    const dim3 grid((W + kDivTX - 1) / kDivTX, (H + kDivTY - 1) / kDivTY, 3);
+    if (neumann)
+        hipLaunchKernelGGL(k_div_adjoint_nm, grid, dim3(kDivTX * kDivTY), 0, st, lam, H, W, dgrad);
+    else
+        hipLaunchKernelGGL(k_div_adjoint, grid, dim3(kDivTX * kDivTY), 0, st, lam, H, W, dgrad);
     GDGS_LAUNCH_CHECK();
     return GDGS_OK;
 }

@@ -3,7 +3,8 @@ Sec. 1.5 and Sec. 2.2, Eq. 21) on the GPU through the C ABI: solves against
 the oracle's exact zero-mean solution at ragged sizes and at 1080p, the
 gradient form recovering an image up to its mean, both render forms against
 the oracle, the Renderer against the entry point, a resumed solve against
-one call, and the argument checks."""
+one call, the argument checks, and the reverse chain against the oracle's
+exact gradients."""
 import numpy as np
 import pytest
 import torch
@@ -157,4 +158,36 @@ def test_zero_rhs_and_argument_checks():
         from paper_2405_05446_amd import autograd as AG
         AG.render(torch.zeros((1, 2), device="cuda"), torch.zeros((1, 3), device="cuda"),
                   torch.zeros(1, device="cuda"), torch.zeros((6, 1), device="cuda"),
-                  torch.ones(1, device="cuda"), W, H, mg=_mg())
+                  torch.ones(1, device="cuda"), W, H, boundary=ring, mg=_mg())
+
+
+def test_div_adjoint_matches_oracle_bit_exactly():
+    H, W = 37, 53
+    lam = np.random.default_rng(0).normal(size=(3, H, W)).astype(np.float32)
+    got = np_(G.gdgs_div_adjoint(torch.from_numpy(lam).cuda(), W, H, neumann=True))
+    ref = op.div_adjoint_neumann(lam.astype(np.float64)).astype(np.float32)
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("H,W,K,seed", [(24, 24, 120, 3), (40, 56, 400, 4)])
+def test_gradients_match_oracle(H, W, K, seed):
+    from oracle import backward as obk
+    from paper_2405_05446_amd.autograd import render as diff_render
+    say(f"[neumann] backward {W}x{H} K={K}")
+    params = wl.raster_scene(K, W, H, seed=seed, ls=(-1.5, 0.3), fx=W)
+    target = (wl.reference_image(H, W, seed=2) - 0.5).astype(np.float32)
+    p64 = {k: v.astype(np.float64) for k, v in params.items()}
+    ref = obk.gradients(p64, H, W, target.astype(np.float64), neumann=True)
+    t = {k: torch.from_numpy(np.ascontiguousarray(v, np.float32)).cuda().requires_grad_(
+        k != "depth") for k, v in params.items()}
+    u = diff_render(t["mean2d"], t["conic"], t["opacity"], t["value"], t["depth"], W, H, None,
+                    _mg(tol=1e-7))
+    loss = 0.5 * ((u - torch.from_numpy(target).cuda()) ** 2).sum()
+    loss.backward()
+    say(f"  loss gpu {loss.item():.6e} oracle {ref['loss']:.6e}")
+    assert abs(loss.item() - ref["loss"]) <= 1e-4 * ref["loss"] + 1e-9
+    for name in ["mean2d", "conic", "opacity", "value"]:
+        g = np_(t[name].grad).astype(np.float64)
+        err = float(np.linalg.norm(g - ref[name]) / max(np.linalg.norm(ref[name]), 1e-30))
+        say(f"  {name}: rel L2 {err:.2e}")
+        assert err <= 1e-3, name
