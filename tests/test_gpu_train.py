@@ -94,3 +94,22 @@ def test_loss_falls_toward_a_synthetic_target():
     losses = [tr.step(cam, target)["loss"] for _ in range(12)]
     say(f"[train] losses {['%.4g' % x for x in losses]}")
     assert losses[-1] < 0.8 * losses[0]
+
+
+def test_loss_falls_under_the_neumann_condition():
+    # Algorithm 1 with the paper's boundary condition: target and iterate are
+    # both zero-mean Neumann reconstructions
+    H, W, K = 64, 64, 2000
+    mg = G.mg_params(tol=1e-6, max_cycles=40, flags=G.NEUMANN)
+    truth = wl.make_scene(K, seed=7, ls=(-3.0, 0.4))
+    cam = wl.make_camera(W, H, pose_index=0)
+    target, st = G.gdgs_render(G.DeviceScene.from_host(truth), cam, None, mg, sync_stats=True)
+    assert G.read_stats(st)["converged"]
+    start = wl.make_scene(K, seed=7, ls=(-3.0, 0.4))
+    rng = np.random.default_rng(8)
+    start.value = (start.value + 0.5 * np.abs(start.value).mean()
+                   * rng.normal(size=start.value.shape)).astype(np.float32)
+    tr = TR.Trainer(G.DeviceScene.from_host(start), mg=mg)
+    losses = [tr.step(cam, target)["loss"] for _ in range(12)]
+    say(f"[train] neumann losses {['%.4g' % x for x in losses]}")
+    assert losses[-1] < 0.8 * losses[0]
