@@ -190,8 +190,29 @@ __global__ __launch_bounds__(kDivTX* kDivTY) void k_div_init(
     const int j = blockIdx.x * kDivTX + (threadIdx.x % kDivTX);
     const size_t HW = (size_t)H * W;
     double bmax = 0.0, bdum = 0.0, bss = 0.0;
+    constexpr int R = kDivRows / kDivTY;
+    // all of a thread's loads first (addresses clamped into the image; values
+    // of cells off the image or on the ring are not used), then the stores
+    float ld[R][4];
 #pragma unroll
-    for (int k = 0; k < kDivRows / kDivTY; ++k) {
+    for (int k = 0; k < R; ++k) {
+        const int i = blockIdx.y * kDivRows + k * kDivTY + (threadIdx.x / kDivTX);
+        const int ic = min(max(i, 1), H - 1), jc = min(max(j, 1), W - 1);
+        const size_t p = (size_t)ic * W + jc;
+        if (grad) {
+            const float* gx = grad + (size_t)(2 * c) * HW;
+            const float* gy = grad + (size_t)(2 * c + 1) * HW;
+            ld[k][0] = gx[p];
+            ld[k][1] = gx[p - 1];
+            ld[k][2] = gy[p];
+            ld[k][3] = gy[p - W];
+        } else {
+            ld[k][0] = rho_in[(size_t)c * HW + p];
+            ld[k][1] = ld[k][2] = ld[k][3] = 0.f;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
         const int i = blockIdx.y * kDivRows + k * kDivTY + (threadIdx.x / kDivTX);
         if (i >= H || j >= W) continue;
         const size_t o = (size_t)c * HW + (size_t)i * W + j;
@@ -200,15 +221,8 @@ __global__ __launch_bounds__(kDivTX* kDivTY) void k_div_init(
             u0[o] = boundary ? boundary[o] : 0.f;
             if (f0) f0[o] = 0.f;
         } else {
-            float rho;
-            if (grad) {
-                const float* gx = grad + (size_t)(2 * c) * HW;
-                const float* gy = grad + (size_t)(2 * c + 1) * HW;
-                const size_t p = (size_t)i * W + j;
-                rho = (gx[p] - gx[p - 1]) + (gy[p] - gy[p - W]);
-            } else {
-                rho = rho_in[o];
-            }
+            const float rho =
+                grad ? (ld[k][0] - ld[k][1]) + (ld[k][2] - ld[k][3]) : ld[k][0];
             if (f0) f0[o] = rho;
             if (!warm) u0[o] = 0.f;
             double b = -(double)rho;

@@ -52,11 +52,17 @@ __global__ __launch_bounds__(256) void k_build_records(gdgs_proj proj,
                                                        int nch, float4* __restrict__ rec) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= K) return;
-    if (proj.count[k] == 0) return;
+    // every load is issued before the culled test (one memory latency, not two)
+    const uint32_t cnt = proj.count[k];
     const uint32_t r0 = proj.rect[k], r1 = proj.rect[K + k];
-    const float ox = (float)(kTile * (int)(r0 & 0xFFFF)), oy = (float)(kTile * (int)(r1 & 0xFFFF));
     const float mx = proj.mean2d[k], my = proj.mean2d[K + k];
     const float ca = proj.conic[k], cb = proj.conic[K + k], cc = proj.conic[2 * K + k];
+    const float op = opacity[k];
+    float vv[6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) vv[m] = m < nch ? value[(size_t)m * K + k] : 0.f;
+    if (cnt == 0) return;
+    const float ox = (float)(kTile * (int)(r0 & 0xFFFF)), oy = (float)(kTile * (int)(r1 & 0xFFFF));
     const float det = ca * cc - cb * cb;
     float ylo = -INFINITY, yhi = INFINITY;
     if (det > 0.f && ca > 0.f) {
@@ -66,11 +72,10 @@ __global__ __launch_bounds__(256) void k_build_records(gdgs_proj proj,
     }
     float4* r = rec + 4 * (size_t)k;
     r[0] = make_float4(mx, my, ox, oy);
-    r[1] = make_float4(ca, 2.f * cb, cc, opacity[k]);
+    r[1] = make_float4(ca, 2.f * cb, cc, op);
     // value rows past nch (the Laplacian form has three) are zero
-    auto v = [&](int m) { return m < nch ? value[(size_t)m * K + k] : 0.f; };
-    r[2] = make_float4(v(0), v(1), v(2), v(3));
-    r[3] = make_float4(v(4), v(5), ylo, yhi);
+    r[2] = make_float4(vv[0], vv[1], vv[2], vv[3]);
+    r[3] = make_float4(vv[4], vv[5], ylo, yhi);
 }
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
