@@ -82,6 +82,8 @@ def parse():
     ap.add_argument("--no-trajectory", action="store_true",
                     help="skip the cold/warm-start camera-path measurement")
     ap.add_argument("--no-fmg", action="store_true", help="skip the full-multigrid leg")
+    ap.add_argument("--large", action="store_true",
+                    help="add the 3840x2160, 4M-splat leg (not run by default)")
     ap.add_argument("--no-neumann", action="store_true",
                     help="skip the Neumann-condition leg")
     ap.add_argument("--no-laplacian", action="store_true",
@@ -279,6 +281,24 @@ def fmg_leg(G, wl, torch, ds, cams, ring, W, H, frames: int, levels: int):
     return {"workload": f"full-multigrid start, {W}x{H}, {ds.K} splats, same poses and ring",
             "Mpix_s": round(H * W / (ms * 1e-3) / 1e6, 2), "ms_per_frame": round(ms, 4),
             "frames": frames, "poisson_ms": round(float(stage[3]), 4),
+            "mg_cycles_mean": float(np.mean([c for c, _ in cyc])),
+            "not_converged": int(sum(1 for _, ok in cyc if not ok))}
+
+
+def large_leg(G, wl, torch, frames: int):
+    """3840x2160 with 4M splats (four times the pixels and splats of the
+    headline workload, same distributions, fx = W), frames as a sequence."""
+    W, H, K = 3840, 2160, 4_000_000
+    sc = wl.make_scene(K, seed=5, z=(2.0, 20.0), ls=(-5.0, 0.7))
+    ds = G.DeviceScene.from_host(sc)
+    ring = torch.from_numpy(wl.reference_image(H, W, seed=1).astype(np.float32)).cuda()
+    cams = [wl.make_camera(W, H, pose_index=i) for i in range(frames)]
+    r = G.Renderer(ds, W, H, G.mg_params(tol=1e-6), capacity=24 * K)
+    ms, stage, cyc = _sequence_leg(G, torch, r, cams, ring, frames)
+    return {"workload": f"{W}x{H}, {K} splats, {frames} poses",
+            "Mpix_s": round(H * W / (ms * 1e-3) / 1e6, 2), "ms_per_frame": round(ms, 4),
+            "stages_ms": {n: round(float(v), 4)
+                          for n, v in zip(("project", "bin_sort", "raster", "poisson"), stage)},
             "mg_cycles_mean": float(np.mean([c for c, _ in cyc])),
             "not_converged": int(sum(1 for _, ok in cyc if not ok))}
 
@@ -555,6 +575,8 @@ def main():
         out["train_step"] = train_leg(G, wl, torch, 10)
     if not args.no_trajectory:
         out["trajectory"] = trajectory_leg(G, wl, torch, ds, ring, mg, W, H, min(args.steps, 50))
+    if args.large:
+        out["large"] = large_leg(G, wl, torch, min(args.steps, 20))
     if not args.no_fmg:
         out["fmg"] = fmg_leg(G, wl, torch, ds, cams, ring, W, H, min(args.steps, 50),
                              mg.levels)

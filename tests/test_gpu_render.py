@@ -187,3 +187,31 @@ def test_warm_start_along_a_trajectory_meets_the_tolerance_in_fewer_cycles():
     for a, b in zip(out[False][0], out[True][0]):
         assert (a - b).abs().max().item() <= 1e-4
     assert sum(out[True][1][1:]) < sum(out[False][1][1:])
+
+
+def test_largest_workload_4k_4m_splats():
+    # four times the pixels and the splats of the 1080p workload: pair counts,
+    # tile indices and the multigrid plan at scale (composite on sampled pixels
+    # vs brute force over all splats, the solve vs the exact DST-I solve)
+    W, H, K = 3840, 2160, 4_000_000
+    say(f"[render] largest workload {W}x{H}, {K} splats")
+    sc = wl.make_scene(K, seed=5, z=(2.0, 20.0), ls=(-5.0, 0.7))
+    cam = wl.make_camera(W, H, pose_index=3)
+    ring = wl.reference_image(H, W, seed=1).astype(np.float32)
+    ds = G.DeviceScene.from_host(sc)
+    cap = 24 * K
+    u, st = G.gdgs_render(ds, cam, torch.from_numpy(ring).cuda(), G.mg_params(tol=1e-6),
+                          capacity=cap, sync_stats=True)
+    torch.cuda.synchronize()
+    s = G.read_stats(st)
+    g = gpu_stages(sc, cam, capacity=cap)
+    say(f"  pairs {g['num_pairs']}, cycles {s['cycles']}")
+    assert g["num_pairs"] <= cap and s["converged"] and not s["overflow"]
+    o = oproject(sc, cam)
+    rows, cols = wl.sample_pixels(H, W, 120, seed=13)
+    ref = oc.render_grad(o, sc.opacity, sc.value, H, W, rows, cols)
+    e1 = np.abs(g["grad"][:, rows, cols] - ref).max()
+    exact = P.solve_dst(P.divergence(g["grad"].astype(np.float32)), ring.astype(np.float64))
+    e2 = np.abs(np_(u) - exact).max()
+    say(f"  composite max-abs {e1:.3e}, poisson max-abs {e2:.3e}")
+    assert e1 <= TOL and e2 <= TOL
