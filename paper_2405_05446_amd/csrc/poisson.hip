@@ -2094,15 +2094,19 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
                : launch_post<2, false>(a, b, l == 0, w.done, w.part, c0, nch, s, may_time);
     };
     auto post = [&](int l, int c0, int nch, hipStream_t s) { post_t(l, c0, nch, s, true); };
-    // everything of a cycle between the finest pre and post passes
-    auto body = [&](int c0, int nch, hipStream_t s) -> gdgs_status {
-        for (int l = 1; l < p.lc; ++l) pre(l, c0, nch, s);
+    // the in-workgroup V-cycle over the grids held in LDS
+    auto lds_cycle = [&](int c0, int nch, hipStream_t s) {
         if (nm)
             hipLaunchKernelGGL((k_mg_lds<true>), dim3(nch), dim3(kLdsThreads), p.lds_bytes, s, lp,
                                w.done, w.part, c0);
         else
             hipLaunchKernelGGL((k_mg_lds<false>), dim3(nch), dim3(kLdsThreads), p.lds_bytes, s, lp,
                                w.done, w.part, c0);
+    };
+    // everything of a cycle between the finest pre and post passes
+    auto body = [&](int c0, int nch, hipStream_t s) -> gdgs_status {
+        for (int l = 1; l < p.lc; ++l) pre(l, c0, nch, s);
+        lds_cycle(c0, nch, s);
         for (int l = p.lc - 1; l >= 1; --l) post(l, c0, nch, s);
         GDGS_LAUNCH_CHECK();
         return GDGS_OK;
@@ -2119,14 +2123,6 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
         if (r != GDGS_OK) return r;
         if (p.lc > 0) post(0, c0, nch, s);
         return finalize(c0, nch, s);
-    };
-    auto lds_cycle = [&](int c0, int nch, hipStream_t s) {
-        if (nm)
-            hipLaunchKernelGGL((k_mg_lds<true>), dim3(nch), dim3(kLdsThreads), p.lds_bytes, s, lp,
-                               w.done, w.part, c0);
-        else
-            hipLaunchKernelGGL((k_mg_lds<false>), dim3(nch), dim3(kLdsThreads), p.lds_bytes, s, lp,
-                               w.done, w.part, c0);
     };
     // Full-multigrid start (nested iteration on the error equation): the
     // residual of the initial image is restricted down to the first grid held
