@@ -130,8 +130,8 @@ typedef struct gdgs_bins {
  * (padded), so the workspace is larger than for the Dirichlet problem;
  * GDGS_MG_WARM_START reads the caller's u as the starting image, and
  * GDGS_MG_RESUME continues from the workspace.  stats: b = mean(rho) - rho
- * over all pixels, and the residual norms are over all pixels.  Not
- * available to the server; the reverse chain uses the same solve and
+ * over all pixels, and the residual norms are over all pixels.  The server
+ * takes it in its parameters; the reverse chain uses the same solve and
  * gdgs_div_adjoint_neumann. */
 #define GDGS_MG_NEUMANN 4
 /* flags: a full-multigrid start (nested iteration) instead of a first V-cycle
@@ -412,7 +412,8 @@ typedef struct gdgs_server_params {
     int64_t hbm_budget;   /* bytes of device memory for in-flight requests */
     int32_t streams;      /* requests in flight at once, 1..16 (1 = plain FIFO) */
     int32_t reserved;     /* 0 */
-    gdgs_mg_params mg;    /* solver parameters of every request; flags must be 0 */
+    gdgs_mg_params mg;    /* solver parameters of every request; flags 0 or
+                             GDGS_MG_NEUMANN (then requests take no boundary) */
 } gdgs_server_params;
 
 typedef struct gdgs_request {

@@ -128,7 +128,7 @@ struct gdgs_server {
         if (it != plans.end()) return &it->second;
         gdgs_mg_params q = mg;
         q.max_cycles = cycles;
-        q.flags = flags;
+        q.flags = flags | (mg.flags & GDGS_MG_NEUMANN);  // the server's boundary condition
         gdgs::MgPlan p;
         if (gdgs::mg_plan(W, H, &q, &p) != GDGS_OK) return nullptr;
         return &plans.emplace(key, p).first->second;
@@ -353,7 +353,8 @@ gdgs_status gdgs_server_create(const gdgs_scene* scene, const gdgs_server_params
     SREQ(params->streams >= 1 && params->streams <= 16, "streams = %d, must be 1..16",
          params->streams);
     SREQ(params->hbm_budget >= (1 << 20), "hbm_budget must be at least 1 MiB");
-    SREQ(params->mg.flags == 0, "server solver flags must be 0");
+    SREQ((params->mg.flags & ~GDGS_MG_NEUMANN) == 0,
+         "server solver flags must be 0 or GDGS_MG_NEUMANN");
     MgPlan probe;
     if (mg_plan(64, 64, &params->mg, &probe) != GDGS_OK) return GDGS_ERR_INVALID_ARGUMENT;
 
@@ -420,6 +421,8 @@ gdgs_status gdgs_server_submit(gdgs_server* srv, const gdgs_request* req, int64_
     SREQ(cam.fx > 0 && cam.fy > 0, "focal lengths must be positive");
     SREQ(req->u && al4(req->u), "u is null or not 4-byte aligned");
     SREQ(!req->boundary || al4(req->boundary), "boundary is not 4-byte aligned");
+    SREQ(!(req->boundary && (srv->mg.flags & GDGS_MG_NEUMANN)),
+         "the Neumann problem takes no boundary data");
     SREQ(!req->u_init || al4(req->u_init), "u_init is not 4-byte aligned");
     std::lock_guard<std::mutex> g(srv->mu);
     SREQ(!srv->stop, "server is shutting down");

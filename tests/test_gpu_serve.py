@@ -153,3 +153,26 @@ def test_warm_started_requests_along_a_camera_path(scene):
         u = r.render(cam)
         torch.cuda.synchronize()
         assert torch.equal(u, b)
+
+
+def test_neumann_server_equals_plain_path(scene):
+    # the paper's boundary condition in serving: mixed sizes, results equal to
+    # the plain per-request path's; a request with boundary data is refused
+    sc, ds = scene
+    mg = G.mg_params(tol=1e-6, max_cycles=30, flags=G.NEUMANN)
+    reqs = requests(12, seed=3)
+    with G.Server(ds, budget=1 << 30, streams=4, mg=mg) as srv:
+        for (W, H), i in reqs:
+            srv.submit(wl.make_camera(W, H, pose_index=i), None, tag=i)
+        done = srv.drain(len(reqs))
+        W, H = SIZES[0]
+        with pytest.raises(G.GdgsError):
+            srv.submit(wl.make_camera(W, H), torch.zeros((3, H, W), device="cuda"))
+    assert all(c["status"] == 0 and c["converged"] == 1 for c in done)
+    by_tag = {c["tag"]: c["u"] for c in done}
+    for (W, H), i in reqs[:6]:
+        r = G.Renderer(ds, W, H, mg)
+        u = r.render(wl.make_camera(W, H, pose_index=i))
+        torch.cuda.synchronize()
+        assert torch.equal(u, by_tag[i])
+        assert abs(float(u.double().mean())) <= 1e-6
