@@ -70,3 +70,37 @@ def test_degenerate_splats():
     err_u = np.abs(u - o["u"]).max()
     say(f"[edges] degenerate: grad {err_g:.3e}, u {err_u:.3e}")
     assert err_g <= TOL and err_u <= TOL
+
+
+@pytest.mark.parametrize("W,H", [(3, 3), (3, 40), (40, 3), (17, 16), (33, 5)])
+def test_neumann_smallest_and_off_by_one_images(W, H):
+    sc = wl.make_scene(300, seed=11, ls=(-2.5, 0.5))
+    cam = wl.make_camera(W, H, pose_index=3)
+    u, s = render(sc, cam, None, G.mg_params(tol=1e-6, max_cycles=40, flags=G.NEUMANN))
+    o = orender(sc, cam, neumann=True)
+    err = np.abs(u - o["u"]).max()
+    say(f"[edges] neumann {W}x{H}: max-abs {err:.3e}, cycles {s['cycles']}")
+    assert err <= TOL and s["converged"]
+    assert np.abs(u.astype(np.float64).mean(axis=(1, 2))).max() <= 1e-6
+
+
+def test_neumann_laplacian_form_with_threshold():
+    from oracle.render import render_laplacian as orender_lap
+    H, W, K = 40, 56, 1500
+    sc = wl.laplacian_scene(wl.make_scene(K, seed=4, ls=(-2.5, 0.5)), seed=4)
+    cam = wl.make_camera(W, H, pose_index=2)
+    ds = G.DeviceScene.from_host(sc)
+    r = G.Renderer(ds, W, H, G.mg_params(tol=1e-6, max_cycles=40), neumann=True,
+                   threshold=0.01)
+    u = r.render(cam)
+    torch.cuda.synchronize()
+    # the oracle solves the GPU's thresholded composite (the threshold is an
+    # exact FP32 comparison, checked elsewhere against the oracle's)
+    rho = np_(r.grad[:3]).astype(np.float64)
+    exact = P.solve_neumann(rho)
+    err = np.abs(np_(u) - exact).max()
+    o = orender_lap(sc, cam, t=0.01, neumann=True)
+    say(f"[edges] neumann laplacian thresholded: max-abs {err:.3e}, "
+        f"vs oracle render {np.abs(np_(u) - o['u']).max():.3e}")
+    assert r.last["converged"] and err <= TOL
+    assert np.abs(np_(u) - o["u"]).max() <= 10 * TOL
