@@ -329,12 +329,19 @@ def trajectory_leg(G, wl, torch, ds, ring, mg, W, H, frames: int):
         r.render_sequence(cams[:4], ring)
         torch.cuda.synchronize()
         cyc = []
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(frames)]
         t0 = time.perf_counter()
-        r.render_sequence(cams, ring, on_frame=lambda i, u, st: cyc.append(st["total_cycles"]))
+        r.render_sequence(cams, ring, events=ev,
+                          on_frame=lambda i, u, st: cyc.append(st["total_cycles"]))
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / frames
+        # per-frame device time (first to last step of the frame's stream work)
+        fr = np.array([ev[i][0].elapsed_time(ev[i][4]) for i in range(frames)])
         res["warm" if warm else "cold"] = {
             "Mpix_s": round(H * W / (ms * 1e-3) / 1e6, 2), "ms_per_frame": round(ms, 4),
+            "frame_gpu_ms": {"mean": round(float(fr.mean()), 4),
+                             "median": round(float(np.median(fr)), 4),
+                             "max": round(float(fr.max()), 4)},
             "mg_cycles_mean": round(float(np.mean(cyc)), 3)}
     return {"workload": f"{frames} frames of a camera path (0.02 deg and 5e-4 units per "
                         f"frame), {W}x{H}, same scene and solver", **res}
