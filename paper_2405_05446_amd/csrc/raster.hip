@@ -119,6 +119,47 @@ __device__ __forceinline__ float pair_exponent(const float4& q0, const float4& q
     return dx * fmaf(q0.x, dx, q0.y * dy) + q0.z * dy * dy;
 }
 
+// Bands of a tile whose 4 x 16 pixel-centre rectangle the support ellipse
+// {E <= E_cut} meets, among those in m (the y-extent test).  With the pair
+// form below, E' = -(A dx^2 + B dx dy + C dy^2) and the support is
+// A dx^2 + B dx dy + C dy^2 <= -log2(1e-5).  Outside the centre the minimum
+// of the quadratic over a rectangle lies on an edge; on a vertical edge
+// dx = X it is C (dy - dy*)^2 + X^2 D / C with dy* = -B X / (2C) clamped to
+// the edge, D = A C - B^2 / 4 (likewise on horizontal edges), a sum of
+// non-negative terms.  A band is dropped only if that minimum exceeds the
+// threshold by a margin above the FP32 rounding of both this test and the
+// per-pixel exponent, so no pixel that would blend the splat loses it.
+__device__ __forceinline__ uint32_t support_bands(const float4& q0, const float4& q1,
+                                                  uint32_t m) {
+    const float A = -q0.x, B = -q0.y, C = -q0.z, mx = q0.w, my = q1.x;
+    const double D = (double)A * (double)C - 0.25 * (double)B * (double)B;
+    if (!(A > 0.f) || !(C > 0.f) || !(D > 0.0)) return m;
+    const float rA = 1.f / A, rC = 1.f / C;
+    const float Df = (float)D, DA = Df * rA, DC = Df * rC;
+    const float X0 = 0.5f - mx, X1 = 15.5f - mx;
+    const float sv = -0.5f * B * rC, sh = -0.5f * B * rA;
+    const float v0 = sv * X0, v1 = sv * X1;  // dy* on the two vertical edges
+    const float w0 = X0 * X0 * DC, w1 = X1 * X1 * DC;
+    const bool xin = X0 <= 0.f && X1 >= 0.f;
+    const float ax = A * fmaxf(X0 * X0, X1 * X1);
+    constexpr float thr = -kEcutL * 1.001f + 1e-3f;
+    uint32_t keep = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const float Y0 = (float)(4 * b) + 0.5f - my, Y1 = Y0 + 3.f;
+        const float d0 = v0 - fminf(fmaxf(v0, Y0), Y1), d1 = v1 - fminf(fmaxf(v1, Y0), Y1);
+        const float h0 = sh * Y0, h1 = sh * Y1;  // dx* on the two horizontal edges
+        const float e0 = h0 - fminf(fmaxf(h0, X0), X1), e1 = h1 - fminf(fmaxf(h1, X0), X1);
+        float q = fminf(fmaf(C * d0, d0, w0), fmaf(C * d1, d1, w1));
+        q = fminf(q, fmaf(A * e0, e0, Y0 * Y0 * DA));
+        q = fminf(q, fmaf(A * e1, e1, Y1 * Y1 * DA));
+        if (xin && Y0 <= 0.f && Y1 >= 0.f) q = 0.f;
+        const float lim = fmaf(1e-5f, ax + C * fmaxf(Y0 * Y0, Y1 * Y1), thr);
+        if (q <= lim) keep |= 1u << b;
+    }
+    return m & keep;
+}
+
 // Composite one splat into a pixel (the Eq. 20 update); counts the
 // contributions when asked to.
 template <bool COUNT, int NCH>
@@ -198,6 +239,7 @@ __global__ __launch_bounds__(256) void k_raster_fwd(const float4* __restrict__ r
                 s_r2[t] = r2;
                 if (NCH > 4) s_r3[t] = r3;
                 m = band_mask(r3.z, r3.w, ty);
+                if (!COUNT && m) m = support_bands(q0, q1, m);
             }
             s_mask[t] = m;
         }
