@@ -7,8 +7,9 @@
 // 16x16 screen tile, one thread per pixel.  The tile's pairs (already in
 // front-to-back order) are consumed in batches of 256: every thread fetches
 // one record into LDS, then all threads walk the batch reading the records as
-// LDS broadcasts.  A wave covers 4 pixel rows of the tile and skips, as a
-// whole, every splat whose support rows miss them.  A pixel stops
+// LDS broadcasts.  A wave covers one 8 x 8 quadrant of the tile and skips,
+// as a whole, every splat whose support ellipse misses it (an exact test
+// with a rounding margin, so no pixel loses a contribution).  A pixel stops
 // accumulating once its transmittance is below 1e-7; the tile stops when all
 // its pixels have.  Splat means are stored relative to the pixel origin of
 // the splat's tile rectangle; when a record enters a tile's batch its mean is
@@ -83,15 +84,14 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-// Row-band mask of a record: bit b set if the support rows [ylo, yhi] meet
-// the pixel-centre rows of band b (rows 4b..4b+3 of the tile).
-__device__ __forceinline__ uint32_t band_mask(float ylo, float yhi, int ty) {
+// Quadrant mask of a record from its support rows [ylo, yhi]: bits 0 and 1
+// (the tile's left and right 8 x 8 quadrants of rows 0..7) if those rows are
+// met, bits 2 and 3 likewise for rows 8..15.
+__device__ __forceinline__ uint32_t quad_rows(float ylo, float yhi, int ty) {
+    const float r0 = (float)(ty * kTile) + 0.5f;
     uint32_t m = 0;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const float lo = (float)(ty * kTile + 4 * b) + 0.5f, hi = lo + 3.f;
-        if (!(yhi < lo || ylo > hi)) m |= 1u << b;
-    }
+    if (!(yhi < r0 || ylo > r0 + 7.f)) m |= 3u;
+    if (!(yhi < r0 + 8.f || ylo > r0 + 15.f)) m |= 12u;
     return m;
 }
 
@@ -119,43 +119,55 @@ __device__ __forceinline__ float pair_exponent(const float4& q0, const float4& q
     return dx * fmaf(q0.x, dx, q0.y * dy) + q0.z * dy * dy;
 }
 
-// Bands of a tile whose 4 x 16 pixel-centre rectangle the support ellipse
-// {E <= E_cut} meets, among those in m (the y-extent test).  With the pair
-// form below, E' = -(A dx^2 + B dx dy + C dy^2) and the support is
-// A dx^2 + B dx dy + C dy^2 <= -log2(1e-5).  Outside the centre the minimum
-// of the quadratic over a rectangle lies on an edge; on a vertical edge
-// dx = X it is C (dy - dy*)^2 + X^2 D / C with dy* = -B X / (2C) clamped to
-// the edge, D = A C - B^2 / 4 (likewise on horizontal edges), a sum of
-// non-negative terms.  A band is dropped only if that minimum exceeds the
-// threshold by a margin above the FP32 rounding of both this test and the
-// per-pixel exponent, so no pixel that would blend the splat loses it.
-__device__ __forceinline__ uint32_t support_bands(const float4& q0, const float4& q1,
+// Quadrants of a tile (8 x 8 pixel centres; bit q: columns 8 (q & 1) ..,
+// rows 8 (q >> 1) ..) that the support ellipse {E <= E_cut} meets, among
+// those in m.  With the pair form below, E' = -(A dx^2 + B dx dy + C dy^2)
+// and the support is A dx^2 + B dx dy + C dy^2 <= -log2(1e-5).  Unless the
+// centre lies in the rectangle, the minimum of the quadratic over it lies on
+// an edge; on a vertical edge dx = X it is C (dy - dy*)^2 + X^2 D / C with
+// dy* = -B X / (2C) clamped to the edge and D = A C - B^2 / 4 (horizontal
+// edges alike), a sum of non-negative terms.  A quadrant is dropped only if
+// that minimum exceeds the threshold by a margin above the FP32 rounding of
+// both this test and the per-pixel exponent, so no pixel that would blend
+// the splat loses it.
+__device__ __forceinline__ uint32_t support_quads(const float4& q0, const float4& q1,
                                                   uint32_t m) {
     const float A = -q0.x, B = -q0.y, C = -q0.z, mx = q0.w, my = q1.x;
     const double D = (double)A * (double)C - 0.25 * (double)B * (double)B;
     if (!(A > 0.f) || !(C > 0.f) || !(D > 0.0)) return m;
     const float rA = 1.f / A, rC = 1.f / C;
     const float Df = (float)D, DA = Df * rA, DC = Df * rC;
-    const float X0 = 0.5f - mx, X1 = 15.5f - mx;
     const float sv = -0.5f * B * rC, sh = -0.5f * B * rA;
-    const float v0 = sv * X0, v1 = sv * X1;  // dy* on the two vertical edges
-    const float w0 = X0 * X0 * DC, w1 = X1 * X1 * DC;
-    const bool xin = X0 <= 0.f && X1 >= 0.f;
-    const float ax = A * fmaxf(X0 * X0, X1 * X1);
+    // edges at pixel centres 0.5, 7.5, 8.5, 15.5: X (columns), Y (rows), the
+    // clamp-free minimisers along them and the constant parts of the minima
+    float X[4], Y[4], v[4], w[4], h[4], g[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float e = (float)(8 * (k >> 1)) + ((k & 1) ? 7.5f : 0.5f);
+        X[k] = e - mx;
+        Y[k] = e - my;
+        v[k] = sv * X[k];
+        w[k] = X[k] * X[k] * DC;
+        h[k] = sh * Y[k];
+        g[k] = Y[k] * Y[k] * DA;
+    }
     constexpr float thr = -kEcutL * 1.001f + 1e-3f;
     uint32_t keep = 0;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const float Y0 = (float)(4 * b) + 0.5f - my, Y1 = Y0 + 3.f;
-        const float d0 = v0 - fminf(fmaxf(v0, Y0), Y1), d1 = v1 - fminf(fmaxf(v1, Y0), Y1);
-        const float h0 = sh * Y0, h1 = sh * Y1;  // dx* on the two horizontal edges
-        const float e0 = h0 - fminf(fmaxf(h0, X0), X1), e1 = h1 - fminf(fmaxf(h1, X0), X1);
-        float q = fminf(fmaf(C * d0, d0, w0), fmaf(C * d1, d1, w1));
-        q = fminf(q, fmaf(A * e0, e0, Y0 * Y0 * DA));
-        q = fminf(q, fmaf(A * e1, e1, Y1 * Y1 * DA));
-        if (xin && Y0 <= 0.f && Y1 >= 0.f) q = 0.f;
-        const float lim = fmaf(1e-5f, ax + C * fmaxf(Y0 * Y0, Y1 * Y1), thr);
-        if (q <= lim) keep |= 1u << b;
+    for (int qd = 0; qd < 4; ++qd) {
+        const int i = 2 * (qd & 1), j = 2 * (qd >> 1);
+        const float x0 = X[i], x1 = X[i + 1], y0 = Y[j], y1 = Y[j + 1];
+        const float d0 = v[i] - fminf(fmaxf(v[i], y0), y1);
+        const float d1 = v[i + 1] - fminf(fmaxf(v[i + 1], y0), y1);
+        const float e0 = h[j] - fminf(fmaxf(h[j], x0), x1);
+        const float e1 = h[j + 1] - fminf(fmaxf(h[j + 1], x0), x1);
+        float q = fminf(fmaf(C * d0, d0, w[i]), fmaf(C * d1, d1, w[i + 1]));
+        q = fminf(q, fmaf(A * e0, e0, g[j]));
+        q = fminf(q, fmaf(A * e1, e1, g[j + 1]));
+        if (x0 <= 0.f && x1 >= 0.f && y0 <= 0.f && y1 >= 0.f) q = 0.f;
+        const float lim =
+            fmaf(1e-5f, A * fmaxf(x0 * x0, x1 * x1) + C * fmaxf(y0 * y0, y1 * y1), thr);
+        if (q <= lim) keep |= 1u << qd;
     }
     return m & keep;
 }
@@ -206,9 +218,11 @@ __global__ __launch_bounds__(256) void k_raster_fwd(const float4* __restrict__ r
     if (tile >= (uint32_t)T) return;
     const int tx = tile % nx, ty = tile / nx;
     const int t = threadIdx.x, lane = __lane_id(), wv = t >> 6;
-    const int px = tx * kTile + (t & 15), py = ty * kTile + (t >> 4);
+    // wave wv: the 8 x 8 quadrant (wv & 1, wv >> 1) of the tile
+    const int ox = 8 * (wv & 1) + (lane & 7), oy = 8 * (wv >> 1) + (lane >> 3);
+    const int px = tx * kTile + ox, py = ty * kTile + oy;
     const bool inside = px < W && py < H;
-    const float xt = (float)(t & 15) + 0.5f, yt = (float)(t >> 4) + 0.5f;  // tile-relative
+    const float xt = (float)ox + 0.5f, yt = (float)oy + 0.5f;  // tile-relative
     const uint64_t lt = lanemask_lt();
     const uint32_t start = ranges[tile], end = ranges[T + tile];
     if (t == 0) {
@@ -238,13 +252,13 @@ __global__ __launch_bounds__(256) void k_raster_fwd(const float4* __restrict__ r
                 s_r1[t] = q1;
                 s_r2[t] = r2;
                 if (NCH > 4) s_r3[t] = r3;
-                m = band_mask(r3.z, r3.w, ty);
-                if (!COUNT && m) m = support_bands(q0, q1, m);
+                m = quad_rows(r3.z, r3.w, ty);
+                if (m) m = support_quads(q0, q1, m);
             }
             s_mask[t] = m;
         }
         __syncthreads();
-        // this wave's list of batch entries whose support meets its rows (empty
+        // this wave's list of batch entries whose support meets its quadrant (empty
         // once all 64 pixels of the wave have stopped accumulating)
         const bool wave_live = __ballot(Tr >= kTmin) != 0ull;
         int cnt = 0;

@@ -19,6 +19,8 @@ TOL = 1e-4
     (3000, 100, 72, (-3, 0.6), 3),        # several tiles, ragged tails both ways
     (1500, 37, 21, (-2.5, 0.5), 5),       # smaller than a few tiles
     (400, 90, 50, (-1.5, 0.4), 2),        # large footprints, deep overlap
+    (1200, 96, 64, (-2.0, 1.2), 1),       # elongated splats at all angles: many wave visits
+                                          # fall outside the support and are dropped
 ])
 def test_raster_full_image_matches_oracle(K, W, H, ls, pose):
     say(f"[raster] K={K} {W}x{H} ls={ls} pose={pose}")
