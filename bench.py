@@ -82,6 +82,8 @@ def parse():
     ap.add_argument("--no-trajectory", action="store_true",
                     help="skip the cold/warm-start camera-path measurement")
     ap.add_argument("--no-fmg", action="store_true", help="skip the full-multigrid leg")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="skip the two-frames-in-flight leg")
     ap.add_argument("--large", action="store_true",
                     help="add the 3840x2160, 4M-splat leg (not run by default)")
     ap.add_argument("--no-neumann", action="store_true",
@@ -271,6 +273,26 @@ def _sequence_leg(G, torch, r, cams, ring, frames: int):
     stage = np.array([[ev[i][k].elapsed_time(ev[i][k + 1]) for k in range(4)]
                       for i in range(frames)]).mean(0)
     return ms, stage, cyc
+
+
+def overlap_leg(torch, r, cams, ring, W, H, frames: int):
+    """The headline workload with two frames in flight: render_sequence with
+    overlap (the two buffer sets on streams of their own, so one frame's
+    binning and compositing run beside the other's multigrid solve).  Same
+    results per frame as the headline loop; wall clock over the frames."""
+    seq = [cams[i % len(cams)] for i in range(frames)]
+    r.render_sequence(seq[:4], ring, overlap=True)
+    torch.cuda.synchronize()
+    cyc = []
+    t0 = time.perf_counter()
+    r.render_sequence(seq, ring, overlap=True,
+                      on_frame=lambda i, u, st: cyc.append((st["total_cycles"], st["converged"])))
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / frames
+    return {"workload": f"headline workload, {W}x{H}, two frames in flight (overlap)",
+            "Mpix_s": round(H * W / (ms * 1e-3) / 1e6, 2), "ms_per_frame": round(ms, 4),
+            "frames": frames, "mg_cycles_mean": float(np.mean([c for c, _ in cyc])),
+            "not_converged": int(sum(1 for _, ok in cyc if not ok))}
 
 
 def fmg_leg(G, wl, torch, ds, cams, ring, W, H, frames: int, levels: int):
@@ -584,6 +606,8 @@ def main():
         out["trajectory"] = trajectory_leg(G, wl, torch, ds, ring, mg, W, H, min(args.steps, 50))
     if args.large:
         out["large"] = large_leg(G, wl, torch, min(args.steps, 20))
+    if not args.no_overlap:
+        out["two_in_flight"] = overlap_leg(torch, r, cams, ring, W, H, args.steps)
     if not args.no_fmg:
         out["fmg"] = fmg_leg(G, wl, torch, ds, cams, ring, W, H, min(args.steps, 50),
                              mg.levels)

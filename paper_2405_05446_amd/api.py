@@ -598,7 +598,8 @@ class Renderer:
         self._enqueue(cam, boundary, events, stream)
         return self._finish(cam, boundary, events, stream)
 
-    def render_sequence(self, cams, boundary=None, events=None, on_frame=None, stream=None):
+    def render_sequence(self, cams, boundary=None, events=None, on_frame=None, stream=None,
+                        overlap=False):
         """Render views one after another without the host waiting in between:
         frame i + 1 is enqueued before frame i is settled.  Two buffer sets
         alternate (this renderer and a twin), so frame i's result stays intact
@@ -606,29 +607,48 @@ class Renderer:
         With warm_start, frame i starts from frame i - 1's image as it stands
         when frame i is enqueued (before any resumed cycles of frame i - 1),
         so results meet the same tolerance but may differ from render()'s in
-        the last bits."""
+        the last bits.
+
+        overlap (without warm_start): the two buffer sets get a stream each,
+        so two frames are in flight on the device at once (one frame's
+        binning and compositing beside the other's multigrid solve); results
+        are unchanged.  Each frame is enqueued behind the work on the caller's
+        stream so far (what on_frame enqueued there for the frame before it on
+        the same buffers), and the caller's stream waits for both at the end."""
         if not hasattr(self, "_twin"):
             self._twin = Renderer(self.scene, self.W, self.H, self.mg, self.capacity,
                                   self.adaptive, self.warm_start, self.threshold, self.neumann)
         rs = [self, self._twin]
+        caller = stream if stream is not None else torch.cuda.current_stream(self.dev)
+        overlap = overlap and not self.warm_start
+        streams = [stream, stream]
+        if overlap:
+            if not hasattr(self, "_seq_streams"):
+                self._seq_streams = [torch.cuda.Stream(device=self.dev) for _ in range(2)]
+            streams = self._seq_streams
         prev = None
         for i, cam in enumerate(cams):
-            r = rs[i % 2]
+            r, rs_i = rs[i % 2], streams[i % 2]
             if prev is not None:
                 r.budget = prev[0].budget
                 if self.warm_start:
                     r._prev_u = prev[0].u
-            r._enqueue(cam, boundary, events[i] if events else None, stream)
+            if overlap:
+                rs_i.wait_stream(caller)
+            r._enqueue(cam, boundary, events[i] if events else None, rs_i)
             if prev is not None:
-                pr, pcam, pi = prev
-                u = pr._finish(pcam, boundary, events[pi] if events else None, stream)
+                pr, pcam, pi, ps = prev
+                u = pr._finish(pcam, boundary, events[pi] if events else None, ps)
                 r.budget = max(r.budget, pr.budget)
                 if on_frame is not None:
                     on_frame(pi, u, pr.last)
-            prev = (r, cam, i)
+            prev = (r, cam, i, rs_i)
         if prev is not None:
-            pr, pcam, pi = prev
-            u = pr._finish(pcam, boundary, events[pi] if events else None, stream)
+            pr, pcam, pi, ps = prev
+            u = pr._finish(pcam, boundary, events[pi] if events else None, ps)
             self.budget = self._twin.budget = pr.budget
             if on_frame is not None:
                 on_frame(pi, u, pr.last)
+        if overlap:
+            for q in streams:
+                caller.wait_stream(q)

@@ -165,6 +165,31 @@ def test_render_sequence_equals_render_frame_by_frame():
     assert seq.capacity > 64
 
 
+def test_render_sequence_with_two_frames_in_flight_equals_render():
+    """The two buffer sets on streams of their own (two frames on the device
+    at once) == render() per view, bit for bit, including a capacity overflow
+    in the middle; the consumer's copies on the caller's stream are ordered
+    before the buffers are reused."""
+    H, W = 64, 96
+    sc = wl.make_scene(5000, seed=13, ls=(-3, 0.6))
+    ds = G.DeviceScene.from_host(sc)
+    ring = torch.from_numpy(wl.reference_image(H, W, seed=1).astype(np.float32)).cuda()
+    cams = [wl.make_camera(W, H, pose_index=i) for i in range(9)]
+    ref = G.Renderer(ds, W, H, G.mg_params(tol=1e-6, max_cycles=30))
+    want = [ref.render(c, ring).clone() for c in cams]
+    seq = G.Renderer(ds, W, H, G.mg_params(tol=1e-6, max_cycles=30), capacity=64)
+    got = {}
+    for rnd in range(2):
+        got.clear()
+        seq.render_sequence(cams, ring, overlap=True,
+                            on_frame=lambda i, u, st: got.__setitem__(i, (u.clone(), st)))
+        torch.cuda.synchronize()
+        assert sorted(got) == list(range(len(cams)))
+        for i, (u, st) in got.items():
+            assert st["converged"] and torch.equal(u, want[i]), (rnd, i)
+    assert seq.capacity > 64
+
+
 def test_warm_start_along_a_trajectory_meets_the_tolerance_in_fewer_cycles():
     """Consecutive views of a moving camera (Sec. 2.2: one view per pose):
     starting each solve from the previous image gives the same images within
