@@ -600,14 +600,14 @@ def main():
                           "unfused_model_GBs": round(unfused_gbs, 1),
                           "unfused_model_frac": round(unfused_gbs / HBM_PEAK_GBS, 4)},
     }
+    if not args.no_overlap:
+        out["two_in_flight"] = overlap_leg(torch, r, cams, ring, W, H, args.steps)
     if not args.no_train:
         out["train_step"] = train_leg(G, wl, torch, 10)
     if not args.no_trajectory:
         out["trajectory"] = trajectory_leg(G, wl, torch, ds, ring, mg, W, H, min(args.steps, 50))
     if args.large:
         out["large"] = large_leg(G, wl, torch, min(args.steps, 20))
-    if not args.no_overlap:
-        out["two_in_flight"] = overlap_leg(torch, r, cams, ring, W, H, args.steps)
     if not args.no_fmg:
         out["fmg"] = fmg_leg(G, wl, torch, ds, cams, ring, W, H, min(args.steps, 50),
                              mg.levels)
