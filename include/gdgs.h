@@ -119,7 +119,7 @@ typedef struct gdgs_bins {
  * written to them since.  Calls totalling n cycles give bit for bit the
  * result of one call with max_cycles = n. */
 #define GDGS_MG_RESUME 2
-/* flags: the paper's Neumann condition (Sec. 1.5 and Sec. 2.2, Eq. 21)
+/* flags: the paper's Neumann condition (Sec. 2.1 "Poisson Equation" and Sec. 2.2 "Poisson Equation", Eq. 21)
  * instead of Dirichlet data on the image ring.  Every one of the H x W pixels
  * is an unknown and no flux crosses the image border: the Laplacian at a
  * pixel sums only its neighbours inside the image, and with gradients the
@@ -143,13 +143,22 @@ typedef struct gdgs_bins {
  * the stopping test is the same.  Ignored with GDGS_MG_RESUME and when every
  * grid fits in one workgroup's LDS. */
 #define GDGS_MG_FMG 8
+/* flags: stop a channel on the normwise backward error instead of the
+ * relative correction: after the first V-cycle with
+ * eta = ||b - A w||_inf / (8 ||w||_inf + ||b||_inf) <= tol (evaluated in FP64
+ * from FP32 iterates).  A backward-error bound, not a bound on the error of w:
+ * for the 5-point operator a small smooth residual can still leave an error
+ * of order (grid size)^2 times the residual, so the default rule (relative
+ * correction) is the safer one; this flag exists to measure the trade-off. */
+#define GDGS_MG_STOP_ETA 16
 typedef struct gdgs_mg_params {
     int32_t levels;        /* grids including the finest, >= 1; 0 = as many as the size allows, at most 8 */
     int32_t pre_sweeps;    /* red-black Gauss-Seidel sweeps before restriction, 1..2 */
     int32_t post_sweeps;   /* sweeps after prolongation, 1..2 */
     int32_t max_cycles;    /* V-cycle limit, 1..64 */
     int32_t coarse_sweeps; /* SOR sweeps on the coarsest grid; 0 = automatic */
-    int32_t flags;         /* GDGS_MG_WARM_START, GDGS_MG_RESUME, GDGS_MG_NEUMANN, GDGS_MG_FMG (or-ed) or 0 */
+    int32_t flags;         /* GDGS_MG_WARM_START, GDGS_MG_RESUME, GDGS_MG_NEUMANN, GDGS_MG_FMG,
+                              GDGS_MG_STOP_ETA (or-ed) or 0 */
     double tol;            /* relative-correction tolerance (see above); 0 runs max_cycles */
 } gdgs_mg_params;
 
@@ -367,7 +376,7 @@ gdgs_status gdgs_adam_step(float* param, const float* grad, float* m, float* v, 
 gdgs_status gdgs_div_adjoint(const float* lam, int32_t W, int32_t H, float* dgrad, void* stream);
 
 /* Transpose of the Neumann divergence (the reverse step of GDGS_MG_NEUMANN,
- * Sec. 1.5 and Sec. 2.2): dgrad[6][H][W] from lam[3][H][W] (every pixel):
+ * Sec. 2.1 and Sec. 2.2): dgrad[6][H][W] from lam[3][H][W] (every pixel):
  * dgx[i][j] = lam[i][j] - lam[i][j+1] for j < W-1 and 0 in the last column,
  * dgy[i][j] = lam[i][j] - lam[i+1][j] for i < H-1 and 0 in the last row.
  * Device arrays, caller-owned; enqueued on stream; size errors are returned. */

@@ -136,6 +136,63 @@ def gradients_from_du(params: dict, H: int, W: int, du: np.ndarray, fw=None, sol
                 lam=lam, dgrad=dgrad, u=fw["u"], grad=fw["grad"])
 
 
+def splat_gradients(params: dict, H: int, W: int, dgrad: np.ndarray, splats) -> dict:
+    """dl/d(mean2d, conic, opacity, value) of the listed splats only, for a
+    given dl/dgrad[6][H][W] (the reverse compositing step of
+    ``gradients_from_du`` restricted to a subset of splats).
+
+    A splat contributes only at pixels of its support box, so its sums run
+    over that box; at each such pixel the whole front-to-back list is formed
+    from the splats whose boxes meet the box (every other splat is zero
+    there), and the splat's own terms are taken from it.  Meant for images
+    too large to composite every pixel.  Returns arrays [.., len(splats)]."""
+    splats = np.asarray(splats, dtype=np.int64)
+    proj = project_2d(params["mean2d"], params["conic"], params["depth"], W, H)
+    alpha = np.asarray(params["opacity"], dtype=np.float64)
+    value = np.asarray(params["value"], dtype=np.float64)
+    dgrad = np.asarray(dgrad, dtype=np.float64)
+    j0, j1, i0, i1 = proj["box"]
+    valid = proj["valid"]
+    n = splats.size
+    out = dict(mean2d=np.zeros((2, n)), conic=np.zeros((3, n)), opacity=np.zeros(n),
+               value=np.zeros((6, n)))
+    for s_, k in enumerate(splats.tolist()):
+        if not valid[k] or j0[k] > j1[k] or i0[k] > i1[k]:
+            continue
+        near = np.nonzero(valid & (j0 <= j1[k]) & (j1 >= j0[k]) & (i0 <= i1[k]) &
+                          (i1 >= i0[k]))[0]            # ascending: index order kept
+        sub = dict(valid=valid[near], box=tuple(b[near] for b in proj["box"]),
+                   mean2d=proj["mean2d"][:, near], conic=proj["conic"][:, near],
+                   depth=proj["depth"][near])
+        me = int(np.searchsorted(near, k))
+        al, va = alpha[near], value[:, near]
+        ca, cb, cc = (proj["conic"][r][k] for r in range(3))
+        for i in range(int(i0[k]), int(i1[k]) + 1):
+            for j in range(int(j0[k]), int(j1[k]) + 1):
+                idx, G, dx, dy = composite.pixel_terms(i, j, sub, al, use_box=True)
+                pos = np.nonzero(idx == me)[0]
+                if pos.size == 0:
+                    continue
+                q = int(pos[0])
+                delta = dgrad[:, i, j]
+                a = al[idx] * G
+                T_prev = np.concatenate([[1.0], np.cumprod(1.0 - a)[:-1]])
+                w = a * T_prev
+                contrib = va[:, idx] * w[None, :]
+                S_q = contrib[:, q + 1:].sum(axis=1)          # sum over the splats behind
+                out["value"][:, s_] += delta * w[q]
+                dl_da = float((delta * (value[:, k] * T_prev[q] - S_q / (1.0 - a[q]))).sum())
+                out["opacity"][s_] += dl_da * G[q]
+                dl_dE = -dl_da * alpha[k] * G[q]
+                ex, ey = dx[q], dy[q]
+                out["mean2d"][0, s_] += dl_dE * (-2.0 * (ca * ex + cb * ey))
+                out["mean2d"][1, s_] += dl_dE * (-2.0 * (cb * ex + cc * ey))
+                out["conic"][0, s_] += dl_dE * ex * ex
+                out["conic"][1, s_] += dl_dE * 2.0 * ex * ey
+                out["conic"][2, s_] += dl_dE * ey * ey
+    return out
+
+
 def support_signature(params: dict, H: int, W: int) -> int:
     """Number of (pixel, splat) pairs inside the support cut-off; a finite
     difference whose two sides differ in this count crossed the cut-off."""
@@ -166,4 +223,5 @@ def finite_difference(params: dict, H: int, W: int, target: np.ndarray, name: st
     return (lp - lm) / (2.0 * h), crossed
 
 
-__all__ = ["forward", "gradients", "finite_difference", "support_signature", "E_CUT"]
+__all__ = ["forward", "gradients", "gradients_from_du", "splat_gradients",
+           "finite_difference", "support_signature", "E_CUT"]

@@ -154,7 +154,7 @@ def backward_error(u: np.ndarray, rho: np.ndarray, boundary=None) -> np.ndarray:
 
 # ---------------------------------------------------------------- Neumann
 # The paper's own boundary condition for the reconstruction is Neumann
-# (Sec. 1.5 and Sec. 2.2, Eq. 21), with the image defined up to a constant.
+# (Sec. 2.1 and Sec. 2.2, Eq. 21), with the image defined up to a constant.
 # Reading used here: every one of the H x W pixels is an unknown and no flux
 # crosses the image border, i.e. the discrete Laplacian at a pixel sums only
 # its neighbours inside the image (these are the normal equations of the

@@ -11,6 +11,6 @@ from .api import (  # noqa: F401
     gdgs_div_adjoint, gdgs_poisson_solve, gdgs_poisson_solve_rhs, gdgs_project,
     gdgs_project_2d, gdgs_project_backward, gdgs_raster_grad, gdgs_raster_grad_backward,
     gdgs_raster_laplacian, gdgs_render, gdgs_render_laplacian, mg_params, new_stats, read_stats,
-    render_workspace_size, workspace, FMG, NEUMANN, RESUME, WARM_START,
+    render_workspace_size, workspace, FMG, NEUMANN, RESUME, STOP_ETA, WARM_START,
 )
 from .serve import Server, now_ns  # noqa: F401

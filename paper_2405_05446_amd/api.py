@@ -52,6 +52,7 @@ WARM_START = 1
 RESUME = 2
 NEUMANN = 4  # no flux across the image border, zero-mean image (boundary must be None)
 FMG = 8      # full-multigrid start of a fresh solve
+STOP_ETA = 16  # stop on the normwise backward error eta instead of the relative correction
 
 
 def mg_params(levels: int = 0, pre: int = 2, post: int = 2, max_cycles: int = 20,
@@ -571,11 +572,14 @@ class Renderer:
             self._set_capacity(int(pairs * 1.25) + 1024)
             self.budget = self.max_cycles
             return self.render(cam, boundary, events, stream)
-        W, H = self.W, self.H
         total = max(st["cycles"])
+        s = stream if stream is not None else torch.cuda.current_stream(self.dev)
         while not st["converged"] and total < self.max_cycles:
             step = min(2, self.max_cycles - total)
-            self._solve(boundary, self._mg(step, RESUME), stream)
+            self._solve(boundary, self._mg(step, RESUME), s)
+            # the resumed cycles run on s, which the current stream need not
+            # follow: wait for s itself before reading the statistics
+            s.synchronize()
             st = read_stats(self.stats)
             total = max(st["cycles"])     # cycle counts accumulate over resumed calls
         st["total_cycles"] = total
@@ -640,6 +644,8 @@ class Renderer:
                 pr, pcam, pi, ps = prev
                 u = pr._finish(pcam, boundary, events[pi] if events else None, ps)
                 r.budget = max(r.budget, pr.budget)
+                if overlap:
+                    caller.wait_stream(ps)   # work on_frame enqueues follows the frame
                 if on_frame is not None:
                     on_frame(pi, u, pr.last)
             prev = (r, cam, i, rs_i)
@@ -647,6 +653,8 @@ class Renderer:
             pr, pcam, pi, ps = prev
             u = pr._finish(pcam, boundary, events[pi] if events else None, ps)
             self.budget = self._twin.budget = pr.budget
+            if overlap:
+                caller.wait_stream(ps)
             if on_frame is not None:
                 on_frame(pi, u, pr.last)
         if overlap:

@@ -152,6 +152,7 @@ struct MgPlan {
     bool resume = false;  // continue the previous solve (setup skipped)
     bool neumann = false; // no flux across the image border, zero-mean gauge
     bool fmg = false;     // full-multigrid start (first cycle of a fresh solve)
+    bool stop_eta = false; // stop on the normwise backward error instead of the correction
 };
 gdgs_status mg_plan(int W, int H, const gdgs_mg_params* mg, MgPlan* plan);
 size_t poisson_ws_bytes(const MgPlan& plan, int W, int H);

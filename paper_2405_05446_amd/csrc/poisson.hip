@@ -21,23 +21,31 @@
 // coarsest grid.
 //
 // Kernels:
-//  * fine grids: one 64x32 tile per workgroup, loaded once with a halo of
-//    2*sweeps+2 into LDS; all sweeps run in LDS (temporal blocking: the valid
-//    region shrinks by one cell per half-sweep), so a pre-smoothing pass reads
-//    u and f once and writes u and the coarse right-hand side once; the
-//    post-smoothing pass stages the coarse correction tile in LDS, adds its
-//    bilinear interpolation, smooths and on the finest grid also produces the
-//    residual and correction norms for the stopping test.  Each thread owns a
-//    fixed segment of one LDS row, so a red or black half-sweep is a strided
-//    loop with no per-cell index arithmetic.  Smoothing is FP32; residuals are
-//    evaluated in FP64 registers, because near convergence the FP32
-//    cancellation noise of f - (sum of neighbours - 4u) would otherwise be fed
-//    to the coarse grids as spurious corrections;
+//  * finest grid (k_fine_pre, k_fine_post): register strips.  A block of four
+//    waves holds 48 rows x 128 columns of the grid in VGPRs (12 rows per wave,
+//    two adjacent columns per lane); column neighbours come from DPP lane
+//    shifts, the rows above and below a wave are exchanged through LDS after
+//    every half-sweep.  The pre pass does its sweeps, writes the smoothed
+//    iterate to the second buffer, evaluates the residual in FP64 registers
+//    and writes its full-weighting restriction; the post pass adds the
+//    bilinear interpolation of the coarse correction, smooths and takes the
+//    residual, iterate and correction norms of the cycle (one partial per
+//    block).  Smoothing is FP32; residuals on this grid are FP64, because near
+//    convergence the FP32 cancellation noise of f - (sum of neighbours - 4u)
+//    would otherwise be fed to the coarse grids as spurious corrections;
+//  * coarse grids too large for one workgroup (k_mg_pre, k_mg_post): 32 x 16
+//    tiles loaded once with a halo of 2*sweeps+2 into LDS, all sweeps in LDS
+//    (temporal blocking: the valid region shrinks by one cell per half-sweep),
+//    so each pass reads u and f once and writes u (and the coarse right-hand
+//    side) once;
 //  * the coarse grids that fit in LDS together are run as a whole V-cycle by
-//    a single workgroup per channel (no launches per coarse level);
-//  * a finalize kernel evaluates eta = ||r||_inf / (8 ||w||_inf + ||b||_inf)
-//    per channel and raises a device flag; every later kernel of a finished
-//    channel returns immediately, so no host synchronisation is needed.
+//    a single workgroup per channel (k_mg_lds: no launches per coarse level);
+//  * a finalize kernel per cycle (k_cycle_finalize) combines the partials of
+//    each channel and applies the stopping rule: the cycle's largest change
+//    of u against the largest |u| (or, under GDGS_MG_STOP_ETA, the normwise
+//    backward error of the residual); a finished channel raises a device flag
+//    and every later kernel of that channel returns at once, so no host
+//    synchronisation is needed.
 #include <functional>
 
 #include "graph.hpp"
@@ -54,8 +62,8 @@ constexpr int kTX = 64, kTY = 32;
 constexpr int kTXs = 32, kTYs = 16;
 constexpr int kTXf = 32, kTYf = 32;   // finest grid
 constexpr int kNTf = 256, kNTs = 256; // threads per block: finest grid, small tiles
-constexpr int kSmallTileBelow = 4096;
-constexpr int kLdsTopCells = 4096;    // largest grid solved inside one workgroup  // blocks of 64 x 32 under which small tiles are used
+constexpr int kSmallTileBelow = 4096; // blocks of 64 x 32 under which small tiles are used
+constexpr int kLdsTopCells = 4096;    // largest grid solved inside one workgroup
 constexpr int kDivTX = 64;
 constexpr int kDivTY = 4;     // threads per block = kDivTX * kDivTY
 constexpr int kDivRows = 16;  // rows per block of the divergence kernel
@@ -1634,7 +1642,8 @@ __global__ __launch_bounds__(kFinThreads) void k_cycle_finalize(const double* __
                                                                const double* __restrict__ bnorm,
                                                                int* __restrict__ done,
                                                                gdgs_stats* __restrict__ stats,
-                                                               double tol, int c0) {
+                                                               double tol, int c0,
+                                                               int stop_eta) {
     __shared__ double sh[3 * (kFinThreads / 64)];
     const int c = c0 + blockIdx.x;
     if (done[c]) return;  // uniform: finished before this cycle
@@ -1668,11 +1677,13 @@ __global__ __launch_bounds__(kFinThreads) void k_cycle_finalize(const double* __
         const double dcyc = dpre + dpost;
         const double rel = umax > 0.0 ? dcyc / umax : (dcyc > 0.0 ? 1.0 : 0.0);
         const double b2 = bnorm[2 * c + 1];
-        stats->eta[c] = rmax / (8.0 * umax + bnorm[2 * c]);
+        const double den = 8.0 * umax + bnorm[2 * c];
+        const double eta = den > 0.0 ? rmax / den : 0.0;
+        stats->eta[c] = eta;
         stats->rel_res[c] = b2 > 0.0 ? sqrt(rss) / b2 : 0.0;
         stats->delta[c] = rel;
         stats->cycles[c] += 1;  // zeroed by setup; accumulates over resumed calls
-        if (rel <= tol) done[c] = 1;
+        if ((stop_eta ? eta : rel) <= tol) done[c] = 1;
     }
 }
 
@@ -1791,7 +1802,8 @@ gdgs_status mg_plan(int W, int H, const gdgs_mg_params* mg, MgPlan* plan) {
                   q.levels, q.pre_sweeps, q.post_sweeps, q.max_cycles, q.tol);
         return GDGS_ERR_INVALID_ARGUMENT;
     }
-    if ((q.flags & ~(GDGS_MG_WARM_START | GDGS_MG_RESUME | GDGS_MG_NEUMANN | GDGS_MG_FMG)) != 0) {
+    if ((q.flags & ~(GDGS_MG_WARM_START | GDGS_MG_RESUME | GDGS_MG_NEUMANN | GDGS_MG_FMG |
+                     GDGS_MG_STOP_ETA)) != 0) {
         set_error("unknown multigrid flags 0x%x", q.flags);
         return GDGS_ERR_INVALID_ARGUMENT;
     }
@@ -1799,6 +1811,7 @@ gdgs_status mg_plan(int W, int H, const gdgs_mg_params* mg, MgPlan* plan) {
     p.resume = (q.flags & GDGS_MG_RESUME) != 0;
     p.neumann = (q.flags & GDGS_MG_NEUMANN) != 0;
     p.fmg = (q.flags & GDGS_MG_FMG) != 0 && !p.resume;
+    p.stop_eta = (q.flags & GDGS_MG_STOP_ETA) != 0;
     p.pre = q.pre_sweeps;
     p.post = q.post_sweeps;
     p.max_cycles = q.max_cycles;
@@ -2113,7 +2126,7 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
     };
     auto finalize = [&](int c0, int nch, hipStream_t s) -> gdgs_status {
         hipLaunchKernelGGL(k_cycle_finalize, dim3(nch), dim3(kFinThreads), 0, s, w.part, nblk,
-                           w.bnorm, w.done, sd, p.tol, c0);
+                           w.bnorm, w.done, sd, p.tol, c0, p.stop_eta ? 1 : 0);
         GDGS_LAUNCH_CHECK();
         return GDGS_OK;
     };

@@ -81,6 +81,42 @@ def test_raster_backward_alone_matches_oracle():
         assert torch.equal(g[name], g3[name])
 
 
+def test_gradients_match_oracle_at_differentiation_workload_on_sampled_splats():
+    """Differentiation workload (512x512, 100k splats): the GPU's gradients of
+    a squared-error loss against the oracle's exact ones on 200 seeded
+    splats.  The oracle takes the loss gradient e = u - target of the GPU's
+    forward image, solves the adjoint Poisson problem exactly (DST-I, zero
+    ring), applies the divergence adjoint and reverse-composites each sampled
+    splat over the pixels of its support box (Sec. 1.1, Eq. 5-7 through
+    Eq. 20/21)."""
+    cfg = wl.CONFIGS["diff"]
+    H, W, K = cfg["H"], cfg["W"], cfg["K"]
+    say(f"[backward] sampled splats vs oracle {W}x{H} K={K}")
+    params = wl.raster_scene(K, W, H, seed=0, ls=cfg["ls"], z=cfg["z"], fx=W)
+    target = (wl.reference_image(H, W, seed=1) - 0.5).astype(np.float32)
+    t = {k: dev(v).requires_grad_(k != "depth") for k, v in params.items()}
+    mg = G.mg_params(tol=1e-7, max_cycles=40)
+    u = diff_render(t["mean2d"], t["conic"], t["opacity"], t["value"], t["depth"], W, H, None, mg)
+    e = torch.zeros_like(u)
+    e[:, 1:-1, 1:-1] = (u - dev(target))[:, 1:-1, 1:-1]
+    (0.5 * (e * e).sum()).backward()
+    torch.cuda.synchronize()
+    # the oracle's reverse chain from the same loss gradient
+    lam = P.solve_dst(np_(e).astype(np.float64), None)
+    dgrad = P.div_adjoint(lam)
+    p64 = {k: v.astype(np.float64) for k, v in params.items()}
+    rng = np.random.default_rng(21)
+    cand = np.nonzero((params["mean2d"][0] > 8) & (params["mean2d"][0] < W - 8) &
+                      (params["mean2d"][1] > 8) & (params["mean2d"][1] < H - 8))[0]
+    splats = np.sort(rng.choice(cand, size=200, replace=False))
+    ref = obk.splat_gradients(p64, H, W, dgrad, splats)
+    for name in ["mean2d", "conic", "opacity", "value"]:
+        got = np_(t[name].grad)[..., splats]
+        err = rel_l2(got, ref[name])
+        say(f"  {name}: rel L2 {err:.2e} over {splats.size} splats")
+        assert err <= 1e-3, name
+
+
 def test_adjoint_identity_at_differentiation_workload_size():
     """u is linear in the gradient values: for the differentiation workload
     (512x512, 100k splats) check <J dv, w> = <dv, J^T w> with J the map from

@@ -1,5 +1,5 @@
 """Neumann variant of the Poisson solve (the paper's boundary condition,
-Sec. 1.5 and Sec. 2.2, Eq. 21) on the GPU through the C ABI: solves against
+Sec. 2.1 and Sec. 2.2, Eq. 21) on the GPU through the C ABI: solves against
 the oracle's exact zero-mean solution at ragged sizes and at 1080p, the
 gradient form recovering an image up to its mean, both render forms against
 the oracle, the Renderer against the entry point, a resumed solve against

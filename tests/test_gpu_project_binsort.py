@@ -39,7 +39,12 @@ def test_project_matches_oracle(name, cfg):
     assert all(_boundary_fluke(o, k) for k in bad), bad[:10]
     live = np.nonzero((g["count"] > 0) & (o["count"] > 0))[0]
     assert live.size > 0.3 * cfg["K"]
-    assert np.array_equal(g["tx0"][live], o["tile_rect"][0][live]) or bad.size
+    # tile rectangles of every live splat that is not an edge fluke
+    sure = np.array([k for k in live if not (k in set(bad.tolist()) or _boundary_fluke(o, k))],
+                    dtype=np.int64)
+    assert sure.size > 0.9 * live.size
+    for w, key in enumerate(("tx0", "tx1", "ty0", "ty1")):
+        assert np.array_equal(g[key][sure], o["tile_rect"][w][sure]), key
     assert fp32_ulp_diff(g["depth"][live], o["depth"][live]).max() <= 1
     np.testing.assert_allclose(g["conic"][:, live], o["conic"][:, live], rtol=2e-6, atol=0)
     mrel_o = o["mean2d"][:, live] - 16 * np.stack([o["tile_rect"][0][live], o["tile_rect"][2][live]])
@@ -83,12 +88,23 @@ def test_bin_sort_is_bit_exact(name, cfg):
     assert np.array_equal(g["tile_order"], np.lexsort((np.arange(T), 32 - bitlen)))
 
 
-def test_bin_sort_matches_oracle_pairs():
-    sc = wl.make_scene(3000, seed=2, z=(2, 6), ls=(-3, 0.6))
-    cam = wl.make_camera(100, 72, pose_index=1)
+@pytest.mark.parametrize("seed,pose", [(2, 1), (4, 6)])
+def test_bin_sort_matches_oracle_pairs(seed, pose):
+    """The GPU's sorted (tile, splat) pairs equal the oracle's, splat by
+    splat: every splat whose support-box edge is not an FP64 rounding fluke
+    has the same pairs in the same order on both sides."""
+    say(f"[bin_sort vs oracle] seed {seed} pose {pose}")
+    sc = wl.make_scene(3000, seed=seed, z=(2, 6), ls=(-3, 0.6))
+    cam = wl.make_camera(100, 72, pose_index=pose)
     g = gpu_stages(sc, cam)
     o = oproject(sc, cam)
     ot, os_ = ob.sorted_pairs(o, 100)
-    gs = g["splats"]
-    if np.array_equal(g["count"], o["count"]):
-        assert np.array_equal(g["tiles"], ot) and np.array_equal(gs, os_)
+    K = sc.K
+    fluke = np.array([_boundary_fluke(o, k) for k in range(K)])
+    diff = g["count"] != o["count"]
+    assert np.all(fluke[diff]), np.nonzero(diff & ~fluke)[0][:10]
+    keep = ~fluke
+    gm, om = keep[g["splats"]], keep[os_]
+    assert gm.sum() > 0.9 * g["splats"].size
+    assert np.array_equal(g["tiles"][gm], ot[om])
+    assert np.array_equal(g["splats"][gm], os_[om])

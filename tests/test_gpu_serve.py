@@ -65,6 +65,60 @@ def test_mixed_equals_alone_and_plain_renderer(scene):
         assert torch.equal(u, alone[i])
 
 
+SERVE_SIZES = [(256, 256), (512, 512), (800, 800), (1920, 1080)]
+
+
+def test_serving_workload_mixed_equals_alone_renderer_and_oracle():
+    """The serving workload's resident 500k-splat scene with two requests of
+    each size (256^2, 512^2, 800^2, 1920x1080): all of them at once over four
+    streams give the same bits as each alone on a one-stream server and as
+    the plain Renderer; at 256^2, 800^2 and 1080p the composite matches the
+    oracle on 300 sampled pixels and the solve matches the exact DST-I solve
+    of the GPU's gradients."""
+    from oracle import poisson as P
+    from oracle.project import project as oproject
+    from tests.gpu_util import gpu_stages, composite_parity
+    cfg = wl.CONFIGS["serve"]
+    say(f"[serve] serving workload, K={cfg['K']}")
+    sc = wl.make_scene(cfg["K"], seed=0, z=cfg["z"], ls=cfg["ls"])
+    ds = G.DeviceScene.from_host(sc)
+    reqs = [(sz, 40 + 2 * k + r) for k, sz in enumerate(SERVE_SIZES) for r in range(2)]
+    ring = {sz: torch.from_numpy(wl.reference_image(sz[1], sz[0], seed=1).astype(np.float32))
+            .cuda() for sz in SERVE_SIZES}
+    mg = G.mg_params(**MG)
+    alone = {}
+    with G.Server(ds, budget=4 << 30, streams=1, mg=mg) as srv:
+        for (W, H), i in reqs:
+            srv.submit(wl.make_camera(W, H, pose_index=i), ring[(W, H)], tag=i)
+            c = srv.drain(1)[0]
+            assert c["status"] == 0 and c["converged"] == 1
+            alone[i] = c["u"].clone()
+    with G.Server(ds, budget=4 << 30, streams=4, mg=mg) as srv:
+        for (W, H), i in reqs[::-1]:
+            srv.submit(wl.make_camera(W, H, pose_index=i), ring[(W, H)], tag=i)
+        done = srv.drain(len(reqs))
+    assert sorted(c["tag"] for c in done) == sorted(i for _, i in reqs)
+    for c in done:
+        assert c["status"] == 0 and c["converged"] == 1
+        assert torch.equal(c["u"], alone[c["tag"]]), c["tag"]
+    for (W, H), i in reqs[::2]:
+        r = G.Renderer(ds, W, H, mg)
+        u = r.render(wl.make_camera(W, H, pose_index=i), ring[(W, H)])
+        torch.cuda.synchronize()
+        assert torch.equal(u, alone[i]), (W, H)
+    for (W, H), i in [reqs[0], reqs[4], reqs[6]]:
+        cam = wl.make_camera(W, H, pose_index=i)
+        g = gpu_stages(sc, cam)
+        o = oproject(sc, cam)
+        rows, cols = wl.sample_pixels(H, W, 300, seed=30 + i)
+        e1, ties = composite_parity(g, o, sc, H, W, rows, cols)
+        exact = P.solve_dst(P.divergence(g["grad"].astype(np.float32)),
+                            np_(ring[(W, H)]).astype(np.float64))
+        e2 = np.abs(np_(alone[i]) - exact).max()
+        say(f"  {W}x{H}: composite max-abs {e1:.3e} ({ties} tie pixels), solve max-abs {e2:.3e}")
+        assert e2 <= 1e-4
+
+
 def test_small_view_against_the_oracle(scene):
     sc, ds = scene
     W, H = 64, 48

@@ -1,4 +1,4 @@
-"""Pins of the oracle's Neumann solve (Sec. 1.5 and Sec. 2.2, Eq. 21: no flux
+"""Pins of the oracle's Neumann solve (Sec. 2.1 and Sec. 2.2, Eq. 21: no flux
 across the image border, image defined up to a constant, fixed here by a
 zero mean).  Checked against two independent exact methods (bordered dense
 LU and the cosine transform), against the least-squares gradient fit the
