@@ -417,10 +417,26 @@ gdgs_status gdgs_raster_grad_backward(const gdgs_proj* proj, const float* opacit
  * outlive the server.  All calls are thread-safe. */
 typedef struct gdgs_server gdgs_server;
 
+/* Server flag: batched solves.  A request's stream carries its projection,
+ * binning, compositing and the solve's set-up; the request then joins a
+ * device table of up to 64 in-flight solves and gives its stream back.  A
+ * separate solver stream runs rounds, each one V-cycle of every solve in the
+ * table: every kernel of a round is a persistent grid whose workgroups take
+ * the tasks of all the solves (finest-grid strips, coarse-grid tiles, in-LDS
+ * coarse V-cycles, end-of-cycle bookkeeping) from the table.  Each task runs
+ * the same code as the per-request kernels, so results are bit for bit those
+ * of gdgs_render alone.  A solve that has converged (or reached
+ * mg.max_cycles) leaves the table and is reported through a completion ring
+ * in pinned host memory.  The solve runs in the request's u directly.
+ * Dirichlet problem only (mg.flags 0); streams + 1 HIP streams are used. */
+#define GDGS_SERVER_BATCHED 1
+
 typedef struct gdgs_server_params {
     int64_t hbm_budget;   /* bytes of device memory for in-flight requests */
-    int32_t streams;      /* requests in flight at once, 1..16 (1 = plain FIFO) */
-    int32_t reserved;     /* 0 */
+    int32_t streams;      /* requests whose front half (projection .. set-up, or the
+                             whole render without GDGS_SERVER_BATCHED) runs at once,
+                             1..16 (1 and no flags = plain FIFO) */
+    int32_t flags;        /* 0 or GDGS_SERVER_BATCHED */
     gdgs_mg_params mg;    /* solver parameters of every request; flags 0 or
                              GDGS_MG_NEUMANN (then requests take no boundary) */
 } gdgs_server_params;

@@ -73,7 +73,7 @@ class Stats(ctypes.Structure):
 
 class ServerParams(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_int64), ("streams", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("mg", MgParams)]
+                ("flags", ctypes.c_int32), ("mg", MgParams)]
 
 
 class Request(ctypes.Structure):

@@ -170,6 +170,42 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
 gdgs_status launch_div_adjoint(const float* lam, int W, int H, float* dgrad, hipStream_t st,
                                bool neumann = false);
 
+// ---------------------------------------------------------------- batched solves
+// Up to kBatchMax Dirichlet solves advance together, one V-cycle of every
+// active solve per round (see poisson.hip).  Completions are written to a
+// ring in host memory (pinned, allocated by the caller).
+constexpr int kBatchMax = 64;
+constexpr int kRingCap = 256;
+struct BatchRec {
+    long long id;
+    int cycles;
+    int converged;
+    double eta;
+    double rel_res;
+};
+struct BatchRing {
+    long long head;   // records written so far; record k is rec[k % kRingCap]
+    long long pad[7];
+    BatchRec rec[kRingCap];
+};
+size_t batch_table_bytes();
+// true if the batched kernels can run this plan (Dirichlet, no FMG or resume,
+// small tiles on every global coarse grid)
+bool batch_supported(const MgPlan& p);
+int batch_depth(const MgPlan& p);  // global coarse grids below the finest
+gdgs_status batch_clear(void* table, hipStream_t st);
+// the solve's set-up (divergence, right-hand-side norms, flags) in its workspace
+gdgs_status launch_poisson_setup(const float* grad, const float* boundary, int W, int H,
+                                 const MgPlan& p, float* u, gdgs_stats* stats, void* ws,
+                                 hipStream_t st);
+gdgs_status batch_activate(void* table, int e, int64_t id, const float* grad, int W, int H,
+                           const MgPlan& p, float* u, gdgs_stats* stats, void* ws,
+                           hipStream_t st);
+gdgs_status batch_deactivate(void* table, int e, hipStream_t st);
+// one V-cycle of every active solve whose global coarse grids are <= depth
+gdgs_status launch_batch_round(void* table, BatchRing* ring, int depth, int pre, int post,
+                               hipStream_t st);
+
 // ---------------------------------------------------------------- whole frame
 // Everything one render carves out of its workspace.
 struct RenderWs {

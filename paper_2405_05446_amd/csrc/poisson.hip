@@ -46,6 +46,7 @@
 //    backward error of the residual); a finished channel raises a device flag
 //    and every later kernel of that channel returns at once, so no host
 //    synchronisation is needed.
+#include <cstring>
 #include <functional>
 
 #include "graph.hpp"
@@ -544,6 +545,7 @@ struct RegionRegs {
 // launch covers channels c0 .. c0 + gridDim.z - 1.
 struct TileId {
     int tx, ty, c;
+    __device__ TileId(int tx_, int ty_, int c_) : tx(tx_), ty(ty_), c(c_) {}
     __device__ explicit TileId(int c0) {
         const int gx = gridDim.x, gy = gridDim.y;
         const int nb = gx * gy * gridDim.z;
@@ -565,9 +567,10 @@ struct TileId {
 // channel returns at once on the finest grid; on coarser grids, whose blocks
 // are few and latency-bound, the done flag is read together with the tile.
 template <int NU, bool FINE, int TX, int TY, int NT, bool NM>
-__global__ __launch_bounds__(NT) void k_mg_pre(LevelDev L, LevelDev C, int zero_guess,
-                                                const int* __restrict__ done,
-                                                double* __restrict__ part, int c0) {
+__device__ __forceinline__ void mg_pre_tile(const LevelDev& L, const LevelDev& C, int zero_guess,
+                                            const int* __restrict__ done,
+                                            double* __restrict__ part, const TileId id, int gx,
+                                            int gy) {
     constexpr int HALO = 2 * NU + 2;
     constexpr int CPT = TX * TY / NT;
     constexpr int RX = TX + 2 * HALO, RY = TY + 2 * HALO;
@@ -575,7 +578,6 @@ __global__ __launch_bounds__(NT) void k_mg_pre(LevelDev L, LevelDev C, int zero_
     __shared__ float sf[RY * RX];
     __shared__ float s_trash[NT];
     __shared__ double sh[3 * (NT / 64)];
-    const TileId id(c0);
     const int c = id.c;
     if (FINE && done[c]) return;
     const int dn = FINE ? 0 : done[c];
@@ -665,19 +667,28 @@ __global__ __launch_bounds__(NT) void k_mg_pre(LevelDev L, LevelDev C, int zero_
         double d1 = 0.0, d2 = 0.0;
         block_reduce3(dmax, d1, d2, sh);
         if (threadIdx.x == 0) {
-            const int nblk = gridDim.x * gridDim.y;
-            part[((size_t)c * nblk + id.ty * gridDim.x + id.tx) * 5 + 3] = dmax;
+            const int nblk = gx * gy;
+            part[((size_t)c * nblk + id.ty * gx + id.tx) * 5 + 3] = dmax;
         }
     }
+}
+
+template <int NU, bool FINE, int TX, int TY, int NT, bool NM>
+__global__ __launch_bounds__(NT) void k_mg_pre(LevelDev L, LevelDev C, int zero_guess,
+                                                const int* __restrict__ done,
+                                                double* __restrict__ part, int c0) {
+    mg_pre_tile<NU, FINE, TX, TY, NT, NM>(L, C, zero_guess, done, part, TileId(c0), gridDim.x,
+                                          gridDim.y);
 }
 
 // Prolongation + correction + post-smoothing.  FINE (the finest grid only):
 // also the residual and correction norms of the cycle.  The done flag is
 // handled as in k_mg_pre.
 template <int NU, bool FINE, int TX, int TY, int NT, bool NM>
-__global__ __launch_bounds__(NT) void k_mg_post(LevelDev L, LevelDev C,
-                                                 const int* __restrict__ done,
-                                                 double* __restrict__ part, int c0) {
+__device__ __forceinline__ void mg_post_tile(const LevelDev& L, const LevelDev& C,
+                                             const int* __restrict__ done,
+                                             double* __restrict__ part, const TileId id, int gx,
+                                             int gy) {
     constexpr bool NORM = FINE;
     constexpr int HALO = 2 * NU + 2;
     constexpr int CPT = TX * TY / NT;
@@ -688,7 +699,6 @@ __global__ __launch_bounds__(NT) void k_mg_post(LevelDev L, LevelDev C,
     __shared__ float se[CY * CX];
     __shared__ float s_trash[NT];
     __shared__ double sh[3 * (NT / 64)];
-    const TileId id(c0);
     const int c = id.c;
     if (FINE && done[c]) return;
     const int dn = FINE ? 0 : done[c];
@@ -791,8 +801,8 @@ __global__ __launch_bounds__(NT) void k_mg_post(LevelDev L, LevelDev C,
         double d1 = 0.0, d2 = 0.0;
         block_reduce3(dmax, d1, d2, sh);
         if (threadIdx.x == 0) {
-            const int nblk = gridDim.x * gridDim.y;
-            const int blk = id.ty * gridDim.x + id.tx;
+            const int nblk = gx * gy;
+            const int blk = id.ty * gx + id.tx;
             double* p = part + ((size_t)c * nblk + blk) * 5;
             p[0] = rmax;
             p[1] = umax;
@@ -800,6 +810,13 @@ __global__ __launch_bounds__(NT) void k_mg_post(LevelDev L, LevelDev C,
             p[4] = dmax;
         }
     }
+}
+
+template <int NU, bool FINE, int TX, int TY, int NT, bool NM>
+__global__ __launch_bounds__(NT) void k_mg_post(LevelDev L, LevelDev C,
+                                                 const int* __restrict__ done,
+                                                 double* __restrict__ part, int c0) {
+    mg_post_tile<NU, FINE, TX, TY, NT, NM>(L, C, done, part, TileId(c0), gridDim.x, gridDim.y);
 }
 
 // ---------------------------------------------------------------- finest grid in register strips
@@ -836,6 +853,18 @@ __device__ __forceinline__ float from_right(float v) {
 // the grid column of its lane's even column.
 struct Strip {
     int c, tile, gi0, gj0, r0, je, lane, w;
+    // strip `tile` of channel c (tiles_x strips per row of strips)
+    __device__ Strip(int c_, int tile_, int tiles_x) {
+        c = c_;
+        tile = tile_;
+        const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+        gi0 = ty * kSTY - kSH;
+        gj0 = tx * kSTX - kSH;
+        w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        lane = threadIdx.x & 63;
+        r0 = w * kSWR;
+        je = gj0 + 2 * lane;
+    }
     __device__ Strip(int c0, int tiles_x) {
         const int nbx = gridDim.x, nb = nbx * gridDim.y;
         const int Lb = xcd_remap(blockIdx.x + nbx * blockIdx.y, nb);
@@ -1521,11 +1550,9 @@ __device__ void lds_wave_tail(const LdsPlan& P, float* lds, int lane, float* tra
 }
 
 template <bool NM>
-__global__ __launch_bounds__(kLdsThreads) void k_mg_lds(LdsPlan P, const int* __restrict__ done,
-                                                        double* __restrict__ part, int c0) {
-    extern __shared__ float lds[];
-    __shared__ double sh[3 * (kLdsThreads / 64)];
-    const int c = c0 + blockIdx.x;
+__device__ __forceinline__ void mg_lds_task(const LdsPlan& P, const int* __restrict__ done,
+                                            double* __restrict__ part, int c, float* lds,
+                                            double* sh) {
     const int lc = P.lc, L = P.L, t = threadIdx.x;
     // load the top level (the done flag is read together with its first
     // chunk); clear the coarser grids and the residuals (their rings stay zero
@@ -1631,21 +1658,25 @@ __global__ __launch_bounds__(kLdsThreads) void k_mg_lds(LdsPlan P, const int* __
     }
 }
 
+template <bool NM>
+__global__ __launch_bounds__(kLdsThreads) void k_mg_lds(LdsPlan P, const int* __restrict__ done,
+                                                        double* __restrict__ part, int c0) {
+    extern __shared__ float lds[];
+    __shared__ double sh[3 * (kLdsThreads / 64)];
+    mg_lds_task<NM>(P, done, part, c0 + blockIdx.x, lds, sh);
+}
+
 // End-of-cycle bookkeeping, one block per channel still running: reduce the
 // per-block partials, write the statistics, raise the channel's flag when the
 // relative correction is <= tol.  (Only these blocks synchronise through
 // memory: a device-scope fence per block of a large grid would write back
 // the L2 of its die each time.)
 constexpr int kFinThreads = 256;
-__global__ __launch_bounds__(kFinThreads) void k_cycle_finalize(const double* __restrict__ part,
-                                                               int nblk,
-                                                               const double* __restrict__ bnorm,
-                                                               int* __restrict__ done,
-                                                               gdgs_stats* __restrict__ stats,
-                                                               double tol, int c0,
-                                                               int stop_eta) {
-    __shared__ double sh[3 * (kFinThreads / 64)];
-    const int c = c0 + blockIdx.x;
+__device__ __forceinline__ void finalize_task(const double* __restrict__ part, int nblk,
+                                              const double* __restrict__ bnorm,
+                                              int* __restrict__ done,
+                                              gdgs_stats* __restrict__ stats, double tol, int c,
+                                              int stop_eta, double* sh) {
     if (done[c]) return;  // uniform: finished before this cycle
     double rmax = 0.0, umax = 0.0, rss = 0.0, dpre = 0.0, dpost = 0.0;
     // two blocks' partials per thread and round, loaded before use
@@ -1685,6 +1716,17 @@ __global__ __launch_bounds__(kFinThreads) void k_cycle_finalize(const double* __
         stats->cycles[c] += 1;  // zeroed by setup; accumulates over resumed calls
         if ((stop_eta ? eta : rel) <= tol) done[c] = 1;
     }
+}
+
+__global__ __launch_bounds__(kFinThreads) void k_cycle_finalize(const double* __restrict__ part,
+                                                               int nblk,
+                                                               const double* __restrict__ bnorm,
+                                                               int* __restrict__ done,
+                                                               gdgs_stats* __restrict__ stats,
+                                                               double tol, int c0,
+                                                               int stop_eta) {
+    __shared__ double sh[3 * (kFinThreads / 64)];
+    finalize_task(part, nblk, bnorm, done, stats, tol, c0 + blockIdx.x, stop_eta, sh);
 }
 
 // ---------------------------------------------------------------- divergence adjoint
@@ -1994,14 +2036,12 @@ size_t poisson_ws_bytes(const MgPlan& plan, int W, int H) {
     return poisson_layout(plan, W, H, nullptr, nullptr);
 }
 
-gdgs_status launch_poisson(const float* grad, const float* rho, const float* boundary, int W,
-                           int H, const MgPlan& p, float* u, gdgs_stats* stats, void* ws,
-                           hipStream_t st, const KeyBuilder* key, bool channel_parallel) {
-    PoissonWs w;
-    poisson_layout(p, W, H, ws, &w);
-    gdgs_stats* sd = stats ? stats : w.stats;
+namespace {
+// The grids of one solve: level 0 is the caller's image (Dirichlet) or the
+// padded workspace array (Neumann), coarser levels live in the workspace.
+void build_levels(const MgPlan& p, const PoissonWs& w, float* u, const float* grad,
+                  const float* rho, LevelDev* lev) {
     const bool nm = p.neumann;
-    LevelDev lev[kMaxLevels];
     lev[0].u = nm ? w.u0 : u;
     lev[0].ub = w.u0b;
     lev[0].f = (grad || nm) ? w.f0 : rho;
@@ -2037,6 +2077,29 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
             v.wy = v.wx = kNmW;
         }
     }
+}
+
+LdsPlan full_lds_plan(const MgPlan& p, const LevelDev* lev) {
+    LdsPlan lp = lds_plan(p, lev);
+    lp.fofs = lev[0].fofs;
+    lp.pre = p.pre;
+    lp.post = p.post;
+    lp.csweeps = p.coarse_sweeps;
+    lp.omega = p.omega;
+    lp.top = lev[p.lc];
+    return lp;
+}
+}  // namespace
+
+gdgs_status launch_poisson(const float* grad, const float* rho, const float* boundary, int W,
+                           int H, const MgPlan& p, float* u, gdgs_stats* stats, void* ws,
+                           hipStream_t st, const KeyBuilder* key, bool channel_parallel) {
+    PoissonWs w;
+    poisson_layout(p, W, H, ws, &w);
+    gdgs_stats* sd = stats ? stats : w.stats;
+    const bool nm = p.neumann;
+    LevelDev lev[kMaxLevels];
+    build_levels(p, w, u, grad, rho, lev);
     const int nblk_div = setup_blocks(p, W, H);
     const dim3 grid_pad((W + 2 + kDivTX - 1) / kDivTX, (H + 2 + kDivRows - 1) / kDivRows, 3);
     auto setup = [&](hipStream_t s) -> gdgs_status {
@@ -2070,13 +2133,7 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
         return GDGS_OK;
     };
 
-    LdsPlan lp = lds_plan(p, lev);
-    lp.fofs = lev[0].fofs;
-    lp.pre = p.pre;
-    lp.post = p.post;
-    lp.csweeps = p.coarse_sweeps;
-    lp.omega = p.omega;
-    lp.top = lev[p.lc];
+    const LdsPlan lp = full_lds_plan(p, lev);
     const int nblk = norm_blocks(p);
     // channels c0 .. c0 + nch - 1 of one grid pass.  pre_nu: nu sweeps (0: the
     // residual of the current iterate restricted, nothing smoothed), from zero
@@ -2292,6 +2349,397 @@ gdgs_status launch_div_adjoint(const float* lam, int W, int H, float* dgrad, hip
         hipLaunchKernelGGL(k_div_adjoint_nm, grid, dim3(kDivTX * kDivTY), 0, st, lam, H, W, dgrad);
     else
         hipLaunchKernelGGL(k_div_adjoint, grid, dim3(kDivTX * kDivTY), 0, st, lam, H, W, dgrad);
+    GDGS_LAUNCH_CHECK();
+    return GDGS_OK;
+}
+
+
+// ---------------------------------------------------------------- batched solves
+// Many Dirichlet solves advance together, one V-cycle per "round": a table of
+// up to kBatchMax in-flight solves lives in device memory, and every kernel of
+// a round is a persistent grid whose workgroups take the tasks of all active
+// solves at one step (a finest-grid strip, a coarse-grid tile, an in-LDS
+// coarse V-cycle, a channel's end-of-cycle bookkeeping) from that table, in a
+// grid-stride loop.  Each task runs the same device code on the same tile as
+// the per-solve kernels, so a solve's result is the same bit for bit alone, in
+// any mix, and on the per-solve path.  A solve leaves the table when all its
+// channels have converged (or max_cycles is reached); the round's last kernel
+// then appends a record to a completion ring in host memory.
+namespace {
+
+struct BatchSolve {
+    LevelDev lev[kMaxLevels];
+    LdsPlan lp;
+    int active;     // takes part in rounds
+    int reported;   // its completion record has been written (device)
+    int lc;         // first grid held in LDS
+    int fine_tiles, fine_tx;  // register strips of the finest grid (per channel, per strip row)
+    int gx[kMaxLevels], gy[kMaxLevels];  // 32 x 16 tiles of each global coarse grid
+    int nblk;       // norm partials per channel
+    int stop_eta, max_cycles;
+    double tol;
+    double* part;
+    double* bnorm;
+    int* done;
+    gdgs_stats* stats;
+    long long id;
+};
+
+struct BatchTable {
+    long long ring_head;  // records written so far (the device's copy)
+    long long pad[7];
+    BatchSolve e[kBatchMax];
+};
+
+enum : int { kBFinePre = 0, kBFinePost, kBPre, kBPost, kBLds, kBFin };
+
+__device__ __forceinline__ int batch_tasks(const BatchSolve& b, int kind, int l) {
+    if (!b.active) return 0;
+    if (kind == kBFinePre || kind == kBFinePost) return b.lc > 0 ? 3 * b.fine_tiles : 0;
+    if (kind == kBPre || kind == kBPost) return (l >= 1 && l < b.lc) ? 3 * b.gx[l] * b.gy[l] : 0;
+    return 3;  // in-LDS V-cycle, finalize: one task per channel
+}
+
+// pref[e] = tasks of entries before e (wave 0 scans the kBatchMax = 64
+// entries, one per lane); returns the total.
+__device__ int batch_prefix(const BatchTable* __restrict__ T, int kind, int l, int* pref) {
+    static_assert(kBatchMax == 64, "one wave scans the table");
+    if (threadIdx.x < 64) {
+        const int e = threadIdx.x;
+        int v = batch_tasks(T->e[e], kind, l);
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(v, d, 64);
+            if (e >= d) v += y;
+        }
+        pref[e + 1] = v;
+        if (e == 0) pref[0] = 0;
+    }
+    __syncthreads();
+    return pref[kBatchMax];
+}
+
+// The entry holding task q: the largest e with pref[e] <= q (an entry with
+// tasks, since q < total).
+__device__ __forceinline__ int batch_find(const int* pref, int q) {
+    int lo = 0, hi = kBatchMax;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pref[mid] <= q)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Task v of a grid-stride loop: the entry and the task's index inside it.
+// Grids are multiples of the 8 XCDs, so every XCD takes a contiguous range of
+// tasks (neighbouring tiles meet in one L2), as in the per-solve kernels.
+struct BatchTask {
+    int e, loc;
+    __device__ BatchTask(const int* pref, int v, int total) {
+        const int q = xcd_remap(v, total);
+        e = __builtin_amdgcn_readfirstlane(batch_find(pref, q));
+        loc = __builtin_amdgcn_readfirstlane(q - pref[e]);
+    }
+};
+
+template <int NU, bool PRE>
+__global__ __launch_bounds__(64 * kSNW) void k_batch_fine(const BatchTable* __restrict__ T) {
+    __shared__ int pref[kBatchMax + 1];
+    __shared__ float2 sx[2][kSNW][2][64];
+    const int total = batch_prefix(T, PRE ? kBFinePre : kBFinePost, 0, pref);
+    for (int v = blockIdx.x; v < total; v += gridDim.x) {
+        const BatchTask k(pref, v, total);
+        const BatchSolve& B = T->e[k.e];
+        const int nt = B.fine_tiles;
+        const int c = k.loc / nt, tile = k.loc - c * nt;
+        __syncthreads();  // the previous task is done with the LDS
+        if (B.done[c]) continue;  // uniform over the block
+        const Strip S(c, tile, B.fine_tx);
+        const LevelDev& L = B.lev[0];
+        const LevelDev& C = B.lev[1];
+        if (PRE) {
+            if (S.interior(L))
+                fine_pre_body<NU, true, false>(L, C, B.part, nt, S, sx);
+            else
+                fine_pre_body<NU, false, false>(L, C, B.part, nt, S, sx);
+        } else {
+            if (S.interior(L))
+                fine_post_body<NU, true, false>(L, C, B.part, nt, S, sx);
+            else
+                fine_post_body<NU, false, false>(L, C, B.part, nt, S, sx);
+        }
+    }
+}
+
+template <int NU, bool PRE>
+__global__ __launch_bounds__(kNTs) void k_batch_mg(const BatchTable* __restrict__ T, int l) {
+    __shared__ int pref[kBatchMax + 1];
+    const int total = batch_prefix(T, PRE ? kBPre : kBPost, l, pref);
+    for (int v = blockIdx.x; v < total; v += gridDim.x) {
+        const BatchTask k(pref, v, total);
+        const BatchSolve& B = T->e[k.e];
+        const int gx = B.gx[l], gy = B.gy[l], per = gx * gy;
+        const int c = k.loc / per, t = k.loc - c * per;
+        const int ty = t / gx, tx = t - ty * gx;
+        __syncthreads();
+        if (PRE)
+            mg_pre_tile<NU, false, kTXs, kTYs, kNTs, false>(B.lev[l], B.lev[l + 1], 1, B.done,
+                                                            B.part, TileId(tx, ty, c), gx, gy);
+        else
+            mg_post_tile<NU, false, kTXs, kTYs, kNTs, false>(B.lev[l], B.lev[l + 1], B.done,
+                                                             B.part, TileId(tx, ty, c), gx, gy);
+    }
+}
+
+__global__ __launch_bounds__(kLdsThreads) void k_batch_lds(const BatchTable* __restrict__ T) {
+    extern __shared__ float lds[];
+    __shared__ double sh[3 * (kLdsThreads / 64)];
+    __shared__ int pref[kBatchMax + 1];
+    const int total = batch_prefix(T, kBLds, 0, pref);
+    for (int v = blockIdx.x; v < total; v += gridDim.x) {
+        const BatchTask k(pref, v, total);
+        const BatchSolve& B = T->e[k.e];
+        __syncthreads();
+        mg_lds_task<false>(B.lp, B.done, B.part, k.loc, lds, sh);
+    }
+}
+
+__global__ __launch_bounds__(kFinThreads) void k_batch_finalize(const BatchTable* __restrict__ T) {
+    __shared__ double sh[3 * (kFinThreads / 64)];
+    __shared__ int pref[kBatchMax + 1];
+    const int total = batch_prefix(T, kBFin, 0, pref);
+    for (int v = blockIdx.x; v < total; v += gridDim.x) {
+        const BatchTask k(pref, v, total);
+        const BatchSolve& B = T->e[k.e];
+        __syncthreads();
+        finalize_task(B.part, B.nblk, B.bnorm, B.done, B.stats, B.tol, k.loc, B.stop_eta, sh);
+    }
+}
+
+// One wave, lane e = entry e: a solve whose channels have all converged (or
+// that has reached max_cycles) stops taking work and gets a completion record
+// in the host ring, in entry order; then the ring's head is published.
+__global__ __launch_bounds__(64) void k_batch_complete(BatchTable* __restrict__ T,
+                                                        BatchRing* __restrict__ ring) {
+    const int e = threadIdx.x;
+    BatchSolve& B = T->e[e];
+    bool rep = false;
+    int cyc = 0, all = 0;
+    double eta = 0.0, rr = 0.0;
+    if (B.active && !B.reported) {
+        int* d = B.done;
+        gdgs_stats* st = B.stats;
+        all = d[0] && d[1] && d[2];
+        cyc = max(st->cycles[0], max(st->cycles[1], st->cycles[2]));
+        if (all || cyc >= B.max_cycles) {
+            rep = true;
+            st->converged = all;
+            if (!all) d[0] = d[1] = d[2] = 1;  // no further work for it
+            B.reported = 1;
+            eta = fmax(st->eta[0], fmax(st->eta[1], st->eta[2]));
+            rr = fmax(st->rel_res[0], fmax(st->rel_res[1], st->rel_res[2]));
+        }
+    }
+    const unsigned long long m = __ballot(rep);
+    const long long head = T->ring_head;
+    if (rep) {
+        const long long k = head + __popcll(m & ((1ull << e) - 1ull));
+        BatchRec* r = &ring->rec[k % kRingCap];
+        __hip_atomic_store(&r->id, B.id, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&r->cycles, cyc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&r->converged, all, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&r->eta, eta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&r->rel_res, rr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");  // system scope: the records before the head
+    if (e == 0 && m != 0ull) {
+        const long long nh = head + __popcll(m);
+        T->ring_head = nh;
+        __hip_atomic_store(&ring->head, nh, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+// Entry e <- v (v travels as a kernel argument, so the host keeps no staging
+// buffer alive); active 0 only clears the entry's flag.
+__global__ void k_batch_set(BatchTable* __restrict__ T, int e, BatchSolve v, int whole) {
+    if (!whole) {
+        if (threadIdx.x == 0) T->e[e].active = 0;
+        return;
+    }
+    static_assert(sizeof(BatchSolve) % 4 == 0, "copied as 32-bit words");
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(&v);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&T->e[e]);
+    for (int i = threadIdx.x; i < (int)(sizeof(BatchSolve) / 4); i += blockDim.x) dst[i] = src[i];
+}
+
+__global__ void k_batch_clear(BatchTable* __restrict__ T) {
+    if (threadIdx.x == 0) T->ring_head = 0;
+    if (threadIdx.x < kBatchMax) {
+        T->e[threadIdx.x].active = 0;
+        T->e[threadIdx.x].reported = 1;
+    }
+}
+
+// Persistent grid of a kernel: the workgroups resident at once on the whole
+// chip (occupancy x compute units), a multiple of the 8 XCDs.
+int persistent_grid(const void* fn, int threads, size_t dyn_lds) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, threads, dyn_lds) != hipSuccess ||
+        cus <= 0 || per <= 0) {
+        (void)hipGetLastError();
+        return 8 * kXcds;
+    }
+    const int g = cus * per;
+    return g < kXcds ? kXcds : g / kXcds * kXcds;
+}
+
+}  // namespace
+
+size_t batch_table_bytes() { return sizeof(BatchTable); }
+
+bool batch_supported(const MgPlan& p) {
+    if (p.neumann || p.fmg || p.resume) return false;
+    for (int l = 1; l < p.lc; ++l) {
+        const int nb = ((p.m[l] + 2 + kTX - 1) / kTX) * ((p.n[l] + 2 + kTY - 1) / kTY) * 3;
+        if (nb >= kSmallTileBelow) return false;  // the batched kernels use the small tiles
+    }
+    return true;
+}
+
+int batch_depth(const MgPlan& p) { return p.lc > 1 ? p.lc - 1 : 0; }
+
+gdgs_status batch_clear(void* table, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_clear, dim3(1), dim3(kBatchMax), 0, st,
+                       static_cast<BatchTable*>(table));
+    GDGS_LAUNCH_CHECK();
+    return GDGS_OK;
+}
+
+gdgs_status launch_poisson_setup(const float* grad, const float* boundary, int W, int H,
+                                 const MgPlan& p, float* u, gdgs_stats* stats, void* ws,
+                                 hipStream_t st) {
+    if (!batch_supported(p)) {
+        set_error("this solve cannot run batched");
+        return GDGS_ERR_UNSUPPORTED;
+    }
+    PoissonWs w;
+    poisson_layout(p, W, H, ws, &w);
+    gdgs_stats* sd = stats ? stats : w.stats;
+    hipLaunchKernelGGL(k_div_init, dim3((W + kDivTX - 1) / kDivTX, (H + kDivRows - 1) / kDivRows, 3),
+                       dim3(kDivTX * kDivTY), 0, st, grad, nullptr, boundary, H, W, w.f0, u,
+                       w.bpart, w.counters, p.warm ? 1 : 0);
+    hipLaunchKernelGGL(k_setup_finalize, dim3(3), dim3(256), 0, st, w.bpart,
+                       setup_blocks(p, W, H), w.bnorm, w.done, w.counters, sd, p.warm ? 1 : 0);
+    GDGS_LAUNCH_CHECK();
+    return GDGS_OK;
+}
+
+gdgs_status batch_activate(void* table, int e, int64_t id, const float* grad, int W, int H,
+                           const MgPlan& p, float* u, gdgs_stats* stats, void* ws,
+                           hipStream_t st) {
+    if (e < 0 || e >= kBatchMax || !batch_supported(p)) {
+        set_error("bad batch entry %d or unsupported solve", e);
+        return GDGS_ERR_INVALID_ARGUMENT;
+    }
+    PoissonWs w;
+    poisson_layout(p, W, H, ws, &w);
+    BatchSolve b;
+    std::memset(&b, 0, sizeof(b));
+    build_levels(p, w, u, grad, nullptr, b.lev);
+    b.lp = full_lds_plan(p, b.lev);
+    b.active = 1;
+    b.reported = 0;
+    b.lc = p.lc;
+    b.fine_tiles = strip_tiles(p.n[0], p.m[0]);
+    b.fine_tx = strip_tiles_x(p.m[0]);
+    for (int l = 1; l < p.levels; ++l) {
+        b.gx[l] = (p.m[l] + 2 + kTXs - 1) / kTXs;
+        b.gy[l] = (p.n[l] + 2 + kTYs - 1) / kTYs;
+    }
+    b.nblk = norm_blocks(p);
+    b.stop_eta = p.stop_eta ? 1 : 0;
+    b.max_cycles = p.max_cycles;
+    b.tol = p.tol;
+    b.part = w.part;
+    b.bnorm = w.bnorm;
+    b.done = w.done;
+    b.stats = stats ? stats : w.stats;
+    b.id = (long long)id;
+    hipLaunchKernelGGL(k_batch_set, dim3(1), dim3(256), 0, st, static_cast<BatchTable*>(table),
+                       e, b, 1);
+    GDGS_LAUNCH_CHECK();
+    return GDGS_OK;
+}
+
+gdgs_status batch_deactivate(void* table, int e, hipStream_t st) {
+    BatchSolve b;
+    std::memset(&b, 0, sizeof(b));
+    hipLaunchKernelGGL(k_batch_set, dim3(1), dim3(64), 0, st, static_cast<BatchTable*>(table),
+                       e, b, 0);
+    GDGS_LAUNCH_CHECK();
+    return GDGS_OK;
+}
+
+gdgs_status launch_batch_round(void* table, BatchRing* ring, int depth, int pre, int post,
+                               hipStream_t st) {
+    static int g_fine[2][2], g_mg[2][2], g_lds, g_fin;
+    static bool sized = false;
+    const size_t lds_bytes = (size_t)lds_budget();
+    if (!sized) {
+        if (hipFuncSetAttribute((const void*)k_batch_lds,
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds_bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("cannot reserve %zu bytes of LDS for the batched coarse solve", lds_bytes);
+            return GDGS_ERR_HIP;
+        }
+        g_fine[0][0] = persistent_grid((const void*)k_batch_fine<1, true>, 64 * kSNW, 0);
+        g_fine[0][1] = persistent_grid((const void*)k_batch_fine<2, true>, 64 * kSNW, 0);
+        g_fine[1][0] = persistent_grid((const void*)k_batch_fine<1, false>, 64 * kSNW, 0);
+        g_fine[1][1] = persistent_grid((const void*)k_batch_fine<2, false>, 64 * kSNW, 0);
+        g_mg[0][0] = persistent_grid((const void*)k_batch_mg<1, true>, kNTs, 0);
+        g_mg[0][1] = persistent_grid((const void*)k_batch_mg<2, true>, kNTs, 0);
+        g_mg[1][0] = persistent_grid((const void*)k_batch_mg<1, false>, kNTs, 0);
+        g_mg[1][1] = persistent_grid((const void*)k_batch_mg<2, false>, kNTs, 0);
+        g_lds = persistent_grid((const void*)k_batch_lds, kLdsThreads, lds_bytes);
+        g_fin = persistent_grid((const void*)k_batch_finalize, kFinThreads, 0);
+        sized = true;
+    }
+    if (depth < 0 || depth >= kMaxLevels || pre < 1 || pre > 2 || post < 1 || post > 2) {
+        set_error("bad batched round (depth %d, sweeps %d/%d)", depth, pre, post);
+        return GDGS_ERR_INVALID_ARGUMENT;
+    }
+    const BatchTable* T = static_cast<const BatchTable*>(table);
+    const int a = pre - 1, b = post - 1;
+    if (pre == 1)
+        hipLaunchKernelGGL((k_batch_fine<1, true>), dim3(g_fine[0][a]), dim3(64 * kSNW), 0, st, T);
+    else
+        hipLaunchKernelGGL((k_batch_fine<2, true>), dim3(g_fine[0][a]), dim3(64 * kSNW), 0, st, T);
+    for (int l = 1; l <= depth; ++l) {
+        if (pre == 1)
+            hipLaunchKernelGGL((k_batch_mg<1, true>), dim3(g_mg[0][a]), dim3(kNTs), 0, st, T, l);
+        else
+            hipLaunchKernelGGL((k_batch_mg<2, true>), dim3(g_mg[0][a]), dim3(kNTs), 0, st, T, l);
+    }
+    hipLaunchKernelGGL(k_batch_lds, dim3(g_lds), dim3(kLdsThreads), lds_bytes, st, T);
+    for (int l = depth; l >= 1; --l) {
+        if (post == 1)
+            hipLaunchKernelGGL((k_batch_mg<1, false>), dim3(g_mg[1][b]), dim3(kNTs), 0, st, T, l);
+        else
+            hipLaunchKernelGGL((k_batch_mg<2, false>), dim3(g_mg[1][b]), dim3(kNTs), 0, st, T, l);
+    }
+    if (post == 1)
+        hipLaunchKernelGGL((k_batch_fine<1, false>), dim3(g_fine[1][b]), dim3(64 * kSNW), 0, st, T);
+    else
+        hipLaunchKernelGGL((k_batch_fine<2, false>), dim3(g_fine[1][b]), dim3(64 * kSNW), 0, st, T);
+    hipLaunchKernelGGL(k_batch_finalize, dim3(g_fin), dim3(kFinThreads), 0, st, T);
+    hipLaunchKernelGGL(k_batch_complete, dim3(1), dim3(64), 0, st, const_cast<BatchTable*>(T),
+                       ring);
     GDGS_LAUNCH_CHECK();
     return GDGS_OK;
 }

@@ -290,6 +290,14 @@ class Core {
         return Next::Complete;
     }
 
+    // A running request gives up its stream but keeps its slot (and counts as
+    // running) until finish_run: its remaining device work is carried
+    // elsewhere (the server's batched solve rounds).
+    void detach_stream(Request* r) {
+        if (r->stream >= 0) stream_busy_[r->stream] = 0;
+        r->stream = -1;
+    }
+
     // Waiting: removed now (true).  Running: flagged, ends after its current
     // run (false).  Unknown or done: false.
     bool cancel(int64_t id) {

@@ -1,5 +1,16 @@
 // Render server: one resident scene, many concurrent views of mixed sizes.
 //
+// Two ways of running the Poisson solves (gdgs_server_params.flags):
+//  * batched (GDGS_SERVER_BATCHED): a request's stream carries its projection,
+//    binning, compositing and the solve's set-up only; then the request joins
+//    the batch table of in-flight solves and gives its stream back.  One solver
+//    stream runs rounds -- one V-cycle of every solve in the table, each kernel
+//    a persistent grid whose workgroups take tile tasks of all of them -- and
+//    a solve that has converged is reported through a completion ring in
+//    pinned host memory.  Its slot returns to the pool once no round that can
+//    still touch it is in flight.
+//  * per request (flags 0), described below.
+//
 // A native scheduler thread owns the device side.  It admits requests through
 // the scheduling core (arrival order, free stream, memory budget), enqueues
 // each request's frame on the request's own stream -- the projection with
@@ -111,6 +122,20 @@ struct gdgs_server {
     std::unordered_map<int64_t, gdgs::Payload> payload;
     std::map<std::tuple<int, int, int, int>, gdgs::MgPlan> plans;  // (W, H, cycles, flags)
     std::deque<gdgs_completion> done;
+    // batched solves (flags & GDGS_SERVER_BATCHED)
+    bool batched = false;
+    hipStream_t solver = nullptr;
+    void* btab = nullptr;                 // device table of in-flight solves
+    gdgs::BatchRing* ring = nullptr;      // completion ring (pinned host memory)
+    long long ring_read = 0;
+    int64_t ent_req[gdgs::kBatchMax];     // request of each entry, -1 = free
+    int ent_state[gdgs::kBatchMax];       // 0 free, 1 in the rounds, 2 leaving
+    int ent_depth[gdgs::kBatchMax];
+    int64_t ent_retire_at[gdgs::kBatchMax];  // rounds that must have completed first
+    std::deque<int64_t> joinq;            // set-up done, waiting for an entry
+    std::deque<std::pair<int64_t, hipEvent_t>> rounds;  // in flight: (sequence, event)
+    std::vector<hipEvent_t> free_round_events;
+    int64_t rounds_enq = 0, rounds_done = 0;
     std::mutex mu;
     std::condition_variable wake;       // scheduler: new work or stop
     std::condition_variable done_cv;    // pollers: a completion
@@ -157,13 +182,21 @@ struct gdgs_server {
         done_cv.notify_all();
     }
 
+    // the plan of a batched solve: the whole cycle limit (no resumed runs)
+    const gdgs::MgPlan* batch_plan(const gdgs::Payload& p, int W, int H) {
+        return plan(W, H, mg.max_cycles, p.u_init ? GDGS_MG_WARM_START : 0);
+    }
+
     // First run of an admission (new request or capacity re-run).
     gdgs_status enqueue_first(gdgs::sched::Request* r) {
         using namespace gdgs;
         const Payload& p = payload.at(r->id);
         const int W = r->W, H = r->H, s = r->stream;
         hipStream_t st = streams[s];
-        const MgPlan* plan = this->plan(W, H, r->run_cycles, p.u_init ? GDGS_MG_WARM_START : 0);
+        const MgPlan* plan = batched
+                                 ? batch_plan(p, W, H)
+                                 : this->plan(W, H, r->run_cycles,
+                                              p.u_init ? GDGS_MG_WARM_START : 0);
         if (!plan) return GDGS_ERR_INVALID_ARGUMENT;
         char* base = arena + r->slot.off;
         SlotLayout L;
@@ -198,6 +231,22 @@ struct gdgs_server {
                                  L.rw.raster_ws, q);
         });
         if (e != GDGS_OK) return e;
+        if (batched) {
+            // the solve runs in the caller's image itself: set-up here, the
+            // V-cycles in the batched rounds once this stream's work is done
+            if (p.u_init && p.u_init != p.u)
+                GDGS_HIP_TRY(hipMemcpyAsync(p.u, p.u_init, sizeof(float) * 3 * (size_t)W * H,
+                                            hipMemcpyDeviceToDevice, st));
+            e = launch_render_stats(L.rw.bins.num_pairs, cap, L.stats, st);
+            if (e != GDGS_OK) return e;
+            e = launch_poisson_setup(L.rw.grad, bnd, W, H, *plan, p.u, L.stats,
+                                     L.rw.poisson_ws, st);
+            if (e != GDGS_OK) return e;
+            GDGS_HIP_TRY(hipMemcpyAsync(&host_stats[r->stream], L.stats, sizeof(gdgs_stats),
+                                        hipMemcpyDeviceToHost, st));
+            GDGS_HIP_TRY(hipEventRecord(events[r->stream], st));
+            return GDGS_OK;
+        }
         // warm start: the slot's image starts as the caller's (the solve sets
         // the ring from the boundary and keeps the interior)
         if (p.u_init)
@@ -256,6 +305,149 @@ struct gdgs_server {
         core->forget(r->id);
     }
 
+    // ---- batched solves
+    // The request's set-up has run and its pair list fitted: enter the table.
+    gdgs_status activate(int e, gdgs::sched::Request* r) {
+        using namespace gdgs;
+        const Payload& p = payload.at(r->id);
+        const MgPlan* pl = batch_plan(p, r->W, r->H);
+        if (!pl) return GDGS_ERR_INVALID_ARGUMENT;
+        SlotLayout L;
+        slot_layout(scene.K, r->W, r->H, r->cap, *pl, arena + r->slot.off, &L);
+        const gdgs_status st = batch_activate(btab, e, r->id, L.rw.grad, r->W, r->H, *pl, p.u,
+                                              L.stats, L.rw.poisson_ws, solver);
+        if (st != GDGS_OK) return st;
+        ent_req[e] = r->id;
+        ent_state[e] = 1;
+        ent_depth[e] = batch_depth(*pl);
+        return GDGS_OK;
+    }
+
+    // Entry e stops taking part in rounds; rounds enqueued before this may
+    // still read its slot, so the slot is freed once they have completed.
+    gdgs_status retire(int e) {
+        const gdgs_status st = gdgs::batch_deactivate(btab, e, solver);
+        ent_state[e] = 2;
+        ent_retire_at[e] = rounds_enq;
+        return st;
+    }
+
+    // One pass of the batched side; true if anything changed.
+    bool batch_step() {
+        using gdgs::sched::Next;
+        bool progress = false;
+        // completed rounds
+        while (!rounds.empty() && hipEventQuery(rounds.front().second) != hipErrorNotReady) {
+            (void)hipGetLastError();
+            rounds_done = rounds.front().first + 1;
+            free_round_events.push_back(rounds.front().second);
+            rounds.pop_front();
+            progress = true;
+        }
+        // completion records: the solve is final in the caller's image
+        const long long head = __atomic_load_n(&ring->head, __ATOMIC_ACQUIRE);
+        while (ring_read < head) {
+            const gdgs::BatchRec rec = ring->rec[ring_read % gdgs::kRingCap];
+            ++ring_read;
+            progress = true;
+            int e = -1;
+            for (int k = 0; k < gdgs::kBatchMax; ++k)
+                if (ent_state[k] == 1 && ent_req[k] == rec.id) e = k;
+            if (e < 0) continue;  // left the table already (cancelled)
+            gdgs::sched::Request* r = core->find(rec.id);
+            r->cycles = rec.cycles;
+            r->converged = rec.converged != 0;
+            if (retire(e) != GDGS_OK && fatal == GDGS_OK) fatal = GDGS_ERR_HIP;
+            complete(*r, r->cancelled ? GDGS_ERR_CANCELLED : GDGS_OK);
+        }
+        // cancelled requests leave the table
+        for (int k = 0; k < gdgs::kBatchMax; ++k) {
+            if (ent_state[k] != 1) continue;
+            gdgs::sched::Request* r = core->find(ent_req[k]);
+            if (!r || !r->cancelled) continue;
+            if (retire(k) != GDGS_OK && fatal == GDGS_OK) fatal = GDGS_ERR_HIP;
+            complete(*r, GDGS_ERR_CANCELLED);
+            progress = true;
+        }
+        // slots of retired entries go back to the pool
+        for (int k = 0; k < gdgs::kBatchMax; ++k) {
+            if (ent_state[k] != 2 || ent_retire_at[k] > rounds_done) continue;
+            if (gdgs::sched::Request* r = core->find(ent_req[k])) {
+                (void)core->finish_run(r, false, r->num_pairs, r->converged, r->cycles);
+                core->forget(r->id);
+            }
+            ent_state[k] = 0;
+            ent_req[k] = -1;
+            progress = true;
+        }
+        // new members
+        while (!joinq.empty()) {
+            int e = -1;
+            for (int k = 0; k < gdgs::kBatchMax && e < 0; ++k)
+                if (ent_state[k] == 0) e = k;
+            if (e < 0) break;
+            const int64_t id = joinq.front();
+            joinq.pop_front();
+            progress = true;
+            gdgs::sched::Request* r = core->find(id);
+            if (r->cancelled) {
+                complete(*r, GDGS_ERR_CANCELLED);
+                (void)core->finish_run(r, false, r->num_pairs, false, 0);
+                core->forget(id);
+                continue;
+            }
+            const gdgs_status st = activate(e, r);
+            if (st != GDGS_OK) {
+                if (fatal == GDGS_OK) fatal = st;
+                complete(*r, st);
+                (void)core->finish_run(r, false, r->num_pairs, false, 0);
+                core->forget(id);
+            }
+        }
+        // the next round (two in flight keep the solver stream busy)
+        int depth = -1;
+        for (int k = 0; k < gdgs::kBatchMax; ++k)
+            if (ent_state[k] == 1) depth = std::max(depth, ent_depth[k]);
+        if (depth >= 0 && rounds.size() < 2) {
+            hipEvent_t ev = nullptr;
+            if (!free_round_events.empty()) {
+                ev = free_round_events.back();
+                free_round_events.pop_back();
+            } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+                (void)hipGetLastError();
+                ev = nullptr;
+            }
+            gdgs_status st = ev ? GDGS_OK : GDGS_ERR_HIP;
+            if (st == GDGS_OK)
+                st = gdgs::launch_batch_round(btab, ring, depth, mg.pre_sweeps, mg.post_sweeps,
+                                              solver);
+            if (st == GDGS_OK && hipEventRecord(ev, solver) != hipSuccess) st = GDGS_ERR_HIP;
+            if (st != GDGS_OK) {
+                // the device side cannot go on: finish every member with the error
+                if (fatal == GDGS_OK) fatal = st;
+                for (int k = 0; k < gdgs::kBatchMax; ++k) {
+                    if (ent_state[k] != 1) continue;
+                    gdgs::sched::Request* r = core->find(ent_req[k]);
+                    complete(*r, st);
+                    ent_state[k] = 2;
+                    ent_retire_at[k] = rounds_enq;
+                }
+                if (ev) free_round_events.push_back(ev);
+            } else {
+                rounds.emplace_back(rounds_enq++, ev);
+            }
+            progress = true;
+        }
+        return progress;
+    }
+
+    bool batch_busy() const {
+        if (!rounds.empty() || !joinq.empty()) return true;
+        for (int k = 0; k < gdgs::kBatchMax; ++k)
+            if (ent_state[k] != 0) return true;
+        return false;
+    }
+
     void loop() {
         using gdgs::sched::Next;
         (void)hipSetDevice(dev);
@@ -275,6 +467,19 @@ struct gdgs_server {
                     continue;
                 }
                 const gdgs_stats& hs = host_stats[s];
+                if (batched) {
+                    // front half done: re-run on overflow, else join the batch
+                    if (hs.overflow != 0 && !r->cancelled) {
+                        (void)core->finish_run(r, true, hs.num_pairs, false, 0);
+                        running[s] = -1;
+                        continue;
+                    }
+                    r->num_pairs = hs.num_pairs;
+                    core->detach_stream(r);
+                    running[s] = -1;
+                    joinq.push_back(id);
+                    continue;
+                }
                 const int cyc = std::max(hs.cycles[0], std::max(hs.cycles[1], hs.cycles[2]));
                 const Next nx = core->finish_run(r, hs.overflow != 0, hs.num_pairs,
                                                  hs.converged != 0, cyc);
@@ -301,9 +506,11 @@ struct gdgs_server {
                 const gdgs_status e = enqueue_first(r);
                 if (e != GDGS_OK) fail(r, e);
             }
-            if (stop && core->waiting() == 0 && core->running() == 0) break;
+            if (batched && batch_step()) progress = true;
+            if (stop && core->waiting() == 0 && core->running() == 0 && !(batched && batch_busy()))
+                break;
             if (progress) continue;
-            if (core->running() > 0) {
+            if (core->running() > 0 || (batched && batch_busy())) {
                 // device work in flight: poll its events again shortly
                 lk.unlock();
                 std::this_thread::yield();
@@ -355,6 +562,10 @@ gdgs_status gdgs_server_create(const gdgs_scene* scene, const gdgs_server_params
     SREQ(params->hbm_budget >= (1 << 20), "hbm_budget must be at least 1 MiB");
     SREQ((params->mg.flags & ~GDGS_MG_NEUMANN) == 0,
          "server solver flags must be 0 or GDGS_MG_NEUMANN");
+    SREQ((params->flags & ~GDGS_SERVER_BATCHED) == 0, "unknown server flags 0x%x",
+         params->flags);
+    SREQ(!((params->flags & GDGS_SERVER_BATCHED) && (params->mg.flags & GDGS_MG_NEUMANN)),
+         "batched solves take the Dirichlet problem only");
     MgPlan probe;
     if (mg_plan(64, 64, &params->mg, &probe) != GDGS_OK) return GDGS_ERR_INVALID_ARGUMENT;
 
@@ -364,11 +575,21 @@ gdgs_status gdgs_server_create(const gdgs_scene* scene, const gdgs_server_params
     s->scene = *scene;
     s->mg = params->mg;
     s->arena_bytes = (size_t)params->hbm_budget & ~(size_t)255;
+    s->batched = (params->flags & GDGS_SERVER_BATCHED) != 0;
+    for (int k = 0; k < kBatchMax; ++k) {
+        s->ent_req[k] = -1;
+        s->ent_state[k] = 0;
+        s->ent_depth[k] = 0;
+        s->ent_retire_at[k] = 0;
+    }
     auto cleanup = [&](hipError_t e, const char* what) {
         set_error("%s: %s", what, hipGetErrorString(e));
         for (auto ev : s->events) (void)hipEventDestroy(ev);
         for (auto st : s->streams) (void)hipStreamDestroy(st);
+        if (s->solver) (void)hipStreamDestroy(s->solver);
         if (s->host_stats) (void)hipHostFree(s->host_stats);
+        if (s->ring) (void)hipHostFree(s->ring);
+        if (s->btab) (void)hipFree(s->btab);
         if (s->arena) (void)hipFree(s->arena);
         delete s;
         return GDGS_ERR_HIP;
@@ -398,6 +619,24 @@ gdgs_status gdgs_server_create(const gdgs_scene* scene, const gdgs_server_params
         if (e != hipSuccess) return cleanup(e, "hipEventCreate");
         s->events.push_back(ev);
     }
+    if (s->batched) {
+        e = hipStreamCreateWithFlags(&s->solver, hipStreamNonBlocking);
+        if (e != hipSuccess) return cleanup(e, "hipStreamCreate (solver)");
+        e = hipMalloc(&s->btab, batch_table_bytes());
+        if (e != hipSuccess) {
+            s->btab = nullptr;
+            return cleanup(e, "allocating the batch table");
+        }
+        e = hipHostMalloc(reinterpret_cast<void**>(&s->ring), sizeof(BatchRing),
+                          hipHostMallocDefault);
+        if (e != hipSuccess) {
+            s->ring = nullptr;
+            return cleanup(e, "hipHostMalloc (completion ring)");
+        }
+        std::memset(s->ring, 0, sizeof(BatchRing));
+        if (batch_clear(s->btab, s->solver) != GDGS_OK)
+            return cleanup(hipErrorLaunchFailure, "clearing the batch table");
+    }
     s->running.assign(params->streams, -1);
     sched::Core::Config cfg;
     cfg.budget = s->arena_bytes;
@@ -426,6 +665,10 @@ gdgs_status gdgs_server_submit(gdgs_server* srv, const gdgs_request* req, int64_
     SREQ(!req->u_init || al4(req->u_init), "u_init is not 4-byte aligned");
     std::lock_guard<std::mutex> g(srv->mu);
     SREQ(!srv->stop, "server is shutting down");
+    if (srv->batched) {
+        const MgPlan* pl = srv->plan(cam.W, cam.H, srv->mg.max_cycles, 0);
+        SREQ(pl && batch_supported(*pl), "a %dx%d view cannot be solved batched", cam.W, cam.H);
+    }
     const int64_t rid = srv->next_id++;
     const int64_t t = req->arrival_ns > 0 ? req->arrival_ns : steady_ns();
     if (!srv->core->submit(rid, req->tag, cam.W, cam.H, t)) {
@@ -462,7 +705,7 @@ gdgs_status gdgs_server_cancel(gdgs_server* srv, int64_t id) {
     SREQ(srv, "server is null");
     std::lock_guard<std::mutex> g(srv->mu);
     sched::Request* r = srv->core->find(id);
-    SREQ(r && r->phase != sched::Phase::Done && !r->cancelled,
+    SREQ(r && r->phase != sched::Phase::Done && !r->cancelled && srv->payload.count(id),
          "request %lld is unknown, finished or already cancelled", (long long)id);
     if (srv->core->cancel(id)) {
         srv->complete(*r, GDGS_ERR_CANCELLED);
@@ -514,8 +757,14 @@ gdgs_status gdgs_server_destroy(gdgs_server* srv) {
     gdgs_status st = GDGS_OK;
     for (auto s : srv->streams)
         if (hipStreamSynchronize(s) != hipSuccess) st = GDGS_ERR_HIP;
+    if (srv->solver && hipStreamSynchronize(srv->solver) != hipSuccess) st = GDGS_ERR_HIP;
     for (auto ev : srv->events) (void)hipEventDestroy(ev);
+    for (auto& r : srv->rounds) (void)hipEventDestroy(r.second);
+    for (auto ev : srv->free_round_events) (void)hipEventDestroy(ev);
     for (auto s : srv->streams) (void)hipStreamDestroy(s);
+    if (srv->solver) (void)hipStreamDestroy(srv->solver);
+    if (srv->ring) (void)hipHostFree(srv->ring);
+    if (srv->btab) (void)hipFree(srv->btab);
     if (srv->host_stats) (void)hipHostFree(srv->host_stats);
     if (srv->arena) (void)hipFree(srv->arena);
     delete srv->core;

@@ -15,6 +15,7 @@ from . import _lib as L
 from .api import DeviceScene, camera_struct, mg_params
 
 F32 = torch.float32
+BATCHED = 1   # GDGS_SERVER_BATCHED
 
 
 def now_ns() -> int:
@@ -26,14 +27,20 @@ class Server:
     """Continuous-batching render server on the current device.
 
     budget: bytes of device memory for in-flight requests (allocated once);
-    streams: requests in flight at once (1 = the plain one-at-a-time path).
+    streams: requests whose front half runs at once (1 without batching = the
+    plain one-at-a-time path);
+    batched: the solves of all in-flight requests advance together in
+    persistent-kernel rounds on one solver stream (GDGS_SERVER_BATCHED;
+    Dirichlet problem only), with streams + 1 HIP streams in all.
     """
 
-    def __init__(self, scene: DeviceScene, budget: int = 4 << 30, streams: int = 4, mg=None):
+    def __init__(self, scene: DeviceScene, budget: int = 4 << 30, streams: int = 4, mg=None,
+                 batched: bool = False):
         self.lib = L.load()
         self.scene = scene
         self.mg = mg if mg is not None else mg_params()
-        p = L.ServerParams(int(budget), int(streams), 0, self.mg)
+        self.batched = bool(batched)
+        p = L.ServerParams(int(budget), int(streams), BATCHED if batched else 0, self.mg)
         h = ctypes.c_void_p()
         L.check(self.lib.gdgs_server_create(ctypes.byref(scene.struct(6)), ctypes.byref(p),
                                             ctypes.byref(h)))

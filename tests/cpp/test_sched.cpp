@@ -169,6 +169,29 @@ static void completion_rules() {
     std::printf("completion: retry, resume, limit, cancel ok\n");
 }
 
+// A request that gives up its stream (its solve continues in the batched
+// rounds) keeps its slot and counts as running; the stream takes the next
+// request at once.
+static void detached_streams() {
+    Core c(cfg(size_t(1) << 30, 1));
+    CHECK(c.submit(1, 0, 64, 64, 0));
+    CHECK(c.submit(2, 0, 64, 64, 1));
+    Request* a = c.admit(10);
+    CHECK(a && a->id == 1 && c.admit(10) == nullptr);   // the one stream is busy
+    const size_t used = c.pool().arena().used();
+    c.detach_stream(a);
+    CHECK(a->stream == -1 && c.running() == 1);
+    Request* b = c.admit(10);
+    CHECK(b && b->id == 2 && b->stream == 0 && c.running() == 2);
+    CHECK(b->slot.off != a->slot.off && c.pool().arena().used() > used);  // both slots held
+    CHECK(c.finish_run(a, false, 10, true, 7) == Next::Complete);
+    CHECK(c.running() == 1 && c.pool().idle_count() == 1);
+    c.forget(1);
+    CHECK(c.finish_run(b, false, 10, true, 7) == Next::Complete);
+    CHECK(c.running() == 0 && c.admit(20) == nullptr);
+    std::printf("detached streams: slot kept, stream reused ok\n");
+}
+
 // Simulated serving: random sizes and arrivals through a fake executor with
 // random durations.  Every request completes exactly once, memory in use
 // never exceeds the budget, at most `streams` run at once, and starts follow
@@ -235,6 +258,7 @@ int main() {
     admission_order();
     memory_blocking();
     completion_rules();
+    detached_streams();
     simulated_serving();
     std::printf("ALL OK\n");
     return 0;

@@ -93,14 +93,16 @@ def test_serving_workload_mixed_equals_alone_renderer_and_oracle():
             c = srv.drain(1)[0]
             assert c["status"] == 0 and c["converged"] == 1
             alone[i] = c["u"].clone()
-    with G.Server(ds, budget=4 << 30, streams=4, mg=mg) as srv:
-        for (W, H), i in reqs[::-1]:
-            srv.submit(wl.make_camera(W, H, pose_index=i), ring[(W, H)], tag=i)
-        done = srv.drain(len(reqs))
-    assert sorted(c["tag"] for c in done) == sorted(i for _, i in reqs)
-    for c in done:
-        assert c["status"] == 0 and c["converged"] == 1
-        assert torch.equal(c["u"], alone[c["tag"]]), c["tag"]
+    for batched in (False, True):
+        with G.Server(ds, budget=4 << 30, streams=3 if batched else 4, mg=mg,
+                      batched=batched) as srv:
+            for (W, H), i in reqs[::-1]:
+                srv.submit(wl.make_camera(W, H, pose_index=i), ring[(W, H)], tag=i)
+            done = srv.drain(len(reqs))
+        assert sorted(c["tag"] for c in done) == sorted(i for _, i in reqs)
+        for c in done:
+            assert c["status"] == 0 and c["converged"] == 1
+            assert torch.equal(c["u"], alone[c["tag"]]), (batched, c["tag"])
     for (W, H), i in reqs[::2]:
         r = G.Renderer(ds, W, H, mg)
         u = r.render(wl.make_camera(W, H, pose_index=i), ring[(W, H)])
@@ -117,6 +119,88 @@ def test_serving_workload_mixed_equals_alone_renderer_and_oracle():
         e2 = np.abs(np_(alone[i]) - exact).max()
         say(f"  {W}x{H}: composite max-abs {e1:.3e} ({ties} tie pixels), solve max-abs {e2:.3e}")
         assert e2 <= 1e-4
+
+
+def test_batched_rounds_equal_alone_and_plain_renderer(scene):
+    """Batched solves (one device table, persistent-kernel rounds, completion
+    ring): 24 mixed requests at once give the bits of the same requests
+    solved alone on a one-stream per-request server and of the plain
+    Renderer; one request alone in the batch gives them too."""
+    sc, ds = scene
+    reqs = requests(24, seed=9)
+    ring = rings()
+    mg = G.mg_params(**MG)
+    alone = {}
+    with G.Server(ds, budget=1 << 30, streams=1, mg=mg) as srv:
+        for (W, H), i in reqs:
+            srv.submit(wl.make_camera(W, H, pose_index=i), ring[(W, H)], tag=i)
+            c = srv.drain(1)[0]
+            assert c["status"] == 0 and c["converged"] == 1
+            alone[i] = c["u"].clone()
+    with G.Server(ds, budget=1 << 30, streams=3, mg=mg, batched=True) as srv:
+        for (W, H), i in reqs:
+            srv.submit(wl.make_camera(W, H, pose_index=i), ring[(W, H)], tag=i)
+        done = srv.drain(len(reqs))
+        # a finished solve's slot is released once the rounds that may still
+        # read it have completed
+        import time
+        t0 = time.perf_counter()
+        while srv.state()["running"] > 0 and time.perf_counter() - t0 < 5.0:
+            time.sleep(0.001)
+        st = srv.state()
+    say(f"[serve batched] {len(done)} done, state {st}")
+    assert sorted(c["tag"] for c in done) == list(range(len(reqs)))
+    for c in done:
+        assert c["status"] == 0 and c["converged"] == 1, c
+        assert torch.equal(c["u"], alone[c["tag"]]), c["tag"]
+    assert st["running"] == 0 and st["waiting"] == 0
+    # one at a time through the batched path
+    with G.Server(ds, budget=1 << 30, streams=1, mg=mg, batched=True) as srv:
+        for (W, H), i in reqs[:5]:
+            srv.submit(wl.make_camera(W, H, pose_index=i), ring[(W, H)], tag=i)
+            c = srv.drain(1)[0]
+            assert c["status"] == 0 and torch.equal(c["u"], alone[i]), i
+    for (W, H), i in reqs[:4]:
+        r = G.Renderer(ds, W, H, mg)
+        u = r.render(wl.make_camera(W, H, pose_index=i), ring[(W, H)])
+        torch.cuda.synchronize()
+        assert torch.equal(u, alone[i])
+
+
+def test_batched_capacity_rerun_limit_and_cancel(scene):
+    """Batched solves: a pair-capacity overflow re-runs the front half with a
+    larger capacity and still gives the alone bits; a cycle limit below the
+    need completes unconverged with exactly that many cycles; a cancelled
+    request completes as cancelled and the others are unaffected."""
+    sc, ds = scene
+    mg = G.mg_params(**MG)
+    # large splats: far more pairs than the initial capacity of 65536
+    big = G.DeviceScene.from_host(wl.make_scene(5000, seed=5, z=(2.0, 6.0), ls=(-2.0, 0.3)))
+    W, H = 320, 180
+    cam = wl.make_camera(W, H, pose_index=2)
+    want = G.Renderer(big, W, H, mg).render(cam).clone()
+    torch.cuda.synchronize()
+    with G.Server(big, budget=1 << 30, streams=2, mg=mg, batched=True) as srv:
+        srv.submit(cam, None, tag=1)
+        c = srv.drain(1)[0]
+    say(f"[serve batched] big splats: {c['num_pairs']} pairs, attempts {c['attempts']}")
+    assert c["status"] == 0 and c["converged"] == 1 and c["attempts"] >= 2
+    assert c["num_pairs"] > 65536 and torch.equal(c["u"], want)
+    W, H = 200, 160
+    ring = torch.from_numpy(wl.reference_image(H, W, seed=1).astype(np.float32)).cuda()
+    cam = wl.make_camera(W, H, pose_index=2)
+    with G.Server(ds, budget=1 << 30, streams=2, mg=G.mg_params(tol=1e-6, max_cycles=3),
+                  batched=True) as srv:
+        srv.submit(cam, ring, tag=2)
+        c = srv.drain(1)[0]
+        assert c["status"] == 0 and c["converged"] == 0 and c["cycles"] == 3
+    with G.Server(ds, budget=1 << 30, streams=1, mg=mg, batched=True) as srv:
+        ids = [srv.submit(wl.make_camera(W, H, pose_index=k), ring, tag=k)[0] for k in range(4)]
+        srv.cancel(ids[3])
+        done = {c["tag"]: c for c in srv.drain(4)}
+        assert done[3]["status"] == 8
+        for k in range(3):
+            assert done[k]["status"] == 0 and done[k]["converged"] == 1
 
 
 def test_small_view_against_the_oracle(scene):
