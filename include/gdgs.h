@@ -304,6 +304,29 @@ gdgs_status gdgs_poisson_solve_rhs(const float* rho, const float* boundary, int3
                                    const gdgs_mg_params* mg, float* u, gdgs_stats* stats_dev,
                                    void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the solve of
+ * gdgs_poisson_solve (same arguments, same kernels, same results) with its
+ * scratch in a fixed device array of the library instead of a caller
+ * workspace.  The array holds GDGS_STATIC_SCRATCH_BYTES (80 MiB) on every GPU
+ * the library runs on, from the first call on that GPU until the process
+ * ends: enough for the Dirichlet problem up to 1920 x 1080 (72.5 MiB) and the
+ * Neumann problem up to about 1.7 Mpixels.  A size that needs more returns
+ * GDGS_ERR_WORKSPACE with a message (gdgs_poisson_workspace_size gives the
+ * need).  This call allocates nothing: no hipMalloc, no stream, event or graph
+ * is created; its kernels are launched directly on `stream`, every channel in
+ * each launch.  The solve initialises the part of the array it reads (a
+ * previous call's contents are overwritten), except under GDGS_MG_RESUME,
+ * which continues whatever solve the array holds on this GPU.  All calls on one
+ * GPU share that GPU's array: calls whose work overlaps on the device (other
+ * streams, other threads) race and must be serialised by the caller.  Errors as
+ * gdgs_poisson_solve, plus GDGS_ERR_HIP if the array's address cannot be
+ * found. */
+#define GDGS_STATIC_SCRATCH_BYTES (80ull << 20)
+gdgs_status gdgs_poisson_solve_static(const float* grad, const float* boundary, int32_t W,
+                                      int32_t H, const gdgs_mg_params* mg, float* u,
+                                      gdgs_stats* stats_dev, void* stream);
+
 /* ------------------------------------------------------------------ */
 /* Steps 1-4 on one stream with no host synchronisation: project, bin and
  * sort, composite, solve.  u[3][H][W] is the recovered image.  If sync_stats

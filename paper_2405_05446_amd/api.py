@@ -235,6 +235,24 @@ def gdgs_poisson_solve_rhs(rho: torch.Tensor, boundary: torch.Tensor | None, W: 
     return _poisson("gdgs_poisson_solve_rhs", rho, 3, boundary, W, H, mg, u, stats, ws, stream)
 
 
+def gdgs_poisson_solve_static(grad: torch.Tensor, boundary: torch.Tensor | None, W: int, H: int,
+                              mg: L.MgParams | None = None, u=None, stats=None, stream=None):
+    """gdgs_poisson_solve with the library's fixed scratch array instead of a
+    workspace (the library allocates nothing for it; u and stats are
+    allocated here unless given)."""
+    lib = L.load()
+    dev = grad.device
+    _need(grad, (6, H, W), F32, "grad")
+    if boundary is not None:
+        _need(boundary, (3, H, W), F32, "boundary")
+    mg = mg if mg is not None else mg_params()
+    u = u if u is not None else torch.empty((3, H, W), dtype=F32, device=dev)
+    _need(u, (3, H, W), F32, "u")
+    L.check(lib.gdgs_poisson_solve_static(L.ptr(grad), L.ptr(boundary), W, H, ctypes.byref(mg),
+                                          L.ptr(u), L.ptr(stats), L.stream_handle(stream)))
+    return u, stats
+
+
 def poisson_workspace_size(W: int, H: int, mg=None) -> int:
     lib = L.load()
     mg = mg if mg is not None else mg_params()

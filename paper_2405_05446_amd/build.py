@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgdgs.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["project.hip", "binsort.hip", "raster.hip", "poisson.hip", "loss.hip", "api.hip",
-           "server.hip"]
+           "server.hip", "noalloc.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 ARCH = os.environ.get("GDGS_ARCH", "gfx950")
