@@ -5,7 +5,8 @@ One step = one frame of the whole path for one seeded camera pose: projection,
 tile binning and depth sort, six-channel gradient compositing, divergence and
 multigrid Poisson solve (8 levels, V(2,2), stop at a 1e-6 relative
 correction) with the
-reference image's ring as Dirichlet data.  Steps cycle over 100 seeded poses.
+reference image's ring as Dirichlet data.  Steps cycle over 100 seeded poses
+(the default of 100 steps times each of them once).
 Inputs are resident in device memory before timing starts.
 
 Prints one JSON line.  Per-stage times come from HIP events recorded on the
@@ -69,13 +70,14 @@ def measured_traffic(kernel: str):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--K", type=int, default=1_000_000)
     ap.add_argument("--W", type=int, default=1920)
     ap.add_argument("--H", type=int, default=1080)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-pixels", type=int, default=400)
+    ap.add_argument("--cpu-pixels", type=int, default=2074,
+                    help="sampled pixels of the oracle's compositing (0.1%% of 1080p)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-train", action="store_true",
                     help="skip the Algorithm-1 iteration measurement")
@@ -97,52 +99,81 @@ def parse():
     return ap.parse_args()
 
 
+def _cpu_model() -> str:
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+_CPU = {}
+
+
+def _cpu_pixels(chunk):
+    """Worker: brute-force compositing of a chunk of sampled pixels (FP64 oracle)."""
+    from oracle import composite as oc
+    rows, cols = chunk
+    c = _CPU
+    return oc.render_grad(c["proj"], c["opacity"], c["value"], c["H"], c["W"], rows, cols)
+
+
 def cpu_baseline(scene, cam, ring, npix):
-    """The FP64 oracle, single-threaded, on a bounded sample of the same frame:
-    projection of every splat, brute-force compositing of npix seeded pixels
-    (extrapolated to the full frame), and the exact DST-I Poisson solve of the
-    full frame.  Returns Mpix/s of the extrapolated frame."""
+    """The FP64 oracle as it stands, on the host's cores, on a bounded sample of
+    the same frame: projection of every splat, brute-force compositing of npix
+    seeded pixels (split over the cores; extrapolated to the full frame), and
+    the exact DST-I Poisson solve of the full frame (scipy.fft on every core).
+    Runs before the GPU is touched, so the worker processes are plain forks.
+    Returns Mpix/s of the extrapolated frame."""
+    import multiprocessing as mp
+
     import workloads as wl
-    from oracle import composite as oc, poisson as P
+    from oracle import poisson as P
     from oracle.project import project
 
     H, W = cam.H, cam.W
-    try:     # one thread throughout, BLAS included, so that `cores` is exact
-        from threadpoolctl import threadpool_limits
-        limit = threadpool_limits(1)
-    except ImportError:
-        limit = None
+    affinity = len(os.sched_getaffinity(0))
+    cores = max(1, min(affinity, int(os.environ.get("OMP_NUM_THREADS", "16") or 16), 16))
     t0 = time.perf_counter()
     proj = project(scene, cam)
     t1 = time.perf_counter()
     rows, cols = wl.sample_pixels(H, W, npix, seed=21)
-    oc.render_grad(proj, scene.opacity, scene.value, H, W, rows, cols)
+    _CPU.update(proj=proj, opacity=scene.opacity, value=scene.value, H=H, W=W)
+    chunks = [(rows[k::cores], cols[k::cores]) for k in range(cores)]
+    with mp.get_context("fork").Pool(cores) as pool:
+        pool.map(_cpu_pixels, chunks)
     t2 = time.perf_counter()
     rng = np.random.default_rng(0)
     grad = rng.laplace(0.0, 0.01, (6, H, W))
-    P.solve_dst(P.divergence(grad), ring, workers=1)
+    P.solve_dst(P.divergence(grad), ring, workers=cores)
     t3 = time.perf_counter()
-    if limit is not None:
-        limit.unregister()
     per_px = (t2 - t1) / rows.size
     frame = (t1 - t0) + per_px * H * W + (t3 - t2)
-    return dict(value=round(H * W / frame / 1e6, 8), unit="Mpix/s", cores=1, kind="oracle",
-                sample=f"FP64 oracle, 1 thread: projection of all {scene.K} splats "
-                       f"({t1 - t0:.2f} s), brute-force compositing of {rows.size} seeded "
-                       f"pixels ({t2 - t1:.2f} s, extrapolated x{H * W / rows.size:.0f} to the "
-                       f"frame), DST-I Poisson of the full frame ({t3 - t2:.2f} s)",
+    return dict(value=round(H * W / frame / 1e6, 8), unit="Mpix/s", cores=cores, kind="oracle",
+                cpu_model=_cpu_model(), affinity_cpus=affinity,
+                sample=f"FP64 oracle on {cores} host processes ({_cpu_model()}): projection "
+                       f"of all {scene.K} splats ({t1 - t0:.2f} s, one process), brute-force "
+                       f"compositing of {rows.size} seeded pixels ({t2 - t1:.2f} s over "
+                       f"{cores} processes, extrapolated x{H * W / rows.size:.0f} to the "
+                       f"frame), DST-I Poisson of the full frame ({t3 - t2:.2f} s, "
+                       f"{cores} FFT workers)",
                 frame_seconds=round(frame, 2))
 
 
 def serving_leg(G, wl, torch, nreq: int, streams: int, budget: int = 4 << 30):
     """Mixed-size serving on one GPU: a resident 500k-splat scene, nreq requests
     with sizes uniform over 256^2, 512^2, 800^2 and 1920x1080 (seed 7), poses
-    1000+i, reference rings.  The plain path is the library's server with one
-    stream (one request at a time, FIFO); the batched path admits up to
-    `streams` requests at once under the same 4 GiB memory budget.  Reports
-    saturation throughput (all requests arrive at once) and p50/p99 latency
-    (completion seen by the host minus scheduled arrival) for Poisson arrivals
-    at fractions of the plain path's saturation rate."""
+    1000+i, reference rings.  Three servers on the same memory budget:
+    `plain`, one request at a time (FIFO, the per-request path); `streams`, up
+    to `streams` requests at once, each on its own stream with its own
+    kernels; `batched`, the front halves on `streams - 1` streams and the
+    solves of all in-flight requests in persistent-kernel rounds on one solver
+    stream (`streams` HIP streams in all).  Reports saturation throughput (all
+    requests arrive at once), p50/p99 latency (completion seen by the host
+    minus scheduled arrival) for Poisson arrivals at fractions of the plain
+    path's saturation rate, and saturation at 1, 4 and 16 GiB budgets."""
     cfg = wl.CONFIGS["serve"]
     sc = wl.make_scene(cfg["K"], seed=0, z=cfg["z"], ls=cfg["ls"])
     ds = G.DeviceScene.from_host(sc)
@@ -172,28 +203,43 @@ def serving_leg(G, wl, torch, nreq: int, streams: int, budget: int = 4 << 30):
     zeros = np.zeros(nreq)
     res = {"requests": nreq, "splats": cfg["K"], "sizes": [list(s) for s in wl.SERVE_SIZES],
            "total_Mpix": round(px / 1e6, 2), "budget_GiB": budget / 2**30,
-           "batched_streams": streams}
-    with G.Server(ds, budget=budget, streams=1, mg=mg) as plain, \
-            G.Server(ds, budget=budget, streams=streams, mg=mg) as batched:
-        run(plain, zeros)                   # warm-up: graphs, capacities, cycle budgets
-        run(batched, zeros)
-        sat_p = run(plain, zeros)
-        sat_b = run(batched, zeros)
-        res["saturation"] = {"plain": sat_p, "batched": sat_b}
+           "hip_streams": {"plain": 1, "streams": streams, "batched": streams}}
+    kinds = {"plain": dict(streams=1), "streams": dict(streams=streams),
+             "batched": dict(streams=max(1, streams - 1), batched=True)}
+    srvs = {k: G.Server(ds, budget=budget, mg=mg, **v) for k, v in kinds.items()}
+    try:
+        for v in srvs.values():
+            run(v, zeros)                    # warm-up: graphs, capacities, cycle budgets
+        res["saturation"] = {k: run(v, zeros) for k, v in srvs.items()}
+        sat_req_s = res["saturation"]["plain"]["req_s"]
         qps = []
-        for f in (0.5, 0.75, 1.0, 1.5):
-            q = f * sat_p["req_s"]
+        for f in (0.25, 0.5, 0.75, 1.0, 1.5, 2.0, 4.0):
+            q = f * sat_req_s
             off = wl.poisson_arrivals(nreq, q, seed=7)
             qps.append({"qps": round(q, 2), "x_plain_saturation": f,
-                        "plain": run(plain, off), "batched": run(batched, off)})
+                        **{k: run(v, off) for k, v in srvs.items()}})
         res["poisson_arrivals"] = qps
-        res["batched_state"] = batched.state()
+        res["batched_state"] = srvs["batched"].state()
         ring = rings[(1920, 1080)]
         paths = {}
         for warm in (False, True):
-            camera_paths(G, wl, batched, ring, streams, 4, warm)   # warm-up
-            paths["warm" if warm else "cold"] = camera_paths(G, wl, batched, ring, streams, 20, warm)
-        res["camera_paths"] = paths
+            camera_paths(G, wl, srvs["batched"], ring, streams, 4, warm)   # warm-up
+            paths["warm" if warm else "cold"] = camera_paths(G, wl, srvs["batched"], ring,
+                                                             streams, 20, warm)
+        res["camera_paths_batched"] = paths
+    finally:
+        for v in srvs.values():
+            v.close()
+    budgets = {}
+    for gib in (1, 4, 16):
+        row = {}
+        for k in ("streams", "batched"):
+            with G.Server(ds, budget=gib << 30, mg=mg, **kinds[k]) as srv:
+                run(srv, zeros)
+                row[k] = run(srv, zeros)
+                row[k]["peak_GiB"] = round(srv.state()["peak_bytes"] / 2**30, 3)
+        budgets[f"{gib}GiB"] = row
+    res["saturation_by_budget"] = budgets
     return res
 
 
@@ -440,6 +486,14 @@ def main():
     import paper_2405_05446_amd as G
     import workloads as wl
 
+    cpu = None
+    if not args.copy_probe and not args.no_cpu_baseline:
+        # the oracle's leg runs first, before anything touches the GPU
+        cfg0 = wl.CONFIGS["full"]
+        cpu = cpu_baseline(wl.make_scene(args.K, seed=0, z=cfg0["z"], ls=cfg0["ls"]),
+                           wl.make_camera(args.W, args.H, pose_index=0),
+                           wl.reference_image(args.H, args.W, seed=1), args.cpu_pixels)
+
     if args.copy_probe:
         n = args.copy_probe * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device="cuda:0")
@@ -583,7 +637,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic (seeded scene and poses; no dataset)",
         "config": {"workload": f"plain render+Poisson, {W}x{H}, {K} gradient splats, "
-                               f"8-level V(2,2) multigrid to a 1e-6 relative correction, 100 seeded poses",
+                               f"8-level V(2,2) multigrid to a 1e-6 relative correction, "
+                               f"{min(args.steps, len(cams))} distinct seeded poses timed",
                    "W": W, "H": H, "splats": K, "pairs": P, "mg_cycles_mean": mean_cycles},
         "latency_ms": {"p50": round(float(np.percentile(frame_ms, 50)), 4),
                        "p99": round(float(np.percentile(frame_ms, 99)), 4)},
@@ -619,8 +674,8 @@ def main():
         out["sparsity"] = sparsity_leg(G, wl, torch, scene, cams[0], ring, mg, W, H)
     if not args.no_serve:
         out["serving"] = serving_leg(G, wl, torch, args.serve_requests, args.serve_streams)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(scene, cams[0], ring_np, args.cpu_pixels)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

@@ -2385,13 +2385,27 @@ struct BatchSolve {
     long long id;
 };
 
+enum : int { kBFinePre = 0, kBFinePost, kBPre, kBPost, kBLds, kBFin };
+// launches of a round: finest pre and post, coarse pre and post for levels
+// 1 .. kMaxLevels - 1, the in-LDS V-cycle and the finalize
+constexpr int kBSteps = 2 + 2 * (kMaxLevels - 1) + 2;
+__host__ __device__ constexpr int bstep(int kind, int l) {
+    return kind == kBFinePre    ? 0
+           : kind == kBFinePost ? 1
+           : kind == kBPre      ? 1 + l
+           : kind == kBPost     ? kMaxLevels + l
+           : kind == kBLds      ? 2 * kMaxLevels
+                                : 2 * kMaxLevels + 1;
+}
+static_assert(bstep(kBFin, 0) == kBSteps - 1, "step numbering");
+
 struct BatchTable {
     long long ring_head;  // records written so far (the device's copy)
     long long pad[7];
+    // per step, tasks of the entries before e (written at the start of a round)
+    int pref[kBSteps][kBatchMax + 1];
     BatchSolve e[kBatchMax];
 };
-
-enum : int { kBFinePre = 0, kBFinePost, kBPre, kBPost, kBLds, kBFin };
 
 __device__ __forceinline__ int batch_tasks(const BatchSolve& b, int kind, int l) {
     if (!b.active) return 0;
@@ -2400,21 +2414,35 @@ __device__ __forceinline__ int batch_tasks(const BatchSolve& b, int kind, int l)
     return 3;  // in-LDS V-cycle, finalize: one task per channel
 }
 
-// pref[e] = tasks of entries before e (wave 0 scans the kBatchMax = 64
-// entries, one per lane); returns the total.
-__device__ int batch_prefix(const BatchTable* __restrict__ T, int kind, int l, int* pref) {
+// Start of a round, one wave (lane e = entry e): the task prefix of every
+// step, so that each workgroup of a step reads 65 integers instead of
+// scanning the table.
+__global__ __launch_bounds__(64) void k_batch_plan(BatchTable* __restrict__ T) {
     static_assert(kBatchMax == 64, "one wave scans the table");
-    if (threadIdx.x < 64) {
-        const int e = threadIdx.x;
-        int v = batch_tasks(T->e[e], kind, l);
+    const int e = threadIdx.x;
+    const BatchSolve& b = T->e[e];
+    for (int s = 0; s < kBSteps; ++s) {
+        int kind, l = 0;
+        if (s == 0) kind = kBFinePre;
+        else if (s == 1) kind = kBFinePost;
+        else if (s < 1 + kMaxLevels) { kind = kBPre; l = s - 1; }
+        else if (s < 2 * kMaxLevels) { kind = kBPost; l = s - kMaxLevels; }
+        else kind = s == 2 * kMaxLevels ? kBLds : kBFin;
+        int v = batch_tasks(b, kind, l);
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
             const int y = __shfl_up(v, d, 64);
             if (e >= d) v += y;
         }
-        pref[e + 1] = v;
-        if (e == 0) pref[0] = 0;
+        T->pref[s][e + 1] = v;
+        if (e == 0) T->pref[s][0] = 0;
     }
+}
+
+// The step's prefix into LDS; returns the total.
+__device__ int batch_prefix(const BatchTable* __restrict__ T, int kind, int l, int* pref) {
+    const int* src = T->pref[bstep(kind, l)];
+    for (int i = threadIdx.x; i <= kBatchMax; i += blockDim.x) pref[i] = src[i];
     __syncthreads();
     return pref[kBatchMax];
 }
@@ -2455,27 +2483,30 @@ __global__ __launch_bounds__(64 * kSNW) void k_batch_fine(const BatchTable* __re
         const BatchSolve& B = T->e[k.e];
         const int nt = B.fine_tiles;
         const int c = k.loc / nt, tile = k.loc - c * nt;
+        const int* done = B.done;
+        double* part = B.part;
+        const int ftx = B.fine_tx;
+        const LevelDev L = B.lev[0];  // copies: fields in scalar registers
+        const LevelDev C = B.lev[1];
         __syncthreads();  // the previous task is done with the LDS
-        if (B.done[c]) continue;  // uniform over the block
-        const Strip S(c, tile, B.fine_tx);
-        const LevelDev& L = B.lev[0];
-        const LevelDev& C = B.lev[1];
+        if (done[c]) continue;  // uniform over the block
+        const Strip S(c, tile, ftx);
         if (PRE) {
             if (S.interior(L))
-                fine_pre_body<NU, true, false>(L, C, B.part, nt, S, sx);
+                fine_pre_body<NU, true, false>(L, C, part, nt, S, sx);
             else
-                fine_pre_body<NU, false, false>(L, C, B.part, nt, S, sx);
+                fine_pre_body<NU, false, false>(L, C, part, nt, S, sx);
         } else {
             if (S.interior(L))
-                fine_post_body<NU, true, false>(L, C, B.part, nt, S, sx);
+                fine_post_body<NU, true, false>(L, C, part, nt, S, sx);
             else
-                fine_post_body<NU, false, false>(L, C, B.part, nt, S, sx);
+                fine_post_body<NU, false, false>(L, C, part, nt, S, sx);
         }
     }
 }
 
 template <int NU, bool PRE>
-__global__ __launch_bounds__(kNTs) void k_batch_mg(const BatchTable* __restrict__ T, int l) {
+__device__ __forceinline__ void batch_mg(const BatchTable* __restrict__ T, int l) {
     __shared__ int pref[kBatchMax + 1];
     const int total = batch_prefix(T, PRE ? kBPre : kBPost, l, pref);
     for (int v = blockIdx.x; v < total; v += gridDim.x) {
@@ -2484,26 +2515,53 @@ __global__ __launch_bounds__(kNTs) void k_batch_mg(const BatchTable* __restrict_
         const int gx = B.gx[l], gy = B.gy[l], per = gx * gy;
         const int c = k.loc / per, t = k.loc - c * per;
         const int ty = t / gx, tx = t - ty * gx;
+        const int* done = B.done;
+        double* part = B.part;
+        const LevelDev L = B.lev[l];
+        const LevelDev C = B.lev[l + 1];
         __syncthreads();
         if (PRE)
-            mg_pre_tile<NU, false, kTXs, kTYs, kNTs, false>(B.lev[l], B.lev[l + 1], 1, B.done,
-                                                            B.part, TileId(tx, ty, c), gx, gy);
+            mg_pre_tile<NU, false, kTXs, kTYs, kNTs, false>(L, C, 1, done, part,
+                                                            TileId(tx, ty, c), gx, gy);
         else
-            mg_post_tile<NU, false, kTXs, kTYs, kNTs, false>(B.lev[l], B.lev[l + 1], B.done,
-                                                             B.part, TileId(tx, ty, c), gx, gy);
+            mg_post_tile<NU, false, kTXs, kTYs, kNTs, false>(L, C, done, part,
+                                                             TileId(tx, ty, c), gx, gy);
     }
+}
+
+// Coarse-grid tiles (the pre pass at 8 waves per SIMD: its registers allow
+// it without spilling; the post pass keeps its registers).
+template <int NU>
+__global__ __launch_bounds__(kNTs) __attribute__((amdgpu_waves_per_eu(8))) void k_batch_mg_pre(
+    const BatchTable* __restrict__ T, int l) {
+    batch_mg<NU, true>(T, l);
+}
+template <int NU>
+__global__ __launch_bounds__(kNTs) void k_batch_mg_post(const BatchTable* __restrict__ T, int l) {
+    batch_mg<NU, false>(T, l);
 }
 
 __global__ __launch_bounds__(kLdsThreads) void k_batch_lds(const BatchTable* __restrict__ T) {
     extern __shared__ float lds[];
     __shared__ double sh[3 * (kLdsThreads / 64)];
     __shared__ int pref[kBatchMax + 1];
+    __shared__ LdsPlan sp;  // the task's plan, read from LDS by every thread
     const int total = batch_prefix(T, kBLds, 0, pref);
     for (int v = blockIdx.x; v < total; v += gridDim.x) {
         const BatchTask k(pref, v, total);
         const BatchSolve& B = T->e[k.e];
+        const int* done = B.done;
+        double* part = B.part;
         __syncthreads();
-        mg_lds_task<false>(B.lp, B.done, B.part, k.loc, lds, sh);
+        {
+            static_assert(sizeof(LdsPlan) % 4 == 0, "copied as 32-bit words");
+            const uint32_t* src = reinterpret_cast<const uint32_t*>(&B.lp);
+            uint32_t* dst = reinterpret_cast<uint32_t*>(&sp);
+            for (int i = threadIdx.x; i < (int)(sizeof(LdsPlan) / 4); i += blockDim.x)
+                dst[i] = src[i];
+        }
+        __syncthreads();
+        mg_lds_task<false>(sp, done, part, k.loc, lds, sh);
     }
 }
 
@@ -2514,8 +2572,14 @@ __global__ __launch_bounds__(kFinThreads) void k_batch_finalize(const BatchTable
     for (int v = blockIdx.x; v < total; v += gridDim.x) {
         const BatchTask k(pref, v, total);
         const BatchSolve& B = T->e[k.e];
+        const double* part = B.part;
+        const double* bnorm = B.bnorm;
+        int* done = B.done;
+        gdgs_stats* st = B.stats;
+        const int nblk = B.nblk, stop_eta = B.stop_eta;
+        const double tol = B.tol;
         __syncthreads();
-        finalize_task(B.part, B.nblk, B.bnorm, B.done, B.stats, B.tol, k.loc, B.stop_eta, sh);
+        finalize_task(part, nblk, bnorm, done, st, tol, k.loc, stop_eta, sh);
     }
 }
 
@@ -2702,10 +2766,10 @@ gdgs_status launch_batch_round(void* table, BatchRing* ring, int depth, int pre,
         g_fine[0][1] = persistent_grid((const void*)k_batch_fine<2, true>, 64 * kSNW, 0);
         g_fine[1][0] = persistent_grid((const void*)k_batch_fine<1, false>, 64 * kSNW, 0);
         g_fine[1][1] = persistent_grid((const void*)k_batch_fine<2, false>, 64 * kSNW, 0);
-        g_mg[0][0] = persistent_grid((const void*)k_batch_mg<1, true>, kNTs, 0);
-        g_mg[0][1] = persistent_grid((const void*)k_batch_mg<2, true>, kNTs, 0);
-        g_mg[1][0] = persistent_grid((const void*)k_batch_mg<1, false>, kNTs, 0);
-        g_mg[1][1] = persistent_grid((const void*)k_batch_mg<2, false>, kNTs, 0);
+        g_mg[0][0] = persistent_grid((const void*)k_batch_mg_pre<1>, kNTs, 0);
+        g_mg[0][1] = persistent_grid((const void*)k_batch_mg_pre<2>, kNTs, 0);
+        g_mg[1][0] = persistent_grid((const void*)k_batch_mg_post<1>, kNTs, 0);
+        g_mg[1][1] = persistent_grid((const void*)k_batch_mg_post<2>, kNTs, 0);
         g_lds = persistent_grid((const void*)k_batch_lds, kLdsThreads, lds_bytes);
         g_fin = persistent_grid((const void*)k_batch_finalize, kFinThreads, 0);
         sized = true;
@@ -2716,22 +2780,23 @@ gdgs_status launch_batch_round(void* table, BatchRing* ring, int depth, int pre,
     }
     const BatchTable* T = static_cast<const BatchTable*>(table);
     const int a = pre - 1, b = post - 1;
+    hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(64), 0, st, static_cast<BatchTable*>(table));
     if (pre == 1)
         hipLaunchKernelGGL((k_batch_fine<1, true>), dim3(g_fine[0][a]), dim3(64 * kSNW), 0, st, T);
     else
         hipLaunchKernelGGL((k_batch_fine<2, true>), dim3(g_fine[0][a]), dim3(64 * kSNW), 0, st, T);
     for (int l = 1; l <= depth; ++l) {
         if (pre == 1)
-            hipLaunchKernelGGL((k_batch_mg<1, true>), dim3(g_mg[0][a]), dim3(kNTs), 0, st, T, l);
+            hipLaunchKernelGGL((k_batch_mg_pre<1>), dim3(g_mg[0][a]), dim3(kNTs), 0, st, T, l);
         else
-            hipLaunchKernelGGL((k_batch_mg<2, true>), dim3(g_mg[0][a]), dim3(kNTs), 0, st, T, l);
+            hipLaunchKernelGGL((k_batch_mg_pre<2>), dim3(g_mg[0][a]), dim3(kNTs), 0, st, T, l);
     }
     hipLaunchKernelGGL(k_batch_lds, dim3(g_lds), dim3(kLdsThreads), lds_bytes, st, T);
     for (int l = depth; l >= 1; --l) {
         if (post == 1)
-            hipLaunchKernelGGL((k_batch_mg<1, false>), dim3(g_mg[1][b]), dim3(kNTs), 0, st, T, l);
+            hipLaunchKernelGGL((k_batch_mg_post<1>), dim3(g_mg[1][b]), dim3(kNTs), 0, st, T, l);
         else
-            hipLaunchKernelGGL((k_batch_mg<2, false>), dim3(g_mg[1][b]), dim3(kNTs), 0, st, T, l);
+            hipLaunchKernelGGL((k_batch_mg_post<2>), dim3(g_mg[1][b]), dim3(kNTs), 0, st, T, l);
     }
     if (post == 1)
         hipLaunchKernelGGL((k_batch_fine<1, false>), dim3(g_fine[1][b]), dim3(64 * kSNW), 0, st, T);
