@@ -275,6 +275,22 @@ gdgs_status gdgs_raster_laplacian(const gdgs_proj* proj, const float* opacity, c
                                   int64_t K, const gdgs_bins* bins, int32_t W, int32_t H,
                                   float* rho, void* ws, size_t ws_bytes, void* stream);
 
+/* Sparse compositing (Sec. 2.2 "Projection": the projected Laplacian field of
+ * Eq. 20 is sparse; Sec. 3.1: the hard threshold T of Eq. 24 gives the sparse
+ * representation): the three-channel composite of gdgs_raster_laplacian with
+ * T applied to every value before it is stored (kept when |x| >= threshold,
+ * ties kept, the comparison in FP32), fused into the compositing kernel, so no
+ * separate pass over rho is made.  threshold >= 0 (0 keeps every value).
+ * nonzero (device uint64, may be NULL) receives the number of values of
+ * rho[3][H][W] that are non-zero after the threshold (zeroed by the call).
+ * Tiles that no splat touches are written as zeros.  Errors as
+ * gdgs_raster_laplacian, plus GDGS_ERR_INVALID_ARGUMENT for threshold < 0. */
+gdgs_status gdgs_raster_laplacian_threshold(const gdgs_proj* proj, const float* opacity,
+                                            const float* lap, int64_t K, const gdgs_bins* bins,
+                                            int32_t W, int32_t H, float threshold, float* rho,
+                                            uint64_t* nonzero, void* ws, size_t ws_bytes,
+                                            void* stream);
+
 /* Profiling companion of gdgs_raster_grad: the same traversal without an
  * image; counts[0] (device, uint64) receives the number of (pixel, splat)
  * contributions the composite makes (terms of the sum of Eq. 20 with a non-zero
@@ -347,6 +363,20 @@ gdgs_status gdgs_render_laplacian(const gdgs_scene* scene, const gdgs_camera* ca
                                   const float* boundary, const gdgs_mg_params* mg,
                                   int64_t pair_capacity, float* u, gdgs_stats* stats_dev,
                                   int sync_stats, void* ws, size_t ws_bytes, void* stream);
+
+/* The sparse form of gdgs_render_laplacian (Sec. 2.2, Eq. 20 and 21, with the
+ * threshold of Eq. 24, Sec. 3.1): compositing with the threshold fused (see
+ * gdgs_raster_laplacian_threshold; nonzero may be NULL), and the solve's
+ * set-up reads rho only in tiles that some splat touches (the others are
+ * exact zeros).  Same arguments, workspace (gdgs_workspace_size) and errors
+ * as gdgs_render_laplacian, plus threshold >= 0.  The result equals
+ * gdgs_raster_laplacian_threshold followed by gdgs_poisson_solve_rhs. */
+gdgs_status gdgs_render_laplacian_sparse(const gdgs_scene* scene, const gdgs_camera* cam,
+                                         const float* boundary, const gdgs_mg_params* mg,
+                                         int64_t pair_capacity, float threshold, float* u,
+                                         gdgs_stats* stats_dev, uint64_t* nonzero,
+                                         int sync_stats, void* ws, size_t ws_bytes,
+                                         void* stream);
 
 /* ------------------------------------------------------------------ */
 /* Backward pass (gradients of a loss on u through the Poisson solve and the

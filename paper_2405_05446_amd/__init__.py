@@ -10,7 +10,8 @@ from .api import (  # noqa: F401
     DeviceScene, Renderer, alloc_bins, alloc_proj, camera_struct, gdgs_bin_sort,
     gdgs_div_adjoint, gdgs_poisson_solve, gdgs_poisson_solve_rhs, gdgs_project,
     gdgs_project_2d, gdgs_project_backward, gdgs_raster_grad, gdgs_raster_grad_backward,
-    gdgs_raster_laplacian, gdgs_render, gdgs_render_laplacian, mg_params, new_stats, read_stats,
+    gdgs_raster_laplacian, gdgs_raster_laplacian_threshold, gdgs_render, gdgs_render_laplacian,
+    gdgs_render_laplacian_sparse, mg_params, new_stats, read_stats,
     render_workspace_size, workspace, FMG, NEUMANN, RESUME, STOP_ETA, WARM_START,
 )
 from .serve import Server, now_ns  # noqa: F401

@@ -142,6 +142,18 @@ _SIGS = {
                                               ctypes.c_int32, P(MgParams), ctypes.c_void_p,
                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                               ctypes.c_void_p]),
+    "gdgs_raster_laplacian_threshold": (ctypes.c_int, [P(Proj), ctypes.c_void_p, ctypes.c_void_p,
+                                                       ctypes.c_int64, P(Bins), ctypes.c_int32,
+                                                       ctypes.c_int32, ctypes.c_float,
+                                                       ctypes.c_void_p, ctypes.c_void_p,
+                                                       ctypes.c_void_p, ctypes.c_size_t,
+                                                       ctypes.c_void_p]),
+    "gdgs_render_laplacian_sparse": (ctypes.c_int, [P(Scene), P(Camera), ctypes.c_void_p,
+                                                    P(MgParams), ctypes.c_int64, ctypes.c_float,
+                                                    ctypes.c_void_p, ctypes.c_void_p,
+                                                    ctypes.c_void_p, ctypes.c_int,
+                                                    ctypes.c_void_p, ctypes.c_size_t,
+                                                    ctypes.c_void_p]),
     "gdgs_poisson_solve_static": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
                                                  ctypes.c_int32, ctypes.c_int32, P(MgParams),
                                                  ctypes.c_void_p, ctypes.c_void_p,

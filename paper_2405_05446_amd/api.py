@@ -369,6 +369,58 @@ def gdgs_raster_laplacian(proj: dict, opacity: torch.Tensor, lap: torch.Tensor, 
     return rho
 
 
+def gdgs_raster_laplacian_threshold(proj: dict, opacity: torch.Tensor, lap: torch.Tensor, K: int,
+                                    bins: dict, W: int, H: int, t: float,
+                                    rho: torch.Tensor | None = None, count: bool = True,
+                                    ws: torch.Tensor | None = None, stream=None):
+    """Three-channel composite with the hard threshold of Eq. 24 fused in:
+    (rho [3][H][W], device int64 count of the kept non-zero values or None)."""
+    lib = L.load()
+    dev = bins["ranges"].device
+    _need(opacity, (K,), F32, "opacity")
+    _need(lap, (3, K), F32, "lap")
+    rho = rho if rho is not None else torch.empty((3, H, W), dtype=F32, device=dev)
+    if rho.dtype != F32 or not rho.is_contiguous() or rho.numel() < 3 * H * W:
+        raise ValueError("rho must be a contiguous float32 buffer of at least 3*H*W values")
+    nz = torch.zeros(1, dtype=torch.int64, device=dev) if count else None
+    need = _size(lib.gdgs_raster_workspace_size, K)
+    ws = ws if ws is not None else workspace(need, dev)
+    L.check(lib.gdgs_raster_laplacian_threshold(
+        ctypes.byref(_proj_struct(proj)), L.ptr(opacity), L.ptr(lap), K,
+        ctypes.byref(_bins_struct(bins)), W, H, float(t), L.ptr(rho), L.ptr(nz), L.ptr(ws),
+        ws.numel(), L.stream_handle(stream)))
+    return rho, nz
+
+
+def gdgs_render_laplacian_sparse(scene: DeviceScene, cam, boundary: torch.Tensor | None,
+                                 t: float = 0.0, mg=None, capacity: int | None = None, u=None,
+                                 stats=None, ws=None, sync_stats=False, count: bool = True,
+                                 stream=None):
+    """gdgs_render_laplacian with the threshold of Eq. 24 fused into the
+    compositing and a set-up that skips tiles without splats: (u, stats,
+    device int64 non-zero count or None)."""
+    lib = L.load()
+    dev = scene.opacity.device
+    W, H = int(cam.W), int(cam.H)
+    mg = mg if mg is not None else mg_params()
+    capacity = int(capacity if capacity is not None else max(1 << 16, 16 * scene.K))
+    if boundary is not None:
+        _need(boundary, (3, H, W), F32, "boundary")
+    u = u if u is not None else torch.empty((3, H, W), dtype=F32, device=dev)
+    _need(u, (3, H, W), F32, "u")
+    stats = stats if stats is not None else new_stats(dev)
+    nz = torch.zeros(1, dtype=torch.int64, device=dev) if count else None
+    if ws is None:
+        ws = workspace(render_workspace_size(scene.K, W, H, capacity, mg), dev)
+    c = camera_struct(cam)
+    L.check(lib.gdgs_render_laplacian_sparse(ctypes.byref(scene.struct(3)), ctypes.byref(c),
+                                             L.ptr(boundary), ctypes.byref(mg), capacity,
+                                             float(t), L.ptr(u), L.ptr(stats), L.ptr(nz),
+                                             1 if sync_stats else 0, L.ptr(ws), ws.numel(),
+                                             L.stream_handle(stream)))
+    return u, stats, nz
+
+
 def gdgs_render_laplacian(scene: DeviceScene, cam, boundary: torch.Tensor | None, mg=None,
                           capacity: int | None = None, u=None, stats=None, ws=None,
                           sync_stats=False, stream=None):
@@ -554,11 +606,14 @@ class Renderer:
         rec(1)
         gdgs_bin_sort(self.proj, K, W, H, self.capacity, self.bins, self.ws_bin, s)
         rec(2)
-        if self.laplacian:
+        if self.laplacian and self.threshold > 0.0:
+            # Eq. 24 fused into the compositing kernel
+            _, self.nonzero = gdgs_raster_laplacian_threshold(
+                self.proj, self.scene.opacity, self.scene.value, K, self.bins, W, H,
+                self.threshold, self.grad, ws=self.ws_ras, stream=s)
+        elif self.laplacian:
             gdgs_raster_laplacian(self.proj, self.scene.opacity, self.scene.value, K, self.bins,
                                   W, H, self.grad, self.ws_ras, s)
-            if self.threshold > 0.0:
-                self.nonzero = gdgs_threshold(self.grad[:3], self.threshold, stream=s)
         else:
             gdgs_raster_grad(self.proj, self.scene.opacity, self.scene.value, K, self.bins, W, H,
                              self.grad, self.ws_ras, s)

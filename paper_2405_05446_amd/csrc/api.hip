@@ -534,8 +534,11 @@ gdgs_status gdgs_bin_sort(const gdgs_proj* proj, int64_t K, int32_t W, int32_t H
 static gdgs_status raster_common(const gdgs_proj* proj, const float* opacity,
                                  const float* value, int64_t K, const gdgs_bins* bins, int32_t W,
                                  int32_t H, float* out, void* ws, size_t ws_bytes, void* stream,
-                                 int nch) {
+                                 int nch, float thr = -1.f, uint64_t* nonzero = nullptr) {
     clear_error();
+    if (nonzero)
+        REQUIRE((reinterpret_cast<uintptr_t>(nonzero) & 7u) == 0,
+                "nonzero is not 8-byte aligned");
     REQUIRE(K >= 0 && K < (int64_t)0xFFFFFFFFll, "K = %lld out of range", (long long)K);
     TRY(check_size(W, H));
     REQUIRE_PTR(out);
@@ -549,13 +552,15 @@ static gdgs_status raster_common(const gdgs_proj* proj, const float* opacity,
     gdgs_proj p = K > 0 ? *proj : gdgs_proj{};
     const gdgs_bins bb = *bins;
     KeyBuilder kb;
-    kb.tag("raster").add(nch).add(K).add(W).add(H).add(ws).add(opacity).add(value).add(out);
+    kb.tag("raster").add(nch).add(K).add(W).add(H).add(ws).add(opacity).add(value).add(out)
+        .add(thr).add(nonzero);
     add_proj(kb, p);
     add_bins(kb, bb);
     return with_graph(
         kb, as_stream(stream),
         [&](hipStream_t s) {
-            return launch_raster(p, opacity, value, K, bb, W, H, out, ws, s, nch);
+            return launch_raster(p, opacity, value, K, bb, W, H, out, ws, s, nch, thr,
+                                 reinterpret_cast<unsigned long long*>(nonzero));
         },
         {"raster"});
 }
@@ -570,6 +575,20 @@ gdgs_status gdgs_raster_laplacian(const gdgs_proj* proj, const float* opacity, c
                                   int64_t K, const gdgs_bins* bins, int32_t W, int32_t H,
                                   float* rho, void* ws, size_t ws_bytes, void* stream) {
     return raster_common(proj, opacity, lap, K, bins, W, H, rho, ws, ws_bytes, stream, 3);
+}
+
+gdgs_status gdgs_raster_laplacian_threshold(const gdgs_proj* proj, const float* opacity,
+                                            const float* lap, int64_t K, const gdgs_bins* bins,
+                                            int32_t W, int32_t H, float threshold, float* rho,
+                                            uint64_t* nonzero, void* ws, size_t ws_bytes,
+                                            void* stream) {
+    if (!(threshold >= 0.f)) {
+        clear_error();
+        set_error("threshold %g must be >= 0", (double)threshold);
+        return GDGS_ERR_INVALID_ARGUMENT;
+    }
+    return raster_common(proj, opacity, lap, K, bins, W, H, rho, ws, ws_bytes, stream, 3,
+                         threshold, nonzero);
 }
 
 gdgs_status gdgs_raster_count(const gdgs_proj* proj, const float* opacity, const float* value,
@@ -632,11 +651,23 @@ gdgs_status gdgs_poisson_solve_rhs(const float* rho, const float* boundary, int3
 
 // nch 6: gradient splats (composite, divergence, solve); nch 3: Laplacian
 // splats (the composite is the right-hand side).
+// sparse (nch 3): the hard threshold thr >= 0 of Eq. 24 fused into the
+// composite (kept values counted into *nonzero), and the solve's set-up skips
+// tiles without splats.
 static gdgs_status render_common(const gdgs_scene* scene, const gdgs_camera* cam,
                                  const float* boundary, const gdgs_mg_params* mg,
                                  int64_t pair_capacity, float* u, gdgs_stats* stats_dev,
-                                 int sync_stats, void* ws, size_t ws_bytes, void* stream, int nch) {
+                                 int sync_stats, void* ws, size_t ws_bytes, void* stream, int nch,
+                                 bool sparse = false, float thr = -1.f,
+                                 unsigned long long* nonzero = nullptr) {
     clear_error();
+    if (sparse) {
+        REQUIRE(nch == 3, "the sparse render takes Laplacian splats");
+        REQUIRE(thr >= 0.f, "threshold %g must be >= 0", (double)thr);
+        if (nonzero)
+            REQUIRE((reinterpret_cast<uintptr_t>(nonzero) & 7u) == 0,
+                    "nonzero is not 8-byte aligned");
+    }
     REQUIRE(scene != nullptr && cam != nullptr, "scene or camera is null");
     const int64_t K = scene->K;
     REQUIRE(K >= 0 && K < (int64_t)0xFFFFFFFFll, "K = %lld out of range", (long long)K);
@@ -671,7 +702,7 @@ static gdgs_status render_common(const gdgs_scene* scene, const gdgs_camera* cam
     const gdgs_scene sc = *scene;
     KeyBuilder kb;
     kb.tag("render").add(nch).add(K).add(W).add(H).add(pair_capacity).add(ws).add(sc.opacity)
-        .add(sc.value).add(boundary).add(u).add(stats_dev);
+        .add(sc.value).add(boundary).add(u).add(stats_dev).add(sparse).add(thr).add(nonzero);
     add_plan(kb, plan);
     KeyBuilder kr = kb;
     kr.tag("bin+raster");
@@ -680,12 +711,14 @@ static gdgs_status render_common(const gdgs_scene* scene, const gdgs_camera* cam
         [&](hipStream_t s) -> gdgs_status {
             TRY(launch_bin_sort(r.proj, K, W, H, r.bins, b, s));
             return launch_raster(r.proj, sc.opacity, sc.value, K, r.bins, W, H, r.grad,
-                                 r.raster_ws, s, nch);
+                                 r.raster_ws, s, nch, sparse ? thr : -1.f,
+                                 sparse ? nonzero : nullptr);
         },
         {"raster"}));
     // the Laplacian composite (first three planes of the gradient buffer) is rho
     TRY(launch_poisson(nch == 6 ? r.grad : nullptr, nch == 6 ? nullptr : r.grad, boundary, W, H,
-                       plan, u, stats_dev, r.poisson_ws, st, &kb));
+                       plan, u, stats_dev, r.poisson_ws, st, &kb, true,
+                       sparse ? r.bins.ranges : nullptr));
     TRY(launch_render_stats(r.bins.num_pairs, pair_capacity, stats_dev, st));
     if (sync_stats) {
         GDGS_HIP_TRY(hipStreamSynchronize(st));
@@ -714,6 +747,17 @@ gdgs_status gdgs_render_laplacian(const gdgs_scene* scene, const gdgs_camera* ca
                                   int sync_stats, void* ws, size_t ws_bytes, void* stream) {
     return render_common(scene, cam, boundary, mg, pair_capacity, u, stats_dev, sync_stats, ws,
                          ws_bytes, stream, 3);
+}
+
+gdgs_status gdgs_render_laplacian_sparse(const gdgs_scene* scene, const gdgs_camera* cam,
+                                         const float* boundary, const gdgs_mg_params* mg,
+                                         int64_t pair_capacity, float threshold, float* u,
+                                         gdgs_stats* stats_dev, uint64_t* nonzero,
+                                         int sync_stats, void* ws, size_t ws_bytes,
+                                         void* stream) {
+    return render_common(scene, cam, boundary, mg, pair_capacity, u, stats_dev, sync_stats, ws,
+                         ws_bytes, stream, 3, true, threshold,
+                         reinterpret_cast<unsigned long long*>(nonzero));
 }
 
 gdgs_status gdgs_div_adjoint(const float* lam, int32_t W, int32_t H, float* dgrad, void* stream) {

@@ -122,9 +122,12 @@ gdgs_status launch_project_2d(const float* mean2d, const float* conic, const flo
 // (a, 2b, c, alpha), (v0..v3), (v4, v5, 0, 0).
 size_t raster_ws_bytes(int64_t K);
 // nch: value rows and output channels (6 image gradients, or 3 Laplacians)
+// thr >= 0 (nch 3 only): the hard threshold of Eq. 24 fused into the store,
+// kept non-zero values counted into *nonzero (zeroed first; may be null)
 gdgs_status launch_raster(const gdgs_proj& proj, const float* opacity, const float* value,
                           int64_t K, const gdgs_bins& bins, int W, int H, float* grad,
-                          void* ws, hipStream_t st, int nch = 6);
+                          void* ws, hipStream_t st, int nch = 6, float thr = -1.f,
+                          unsigned long long* nonzero = nullptr);
 gdgs_status launch_raster_count(const gdgs_proj& proj, const float* opacity, const float* value,
                                 int64_t K, const gdgs_bins& bins, int W, int H,
                                 unsigned long long* counts, void* ws, hipStream_t st);
@@ -163,10 +166,14 @@ class KeyBuilder;
 // stream (lowest latency for one solve); false runs all channels in each
 // launch on `st`, the whole solve replayed as one graph (least host work,
 // for callers that already overlap many solves).
+// tile_ranges ([2][T] tile pair ranges of the composite that produced rho, or
+// null): the Dirichlet set-up of a given rho skips reading tiles that no splat
+// touches (their composite is exactly zero).
 gdgs_status launch_poisson(const float* grad, const float* rho, const float* boundary, int W,
                            int H, const MgPlan& plan, float* u, gdgs_stats* stats, void* ws,
                            hipStream_t st, const KeyBuilder* key = nullptr,
-                           bool channel_parallel = true);
+                           bool channel_parallel = true,
+                           const uint32_t* tile_ranges = nullptr);
 gdgs_status launch_div_adjoint(const float* lam, int W, int H, float* dgrad, hipStream_t st,
                                bool neumann = false);
 

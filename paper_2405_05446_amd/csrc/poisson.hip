@@ -188,10 +188,13 @@ __global__ void k_publish_converged(const int* __restrict__ done, gdgs_stats* __
 // rho (from the gradients or given), the level-0 right-hand side f0, the
 // initial u0 (ring = boundary, interior 0 unless warm), and per-block
 // max|b|, sum b^2 with b = -rho + ring neighbours.
+// ranges (rho given, or null): the [2][T] tile pair ranges of the composite
+// that produced rho; a tile without pairs holds exact zeros and is not read.
 __global__ __launch_bounds__(kDivTX* kDivTY) void k_div_init(
     const float* __restrict__ grad, const float* __restrict__ rho_in,
     const float* __restrict__ boundary, int H, int W, float* __restrict__ f0,
-    float* __restrict__ u0, double* __restrict__ bpart, int* __restrict__ counters, int warm) {
+    float* __restrict__ u0, double* __restrict__ bpart, int* __restrict__ counters, int warm,
+    const uint32_t* __restrict__ ranges = nullptr) {
     __shared__ double sh[3 * 4];
     const int c = blockIdx.z;
     if (blockIdx.x == 0 && blockIdx.y == 0 && c == 0 && threadIdx.x < kCounters)
@@ -215,6 +218,11 @@ __global__ __launch_bounds__(kDivTX* kDivTY) void k_div_init(
             ld[k][1] = gx[p - 1];
             ld[k][2] = gy[p];
             ld[k][3] = gy[p - W];
+        } else if (ranges) {
+            const int ntx = (W + kTile - 1) / kTile, T = ntx * ((H + kTile - 1) / kTile);
+            const int tile = (ic / kTile) * ntx + jc / kTile;
+            ld[k][0] = ranges[tile] != ranges[T + tile] ? rho_in[(size_t)c * HW + p] : 0.f;
+            ld[k][1] = ld[k][2] = ld[k][3] = 0.f;
         } else {
             ld[k][0] = rho_in[(size_t)c * HW + p];
             ld[k][1] = ld[k][2] = ld[k][3] = 0.f;
@@ -2093,7 +2101,8 @@ LdsPlan full_lds_plan(const MgPlan& p, const LevelDev* lev) {
 
 gdgs_status launch_poisson(const float* grad, const float* rho, const float* boundary, int W,
                            int H, const MgPlan& p, float* u, gdgs_stats* stats, void* ws,
-                           hipStream_t st, const KeyBuilder* key, bool channel_parallel) {
+                           hipStream_t st, const KeyBuilder* key, bool channel_parallel,
+                           const uint32_t* tile_ranges) {
     PoissonWs w;
     poisson_layout(p, W, H, ws, &w);
     gdgs_stats* sd = stats ? stats : w.stats;
@@ -2126,7 +2135,8 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
         hipLaunchKernelGGL(k_div_init,
                            dim3((W + kDivTX - 1) / kDivTX, (H + kDivRows - 1) / kDivRows, 3),
                            dim3(kDivTX * kDivTY), 0, s, grad, grad ? nullptr : rho, boundary, H,
-                           W, grad ? w.f0 : nullptr, u, w.bpart, w.counters, p.warm ? 1 : 0);
+                           W, grad ? w.f0 : nullptr, u, w.bpart, w.counters, p.warm ? 1 : 0,
+                           grad ? nullptr : tile_ranges);
         hipLaunchKernelGGL(k_setup_finalize, dim3(3), dim3(256), 0, s, w.bpart, nblk_div,
                            w.bnorm, w.done, w.counters, sd, p.warm ? 1 : 0);
         GDGS_LAUNCH_CHECK();
@@ -2696,7 +2706,7 @@ gdgs_status launch_poisson_setup(const float* grad, const float* boundary, int W
     gdgs_stats* sd = stats ? stats : w.stats;
     hipLaunchKernelGGL(k_div_init, dim3((W + kDivTX - 1) / kDivTX, (H + kDivRows - 1) / kDivRows, 3),
                        dim3(kDivTX * kDivTY), 0, st, grad, nullptr, boundary, H, W, w.f0, u,
-                       w.bpart, w.counters, p.warm ? 1 : 0);
+                       w.bpart, w.counters, p.warm ? 1 : 0, nullptr);
     hipLaunchKernelGGL(k_setup_finalize, dim3(3), dim3(256), 0, st, w.bpart,
                        setup_blocks(p, W, H), w.bnorm, w.done, w.counters, sd, p.warm ? 1 : 0);
     GDGS_LAUNCH_CHECK();

@@ -198,14 +198,18 @@ __device__ __forceinline__ void blend(const float4& q0, const float4& q1, const 
 // COUNT: write no image; add the number of (pixel, splat) contributions of
 // the block to counts[0] (profiling only).  NCH: channels written (6 image
 // gradients, or 3 Laplacians).
-template <bool COUNT, int NCH>
+// THR: the hard threshold of Eq. 24 (Sec. 3.1) is applied to each composited
+// value before it is stored (a value is kept when |x| >= thr), and the kept
+// non-zero values are counted into counts[0].
+template <bool COUNT, int NCH, bool THR = false>
 __global__ __launch_bounds__(256) void k_raster_fwd(const float4* __restrict__ rec,
                                                     const uint32_t* __restrict__ splat_of_pair,
                                                     const uint32_t* __restrict__ ranges,
                                                     const uint32_t* __restrict__ tile_order, int T,
                                                     int nx, int W, int H, int64_t K,
                                                     float* __restrict__ grad,
-                                                    unsigned long long* __restrict__ counts) {
+                                                    unsigned long long* __restrict__ counts,
+                                                    float thr = 0.f) {
     // per batch entry: the pair's exponent form (s_r0, s_r1) and the values
     // (s_r2, s_r3); slot kBatch is inert (alpha 0), used to pad the wave lists
     __shared__ float4 s_r0[kBatch + 1], s_r1[kBatch + 1], s_r2[kBatch + 1], s_r3[kBatch + 1];
@@ -294,10 +298,21 @@ __global__ __launch_bounds__(256) void k_raster_fwd(const float4* __restrict__ r
         if (lane == 0) atomicAdd(counts, v);
         return;
     }
+    uint32_t kept = 0;
     if (inside) {
         const size_t HW = (size_t)H * W, p = (size_t)py * W + px;
 #pragma unroll
-        for (int m = 0; m < NCH; ++m) grad[m * HW + p] = acc[m];
+        for (int m = 0; m < NCH; ++m) {
+            const float v = THR ? (fabsf(acc[m]) >= thr ? acc[m] : 0.f) : acc[m];
+            grad[m * HW + p] = v;
+            kept += (THR && v != 0.f) ? 1u : 0u;
+        }
+    }
+    if (THR && counts) {
+        unsigned long long v = kept;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+        if (lane == 0 && v) atomicAdd(counts, v);
     }
 }
 
@@ -495,7 +510,11 @@ size_t raster_ws_bytes(int64_t K) {
 
 gdgs_status launch_raster(const gdgs_proj& proj, const float* opacity, const float* value,
                           int64_t K, const gdgs_bins& bins, int W, int H, float* grad, void* ws,
-                          hipStream_t st, int nch) {
+                          hipStream_t st, int nch, float thr, unsigned long long* nonzero) {
+    if (thr >= 0.f && nch != 3) {
+        set_error("the threshold applies to the three-channel (Laplacian) composite");
+        return GDGS_ERR_INVALID_ARGUMENT;
+    }
     Carver c(ws);
     float4* rec = c.take<float4>(4 * (size_t)(K > 0 ? K : 1));
     const int nx = tiles_x(W), T = nx * tiles_y(H);
@@ -507,14 +526,23 @@ gdgs_status launch_raster(const gdgs_proj& proj, const float* opacity, const flo
     hipEvent_t ev0, ev1;
     const bool timed = timer_events("raster", &ev0, &ev1);
     if (timed) GDGS_HIP_TRY(hipEventRecord(ev0, st));
-    if (nch == 3)
+    if (thr >= 0.f) {
+        if (nonzero) {
+            const gdgs_status z =
+                launch_fill_u32(reinterpret_cast<uint32_t*>(nonzero), 2, 0u, st);
+            if (z != GDGS_OK) return z;
+        }
+        hipLaunchKernelGGL((k_raster_fwd<false, 3, true>), dim3(T), dim3(256), 0, st, rec,
+                           bins.splat_of_pair, bins.ranges, bins.tile_order, T, nx, W, H, K, grad,
+                           nonzero, thr);
+    } else if (nch == 3)
         hipLaunchKernelGGL((k_raster_fwd<false, 3>), dim3(T), dim3(256), 0, st, rec,
                            bins.splat_of_pair, bins.ranges, bins.tile_order, T, nx, W, H, K, grad,
-                           nullptr);
+                           nullptr, 0.f);
     else
         hipLaunchKernelGGL((k_raster_fwd<false, 6>), dim3(T), dim3(256), 0, st, rec,
                            bins.splat_of_pair, bins.ranges, bins.tile_order, T, nx, W, H, K, grad,
-                           nullptr);
+                           nullptr, 0.f);
     if (timed) GDGS_HIP_TRY(hipEventRecord(ev1, st));
     GDGS_LAUNCH_CHECK();
     return GDGS_OK;
@@ -535,7 +563,7 @@ gdgs_status launch_raster_count(const gdgs_proj& proj, const float* opacity, con
     }
     hipLaunchKernelGGL((k_raster_fwd<true, 6>), dim3(T), dim3(256), 0, st, rec,
                        bins.splat_of_pair, bins.ranges, bins.tile_order, T, nx, W, H, K, nullptr,
-                       counts);
+                       counts, 0.f);
     GDGS_LAUNCH_CHECK();
     return GDGS_OK;
 }

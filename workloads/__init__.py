@@ -76,6 +76,11 @@ CONFIGS = {
                  tol=1e-6, ring="zero"),
     "serve": dict(W=1920, H=1080, K=500_000, z=(2.0, 20.0), ls=(-5.0, 0.7),
                   levels=8, tol=1e-6, ring="reference"),
+    # the sparse regime of the paper's trained scenes: a few thousand splats
+    # per scene (5,100 is the largest count reported) carrying Laplacian
+    # values, at 1080p, with the full workload's distributions
+    "sparse": dict(W=1920, H=1080, K=5_100, z=(2.0, 20.0), ls=(-5.0, 0.7),
+                   levels=8, tol=1e-6, ring="reference"),
 }
 
 # Serving mix: request sizes drawn uniformly from these (W, H).
