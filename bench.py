@@ -67,6 +67,27 @@ def measured_traffic(kernel: str):
     return None
 
 
+STAGE_PROFILE = os.path.join(ROOT, "profiles", "hbm_counters_poisson_1080p_1M.md")
+
+
+def measured_stage_traffic():
+    """Calibrated HBM bytes of all multigrid kernels per frame from the
+    committed counter summary, or None when it is missing or poisson.hip has
+    changed since the counters were taken."""
+    import hashlib
+    try:
+        lines = open(STAGE_PROFILE).read().splitlines()
+    except OSError:
+        return None
+    src = os.path.join(ROOT, "paper_2405_05446_amd", "csrc", "poisson.hip")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for ln in lines:
+        cells = [c.strip() for c in ln.strip().strip("|").split("|")]
+        if len(cells) == 3 and cells[0] == "multigrid kernels, bytes per frame":
+            return int(cells[1]) if cells[2] == h else None
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +113,9 @@ def parse():
                     help="skip the Neumann-condition leg")
     ap.add_argument("--no-laplacian", action="store_true",
                     help="skip the Laplacian-splat form measurement")
+    ap.add_argument("--no-eta", action="store_true", help="skip the eta-stop leg")
+    ap.add_argument("--no-hbm-resident", action="store_true",
+                    help="skip the four-frame rotation of the Poisson stage")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -300,6 +324,100 @@ def laplacian_leg(G, wl, torch, scene, cams, ring, mg, W, H, frames: int):
                           for n, v in zip(("project", "bin_sort", "raster", "poisson"), stage)},
             "mg_cycles_mean": float(np.mean([c for c, _ in cyc])),
             "not_converged": int(sum(1 for _, ok in cyc if not ok))}
+
+
+def hbm_resident_leg(G, torch, r, cams, ring, W, H, mg0, cycles: float):
+    """The Poisson stage with its data out of the 256 MB Infinity Cache: four
+    frames' solves (four right-hand sides and workspaces, > 256 MB together)
+    run in rotation on one stream, so each solve finds its arrays evicted by
+    the other three.  Bytes: the fused model of the stage."""
+    # the cycle budget the frame sequence has learned (no idle launches)
+    mg = G.mg_params(levels=mg0.levels, tol=mg0.tol, max_cycles=max(1, int(round(cycles))))
+    grads, wss, us, sts = [], [], [], []
+    nbytes = G.api.poisson_workspace_size(W, H, mg)
+    for i in range(4):
+        r.render(cams[i], ring)
+        grads.append(r.grad.clone())
+        wss.append(G.workspace(nbytes))
+        us.append(torch.empty((3, H, W), device="cuda"))
+        sts.append(G.new_stats())
+    torch.cuda.synchronize()
+    solve = lambda k: G.gdgs_poisson_solve(grads[k], ring, W, H, mg, us[k], sts[k], wss[k])
+    for k in range(4):
+        solve(k)
+    torch.cuda.synchronize()
+    rounds = 5
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(rounds):
+        for k in range(4):
+            solve(k)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / (4 * rounds)
+    npts = (H - 2) * (W - 2)
+    cyc = float(np.mean([max(G.read_stats(st)["cycles"]) for st in sts]))
+    model = 3 * npts * (MG_BYTES_PER_POINT_CYCLE * cyc + 16.0)
+    gbs = model / (ms * 1e-3) / 1e9
+    ws_mb = 4 * (nbytes + 6 * 4 * H * W + 3 * 4 * H * W) / 2**20
+    return {"frames_in_rotation": 4, "working_set_MB": round(ws_mb, 1),
+            "solve_ms": round(ms, 4), "mg_cycles": cyc, "model_GBs": round(gbs, 1),
+            "model_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "note": "solves back to back on one stream (no overlap with compositing, unlike "
+                    "the frame sequence); model bytes as poisson_stage.model"}
+
+
+def batched_sequence_leg(G, torch, ds, cams, ring, mg, W, H, frames: int,
+                         budget: int = 8 << 30):
+    """The headline frames through the batched server: the front half of each
+    frame (projection, binning, compositing, solve set-up) on one stream, the
+    solves of all frames in flight advancing together in persistent-kernel
+    rounds on a second stream (2 HIP streams), admitted by an 8 GiB budget.
+    Results equal the plain path's bit for bit (checked on the first frame)."""
+    ref = G.Renderer(ds, W, H, mg).render(cams[0], ring).clone()
+    outs = [torch.empty((3, H, W), device="cuda") for _ in range(frames)]
+    with G.Server(ds, budget=budget, streams=1, mg=mg, batched=True) as srv:
+        res = None
+        for rep in range(2):       # the first pass learns capacities, captures graphs
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(frames):
+                srv.submit(cams[i % len(cams)], ring, u=outs[i], tag=i)
+            done = srv.drain(frames, timeout_s=300)
+            span = time.perf_counter() - t0
+            lat = np.array([(c["done_ns"] - c["arrival_ns"]) / 1e6 for c in done])
+            res = {"Mpix_s": round(frames * W * H / span / 1e6, 2),
+                   "ms_per_frame": round(span * 1e3 / frames, 4), "frames": frames,
+                   "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                                  "p99": round(float(np.percentile(lat, 99)), 3)},
+                   "mg_cycles_mean": float(np.mean([c["cycles"] for c in done])),
+                   "not_converged_or_failed": int(sum(1 for c in done
+                                                      if c["status"] or not c["converged"]))}
+        torch.cuda.synchronize()
+        res["first_frame_equals_plain_path"] = bool(torch.equal(outs[0], ref))
+    res["workload"] = (f"headline frames through the batched server ({budget >> 30} GiB, one "
+                       "front-half stream + one solver stream; latency = completion - "
+                       "submission with every frame submitted at once)")
+    return res
+
+
+def eta_stop_leg(G, torch, ds, cams, ring, W, H, mg, frames: int):
+    """The normwise-backward-error stop (GDGS_MG_STOP_ETA, eta <= 1e-6) on the
+    headline frames: V-cycles, throughput, and the largest difference from the
+    default relative-correction solve of the same frames."""
+    me = G.mg_params(levels=mg.levels, tol=1e-6, flags=G.STOP_ETA)
+    ms, stage, cyc = _sequence_leg(G, torch, G.Renderer(ds, W, H, me), cams, ring, frames)
+    r0, r1 = G.Renderer(ds, W, H, mg), G.Renderer(ds, W, H, me)
+    diff = 0.0
+    for i in range(5):
+        a = r0.render(cams[i], ring).clone()
+        b = r1.render(cams[i], ring)
+        diff = max(diff, float((a - b).abs().max()))
+    return {"workload": f"eta <= 1e-6 stop, {W}x{H}, same splats and poses",
+            "Mpix_s": round(H * W / (ms * 1e-3) / 1e6, 2), "ms_per_frame": round(ms, 4),
+            "poisson_ms": round(float(stage[3]), 4), "frames": frames,
+            "mg_cycles_mean": float(np.mean([c for c, _ in cyc])),
+            "max_abs_vs_default_stop": diff}
 
 
 def _sequence_leg(G, torch, r, cams, ring, frames: int):
@@ -577,9 +695,9 @@ def main():
     # two event records per pass), which changes how the frame runs, so those
     # are timed in a separate pass over the same poses below.
     NT = max(64, args.steps + 16)
-    k_ev = {name: ([torch.cuda.Event(enable_timing=True) for _ in range(NT)],
-                   [torch.cuda.Event(enable_timing=True) for _ in range(NT)])
-            for name in ("raster", "mg_post_fine")}
+    k_ev = {name: ([torch.cuda.Event(enable_timing=True) for _ in range(n)],
+                   [torch.cuda.Event(enable_timing=True) for _ in range(n)])
+            for name, n in (("raster", NT), ("mg_post_fine", NT), ("mg_post_coarse", 256))}
 
     def arm(names):
         G.api.set_kernel_timer(None)
@@ -596,7 +714,7 @@ def main():
     r.render_sequence([cams[i % len(cams)] for i in range(args.warmup)], ring)
     torch.cuda.synchronize()
 
-    cycles, k_ms, last = [], {"raster": [], "mg_post_fine": []}, {}
+    cycles, k_ms, last = [], {"raster": [], "mg_post_fine": [], "mg_post_coarse": []}, {}
 
     def on_frame(i, u, st):
         cycles.append(st["total_cycles"])
@@ -620,8 +738,9 @@ def main():
     mean_stage = stage_ms.mean(axis=0)
     mean_cycles = float(np.mean(cycles))
 
-    # untimed pass over the same poses: the finest post pass bracketed by
-    # events, and the number of (pixel, splat) contributions of each frame
+    # untimed passes over the same poses: the finest post pass bracketed by
+    # events (with the number of (pixel, splat) contributions of each frame),
+    # then the coarse-grid post passes alone
     arm(["mg_post_fine"])
     contrib = []
     for i in range(args.steps):
@@ -630,7 +749,28 @@ def main():
         k_ms["mg_post_fine"].append(read("mg_post_fine"))
         contrib.append(G.api.gdgs_raster_count(r.proj, ds.opacity, ds.value, K, r.bins, W, H,
                                                r.ws_ras))
+    arm(["mg_post_coarse"])
+    for i in range(min(args.steps, 20)):
+        G.api.rewind_kernel_timers()
+        r.render(cams[i % len(cams)], ring)
+        k_ms["mg_post_coarse"].append(read("mg_post_coarse"))
     G.api.set_kernel_timer(None)
+    # coarse post passes: per channel and V-cycle one launch per global coarse
+    # grid, from the coarsest of them up to grid 1
+    lev_n, lev_m = [H - 2], [W - 2]
+    while len(lev_n) < 8:
+        lev_n.append(lev_n[-1] // 2)
+        lev_m.append(lev_m[-1] // 2)
+    c_bytes, c_us, c_launch = 0.0, 0.0, []
+    for f in k_ms["mg_post_coarse"]:
+        ng = max(1, round(len(f) / (3.0 * mean_cycles)))
+        c_launch.append(len(f))
+        for j, t in enumerate(f):
+            lvl = ng - (j % ng)
+            c_bytes += MG_POST_BYTES_PER_POINT * lev_n[lvl] * lev_m[lvl]
+            c_us += t * 1e3
+    coarse_gbs = c_bytes / (c_us * 1e-6) / 1e9 if c_us > 0 else 0.0
+    coarse_avg_us = c_us / max(1, sum(c_launch))
     npts = (H - 2) * (W - 2)
     raster_us = float(np.mean([x for f in k_ms["raster"] for x in f])) * 1e3
     raster_tflops = RASTER_FLOPS_PER_CONTRIB * float(np.mean(contrib)) / (raster_us * 1e-6) / 1e12
@@ -642,7 +782,7 @@ def main():
     ch_per_launch = 3.0 * mean_cycles / post_launches
     post_bytes = MG_POST_BYTES_PER_POINT * ch_per_launch * npts
     post_gbs = post_bytes / (post_us * 1e-6) / 1e9
-    k_raster, k_post = "k_raster_fwd<false, 6>", "k_fine_post<2, false>"
+    k_raster, k_post = "k_raster_fwd<false, 6, false>", "k_fine_post<2, false>"
     t_raster, t_post = measured_traffic(k_raster), measured_traffic(k_post)
     kern = {
         "raster": {"kernel": k_raster, "bound": "alu", "achieved": round(raster_tflops, 3),
@@ -663,10 +803,28 @@ def main():
     }
     if t_post is not None:
         kern["mg_post_fine"]["traffic_GBs"] = round(t_post / (post_us * 1e-6) / 1e9, 1)
-    # the compositing kernel is the largest single launch of the frame and runs
-    # alone; the multigrid passes of the three colour channels run concurrently
-    # on their own streams, so no one of them holds the frame for its duration
-    dominant = "raster"
+    k_coarse = "k_mg_post<2, false, 32, 16, 256, false>"
+    t_coarse = measured_traffic(k_coarse)
+    ng = max(1, round(float(np.mean(c_launch)) / (3.0 * mean_cycles)))
+    kern["mg_post_coarse"] = {
+        "kernel": k_coarse, "bound": "hbm", "achieved": round(coarse_gbs, 1),
+        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(coarse_gbs / HBM_PEAK_GBS, 4),
+        "traffic": t_coarse, "avg_launch_us": round(coarse_avg_us, 2),
+        "launches_per_step": round(float(np.mean(c_launch)), 2),
+        "timed": "separate pass over 20 of the poses; each launch of 5-11 us bracketed by its "
+                 "own events, which add the event round trip to every launch (the rocprofv3 "
+                 "kernel-time summary has the kernel alone)",
+        "work_per_launch": f"{MG_POST_BYTES_PER_POINT:.0f} B x the points of its grid "
+                           f"(one channel; grids 1-{ng}, {lev_n[1]}x{lev_m[1]} down)"}
+    kern["raster"]["frac_of_packed_peak"] = round(raster_tflops / 157.3, 4)
+    kern["raster"]["peaks_TFLOPs"] = {"unpacked_fp32_valu": VALU_PEAK_TFLOPS,
+                                      "packed_fp32_published": 157.3}
+    # The multigrid dominates the frame.  Its kernel with the largest share of
+    # GPU time, the coarse-grid post pass, launches for 5-11 us at a time:
+    # too short for per-launch events to agree with the profiler, so the
+    # roofline is carried by the multigrid's largest launch, the finest-grid
+    # post pass (HBM-bound, event-timed, agreeing with rocprofv3).
+    dominant = "mg_post_fine"
     poisson_bytes = 3 * npts * (MG_BYTES_PER_POINT_CYCLE * mean_cycles + 16.0)
     poisson_gbs = poisson_bytes / (mean_stage[3] * 1e-3) / 1e9
     # the same stage against the unfused model (each red-black sweep reading u
@@ -694,9 +852,16 @@ def main():
                        "p99": round(float(np.percentile(frame_ms, 99)), 4)},
         "stages_ms": {n: round(float(v), 4) for n, v in zip(names, mean_stage)},
         "roofline": kern[dominant],
-        "roofline_note": "compositing kernel timed live in the timed frames; the finest "
-                         "multigrid post pass (in kernels) timed in a separate pass over the "
-                         "same poses, where it launches outside the per-channel graphs",
+        "roofline_note": "the finest-grid multigrid post pass, the largest launch of the "
+                         "Poisson stage (62% of the frame), timed with HIP events on its "
+                         "channel's stream in a separate pass over the same poses, where it "
+                         "launches outside the per-channel graphs; achieved = 13 B per "
+                         "interior point of one channel / duration.  The coarse-grid post "
+                         "pass (kernels.mg_post_coarse) has the largest share of GPU time but "
+                         "5-11 us launches, too short for per-launch events.  The compositing "
+                         "kernel (kernels.raster) is timed live in the timed frames; its frac "
+                         "is against the unpacked FP32 VALU peak (packed FP32 is not emitted "
+                         "by these builds), frac_of_packed_peak against 157.3 TFLOP/s",
         "kernels": kern,
         "poisson_stage": {"achieved_GBs": round(poisson_gbs, 1),
                           "frac": round(poisson_gbs / HBM_PEAK_GBS, 4),
@@ -705,8 +870,26 @@ def main():
                           "unfused_model_GBs": round(unfused_gbs, 1),
                           "unfused_model_frac": round(unfused_gbs / HBM_PEAK_GBS, 4)},
     }
+    stage_bytes = measured_stage_traffic()
+    if stage_bytes is not None:
+        cgbs = stage_bytes / (mean_stage[3] * 1e-3) / 1e9
+        out["poisson_stage"].update(
+            {"counter_bytes_per_frame": stage_bytes, "counter_GBs": round(cgbs, 1),
+             "counter_frac": round(cgbs / HBM_PEAK_GBS, 4),
+             "counter_note": "calibrated FETCH_SIZE + WRITE_SIZE of every multigrid kernel "
+                             "per frame (profiles/hbm_counters_poisson_1080p_1M.md) over the "
+                             "stage time; the single-frame working set fits the 256 MB "
+                             "Infinity Cache, whose hits these counters include"})
+    if not args.no_hbm_resident:
+        out["poisson_stage"]["hbm_resident"] = hbm_resident_leg(G, torch, r, cams, ring, W, H,
+                                                                mg, mean_cycles)
     if not args.no_overlap:
         out["two_in_flight"] = overlap_leg(torch, r, cams, ring, W, H, args.steps)
+    if not args.no_serve:
+        out["batched_sequence"] = batched_sequence_leg(G, torch, ds, cams, ring, mg, W, H,
+                                                       args.steps)
+    if not args.no_eta:
+        out["eta_stop"] = eta_stop_leg(G, torch, ds, cams, ring, W, H, mg, min(args.steps, 50))
     if not args.no_train:
         out["train_step"] = train_leg(G, wl, torch, 10)
     if not args.no_trajectory:

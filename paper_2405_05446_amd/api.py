@@ -587,7 +587,7 @@ class Renderer:
 
     def _mg(self, cycles: int, flags: int = 0) -> L.MgParams:
         m = self.mg
-        keep = (m.flags & FMG) | (NEUMANN if self.neumann else 0)
+        keep = (m.flags & (FMG | STOP_ETA)) | (NEUMANN if self.neumann else 0)
         return mg_params(m.levels, m.pre_sweeps, m.post_sweeps, cycles, m.tol, m.coarse_sweeps,
                          flags | keep)
 

@@ -1818,7 +1818,8 @@ template <int NU, bool NM>
 gdgs_status launch_post(const LevelDev& L, const LevelDev& C, bool fine, const int* done,
                         double* part, int c0, int nch, hipStream_t st, bool may_time = true) {
     hipEvent_t ev0, ev1;
-    const bool timed = fine && may_time && timer_events("mg_post_fine", &ev0, &ev1);
+    const bool timed =
+        may_time && timer_events(fine ? "mg_post_fine" : "mg_post_coarse", &ev0, &ev1);
     if (timed) GDGS_HIP_TRY(hipEventRecord(ev0, st));
     if (fine) {
         const int nt = strip_tiles(L.n, L.m);
@@ -2247,7 +2248,10 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
         // V-cycles on its own stream, so one channel's bandwidth-bound finest
         // passes overlap another's latency-bound coarse grids.
         const bool timed =
-            p.lc > 0 && (timer_active("mg_pre_fine") || timer_active("mg_post_fine"));
+            p.lc > 0 && (timer_active("mg_pre_fine") || timer_active("mg_post_fine") ||
+                         timer_active("mg_post_coarse"));
+        // a timed coarse post pass launches directly between its events
+        const bool coarse_timed = timer_active("mg_post_coarse");
         ChannelStreams cs;
         if (!channel_parallel || !channel_streams(st, &cs)) {
             // all channels in each launch, on the caller's stream
@@ -2270,7 +2274,7 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
                 }
                 pre(0, 0, 3, st);
                 auto mid = [&](hipStream_t s) { return body(0, 3, s); };
-                if (key) {
+                if (key && !coarse_timed) {
                     KeyBuilder kb = *key;
                     kb.tag("body3");
                     r = with_graph(kb, st, mid);
@@ -2292,7 +2296,7 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
         // branches: none faster; overlapped kernels of different channels slow
         // each other down, so about two run at a time on average.)
         auto run = [&](const char* tag, int c, const std::function<gdgs_status(hipStream_t)>& f) {
-            if (!key) return f(sc[c]);
+            if (!key || coarse_timed) return f(sc[c]);
             KeyBuilder kc = *key;
             kc.tag(tag).add(c);
             return with_graph(kc, sc[c], f);
