@@ -105,8 +105,10 @@ def parse():
     ap.add_argument("--no-trajectory", action="store_true",
                     help="skip the cold/warm-start camera-path measurement")
     ap.add_argument("--no-fmg", action="store_true", help="skip the full-multigrid leg")
-    ap.add_argument("--no-overlap", action="store_true",
-                    help="skip the two-frames-in-flight leg")
+    ap.add_argument("--no-overlap", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--overlap", action="store_true",
+                    help="add the two-frames-in-flight leg (two frame streams, each with its "
+                         "own channel streams: more streams than the 4 hardware queues)")
     ap.add_argument("--large", action="store_true",
                     help="add the 3840x2160, 4M-splat leg (not run by default)")
     ap.add_argument("--no-neumann", action="store_true",
@@ -883,7 +885,7 @@ def main():
     if not args.no_hbm_resident:
         out["poisson_stage"]["hbm_resident"] = hbm_resident_leg(G, torch, r, cams, ring, W, H,
                                                                 mg, mean_cycles)
-    if not args.no_overlap:
+    if args.overlap and not args.no_overlap:
         out["two_in_flight"] = overlap_leg(torch, r, cams, ring, W, H, args.steps)
     if not args.no_serve:
         out["batched_sequence"] = batched_sequence_leg(G, torch, ds, cams, ring, mg, W, H,

@@ -2763,9 +2763,14 @@ gdgs_status batch_deactivate(void* table, int e, hipStream_t st) {
     return GDGS_OK;
 }
 
+namespace {
+int g_fine[2][2], g_mg[2][2], g_lds, g_fin;  // persistent grid sizes (set once)
+gdgs_status enqueue_batch_round(const BatchTable* T, BatchRing* ring, int depth, int pre,
+                                int post, int a, int b, size_t lds_bytes, hipStream_t st);
+}  // namespace
+
 gdgs_status launch_batch_round(void* table, BatchRing* ring, int depth, int pre, int post,
                                hipStream_t st) {
-    static int g_fine[2][2], g_mg[2][2], g_lds, g_fin;
     static bool sized = false;
     const size_t lds_bytes = (size_t)lds_budget();
     if (!sized) {
@@ -2794,7 +2799,19 @@ gdgs_status launch_batch_round(void* table, BatchRing* ring, int depth, int pre,
     }
     const BatchTable* T = static_cast<const BatchTable*>(table);
     const int a = pre - 1, b = post - 1;
-    hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(64), 0, st, static_cast<BatchTable*>(table));
+    // the round's launches depend only on the table, the ring, the depth and
+    // the sweeps: one cached graph per such set, replayed every round
+    KeyBuilder kb;
+    kb.tag("batch-round").add(table).add(ring).add(depth).add(pre).add(post);
+    return with_graph(kb, st, [&](hipStream_t s) -> gdgs_status {
+        return enqueue_batch_round(T, ring, depth, pre, post, a, b, lds_bytes, s);
+    });
+}
+
+namespace {
+gdgs_status enqueue_batch_round(const BatchTable* T, BatchRing* ring, int depth, int pre,
+                                int post, int a, int b, size_t lds_bytes, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(64), 0, st, const_cast<BatchTable*>(T));
     if (pre == 1)
         hipLaunchKernelGGL((k_batch_fine<1, true>), dim3(g_fine[0][a]), dim3(64 * kSNW), 0, st, T);
     else
@@ -2822,5 +2839,6 @@ gdgs_status launch_batch_round(void* table, BatchRing* ring, int depth, int pre,
     GDGS_LAUNCH_CHECK();
     return GDGS_OK;
 }
+}  // namespace
 
 }  // namespace gdgs
