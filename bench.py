@@ -100,6 +100,8 @@ def parse():
     ap.add_argument("--cpu-pixels", type=int, default=2074,
                     help="sampled pixels of the oracle's compositing (0.1%% of 1080p)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-serving-sweep", action="store_true",
+                    help="keep the batched-server sequence, skip the arrival-rate sweep")
     ap.add_argument("--no-train", action="store_true",
                     help="skip the Algorithm-1 iteration measurement")
     ap.add_argument("--no-trajectory", action="store_true",
@@ -907,7 +909,7 @@ def main():
         out["laplacian_form"] = laplacian_leg(G, wl, torch, scene, cams, ring, mg, W, H,
                                               min(args.steps, 50))
         out["sparsity"] = sparsity_leg(G, wl, torch, min(args.steps, 50))
-    if not args.no_serve:
+    if not args.no_serve and not args.no_serving_sweep:
         out["serving"] = serving_leg(G, wl, torch, args.serve_requests, args.serve_streams)
     if cpu is not None:
         out["cpu_baseline"] = cpu

@@ -83,13 +83,16 @@ def test_convergence_factor_per_cycle():
     rng = np.random.default_rng(1)
     rho = np.zeros((3, H, W))
     rho[:, 1:-1, 1:-1] = rng.normal(0, 0.05, (3, H - 2, W - 2))
+    # cycles 1-3 only: by the fourth the relative residual of this white-noise
+    # right-hand side sits at the FP32 rounding floor of the iterate (about
+    # 4.5 x 2^-24 x rms(u) / rms(rho), ~3e-5 here), where the ratio means nothing
     etas = []
-    for cyc in (1, 2, 3, 4):
+    for cyc in (1, 2, 3):
         _, st = solve_rhs(rho, None, G.mg_params(tol=0.0, max_cycles=cyc))
         etas.append(max(st["rel_res"]))
-    factors = [etas[i + 1] / etas[i] for i in range(3)]
+    factors = [etas[i + 1] / etas[i] for i in range(2)]
     say(f"[poisson] rel_res per cycle {etas}, factors {factors}")
-    assert max(factors) <= 0.2
+    assert max(factors) <= 0.1
 
 
 def test_warm_start_continues_from_the_given_iterate():
