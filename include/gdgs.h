@@ -204,6 +204,15 @@ void gdgs_clear_graphs(void);
  * outlive the timer.  n <= 0 clears that name, kernel NULL clears all. */
 gdgs_status gdgs_set_kernel_timer(const char* kernel, void** start_events, void** stop_events,
                                   int n);
+/* Host-only profiling hook: each timed launch of an armed multigrid post
+ * pass ("mg_post_fine" or "mg_post_coarse") is issued `repeats` (1..64) times
+ * in a row between its two events, so that the event overhead is spread over
+ * the repeats.  A post pass reads the second buffer, the right-hand side and
+ * the coarse correction and writes the iterate and its norm records, none of
+ * which it reads, so the repeats leave every result unchanged.  Re-arming the
+ * name resets it to 1.  GDGS_ERR_INVALID_ARGUMENT for another name, a name
+ * not armed, or repeats out of range. */
+gdgs_status gdgs_set_kernel_timer_repeats(const char* kernel, int repeats);
 /* Start every armed timer at pair 0 again. */
 void gdgs_rewind_kernel_timers(void);
 /* Number of launches of `kernel` bracketed since arming or the last rewind

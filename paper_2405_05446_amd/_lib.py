@@ -107,6 +107,7 @@ _SIGS = {
     "gdgs_clear_graphs": (None, []),
     "gdgs_set_kernel_timer": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_int]),
+    "gdgs_set_kernel_timer_repeats": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int]),
     "gdgs_rewind_kernel_timers": (None, []),
     "gdgs_kernel_timer_count": (ctypes.c_int, [ctypes.c_char_p]),
     "gdgs_bin_sort_workspace_size": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,

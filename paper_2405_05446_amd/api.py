@@ -465,6 +465,13 @@ def set_kernel_timer(name: str | None, starts=None, stops=None):
     L.check(lib.gdgs_set_kernel_timer(name.encode(), A, B, n))
 
 
+def set_kernel_timer_repeats(name: str, repeats: int):
+    """Issue each timed launch of an armed multigrid post pass ("mg_post_fine",
+    "mg_post_coarse") `repeats` times between its events (see
+    gdgs_set_kernel_timer_repeats); results are unchanged."""
+    L.check(L.load().gdgs_set_kernel_timer_repeats(name.encode(), int(repeats)))
+
+
 def rewind_kernel_timers():
     """Start every armed kernel timer at its first event pair again."""
     L.load().gdgs_rewind_kernel_timers()

@@ -48,6 +48,14 @@ bool timer_events(const char* name, hipEvent_t* start, hipEvent_t* stop) {
     return false;
 }
 
+int timer_repeats(const char* name) {
+    const KernelTimer* ts = kernel_timers();
+    for (int k = 0; k < kMaxTimers; ++k)
+        if (ts[k].n > 0 && std::strncmp(ts[k].name, name, sizeof(ts[k].name)) == 0)
+            return ts[k].repeats;
+    return 1;
+}
+
 namespace {
 struct GraphCache {
     std::mutex mu;
@@ -338,6 +346,23 @@ gdgs_status gdgs_set_kernel_timer(const char* kernel, void** start_events, void*
     t.stops = reinterpret_cast<hipEvent_t*>(stop_events);
     t.n = n;
     return GDGS_OK;
+}
+
+gdgs_status gdgs_set_kernel_timer_repeats(const char* kernel, int repeats) {
+    clear_error();
+    REQUIRE(kernel != nullptr, "kernel name is null");
+    REQUIRE(repeats >= 1 && repeats <= 64, "repeats %d outside [1, 64]", repeats);
+    REQUIRE(std::strcmp(kernel, "mg_post_fine") == 0 || std::strcmp(kernel, "mg_post_coarse") == 0,
+            "repeats apply to the multigrid post passes only (\"mg_post_fine\", "
+            "\"mg_post_coarse\")");
+    KernelTimer* ts = kernel_timers();
+    for (int k = 0; k < kMaxTimers; ++k)
+        if (ts[k].n > 0 && std::strncmp(ts[k].name, kernel, sizeof(ts[k].name)) == 0) {
+            ts[k].repeats = repeats;
+            return GDGS_OK;
+        }
+    set_error("timer \"%s\" is not armed", kernel);
+    return GDGS_ERR_INVALID_ARGUMENT;
 }
 
 void gdgs_rewind_kernel_timers(void) { reset_timers(); }

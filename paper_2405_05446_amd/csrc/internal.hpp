@@ -238,11 +238,15 @@ struct KernelTimer {
     hipEvent_t* stops = nullptr;
     int n = 0;
     int next = 0;
+    int repeats = 1;  // launches between one pair (idempotent kernels only)
 };
 constexpr int kMaxTimers = 4;
 KernelTimer* kernel_timers();  // [kMaxTimers]
 // Event pair (start, stop) to bracket this launch of `name` with, or false.
 bool timer_events(const char* name, hipEvent_t* start, hipEvent_t* stop);
+// How many times a timed launch of `name` is issued between its events (1
+// unless set by gdgs_set_kernel_timer_repeats).
+int timer_repeats(const char* name);
 // Timed launches count from pair 0 again (called at every ABI entry).
 void reset_timers();
 

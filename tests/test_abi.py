@@ -65,3 +65,17 @@ def test_image_size_limits(lib):
     assert g(10, 64, 16 * 65535 + 1, 100, ctypes.byref(n)) == 1
     assert g(10, 16 * 65535, 64, 100, ctypes.byref(n)) == 0
     assert g(10, 3, 3, 100, ctypes.byref(n)) == 0
+
+
+def test_timer_repeats_validate_on_the_host(lib):
+    # repeats apply to an armed multigrid post pass only; nothing here touches
+    # the GPU (no timer is armed)
+    f = lib.gdgs_set_kernel_timer_repeats
+    f.argtypes = [ctypes.c_char_p, ctypes.c_int]
+    lib.gdgs_last_error.restype = ctypes.c_char_p
+    assert f(b"raster", 4) == 1
+    assert b"post passes only" in lib.gdgs_last_error()
+    assert f(b"mg_post_fine", 0) == 1 and f(b"mg_post_fine", 65) == 1
+    assert f(b"mg_post_fine", 4) == 1
+    assert b"not armed" in lib.gdgs_last_error()
+    assert f(None, 4) == 1

@@ -15,6 +15,13 @@ CASES = [
     ("ragged", dict(K=3000, W=100, H=72, z=(2, 6), ls=(-3, 0.6), pose=3)),
     ("wide", dict(K=20000, W=333, H=190, z=(2, 20), ls=(-4, 0.7), pose=7)),
 ]
+# the sort alone at the mid and full sizes: hundreds of 2048-key tiles in the
+# depth sort and thousands in the pair sort, so every pass's look-back walks
+# across many tiles
+SORT_CASES = CASES + [
+    ("mid", dict(K=200_000, W=800, H=800, z=(2, 6), ls=(-4, 0.5), pose=2)),
+    ("full", dict(K=1_000_000, W=1920, H=1080, z=(2, 20), ls=(-5, 0.7), pose=5)),
+]
 
 
 def _boundary_fluke(o, k):
@@ -51,7 +58,7 @@ def test_project_matches_oracle(name, cfg):
     np.testing.assert_allclose(g["mean2d_rel"][:, live], mrel_o, rtol=1e-6, atol=2e-6)
 
 
-@pytest.mark.parametrize("name,cfg", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("name,cfg", SORT_CASES, ids=[c[0] for c in SORT_CASES])
 def test_bin_sort_is_bit_exact(name, cfg):
     say(f"[bin_sort] {name} {cfg}")
     sc = wl.make_scene(cfg["K"], seed=1, z=cfg["z"], ls=cfg["ls"])
@@ -60,15 +67,19 @@ def test_bin_sort_is_bit_exact(name, cfg):
     W, H, K = cfg["W"], cfg["H"], cfg["K"]
     nx = (W + 15) // 16
     T = nx * ((H + 15) // 16)
-    # expected from the GPU's own rectangles and FP32 depths
-    tiles, splats = [], []
-    for k in np.nonzero(g["count"] > 0)[0]:
-        ty, tx = np.meshgrid(np.arange(g["ty0"][k], g["ty1"][k]),
-                             np.arange(g["tx0"][k], g["tx1"][k]), indexing="ij")
-        tiles.append((ty * nx + tx).ravel())
-        splats.append(np.full(tiles[-1].size, k))
-    tiles = np.concatenate(tiles)
-    splats = np.concatenate(splats)
+    # expected from the GPU's own rectangles and FP32 depths: every tile of
+    # each live splat's rectangle, row by row
+    live = np.nonzero(g["count"] > 0)[0]
+    w = g["tx1"][live] - g["tx0"][live]
+    h = g["ty1"][live] - g["ty0"][live]
+    cnt = w * h
+    splats = np.repeat(live, cnt)
+    first = np.repeat(np.cumsum(cnt) - cnt, cnt)
+    local = np.arange(splats.size) - first
+    wr = np.repeat(w, cnt)
+    tiles = ((np.repeat(g["ty0"][live], cnt) + local // wr) * nx
+             + np.repeat(g["tx0"][live], cnt) + local % wr)
+    say(f"[bin_sort] {name}: {K} splats, {splats.size} pairs, {T} tiles")
     assert g["num_pairs"] == tiles.size == int(g["count"].sum())
     dbits = g["depth"].view(np.uint32).astype(np.int64)
     o = np.lexsort((splats, dbits[splats], tiles))

@@ -1,0 +1,43 @@
+"""The kernel-timer hook: timed launches bracket the named pass, and repeated
+post passes between one event pair leave every result unchanged."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2405_05446_amd as G
+import workloads as wl
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("name", ["mg_post_fine", "mg_post_coarse"])
+def test_repeated_post_passes_change_nothing(name):
+    W, H, K = 640, 360, 40_000
+    sc = wl.make_scene(K, seed=3, z=(2, 20), ls=(-4.5, 0.7))
+    ds = G.DeviceScene.from_host(sc)
+    ring = torch.from_numpy(wl.reference_image(H, W, seed=1).astype(np.float32)).cuda()
+    cam = wl.make_camera(W, H, pose_index=4)
+    r = G.Renderer(ds, W, H, G.mg_params(levels=8, tol=1e-6))
+    want = r.render(cam, ring).clone()
+    cycles = r.last["total_cycles"]
+    n = 64
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+    stops = [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+    try:
+        G.api.set_kernel_timer(name, starts, stops)
+        G.api.set_kernel_timer_repeats(name, 5)
+        G.api.rewind_kernel_timers()
+        got = r.render(cam, ring)
+        torch.cuda.synchronize()
+        timed = G.api.kernel_timer_count(name)
+        ms = [starts[i].elapsed_time(stops[i]) for i in range(timed)]
+    finally:
+        G.api.set_kernel_timer(None)
+    say(f"[timer] {name}: {timed} timed launches x5, mean {np.mean(ms) * 1e3:.1f} us per pair, "
+        f"cycles {cycles} -> {r.last['total_cycles']}")
+    assert timed > 0 and all(t > 0 for t in ms)
+    assert r.last["total_cycles"] == cycles
+    assert torch.equal(got, want)
+    # the hook is off again: a later frame equals the first as well
+    assert torch.equal(r.render(cam, ring), want)
