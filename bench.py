@@ -124,6 +124,8 @@ def parse():
                     help="skip the four-frame rotation of the Poisson stage")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--post-repeats", type=int, default=POST_REPEATS,
+                    help="launches of a timed multigrid post pass between one event pair")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -746,12 +748,16 @@ def main():
 
     # untimed passes over the same poses: the finest post pass bracketed by
     # events (with the number of (pixel, splat) contributions of each frame),
-    # then the coarse-grid post passes alone.  Each timed launch is issued
-    # POST_REPEATS times between its two events (a post pass reads none of
-    # what it writes, so the repeats change no result), which spreads the
-    # few microseconds the event records add over the repeats
+    # then the coarse-grid post passes alone.  In these passes every
+    # multigrid launch covers all three channels on one stream (no other
+    # kernel runs beside the timed one; results are the same), and each timed
+    # launch is issued `reps` times between its two events (a post pass reads
+    # none of what it writes, so the repeats change no result), which spreads
+    # the few microseconds the event records add over the repeats
+    reps = max(1, args.post_repeats)
+    G.api.set_channel_streams(False)
     arm(["mg_post_fine"])
-    G.api.set_kernel_timer_repeats("mg_post_fine", POST_REPEATS)
+    G.api.set_kernel_timer_repeats("mg_post_fine", reps)
     contrib = []
     for i in range(args.steps):
         G.api.rewind_kernel_timers()
@@ -760,35 +766,35 @@ def main():
         contrib.append(G.api.gdgs_raster_count(r.proj, ds.opacity, ds.value, K, r.bins, W, H,
                                                r.ws_ras))
     arm(["mg_post_coarse"])
-    G.api.set_kernel_timer_repeats("mg_post_coarse", POST_REPEATS)
+    G.api.set_kernel_timer_repeats("mg_post_coarse", reps)
     for i in range(min(args.steps, 20)):
         G.api.rewind_kernel_timers()
         r.render(cams[i % len(cams)], ring)
         k_ms["mg_post_coarse"].append(read("mg_post_coarse"))
     G.api.set_kernel_timer(None)
-    # coarse post passes: per channel and V-cycle one launch per global coarse
-    # grid, from the coarsest of them up to grid 1
+    G.api.set_channel_streams(True)
+    # coarse post passes: per V-cycle one launch (all three channels) per
+    # global coarse grid, from the coarsest of them up to grid 1
     lev_n, lev_m = [H - 2], [W - 2]
     while len(lev_n) < 8:
         lev_n.append(lev_n[-1] // 2)
         lev_m.append(lev_m[-1] // 2)
     c_bytes, c_us, c_launch = 0.0, 0.0, []
     for f in k_ms["mg_post_coarse"]:
-        ng = max(1, round(len(f) / (3.0 * mean_cycles)))
+        ng = max(1, round(len(f) / mean_cycles))
         c_launch.append(len(f))
         for j, t in enumerate(f):
             lvl = ng - (j % ng)
-            c_bytes += MG_POST_BYTES_PER_POINT * lev_n[lvl] * lev_m[lvl]
-            c_us += t * 1e3 / POST_REPEATS
+            c_bytes += MG_POST_BYTES_PER_POINT * 3 * lev_n[lvl] * lev_m[lvl]
+            c_us += t * 1e3 / reps
     coarse_gbs = c_bytes / (c_us * 1e-6) / 1e9 if c_us > 0 else 0.0
     coarse_avg_us = c_us / max(1, sum(c_launch))
     npts = (H - 2) * (W - 2)
     raster_us = float(np.mean([x for f in k_ms["raster"] for x in f])) * 1e3
     raster_tflops = RASTER_FLOPS_PER_CONTRIB * float(np.mean(contrib)) / (raster_us * 1e-6) / 1e12
-    post_all = [x / POST_REPEATS for f in k_ms["mg_post_fine"] for x in f]
+    post_all = [x / reps for f in k_ms["mg_post_fine"] for x in f]
     post_us = float(np.mean(post_all)) * 1e3
-    # launches per frame: one per channel per V-cycle when the channels run on
-    # their own streams (each launch then covers one channel)
+    # timed launches per frame: one per V-cycle, each over the three channels
     post_launches = float(np.mean([len(f) for f in k_ms["mg_post_fine"]]))
     ch_per_launch = 3.0 * mean_cycles / post_launches
     post_bytes = MG_POST_BYTES_PER_POINT * ch_per_launch * npts
@@ -808,9 +814,10 @@ def main():
                          "frac": round(post_gbs / HBM_PEAK_GBS, 4), "traffic": t_post,
                          "avg_launch_us": round(post_us, 2),
                          "launches_per_step": round(post_launches, 2),
-                         "timed": f"separate pass over the same poses; each timed launch "
-                                  f"issued {POST_REPEATS} times between one event pair "
-                                  f"(results unchanged), duration = elapsed / {POST_REPEATS}",
+                         "timed": f"separate pass over the same poses with each launch over "
+                                  f"all three channels on one stream (nothing beside it); each "
+                                  f"timed launch issued {reps} times between one event pair "
+                                  f"(results unchanged), duration = elapsed / {reps}",
                          "work_per_launch": f"{MG_POST_BYTES_PER_POINT:.0f} B x "
                                             f"{ch_per_launch:.3g} channel(s) x {npts} points"},
     }
@@ -818,17 +825,17 @@ def main():
         kern["mg_post_fine"]["traffic_GBs"] = round(t_post / (post_us * 1e-6) / 1e9, 1)
     k_coarse = "k_mg_post<2, false, 32, 16, 256, false>"
     t_coarse = measured_traffic(k_coarse)
-    ng = max(1, round(float(np.mean(c_launch)) / (3.0 * mean_cycles)))
+    ng = max(1, round(float(np.mean(c_launch)) / mean_cycles))
     kern["mg_post_coarse"] = {
         "kernel": k_coarse, "bound": "hbm", "achieved": round(coarse_gbs, 1),
         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(coarse_gbs / HBM_PEAK_GBS, 4),
         "traffic": t_coarse, "avg_launch_us": round(coarse_avg_us, 2),
         "launches_per_step": round(float(np.mean(c_launch)), 2),
-        "timed": f"separate pass over 20 of the poses; each timed launch issued {POST_REPEATS} "
-                 f"times between one event pair (results unchanged), duration = elapsed / "
-                 f"{POST_REPEATS}",
+        "timed": f"separate pass over 20 of the poses with each launch over all three channels "
+                 f"on one stream; each timed launch issued {reps} times between one event pair "
+                 f"(results unchanged), duration = elapsed / {reps}",
         "work_per_launch": f"{MG_POST_BYTES_PER_POINT:.0f} B x the points of its grid "
-                           f"(one channel; grids 1-{ng}, {lev_n[1]}x{lev_m[1]} down)"}
+                           f"(three channels; grids 1-{ng}, {lev_n[1]}x{lev_m[1]} down)"}
     kern["raster"]["frac_of_packed_peak"] = round(raster_tflops / 157.3, 4)
     kern["raster"]["peaks_TFLOPs"] = {"unpacked_fp32_valu": VALU_PEAK_TFLOPS,
                                       "packed_fp32_published": 157.3}
@@ -867,12 +874,12 @@ def main():
         "roofline": kern[dominant],
         "roofline_note": f"the finest-grid multigrid post pass, the largest launch of the "
                          f"Poisson stage ({100.0 * mean_stage[3] / ms:.0f}% of the frame), "
-                         f"timed with HIP events on its channel's stream in a separate pass "
-                         f"over the same poses, where it launches outside the per-channel "
-                         f"graphs, each timed launch issued {POST_REPEATS} times between one "
-                         f"event pair (a post pass reads none of what it writes, so results "
-                         f"are unchanged); achieved = 13 B per interior point of one channel / "
-                         f"duration.  The coarse-grid post passes (kernels.mg_post_coarse) "
+                         f"timed with HIP events in a separate pass over the same poses in "
+                         f"which every multigrid launch covers the three channels on one stream "
+                         f"(no kernel beside the timed one), each timed launch issued {reps} "
+                         f"times between one event pair (a post pass reads none of what it "
+                         f"writes, so results are unchanged); achieved = 13 B per interior "
+                         f"point per channel x 3 channels / duration.  The coarse-grid post passes (kernels.mg_post_coarse) "
                          f"are timed the same way.  The compositing kernel (kernels.raster) "
                          f"is timed live in the timed frames; its frac is against the unpacked "
                          f"FP32 VALU peak (packed FP32 is not emitted by these builds), "

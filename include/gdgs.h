@@ -191,6 +191,13 @@ const char* gdgs_version(void);
  * launch directly.  gdgs_clear_graphs() destroys the cached graphs. */
 void gdgs_set_graphs(int enable);
 void gdgs_clear_graphs(void);
+/* Host-only switch (default on): the Poisson calls run each colour channel's
+ * V-cycles on a helper stream of its own, bound to the caller's stream, so
+ * that the three channels overlap.  Off, every multigrid launch covers all
+ * three channels on the caller's stream (one kernel at a time: the timing
+ * of a single launch is then that of the kernel alone).  Results are the
+ * same bit for bit either way. */
+void gdgs_set_channel_streams(int enable);
 /* Host-only profiling hook (up to 4 names at once).  After arming, the i-th
  * launch of the named kernel (i < n, counted over all later calls until the
  * next gdgs_rewind_kernel_timers or re-arming) is bracketed by

@@ -105,6 +105,7 @@ _SIGS = {
     "gdgs_version": (ctypes.c_char_p, []),
     "gdgs_set_graphs": (None, [ctypes.c_int]),
     "gdgs_clear_graphs": (None, []),
+    "gdgs_set_channel_streams": (None, [ctypes.c_int]),
     "gdgs_set_kernel_timer": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_int]),
     "gdgs_set_kernel_timer_repeats": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int]),

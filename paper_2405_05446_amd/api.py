@@ -465,6 +465,13 @@ def set_kernel_timer(name: str | None, starts=None, stops=None):
     L.check(lib.gdgs_set_kernel_timer(name.encode(), A, B, n))
 
 
+def set_channel_streams(enable: bool):
+    """Run each colour channel's V-cycles on a helper stream of its own (the
+    default) or every multigrid launch over all three channels on the
+    caller's stream (see gdgs_set_channel_streams); results are the same."""
+    L.load().gdgs_set_channel_streams(1 if enable else 0)
+
+
 def set_kernel_timer_repeats(name: str, repeats: int):
     """Issue each timed launch of an armed multigrid post pass ("mg_post_fine",
     "mg_post_coarse") `repeats` times between its events (see

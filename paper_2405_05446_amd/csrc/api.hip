@@ -105,6 +105,11 @@ int& graphs_flag() {
     return v;
 }
 
+int& channel_streams_flag() {
+    static int v = 1;
+    return v;
+}
+
 hipStream_t capture_stream(int dev) {
     thread_local std::map<int, hipStream_t> streams;
     auto it = streams.find(dev);
@@ -316,6 +321,8 @@ const char* gdgs_last_error(void) { return g_err; }
 const char* gdgs_version(void) { return "gdgs 0.1 gfx950"; }
 
 void gdgs_set_graphs(int enable) { graphs_flag() = enable ? 1 : 0; }
+
+void gdgs_set_channel_streams(int enable) { channel_streams_flag() = enable ? 1 : 0; }
 
 void gdgs_clear_graphs(void) { graph_cache_impl().clear(); }
 

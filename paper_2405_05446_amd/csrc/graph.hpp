@@ -33,6 +33,9 @@ class KeyBuilder {
 hipGraphExec_t graph_find(const std::string& key);
 void graph_put(const std::string& key, hipGraphExec_t exec);
 int& graphs_flag();
+// gdgs_set_channel_streams: 0 runs every Poisson launch over all three
+// channels on the caller's stream
+int& channel_streams_flag();
 hipStream_t capture_stream(int dev);
 bool timer_active(const char* name);
 

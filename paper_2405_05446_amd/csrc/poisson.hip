@@ -2267,7 +2267,7 @@ gdgs_status launch_poisson(const float* grad, const float* rho, const float* bou
         // a timed coarse post pass launches directly between its events
         const bool coarse_timed = timer_active("mg_post_coarse");
         ChannelStreams cs;
-        if (!channel_parallel || !channel_streams(st, &cs)) {
+        if (!channel_parallel || !channel_streams_flag() || !channel_streams(st, &cs)) {
             // all channels in each launch, on the caller's stream
             if (!timed) {
                 auto all = [&](hipStream_t s) -> gdgs_status {

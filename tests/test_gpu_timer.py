@@ -41,3 +41,24 @@ def test_repeated_post_passes_change_nothing(name):
     assert torch.equal(got, want)
     # the hook is off again: a later frame equals the first as well
     assert torch.equal(r.render(cam, ring), want)
+
+
+def test_channels_on_one_stream_give_the_same_image():
+    # gdgs_set_channel_streams(0): every multigrid launch over the three
+    # channels on the caller's stream, as the bench's timing passes run
+    W, H, K = 640, 360, 40_000
+    sc = wl.make_scene(K, seed=5, z=(2, 20), ls=(-4.5, 0.7))
+    ds = G.DeviceScene.from_host(sc)
+    ring = torch.from_numpy(wl.reference_image(H, W, seed=1).astype(np.float32)).cuda()
+    cam = wl.make_camera(W, H, pose_index=6)
+    r = G.Renderer(ds, W, H, G.mg_params(levels=8, tol=1e-6))
+    want = r.render(cam, ring).clone()
+    try:
+        G.api.set_channel_streams(False)
+        got = r.render(cam, ring).clone()
+        st = r.last
+    finally:
+        G.api.set_channel_streams(True)
+    say(f"[timer] channels on one stream: cycles {st['total_cycles']}")
+    assert torch.equal(got, want)
+    assert torch.equal(r.render(cam, ring), want)
