@@ -43,15 +43,20 @@ MG_POST_BYTES_PER_POINT = 13.0
 RASTER_FLOPS_PER_CONTRIB = 26.0
 # launches of a timed multigrid post pass between one event pair
 POST_REPEATS = 8
+# launch geometry, to find a launch's row in the counter summary: the
+# compositing kernel runs 256 threads per 16x16 tile; a finest-grid strip
+# block (256 threads) outputs 116 columns x 36 rows of the grid with its ring
+FINE_STRIP_OUT = (116, 36)
 
 
 PROFILE = os.path.join(ROOT, "profiles", "hbm_counters_render_1080p_1M.md")
 
 
-def measured_traffic(kernel: str):
-    """Calibrated HBM bytes per launch of `kernel` from the committed rocprofv3
-    counter summary, or None when there is none or the kernel's source file
-    has changed since the counters were taken (its hash no longer matches)."""
+def measured_traffic(kernel: str, items: int):
+    """Calibrated HBM bytes per launch of `kernel` over `items` work-items from
+    the committed rocprofv3 counter summary, or None when there is none or the
+    kernel's source file has changed since the counters were taken (its hash
+    no longer matches)."""
     import hashlib
     try:
         lines = open(PROFILE).read().splitlines()
@@ -59,13 +64,13 @@ def measured_traffic(kernel: str):
         return None
     for ln in lines:
         cells = [c.strip() for c in ln.strip().strip("|").split("|")]
-        if len(cells) == 7 and cells[0] == f"`{kernel}`":
-            src = os.path.join(ROOT, "paper_2405_05446_amd", "csrc", cells[1])
+        if len(cells) == 8 and cells[0] == f"`{kernel}`" and cells[1] == str(items):
+            src = os.path.join(ROOT, "paper_2405_05446_amd", "csrc", cells[2])
             try:
                 h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
             except OSError:
                 return None
-            return int(cells[6]) if h == cells[2] else None
+            return int(cells[7]) if h == cells[3] else None
     return None
 
 
@@ -800,7 +805,9 @@ def main():
     post_bytes = MG_POST_BYTES_PER_POINT * ch_per_launch * npts
     post_gbs = post_bytes / (post_us * 1e-6) / 1e9
     k_raster, k_post = "k_raster_fwd<false, 6, false>", "k_fine_post<2, false>"
-    t_raster, t_post = measured_traffic(k_raster), measured_traffic(k_post)
+    raster_items = -(-W // 16) * -(-H // 16) * 256
+    post_items = -(-W // FINE_STRIP_OUT[0]) * -(-H // FINE_STRIP_OUT[1]) * 256 * round(ch_per_launch)
+    t_raster, t_post = measured_traffic(k_raster, raster_items), measured_traffic(k_post, post_items)
     kern = {
         "raster": {"kernel": k_raster, "bound": "alu", "achieved": round(raster_tflops, 3),
                    "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -824,7 +831,7 @@ def main():
     if t_post is not None:
         kern["mg_post_fine"]["traffic_GBs"] = round(t_post / (post_us * 1e-6) / 1e9, 1)
     k_coarse = "k_mg_post<2, false, 32, 16, 256, false>"
-    t_coarse = measured_traffic(k_coarse)
+    t_coarse = None   # one row per coarse grid: no single launch size
     ng = max(1, round(float(np.mean(c_launch)) / mean_cycles))
     kern["mg_post_coarse"] = {
         "kernel": k_coarse, "bound": "hbm", "achieved": round(coarse_gbs, 1),
