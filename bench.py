@@ -114,10 +114,8 @@ def parse():
     ap.add_argument("--no-trajectory", action="store_true",
                     help="skip the cold/warm-start camera-path measurement")
     ap.add_argument("--no-fmg", action="store_true", help="skip the full-multigrid leg")
-    ap.add_argument("--no-overlap", action="store_true", help=argparse.SUPPRESS)
-    ap.add_argument("--overlap", action="store_true",
-                    help="add the two-frames-in-flight leg (two frame streams, each with its "
-                         "own channel streams: more streams than the 4 hardware queues)")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="skip the two-frames-in-flight leg")
     ap.add_argument("--large", action="store_true",
                     help="add the 3840x2160, 4M-splat leg (not run by default)")
     ap.add_argument("--no-neumann", action="store_true",
@@ -453,23 +451,32 @@ def _sequence_leg(G, torch, r, cams, ring, frames: int):
 
 
 def overlap_leg(torch, r, cams, ring, W, H, frames: int):
-    """The headline workload with two frames in flight: render_sequence with
-    overlap (the two buffer sets on streams of their own, so one frame's
-    binning and compositing run beside the other's multigrid solve).  Same
-    results per frame as the headline loop; wall clock over the frames."""
+    """The headline frames with two in flight (render_sequence(overlap=True)):
+    each frame's projection, binning and compositing run on the caller's
+    stream beside the previous frame's solve on the renderer's solve stream
+    (four HIP streams with the solve's two channel streams).  Wall clock over
+    the frames; the last frame is compared with the plain path bit for bit."""
     seq = [cams[i % len(cams)] for i in range(frames)]
     r.render_sequence(seq[:4], ring, overlap=True)
     torch.cuda.synchronize()
-    cyc = []
+    cyc, last = [], {}
+
+    def on_frame(i, u, st):
+        cyc.append((st["total_cycles"], st["converged"]))
+        if i == frames - 1:
+            last["u"] = u.clone()
+
     t0 = time.perf_counter()
-    r.render_sequence(seq, ring, overlap=True,
-                      on_frame=lambda i, u, st: cyc.append((st["total_cycles"], st["converged"])))
+    r.render_sequence(seq, ring, overlap=True, on_frame=on_frame)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / frames
-    return {"workload": f"headline workload, {W}x{H}, two frames in flight (overlap)",
+    same = bool(torch.equal(last["u"], r.render(seq[-1], ring)))
+    return {"workload": f"headline frames, {W}x{H}, two in flight (front halves on the caller's "
+                        f"stream, solves on one solve stream; 4 HIP streams)",
             "Mpix_s": round(H * W / (ms * 1e-3) / 1e6, 2), "ms_per_frame": round(ms, 4),
             "frames": frames, "mg_cycles_mean": float(np.mean([c for c, _ in cyc])),
-            "not_converged": int(sum(1 for _, ok in cyc if not ok))}
+            "not_converged": int(sum(1 for _, ok in cyc if not ok)),
+            "last_frame_equals_plain_path": same}
 
 
 def fmg_leg(G, wl, torch, ds, cams, ring, W, H, frames: int, levels: int):
@@ -926,7 +933,7 @@ def main():
     if not args.no_hbm_resident:
         out["poisson_stage"]["hbm_resident"] = hbm_resident_leg(G, torch, r, cams, ring, W, H,
                                                                 mg, mean_cycles)
-    if args.overlap and not args.no_overlap:
+    if not args.no_overlap:
         out["two_in_flight"] = overlap_leg(torch, r, cams, ring, W, H, args.steps)
     if not args.no_serve:
         out["batched_sequence"] = batched_sequence_leg(G, torch, ds, cams, ring, mg, W, H,

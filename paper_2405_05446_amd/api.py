@@ -608,12 +608,20 @@ class Renderer:
     def _enqueue(self, cam, boundary, events, stream):
         """Enqueue one frame (no waiting): the four steps, then an asynchronous
         copy of its statistics and pair count to pinned host memory."""
-        K, W, H = self.scene.K, self.W, self.H
         s = stream if stream is not None else torch.cuda.current_stream(self.dev)
+        self._enqueue_front(cam, events, s)
+        self._enqueue_solve(boundary, events, s)
+
+    def _host_buffers(self):
         if not hasattr(self, "_h_stats"):
             self._h_stats = torch.empty(STATS_BYTES, dtype=torch.uint8, pin_memory=True)
             self._h_pairs = torch.empty(1, dtype=torch.int64, pin_memory=True)
             self._done = torch.cuda.Event()
+
+    def _enqueue_front(self, cam, events, s):
+        """Projection, binning and compositing of one frame on stream s."""
+        K, W, H = self.scene.K, self.W, self.H
+        self._host_buffers()
         rec = (lambda i: events[i].record(s)) if events else (lambda i: None)
         rec(0)
         gdgs_project(self.scene, cam, self.proj, s)
@@ -632,6 +640,12 @@ class Renderer:
             gdgs_raster_grad(self.proj, self.scene.opacity, self.scene.value, K, self.bins, W, H,
                              self.grad, self.ws_ras, s)
         rec(3)
+
+    def _enqueue_solve(self, boundary, events, s):
+        """The Poisson solve of the composited frame on stream s, then the
+        copies of its statistics and pair count to pinned host memory."""
+        self._host_buffers()
+        rec = (lambda i: events[i].record(s)) if events else (lambda i: None)
         flags = 0
         if self.warm_start and self._prev_u is not None:
             if self._prev_u is not self.u:
@@ -656,12 +670,14 @@ class Renderer:
                   rel_res=list(sr.rel_res), b_norm=list(sr.b_norm), delta=list(sr.delta))
         pairs = int(self._h_pairs[0])
         if pairs > self.capacity:
+            self._extra = True   # the frame is rendered again after its first solve
             self._set_capacity(int(pairs * 1.25) + 1024)
             self.budget = self.max_cycles
             return self.render(cam, boundary, events, stream)
         total = max(st["cycles"])
         s = stream if stream is not None else torch.cuda.current_stream(self.dev)
         while not st["converged"] and total < self.max_cycles:
+            self._extra = True   # resumed cycles follow the frame's first solve
             step = min(2, self.max_cycles - total)
             self._solve(boundary, self._mg(step, RESUME), s)
             # the resumed cycles run on s, which the current stream need not
@@ -700,50 +716,93 @@ class Renderer:
         so results meet the same tolerance but may differ from render()'s in
         the last bits.
 
-        overlap (without warm_start): the two buffer sets get a stream each,
-        so two frames are in flight on the device at once (one frame's
-        binning and compositing beside the other's multigrid solve); results
-        are unchanged.  Each frame is enqueued behind the work on the caller's
-        stream so far (what on_frame enqueued there for the frame before it on
-        the same buffers), and the caller's stream waits for both at the end."""
+        overlap (without warm_start): two frames in flight.  Each frame's
+        projection, binning and compositing run on the caller's stream and
+        its solve on one solve stream of this renderer (plus the two channel
+        streams the library binds to it: four streams in all, the hardware
+        queues a process gets), so one frame's front half runs beside the
+        previous frame's solve; results are unchanged.  A buffer set's next
+        front half waits for its previous solve (resumed cycles included),
+        and work that on_frame(i) enqueues on the caller's stream follows
+        frame i's solve."""
         if not hasattr(self, "_twin"):
             self._twin = Renderer(self.scene, self.W, self.H, self.mg, self.capacity,
                                   self.adaptive, self.warm_start, self.threshold, self.neumann)
         rs = [self, self._twin]
         caller = stream if stream is not None else torch.cuda.current_stream(self.dev)
-        overlap = overlap and not self.warm_start
-        streams = [stream, stream]
-        if overlap:
-            if not hasattr(self, "_seq_streams"):
-                self._seq_streams = [torch.cuda.Stream(device=self.dev) for _ in range(2)]
-            streams = self._seq_streams
+        if overlap and not self.warm_start:
+            self._sequence_overlap(rs, cams, boundary, events, on_frame, caller)
+            return
         prev = None
         for i, cam in enumerate(cams):
-            r, rs_i = rs[i % 2], streams[i % 2]
+            r = rs[i % 2]
             if prev is not None:
                 r.budget = prev[0].budget
                 if self.warm_start:
                     r._prev_u = prev[0].u
-            if overlap:
-                rs_i.wait_stream(caller)
-            r._enqueue(cam, boundary, events[i] if events else None, rs_i)
+            r._enqueue(cam, boundary, events[i] if events else None, stream)
             if prev is not None:
-                pr, pcam, pi, ps = prev
-                u = pr._finish(pcam, boundary, events[pi] if events else None, ps)
+                pr, pcam, pi = prev
+                u = pr._finish(pcam, boundary, events[pi] if events else None, stream)
                 r.budget = max(r.budget, pr.budget)
-                if overlap:
-                    caller.wait_stream(ps)   # work on_frame enqueues follows the frame
                 if on_frame is not None:
                     on_frame(pi, u, pr.last)
-            prev = (r, cam, i, rs_i)
+            prev = (r, cam, i)
         if prev is not None:
-            pr, pcam, pi, ps = prev
-            u = pr._finish(pcam, boundary, events[pi] if events else None, ps)
+            pr, pcam, pi = prev
+            u = pr._finish(pcam, boundary, events[pi] if events else None, stream)
             self.budget = self._twin.budget = pr.budget
-            if overlap:
-                caller.wait_stream(ps)
             if on_frame is not None:
                 on_frame(pi, u, pr.last)
-        if overlap:
-            for q in streams:
-                caller.wait_stream(q)
+
+    def _sequence_overlap(self, rs, cams, boundary, events, on_frame, C):
+        if not hasattr(self, "_solve_stream"):
+            self._solve_stream = torch.cuda.Stream(device=self.dev)
+        P = self._solve_stream
+        for r in rs:
+            r._host_buffers()
+            if not hasattr(r, "_fronted"):
+                r._fronted = torch.cuda.Event()
+                r._solved = torch.cuda.Event()
+            r._in_flight = False
+            r._settled = None
+        P.wait_stream(C)   # the solves follow the caller's earlier work
+
+        def settle(pr, pcam, pi):
+            # The frame's own done event marks the end of its solve; when the
+            # settling adds work (resumed cycles or a re-render, queued on P
+            # behind the next frame's solve), a new event after that work.
+            pr._extra = False
+            u = pr._finish(pcam, boundary, events[pi] if events else None, P)
+            if pr._extra:
+                pr._solved.record(P)
+                pr._settled = pr._solved
+            else:
+                pr._settled = pr._done
+            C.wait_event(pr._settled)   # on_frame's work follows the frame
+            if on_frame is not None:
+                on_frame(pi, u, pr.last)
+
+        prev = None
+        for i, cam in enumerate(cams):
+            r = rs[i % 2]
+            ev = events[i] if events else None
+            if prev is not None:
+                r.budget = prev[0].budget
+            if r._in_flight:
+                C.wait_event(r._settled)  # the set's previous frame is done with its buffers
+            r._enqueue_front(cam, ev, C)
+            r._fronted.record(C)
+            P.wait_event(r._fronted)
+            r._enqueue_solve(boundary, ev, P)
+            r._in_flight = True
+            if prev is not None:
+                pr, pcam, pi = prev
+                settle(pr, pcam, pi)
+                r.budget = max(r.budget, pr.budget)
+            prev = (r, cam, i)
+        if prev is not None:
+            pr, pcam, pi = prev
+            settle(pr, pcam, pi)
+            self.budget = self._twin.budget = pr.budget
+        C.wait_stream(P)
