@@ -264,3 +264,37 @@ def test_largest_workload_4k_4m_splats():
     e2 = np.abs(np_(u) - exact).max()
     say(f"  composite max-abs {e1:.3e}, poisson max-abs {e2:.3e}")
     assert e1 <= TOL and e2 <= TOL
+
+
+@pytest.mark.parametrize("form", ["neumann", "laplacian_threshold"])
+def test_two_frames_in_flight_other_forms_equal_render(form):
+    """Two frames in flight (front halves on the caller's stream, solves on
+    the renderer's solve stream) for the Neumann problem and for thresholded
+    Laplacian splats: every frame equals render() bit for bit."""
+    H, W = 90, 140
+    base = wl.make_scene(6000, seed=21, ls=(-3, 0.6))
+    if form == "neumann":
+        sc = base
+        mk = lambda: G.Renderer(G.DeviceScene.from_host(sc), W, H,
+                                G.mg_params(tol=1e-6, max_cycles=40), neumann=True)
+        ring = None
+    else:
+        sc = wl.laplacian_scene(base, seed=21)
+        mk = lambda: G.Renderer(G.DeviceScene.from_host(sc), W, H,
+                                G.mg_params(tol=1e-6, max_cycles=40), threshold=2e-3)
+        ring = torch.from_numpy(wl.reference_image(H, W, seed=1).astype(np.float32)).cuda()
+    cams = [wl.make_camera(W, H, pose_index=i) for i in range(5)]
+    ref = mk()
+    want = []
+    for c in cams:
+        want.append(ref.render(c, ring).clone())
+    seq = mk()
+    got = {}
+    seq.render_sequence(cams, ring, overlap=True,
+                        on_frame=lambda i, u, st: got.__setitem__(i, (u.clone(), st)))
+    torch.cuda.synchronize()
+    say(f"[render] two in flight, {form}: cycles "
+        f"{[got[i][1]['total_cycles'] for i in sorted(got)]}")
+    assert sorted(got) == list(range(len(cams)))
+    for i, (u, st) in got.items():
+        assert st["converged"] and torch.equal(u, want[i]), i
