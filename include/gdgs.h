@@ -37,6 +37,18 @@
  * (thread-local).  Conditions found on the device (pair-capacity overflow,
  * non-convergence) are reported in a device-side gdgs_stats the caller reads
  * after synchronising the stream; they are not call failures.
+ *
+ * Environment (read once per process):
+ *   - GDGS_GRAPHS=0: launch directly instead of replaying cached HIP graphs
+ *     (gdgs_set_graphs);
+ *   - GDGS_CHANNEL_STREAMS=0: run every multigrid launch over the three
+ *     channels on the caller's stream (gdgs_set_channel_streams);
+ *   - GDGS_LOG=0..3: host log lines on stderr, prefixed "gdgs[<level>] ":
+ *     0 none (default), 1 every error the library records (the text of
+ *     gdgs_last_error), 2 also graph captures and server events, 3 also every
+ *     entry-point call and multigrid plan.
+ * Every entry point also opens a roctx range named after it (visible with
+ * rocprofv3 --marker-trace); a range spans the host's enqueue of the call.
  */
 #ifndef GDGS_H
 #define GDGS_H

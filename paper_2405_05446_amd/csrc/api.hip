@@ -25,6 +25,27 @@ void set_error(const char* fmt, ...) {
     va_start(ap, fmt);
     vsnprintf(g_err, sizeof(g_err), fmt, ap);
     va_end(ap);
+    GDGS_LOG(1, "%s", g_err);
+}
+
+int log_level() {
+    static const int v = [] {
+        const char* e = std::getenv("GDGS_LOG");
+        if (!e || !*e) return 0;
+        const int l = std::atoi(e);
+        return l < 0 ? 0 : (l > 3 ? 3 : l);
+    }();
+    return v;
+}
+
+void log_msg(int level, const char* fmt, ...) {
+    static const char* const names[4] = {"", "error", "info", "debug"};
+    char line[640];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(line, sizeof(line), fmt, ap);
+    va_end(ap);
+    std::fprintf(stderr, "gdgs[%s] %s\n", names[level < 0 ? 0 : (level > 3 ? 3 : level)], line);
 }
 
 void clear_error() { g_err[0] = '\0'; }
@@ -328,6 +349,7 @@ void gdgs_clear_graphs(void) { graph_cache_impl().clear(); }
 
 gdgs_status gdgs_set_kernel_timer(const char* kernel, void** start_events, void** stop_events,
                                   int n) {
+    GDGS_TRACE("gdgs_set_kernel_timer");
     clear_error();
     KernelTimer* ts = kernel_timers();
     if (kernel == nullptr) {
@@ -356,6 +378,7 @@ gdgs_status gdgs_set_kernel_timer(const char* kernel, void** start_events, void*
 }
 
 gdgs_status gdgs_set_kernel_timer_repeats(const char* kernel, int repeats) {
+    GDGS_TRACE("gdgs_set_kernel_timer_repeats");
     clear_error();
     REQUIRE(kernel != nullptr, "kernel name is null");
     REQUIRE(repeats >= 1 && repeats <= 64, "repeats %d outside [1, 64]", repeats);
@@ -385,6 +408,7 @@ int gdgs_kernel_timer_count(const char* kernel) {
 
 gdgs_status gdgs_bin_sort_workspace_size(int64_t K, int32_t W, int32_t H, int64_t pair_capacity,
                                          size_t* bytes) {
+    GDGS_TRACE("gdgs_bin_sort_workspace_size");
     clear_error();
     REQUIRE(bytes != nullptr, "bytes is null");
     REQUIRE(K >= 0 && K < (int64_t)0xFFFFFFFFll, "K = %lld out of range", (long long)K);
@@ -396,6 +420,7 @@ gdgs_status gdgs_bin_sort_workspace_size(int64_t K, int32_t W, int32_t H, int64_
 }
 
 gdgs_status gdgs_raster_workspace_size(int64_t K, size_t* bytes) {
+    GDGS_TRACE("gdgs_raster_workspace_size");
     clear_error();
     REQUIRE(bytes != nullptr, "bytes is null");
     REQUIRE(K >= 0 && K < (int64_t)0xFFFFFFFFll, "K = %lld out of range", (long long)K);
@@ -405,6 +430,7 @@ gdgs_status gdgs_raster_workspace_size(int64_t K, size_t* bytes) {
 
 gdgs_status gdgs_poisson_workspace_size(int32_t W, int32_t H, const gdgs_mg_params* mg,
                                         size_t* bytes) {
+    GDGS_TRACE("gdgs_poisson_workspace_size");
     clear_error();
     REQUIRE(bytes != nullptr, "bytes is null");
     TRY(check_size(W, H));
@@ -416,6 +442,7 @@ gdgs_status gdgs_poisson_workspace_size(int32_t W, int32_t H, const gdgs_mg_para
 
 gdgs_status gdgs_workspace_size(int64_t K, int32_t W, int32_t H, int64_t pair_capacity,
                                 const gdgs_mg_params* mg, size_t* bytes) {
+    GDGS_TRACE("gdgs_workspace_size");
     clear_error();
     REQUIRE(bytes != nullptr, "bytes is null");
     REQUIRE(K >= 0 && K < (int64_t)0xFFFFFFFFll, "K = %lld out of range", (long long)K);
@@ -429,6 +456,7 @@ gdgs_status gdgs_workspace_size(int64_t K, int32_t W, int32_t H, int64_t pair_ca
 }
 
 gdgs_status gdgs_raster_backward_workspace_size(int64_t K, int64_t pair_capacity, size_t* bytes) {
+    GDGS_TRACE("gdgs_raster_backward_workspace_size");
     clear_error();
     REQUIRE(bytes != nullptr, "bytes is null");
     REQUIRE(K >= 0 && K < (int64_t)0xFFFFFFFFll, "K = %lld out of range", (long long)K);
@@ -440,6 +468,7 @@ gdgs_status gdgs_raster_backward_workspace_size(int64_t K, int64_t pair_capacity
 
 gdgs_status gdgs_project(const gdgs_scene* scene, const gdgs_camera* cam, const gdgs_proj* out,
                          void* stream) {
+    GDGS_TRACE("gdgs_project");
     clear_error();
     REQUIRE(scene != nullptr && cam != nullptr, "scene or camera is null");
     REQUIRE(scene->K >= 0 && scene->K < (int64_t)0xFFFFFFFFll, "K = %lld out of range",
@@ -456,6 +485,7 @@ gdgs_status gdgs_project(const gdgs_scene* scene, const gdgs_camera* cam, const 
 }
 
 gdgs_status gdgs_threshold(float* x, int64_t n, float t, uint64_t* nonzero_dev, void* stream) {
+    GDGS_TRACE("gdgs_threshold");
     clear_error();
     REQUIRE(n >= 0, "n must be >= 0");
     REQUIRE(t >= 0.f, "threshold must be >= 0");
@@ -468,6 +498,7 @@ gdgs_status gdgs_threshold(float* x, int64_t n, float t, uint64_t* nonzero_dev, 
 }
 
 gdgs_status gdgs_image_loss_workspace_size(int32_t W, int32_t H, size_t* bytes) {
+    GDGS_TRACE("gdgs_image_loss_workspace_size");
     clear_error();
     REQUIRE(bytes != nullptr, "bytes is null");
     TRY(check_size(W, H));
@@ -478,6 +509,7 @@ gdgs_status gdgs_image_loss_workspace_size(int32_t W, int32_t H, size_t* bytes) 
 gdgs_status gdgs_image_loss(const float* c, const float* im, int32_t W, int32_t H, double lam,
                             double beta, double* loss_dev, float* dc, void* ws, size_t ws_bytes,
                             void* stream) {
+    GDGS_TRACE("gdgs_image_loss");
     clear_error();
     TRY(check_size(W, H));
     REQUIRE_PTR(c);
@@ -493,6 +525,7 @@ gdgs_status gdgs_image_loss(const float* c, const float* im, int32_t W, int32_t 
 gdgs_status gdgs_adam_step(float* param, const float* grad, float* m, float* v, int64_t n,
                            int32_t t, float lr, float beta1, float beta2, float eps, float lo,
                            float hi, void* stream) {
+    GDGS_TRACE("gdgs_adam_step");
     clear_error();
     REQUIRE(n >= 0, "n must be >= 0");
     REQUIRE(t >= 1, "step t must be >= 1");
@@ -511,6 +544,7 @@ gdgs_status gdgs_adam_step(float* param, const float* grad, float* m, float* v, 
 gdgs_status gdgs_project_backward(const gdgs_scene* scene, const gdgs_camera* cam,
                                   const float* dmean2d, const float* dconic, float* dmean,
                                   float* dlog_scale, float* dquat, void* stream) {
+    GDGS_TRACE("gdgs_project_backward");
     clear_error();
     REQUIRE(scene != nullptr && cam != nullptr, "scene or camera is null");
     const int64_t K = scene->K;
@@ -531,6 +565,7 @@ gdgs_status gdgs_project_backward(const gdgs_scene* scene, const gdgs_camera* ca
 
 gdgs_status gdgs_project_2d(const float* mean2d, const float* conic, const float* depth,
                             int64_t K, int32_t W, int32_t H, const gdgs_proj* out, void* stream) {
+    GDGS_TRACE("gdgs_project_2d");
     clear_error();
     REQUIRE(K >= 0 && K < (int64_t)0xFFFFFFFFll, "K = %lld out of range", (long long)K);
     TRY(check_size(W, H));
@@ -544,6 +579,7 @@ gdgs_status gdgs_project_2d(const float* mean2d, const float* conic, const float
 
 gdgs_status gdgs_bin_sort(const gdgs_proj* proj, int64_t K, int32_t W, int32_t H,
                           const gdgs_bins* bins, void* ws, size_t ws_bytes, void* stream) {
+    GDGS_TRACE("gdgs_bin_sort");
     clear_error();
     REQUIRE(K >= 0 && K < (int64_t)0xFFFFFFFFll, "K = %lld out of range", (long long)K);
     TRY(check_size(W, H));
@@ -600,12 +636,14 @@ static gdgs_status raster_common(const gdgs_proj* proj, const float* opacity,
 gdgs_status gdgs_raster_grad(const gdgs_proj* proj, const float* opacity, const float* value,
                              int64_t K, const gdgs_bins* bins, int32_t W, int32_t H, float* grad,
                              void* ws, size_t ws_bytes, void* stream) {
+    GDGS_TRACE("gdgs_raster_grad");
     return raster_common(proj, opacity, value, K, bins, W, H, grad, ws, ws_bytes, stream, 6);
 }
 
 gdgs_status gdgs_raster_laplacian(const gdgs_proj* proj, const float* opacity, const float* lap,
                                   int64_t K, const gdgs_bins* bins, int32_t W, int32_t H,
                                   float* rho, void* ws, size_t ws_bytes, void* stream) {
+    GDGS_TRACE("gdgs_raster_laplacian");
     return raster_common(proj, opacity, lap, K, bins, W, H, rho, ws, ws_bytes, stream, 3);
 }
 
@@ -614,6 +652,7 @@ gdgs_status gdgs_raster_laplacian_threshold(const gdgs_proj* proj, const float* 
                                             int32_t W, int32_t H, float threshold, float* rho,
                                             uint64_t* nonzero, void* ws, size_t ws_bytes,
                                             void* stream) {
+    GDGS_TRACE("gdgs_raster_laplacian_threshold");
     if (!(threshold >= 0.f)) {
         clear_error();
         set_error("threshold %g must be >= 0", (double)threshold);
@@ -626,6 +665,7 @@ gdgs_status gdgs_raster_laplacian_threshold(const gdgs_proj* proj, const float* 
 gdgs_status gdgs_raster_count(const gdgs_proj* proj, const float* opacity, const float* value,
                               int64_t K, const gdgs_bins* bins, int32_t W, int32_t H,
                               uint64_t* counts, void* ws, size_t ws_bytes, void* stream) {
+    GDGS_TRACE("gdgs_raster_count");
     clear_error();
     REQUIRE(K >= 0 && K < (int64_t)0xFFFFFFFFll, "K = %lld out of range", (long long)K);
     TRY(check_size(W, H));
@@ -668,6 +708,7 @@ static gdgs_status poisson_common(const float* grad, const float* rho, const flo
 gdgs_status gdgs_poisson_solve(const float* grad, const float* boundary, int32_t W, int32_t H,
                                const gdgs_mg_params* mg, float* u, gdgs_stats* stats_dev,
                                void* ws, size_t ws_bytes, void* stream) {
+    GDGS_TRACE("gdgs_poisson_solve");
     clear_error();
     REQUIRE_PTR(grad);
     return poisson_common(grad, nullptr, boundary, W, H, mg, u, stats_dev, ws, ws_bytes, stream);
@@ -676,6 +717,7 @@ gdgs_status gdgs_poisson_solve(const float* grad, const float* boundary, int32_t
 gdgs_status gdgs_poisson_solve_rhs(const float* rho, const float* boundary, int32_t W, int32_t H,
                                    const gdgs_mg_params* mg, float* u, gdgs_stats* stats_dev,
                                    void* ws, size_t ws_bytes, void* stream) {
+    GDGS_TRACE("gdgs_poisson_solve_rhs");
     clear_error();
     REQUIRE_PTR(rho);
     return poisson_common(nullptr, rho, boundary, W, H, mg, u, stats_dev, ws, ws_bytes, stream);
@@ -769,6 +811,7 @@ gdgs_status gdgs_render(const gdgs_scene* scene, const gdgs_camera* cam, const f
                         const gdgs_mg_params* mg, int64_t pair_capacity, float* u,
                         gdgs_stats* stats_dev, int sync_stats, void* ws, size_t ws_bytes,
                         void* stream) {
+    GDGS_TRACE("gdgs_render");
     return render_common(scene, cam, boundary, mg, pair_capacity, u, stats_dev, sync_stats, ws,
                          ws_bytes, stream, 6);
 }
@@ -777,6 +820,7 @@ gdgs_status gdgs_render_laplacian(const gdgs_scene* scene, const gdgs_camera* ca
                                   const float* boundary, const gdgs_mg_params* mg,
                                   int64_t pair_capacity, float* u, gdgs_stats* stats_dev,
                                   int sync_stats, void* ws, size_t ws_bytes, void* stream) {
+    GDGS_TRACE("gdgs_render_laplacian");
     return render_common(scene, cam, boundary, mg, pair_capacity, u, stats_dev, sync_stats, ws,
                          ws_bytes, stream, 3);
 }
@@ -787,12 +831,14 @@ gdgs_status gdgs_render_laplacian_sparse(const gdgs_scene* scene, const gdgs_cam
                                          gdgs_stats* stats_dev, uint64_t* nonzero,
                                          int sync_stats, void* ws, size_t ws_bytes,
                                          void* stream) {
+    GDGS_TRACE("gdgs_render_laplacian_sparse");
     return render_common(scene, cam, boundary, mg, pair_capacity, u, stats_dev, sync_stats, ws,
                          ws_bytes, stream, 3, true, threshold,
                          reinterpret_cast<unsigned long long*>(nonzero));
 }
 
 gdgs_status gdgs_div_adjoint(const float* lam, int32_t W, int32_t H, float* dgrad, void* stream) {
+    GDGS_TRACE("gdgs_div_adjoint");
     clear_error();
     TRY(check_size(W, H));
     REQUIRE_PTR(lam);
@@ -802,6 +848,7 @@ gdgs_status gdgs_div_adjoint(const float* lam, int32_t W, int32_t H, float* dgra
 
 gdgs_status gdgs_div_adjoint_neumann(const float* lam, int32_t W, int32_t H, float* dgrad,
                                      void* stream) {
+    GDGS_TRACE("gdgs_div_adjoint_neumann");
     clear_error();
     TRY(check_size(W, H));
     REQUIRE_PTR(lam);
@@ -814,6 +861,7 @@ gdgs_status gdgs_raster_grad_backward(const gdgs_proj* proj, const float* opacit
                                       int32_t W, int32_t H, const float* grad, const float* dgrad,
                                       float* dmean2d, float* dconic, float* dopacity,
                                       float* dvalue, void* ws, size_t ws_bytes, void* stream) {
+    GDGS_TRACE("gdgs_raster_grad_backward");
     clear_error();
     REQUIRE(K >= 0 && K < (int64_t)0xFFFFFFFFll, "K = %lld out of range", (long long)K);
     TRY(check_size(W, H));

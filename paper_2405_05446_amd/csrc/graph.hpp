@@ -90,6 +90,11 @@ gdgs_status with_graph(KeyBuilder& kb, hipStream_t st, F&& enqueue,
             set_error("graph capture failed: %s", hipGetErrorString(e));
             return GDGS_ERR_HIP;
         }
+        if (log_level() >= 2) {
+            size_t nodes = 0;
+            (void)hipGraphGetNodes(g, nullptr, &nodes);
+            log_msg(2, "captured graph \"%s\": %zu nodes", kb.str().c_str(), nodes);
+        }
         const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (ei != hipSuccess) {

@@ -10,6 +10,7 @@
 #include <string>
 
 #include "../../include/gdgs.h"
+#include "trace.hpp"
 
 namespace gdgs {
 

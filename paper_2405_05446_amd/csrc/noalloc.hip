@@ -58,6 +58,7 @@ using namespace gdgs;
 extern "C" gdgs_status gdgs_poisson_solve_static(const float* grad, const float* boundary,
                                                  int32_t W, int32_t H, const gdgs_mg_params* mg,
                                                  float* u, gdgs_stats* stats_dev, void* stream) {
+    GDGS_TRACE("gdgs_poisson_solve_static");
     clear_error();
     auto aligned4 = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; };
     if (grad == nullptr || !aligned4(grad) || u == nullptr || !aligned4(u) ||

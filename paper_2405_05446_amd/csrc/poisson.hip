@@ -1952,6 +1952,11 @@ gdgs_status mg_plan(int W, int H, const gdgs_mg_params* mg, MgPlan* plan) {
         if (k > 4096) k = 4096;
         p.coarse_sweeps = k;
     }
+    GDGS_LOG(3, "multigrid plan %dx%d: %d grids (the last %d in one workgroup), V(%d,%d), "
+                "%d coarsest sweeps, tol %g, flags%s%s%s%s%s", W, H, p.levels, p.levels - p.lc,
+             p.pre, p.post, p.coarse_sweeps, p.tol, p.warm ? " warm" : "",
+             p.resume ? " resume" : "", p.neumann ? " neumann" : "", p.fmg ? " fmg" : "",
+             p.stop_eta ? " eta" : "");
     *plan = p;
     return GDGS_OK;
 }

@@ -470,6 +470,8 @@ struct gdgs_server {
                 if (batched) {
                     // front half done: re-run on overflow, else join the batch
                     if (hs.overflow != 0 && !r->cancelled) {
+                        GDGS_LOG(2, "server: request %lld needs %lld pairs; run again with a "
+                                    "larger capacity", (long long)id, (long long)hs.num_pairs);
                         (void)core->finish_run(r, true, hs.num_pairs, false, 0);
                         running[s] = -1;
                         continue;
@@ -481,6 +483,9 @@ struct gdgs_server {
                     continue;
                 }
                 const int cyc = std::max(hs.cycles[0], std::max(hs.cycles[1], hs.cycles[2]));
+                if (hs.overflow != 0)
+                    GDGS_LOG(2, "server: request %lld needs %lld pairs; run again with a "
+                                "larger capacity", (long long)id, (long long)hs.num_pairs);
                 const Next nx = core->finish_run(r, hs.overflow != 0, hs.num_pairs,
                                                  hs.converged != 0, cyc);
                 if (nx == Next::Resume) {
@@ -548,6 +553,7 @@ int64_t gdgs_now_ns(void) { return steady_ns(); }
 
 gdgs_status gdgs_server_create(const gdgs_scene* scene, const gdgs_server_params* params,
                                gdgs_server** out) {
+    GDGS_TRACE("gdgs_server_create");
     clear_error();
     SREQ(scene && params && out, "scene, params or out is null");
     const int64_t K = scene->K;
@@ -648,10 +654,13 @@ gdgs_status gdgs_server_create(const gdgs_scene* scene, const gdgs_server_params
     s->core = new sched::Core(cfg);
     s->thread = std::thread([s] { s->loop(); });
     *out = s;
+    GDGS_LOG(2, "server created: %zu-byte budget, %d front-half stream(s), %s solves",
+             (size_t)s->arena_bytes, params->streams, s->batched ? "batched" : "per-request");
     return GDGS_OK;
 }
 
 gdgs_status gdgs_server_submit(gdgs_server* srv, const gdgs_request* req, int64_t* id) {
+    GDGS_TRACE("gdgs_server_submit");
     clear_error();
     SREQ(srv && req && id, "server, request or id is null");
     const gdgs_camera& cam = req->cam;
@@ -685,6 +694,7 @@ gdgs_status gdgs_server_submit(gdgs_server* srv, const gdgs_request* req, int64_
 
 gdgs_status gdgs_server_poll(gdgs_server* srv, gdgs_completion* out, int32_t max, int32_t wait_us,
                              int32_t* n) {
+    GDGS_TRACE("gdgs_server_poll");
     clear_error();
     SREQ(srv && n && (max == 0 || out) && max >= 0, "bad poll arguments");
     std::unique_lock<std::mutex> lk(srv->mu);
@@ -701,6 +711,7 @@ gdgs_status gdgs_server_poll(gdgs_server* srv, gdgs_completion* out, int32_t max
 }
 
 gdgs_status gdgs_server_cancel(gdgs_server* srv, int64_t id) {
+    GDGS_TRACE("gdgs_server_cancel");
     clear_error();
     SREQ(srv, "server is null");
     std::lock_guard<std::mutex> g(srv->mu);
@@ -716,6 +727,7 @@ gdgs_status gdgs_server_cancel(gdgs_server* srv, int64_t id) {
 }
 
 gdgs_status gdgs_server_query(gdgs_server* srv, gdgs_server_state* out) {
+    GDGS_TRACE("gdgs_server_query");
     clear_error();
     SREQ(srv && out, "server or out is null");
     std::lock_guard<std::mutex> g(srv->mu);
@@ -737,8 +749,10 @@ gdgs_status gdgs_server_query(gdgs_server* srv, gdgs_server_state* out) {
 }
 
 gdgs_status gdgs_server_destroy(gdgs_server* srv) {
+    GDGS_TRACE("gdgs_server_destroy");
     clear_error();
     if (!srv) return GDGS_OK;
+    GDGS_LOG(2, "server destroyed");
     {
         std::lock_guard<std::mutex> g(srv->mu);
         srv->stop = true;
