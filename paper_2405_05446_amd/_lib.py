@@ -60,7 +60,7 @@ class MgParams(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("pre_sweeps", ctypes.c_int32),
                 ("post_sweeps", ctypes.c_int32), ("max_cycles", ctypes.c_int32),
                 ("coarse_sweeps", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("tol", ctypes.c_double)]
+                ("tol", ctypes.c_double), ("smooth_weight", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):

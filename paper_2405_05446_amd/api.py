@@ -56,8 +56,12 @@ STOP_ETA = 16  # stop on the normwise backward error eta instead of the relative
 
 
 def mg_params(levels: int = 0, pre: int = 2, post: int = 2, max_cycles: int = 20,
-              tol: float = 1e-6, coarse_sweeps: int = 0, flags: int = 0) -> L.MgParams:
-    return L.MgParams(levels, pre, post, max_cycles, coarse_sweeps, flags, float(tol))
+              tol: float = 1e-6, coarse_sweeps: int = 0, flags: int = 0,
+              smooth_weight: float = 0.0) -> L.MgParams:
+    """smooth_weight: over-relaxation of the red-black sweeps (0 = the library's
+    default, 1 = plain Gauss-Seidel)."""
+    return L.MgParams(levels, pre, post, max_cycles, coarse_sweeps, flags, float(tol),
+                      float(smooth_weight))
 
 
 @dataclass
@@ -603,7 +607,7 @@ class Renderer:
         m = self.mg
         keep = (m.flags & (FMG | STOP_ETA)) | (NEUMANN if self.neumann else 0)
         return mg_params(m.levels, m.pre_sweeps, m.post_sweeps, cycles, m.tol, m.coarse_sweeps,
-                         flags | keep)
+                         flags | keep, m.smooth_weight)
 
     def _enqueue(self, cam, boundary, events, stream):
         """Enqueue one frame (no waiting): the four steps, then an asynchronous

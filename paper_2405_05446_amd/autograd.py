@@ -40,7 +40,7 @@ def _adjoint(ctx, du, W, H):
     m = ctx.mg
     nm = bool(m.flags & A.NEUMANN)
     mg = A.mg_params(m.levels, m.pre_sweeps, m.post_sweeps, m.max_cycles, m.tol,
-                     m.coarse_sweeps, m.flags & (A.NEUMANN | A.FMG))
+                     m.coarse_sweeps, m.flags & (A.NEUMANN | A.FMG), m.smooth_weight)
     lam, _ = A.gdgs_poisson_solve_rhs(du, None, W, H, mg)
     return A.gdgs_div_adjoint(lam, W, H, neumann=nm)
 

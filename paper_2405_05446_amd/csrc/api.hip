@@ -302,7 +302,7 @@ gdgs_status launch_render_stats(const int64_t* num_pairs, int64_t cap, gdgs_stat
 
 void add_plan(KeyBuilder& kb, const MgPlan& p) {
     kb.add(p.levels).add(p.lc).add(p.pre).add(p.post).add(p.max_cycles).add(p.coarse_sweeps)
-        .add(p.omega).add(p.tol).add(p.warm).add(p.resume).add(p.neumann).add(p.fmg).add(p.stop_eta)
+        .add(p.omega).add(p.sw).add(p.tol).add(p.warm).add(p.resume).add(p.neumann).add(p.fmg).add(p.stop_eta)
         .add(p.lds_bytes);
     for (int l = 0; l < p.levels; ++l) kb.add(p.n[l]).add(p.m[l]).add(p.pitch[l]);
 }

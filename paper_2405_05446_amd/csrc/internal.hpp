@@ -151,6 +151,7 @@ struct MgPlan {
     size_t lds_bytes = 0; // dynamic LDS of the in-workgroup V-cycle
     int pre = 2, post = 2, max_cycles = 20, coarse_sweeps = 0;
     float omega = 1.0f;   // SOR factor on the coarsest grid
+    float sw = 1.0f;      // over-relaxation weight of the red-black smoothing sweeps
     double tol = 1e-6;
     bool warm = false;    // start from the caller's u instead of zero
     bool resume = false;  // continue the previous solve (setup skipped)

@@ -79,3 +79,17 @@ def test_timer_repeats_validate_on_the_host(lib):
     assert f(b"mg_post_fine", 4) == 1
     assert b"not armed" in lib.gdgs_last_error()
     assert f(None, 4) == 1
+
+
+def test_smoothing_weight_validates_on_the_host(lib):
+    # the multigrid parameters are checked before any device call
+    import paper_2405_05446_amd._lib as L
+    f = lib.gdgs_poisson_workspace_size
+    f.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(L.MgParams),
+                  ctypes.POINTER(ctypes.c_size_t)]
+    lib.gdgs_last_error.restype = ctypes.c_char_p
+    n = ctypes.c_size_t(0)
+    for w in (2.0, 1.6, 0.4, -1.0, float("nan")):
+        mg = L.MgParams(0, 2, 2, 20, 0, 0, 1e-6, w)
+        assert f(64, 64, ctypes.byref(mg), ctypes.byref(n)) == 1, w
+        assert b"smoothing weight" in lib.gdgs_last_error(), w
