@@ -92,33 +92,42 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* s_tmp,
     return off + inc - x;
 }
 
+// gate (the first depth pass only): key i is keys[i] where gate[i] != 0 and
+// 0xFFFFFFFF (last) where it is 0, i.e. the depth bits of the splats with
+// tiles and the culled splats after them, read straight from the projection.
+__device__ __forceinline__ uint32_t gated_key(const uint32_t* __restrict__ keys,
+                                              const uint32_t* __restrict__ gate, int64_t i) {
+    const uint32_t k = keys[i];
+    return gate ? (gate[i] ? k : 0xFFFFFFFFu) : k;
+}
+
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(
-    const uint32_t* __restrict__ keys, const int64_t* n_dev, int64_t n_host, int64_t cap,
-    int shift, int bits, uint32_t* __restrict__ hist) {
-    __shared__ uint32_t s_h[kRadix];
-    const int G = gridDim.x, b = blockIdx.x, t = threadIdx.x;
-    s_h[t] = 0;
+    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ gate, const int64_t* n_dev,
+    int64_t n_host, int64_t cap, int shift, int bits, uint32_t* __restrict__ hist) {
+    __shared__ uint32_t s_h[kWaves][kRadix];  // one row per wave: fewer colliding atomics
+    const int G = gridDim.x, b = blockIdx.x, t = threadIdx.x, w = t >> 6;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) s_h[i][t] = 0;
     __syncthreads();
     int64_t lo, hi;
     block_range(clamp_n(n_dev, n_host, cap), G, b, &lo, &hi);
     const uint32_t mask = (1u << bits) - 1u;
-    const uint64_t lt = lanemask_lt();
     for (int64_t base = lo; base < hi; base += kSortTile) {
         uint32_t d[kSortItems];
 #pragma unroll
         for (int r = 0; r < kSortItems; ++r) {
             const int64_t i = base + r * kSortThreads + t;
-            d[r] = i < hi ? (keys[i] >> shift) & mask : 0u;
+            d[r] = i < hi ? (gated_key(keys, gate, i) >> shift) & mask : 0u;
         }
 #pragma unroll
-        for (int r = 0; r < kSortItems; ++r) {
-            const bool valid = base + r * kSortThreads + t < hi;
-            const uint64_t peers = match_digit(d[r], valid, bits);
-            if (valid && (peers & lt) == 0) atomicAdd(&s_h[d[r]], (uint32_t)__popcll(peers));
-        }
+        for (int r = 0; r < kSortItems; ++r)
+            if (base + r * kSortThreads + t < hi) atomicAdd(&s_h[w][d[r]], 1u);
     }
     __syncthreads();
-    hist[(size_t)t * G + b] = s_h[t];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) sum += s_h[i][t];
+    hist[(size_t)t * G + b] = sum;
 }
 
 // Block d: exclusive scan of digit d's block counts (in place) and its total.
@@ -152,10 +161,12 @@ struct Vals {
     uint32_t* out[3];
 };
 
+// Value array v with in[v] null carries the element's index.
 template <int NV>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
-    const uint32_t* __restrict__ kin, uint32_t* __restrict__ kout, Vals vals,
-    const int64_t* n_dev, int64_t n_host, int64_t cap, int shift, int bits,
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ gate,
+    uint32_t* __restrict__ kout, Vals vals, const int64_t* n_dev, int64_t n_host, int64_t cap,
+    int shift, int bits,
     const uint32_t* __restrict__ hist, const uint32_t* __restrict__ digit_tot) {
     __shared__ uint32_t s_base[kRadix];
     __shared__ uint32_t s_wcnt[kWaves][kRadix];
@@ -182,9 +193,10 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
         for (int r = 0; r < kSortItems; ++r) {
             const int64_t i = wbase + r * 64 + lane;
             const bool valid = i < hi;
-            key[r] = valid ? kin[i] : 0u;
+            key[r] = valid ? gated_key(kin, gate, i) : 0u;
 #pragma unroll
-            for (int v = 0; v < NV; ++v) val[v][r] = valid ? vals.in[v][i] : 0u;
+            for (int v = 0; v < NV; ++v)
+                val[v][r] = valid ? (vals.in[v] ? vals.in[v][i] : (uint32_t)i) : 0u;
         }
 #pragma unroll
         for (int r = 0; r < kSortItems; ++r) {
@@ -236,14 +248,6 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
 }
 
 // ---------------------------------------------------------------- binning
-__global__ void k_depth_keys(const float* __restrict__ depth, const uint32_t* __restrict__ count,
-                             int64_t K, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= K) return;
-    keys[k] = count[k] ? __float_as_uint(depth[k]) : 0xFFFFFFFFu;
-    vals[k] = (uint32_t)k;
-}
-
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 2;   // 512 splats per block: enough blocks to hide the emission's latency
 constexpr int kScanTile = kScanThreads * kScanItems;
@@ -382,15 +386,33 @@ __global__ __launch_bounds__(kScanThreads) void k_emit_pairs(
     }
 }
 
-__global__ void k_tile_ranges(const uint32_t* __restrict__ tiles, const int64_t* n_dev, int64_t cap,
-                              uint32_t* __restrict__ ranges, int T) {
+// Tile ranges from the sorted tile ids: block b covers pairs
+// b * 256 * kRangeItems .., thread t every 256th of them (coalesced); all of
+// a thread's loads, with each pair's two neighbours, are issued before any
+// comparison.
+constexpr int kRangeItems = 8;
+__global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t* __restrict__ tiles,
+                                                     const int64_t* n_dev, int64_t cap,
+                                                     uint32_t* __restrict__ ranges, int T) {
     const int64_t n = clamp_n(n_dev, 0, cap);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t tl = tiles[i];
-        if (tl >= (uint32_t)T) continue;
-        if (i == 0 || tiles[i - 1] != tl) ranges[tl] = (uint32_t)i;
-        if (i == n - 1 || tiles[i + 1] != tl) ranges[T + tl] = (uint32_t)(i + 1);
+    const int64_t base = (int64_t)blockIdx.x * 256 * kRangeItems + threadIdx.x;
+    if (base >= n) return;
+    uint32_t prev[kRangeItems], cur[kRangeItems], next[kRangeItems];
+#pragma unroll
+    for (int k = 0; k < kRangeItems; ++k) {
+        const int64_t i = base + 256 * k;
+        const bool in = i < n;
+        cur[k] = in ? tiles[i] : 0xFFFFFFFFu;
+        prev[k] = (in && i > 0) ? tiles[i - 1] : 0xFFFFFFFFu;
+        next[k] = (i + 1 < n) ? tiles[i + 1] : 0xFFFFFFFFu;
+    }
+#pragma unroll
+    for (int k = 0; k < kRangeItems; ++k) {
+        const int64_t i = base + 256 * k;
+        const uint32_t tl = cur[k];
+        if (i >= n || tl >= (uint32_t)T) continue;
+        if (prev[k] != tl) ranges[tl] = (uint32_t)i;
+        if (next[k] != tl) ranges[T + tl] = (uint32_t)(i + 1);
     }
 }
 
@@ -511,11 +533,14 @@ int bitlen(uint64_t x) {
 }
 
 // One full LSD sort of keys with NV value arrays over `key_bits` key bits.
-// Pass 0 reads (kin0, vin0[]); pass p > 0 reads buffer set (p + 1) & 1 ... as
+// Pass 0 reads (kin0, vin0[]), its keys gated by gate0 if that is not null
+// (see gated_key) and a null vin0[v] standing for the element indices; pass
+// p > 0 reads buffer set (p + 1) & 1 ... as
 // written by pass p - 1: pass p writes set (p + 1) & 1, the last pass writes
 // (kfin, vfin[]).  buf sets: (kb[i], vb[v][i]).
 template <int NV>
-gdgs_status radix_sort(const uint32_t* kin0, const uint32_t* const* vin0, uint32_t* const* kb,
+gdgs_status radix_sort(const uint32_t* kin0, const uint32_t* gate0, const uint32_t* const* vin0,
+                       uint32_t* const* kb,
                        uint32_t* const (*vb)[2], uint32_t* kfin, uint32_t* const* vfin,
                        const int64_t* n_dev, int64_t n_host, int64_t cap, int key_bits,
                        uint32_t* hist, uint32_t* digit_tot, hipStream_t st) {
@@ -535,11 +560,12 @@ gdgs_status radix_sort(const uint32_t* kin0, const uint32_t* const* vin0, uint32
             vals.in[v] = p == 0 ? vin0[v] : vb[v][p & 1];
             vals.out[v] = last ? vfin[v] : vb[v][(p + 1) & 1];
         }
-        hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(kSortThreads), 0, st, kin, n_dev, n_host,
-                           cap, shift, bits, hist);
+        const uint32_t* gate = p == 0 ? gate0 : nullptr;
+        hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(kSortThreads), 0, st, kin, gate, n_dev,
+                           n_host, cap, shift, bits, hist);
         hipLaunchKernelGGL(k_radix_scan, dim3(kRadix), dim3(256), 0, st, hist, G, digit_tot);
-        hipLaunchKernelGGL(k_radix_scatter<NV>, dim3(G), dim3(kSortThreads), 0, st, kin, kout,
-                           vals, n_dev, n_host, cap, shift, bits, hist, digit_tot);
+        hipLaunchKernelGGL(k_radix_scatter<NV>, dim3(G), dim3(kSortThreads), 0, st, kin, gate,
+                           kout, vals, n_dev, n_host, cap, shift, bits, hist, digit_tot);
     }
     GDGS_LAUNCH_CHECK();
     return GDGS_OK;
@@ -614,18 +640,18 @@ gdgs_status launch_bin_sort(const gdgs_proj& proj, int64_t K, int W, int H, cons
         return GDGS_OK;
     }
     // 1. depth order of the splats; their rectangles ride along, so that the
-    //    scan and the emission read them in rank order without gathers
-    hipLaunchKernelGGL(k_depth_keys, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, st,
-                       proj.depth, proj.count, K, ws.dkey[0], ws.dval[0]);
+    //    scan and the emission read them in rank order without gathers.  The
+    //    first pass keys the splats straight from the projection's depth and
+    //    tile count, with the splat indices as the first values
     {
-        const uint32_t* vin0[3] = {ws.dval[0], proj.rect, proj.rect + K};
+        const uint32_t* vin0[3] = {nullptr, proj.rect, proj.rect + K};
         uint32_t* const kb[2] = {ws.dkey[0], ws.dkey[1]};
         uint32_t* const vb[3][2] = {{ws.dval[0], ws.dval[1]},
                                     {ws.drect[0][0], ws.drect[0][1]},
                                     {ws.drect[1][0], ws.drect[1][1]}};
         uint32_t* const vfin[3] = {bins.order, ws.drect[0][0], ws.drect[1][0]};
-        s = radix_sort<3>(ws.dkey[0], vin0, kb, vb, ws.dkey[0], vfin, nullptr, K, K, 32, ws.hist,
-                          ws.digit_tot, st);
+        s = radix_sort<3>(reinterpret_cast<const uint32_t*>(proj.depth), proj.count, vin0, kb, vb,
+                          ws.dkey[0], vfin, nullptr, K, K, 32, ws.hist, ws.digit_tot, st);
         if (s != GDGS_OK) return s;
     }
     const uint32_t* rect0 = ws.drect[0][0];
@@ -646,11 +672,13 @@ gdgs_status launch_bin_sort(const gdgs_proj& proj, int64_t K, int W, int H, cons
         uint32_t* const kb[2] = {ws.pkey[0], ws.pkey[1]};
         uint32_t* const vb[1][2] = {{ws.pval[0], ws.pval[1]}};
         uint32_t* const vfin[1] = {bins.splat_of_pair};
-        s = radix_sort<1>(ws.pkey[0], vin0, kb, vb, bins.tile_of_pair, vfin, bins.num_pairs, 0,
-                          bins.capacity, tbits, ws.hist, ws.digit_tot, st);
+        s = radix_sort<1>(ws.pkey[0], nullptr, vin0, kb, vb, bins.tile_of_pair, vfin,
+                          bins.num_pairs, 0, bins.capacity, tbits, ws.hist, ws.digit_tot, st);
         if (s != GDGS_OK) return s;
     }
-    hipLaunchKernelGGL(k_tile_ranges, dim3(2048), dim3(256), 0, st, bins.tile_of_pair,
+    const int64_t rblocks = (bins.capacity + 256 * kRangeItems - 1) / (256 * kRangeItems);
+    hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)rblocks), dim3(256), 0, st,
+                       bins.tile_of_pair,
                        bins.num_pairs, bins.capacity, bins.ranges, T);
     GDGS_LAUNCH_CHECK();
     if (bins.tile_order) return launch_tile_order(bins.ranges, T, ws.tile_bh, bins.tile_order, st);
