@@ -1964,8 +1964,9 @@ gdgs_status mg_plan(int W, int H, const gdgs_mg_params* mg, MgPlan* plan) {
     } else {
         // SOR sweeps for a 1e-2 error reduction, (omega - 1)^k <= 1e-2: the
         // coarsest correction only has to be small against the V-cycle's own
-        // contraction (about 0.06).  (Measured at 1080p, where this gives 8:
-        // 8 to 32 sweeps keep 6 cycles, 4 sweeps need 11.)
+        // contraction (about 0.02).  (At 1080p this gives 8; an FP64
+        // emulation of the cycle keeps 5 cycles with 6 or more sweeps and
+        // needs 9 with 4.)
         const double rho = p.omega - 1.0;
         int k = rho > 0.0 ? (int)ceil(log(1e-2) / log(rho)) : 4;
         if (k < 4) k = 4;
