@@ -1713,7 +1713,12 @@ __device__ __forceinline__ void finalize_task(const double* __restrict__ part, i
                                               int* __restrict__ done,
                                               gdgs_stats* __restrict__ stats, double tol, int c,
                                               int stop_eta, double* sh) {
-    if (done[c]) return;  // uniform: finished before this cycle
+    // every load of the task is issued before any is waited for: the flag,
+    // the norms of b, the cycle count and the block partials (one memory
+    // latency instead of three in a row)
+    const int dn = done[c];
+    const double bn_inf = bnorm[2 * c], bn_2 = bnorm[2 * c + 1];
+    const int cyc = stats->cycles[c];
     double rmax = 0.0, umax = 0.0, rss = 0.0, dpre = 0.0, dpost = 0.0;
     // two blocks' partials per thread and round, loaded before use
     constexpr int nt = kFinThreads;
@@ -1736,6 +1741,7 @@ __device__ __forceinline__ void finalize_task(const double* __restrict__ part, i
             dpost = fmax(dpost, v[k][4]);
         }
     }
+    if (dn) return;  // uniform: finished before this cycle
     block_reduce3(rmax, umax, rss, sh);
     double d0 = 0.0;
     block_reduce3(dpre, dpost, d0, sh);
@@ -1743,13 +1749,12 @@ __device__ __forceinline__ void finalize_task(const double* __restrict__ part, i
         // |u_k - u_{k-1}| <= (change in pre-smoothing) + (change in the post pass)
         const double dcyc = dpre + dpost;
         const double rel = umax > 0.0 ? dcyc / umax : (dcyc > 0.0 ? 1.0 : 0.0);
-        const double b2 = bnorm[2 * c + 1];
-        const double den = 8.0 * umax + bnorm[2 * c];
+        const double den = 8.0 * umax + bn_inf;
         const double eta = den > 0.0 ? rmax / den : 0.0;
         stats->eta[c] = eta;
-        stats->rel_res[c] = b2 > 0.0 ? sqrt(rss) / b2 : 0.0;
+        stats->rel_res[c] = bn_2 > 0.0 ? sqrt(rss) / bn_2 : 0.0;
         stats->delta[c] = rel;
-        stats->cycles[c] += 1;  // zeroed by setup; accumulates over resumed calls
+        stats->cycles[c] = cyc + 1;  // zeroed by setup; accumulates over resumed calls
         if ((stop_eta ? eta : rel) <= tol) done[c] = 1;
     }
 }
